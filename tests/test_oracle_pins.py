@@ -1,0 +1,396 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU needed).
+
+Each test ties one oracle function to something outside itself: a library routine (numpy's
+Philox), the paper's own formula or worked example (Figures 1-3), closed forms and brute
+force, hand-worked generations, an independent literal reading of Algorithms 3/4, or an
+invariant the method guarantees.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from literal_alg34 import LiteralParGomea, initial_population
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------------------------------
+# Philox
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("key,ctr", [((0, 0), (0, 0, 0, 0)), ((1, 2), (5, 6, 7, 8)),
+                                     ((2**64 - 1, 12345), (2**64 - 2, 3, 2**63, 9))])
+def test_philox4x64_matches_numpy(key, ctr):
+    """The shared Philox round template, 4x64 instance, against numpy.random.Philox (which
+    increments its counter before producing a block)."""
+    bg = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(ctr, np.uint64))
+    want = bg.random_raw(4)
+    c = list(ctr)
+    c[0] = (c[0] + 1) % 2**64
+    if c[0] == 0:
+        c[1] = (c[1] + 1) % 2**64
+    got = oracle.philox4x64(key, c)
+    assert [int(x) for x in got] == [int(x) for x in want]
+
+
+def test_philox4x32_bits_balanced_and_counter_sensitive():
+    """4x32 instance (same template): outputs change with every counter word and key word,
+    and bits are balanced over many blocks."""
+    base = oracle.philox4x32((1, 2), (3, 4, 5, 6))
+    for pos in range(4):
+        c = [3, 4, 5, 6]
+        c[pos] ^= 1
+        assert not np.array_equal(oracle.philox4x32((1, 2), c), base)
+    assert not np.array_equal(oracle.philox4x32((1, 3), (3, 4, 5, 6)), base)
+    ones = 0
+    for t in range(2000):
+        out = oracle.philox4x32((7, 0), (t, 0, 0, 0))
+        ones += sum(bin(int(x)).count("1") for x in out)
+    frac = ones / (2000 * 128)
+    assert abs(frac - 0.5) < 0.005
+
+
+# ------------------------------------------------------------------------------------------
+# Max-Cut objective
+# ------------------------------------------------------------------------------------------
+def paper_objective(g, x):
+    """Section 6.2 objective with x in {-1, 1}: one half of the sum over pairs i < j of
+    w_ij (1 - x_i x_j) (pairs without an edge have w = 0)."""
+    s = 2 * np.asarray(x, np.int64) - 1
+    total = 0
+    for e in range(g.m):
+        i, j = sorted((int(g.u[e]), int(g.v[e])))
+        total += int(g.w[e]) * (1 - s[i] * s[j])
+    assert total % 2 == 0
+    return total // 2
+
+
+def brute_force_max(g):
+    best = None
+    for bits in itertools.product((0, 1), repeat=g.n):
+        f = oracle.maxcut(g, np.array(bits, np.uint8))
+        best = f if best is None else max(best, f)
+    return best
+
+
+def test_maxcut_equals_paper_formula():
+    rng = np.random.default_rng(0)
+    for n, d in ((30, 3), (40, 4), (25, 6)):
+        g = workloads.configuration_model(n, d, seed=n, weights="signed50")
+        for _ in range(5):
+            x = rng.integers(0, 2, n).astype(np.uint8)
+            assert oracle.maxcut(g, x) == paper_objective(g, x)
+
+
+def test_maxcut_closed_forms_brute_force():
+    bowtie = workloads.from_edges(5, [(0, 1), (0, 2), (1, 2), (2, 3), (2, 4), (3, 4)])
+    assert brute_force_max(bowtie) == 4          # Figure 1 graph, unit weights
+    c5 = workloads.from_edges(5, [(i, (i + 1) % 5) for i in range(5)])
+    assert brute_force_max(c5) == 4              # odd cycle: all edges but one
+    c6 = workloads.from_edges(6, [(i, (i + 1) % 6) for i in range(6)])
+    assert brute_force_max(c6) == 6              # even cycle is bipartite
+    for n in (4, 5, 6):
+        kn = workloads.from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+        assert brute_force_max(kn) == (n * n) // 4   # complete graph: floor(n^2 / 4)
+    t4 = workloads.torus(4, 1, 9, seed=3)
+    assert brute_force_max(t4) == t4.total_weight    # even torus is bipartite
+
+
+def test_maxcut_symmetries_and_checkerboard():
+    g = workloads.torus(10, 1, 5, seed=1)
+    assert oracle.maxcut(g, np.zeros(g.n, np.uint8)) == 0
+    r, c = np.divmod(np.arange(g.n), 10)
+    board = ((r + c) % 2).astype(np.uint8)
+    assert oracle.maxcut(g, board) == g.total_weight
+    assert oracle.maxcut(g, 1 - board) == g.total_weight
+    x = np.random.default_rng(1).integers(0, 2, g.n).astype(np.uint8)
+    assert oracle.maxcut(g, x) == oracle.maxcut(g, 1 - x)
+
+
+# ------------------------------------------------------------------------------------------
+# FOS, LMIG and colouring
+# ------------------------------------------------------------------------------------------
+def test_fos_builders():
+    g = workloads.configuration_model(200, 5, seed=4, weights="uniform")
+    p, v = oracle.fos(g, 0)
+    assert np.array_equal(p, np.arange(g.n + 1)) and np.array_equal(v, np.arange(g.n))
+    p, v = oracle.fos(g, 1)
+    nb = [set() for _ in range(g.n)]
+    for a, b in zip(g.u, g.v):
+        nb[a].add(int(b))
+        nb[b].add(int(a))
+    for x in range(g.n):
+        assert v[p[x]:p[x + 1]].tolist() == sorted(nb[x] | {x})
+
+
+def read_fig123():
+    vig, sets, lmig, caption = [], {}, set(), []
+    with open(os.path.join(GOLDEN, "fig123_lmig.txt")) as fh:
+        for line in fh:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            nums = [int(x) for x in t[1:]]
+            if t[0] == "vig":
+                vig.append((nums[0] - 1, nums[1] - 1))
+            elif t[0] == "set":
+                sets[nums[0]] = [x - 1 for x in nums[1:]]
+            elif t[0] == "lmig":
+                lmig.add(tuple(sorted((nums[0] - 1, nums[1] - 1))))
+            elif t[0] == "caption":
+                caption.append([x - 1 for x in nums])
+    g = workloads.from_edges(5, vig)
+    order = sorted(sets)
+    ptr = np.zeros(len(order) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(sets[j]) for j in order])
+    vars_ = np.concatenate([np.asarray(sets[j], np.int32) for j in order])
+    return g, ptr, vars_, lmig, caption
+
+
+def test_lmig_of_figure3():
+    g, ptr, vars_, lmig, _ = read_fig123()
+    assert len(lmig) == 22
+    got = {tuple(p) for p in oracle.lmig_pairwise(g, ptr, vars_).tolist()}
+    assert got == lmig
+
+
+def valid_colouring(pairs, colour):
+    return all(colour[a] != colour[b] for a, b in pairs)
+
+
+def test_colouring_of_figure3():
+    """Welsh-Powell with (degree desc, index asc): {F3}, {F6}, {F8}, {F1,F4}, {F2,F5}, {F7};
+    k = 6 = chromatic number ({F3..F8} is a 6-clique).  The caption's grouping is another
+    valid 6-colouring."""
+    g, ptr, vars_, lmig, caption = read_fig123()
+    k, col, deg = oracle.colour(g, ptr, vars_)
+    assert k == 6
+    classes = sorted(sorted(int(j) for j in np.nonzero(col == c)[0]) for c in range(k))
+    assert classes == sorted([[2], [5], [7], [0, 3], [1, 4], [6]])
+    assert col[2] == 0 and col[5] == 1 and col[7] == 2 and col[0] == col[3] == 3
+    assert deg.tolist() == [4, 4, 7, 5, 5, 7, 5, 7]
+    assert valid_colouring(lmig, col)
+    cap = np.zeros(8, np.int64)
+    for c, members in enumerate(caption):
+        cap[members] = c
+    assert sorted(sum(caption, [])) == list(range(8))
+    assert valid_colouring(lmig, cap)
+    clique = [2, 3, 4, 5, 6, 7]
+    assert all(tuple(sorted(p)) in lmig for p in itertools.combinations(clique, 2))
+
+
+@pytest.mark.parametrize("n,d,kind", [(40, 3, 0), (40, 3, 1), (30, 5, 1), (24, 8, 1)])
+def test_colouring_valid_and_degree_matches_pairwise_lmig(n, d, kind):
+    g = workloads.configuration_model(n, d, seed=n * d, weights="uniform")
+    ptr, vars_ = oracle.fos(g, kind)
+    pairs = oracle.lmig_pairwise(g, ptr, vars_)
+    k, col, deg = oracle.colour(g, ptr, vars_)
+    pdeg = np.bincount(pairs.ravel(), minlength=len(ptr) - 1)
+    assert np.array_equal(pdeg, deg)
+    assert valid_colouring(pairs.tolist(), col)
+    assert set(col.tolist()) == set(range(k))
+    # Welsh-Powell bound: k <= max_i min(d_(i) + 1, i) over the sorted degree sequence.
+    ds = sorted(deg.tolist(), reverse=True)
+    assert k <= max(min(dd + 1, i + 1) for i, dd in enumerate(ds))
+
+
+def test_colouring_on_tori():
+    g = workloads.torus(10, 1, 5, seed=1)
+    ptr, vars_ = oracle.fos(g, 0)
+    k, col, _ = oracle.colour(g, ptr, vars_)
+    r, c = np.divmod(np.arange(g.n), 10)
+    parity = (r + c) % 2
+    assert k == 2
+    assert len(set(zip(col.tolist(), parity.tolist()))) == 2  # classes = checkerboard parity
+    g = workloads.torus(12, 1, 5, seed=1)
+    ptr, vars_ = oracle.fos(g, 1)
+    k, col, _ = oracle.colour(g, ptr, vars_)
+    assert k >= 8
+    assert valid_colouring(oracle.lmig_pairwise(g, ptr, vars_).tolist(), col)
+
+
+# ------------------------------------------------------------------------------------------
+# GOM generations
+# ------------------------------------------------------------------------------------------
+def read_hand_cases():
+    cases = []
+    with open(os.path.join(GOLDEN, "hand_generations.txt")) as fh:
+        for line in fh:
+            if not line.startswith("case "):
+                continue
+            head, start, pop, fit, elite, fe, cnt = [s.split() for s in line.split("|")]
+            cases.append({
+                "name": head[1], "rule": 1 if head[2] == "always" else 0,
+                "w": [int(head[3]), int(head[4])],
+                "start": [[int(ch) for ch in s] for s in start],
+                "pop": [[int(ch) for ch in s] for s in pop], "fit": [int(x) for x in fit],
+                "elite": [int(ch) for ch in elite[0]], "fE": int(fe[0]),
+                "evaluated": int(cnt[0]), "accepted": int(cnt[1])})
+    return cases
+
+
+@pytest.mark.parametrize("case", read_hand_cases(), ids=lambda c: f"{c['name']}-{c['rule']}")
+def test_hand_worked_generation(case):
+    g = workloads.from_edges(3, [(0, 1), (1, 2)], case["w"])
+    ptr, vars_ = oracle.fos(g, 0)
+    N = len(case["start"])
+    run = oracle.Run(g, ptr, vars_, pop=N, seed=1, rule=case["rule"],
+                     order=oracle.ORDER_FIXED)
+    cp, ce = run.classes()
+    assert ce[cp[0]:cp[1]].tolist() == [1] and ce[cp[1]:cp[2]].tolist() == [0, 2]
+    start = np.array(case["start"], np.uint8)
+    f0 = [oracle.maxcut(g, x) for x in start]
+    b = int(np.argmax(f0))
+    run.set_state(start, start[b], f0[b], 0, [0, 0, 0])
+    run.generation()
+    s = run.state()
+    assert s["genes"].tolist() == case["pop"]
+    assert s["fitness"].tolist() == case["fit"]
+    assert s["elite"].tolist() == case["elite"] and s["elite_fitness"] == case["fE"]
+    assert (s["evaluated"], s["accepted"]) == (case["evaluated"], case["accepted"])
+    assert s["attempted"] == N * 3
+
+
+@pytest.mark.parametrize("n,d,kind,pop,rule,order", [
+    (12, 3, 1, 5, 0, 0), (16, 4, 0, 4, 0, 0), (14, 3, 1, 7, 1, 0), (20, 2, 1, 3, 0, 1),
+    (18, 5, 1, 9, 0, 0)])
+def test_oracle_equals_literal_algorithm_3_4(n, d, kind, pop, rule, order):
+    """The step-at-a-time oracle against the literal whole-group reading of Algorithms 3/4
+    (O' insertion, keyed dependent-subfunction sums, M_IMP, reset/insert), every generation."""
+    g = workloads.configuration_model(n, d, seed=n + 100 * d, weights="signed50")
+    ptr, vars_ = oracle.fos(g, kind)
+    run = oracle.Run(g, ptr, vars_, pop=pop, seed=n * pop, rule=rule, order=order)
+    cp, ce = run.classes()
+    classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(len(cp) - 1)]
+    lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=n * pop, rule=rule, order=order)
+    s = run.state()
+    assert np.array_equal(s["genes"], lit.P)
+    for gen in range(6):
+        run.generation()
+        lit.generation()
+        s = run.state()
+        assert np.array_equal(s["genes"], lit.P), gen
+        assert s["fitness"].tolist() == lit.f.tolist(), gen
+        assert np.array_equal(s["elite"], lit.E) and s["elite_fitness"] == lit.fE
+        assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted)
+
+
+def test_initial_population_rule():
+    g = workloads.torus(12, 1, 3, seed=2)
+    ptr, vars_ = oracle.fos(g, 0)
+    run = oracle.Run(g, ptr, vars_, pop=6, seed=99)
+    assert np.array_equal(run.state()["genes"], initial_population(g.n, 6, 99))
+    s = run.state()
+    assert s["fitness"].tolist() == [oracle.maxcut(g, x) for x in s["genes"]]
+    b = int(np.argmax(s["fitness"]))
+    assert np.array_equal(s["elite"], s["genes"][b]) and s["elite_fitness"] == s["fitness"][b]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_partial_delta_equals_full_reevaluation(kind):
+    """Debug mode re-evaluates the whole solution after every step and counts mismatches
+    with the partially updated fitness (Section 2.2)."""
+    for n, d in ((60, 3), (50, 6)):
+        g = workloads.configuration_model(n, d, seed=d, weights="signed50")
+        ptr, vars_ = oracle.fos(g, kind)
+        run = oracle.Run(g, ptr, vars_, pop=8, seed=3, flags=oracle.FLAG_DEBUG)
+        run.run(1 << 62, 8)
+        s = run.state()
+        assert s["debug_mismatches"] == 0
+        assert s["evaluated"] > 0 and s["accepted"] > 0
+        assert s["fitness"].tolist() == [oracle.maxcut(g, x) for x in s["genes"]]
+
+
+def test_order_within_class_is_irrelevant():
+    """Reverse the visiting order of solutions and sets inside every class: same result."""
+    g = workloads.configuration_model(300, 4, seed=5, weights="signed50")
+    ptr, vars_ = oracle.fos(g, 1)
+    a = oracle.Run(g, ptr, vars_, pop=12, seed=4)
+    b = oracle.Run(g, ptr, vars_, pop=12, seed=4, flags=oracle.FLAG_REVERSE)
+    a.run(1 << 62, 10)
+    b.run(1 << 62, 10)
+    sa, sb = a.state(), b.state()
+    for key in ("genes", "fitness", "elite", "evaluated", "accepted"):
+        assert np.array_equal(sa[key], sb[key])
+
+
+def test_univariate_trajectory_independent_of_donor_draws():
+    """With single-variable sets any differing donor carries the flipped gene, so changing
+    every donor draw (salted donor key) leaves the univariate trajectory unchanged; with the
+    neighbourhood FOS it changes."""
+    g = workloads.configuration_model(400, 4, seed=8, weights="signed50")
+    for kind, same in ((0, True), (1, False)):
+        ptr, vars_ = oracle.fos(g, kind)
+        a = oracle.Run(g, ptr, vars_, pop=16, seed=6)
+        b = oracle.Run(g, ptr, vars_, pop=16, seed=6, donor_salt=0x5DEECE66D)
+        a.run(1 << 62, 8)
+        b.run(1 << 62, 8)
+        assert np.array_equal(a.state()["genes"], b.state()["genes"]) == same
+
+
+def test_monotone_fitness_and_bounds():
+    g = workloads.configuration_model(16, 3, seed=7, weights="uniform", w_lo=1, w_hi=20)
+    ptr, vars_ = oracle.fos(g, 1)
+    run = oracle.Run(g, ptr, vars_, pop=10, seed=2)
+    best = brute_force_max(g)
+    prev = run.state()
+    for _ in range(10):
+        run.generation()
+        s = run.state()
+        assert (s["fitness"] >= prev["fitness"]).all()
+        assert s["elite_fitness"] >= prev["elite_fitness"]
+        assert s["elite_fitness"] <= best
+        assert s["elite_fitness"] == oracle.maxcut(g, s["elite"])
+        prev = s
+
+
+def test_converged_population_is_fixed_point():
+    g = workloads.torus(6, 1, 5, seed=1)
+    ptr, vars_ = oracle.fos(g, 1)
+    run = oracle.Run(g, ptr, vars_, pop=5, seed=2)
+    x = np.random.default_rng(3).integers(0, 2, g.n).astype(np.uint8)
+    run.set_state(np.tile(x, (5, 1)), x, oracle.maxcut(g, x), 0, [0, 0, 0])
+    run.run(1 << 62, 4)
+    s = run.state()
+    assert (s["genes"] == x).all() and s["evaluated"] == 0 and s["accepted"] == 0
+
+
+def test_checkpoint_resume_reproduces_run():
+    g = workloads.configuration_model(500, 3, seed=2, weights="signed50")
+    ptr, vars_ = oracle.fos(g, 1)
+    a = oracle.Run(g, ptr, vars_, pop=9, seed=5)
+    a.run(1 << 62, 4)
+    snap = a.state()
+    b = oracle.Run(g, ptr, vars_, pop=9, seed=5)
+    b.set_state(snap["genes"], snap["elite"], snap["elite_fitness"], snap["generation"],
+                [snap["attempted"], snap["evaluated"], snap["accepted"]])
+    a.run(1 << 62, 9)
+    b.run(1 << 62, 9)
+    sa, sb = a.state(), b.state()
+    for key in ("genes", "fitness", "elite", "elite_fitness", "generation", "attempted",
+                "evaluated", "accepted"):
+        assert np.array_equal(sa[key], sb[key])
+
+
+def test_small_torus_reaches_total_weight():
+    """Observed (not guaranteed by the method): a 6x6 torus is solved to its bipartite
+    optimum, and the optimum genotype is a checkerboard."""
+    g = workloads.torus(6, 1, 9, seed=5)
+    ptr, vars_ = oracle.fos(g, 1)
+    run = oracle.Run(g, ptr, vars_, pop=16, seed=1)
+    run.run(g.total_weight, 200)
+    s = run.state()
+    assert s["elite_fitness"] == g.total_weight
+    r, c = np.divmod(np.arange(g.n), 6)
+    board = ((r + c) % 2).astype(np.uint8)
+    assert np.array_equal(s["elite"], board) or np.array_equal(s["elite"], 1 - board)
+
+
+def test_target_checked_before_first_generation():
+    g = workloads.torus(6, 1, 9, seed=5)
+    ptr, vars_ = oracle.fos(g, 0)
+    run = oracle.Run(g, ptr, vars_, pop=4, seed=1)
+    assert run.run(run.state()["elite_fitness"], 50) == 0

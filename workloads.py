@@ -1,0 +1,144 @@
+"""Seeded synthetic Max-Cut inputs shared by the tests, the oracle checks and the benchmark.
+
+This module only *generates graphs* (vertex count, edge endpoints, integer weights) from
+numpy's seeded generator.  It holds none of the optimisation method's arithmetic: no fitness,
+no Philox, no colouring, no GOM.  Both the CPU oracle and the GPU library receive the same
+arrays produced here and nothing else.
+
+The paper's benchmark sets (fully connected graphs, 2D tori and BIQMAC instances; Section 6.2)
+are not available, so seeded stand-ins with the same structure are used:
+
+* ``torus(L, ...)`` -- an L x L grid with wrap-around on both axes (the structure of set B:
+  every vertex has exactly four neighbours, m = 2 L^2 edges).
+* ``configuration_model(n, d, ...)`` -- a random d-regular multigraph from the configuration
+  model with self-loops and repeated pairs removed (sparse, unstructured graphs in the regime
+  of the larger set-C instances).
+
+Weights are drawn after the structure from the same generator.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Graph:
+    """A simple undirected edge-weighted graph as three aligned int32 edge arrays."""
+
+    n: int
+    u: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.u.shape[0])
+
+    @property
+    def total_weight(self) -> int:
+        return int(self.w.astype(np.int64).sum())
+
+
+def _as_graph(n: int, u, v, w, name: str) -> Graph:
+    return Graph(n=int(n), u=np.ascontiguousarray(u, dtype=np.int32),
+                 v=np.ascontiguousarray(v, dtype=np.int32),
+                 w=np.ascontiguousarray(w, dtype=np.int32), name=name)
+
+
+def torus(L: int, w_lo: int, w_hi: int, seed: int) -> Graph:
+    """L x L torus; vertex id r*L + c; per vertex in row-major order its edge to the right,
+    then its edge downwards (both with wrap-around).  Weights uniform in [w_lo, w_hi]."""
+    if L < 3:
+        raise ValueError("a simple L x L torus needs L >= 3")
+    rng = np.random.default_rng(seed)
+    r, c = np.divmod(np.arange(L * L, dtype=np.int64), L)
+    vid = r * L + c
+    right = r * L + (c + 1) % L
+    down = ((r + 1) % L) * L + c
+    u = np.stack([vid, vid], axis=1).reshape(-1)
+    v = np.stack([right, down], axis=1).reshape(-1)
+    w = rng.integers(w_lo, w_hi + 1, size=u.shape[0], dtype=np.int64)
+    return _as_graph(L * L, u, v, w, f"torus{L}x{L}")
+
+
+def signed_uniform(rng: np.random.Generator, size: int, mag: int) -> np.ndarray:
+    """Integers uniform over {-mag..-1} U {1..mag} (zero excluded)."""
+    k = rng.integers(0, 2 * mag, size=size, dtype=np.int64)
+    return np.where(k < mag, k - mag, k - mag + 1)
+
+
+def configuration_model(n: int, d: int, seed: int, weights: str = "signed50",
+                        w_lo: int = 1, w_hi: int = 100) -> Graph:
+    """Random d-regular graph from the configuration model: n*d stubs shuffled, consecutive
+    stubs paired; self-loops and repeated unordered pairs are dropped (first occurrence
+    kept), so a few vertices end with degree below d.  ``weights`` is ``"signed50"``
+    (uniform over +-1..50, zero excluded) or ``"uniform"`` (uniform in [w_lo, w_hi])."""
+    if (n * d) % 2:
+        raise ValueError("n*d must be even")
+    rng = np.random.default_rng(seed)
+    stubs = np.repeat(np.arange(n, dtype=np.int64), d)
+    rng.shuffle(stubs)
+    a, b = stubs[0::2], stubs[1::2]
+    keep = a != b
+    a, b = a[keep], b[keep]
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    key = lo * n + hi
+    _, first = np.unique(key, return_index=True)
+    first.sort()
+    a, b = a[first], b[first]
+    if weights == "signed50":
+        w = signed_uniform(rng, a.shape[0], 50)
+    elif weights == "uniform":
+        w = rng.integers(w_lo, w_hi + 1, size=a.shape[0], dtype=np.int64)
+    else:
+        raise ValueError(weights)
+    return _as_graph(n, a, b, w, f"cm{n}d{d}")
+
+
+def from_edges(n: int, edges, weights=None, name: str = "") -> Graph:
+    """Graph from an explicit edge list (pairs), unit weights unless given."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    w = np.ones(e.shape[0], dtype=np.int64) if weights is None else np.asarray(weights)
+    return _as_graph(n, e[:, 0], e[:, 1], w, name)
+
+
+# Fully-specified workloads.  FOS kind: 0 = univariate, 1 = neighbourhood {v} U N(v).
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    graph_fn: object = field(repr=False)
+    fos: int
+    pop: int
+    max_gens: int
+    to_total_weight: bool  # run until the elite reaches the total weight (bipartite tori)
+    seeds: tuple = (1, 2, 3, 4, 5)
+
+    def graph(self) -> Graph:
+        return self.graph_fn()
+
+
+def _c1():
+    return torus(10, 1, 5, seed=1)
+
+
+def _c2():
+    return torus(100, 1, 100, seed=2)
+
+
+def _c3(d):
+    return lambda: configuration_model(100_000, d, seed=3, weights="signed50")
+
+
+WORKLOADS = {
+    # 10x10 torus, weights U{1..5}, univariate FOS, population 16, 20 generations.
+    "torus10_uni_p16": Workload("torus10_uni_p16", _c1, 0, 16, 20, False),
+    # 100x100 torus, weights U{1..100}, neighbourhood FOS, population 64, to optimum or 500.
+    "torus100_nbhd_p64": Workload("torus100_nbhd_p64", _c2, 1, 64, 500, True),
+}
+for _d in (3, 6, 12):
+    for _k, _fn in ((0, "uni"), (1, "nbhd")):
+        WORKLOADS[f"cm100k_d{_d}_{_fn}_p32"] = Workload(
+            f"cm100k_d{_d}_{_fn}_p32", _c3(_d), _k, 32, 200, False)
