@@ -1,0 +1,209 @@
+/*
+ * gom.h -- C ABI of libgom: parallel Gene-pool Optimal Mixing (GOM) with partial evaluations
+ * on weighted Max-Cut, parallelised by colouring the linkage-model interaction graph, on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Paper: A. Bouter, P.A.N. Bosman, "GPU-Accelerated Parallel Gene-pool Optimal Mixing in a
+ * Gray-Box Optimization Setting", arXiv 2203.08680.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns an int status: GOM_OK (0) or a negative GOM_E_* code.  No C++
+ *    exception crosses this boundary.  gom_last_error() gives a message for the last failure
+ *    on the calling thread.
+ *  - On failure, outputs are left untouched and handles are unchanged.
+ *  - Host arrays passed in are borrowed for the duration of the call (copied when kept).
+ *  - Handles are owned by the caller and released with the matching *_free call.
+ *  - Device memory is owned by the caller: a state lives inside a caller-provided device
+ *    arena of gom_state_bytes() bytes (for example a torch uint8 tensor).  The library never
+ *    allocates device memory.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream); all device work is enqueued on it.
+ *  - Vertices are 0-based.  Genes are bits: gene 1 puts the vertex on one side of the cut,
+ *    gene 0 on the other (the paper's x in {-1, 1}).
+ */
+#ifndef GOM_H
+#define GOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mc_graph mc_graph;
+typedef struct gom_fos gom_fos;
+typedef struct gom_state gom_state;
+
+enum {
+    GOM_OK = 0,
+    GOM_E_ARG = -1,    /* null pointer, bad enum, inconsistent sizes */
+    GOM_E_GRAPH = -2,  /* invalid graph: vertex out of range, self-loop, repeated edge */
+    GOM_E_RANGE = -3,  /* size outside what this build supports */
+    GOM_E_NOMEM = -4,  /* host allocation failed, or the arena is too small */
+    GOM_E_DEVICE = -5, /* a HIP call failed (message names it) */
+    GOM_E_STATE = -6   /* call not valid in the handle's current state (e.g. not coloured) */
+};
+
+enum { GOM_FOS_UNIVARIATE = 0, GOM_FOS_NEIGHBOURHOOD = 1 };
+enum { GOM_NEUTRAL_PAPER = 0, GOM_NEUTRAL_ALWAYS = 1 };
+enum { GOM_ORDER_RANDOM = 0, GOM_ORDER_FIXED = 1 };
+
+/* Largest population one state holds: one 64-bit population word per vertex. */
+#define GOM_MAX_POP 64
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *gom_last_error(void);
+
+/* ABI version (incremented on incompatible changes). */
+int gom_version(void);
+
+/*
+ * Weighted Max-Cut instance (Section 6.2: a graph G = (V, E) with a weight w(i, j) per edge).
+ * Because w is a function of the vertex pair, the graph must be simple.
+ *   n_vertices  number of vertices (>= 1)
+ *   n_edges     number of edges m (>= 1, 2m < 2^31)
+ *   u, v        host int32[m] endpoints, each in [0, n_vertices)
+ *   w           host int32[m] weights (any sign); NULL = all weights 1
+ *   out         receives the new handle
+ * Errors: GOM_E_ARG (null), GOM_E_RANGE (n < 1, m < 1, 2m >= 2^31), GOM_E_GRAPH (endpoint out
+ * of range, u == v, the same unordered pair twice).
+ * The graph is stored as CSR with each row sorted by neighbour id; total weight in int64.
+ */
+int mc_graph_load(int32_t n_vertices, int64_t n_edges, const int32_t *u, const int32_t *v,
+                  const int32_t *w, mc_graph **out);
+
+/* Sizes of a graph: vertices, edges, sum of weights, maximum degree.  Any output may be NULL. */
+int mc_graph_info(const mc_graph *g, int32_t *n, int64_t *m, int64_t *total_weight,
+                  int32_t *max_degree);
+
+/* CSR copy: row_ptr int32[n+1], col int32[2m], w int32[2m] (rows ascending by col). */
+int mc_graph_csr(const mc_graph *g, int32_t *row_ptr, int32_t *col, int32_t *w);
+
+void mc_graph_free(mc_graph *g);
+
+/*
+ * Family of subsets (FOS, the linkage model of Section 4.1): a list of variable sets that
+ * together cover every variable.
+ *   kind GOM_FOS_UNIVARIATE     set v = {v}, v = 0..n-1
+ *   kind GOM_FOS_NEIGHBOURHOOD  set v = {v} + N(v) (the vertex and its neighbours), ascending
+ * Errors: GOM_E_ARG (null, bad kind).
+ */
+int gom_fos_build(const mc_graph *g, int kind, gom_fos **out);
+
+/*
+ * FOS from explicit sets: set j holds vars[ptr[j] .. ptr[j+1]-1] (host int32 arrays,
+ * ptr[0] = 0, ptr non-decreasing).  Errors: GOM_E_ARG (null, n_sets < 1, empty set, variable
+ * out of range, a variable twice in one set, a variable in no set: the FOS must be complete).
+ */
+int gom_fos_from_sets(const mc_graph *g, int32_t n_sets, const int32_t *ptr,
+                      const int32_t *vars, gom_fos **out);
+
+/* FOS sizes: number of sets, total members, largest set.  Outputs may be NULL. */
+int gom_fos_info(const gom_fos *f, int32_t *n_sets, int64_t *n_members, int32_t *max_set);
+
+/* Copy the sets out: ptr int32[n_sets+1], vars int32[n_members] (each set ascending). */
+int gom_fos_get(const gom_fos *f, int32_t *ptr, int32_t *vars);
+
+void gom_fos_free(gom_fos *f);
+
+/*
+ * Group the FOS into mutually independent sets (Section 5.2): the Linkage Model Interaction
+ * Graph joins sets j and k when they share a variable or a graph edge joins a variable of one
+ * to a variable of the other; it is coloured greedily with Welsh-Powell (sets in order of
+ * decreasing LMIG degree, ties by increasing set index, each taking the smallest colour not
+ * held by a conflicting set coloured before it).  The LMIG is never stored.
+ * Colour classes are numbered by first appearance in that order.  The colouring is stored in
+ * the FOS handle; *n_colours receives the number of classes k.
+ */
+int gom_colour(const mc_graph *g, gom_fos *f, int32_t *n_colours);
+
+/* Read the colouring: colour_of_set int32[n_sets], class_ptr int32[k+1], class_elems
+ * int32[n_sets] (class c = class_elems[class_ptr[c] .. class_ptr[c+1]-1], ascending).
+ * Any output may be NULL.  GOM_E_STATE if gom_colour was not called. */
+int gom_colour_get(const gom_fos *f, int32_t *colour_of_set, int32_t *class_ptr,
+                   int32_t *class_elems);
+
+/* Device arena bytes needed for a state of population `pop` on (g, f).  f must be coloured.
+ * GOM_E_RANGE unless 2 <= pop <= GOM_MAX_POP. */
+int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop, size_t *bytes);
+
+/*
+ * Create a run of parallel GOMEA (Algorithm 3) on device memory:
+ *   pop           population size N, 2..GOM_MAX_POP
+ *   seed          64-bit seed of every random draw (initial population, class order, donors)
+ *   neutral_rule  GOM_NEUTRAL_PAPER: accept a step when the fitness rises, or stays equal
+ *                 and the solution (at the start of the generation) differs from the
+ *                 elitist (Section 5.3); GOM_NEUTRAL_ALWAYS: accept whenever it does not fall
+ *   class_order   GOM_ORDER_RANDOM: classes in a random order per generation (Algorithm 3);
+ *                 GOM_ORDER_FIXED: ascending class index
+ *   dev_arena     device pointer to >= gom_state_bytes() bytes, 256-byte aligned, owned by
+ *                 the caller and kept alive until gom_state_free
+ * The instance data are copied into the arena; g and f may be freed afterwards.  The initial
+ * population (uniform random genes), its fitness and the elitist are computed on the device.
+ * Returns after the device work of the initialisation has completed.
+ * Errors: GOM_E_ARG, GOM_E_RANGE, GOM_E_STATE (f not coloured), GOM_E_NOMEM (arena too small
+ * or misaligned), GOM_E_DEVICE.
+ */
+int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
+                   int neutral_rule, int class_order, void *dev_arena, size_t arena_bytes,
+                   void *stream, gom_state **out);
+
+/* Enqueue one generation (Algorithm 3: clone, every colour class in the generation's order,
+ * then P <- O and the elitist update).  Asynchronous. */
+int gom_generation(gom_state *s, void *stream);
+
+typedef struct {
+    int32_t generations; /* generations run by this call */
+    int32_t reached;     /* 1 if the elitist fitness is >= target */
+    int64_t best;        /* elitist fitness */
+    int64_t attempted;   /* cumulative (solution, set) pairs visited: N * n_sets per generation */
+    int64_t evaluated;   /* cumulative pairs that found a differing donor and were evaluated */
+    int64_t accepted;    /* cumulative accepted steps */
+} gom_result;
+
+/*
+ * Run generations until the elitist fitness is >= target or the state has run
+ * max_generations generations in total (the target is also tested before the first one).
+ * Synchronous: returns when the device work has finished.  Generations are enqueued ahead in
+ * small chunks; a generation enqueued after the target was reached does nothing on the device.
+ */
+int gom_run_to_target(gom_state *s, int64_t target, int32_t max_generations, void *stream,
+                      gom_result *out);
+
+/*
+ * Copy the state to the host (synchronous):
+ *   genes         uint8[N * n] solution-major (genes[i*n + v]) or NULL
+ *   fitness       int64[N] or NULL
+ *   elite         uint8[n] or NULL; elite_fitness, generation: or NULL
+ *   counters      int64[3] {attempted, evaluated, accepted} or NULL
+ */
+int gom_state_read(gom_state *s, void *stream, uint8_t *genes, int64_t *fitness, uint8_t *elite,
+                   int64_t *elite_fitness, int32_t *generation, int64_t *counters);
+
+/*
+ * Overwrite the state (resume from a checkpoint): genes uint8[N*n] (0/1), elite uint8[n],
+ * the elitist fitness, the generation counter and counters {attempted, evaluated, accepted}.
+ * Fitness is recomputed on the device.  GOM_E_ARG for a gene outside {0, 1}.
+ */
+int gom_state_write(gom_state *s, void *stream, const uint8_t *genes, const uint8_t *elite,
+                    int64_t elite_fitness, int32_t generation, const int64_t *counters);
+
+/*
+ * Kernel timing: when enabled, a pair of HIP events brackets every colour-class sweep launch
+ * on the launch stream.  gom_timing_read waits for the recorded events, returns the summed
+ * elapsed milliseconds and the number of launches since the last read, and resets them.
+ */
+int gom_timing_enable(gom_state *s, int enable);
+int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launches);
+
+/* Sizes of a state: vertices, population, sets, classes, largest class. */
+int gom_state_info(const gom_state *s, int32_t *n, int32_t *pop, int32_t *n_sets,
+                   int32_t *n_classes, int32_t *max_class);
+
+/* Releases host resources of the state; the caller frees the arena afterwards. */
+void gom_state_free(gom_state *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOM_H */

@@ -1,0 +1,853 @@
+// gom_host.cpp -- host side of libgom: instance and linkage-model handling, Welsh-Powell
+// colouring, the class-ordered element records, the device arena layout and the generation
+// driver behind the C ABI declared in include/gom.h.
+#include "../../include/gom.h"
+#include "gom_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace gom;
+
+// ------------------------------------------------------------------------------------------
+// Errors
+// ------------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(GOM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                                            \
+    }                                                                                        \
+    catch (const std::bad_alloc &) {                                                         \
+        return fail(GOM_E_NOMEM, "host allocation failed");                                  \
+    }                                                                                        \
+    catch (...) {                                                                            \
+        return fail(GOM_E_ARG, "unexpected internal error");                                 \
+    }
+
+// ------------------------------------------------------------------------------------------
+// Handles
+// ------------------------------------------------------------------------------------------
+struct mc_graph {
+    int32_t n = 0;
+    int64_t m = 0;
+    std::vector<int32_t> eu, ev, ew;        // edges as given
+    std::vector<int32_t> row_ptr, col, wt;  // CSR, rows ascending by neighbour
+    int64_t total_weight = 0;
+    int32_t max_degree = 0;
+};
+
+struct gom_fos {
+    int32_t n_vars = 0;
+    int32_t n_sets = 0;
+    std::vector<int32_t> ptr, vars;  // each set ascending
+    int32_t max_set = 0;
+    bool coloured = false;
+    int32_t k = 0;
+    std::vector<int32_t> colour, class_ptr, class_elems;
+};
+
+namespace {
+
+struct Layout {
+    size_t st, fit, E, P, O, eu, ev, ew, mptr, mem_v, mem_dptr, dep, total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int64_t members, int64_t deps) {
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    L.st = take(sizeof(DevState));
+    L.fit = take(sizeof(int64_t) * GOM_MAX_POP);
+    L.E = take(sizeof(uint64_t) * (size_t)((n + 63) / 64));
+    L.P = take(sizeof(uint64_t) * (size_t)n);
+    L.O = take(sizeof(uint64_t) * (size_t)n);
+    L.eu = take(sizeof(int32_t) * (size_t)m);
+    L.ev = take(sizeof(int32_t) * (size_t)m);
+    L.ew = take(sizeof(int32_t) * (size_t)m);
+    L.mptr = take(sizeof(int32_t) * (size_t)(n_sets + 1));
+    L.mem_v = take(sizeof(int32_t) * (size_t)members);
+    L.mem_dptr = take(sizeof(int32_t) * (size_t)(members + 1));
+    L.dep = take(sizeof(int2) * (size_t)deps);
+    L.total = o;
+    return L;
+}
+
+// Element records in class order: for each class position s the members of the set and, per
+// member, its dependent edges: outside neighbours as {v, w}; edges to a member with a larger
+// position inside the set as {~v, w} (each inside edge listed once).
+struct Records {
+    std::vector<int32_t> mptr, mem_v, mem_dptr;
+    std::vector<int2> dep;
+};
+
+int64_t count_deps(const mc_graph &g, const gom_fos &f) {
+    std::vector<int32_t> stamp((size_t)g.n, -1);
+    int64_t total = 0;
+    for (int32_t j = 0; j < f.n_sets; ++j) {
+        for (int32_t t = f.ptr[j]; t < f.ptr[j + 1]; ++t) stamp[f.vars[t]] = j;
+        int64_t inside2 = 0, all = 0;
+        for (int32_t t = f.ptr[j]; t < f.ptr[j + 1]; ++t) {
+            const int32_t u = f.vars[t];
+            all += g.row_ptr[u + 1] - g.row_ptr[u];
+            for (int32_t q = g.row_ptr[u]; q < g.row_ptr[u + 1]; ++q) inside2 += stamp[g.col[q]] == j;
+        }
+        total += all - inside2 / 2;
+    }
+    return total;
+}
+
+void build_records(const mc_graph &g, const gom_fos &f, Records &R) {
+    std::vector<int32_t> pos((size_t)g.n, -1), owner((size_t)g.n, -1);
+    R.mptr.assign((size_t)f.n_sets + 1, 0);
+    R.mem_v.clear();
+    R.mem_dptr.clear();
+    R.dep.clear();
+    R.mem_v.reserve((size_t)f.ptr[f.n_sets]);
+    R.mem_dptr.reserve((size_t)f.ptr[f.n_sets] + 1);
+    int32_t s = 0;
+    for (int32_t c = 0; c < f.k; ++c)
+        for (int32_t t = f.class_ptr[c]; t < f.class_ptr[c + 1]; ++t, ++s) {
+            const int32_t j = f.class_elems[t];
+            const int32_t b = f.ptr[j], e = f.ptr[j + 1];
+            for (int32_t q = b; q < e; ++q) {
+                owner[f.vars[q]] = j;
+                pos[f.vars[q]] = q - b;
+            }
+            for (int32_t q = b; q < e; ++q) {
+                const int32_t u = f.vars[q];
+                R.mem_v.push_back(u);
+                R.mem_dptr.push_back((int32_t)R.dep.size());
+                for (int32_t r = g.row_ptr[u]; r < g.row_ptr[u + 1]; ++r) {
+                    const int32_t v = g.col[r];
+                    if (owner[v] == j) {
+                        if (pos[v] > q - b) R.dep.push_back(make_int2(~v, g.wt[r]));
+                    } else {
+                        R.dep.push_back(make_int2(v, g.wt[r]));
+                    }
+                }
+            }
+            R.mptr[(size_t)s + 1] = (int32_t)R.mem_v.size();
+        }
+    R.mem_dptr.push_back((int32_t)R.dep.size());
+}
+
+}  // namespace
+
+struct gom_state {
+    int32_t n = 0, N = 0, n_sets = 0, k = 0, max_class = 0;
+    int64_t m = 0;
+    uint64_t seed = 0;
+    int rule = 0, order = 0;
+    bool univariate = false;
+    std::vector<int32_t> class_ptr;
+    char *arena = nullptr;
+    Layout L{};
+    DevState *d_st = nullptr;
+    int64_t *d_fit = nullptr;
+    uint64_t *d_E = nullptr, *d_P = nullptr, *d_O = nullptr;
+    int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
+    int32_t *d_mptr = nullptr, *d_mem_v = nullptr, *d_mem_dptr = nullptr;
+    int2 *d_dep = nullptr;
+    int32_t g_host = 0;                 // next generation index to enqueue
+    int32_t g_base = 0;                 // generation at which attempted_base was set
+    int64_t attempted_base = 0;
+    DevState *h_st = nullptr;           // two pinned host slots
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+    int max_grid = 2048;
+    bool timing = false;
+    std::vector<hipEvent_t> tev;        // begin/end pairs
+    size_t tev_used = 0;
+    double t_ms = 0.0;
+    int64_t t_launches = 0;
+};
+
+// ------------------------------------------------------------------------------------------
+// Graph
+// ------------------------------------------------------------------------------------------
+extern "C" const char *gom_last_error(void) { return g_err.c_str(); }
+extern "C" int gom_version(void) { return 1; }
+
+extern "C" int mc_graph_load(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
+                             const int32_t *w, mc_graph **out) {
+    GUARD_BEGIN
+    if (!u || !v || !out) return fail(GOM_E_ARG, "mc_graph_load: null argument");
+    if (n < 1) return fail(GOM_E_RANGE, "mc_graph_load: n_vertices must be >= 1 (got %d)", n);
+    if (m < 1 || 2 * m >= ((int64_t)1 << 31))
+        return fail(GOM_E_RANGE, "mc_graph_load: n_edges must be in [1, 2^30) (got %lld)",
+                    (long long)m);
+    for (int64_t e = 0; e < m; ++e) {
+        if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n)
+            return fail(GOM_E_GRAPH, "mc_graph_load: edge %lld endpoint out of range",
+                        (long long)e);
+        if (u[e] == v[e])
+            return fail(GOM_E_GRAPH, "mc_graph_load: edge %lld is a self-loop", (long long)e);
+    }
+    auto *g = new mc_graph;
+    g->n = n;
+    g->m = m;
+    g->eu.assign(u, u + m);
+    g->ev.assign(v, v + m);
+    if (w) g->ew.assign(w, w + m);
+    else g->ew.assign((size_t)m, 1);
+    g->row_ptr.assign((size_t)n + 1, 0);
+    for (int64_t e = 0; e < m; ++e) {
+        g->row_ptr[(size_t)u[e] + 1]++;
+        g->row_ptr[(size_t)v[e] + 1]++;
+    }
+    for (int32_t x = 0; x < n; ++x) g->row_ptr[(size_t)x + 1] += g->row_ptr[x];
+    std::vector<int32_t> fill(g->row_ptr.begin(), g->row_ptr.end() - 1);
+    std::vector<std::pair<int32_t, int32_t>> adj((size_t)(2 * m));
+    for (int64_t e = 0; e < m; ++e) {
+        adj[(size_t)fill[u[e]]++] = {v[e], g->ew[e]};
+        adj[(size_t)fill[v[e]]++] = {u[e], g->ew[e]};
+        g->total_weight += g->ew[e];
+    }
+    g->col.resize((size_t)(2 * m));
+    g->wt.resize((size_t)(2 * m));
+    for (int32_t x = 0; x < n; ++x) {
+        auto b = adj.begin() + g->row_ptr[x], e = adj.begin() + g->row_ptr[(size_t)x + 1];
+        std::sort(b, e);
+        for (auto it = b; it != e; ++it) {
+            if (it != b && it->first == (it - 1)->first) {
+                const int32_t y = it->first;
+                delete g;
+                return fail(GOM_E_GRAPH, "mc_graph_load: edge {%d, %d} appears twice", x, y);
+            }
+            g->col[(size_t)(it - adj.begin())] = it->first;
+            g->wt[(size_t)(it - adj.begin())] = it->second;
+        }
+        g->max_degree = std::max(g->max_degree, (int32_t)(e - b));
+    }
+    *out = g;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int mc_graph_info(const mc_graph *g, int32_t *n, int64_t *m, int64_t *total_weight,
+                             int32_t *max_degree) {
+    if (!g) return fail(GOM_E_ARG, "mc_graph_info: null graph");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (total_weight) *total_weight = g->total_weight;
+    if (max_degree) *max_degree = g->max_degree;
+    return GOM_OK;
+}
+
+extern "C" int mc_graph_csr(const mc_graph *g, int32_t *row_ptr, int32_t *col, int32_t *w) {
+    if (!g || !row_ptr || !col || !w) return fail(GOM_E_ARG, "mc_graph_csr: null argument");
+    std::copy(g->row_ptr.begin(), g->row_ptr.end(), row_ptr);
+    std::copy(g->col.begin(), g->col.end(), col);
+    std::copy(g->wt.begin(), g->wt.end(), w);
+    return GOM_OK;
+}
+
+extern "C" void mc_graph_free(mc_graph *g) { delete g; }
+
+// ------------------------------------------------------------------------------------------
+// FOS
+// ------------------------------------------------------------------------------------------
+extern "C" int gom_fos_build(const mc_graph *g, int kind, gom_fos **out) {
+    GUARD_BEGIN
+    if (!g || !out) return fail(GOM_E_ARG, "gom_fos_build: null argument");
+    if (kind != GOM_FOS_UNIVARIATE && kind != GOM_FOS_NEIGHBOURHOOD)
+        return fail(GOM_E_ARG, "gom_fos_build: unknown kind %d", kind);
+    auto *f = new gom_fos;
+    f->n_vars = g->n;
+    f->n_sets = g->n;
+    f->ptr.assign((size_t)g->n + 1, 0);
+    for (int32_t v = 0; v < g->n; ++v) {
+        if (kind == GOM_FOS_UNIVARIATE) {
+            f->vars.push_back(v);
+        } else {
+            // {v} + N(v), ascending: the CSR row is already ascending; insert v in place.
+            const int32_t b = g->row_ptr[v], e = g->row_ptr[(size_t)v + 1];
+            bool put = false;
+            for (int32_t q = b; q < e; ++q) {
+                if (!put && g->col[q] > v) { f->vars.push_back(v); put = true; }
+                f->vars.push_back(g->col[q]);
+            }
+            if (!put) f->vars.push_back(v);
+        }
+        f->ptr[(size_t)v + 1] = (int32_t)f->vars.size();
+        f->max_set = std::max(f->max_set, f->ptr[(size_t)v + 1] - f->ptr[v]);
+    }
+    *out = f;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_fos_from_sets(const mc_graph *g, int32_t n_sets, const int32_t *ptr,
+                                 const int32_t *vars, gom_fos **out) {
+    GUARD_BEGIN
+    if (!g || !ptr || !vars || !out) return fail(GOM_E_ARG, "gom_fos_from_sets: null argument");
+    if (n_sets < 1) return fail(GOM_E_ARG, "gom_fos_from_sets: n_sets must be >= 1");
+    if (ptr[0] != 0) return fail(GOM_E_ARG, "gom_fos_from_sets: ptr[0] must be 0");
+    std::vector<int32_t> seen((size_t)g->n, -1);
+    std::vector<char> covered((size_t)g->n, 0);
+    auto *f = new gom_fos;
+    f->n_vars = g->n;
+    f->n_sets = n_sets;
+    f->ptr.assign(ptr, ptr + n_sets + 1);
+    for (int32_t j = 0; j < n_sets; ++j) {
+        if (ptr[j + 1] <= ptr[j]) {
+            delete f;
+            return fail(GOM_E_ARG, "gom_fos_from_sets: set %d is empty or ptr decreases", j);
+        }
+        std::vector<int32_t> s(vars + ptr[j], vars + ptr[j + 1]);
+        for (int32_t x : s) {
+            if (x < 0 || x >= g->n) {
+                delete f;
+                return fail(GOM_E_ARG, "gom_fos_from_sets: variable %d out of range in set %d",
+                            x, j);
+            }
+            if (seen[x] == j) {
+                delete f;
+                return fail(GOM_E_ARG, "gom_fos_from_sets: variable %d twice in set %d", x, j);
+            }
+            seen[x] = j;
+            covered[x] = 1;
+        }
+        std::sort(s.begin(), s.end());
+        f->vars.insert(f->vars.end(), s.begin(), s.end());
+        f->max_set = std::max(f->max_set, (int32_t)s.size());
+    }
+    for (int32_t x = 0; x < g->n; ++x)
+        if (!covered[x]) {
+            delete f;
+            return fail(GOM_E_ARG, "gom_fos_from_sets: variable %d is in no set (FOS must be "
+                                   "complete)", x);
+        }
+    *out = f;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_fos_info(const gom_fos *f, int32_t *n_sets, int64_t *n_members,
+                            int32_t *max_set) {
+    if (!f) return fail(GOM_E_ARG, "gom_fos_info: null fos");
+    if (n_sets) *n_sets = f->n_sets;
+    if (n_members) *n_members = (int64_t)f->vars.size();
+    if (max_set) *max_set = f->max_set;
+    return GOM_OK;
+}
+
+extern "C" int gom_fos_get(const gom_fos *f, int32_t *ptr, int32_t *vars) {
+    if (!f || !ptr || !vars) return fail(GOM_E_ARG, "gom_fos_get: null argument");
+    std::copy(f->ptr.begin(), f->ptr.end(), ptr);
+    std::copy(f->vars.begin(), f->vars.end(), vars);
+    return GOM_OK;
+}
+
+extern "C" void gom_fos_free(gom_fos *f) { delete f; }
+
+// ------------------------------------------------------------------------------------------
+// Colouring: first-fit in Welsh-Powell order (decreasing LMIG degree, then increasing index).
+// The LMIG neighbours of set j are the sets containing a variable of N[F_j] (F_j and the
+// graph neighbours of its members); they are enumerated through a variable -> sets index
+// with a stamp array, so the LMIG is never stored.  First-fit over this order gives exactly
+// the classes of the colour-by-colour Welsh-Powell sweep.
+// ------------------------------------------------------------------------------------------
+extern "C" int gom_colour(const mc_graph *g, gom_fos *f, int32_t *n_colours) {
+    GUARD_BEGIN
+    if (!g || !f) return fail(GOM_E_ARG, "gom_colour: null argument");
+    if (f->n_vars != g->n) return fail(GOM_E_ARG, "gom_colour: FOS built for another graph");
+    const int32_t S = f->n_sets;
+    std::vector<int32_t> vs_ptr((size_t)g->n + 1, 0), vs(f->vars.size());
+    for (int32_t x : f->vars) vs_ptr[(size_t)x + 1]++;
+    for (int32_t x = 0; x < g->n; ++x) vs_ptr[(size_t)x + 1] += vs_ptr[x];
+    {
+        std::vector<int32_t> fill(vs_ptr.begin(), vs_ptr.end() - 1);
+        for (int32_t j = 0; j < S; ++j)
+            for (int32_t t = f->ptr[j]; t < f->ptr[(size_t)j + 1]; ++t)
+                vs[(size_t)fill[f->vars[t]]++] = j;
+    }
+    auto for_conflicts = [&](int32_t j, auto &&fn) {
+        for (int32_t t = f->ptr[j]; t < f->ptr[(size_t)j + 1]; ++t) {
+            const int32_t u = f->vars[t];
+            for (int32_t a = vs_ptr[u]; a < vs_ptr[(size_t)u + 1]; ++a) fn(vs[a]);
+            for (int32_t q = g->row_ptr[u]; q < g->row_ptr[(size_t)u + 1]; ++q) {
+                const int32_t x = g->col[q];
+                for (int32_t a = vs_ptr[x]; a < vs_ptr[(size_t)x + 1]; ++a) fn(vs[a]);
+            }
+        }
+    };
+    std::vector<int32_t> stamp((size_t)S, -1);
+    std::vector<int64_t> deg((size_t)S, 0);
+    for (int32_t j = 0; j < S; ++j) {
+        int64_t d = 0;
+        stamp[j] = j;
+        for_conflicts(j, [&](int32_t k) {
+            if (stamp[k] != j) { stamp[k] = j; ++d; }
+        });
+        deg[j] = d;
+    }
+    std::vector<int32_t> order((size_t)S);
+    for (int32_t j = 0; j < S; ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return deg[a] != deg[b] ? deg[a] > deg[b] : a < b;
+    });
+    std::vector<int32_t> colour((size_t)S, -1), used;
+    int32_t k = 0;
+    for (int32_t j : order) {
+        for_conflicts(j, [&](int32_t x) {
+            if (colour[x] >= 0) used[colour[x]] = j;
+        });
+        int32_t c = 0;
+        while (c < k && used[c] == j) ++c;
+        if (c == k) {
+            used.push_back(-1);
+            ++k;
+        }
+        colour[j] = c;
+    }
+    f->k = k;
+    f->colour = colour;
+    f->class_ptr.assign((size_t)k + 1, 0);
+    for (int32_t j = 0; j < S; ++j) f->class_ptr[(size_t)colour[j] + 1]++;
+    for (int32_t c = 0; c < k; ++c) f->class_ptr[(size_t)c + 1] += f->class_ptr[c];
+    f->class_elems.assign((size_t)S, 0);
+    std::vector<int32_t> fill(f->class_ptr.begin(), f->class_ptr.end() - 1);
+    for (int32_t j = 0; j < S; ++j) f->class_elems[(size_t)fill[colour[j]]++] = j;
+    f->coloured = true;
+    if (n_colours) *n_colours = k;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_colour_get(const gom_fos *f, int32_t *colour_of_set, int32_t *class_ptr,
+                              int32_t *class_elems) {
+    if (!f) return fail(GOM_E_ARG, "gom_colour_get: null fos");
+    if (!f->coloured) return fail(GOM_E_STATE, "gom_colour_get: FOS not coloured");
+    if (colour_of_set) std::copy(f->colour.begin(), f->colour.end(), colour_of_set);
+    if (class_ptr) std::copy(f->class_ptr.begin(), f->class_ptr.end(), class_ptr);
+    if (class_elems) std::copy(f->class_elems.begin(), f->class_elems.end(), class_elems);
+    return GOM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// State
+// ------------------------------------------------------------------------------------------
+static int check_state_args(const mc_graph *g, const gom_fos *f, int32_t pop) {
+    if (!g || !f) return fail(GOM_E_ARG, "null graph or fos");
+    if (f->n_vars != g->n) return fail(GOM_E_ARG, "FOS built for another graph");
+    if (!f->coloured) return fail(GOM_E_STATE, "FOS not coloured (call gom_colour first)");
+    if (pop < 2 || pop > GOM_MAX_POP)
+        return fail(GOM_E_RANGE, "population %d outside [2, %d]", pop, GOM_MAX_POP);
+    return GOM_OK;
+}
+
+extern "C" int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop, size_t *bytes) {
+    GUARD_BEGIN
+    int rc = check_state_args(g, f, pop);
+    if (rc) return rc;
+    if (!bytes) return fail(GOM_E_ARG, "gom_state_bytes: null output");
+    *bytes = make_layout(g->n, g->m, f->n_sets, (int64_t)f->vars.size(), count_deps(*g, *f)).total;
+    return GOM_OK;
+    GUARD_END
+}
+
+static std::vector<int32_t> class_order(const gom_state *s, int32_t gen) {
+    std::vector<int32_t> perm((size_t)s->k);
+    for (int32_t c = 0; c < s->k; ++c) perm[c] = c;
+    if (s->order == GOM_ORDER_RANDOM)
+        for (int32_t t = s->k - 1; t >= 1; --t) {
+            const U32x4 r = philox(s->seed, (uint32_t)gen, kOrderStream, (uint32_t)t, 0u);
+            const int32_t x = (int32_t)(((uint64_t)r.x * (uint64_t)(t + 1)) >> 32);
+            std::swap(perm[t], perm[x]);
+        }
+    return perm;
+}
+
+static int timing_record(gom_state *s, hipStream_t st, bool begin) {
+    if (!s->timing) return GOM_OK;
+    if (begin && s->tev_used + 2 > s->tev.size()) {
+        if (s->tev.size() < (size_t)(1 << 15)) {
+            const size_t grow = s->tev.size() ? s->tev.size() : 256;
+            for (size_t q = 0; q < grow; ++q) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                s->tev.push_back(e);
+            }
+        } else {
+            // Pool full: fold the recorded pairs into the running total and reuse them.
+            for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
+                float ms = 0.f;
+                HIP_TRY(hipEventSynchronize(s->tev[q + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]));
+                s->t_ms += ms;
+                s->t_launches++;
+            }
+            s->tev_used = 0;
+        }
+    }
+    HIP_TRY(hipEventRecord(s->tev[s->tev_used++], st));
+    return GOM_OK;
+}
+
+// Enqueue generation `gen` (Algorithm 3): every colour class in the generation's order, then
+// the epilogue.  Kernels skip their work when the elitist has already reached `target`.
+static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStream_t st) {
+    const std::vector<int32_t> perm = class_order(s, gen);
+    SweepArgs a{};
+    a.P = s->d_P;
+    a.O = s->d_O;
+    a.fit = s->d_fit;
+    a.st = s->d_st;
+    a.mptr = s->d_mptr;
+    a.mem_v = s->d_mem_v;
+    a.mem_dptr = s->d_mem_dptr;
+    a.dep = s->d_dep;
+    a.seed = s->seed;
+    a.target = target;
+    a.N = s->N;
+    a.gen = gen;
+    a.always = s->rule == GOM_NEUTRAL_ALWAYS;
+    for (int32_t t = 0; t < s->k; ++t) {
+        const int32_t c = perm[t];
+        a.cls = c;
+        a.cbase = s->class_ptr[c];
+        a.csize = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
+        int rc = timing_record(s, st, true);
+        if (rc) return rc;
+        HIP_TRY(launch_class_sweep(a, s->univariate, s->max_grid, st));
+        rc = timing_record(s, st, false);
+        if (rc) return rc;
+    }
+    EpilogueArgs e{};
+    e.P = s->d_P;
+    e.O = s->d_O;
+    e.E = s->d_E;
+    e.fit = s->d_fit;
+    e.st = s->d_st;
+    e.target = target;
+    e.n = s->n;
+    e.N = s->N;
+    e.mode = kEpiGeneration;
+    HIP_TRY(launch_epilogue(e, st));
+    return GOM_OK;
+}
+
+extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
+                              int neutral_rule, int class_order_kind, void *dev_arena,
+                              size_t arena_bytes, void *stream, gom_state **out) {
+    GUARD_BEGIN
+    int rc = check_state_args(g, f, pop);
+    if (rc) return rc;
+    if (!dev_arena || !out) return fail(GOM_E_ARG, "gom_state_init: null arena or output");
+    if (neutral_rule != GOM_NEUTRAL_PAPER && neutral_rule != GOM_NEUTRAL_ALWAYS)
+        return fail(GOM_E_ARG, "gom_state_init: unknown neutral rule %d", neutral_rule);
+    if (class_order_kind != GOM_ORDER_RANDOM && class_order_kind != GOM_ORDER_FIXED)
+        return fail(GOM_E_ARG, "gom_state_init: unknown class order %d", class_order_kind);
+    if ((reinterpret_cast<uintptr_t>(dev_arena) & 255) != 0)
+        return fail(GOM_E_NOMEM, "gom_state_init: arena must be 256-byte aligned");
+    Records R;
+    build_records(*g, *f, R);
+    const Layout L = make_layout(g->n, g->m, f->n_sets, (int64_t)R.mem_v.size(),
+                                 (int64_t)R.dep.size());
+    if (arena_bytes < L.total)
+        return fail(GOM_E_NOMEM, "gom_state_init: arena has %zu bytes, needs %zu", arena_bytes,
+                    L.total);
+    hipStream_t st = (hipStream_t)stream;
+    auto *s = new gom_state;
+    s->n = g->n;
+    s->m = g->m;
+    s->N = pop;
+    s->n_sets = f->n_sets;
+    s->k = f->k;
+    s->seed = seed;
+    s->rule = neutral_rule;
+    s->order = class_order_kind;
+    s->univariate = f->max_set == 1;
+    s->class_ptr = f->class_ptr;
+    for (int32_t c = 0; c < f->k; ++c)
+        s->max_class = std::max(s->max_class, f->class_ptr[(size_t)c + 1] - f->class_ptr[c]);
+    s->arena = (char *)dev_arena;
+    s->L = L;
+    s->d_st = (DevState *)(s->arena + L.st);
+    s->d_fit = (int64_t *)(s->arena + L.fit);
+    s->d_E = (uint64_t *)(s->arena + L.E);
+    s->d_P = (uint64_t *)(s->arena + L.P);
+    s->d_O = (uint64_t *)(s->arena + L.O);
+    s->d_eu = (int32_t *)(s->arena + L.eu);
+    s->d_ev = (int32_t *)(s->arena + L.ev);
+    s->d_ew = (int32_t *)(s->arena + L.ew);
+    s->d_mptr = (int32_t *)(s->arena + L.mptr);
+    s->d_mem_v = (int32_t *)(s->arena + L.mem_v);
+    s->d_mem_dptr = (int32_t *)(s->arena + L.mem_dptr);
+    s->d_dep = (int2 *)(s->arena + L.dep);
+    auto cleanup = [&](int code) {
+        gom_state_free(s);
+        return code;
+    };
+    auto h2d = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    hipError_t e = hipHostMalloc((void **)&s->h_st, 2 * sizeof(DevState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->chunk_ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->chunk_ev[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = h2d(s->d_eu, g->eu.data(), sizeof(int32_t) * (size_t)g->m);
+    if (e == hipSuccess) e = h2d(s->d_ev, g->ev.data(), sizeof(int32_t) * (size_t)g->m);
+    if (e == hipSuccess) e = h2d(s->d_ew, g->ew.data(), sizeof(int32_t) * (size_t)g->m);
+    if (e == hipSuccess) e = h2d(s->d_mptr, R.mptr.data(), sizeof(int32_t) * R.mptr.size());
+    if (e == hipSuccess) e = h2d(s->d_mem_v, R.mem_v.data(), sizeof(int32_t) * R.mem_v.size());
+    if (e == hipSuccess)
+        e = h2d(s->d_mem_dptr, R.mem_dptr.data(), sizeof(int32_t) * R.mem_dptr.size());
+    if (e == hipSuccess) e = h2d(s->d_dep, R.dep.data(), sizeof(int2) * R.dep.size());
+    if (e == hipSuccess) e = launch_init_population(s->d_P, s->d_O, s->d_fit, s->d_st, s->n, pop,
+                                                    seed, st);
+    if (e == hipSuccess) e = launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, pop,
+                                                 s->d_fit, st);
+    if (e == hipSuccess) {
+        EpilogueArgs ea{};
+        ea.P = s->d_P;
+        ea.O = s->d_O;
+        ea.E = s->d_E;
+        ea.fit = s->d_fit;
+        ea.st = s->d_st;
+        ea.target = INT64_MAX;
+        ea.n = s->n;
+        ea.N = pop;
+        ea.mode = kEpiInit;
+        e = launch_epilogue(ea, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging buffers die below
+    if (e != hipSuccess)
+        return cleanup(fail(GOM_E_DEVICE, "gom_state_init: %s", hipGetErrorString(e)));
+    *out = s;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_generation(gom_state *s, void *stream) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_generation: null state");
+    int rc = enqueue_generation(s, s->g_host, INT64_MAX, (hipStream_t)stream);
+    if (rc) return rc;
+    s->g_host++;
+    return GOM_OK;
+    GUARD_END
+}
+
+static int read_scalars(gom_state *s, hipStream_t st, DevState *h) {
+    HIP_TRY(hipMemcpyAsync(h, s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GOM_OK;
+}
+
+extern "C" int gom_run_to_target(gom_state *s, int64_t target, int32_t max_generations,
+                                 void *stream, gom_result *out) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_run_to_target: null state");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = read_scalars(s, st, &s->h_st[0]);
+    if (rc) return rc;
+    s->g_host = s->h_st[0].generation;
+    const int32_t g0 = s->g_host;
+    constexpr int32_t kChunk = 4;
+    if (s->h_st[0].elite_fitness < target && s->g_host < max_generations) {
+        int32_t issued = s->g_host;
+        int slot = 0, prev = -1;
+        for (;;) {
+            const int32_t n = std::min(kChunk, max_generations - issued);
+            int cur = -1;
+            if (n > 0) {
+                for (int32_t t = 0; t < n; ++t) {
+                    rc = enqueue_generation(s, issued + t, target, st);
+                    if (rc) return rc;
+                }
+                issued += n;
+                cur = slot;
+                HIP_TRY(hipMemcpyAsync(&s->h_st[cur], s->d_st, sizeof(DevState),
+                                       hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipEventRecord(s->chunk_ev[cur], st));
+                slot ^= 1;
+            }
+            if (prev >= 0) {
+                HIP_TRY(hipEventSynchronize(s->chunk_ev[prev]));
+                if (s->h_st[prev].elite_fitness >= target) break;
+            }
+            if (cur < 0) break;
+            prev = cur;
+        }
+    }
+    DevState fin;
+    rc = read_scalars(s, st, &fin);
+    if (rc) return rc;
+    s->g_host = fin.generation;
+    if (out) {
+        out->generations = fin.generation - g0;
+        out->reached = fin.elite_fitness >= target;
+        out->best = fin.elite_fitness;
+        out->attempted =
+            s->attempted_base + (int64_t)s->N * s->n_sets * (int64_t)(fin.generation - s->g_base);
+        out->evaluated = fin.evaluated;
+        out->accepted = fin.accepted;
+    }
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_state_read(gom_state *s, void *stream, uint8_t *genes, int64_t *fitness,
+                              uint8_t *elite, int64_t *elite_fitness, int32_t *generation,
+                              int64_t *counters) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_state_read: null state");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<uint64_t> P, E;
+    int64_t fit[GOM_MAX_POP];
+    if (genes) {
+        P.resize((size_t)s->n);
+        HIP_TRY(hipMemcpyAsync(P.data(), s->d_P, sizeof(uint64_t) * (size_t)s->n,
+                               hipMemcpyDeviceToHost, st));
+    }
+    if (elite) {
+        E.resize((size_t)((s->n + 63) / 64));
+        HIP_TRY(hipMemcpyAsync(E.data(), s->d_E, sizeof(uint64_t) * E.size(),
+                               hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipMemcpyAsync(fit, s->d_fit, sizeof(int64_t) * (size_t)s->N, hipMemcpyDeviceToHost,
+                           st));
+    DevState h;
+    int rc = read_scalars(s, st, &h);
+    if (rc) return rc;
+    if (genes)
+        for (int32_t i = 0; i < s->N; ++i) {
+            uint8_t *row = genes + (size_t)i * (size_t)s->n;
+            for (int32_t v = 0; v < s->n; ++v) row[v] = (uint8_t)((P[(size_t)v] >> i) & 1u);
+        }
+    if (elite)
+        for (int32_t v = 0; v < s->n; ++v) elite[v] = (uint8_t)((E[(size_t)v >> 6] >> (v & 63)) & 1u);
+    if (fitness) std::copy(fit, fit + s->N, fitness);
+    if (elite_fitness) *elite_fitness = h.elite_fitness;
+    if (generation) *generation = h.generation;
+    if (counters) {
+        counters[0] =
+            s->attempted_base + (int64_t)s->N * s->n_sets * (int64_t)(h.generation - s->g_base);
+        counters[1] = h.evaluated;
+        counters[2] = h.accepted;
+    }
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_state_write(gom_state *s, void *stream, const uint8_t *genes,
+                               const uint8_t *elite, int64_t elite_fitness, int32_t generation,
+                               const int64_t *counters) {
+    GUARD_BEGIN
+    if (!s || !genes || !elite || !counters) return fail(GOM_E_ARG, "gom_state_write: null argument");
+    if (generation < 0) return fail(GOM_E_ARG, "gom_state_write: negative generation");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<uint64_t> P((size_t)s->n, 0), E((size_t)((s->n + 63) / 64), 0);
+    for (int32_t i = 0; i < s->N; ++i) {
+        const uint8_t *row = genes + (size_t)i * (size_t)s->n;
+        for (int32_t v = 0; v < s->n; ++v) {
+            if (row[v] > 1) return fail(GOM_E_ARG, "gom_state_write: gene outside {0, 1}");
+            P[(size_t)v] |= (uint64_t)row[v] << i;
+        }
+    }
+    for (int32_t v = 0; v < s->n; ++v) {
+        if (elite[v] > 1) return fail(GOM_E_ARG, "gom_state_write: elite gene outside {0, 1}");
+        E[(size_t)v >> 6] |= (uint64_t)elite[v] << (v & 63);
+    }
+    DevState h{};
+    h.elite_fitness = elite_fitness;
+    h.evaluated = counters[1];
+    h.accepted = counters[2];
+    h.generation = generation;
+    HIP_TRY(hipMemcpyAsync(s->d_P, P.data(), sizeof(uint64_t) * P.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->d_O, P.data(), sizeof(uint64_t) * P.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->d_E, E.data(), sizeof(uint64_t) * E.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->d_st, &h, sizeof(DevState), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_zero_state(s->d_fit, s->d_st, st));
+    HIP_TRY(launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, s->N, s->d_fit, st));
+    EpilogueArgs ea{};
+    ea.P = s->d_P;
+    ea.O = s->d_O;
+    ea.E = s->d_E;
+    ea.fit = s->d_fit;
+    ea.st = s->d_st;
+    ea.target = INT64_MAX;
+    ea.n = s->n;
+    ea.N = s->N;
+    ea.mode = kEpiRefresh;
+    HIP_TRY(launch_epilogue(ea, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    s->g_host = generation;
+    s->g_base = generation;
+    s->attempted_base = counters[0];
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_timing_enable(gom_state *s, int enable) {
+    if (!s) return fail(GOM_E_ARG, "gom_timing_enable: null state");
+    s->timing = enable != 0;
+    return GOM_OK;
+}
+
+extern "C" int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launches) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_timing_read: null state");
+    for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventSynchronize(s->tev[q + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]));
+        s->t_ms += ms;
+        s->t_launches++;
+    }
+    s->tev_used = 0;
+    if (class_ms_total) *class_ms_total = s->t_ms;
+    if (class_launches) *class_launches = s->t_launches;
+    s->t_ms = 0.0;
+    s->t_launches = 0;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_state_info(const gom_state *s, int32_t *n, int32_t *pop, int32_t *n_sets,
+                              int32_t *n_classes, int32_t *max_class) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_info: null state");
+    if (n) *n = s->n;
+    if (pop) *pop = s->N;
+    if (n_sets) *n_sets = s->n_sets;
+    if (n_classes) *n_classes = s->k;
+    if (max_class) *max_class = s->max_class;
+    return GOM_OK;
+}
+
+extern "C" void gom_state_free(gom_state *s) {
+    if (!s) return;
+    for (hipEvent_t e : s->tev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->chunk_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->h_st) (void)hipHostFree(s->h_st);
+    delete s;
+}

@@ -1,0 +1,106 @@
+// gom_internal.h -- structures shared by the host driver (gom_host.cpp) and the kernels
+// (gom_kernels.hip) of libgom.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gom {
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), keyed by a 64-bit seed split into
+// (low, high) words.  Ten rounds; each multiplies counter words 0 and 2 by the two round
+// multipliers, swaps in the high halves xor-ed with the other words and the round key, and
+// advances the key by the two Weyl increments.  Used on the host (class order) and on the
+// device (initial population, donor draws).
+struct U32x4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ __forceinline__ U32x4 philox(uint64_t seed, uint32_t c0, uint32_t c1,
+                                                 uint32_t c2, uint32_t c3) {
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+#endif
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = n0;
+        x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {x0, x1, x2, x3};
+}
+
+// Counter word values that keep the three Philox streams apart: generation indices and class
+// indices are below 0xFFFFFFFF.
+constexpr uint32_t kInitStream = 0xFFFFFFFFu;   // counter (kInitStream, i, v/128, 0)
+constexpr uint32_t kOrderStream = 0xFFFFFFFFu;  // counter (g, kOrderStream, t, 0)
+
+// Per-run scalars the kernels read and the generation epilogue updates.
+struct alignas(64) DevState {
+    int64_t elite_fitness;   // fitness of the elitist
+    uint64_t eq;             // bit i: solution i equals the elitist (start of generation)
+    uint64_t mism;           // epilogue accumulator: solutions differing from the elitist
+    int64_t evaluated;       // cumulative pairs with a differing donor
+    int64_t accepted;        // cumulative accepted steps
+    int32_t generation;      // generations completed
+    uint32_t blocks_done;    // epilogue arrival counter (zero between launches)
+    int32_t best;            // index of the best solution at the last epilogue
+    int32_t pad[3];
+};
+
+// One colour-class sweep launch.  Element records are stored in class order: record s (class
+// position p of class c is s = class_start[c] + p) lists its members
+// mem_v[mptr[s] .. mptr[s+1]-1]; member m's dependent edges are dep[mem_dptr[m] ..
+// mem_dptr[m+1]-1], each {v, w}: v >= 0 is an outside neighbour, v < 0 encodes ~v, a member
+// with a larger position (an edge inside the set, listed once).
+struct SweepArgs {
+    const uint64_t *P;      // population at generation start, one word per vertex
+    uint64_t *O;            // offspring, one word per vertex
+    int64_t *fit;           // fitness[64]
+    const DevState *st;
+    const int32_t *mptr;
+    const int32_t *mem_v;
+    const int32_t *mem_dptr;
+    const int2 *dep;
+    uint64_t seed;
+    int64_t target;         // generation runs only while elite_fitness < target
+    int32_t N;              // population size
+    int32_t gen;            // generation index g
+    int32_t cls;            // colour class c
+    int32_t cbase;          // first record of the class
+    int32_t csize;          // number of sets in the class
+    int32_t always;         // neutral rule: 1 = accept equal fitness always
+};
+
+struct EpilogueArgs {
+    uint64_t *P;
+    const uint64_t *O;
+    uint64_t *E;            // elitist bits, bit (v mod 64) of word v / 64
+    const int64_t *fit;
+    DevState *st;
+    int64_t target;
+    int32_t n;
+    int32_t N;
+    int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh eq only
+};
+
+enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };
+
+// Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st, int n,
+                                  int N, uint64_t seed, hipStream_t s);
+hipError_t launch_zero_state(int64_t *fit, DevState *st, hipStream_t s);
+hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32_t *ev,
+                               const int32_t *ew, int64_t m, int N, int64_t *fit, hipStream_t s);
+hipError_t launch_class_sweep(const SweepArgs &a, bool univariate, int max_grid, hipStream_t s);
+hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
+
+}  // namespace gom

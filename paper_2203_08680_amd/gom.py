@@ -1,0 +1,348 @@
+"""Thin ctypes binding of libgom (include/gom.h): the same entry-point names, argument
+marshalling only.  Every step of the optimisation runs inside libgom's HIP kernels; PyTorch
+provides the device arena (a uint8 tensor) and the stream.  There is no CPU fallback: if
+libgom.so is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgom.so")
+
+GOM_OK, GOM_E_ARG, GOM_E_GRAPH, GOM_E_RANGE, GOM_E_NOMEM, GOM_E_DEVICE, GOM_E_STATE = (
+    0, -1, -2, -3, -4, -5, -6)
+GOM_FOS_UNIVARIATE, GOM_FOS_NEIGHBOURHOOD = 0, 1
+GOM_NEUTRAL_PAPER, GOM_NEUTRAL_ALWAYS = 0, 1
+GOM_ORDER_RANDOM, GOM_ORDER_FIXED = 0, 1
+GOM_MAX_POP = 64
+
+EXPORTED = (
+    "gom_last_error", "gom_version", "mc_graph_load", "mc_graph_info", "mc_graph_csr",
+    "mc_graph_free", "gom_fos_build", "gom_fos_from_sets", "gom_fos_info", "gom_fos_get",
+    "gom_fos_free", "gom_colour", "gom_colour_get", "gom_state_bytes", "gom_state_init",
+    "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
+    "gom_timing_enable", "gom_timing_read", "gom_state_info", "gom_state_free",
+)
+
+
+class GomError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libgom error {code}: {msg}")
+        self.code = code
+
+
+class gom_result(C.Structure):
+    _fields_ = [("generations", C.c_int32), ("reached", C.c_int32), ("best", C.c_int64),
+                ("attempted", C.c_int64), ("evaluated", C.c_int64), ("accepted", C.c_int64)]
+
+
+_lib = None
+_vp = C.c_void_p
+_i32, _i64, _u64, _sz = C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+_P = C.POINTER
+
+
+def lib() -> C.CDLL:
+    """Load libgom.so from the package directory (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2203_08680_amd.build "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    # torch first: its bundled HIP runtime is then the one libgom binds to (same soname), so
+    # the process holds a single runtime and the arena/stream handles are valid in libgom.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "gom_last_error": (C.c_char_p, []),
+        "gom_version": (C.c_int, []),
+        "mc_graph_load": (C.c_int, [_i32, _i64, _vp, _vp, _vp, _P(_vp)]),
+        "mc_graph_info": (C.c_int, [_vp, _P(_i32), _P(_i64), _P(_i64), _P(_i32)]),
+        "mc_graph_csr": (C.c_int, [_vp, _vp, _vp, _vp]),
+        "mc_graph_free": (None, [_vp]),
+        "gom_fos_build": (C.c_int, [_vp, C.c_int, _P(_vp)]),
+        "gom_fos_from_sets": (C.c_int, [_vp, _i32, _vp, _vp, _P(_vp)]),
+        "gom_fos_info": (C.c_int, [_vp, _P(_i32), _P(_i64), _P(_i32)]),
+        "gom_fos_get": (C.c_int, [_vp, _vp, _vp]),
+        "gom_fos_free": (None, [_vp]),
+        "gom_colour": (C.c_int, [_vp, _vp, _P(_i32)]),
+        "gom_colour_get": (C.c_int, [_vp, _vp, _vp, _vp]),
+        "gom_state_bytes": (C.c_int, [_vp, _vp, _i32, _P(_sz)]),
+        "gom_state_init": (C.c_int, [_vp, _vp, _i32, _u64, C.c_int, C.c_int, _vp, _sz, _vp,
+                                     _P(_vp)]),
+        "gom_generation": (C.c_int, [_vp, _vp]),
+        "gom_run_to_target": (C.c_int, [_vp, _i64, _i32, _vp, _P(gom_result)]),
+        "gom_state_read": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(_i64), _P(_i32), _vp]),
+        "gom_state_write": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _vp]),
+        "gom_timing_enable": (C.c_int, [_vp, C.c_int]),
+        "gom_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
+        "gom_state_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
+        "gom_state_free": (None, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != GOM_OK:
+        raise GomError(rc, lib().gom_last_error().decode())
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------------------------------
+# Graph
+# ------------------------------------------------------------------------------------------
+class McGraph:
+    """Owned mc_graph handle."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mc_graph_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        n, m, W, dmax = _i32(), _i64(), _i64(), _i32()
+        _check(lib().mc_graph_info(self.handle, C.byref(n), C.byref(m), C.byref(W),
+                                   C.byref(dmax)))
+        return {"n": n.value, "m": m.value, "total_weight": W.value, "max_degree": dmax.value}
+
+    def csr(self):
+        inf = self.info()
+        rp = np.zeros(inf["n"] + 1, np.int32)
+        col = np.zeros(2 * inf["m"], np.int32)
+        w = np.zeros(2 * inf["m"], np.int32)
+        _check(lib().mc_graph_csr(self.handle, _ptr(rp), _ptr(col), _ptr(w)))
+        return rp, col, w
+
+
+def mc_graph_load(n_vertices: int, u, v, w=None) -> McGraph:
+    u = np.ascontiguousarray(u, np.int32)
+    v = np.ascontiguousarray(v, np.int32)
+    if u.shape != v.shape:
+        raise ValueError("u and v differ in length")
+    wa = None if w is None else np.ascontiguousarray(w, np.int32)
+    if wa is not None and wa.shape != u.shape:
+        raise ValueError("w differs in length from u")
+    h = _vp()
+    _check(lib().mc_graph_load(int(n_vertices), int(u.shape[0]), _ptr(u), _ptr(v),
+                               None if wa is None else _ptr(wa), C.byref(h)))
+    return McGraph(h.value)
+
+
+# ------------------------------------------------------------------------------------------
+# FOS and colouring
+# ------------------------------------------------------------------------------------------
+class GomFos:
+    """Owned gom_fos handle."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gom_fos_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        s, mem, mx = _i32(), _i64(), _i32()
+        _check(lib().gom_fos_info(self.handle, C.byref(s), C.byref(mem), C.byref(mx)))
+        return {"n_sets": s.value, "n_members": mem.value, "max_set": mx.value}
+
+    def sets(self):
+        inf = self.info()
+        ptr = np.zeros(inf["n_sets"] + 1, np.int32)
+        vars_ = np.zeros(inf["n_members"], np.int32)
+        _check(lib().gom_fos_get(self.handle, _ptr(ptr), _ptr(vars_)))
+        return ptr, vars_
+
+
+def gom_fos_build(g: McGraph, kind: int) -> GomFos:
+    h = _vp()
+    _check(lib().gom_fos_build(g.handle, int(kind), C.byref(h)))
+    return GomFos(h.value)
+
+
+def gom_fos_from_sets(g: McGraph, ptr, vars_) -> GomFos:
+    ptr = np.ascontiguousarray(ptr, np.int32)
+    vars_ = np.ascontiguousarray(vars_, np.int32)
+    h = _vp()
+    _check(lib().gom_fos_from_sets(g.handle, int(ptr.shape[0] - 1), _ptr(ptr), _ptr(vars_),
+                                   C.byref(h)))
+    return GomFos(h.value)
+
+
+def gom_colour(g: McGraph, f: GomFos) -> int:
+    k = _i32()
+    _check(lib().gom_colour(g.handle, f.handle, C.byref(k)))
+    return k.value
+
+
+def gom_colour_get(f: GomFos, k: int):
+    """(colour_of_set, class_ptr, class_elems)."""
+    S = f.info()["n_sets"]
+    col = np.zeros(S, np.int32)
+    cp = np.zeros(k + 1, np.int32)
+    ce = np.zeros(S, np.int32)
+    _check(lib().gom_colour_get(f.handle, _ptr(col), _ptr(cp), _ptr(ce)))
+    return col, cp, ce
+
+
+# ------------------------------------------------------------------------------------------
+# State
+# ------------------------------------------------------------------------------------------
+def gom_state_bytes(g: McGraph, f: GomFos, pop: int) -> int:
+    b = _sz()
+    _check(lib().gom_state_bytes(g.handle, f.handle, int(pop), C.byref(b)))
+    return b.value
+
+
+class GomState:
+    """Owned gom_state handle plus the torch tensor that holds its device arena."""
+
+    def __init__(self, handle: int, arena, n: int, pop: int):
+        self.handle = handle
+        self.arena = arena
+        self.n = n
+        self.pop = pop
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gom_state_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        n, pop, s, k, mx = _i32(), _i32(), _i32(), _i32(), _i32()
+        _check(lib().gom_state_info(self.handle, C.byref(n), C.byref(pop), C.byref(s),
+                                    C.byref(k), C.byref(mx)))
+        return {"n": n.value, "pop": pop.value, "n_sets": s.value, "n_classes": k.value,
+                "max_class": mx.value}
+
+
+def gom_state_init(g: McGraph, f: GomFos, pop: int, seed: int,
+                   neutral_rule: int = GOM_NEUTRAL_PAPER, class_order: int = GOM_ORDER_RANDOM,
+                   device=None, stream=None) -> GomState:
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    nbytes = gom_state_bytes(g, f, pop)
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    off = (-arena.data_ptr()) % 256
+    h = _vp()
+    with torch.cuda.device(dev):
+        _check(lib().gom_state_init(g.handle, f.handle, int(pop), int(seed) & (2**64 - 1),
+                                    int(neutral_rule), int(class_order),
+                                    arena.data_ptr() + off, nbytes, _stream_handle(stream),
+                                    C.byref(h)))
+    return GomState(h.value, arena, g.info()["n"], pop)
+
+
+def gom_generation(s: GomState, stream=None):
+    _check(lib().gom_generation(s.handle, _stream_handle(stream)))
+
+
+@dataclass
+class RunResult:
+    generations: int
+    reached: bool
+    best: int
+    attempted: int
+    evaluated: int
+    accepted: int
+
+
+def gom_run_to_target(s: GomState, target: int, max_generations: int,
+                      stream=None) -> RunResult:
+    r = gom_result()
+    _check(lib().gom_run_to_target(s.handle, int(target), int(max_generations),
+                                   _stream_handle(stream), C.byref(r)))
+    return RunResult(r.generations, bool(r.reached), r.best, r.attempted, r.evaluated,
+                     r.accepted)
+
+
+def gom_state_read(s: GomState, genes: bool = True, stream=None) -> dict:
+    G = np.zeros((s.pop, s.n), np.uint8) if genes else None
+    f = np.zeros(s.pop, np.int64)
+    E = np.zeros(s.n, np.uint8)
+    fE, gen = _i64(), _i32()
+    cnt = np.zeros(3, np.int64)
+    _check(lib().gom_state_read(s.handle, _stream_handle(stream),
+                                _ptr(G) if genes else None, _ptr(f), _ptr(E), C.byref(fE),
+                                C.byref(gen), _ptr(cnt)))
+    return {"genes": G, "fitness": f, "elite": E, "elite_fitness": fE.value,
+            "generation": gen.value, "attempted": int(cnt[0]), "evaluated": int(cnt[1]),
+            "accepted": int(cnt[2])}
+
+
+def gom_state_write(s: GomState, genes, elite, elite_fitness: int, generation: int, counters,
+                    stream=None):
+    genes = np.ascontiguousarray(genes, np.uint8).reshape(s.pop, s.n)
+    elite = np.ascontiguousarray(elite, np.uint8).reshape(s.n)
+    cnt = np.ascontiguousarray(np.asarray(counters[:3], np.int64))
+    _check(lib().gom_state_write(s.handle, _stream_handle(stream), _ptr(genes), _ptr(elite),
+                                 int(elite_fitness), int(generation), _ptr(cnt)))
+
+
+def gom_timing_enable(s: GomState, enable: bool = True):
+    _check(lib().gom_timing_enable(s.handle, 1 if enable else 0))
+
+
+def gom_timing_read(s: GomState):
+    """(summed class-sweep milliseconds, launches) since the last read."""
+    ms, n = C.c_double(), _i64()
+    _check(lib().gom_timing_read(s.handle, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def gom_version() -> int:
+    return int(lib().gom_version())
+
+
+# ------------------------------------------------------------------------------------------
+# Convenience: one object for a whole instance set-up (graph + FOS + colouring)
+# ------------------------------------------------------------------------------------------
+class Instance:
+    """A loaded graph with its coloured FOS, ready to create states from."""
+
+    def __init__(self, n: int, u, v, w, fos_kind: int | None = None, sets=None):
+        self.graph = mc_graph_load(n, u, v, w)
+        if sets is not None:
+            self.fos = gom_fos_from_sets(self.graph, sets[0], sets[1])
+        else:
+            self.fos = gom_fos_build(self.graph, fos_kind)
+        self.k = gom_colour(self.graph, self.fos)
+        inf = self.graph.info()
+        self.n, self.m, self.total_weight = inf["n"], inf["m"], inf["total_weight"]
+
+    def classes(self):
+        return gom_colour_get(self.fos, self.k)
+
+    def state(self, pop: int, seed: int, neutral_rule: int = GOM_NEUTRAL_PAPER,
+              class_order: int = GOM_ORDER_RANDOM, device=None, stream=None) -> GomState:
+        return gom_state_init(self.graph, self.fos, pop, seed, neutral_rule, class_order,
+                              device, stream)

@@ -1,0 +1,192 @@
+"""GPU parity: libgom (HIP, through the C ABI) against the CPU oracle, element by element.
+
+Every comparison is exact (integer genes, fitness, elitist and counters): the method has no
+floating point, so the bar is bit-exactness.  Each case prints its name first so a failing
+GPU step can be identified from the log.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2203_08680_amd import gom
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("genes", "fitness", "elite", "elite_fitness", "generation", "attempted", "evaluated",
+        "accepted")
+
+
+def assert_same(a, b, where):
+    for key in KEYS:
+        x, y = np.asarray(a[key]), np.asarray(b[key])
+        if not np.array_equal(x, y):
+            if key == "genes":
+                bad = np.argwhere(x != y)
+                raise AssertionError(f"{where}: genes differ at {len(bad)} places, first "
+                                     f"(solution, vertex) {bad[:5].tolist()}")
+            raise AssertionError(f"{where}: {key} differs: gpu {x} oracle {y}")
+
+
+def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None):
+    if sets is None:
+        ptr, vars_ = oracle.fos(g, kind)
+        inst = gom.Instance(g.n, g.u, g.v, g.w, kind)
+    else:
+        ptr, vars_ = sets
+        inst = gom.Instance(g.n, g.u, g.v, g.w, sets=sets)
+    st = inst.state(pop=pop, seed=seed, neutral_rule=rule, class_order=order)
+    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule, order=order)
+    return inst, st, ref
+
+
+def lockstep(st, ref, gens, label, genes_every=1):
+    assert_same(gom.gom_state_read(st), ref.state(), f"{label} init")
+    for gen in range(gens):
+        gom.gom_generation(st)
+        ref.generation()
+        full = (gen % genes_every == 0) or gen == gens - 1
+        a = gom.gom_state_read(st, genes=full)
+        b = ref.state(genes=full)
+        if not full:
+            a["genes"] = b["genes"] = None
+        assert_same(a, b, f"{label} gen {gen}")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_torus10_univariate_p16_all_generations(cuda, seed):
+    """10x10 torus, weights U{1..5}, univariate FOS, population 16, 20 generations."""
+    print(f"case torus10_uni_p16 seed={seed}", flush=True)
+    g = workloads.torus(10, 1, 5, seed=1)
+    _, st, ref = make_pair(g, 0, 16, seed)
+    lockstep(st, ref, 20, f"torus10 uni seed {seed}")
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_torus100_neighbourhood_p64_first_generations(cuda, seed):
+    """100x100 torus, weights U{1..100}, neighbourhood FOS, population 64 (8 classes)."""
+    print(f"case torus100_nbhd_p64 seed={seed}", flush=True)
+    g = workloads.torus(100, 1, 100, seed=2)
+    _, st, ref = make_pair(g, 1, 64, seed)
+    lockstep(st, ref, 6, f"torus100 nbhd seed {seed}")
+
+
+RAGGED = [
+    # (n, d, fos kind, population, rule, order)
+    (1001, 4, 1, 2, 0, 0),
+    (997, 6, 1, 3, 1, 0),
+    (1500, 3, 0, 17, 0, 1),
+    (2000, 5, 1, 33, 0, 0),
+    (777, 8, 1, 50, 1, 1),
+    (1024, 4, 0, 64, 0, 0),
+    (513, 12, 1, 64, 0, 0),
+    (640, 2, 1, 31, 0, 0),
+]
+
+
+@pytest.mark.parametrize("n,d,kind,pop,rule,order", RAGGED)
+def test_random_graphs_ragged(cuda, n, d, kind, pop, rule, order):
+    """Random graphs whose sizes leave ragged tiles, populations that are not powers of two,
+    both neutral rules and both class orders."""
+    print(f"case ragged n={n} d={d} kind={kind} pop={pop} rule={rule} order={order}", flush=True)
+    if (n * d) % 2:
+        n += 1
+    g = workloads.configuration_model(n, d, seed=n + d, weights="signed50")
+    _, st, ref = make_pair(g, kind, pop, seed=n * 7 + pop, rule=rule, order=order)
+    lockstep(st, ref, 12, f"ragged n={n} d={d}")
+
+
+def test_explicit_overlapping_sets(cuda):
+    """A FOS of overlapping sets of mixed sizes (like linkage-tree nodes) on a random graph."""
+    print("case explicit overlapping sets", flush=True)
+    g = workloads.configuration_model(400, 3, seed=11, weights="uniform", w_lo=1, w_hi=9)
+    rng = np.random.default_rng(5)
+    sets = [[v] for v in range(g.n)]
+    for _ in range(150):
+        size = int(rng.integers(2, 9))
+        sets.append(sorted(rng.choice(g.n, size=size, replace=False).tolist()))
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(s) for s in sets])
+    vars_ = np.concatenate([np.asarray(s, np.int32) for s in sets])
+    _, st, ref = make_pair(g, None, 24, seed=3, sets=(ptr, vars_))
+    lockstep(st, ref, 10, "explicit sets")
+
+
+@pytest.mark.parametrize("d,kind", [(3, 0), (3, 1), (6, 0), (6, 1), (12, 0), (12, 1)])
+def test_cm100k_full_size(cuda, d, kind):
+    """Random d-regular graphs, n = 100000, weights +-U{1..50}, population 32: the full
+    instance, first two generations compared in full."""
+    print(f"case cm100k d={d} kind={kind}", flush=True)
+    g = workloads.configuration_model(100_000, d, seed=3, weights="signed50")
+    _, st, ref = make_pair(g, kind, 32, seed=1)
+    lockstep(st, ref, 2 if kind == 0 or d < 12 else 1, f"cm100k d={d} kind={kind}")
+
+
+def test_run_to_target_matches_oracle(cuda):
+    """gom_run_to_target stops at the same generation and state as the oracle's run."""
+    print("case run_to_target torus10", flush=True)
+    g = workloads.torus(10, 1, 5, seed=1)
+    for seed in (1, 2, 3):
+        _, st, ref = make_pair(g, 1, 16, seed)
+        target = ref.state()["elite_fitness"] + 40
+        r = gom.gom_run_to_target(st, target, 60)
+        ran = ref.run(target, 60)
+        assert r.generations == ran
+        a, b = gom.gom_state_read(st), ref.state()
+        assert_same(a, b, f"run_to_target seed {seed}")
+        assert r.reached == (b["elite_fitness"] >= target)
+        assert r.best == b["elite_fitness"]
+        assert (r.attempted, r.evaluated, r.accepted) == (b["attempted"], b["evaluated"],
+                                                          b["accepted"])
+
+
+def test_torus100_run_to_generation_30(cuda):
+    """The benchmark workload run through gom_run_to_target for 30 generations (the launch
+    sequence the benchmark times) against 30 oracle generations."""
+    print("case torus100 run_to_target 30 gens", flush=True)
+    g = workloads.torus(100, 1, 100, seed=2)
+    _, st, ref = make_pair(g, 1, 64, seed=1)
+    r = gom.gom_run_to_target(st, g.total_weight, 30)
+    ref.run(g.total_weight, 30)
+    assert r.generations == ref.state(genes=False)["generation"]
+    assert_same(gom.gom_state_read(st), ref.state(), "torus100 30 gens")
+
+
+def test_checkpoint_resume_is_exact(cuda):
+    """State read after 5 generations, written into a fresh state, continued 5 more: equals
+    10 uninterrupted generations (and the oracle)."""
+    print("case checkpoint/resume", flush=True)
+    g = workloads.configuration_model(3000, 4, seed=9, weights="signed50")
+    inst, st, ref = make_pair(g, 1, 40, seed=8)
+    for _ in range(5):
+        gom.gom_generation(st)
+    snap = gom.gom_state_read(st)
+    st2 = inst.state(pop=40, seed=8)
+    gom.gom_state_write(st2, snap["genes"], snap["elite"], snap["elite_fitness"],
+                        snap["generation"], [snap["attempted"], snap["evaluated"],
+                                             snap["accepted"]])
+    assert_same(gom.gom_state_read(st2), snap, "after write")
+    for _ in range(5):
+        gom.gom_generation(st)
+        gom.gom_generation(st2)
+    ref.run(1 << 62, 10)
+    a, b = gom.gom_state_read(st), gom.gom_state_read(st2)
+    assert_same(a, b, "resumed vs uninterrupted")
+    assert_same(a, ref.state(), "uninterrupted vs oracle")
+
+
+def test_converged_population_is_fixed_point(cuda):
+    """All solutions equal: no donor differs anywhere, nothing changes, nothing is evaluated."""
+    print("case converged fixed point", flush=True)
+    g = workloads.torus(12, 1, 9, seed=4)
+    inst, st, ref = make_pair(g, 1, 20, seed=2)
+    x = np.random.default_rng(0).integers(0, 2, g.n).astype(np.uint8)
+    genes = np.tile(x, (20, 1))
+    f = oracle.maxcut(g, x)
+    gom.gom_state_write(st, genes, x, f, 0, [0, 0, 0])
+    for _ in range(3):
+        gom.gom_generation(st)
+    s = gom.gom_state_read(st)
+    assert np.array_equal(s["genes"], genes)
+    assert s["evaluated"] == 0 and s["accepted"] == 0
+    assert (s["fitness"] == f).all() and s["elite_fitness"] == f

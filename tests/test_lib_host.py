@@ -1,0 +1,165 @@
+"""libgom host logic on the CPU (no GPU calls): the C ABI loads and exports every declared
+entry point, input validation, CSR, FOS builders and the Welsh-Powell colouring, the latter
+compared with the oracle's independently written colouring."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2203_08680_amd import gom
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gom.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b((?:gom|mc)_\w+)\s*\(", src,
+                       flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_entry_point(gomlib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(gomlib, name), name
+    assert set(names) == set(gom.EXPORTED)
+    assert gom.gom_version() == 1
+
+
+def test_graph_validation(gomlib):
+    with pytest.raises(gom.GomError) as e:
+        gom.mc_graph_load(3, [0, 1], [1, 3], [1, 1])
+    assert e.value.code == gom.GOM_E_GRAPH
+    with pytest.raises(gom.GomError) as e:
+        gom.mc_graph_load(3, [0, 1], [1, 1], [1, 1])
+    assert e.value.code == gom.GOM_E_GRAPH          # self-loop
+    with pytest.raises(gom.GomError) as e:
+        gom.mc_graph_load(3, [0, 1], [1, 0], [1, 1])
+    assert e.value.code == gom.GOM_E_GRAPH          # {0, 1} twice
+    with pytest.raises(gom.GomError) as e:
+        gom.mc_graph_load(3, [], [], [])
+    assert e.value.code == gom.GOM_E_RANGE          # no edges
+    with pytest.raises(gom.GomError) as e:
+        gom.mc_graph_load(0, [0], [1], [1])
+    assert e.value.code == gom.GOM_E_RANGE
+    assert "n_vertices" in gomlib.gom_last_error().decode()
+
+
+def test_graph_csr_and_info(gomlib):
+    g = workloads.configuration_model(500, 5, seed=1, weights="signed50")
+    h = gom.mc_graph_load(g.n, g.u, g.v, g.w)
+    inf = h.info()
+    assert inf["n"] == g.n and inf["m"] == g.m and inf["total_weight"] == g.total_weight
+    rp, col, w = h.csr()
+    deg = np.bincount(np.concatenate([g.u, g.v]), minlength=g.n)
+    assert np.array_equal(np.diff(rp), deg) and inf["max_degree"] == deg.max()
+    pairs = {}
+    for a, b, x in zip(g.u, g.v, g.w):
+        pairs[(int(a), int(b))] = pairs[(int(b), int(a))] = int(x)
+    for v in range(g.n):
+        row = col[rp[v]:rp[v + 1]]
+        assert np.all(np.diff(row) > 0)
+        for c, x in zip(row, w[rp[v]:rp[v + 1]]):
+            assert pairs[(v, int(c))] == int(x)
+    unit = gom.mc_graph_load(3, [0, 1], [1, 2])
+    assert unit.info()["total_weight"] == 2
+
+
+def test_fos_builders_match_oracle(gomlib):
+    g = workloads.configuration_model(300, 4, seed=2, weights="uniform")
+    h = gom.mc_graph_load(g.n, g.u, g.v, g.w)
+    for kind in (0, 1):
+        f = gom.gom_fos_build(h, kind)
+        p, v = f.sets()
+        op, ov = oracle.fos(g, kind)
+        assert np.array_equal(p, op) and np.array_equal(v, ov)
+    with pytest.raises(gom.GomError):
+        gom.gom_fos_build(h, 7)
+
+
+def test_fos_from_sets_validation(gomlib):
+    h = gom.mc_graph_load(4, [0, 1, 2], [1, 2, 3])
+    for ptr, vars_ in (([0, 2, 3], [0, 1, 2]),          # vertex 3 in no set
+                       ([0, 2, 4], [0, 0, 2, 3]),       # 0 twice in one set
+                       ([0, 0, 4], [0, 1, 2, 3]),       # empty set
+                       ([0, 2, 4], [0, 1, 2, 9])):      # out of range
+        with pytest.raises(gom.GomError) as e:
+            gom.gom_fos_from_sets(h, ptr, vars_)
+        assert e.value.code == gom.GOM_E_ARG
+    f = gom.gom_fos_from_sets(h, [0, 2, 4, 5], [3, 1, 0, 2, 1])
+    p, v = f.sets()
+    assert v.tolist() == [1, 3, 0, 2, 1]
+    assert f.info() == {"n_sets": 3, "n_members": 5, "max_set": 2}
+
+
+def test_colour_before_and_after(gomlib):
+    h = gom.mc_graph_load(4, [0, 1, 2], [1, 2, 3])
+    f = gom.gom_fos_build(h, 0)
+    with pytest.raises(gom.GomError) as e:
+        gom.gom_colour_get(f, 1)
+    assert e.value.code == gom.GOM_E_STATE
+    with pytest.raises(gom.GomError) as e:
+        gom.gom_state_bytes(h, f, 8)
+    assert e.value.code == gom.GOM_E_STATE
+    k = gom.gom_colour(h, f)
+    assert k == 2
+    for pop in (1, 65):
+        with pytest.raises(gom.GomError) as e:
+            gom.gom_state_bytes(h, f, pop)
+        assert e.value.code == gom.GOM_E_RANGE
+    assert gom.gom_state_bytes(h, f, 64) > 0
+
+
+def test_figure3_colouring(gomlib):
+    g = workloads.from_edges(5, [(0, 1), (0, 2), (1, 2), (2, 3), (2, 4), (3, 4)])
+    h = gom.mc_graph_load(g.n, g.u, g.v, g.w)
+    sets = [[0], [1], [2], [3], [4], [0, 2], [3, 4], [0, 1, 2]]
+    ptr = np.cumsum([0] + [len(s) for s in sets])
+    f = gom.gom_fos_from_sets(h, ptr, sum(sets, []))
+    k = gom.gom_colour(h, f)
+    col, cp, ce = gom.gom_colour_get(f, k)
+    assert k == 6
+    assert [ce[cp[c]:cp[c + 1]].tolist() for c in range(k)] == [[2], [5], [7], [0, 3], [1, 4],
+                                                                [6]]
+
+
+@pytest.mark.parametrize("maker,kind", [
+    (lambda: workloads.torus(10, 1, 5, 1), 0), (lambda: workloads.torus(100, 1, 100, 2), 1),
+    (lambda: workloads.configuration_model(20000, 3, 3), 1),
+    (lambda: workloads.configuration_model(20000, 12, 3), 1),
+    (lambda: workloads.configuration_model(5000, 8, 3), 0)])
+def test_colouring_equals_oracle(gomlib, maker, kind):
+    g = maker()
+    h = gom.mc_graph_load(g.n, g.u, g.v, g.w)
+    f = gom.gom_fos_build(h, kind)
+    k = gom.gom_colour(h, f)
+    col, cp, ce = gom.gom_colour_get(f, k)
+    p, v = oracle.fos(g, kind)
+    ok, ocol, _ = oracle.colour(g, p, v)
+    assert k == ok and np.array_equal(col, ocol)
+    for c in range(k):
+        members = ce[cp[c]:cp[c + 1]]
+        assert np.all(np.diff(members) > 0) and np.all(col[members] == c)
+
+
+def test_state_init_rejects_small_arena(gomlib):
+    h = gom.mc_graph_load(4, [0, 1, 2], [1, 2, 3])
+    f = gom.gom_fos_build(h, 1)
+    gom.gom_colour(h, f)
+    need = gom.gom_state_bytes(h, f, 4)
+    out = C.c_void_p()
+    rc = gomlib.gom_state_init(h.handle, f.handle, 4, 1, 0, 0, C.c_void_p(256), need - 1,
+                               None, C.byref(out))
+    assert rc == gom.GOM_E_NOMEM
+    rc = gomlib.gom_state_init(h.handle, f.handle, 4, 1, 9, 0, C.c_void_p(256), need, None,
+                               C.byref(out))
+    assert rc == gom.GOM_E_ARG
+    rc = gomlib.gom_state_init(h.handle, f.handle, 4, 1, 0, 0, C.c_void_p(257), need, None,
+                               C.byref(out))
+    assert rc == gom.GOM_E_NOMEM
