@@ -1,0 +1,201 @@
+"""Benchmark: parallel GOM partial evaluations per second and time-to-optimum on one MI355X.
+
+Workload: plain GOM (one instance per launch sequence) on a 100x100 torus (n = 10,000,
+m = 20,000), int32 weights uniform in [1, 100], neighbourhood FOS ({v} plus its 4
+neighbours), population 64, run until the elitist reaches the total weight (the optimum of a
+bipartite torus) or 500 generations; int64 fitness.
+
+A step is one whole run of the hot path: a fresh initial population on the device (new seed),
+its fitness and elitist, then generations until the target or the limit.  Timed steps use
+seeds 1..K.  `value` = attempted partial evaluations (population x FOS sets x generations,
+summed over the steps) per second of the timed region; time-to-optimum per run is reported
+beside it.
+
+Also reported: the roofline of the dominant kernel (the colour-class sweep: algorithmic bytes
+per launch over its mean launch time, from HIP events recorded around every sweep launch on
+the launch stream during the timed steps) and the CPU oracle timed on a bounded sample of the
+same workload on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = "GOM partial evals/sec and time-to-optimum at 1 GPU, batched vs plain (bit-exact)"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "torus100x100_nbhd_pop64_to_optimum_or_500"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def class_sweep_bytes(g, set_ptr, set_vars, class_ptr, class_elems, pop):
+    """Algorithmic bytes of each class-sweep launch: the population words of the vertices the
+    class's sets touch (N[F_j]: members and their neighbours) read once from O, the members'
+    words read from P and written to O, and each member's adjacency (an int32 row pointer plus
+    an int32 (neighbour, weight) pair per incident edge)."""
+    bp = pop / 8.0
+    deg = np.bincount(np.concatenate([g.u, g.v]), minlength=g.n).astype(np.int64)
+    nbrs = [[] for _ in range(g.n)]
+    for a, b in zip(g.u.tolist(), g.v.tolist()):
+        nbrs[a].append(b)
+        nbrs[b].append(a)
+    out = []
+    for c in range(len(class_ptr) - 1):
+        touched = set()
+        members = 0
+        adj = 0
+        for j in class_elems[class_ptr[c]:class_ptr[c + 1]].tolist():
+            F = set_vars[set_ptr[j]:set_ptr[j + 1]].tolist()
+            members += len(F)
+            for u in F:
+                touched.add(u)
+                touched.update(nbrs[u])
+                adj += 4 + 8 * int(deg[u])
+        out.append(bp * (len(touched) + 2 * members) + adj)
+    return np.array(out)
+
+
+def cpu_baseline(g, set_ptr, set_vars, pop, gens):
+    """The oracle, unchanged, on seed 1's first `gens` generations of the same workload."""
+    import oracle
+    run = oracle.Run(g, set_ptr, set_vars, pop=pop, seed=1)
+    t0 = time.perf_counter()
+    ran = run.run(g.total_weight, gens)
+    dt = time.perf_counter() - t0
+    s = run.state(genes=False)
+    return {"value": s["attempted"] / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"seed 1, first {ran} generations of the benchmark run "
+                      f"({s['attempted']} attempted partial evaluations in {dt:.2f} s, "
+                      "single-threaded C oracle)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-gens", type=int, default=20,
+                    help="generations of the oracle sample for the CPU baseline")
+    ap.add_argument("--schedule", choices=("auto", "class", "resident"), default="auto",
+                    help="launch schedule of the generations (results are identical)")
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="do not record HIP events around sweep launches (roofline omitted)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent instances would shard across GPUs with no communication)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_08680_amd import build as gbuild
+    from paper_2203_08680_amd import gom
+    if not os.path.exists(gom.LIB_PATH):
+        gbuild.build()
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+
+    wl = workloads.WORKLOADS["torus100_nbhd_p64"]
+    g = wl.graph()
+    target = g.total_weight
+    inst = gom.Instance(g.n, g.u, g.v, g.w, wl.fos)
+    st = inst.state(pop=wl.pop, seed=1000)
+    gom.gom_state_set_schedule(st, {"auto": gom.GOM_SCHED_AUTO,
+                                    "class": gom.GOM_SCHED_CLASS_LAUNCH,
+                                    "resident": gom.GOM_SCHED_RESIDENT}[args.schedule])
+    sched = gom.gom_state_get_schedule(st)
+    sched_name = "resident" if sched == gom.GOM_SCHED_RESIDENT else "class_launch"
+    info = st.info()
+    _, class_ptr, class_elems = inst.classes()
+    set_ptr, set_vars = inst.fos.sets()
+    cbytes = class_sweep_bytes(g, set_ptr, set_vars, class_ptr, class_elems, wl.pop)
+
+    def one_run(seed):
+        gom.gom_state_reseed(st, seed)
+        return gom.gom_run_to_target(st, target, wl.max_gens)
+
+    for w in range(args.warmup):
+        r = one_run(1000 + w)
+        log(f"warmup {w}: generations {r.generations} reached {r.reached}")
+    torch.cuda.synchronize()
+
+    if not args.no_kernel_events:
+        gom.gom_timing_enable(st, True)
+        gom.gom_timing_read(st)
+    runs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s0 = time.perf_counter()
+        r = one_run(k + 1)
+        runs.append((r, time.perf_counter() - s0))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    if not args.no_kernel_events:
+        sweep_ms, launches = gom.gom_timing_read(st)
+        gom.gom_timing_enable(st, False)
+    for k, (r, dt) in enumerate(runs):
+        log(f"step {k} seed {k + 1}: generations {r.generations} reached {r.reached} "
+            f"best {r.best}/{target} attempted {r.attempted} evaluated {r.evaluated} "
+            f"accepted {r.accepted} time {dt * 1e3:.2f} ms")
+
+    attempted = sum(r.attempted for r, _ in runs)
+    gens = sum(r.generations for r, _ in runs)
+    tto = [dt * 1e3 for r, dt in runs if r.reached]
+    value = attempted / total
+    roofline = None
+    if not args.no_kernel_events and launches:
+        # class launch: every class is swept once per generation, so the mean over launches
+        # of the algorithmic bytes is the mean over classes; resident: one launch sweeps
+        # every class of a generation
+        avg_bytes = float(cbytes.mean() if sched_name == "class_launch" else cbytes.sum())
+        avg_s = sweep_ms / 1e3 / launches
+        achieved = avg_bytes / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                    "traffic": None,
+                    "kernel": "k_class_sweep" if sched_name == "class_launch"
+                    else "k_resident_sweep",
+                    "bytes_per_launch": round(avg_bytes, 1),
+                    "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(g, set_ptr, set_vars, wl.pop, args.cpu_gens)
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": g.n, "m": g.m, "fos": "neighbourhood",
+                   "pop": wl.pop, "max_generations": wl.max_gens, "target": target,
+                   "classes": info["n_classes"], "seeds": list(range(1, args.steps + 1)),
+                   "mode": "plain", "schedule": sched_name},
+        "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,
+        "reached": len(tto), "generations_total": gens,
+        "us_per_generation": total * 1e6 / max(gens, 1),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,14 @@ int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t se
                    int neutral_rule, int class_order, void *dev_arena, size_t arena_bytes,
                    void *stream, gom_state **out);
 
+/*
+ * Start the run again from a new initial population drawn with `seed` (Algorithm 3,
+ * InitializePopulation, then the fitness of every solution and the initial elitist), keeping
+ * the instance data already in the arena.  Generation and counters restart at 0.
+ * Asynchronous: enqueued on `stream`.
+ */
+int gom_state_reseed(gom_state *s, uint64_t seed, void *stream);
+
 /* Enqueue one generation (Algorithm 3: clone, every colour class in the generation's order,
  * then P <- O and the elitist update).  Asynchronous. */
 int gom_generation(gom_state *s, void *stream);
@@ -195,6 +203,23 @@ int gom_state_write(gom_state *s, void *stream, const uint8_t *genes, const uint
  */
 int gom_timing_enable(gom_state *s, int enable);
 int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launches);
+
+/*
+ * Launch schedule of a state's generations (results are identical under every schedule):
+ *   GOM_SCHED_CLASS_LAUNCH  one kernel launch per colour class, each covering every
+ *                           (solution, set) pair of the class; suits large instances
+ *   GOM_SCHED_RESIDENT      one launch per generation, one workgroup per solution holding its
+ *                           offspring in LDS and running all classes with barriers between
+ *                           them; needs n bytes of LDS per workgroup and at most
+ *                           GOM_RESIDENT_MAX_CLASSES classes
+ *   GOM_SCHED_AUTO          resident when it fits the device, class launch otherwise
+ * GOM_E_RANGE when the resident schedule does not fit this instance or device.
+ */
+enum { GOM_SCHED_AUTO = 0, GOM_SCHED_CLASS_LAUNCH = 1, GOM_SCHED_RESIDENT = 2 };
+#define GOM_RESIDENT_MAX_CLASSES 1536
+int gom_state_set_schedule(gom_state *s, int schedule);
+/* The schedule in use (GOM_SCHED_CLASS_LAUNCH or GOM_SCHED_RESIDENT). */
+int gom_state_get_schedule(const gom_state *s, int *schedule);
 
 /* Sizes of a state: vertices, population, sets, classes, largest class. */
 int gom_state_info(const gom_state *s, int32_t *n, int32_t *pop, int32_t *n_sets,

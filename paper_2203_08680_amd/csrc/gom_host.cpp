@@ -71,12 +71,13 @@ struct gom_fos {
 namespace {
 
 struct Layout {
-    size_t st, fit, E, P, O, eu, ev, ew, mptr, mem_v, mem_dptr, dep, total;
+    size_t st, fit, E, P, O, rows, cptr, eu, ev, ew, mptr, mem_v, mem_dptr, dep, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int64_t members, int64_t deps) {
+Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
+                   int64_t members, int64_t deps) {
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -89,6 +90,8 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int64_t members, int64_
     L.E = take(sizeof(uint64_t) * (size_t)((n + 63) / 64));
     L.P = take(sizeof(uint64_t) * (size_t)n);
     L.O = take(sizeof(uint64_t) * (size_t)n);
+    L.rows = take(sizeof(uint64_t) * (size_t)pop * (size_t)((n + 63) / 64));
+    L.cptr = take(sizeof(int32_t) * (size_t)(k + 1));
     L.eu = take(sizeof(int32_t) * (size_t)m);
     L.ev = take(sizeof(int32_t) * (size_t)m);
     L.ew = take(sizeof(int32_t) * (size_t)m);
@@ -172,7 +175,10 @@ struct gom_state {
     Layout L{};
     DevState *d_st = nullptr;
     int64_t *d_fit = nullptr;
-    uint64_t *d_E = nullptr, *d_P = nullptr, *d_O = nullptr;
+    uint64_t *d_E = nullptr, *d_P = nullptr, *d_O = nullptr, *d_rows = nullptr;
+    int32_t *d_cptr = nullptr;
+    int sched = GOM_SCHED_CLASS_LAUNCH;  // schedule in use
+    bool resident_ok = false;            // resident schedule fits instance and device
     int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
     int32_t *d_mptr = nullptr, *d_mem_v = nullptr, *d_mem_dptr = nullptr;
     int2 *d_dep = nullptr;
@@ -469,7 +475,8 @@ extern "C" int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop,
     int rc = check_state_args(g, f, pop);
     if (rc) return rc;
     if (!bytes) return fail(GOM_E_ARG, "gom_state_bytes: null output");
-    *bytes = make_layout(g->n, g->m, f->n_sets, (int64_t)f->vars.size(), count_deps(*g, *f)).total;
+    *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)f->vars.size(),
+                         count_deps(*g, *f)).total;
     return GOM_OK;
     GUARD_END
 }
@@ -514,8 +521,52 @@ static int timing_record(gom_state *s, hipStream_t st, bool begin) {
 
 // Enqueue generation `gen` (Algorithm 3): every colour class in the generation's order, then
 // the epilogue.  Kernels skip their work when the elitist has already reached `target`.
+static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool rows) {
+    EpilogueArgs e{};
+    e.P = s->d_P;
+    e.O = s->d_O;
+    e.rows = rows ? s->d_rows : nullptr;
+    e.E = s->d_E;
+    e.fit = s->d_fit;
+    e.st = s->d_st;
+    e.target = target;
+    e.n = s->n;
+    e.N = s->N;
+    e.mode = kEpiGeneration;
+    e.row_words = (s->n + 63) / 64;
+    HIP_TRY(launch_epilogue(e, st));
+    return GOM_OK;
+}
+
 static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStream_t st) {
     const std::vector<int32_t> perm = class_order(s, gen);
+    if (s->sched == GOM_SCHED_RESIDENT) {
+        ResidentArgs r{};
+        r.P = s->d_P;
+        r.rows = s->d_rows;
+        r.fit = s->d_fit;
+        r.st = s->d_st;
+        r.mptr = s->d_mptr;
+        r.mem_v = s->d_mem_v;
+        r.mem_dptr = s->d_mem_dptr;
+        r.dep = s->d_dep;
+        r.class_ptr = s->d_cptr;
+        r.seed = s->seed;
+        r.target = target;
+        r.n = s->n;
+        r.N = s->N;
+        r.gen = gen;
+        r.k = s->k;
+        r.always = s->rule == GOM_NEUTRAL_ALWAYS;
+        r.row_words = (s->n + 63) / 64;
+        for (int32_t t = 0; t < s->k; ++t) r.order[t] = (uint16_t)perm[t];
+        int rc = timing_record(s, st, true);
+        if (rc) return rc;
+        HIP_TRY(launch_resident_sweep(r, s->univariate, st));
+        rc = timing_record(s, st, false);
+        if (rc) return rc;
+        return enqueue_epilogue(s, target, st, true);
+    }
     SweepArgs a{};
     a.P = s->d_P;
     a.O = s->d_O;
@@ -541,18 +592,33 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         rc = timing_record(s, st, false);
         if (rc) return rc;
     }
-    EpilogueArgs e{};
-    e.P = s->d_P;
-    e.O = s->d_O;
-    e.E = s->d_E;
-    e.fit = s->d_fit;
-    e.st = s->d_st;
-    e.target = target;
-    e.n = s->n;
-    e.N = s->N;
-    e.mode = kEpiGeneration;
-    HIP_TRY(launch_epilogue(e, st));
-    return GOM_OK;
+    return enqueue_epilogue(s, target, st, false);
+}
+
+// InitializePopulation (Algorithm 3), full fitness of every solution, initial elitist.
+static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
+    hipError_t e = launch_init_population(s->d_P, s->d_O, s->d_fit, s->d_st, s->n, s->N,
+                                          s->seed, st);
+    if (e == hipSuccess)
+        e = launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, s->N, s->d_fit, st);
+    if (e != hipSuccess) return e;
+    EpilogueArgs ea{};
+    ea.P = s->d_P;
+    ea.O = s->d_O;
+    ea.E = s->d_E;
+    ea.fit = s->d_fit;
+    ea.st = s->d_st;
+    ea.target = INT64_MAX;
+    ea.n = s->n;
+    ea.N = s->N;
+    ea.mode = kEpiInit;
+    e = launch_epilogue(ea, st);
+    if (e == hipSuccess) {
+        s->g_host = 0;
+        s->g_base = 0;
+        s->attempted_base = 0;
+    }
+    return e;
 }
 
 extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
@@ -570,7 +636,7 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
         return fail(GOM_E_NOMEM, "gom_state_init: arena must be 256-byte aligned");
     Records R;
     build_records(*g, *f, R);
-    const Layout L = make_layout(g->n, g->m, f->n_sets, (int64_t)R.mem_v.size(),
+    const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.mem_v.size(),
                                  (int64_t)R.dep.size());
     if (arena_bytes < L.total)
         return fail(GOM_E_NOMEM, "gom_state_init: arena has %zu bytes, needs %zu", arena_bytes,
@@ -596,6 +662,8 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->d_E = (uint64_t *)(s->arena + L.E);
     s->d_P = (uint64_t *)(s->arena + L.P);
     s->d_O = (uint64_t *)(s->arena + L.O);
+    s->d_rows = (uint64_t *)(s->arena + L.rows);
+    s->d_cptr = (int32_t *)(s->arena + L.cptr);
     s->d_eu = (int32_t *)(s->arena + L.eu);
     s->d_ev = (int32_t *)(s->arena + L.ev);
     s->d_ew = (int32_t *)(s->arena + L.ew);
@@ -616,32 +684,36 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     if (e == hipSuccess) e = h2d(s->d_eu, g->eu.data(), sizeof(int32_t) * (size_t)g->m);
     if (e == hipSuccess) e = h2d(s->d_ev, g->ev.data(), sizeof(int32_t) * (size_t)g->m);
     if (e == hipSuccess) e = h2d(s->d_ew, g->ew.data(), sizeof(int32_t) * (size_t)g->m);
+    if (e == hipSuccess)
+        e = h2d(s->d_cptr, f->class_ptr.data(), sizeof(int32_t) * f->class_ptr.size());
+    if (e == hipSuccess) {
+        int dev = 0, lds_max = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        s->resident_ok = e == hipSuccess && s->k <= kResidentMaxClasses &&
+                         resident_lds_bytes(s->n) <= (size_t)lds_max;
+        s->sched = s->resident_ok ? GOM_SCHED_RESIDENT : GOM_SCHED_CLASS_LAUNCH;
+    }
     if (e == hipSuccess) e = h2d(s->d_mptr, R.mptr.data(), sizeof(int32_t) * R.mptr.size());
     if (e == hipSuccess) e = h2d(s->d_mem_v, R.mem_v.data(), sizeof(int32_t) * R.mem_v.size());
     if (e == hipSuccess)
         e = h2d(s->d_mem_dptr, R.mem_dptr.data(), sizeof(int32_t) * R.mem_dptr.size());
     if (e == hipSuccess) e = h2d(s->d_dep, R.dep.data(), sizeof(int2) * R.dep.size());
-    if (e == hipSuccess) e = launch_init_population(s->d_P, s->d_O, s->d_fit, s->d_st, s->n, pop,
-                                                    seed, st);
-    if (e == hipSuccess) e = launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, pop,
-                                                 s->d_fit, st);
-    if (e == hipSuccess) {
-        EpilogueArgs ea{};
-        ea.P = s->d_P;
-        ea.O = s->d_O;
-        ea.E = s->d_E;
-        ea.fit = s->d_fit;
-        ea.st = s->d_st;
-        ea.target = INT64_MAX;
-        ea.n = s->n;
-        ea.N = pop;
-        ea.mode = kEpiInit;
-        e = launch_epilogue(ea, st);
-    }
+    if (e == hipSuccess) e = enqueue_initial_population(s, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging buffers die below
     if (e != hipSuccess)
         return cleanup(fail(GOM_E_DEVICE, "gom_state_init: %s", hipGetErrorString(e)));
     *out = s;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_state_reseed(gom_state *s, uint64_t seed, void *stream) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_state_reseed: null state");
+    s->seed = seed;
+    HIP_TRY(enqueue_initial_population(s, (hipStream_t)stream));
     return GOM_OK;
     GUARD_END
 }
@@ -830,6 +902,33 @@ extern "C" int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *cl
     s->t_launches = 0;
     return GOM_OK;
     GUARD_END
+}
+
+extern "C" int gom_state_set_schedule(gom_state *s, int schedule) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_schedule: null state");
+    switch (schedule) {
+    case GOM_SCHED_AUTO:
+        s->sched = s->resident_ok ? GOM_SCHED_RESIDENT : GOM_SCHED_CLASS_LAUNCH;
+        return GOM_OK;
+    case GOM_SCHED_CLASS_LAUNCH:
+        s->sched = schedule;
+        return GOM_OK;
+    case GOM_SCHED_RESIDENT:
+        if (!s->resident_ok)
+            return fail(GOM_E_RANGE, "gom_state_set_schedule: resident schedule needs %zu bytes "
+                        "of LDS and at most %d classes (instance: %d classes)",
+                        resident_lds_bytes(s->n), kResidentMaxClasses, s->k);
+        s->sched = schedule;
+        return GOM_OK;
+    default:
+        return fail(GOM_E_ARG, "gom_state_set_schedule: unknown schedule %d", schedule);
+    }
+}
+
+extern "C" int gom_state_get_schedule(const gom_state *s, int *schedule) {
+    if (!s || !schedule) return fail(GOM_E_ARG, "gom_state_get_schedule: null argument");
+    *schedule = s->sched;
+    return GOM_OK;
 }
 
 extern "C" int gom_state_info(const gom_state *s, int32_t *n, int32_t *pop, int32_t *n_sets,

@@ -82,7 +82,9 @@ struct SweepArgs {
 
 struct EpilogueArgs {
     uint64_t *P;
-    const uint64_t *O;
+    uint64_t *O;            // offspring planes (read; rewritten when rows is set)
+    const uint64_t *rows;   // if non-null: offspring as one bit row per solution (resident
+                            // schedule); the epilogue transposes them into P and O
     uint64_t *E;            // elitist bits, bit (v mod 64) of word v / 64
     const int64_t *fit;
     DevState *st;
@@ -90,6 +92,37 @@ struct EpilogueArgs {
     int32_t n;
     int32_t N;
     int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh eq only
+    int32_t row_words;      // words per row, ceil(n / 64)
+};
+
+// Resident schedule: one block per solution runs every colour class of a generation with
+// the solution's offspring genes held in LDS (one byte per vertex), classes separated by
+// block barriers.  Valid because donors are read from P (fixed during the generation) and
+// the acceptance test only reads P_i's equality with the elitist, so solutions do not
+// interact within a generation.
+constexpr int kResidentThreads = 1024;
+constexpr int kResidentMaxClasses = 1536;
+constexpr int kResidentChunkSlots = kResidentThreads;  // Philox calls per round (8 sets each)
+
+struct ResidentArgs {
+    const uint64_t *P;
+    uint64_t *rows;         // N rows of row_words words: bit (v mod 64) of word v / 64
+    int64_t *fit;
+    DevState *st;
+    const int32_t *mptr;
+    const int32_t *mem_v;
+    const int32_t *mem_dptr;
+    const int2 *dep;
+    const int32_t *class_ptr;
+    uint64_t seed;
+    int64_t target;
+    int32_t n;
+    int32_t N;
+    int32_t gen;
+    int32_t k;
+    int32_t always;
+    int32_t row_words;
+    uint16_t order[kResidentMaxClasses];  // class order of this generation
 };
 
 enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };
@@ -102,5 +135,7 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
                                const int32_t *ew, int64_t m, int N, int64_t *fit, hipStream_t s);
 hipError_t launch_class_sweep(const SweepArgs &a, bool univariate, int max_grid, hipStream_t s);
 hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
+hipError_t launch_resident_sweep(const ResidentArgs &a, bool univariate, hipStream_t s);
+size_t resident_lds_bytes(int n);
 
 }  // namespace gom

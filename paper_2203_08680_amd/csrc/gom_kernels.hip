@@ -8,7 +8,11 @@
 //   fit    int64 fitness per solution.
 //   records of the FOS sets in colour-class order (see SweepArgs).
 //
-// Generation = one k_class_sweep launch per colour class (in the generation's class order),
+// A generation runs under one of two schedules with identical results:
+//   class launch: one k_class_sweep launch per colour class (in the generation's class
+//     order), lane = solution, offspring in the O planes;
+//   resident:     one k_resident_sweep launch (block = solution, offspring in LDS, all
+//     classes), offspring written back as one bit row per solution;
 // then one k_epilogue launch (P <- O, elitist update, equality flags).  Integer arithmetic
 // only, so every result is exact and independent of the order in which waves run.
 #include "gom_internal.h"
@@ -321,8 +325,22 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpilogueArgs a) {
     const int v = blockIdx.x * kEpiThreads + tid;
     const bool in = v < a.n;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-    const uint64_t o = in ? a.O[v] : 0ull;
-    if (a.mode == kEpiGeneration && in) a.P[v] = o;
+    uint64_t o = 0ull;
+    if (in) {
+        if (a.rows) {
+            // resident schedule: gather bit v of every solution's row
+            const size_t wv = (size_t)(v >> 6);
+            const uint32_t sh = (uint32_t)(v & 63);
+            for (int t = 0; t < a.N; ++t)
+                o |= ((a.rows[(size_t)t * a.row_words + wv] >> sh) & 1ull) << t;
+        } else {
+            o = a.O[v];
+        }
+    }
+    if (a.mode == kEpiGeneration && in) {
+        a.P[v] = o;
+        if (a.rows) a.O[v] = o;
+    }
     uint32_t eb;
     if (newE) {
         eb = in ? bit_of(o, (uint32_t)b) : 0u;
@@ -359,6 +377,151 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpilogueArgs a) {
     }
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Resident schedule: one block per solution i runs all colour classes of one generation.
+// The solution's offspring O_i lives in LDS, one byte per vertex; lane = set.  Per class:
+// the block draws the Philox calls of the class once (thread t draws chunk t: the fields of
+// 8 consecutive class positions), then every thread takes class positions t, t + 1024, ...
+// and runs the GOM step for (i, set) exactly as the class-launch kernel does, reading the
+// donors' genes from the population words P[u] and O_i from LDS.  Sets of one class never
+// touch each other's variables or neighbours, so their byte updates do not race; a block
+// barrier separates classes.  At the end the block packs O_i into a bit row (one ballot per
+// 64 vertices), adds its fitness change to fit[i] and its counts to the run counters.
+// ------------------------------------------------------------------------------------------
+constexpr int kResRngBytes = kResidentChunkSlots * 16;
+constexpr int kResRedBytes = 256;
+
+template <bool UNI>
+__global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
+    DevState *st = a.st;
+    if (st->elite_fitness >= a.target) return;
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t(*rng)[4] = reinterpret_cast<uint32_t(*)[4]>(lds);
+    int64_t *redf = reinterpret_cast<int64_t *>(lds + kResRngBytes);
+    uint32_t *redc = reinterpret_cast<uint32_t *>(lds + kResRngBytes + 128);
+    uint8_t *ob = lds + kResRngBytes + kResRedBytes;
+
+    const int i = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    const uint64_t cand = popm & ~(1ull << i);
+    const bool neutral_ok = a.always || !bit_of(st->eq, (uint32_t)i);
+
+    for (int v = tid; v < a.n; v += kResidentThreads) ob[v] = (uint8_t)bit_of(a.P[v], (uint32_t)i);
+    __syncthreads();
+
+    int64_t facc = 0;
+    uint32_t n_eval = 0, n_acc = 0;
+    for (int t = 0; t < a.k; ++t) {
+        const int c = a.order[t];
+        const int cbase = a.class_ptr[c];
+        const int csize = a.class_ptr[c + 1] - cbase;
+        for (int base = 0; base < csize; base += 8 * kResidentChunkSlots) {
+            const int span = min(csize - base, 8 * kResidentChunkSlots);
+            if constexpr (!UNI) {
+                if (tid < ((span + 7) >> 3)) {
+                    const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)c, (uint32_t)i,
+                                           (uint32_t)((base >> 3) + tid));
+                    rng[tid][0] = r.x;
+                    rng[tid][1] = r.y;
+                    rng[tid][2] = r.z;
+                    rng[tid][3] = r.w;
+                }
+                __syncthreads();
+            }
+            for (int q = tid; q < span; q += kResidentThreads) {
+                const int s = cbase + base + q;
+                int m0, m1;
+                if constexpr (UNI) {
+                    m0 = s;
+                    m1 = s + 1;
+                } else {
+                    m0 = a.mptr[s];
+                    m1 = a.mptr[s + 1];
+                }
+                uint64_t D = 0;
+                for (int m = m0; m < m1; ++m) {
+                    const int u = a.mem_v[m];
+                    D |= a.P[u] ^ (0ull - (uint64_t)ob[u]);
+                }
+                D &= cand;
+                const uint32_t cnt = (uint32_t)__popcll(D);
+                if (cnt == 0) continue;
+                uint32_t d = 0;
+                if constexpr (!UNI) {
+                    const int f = q & 7;
+                    const uint32_t h = (rng[q >> 3][f >> 1] >> (16 * (f & 1))) & 0xFFFFu;
+                    d = select_bit(D, (h * cnt) >> 16);
+                }
+                int64_t delta = 0;
+                for (int m = m0; m < m1; ++m) {
+                    const int u = a.mem_v[m];
+                    const uint32_t oq = ob[u];
+                    uint32_t cq = 1u;
+                    if constexpr (!UNI) cq = bit_of(a.P[u], d) ^ oq;
+                    const int e1 = a.mem_dptr[m + 1];
+                    for (int e = a.mem_dptr[m]; e < e1; ++e) {
+                        const int2 en = a.dep[e];
+                        uint32_t flip, ov;
+                        if (en.x >= 0) {
+                            ov = ob[en.x];
+                            flip = cq;
+                        } else {
+                            const int v = ~en.x;
+                            ov = ob[v];
+                            flip = cq ^ (bit_of(a.P[v], d) ^ ov);
+                        }
+                        const int32_t sw = (oq == ov) ? en.y : -en.y;
+                        delta += flip ? sw : 0;
+                    }
+                }
+                ++n_eval;
+                if (delta > 0 || (delta == 0 && neutral_ok)) {
+                    for (int m = m0; m < m1; ++m) {
+                        const int u = a.mem_v[m];
+                        if constexpr (UNI) {
+                            ob[u] ^= 1u;
+                        } else {
+                            const uint32_t oq = ob[u];
+                            if (bit_of(a.P[u], d) ^ oq) ob[u] = (uint8_t)(oq ^ 1u);
+                        }
+                    }
+                    facc += delta;
+                    ++n_acc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int v0 = wave * 64; v0 < a.n; v0 += kResidentThreads) {
+        const int v = v0 + lane;
+        const uint64_t word = ballot64(v < a.n && ob[v] != 0);
+        if (lane == 0) a.rows[(size_t)i * a.row_words + (v0 >> 6)] = word;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) facc += __shfl_xor(facc, off, 64);
+    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
+    if (lane == 0) {
+        redf[wave] = facc;
+        redc[wave] = ce;
+        redc[16 + wave] = ca;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t sf = 0;
+        uint32_t se = 0, sa = 0;
+        for (int w = 0; w < kResidentThreads / 64; ++w) {
+            sf += redf[w];
+            se += redc[w];
+            sa += redc[16 + w];
+        }
+        a.fit[i] += sf;
+        if (se) atomicAdd((unsigned long long *)&st->evaluated, (unsigned long long)se);
+        if (sa) atomicAdd((unsigned long long *)&st->accepted, (unsigned long long)sa);
+    }
+}
 }  // namespace
 
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st, int n,
@@ -401,6 +564,29 @@ hipError_t launch_class_sweep(const SweepArgs &a, bool univariate, int max_grid,
         else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, false>), gd, bd, 0, s, a);
         else hipLaunchKernelGGL((k_class_sweep<64, false>), gd, bd, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+size_t resident_lds_bytes(int n) {
+    return (size_t)kResRngBytes + kResRedBytes + (((size_t)n + 15) & ~(size_t)15);
+}
+
+hipError_t launch_resident_sweep(const ResidentArgs &a, bool univariate, hipStream_t s) {
+    const size_t lds = resident_lds_bytes(a.n);
+    // Raise the dynamic LDS limit of the kernel to what this launch needs (once per size).
+    static size_t attr_bytes[2] = {0, 0};
+    const void *fn = univariate ? (const void *)k_resident_sweep<true>
+                                : (const void *)k_resident_sweep<false>;
+    if (lds > attr_bytes[univariate]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        attr_bytes[univariate] = lds;
+    }
+    if (univariate)
+        hipLaunchKernelGGL((k_resident_sweep<true>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_resident_sweep<false>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -19,13 +19,15 @@ GOM_FOS_UNIVARIATE, GOM_FOS_NEIGHBOURHOOD = 0, 1
 GOM_NEUTRAL_PAPER, GOM_NEUTRAL_ALWAYS = 0, 1
 GOM_ORDER_RANDOM, GOM_ORDER_FIXED = 0, 1
 GOM_MAX_POP = 64
+GOM_SCHED_AUTO, GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT = 0, 1, 2
 
 EXPORTED = (
     "gom_last_error", "gom_version", "mc_graph_load", "mc_graph_info", "mc_graph_csr",
     "mc_graph_free", "gom_fos_build", "gom_fos_from_sets", "gom_fos_info", "gom_fos_get",
     "gom_fos_free", "gom_colour", "gom_colour_get", "gom_state_bytes", "gom_state_init",
-    "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
-    "gom_timing_enable", "gom_timing_read", "gom_state_info", "gom_state_free",
+    "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
+    "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
+    "gom_state_info", "gom_state_free",
 )
 
 
@@ -75,12 +77,15 @@ def lib() -> C.CDLL:
         "gom_state_bytes": (C.c_int, [_vp, _vp, _i32, _P(_sz)]),
         "gom_state_init": (C.c_int, [_vp, _vp, _i32, _u64, C.c_int, C.c_int, _vp, _sz, _vp,
                                      _P(_vp)]),
+        "gom_state_reseed": (C.c_int, [_vp, _u64, _vp]),
         "gom_generation": (C.c_int, [_vp, _vp]),
         "gom_run_to_target": (C.c_int, [_vp, _i64, _i32, _vp, _P(gom_result)]),
         "gom_state_read": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(_i64), _P(_i32), _vp]),
         "gom_state_write": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _vp]),
         "gom_timing_enable": (C.c_int, [_vp, C.c_int]),
         "gom_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
+        "gom_state_set_schedule": (C.c_int, [_vp, C.c_int]),
+        "gom_state_get_schedule": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
         "gom_state_free": (None, [_vp]),
     }
@@ -262,6 +267,10 @@ def gom_state_init(g: McGraph, f: GomFos, pop: int, seed: int,
     return GomState(h.value, arena, g.info()["n"], pop)
 
 
+def gom_state_reseed(s: GomState, seed: int, stream=None):
+    _check(lib().gom_state_reseed(s.handle, int(seed) & (2**64 - 1), _stream_handle(stream)))
+
+
 def gom_generation(s: GomState, stream=None):
     _check(lib().gom_generation(s.handle, _stream_handle(stream)))
 
@@ -317,6 +326,16 @@ def gom_timing_read(s: GomState):
     ms, n = C.c_double(), _i64()
     _check(lib().gom_timing_read(s.handle, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def gom_state_set_schedule(s: GomState, schedule: int):
+    _check(lib().gom_state_set_schedule(s.handle, int(schedule)))
+
+
+def gom_state_get_schedule(s: GomState) -> int:
+    v = C.c_int()
+    _check(lib().gom_state_get_schedule(s.handle, C.byref(v)))
+    return v.value
 
 
 def gom_version() -> int:

@@ -28,7 +28,11 @@ def assert_same(a, b, where):
             raise AssertionError(f"{where}: {key} differs: gpu {x} oracle {y}")
 
 
-def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None):
+SCHEDS = [gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT]
+SCHED_IDS = ["class_launch", "resident"]
+
+
+def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None, sched=gom.GOM_SCHED_AUTO):
     if sets is None:
         ptr, vars_ = oracle.fos(g, kind)
         inst = gom.Instance(g.n, g.u, g.v, g.w, kind)
@@ -36,6 +40,7 @@ def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None):
         ptr, vars_ = sets
         inst = gom.Instance(g.n, g.u, g.v, g.w, sets=sets)
     st = inst.state(pop=pop, seed=seed, neutral_rule=rule, class_order=order)
+    gom.gom_state_set_schedule(st, sched)
     ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule, order=order)
     return inst, st, ref
 
@@ -53,21 +58,23 @@ def lockstep(st, ref, gens, label, genes_every=1):
         assert_same(a, b, f"{label} gen {gen}")
 
 
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
-def test_torus10_univariate_p16_all_generations(cuda, seed):
+def test_torus10_univariate_p16_all_generations(cuda, seed, sched):
     """10x10 torus, weights U{1..5}, univariate FOS, population 16, 20 generations."""
-    print(f"case torus10_uni_p16 seed={seed}", flush=True)
+    print(f"case torus10_uni_p16 seed={seed} sched={sched}", flush=True)
     g = workloads.torus(10, 1, 5, seed=1)
-    _, st, ref = make_pair(g, 0, 16, seed)
+    _, st, ref = make_pair(g, 0, 16, seed, sched=sched)
     lockstep(st, ref, 20, f"torus10 uni seed {seed}")
 
 
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("seed", [1, 2])
-def test_torus100_neighbourhood_p64_first_generations(cuda, seed):
+def test_torus100_neighbourhood_p64_first_generations(cuda, seed, sched):
     """100x100 torus, weights U{1..100}, neighbourhood FOS, population 64 (8 classes)."""
-    print(f"case torus100_nbhd_p64 seed={seed}", flush=True)
+    print(f"case torus100_nbhd_p64 seed={seed} sched={sched}", flush=True)
     g = workloads.torus(100, 1, 100, seed=2)
-    _, st, ref = make_pair(g, 1, 64, seed)
+    _, st, ref = make_pair(g, 1, 64, seed, sched=sched)
     lockstep(st, ref, 6, f"torus100 nbhd seed {seed}")
 
 
@@ -84,21 +91,25 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("n,d,kind,pop,rule,order", RAGGED)
-def test_random_graphs_ragged(cuda, n, d, kind, pop, rule, order):
+def test_random_graphs_ragged(cuda, n, d, kind, pop, rule, order, sched):
     """Random graphs whose sizes leave ragged tiles, populations that are not powers of two,
     both neutral rules and both class orders."""
-    print(f"case ragged n={n} d={d} kind={kind} pop={pop} rule={rule} order={order}", flush=True)
+    print(f"case ragged n={n} d={d} kind={kind} pop={pop} rule={rule} order={order} "
+          f"sched={sched}", flush=True)
     if (n * d) % 2:
         n += 1
     g = workloads.configuration_model(n, d, seed=n + d, weights="signed50")
-    _, st, ref = make_pair(g, kind, pop, seed=n * 7 + pop, rule=rule, order=order)
+    _, st, ref = make_pair(g, kind, pop, seed=n * 7 + pop, rule=rule, order=order,
+                           sched=sched)
     lockstep(st, ref, 12, f"ragged n={n} d={d}")
 
 
-def test_explicit_overlapping_sets(cuda):
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_explicit_overlapping_sets(cuda, sched):
     """A FOS of overlapping sets of mixed sizes (like linkage-tree nodes) on a random graph."""
-    print("case explicit overlapping sets", flush=True)
+    print(f"case explicit overlapping sets sched={sched}", flush=True)
     g = workloads.configuration_model(400, 3, seed=11, weights="uniform", w_lo=1, w_hi=9)
     rng = np.random.default_rng(5)
     sets = [[v] for v in range(g.n)]
@@ -108,26 +119,28 @@ def test_explicit_overlapping_sets(cuda):
     ptr = np.zeros(len(sets) + 1, np.int32)
     ptr[1:] = np.cumsum([len(s) for s in sets])
     vars_ = np.concatenate([np.asarray(s, np.int32) for s in sets])
-    _, st, ref = make_pair(g, None, 24, seed=3, sets=(ptr, vars_))
+    _, st, ref = make_pair(g, None, 24, seed=3, sets=(ptr, vars_), sched=sched)
     lockstep(st, ref, 10, "explicit sets")
 
 
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("d,kind", [(3, 0), (3, 1), (6, 0), (6, 1), (12, 0), (12, 1)])
-def test_cm100k_full_size(cuda, d, kind):
+def test_cm100k_full_size(cuda, d, kind, sched):
     """Random d-regular graphs, n = 100000, weights +-U{1..50}, population 32: the full
     instance, first two generations compared in full."""
-    print(f"case cm100k d={d} kind={kind}", flush=True)
+    print(f"case cm100k d={d} kind={kind} sched={sched}", flush=True)
     g = workloads.configuration_model(100_000, d, seed=3, weights="signed50")
-    _, st, ref = make_pair(g, kind, 32, seed=1)
+    _, st, ref = make_pair(g, kind, 32, seed=1, sched=sched)
     lockstep(st, ref, 2 if kind == 0 or d < 12 else 1, f"cm100k d={d} kind={kind}")
 
 
-def test_run_to_target_matches_oracle(cuda):
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_run_to_target_matches_oracle(cuda, sched):
     """gom_run_to_target stops at the same generation and state as the oracle's run."""
-    print("case run_to_target torus10", flush=True)
+    print(f"case run_to_target torus10 sched={sched}", flush=True)
     g = workloads.torus(10, 1, 5, seed=1)
     for seed in (1, 2, 3):
-        _, st, ref = make_pair(g, 1, 16, seed)
+        _, st, ref = make_pair(g, 1, 16, seed, sched=sched)
         target = ref.state()["elite_fitness"] + 40
         r = gom.gom_run_to_target(st, target, 60)
         ran = ref.run(target, 60)
@@ -140,12 +153,13 @@ def test_run_to_target_matches_oracle(cuda):
                                                           b["accepted"])
 
 
-def test_torus100_run_to_generation_30(cuda):
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_torus100_run_to_generation_30(cuda, sched):
     """The benchmark workload run through gom_run_to_target for 30 generations (the launch
     sequence the benchmark times) against 30 oracle generations."""
-    print("case torus100 run_to_target 30 gens", flush=True)
+    print(f"case torus100 run_to_target 30 gens sched={sched}", flush=True)
     g = workloads.torus(100, 1, 100, seed=2)
-    _, st, ref = make_pair(g, 1, 64, seed=1)
+    _, st, ref = make_pair(g, 1, 64, seed=1, sched=sched)
     r = gom.gom_run_to_target(st, g.total_weight, 30)
     ref.run(g.total_weight, 30)
     assert r.generations == ref.state(genes=False)["generation"]
@@ -154,19 +168,24 @@ def test_torus100_run_to_generation_30(cuda):
 
 def test_checkpoint_resume_is_exact(cuda):
     """State read after 5 generations, written into a fresh state, continued 5 more: equals
-    10 uninterrupted generations (and the oracle)."""
+    10 uninterrupted generations (and the oracle).  The resumed state runs the other
+    schedule, and the original switches schedule half-way."""
     print("case checkpoint/resume", flush=True)
     g = workloads.configuration_model(3000, 4, seed=9, weights="signed50")
-    inst, st, ref = make_pair(g, 1, 40, seed=8)
+    inst, st, ref = make_pair(g, 1, 40, seed=8, sched=gom.GOM_SCHED_RESIDENT)
     for _ in range(5):
         gom.gom_generation(st)
     snap = gom.gom_state_read(st)
     st2 = inst.state(pop=40, seed=8)
+    gom.gom_state_set_schedule(st2, gom.GOM_SCHED_CLASS_LAUNCH)
     gom.gom_state_write(st2, snap["genes"], snap["elite"], snap["elite_fitness"],
                         snap["generation"], [snap["attempted"], snap["evaluated"],
                                              snap["accepted"]])
     assert_same(gom.gom_state_read(st2), snap, "after write")
-    for _ in range(5):
+    for t in range(5):
+        if t == 2:
+            gom.gom_state_set_schedule(st, gom.GOM_SCHED_CLASS_LAUNCH)
+            gom.gom_state_set_schedule(st2, gom.GOM_SCHED_RESIDENT)
         gom.gom_generation(st)
         gom.gom_generation(st2)
     ref.run(1 << 62, 10)
@@ -175,11 +194,12 @@ def test_checkpoint_resume_is_exact(cuda):
     assert_same(a, ref.state(), "uninterrupted vs oracle")
 
 
-def test_converged_population_is_fixed_point(cuda):
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_converged_population_is_fixed_point(cuda, sched):
     """All solutions equal: no donor differs anywhere, nothing changes, nothing is evaluated."""
-    print("case converged fixed point", flush=True)
+    print(f"case converged fixed point sched={sched}", flush=True)
     g = workloads.torus(12, 1, 9, seed=4)
-    inst, st, ref = make_pair(g, 1, 20, seed=2)
+    inst, st, ref = make_pair(g, 1, 20, seed=2, sched=sched)
     x = np.random.default_rng(0).integers(0, 2, g.n).astype(np.uint8)
     genes = np.tile(x, (20, 1))
     f = oracle.maxcut(g, x)
@@ -190,3 +210,33 @@ def test_converged_population_is_fixed_point(cuda):
     assert np.array_equal(s["genes"], genes)
     assert s["evaluated"] == 0 and s["accepted"] == 0
     assert (s["fitness"] == f).all() and s["elite_fitness"] == f
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_reseed_equals_fresh_state(cuda, sched):
+    """gom_state_reseed restarts the run from the new seed's initial population: identical to
+    a state created with that seed, and to the oracle, through several generations."""
+    print(f"case reseed sched={sched}", flush=True)
+    g = workloads.torus(20, 1, 50, seed=6)
+    inst, st, _ = make_pair(g, 1, 48, seed=5, sched=sched)
+    for _ in range(3):
+        gom.gom_generation(st)
+    gom.gom_state_reseed(st, 9)
+    ptr, vars_ = oracle.fos(g, 1)
+    ref = oracle.Run(g, ptr, vars_, pop=48, seed=9)
+    lockstep(st, ref, 5, "reseed")
+
+
+def test_schedule_selection(cuda):
+    """AUTO picks the resident schedule when the instance fits in LDS; the class-launch
+    schedule is always available."""
+    g = workloads.torus(10, 1, 5, seed=1)
+    inst = gom.Instance(g.n, g.u, g.v, g.w, 1)
+    st = inst.state(pop=8, seed=1)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_RESIDENT
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_CLASS_LAUNCH)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_CLASS_LAUNCH
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_AUTO)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_RESIDENT
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_schedule(st, 9)
