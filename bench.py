@@ -36,46 +36,65 @@ import workloads  # noqa: E402
 
 METRIC = "GOM partial evals/sec and time-to-optimum at 1 GPU, batched vs plain (bit-exact)"
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "torus100x100_nbhd_pop64_to_optimum_or_500"
+DEFAULT_WORKLOAD = "torus100_nbhd_p64"
+WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_500"}
+
+
+# HBM traffic per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a device
+# copy of known size), with the hash of the kernel sources they were taken on.  Reported as
+# roofline.traffic only while the sources still hash the same; the summaries and commands are
+# in profiles/.
+MEASURED_TRAFFIC = {
+    ("k_resident_sweep", "torus100_nbhd_p64"): {
+        "bytes": 16226343, "source": "d34832e2e496c372",
+        "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
+    ("k_class_sweep", "torus100_nbhd_p64"): {
+        "bytes": 900751, "source": "d34832e2e496c372",
+        "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gom_kernels.hip", "gom_internal.h"):
+        with open(os.path.join(ROOT, "paper_2203_08680_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def class_sweep_bytes(g, set_ptr, set_vars, class_ptr, class_elems, pop):
+def class_sweep_bytes(csr, set_ptr, set_vars, class_ptr, class_elems, pop):
     """Algorithmic bytes of each class-sweep launch: the population words of the vertices the
     class's sets touch (N[F_j]: members and their neighbours) read once from O, the members'
     words read from P and written to O, and each member's adjacency (an int32 row pointer plus
     an int32 (neighbour, weight) pair per incident edge)."""
+    row_ptr, col, _ = csr
     bp = pop / 8.0
-    deg = np.bincount(np.concatenate([g.u, g.v]), minlength=g.n).astype(np.int64)
-    nbrs = [[] for _ in range(g.n)]
-    for a, b in zip(g.u.tolist(), g.v.tolist()):
-        nbrs[a].append(b)
-        nbrs[b].append(a)
+    deg = np.diff(row_ptr).astype(np.int64)
+    sizes = np.diff(set_ptr)
     out = []
     for c in range(len(class_ptr) - 1):
-        touched = set()
-        members = 0
-        adj = 0
-        for j in class_elems[class_ptr[c]:class_ptr[c + 1]].tolist():
-            F = set_vars[set_ptr[j]:set_ptr[j + 1]].tolist()
-            members += len(F)
-            for u in F:
-                touched.add(u)
-                touched.update(nbrs[u])
-                adj += 4 + 8 * int(deg[u])
-        out.append(bp * (len(touched) + 2 * members) + adj)
+        sets = class_elems[class_ptr[c]:class_ptr[c + 1]]
+        members = np.concatenate([set_vars[set_ptr[j]:set_ptr[j] + sizes[j]] for j in sets]) \
+            if len(sets) < 64 else set_vars[np.concatenate(
+                [np.arange(set_ptr[j], set_ptr[j + 1]) for j in sets])]
+        starts, counts = row_ptr[members], deg[members]
+        idx = np.repeat(starts - np.cumsum(counts) + counts, counts) + np.arange(counts.sum())
+        touched = np.unique(np.concatenate([members, col[idx]]))
+        out.append(bp * (touched.size + 2 * members.size) + float(np.sum(4 + 8 * counts)))
     return np.array(out)
 
 
-def cpu_baseline(g, set_ptr, set_vars, pop, gens):
+def cpu_baseline(g, set_ptr, set_vars, pop, gens, target):
     """The oracle, unchanged, on seed 1's first `gens` generations of the same workload."""
     import oracle
     run = oracle.Run(g, set_ptr, set_vars, pop=pop, seed=1)
     t0 = time.perf_counter()
-    ran = run.run(g.total_weight, gens)
+    ran = run.run(target, gens)
     dt = time.perf_counter() - t0
     s = run.state(genes=False)
     return {"value": s["attempted"] / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
@@ -94,6 +113,13 @@ def main():
                     help="generations of the oracle sample for the CPU baseline")
     ap.add_argument("--schedule", choices=("auto", "class", "resident"), default="auto",
                     help="launch schedule of the generations (results are identical)")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads.WORKLOADS),
+                    help="workload (default: the benchmark configuration)")
+    ap.add_argument("--max-gens", type=int, default=None,
+                    help="override the workload's generation limit")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="after the timed steps, run a device copy of this many MiB (a known "
+                         "byte count for scaling profiler traffic counters)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="do not record HIP events around sweep launches (roofline omitted)")
     args = ap.parse_args()
@@ -112,9 +138,10 @@ def main():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
 
-    wl = workloads.WORKLOADS["torus100_nbhd_p64"]
+    wl = workloads.WORKLOADS[args.workload]
+    max_gens = args.max_gens or wl.max_gens
     g = wl.graph()
-    target = g.total_weight
+    target = g.total_weight if wl.to_total_weight else (1 << 62)
     inst = gom.Instance(g.n, g.u, g.v, g.w, wl.fos)
     st = inst.state(pop=wl.pop, seed=1000)
     gom.gom_state_set_schedule(st, {"auto": gom.GOM_SCHED_AUTO,
@@ -125,11 +152,12 @@ def main():
     info = st.info()
     _, class_ptr, class_elems = inst.classes()
     set_ptr, set_vars = inst.fos.sets()
-    cbytes = class_sweep_bytes(g, set_ptr, set_vars, class_ptr, class_elems, wl.pop)
+    cbytes = class_sweep_bytes(inst.graph.csr(), set_ptr, set_vars, class_ptr, class_elems,
+                               wl.pop)
 
     def one_run(seed):
         gom.gom_state_reseed(st, seed)
-        return gom.gom_run_to_target(st, target, wl.max_gens)
+        return gom.gom_run_to_target(st, target, max_gens)
 
     for w in range(args.warmup):
         r = one_run(1000 + w)
@@ -151,6 +179,14 @@ def main():
     if not args.no_kernel_events:
         sweep_ms, launches = gom.gom_timing_read(st)
         gom.gom_timing_enable(st, False)
+    if args.copy_calib_mb:
+        nbytes = args.copy_calib_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
     for k, (r, dt) in enumerate(runs):
         log(f"step {k} seed {k + 1}: generations {r.generations} reached {r.reached} "
             f"best {r.best}/{target} attempted {r.attempted} evaluated {r.evaluated} "
@@ -168,16 +204,20 @@ def main():
         avg_bytes = float(cbytes.mean() if sched_name == "class_launch" else cbytes.sum())
         avg_s = sweep_ms / 1e3 / launches
         achieved = avg_bytes / avg_s / 1e9
+        kname = "k_class_sweep" if sched_name == "class_launch" else "k_resident_sweep"
+        meas = MEASURED_TRAFFIC.get((kname, args.workload))
+        traffic = meas["bytes"] if meas and meas["source"] == kernel_source_hash() else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                    "traffic": None,
+                    "traffic": traffic,
+                    "traffic_profile": meas["profile"] if traffic else None,
                     "kernel": "k_class_sweep" if sched_name == "class_launch"
                     else "k_resident_sweep",
                     "bytes_per_launch": round(avg_bytes, 1),
                     "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, set_ptr, set_vars, wl.pop, args.cpu_gens)
+        cpu = cpu_baseline(g, set_ptr, set_vars, wl.pop, min(args.cpu_gens, max_gens), target)
         log(f"cpu baseline: {cpu}")
 
     line = {
@@ -185,8 +225,10 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": total * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": g.n, "m": g.m, "fos": "neighbourhood",
-                   "pop": wl.pop, "max_generations": wl.max_gens, "target": target,
+        "config": {"workload": WORKLOAD_NAMES.get(args.workload, args.workload), "n": g.n,
+                   "m": g.m, "fos": "neighbourhood" if wl.fos == 1 else "univariate",
+                   "pop": wl.pop, "max_generations": max_gens,
+                   "target": target if wl.to_total_weight else None,
                    "classes": info["n_classes"], "seeds": list(range(1, args.steps + 1)),
                    "mode": "plain", "schedule": sched_name},
         "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,

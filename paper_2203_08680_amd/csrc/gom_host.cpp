@@ -71,13 +71,13 @@ struct gom_fos {
 namespace {
 
 struct Layout {
-    size_t st, fit, E, P, O, rows, cptr, eu, ev, ew, mptr, mem_v, mem_dptr, dep, total;
+    size_t st, fit, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
-                   int64_t members, int64_t deps) {
+                   int64_t rec_words) {
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -92,74 +92,135 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
     L.O = take(sizeof(uint64_t) * (size_t)n);
     L.rows = take(sizeof(uint64_t) * (size_t)pop * (size_t)((n + 63) / 64));
     L.cptr = take(sizeof(int32_t) * (size_t)(k + 1));
+    L.crec = take(sizeof(int2) * (size_t)k);
     L.eu = take(sizeof(int32_t) * (size_t)m);
     L.ev = take(sizeof(int32_t) * (size_t)m);
     L.ew = take(sizeof(int32_t) * (size_t)m);
-    L.mptr = take(sizeof(int32_t) * (size_t)(n_sets + 1));
-    L.mem_v = take(sizeof(int32_t) * (size_t)members);
-    L.mem_dptr = take(sizeof(int32_t) * (size_t)(members + 1));
-    L.dep = take(sizeof(int2) * (size_t)deps);
+    L.roff = take(sizeof(int32_t) * (size_t)(n_sets + 1));
+    L.recs = take(sizeof(int32_t) * (size_t)rec_words);
     L.total = o;
     return L;
 }
 
-// Element records in class order: for each class position s the members of the set and, per
-// member, its dependent edges: outside neighbours as {v, w}; edges to a member with a larger
-// position inside the set as {~v, w} (each inside edge listed once).
+// Set records in class order, one per class position s, at word offset roff[s] of `words`,
+// each on a 16-byte boundary (layout documented in gom_kernels.hip): the set's variables and
+// the edges that depend on them, split into outside edges (to a vertex v outside the set) and
+// inside edges (both ends in the set, listed once).  16 zero words follow the last record so
+// the kernels' fixed-size header reads stay inside the buffer.
 struct Records {
-    std::vector<int32_t> mptr, mem_v, mem_dptr;
-    std::vector<int2> dep;
+    std::vector<int32_t> roff, words;
+    std::vector<int2> class_rec;  // per class {first word, stride or 0}
 };
 
-int64_t count_deps(const mc_graph &g, const gom_fos &f) {
-    std::vector<int32_t> stamp((size_t)g.n, -1);
-    int64_t total = 0;
-    for (int32_t j = 0; j < f.n_sets; ++j) {
-        for (int32_t t = f.ptr[j]; t < f.ptr[j + 1]; ++t) stamp[f.vars[t]] = j;
-        int64_t inside2 = 0, all = 0;
-        for (int32_t t = f.ptr[j]; t < f.ptr[j + 1]; ++t) {
-            const int32_t u = f.vars[t];
-            all += g.row_ptr[u + 1] - g.row_ptr[u];
-            for (int32_t q = g.row_ptr[u]; q < g.row_ptr[u + 1]; ++q) inside2 += stamp[g.col[q]] == j;
-        }
-        total += all - inside2 / 2;
-    }
-    return total;
-}
+constexpr int kSmallSet = 7;
+constexpr int32_t kMaxVertexSmall = 1 << 28;
 
-void build_records(const mc_graph &g, const gom_fos &f, Records &R) {
+int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records &R) {
+    const int32_t S = f.n_sets;
     std::vector<int32_t> pos((size_t)g.n, -1), owner((size_t)g.n, -1);
-    R.mptr.assign((size_t)f.n_sets + 1, 0);
-    R.mem_v.clear();
-    R.mem_dptr.clear();
-    R.dep.clear();
-    R.mem_v.reserve((size_t)f.ptr[f.n_sets]);
-    R.mem_dptr.reserve((size_t)f.ptr[f.n_sets] + 1);
+    R.roff.assign((size_t)S + 1, 0);
+    R.words.clear();
+    auto pad4 = [&]() {
+        while (R.words.size() & 3) R.words.push_back(0);
+    };
+    std::vector<std::pair<int32_t, int32_t>> ent;  // (x, w)
+    std::vector<int32_t> ends;
+    R.class_rec.assign((size_t)f.k, make_int2(0, 0));
     int32_t s = 0;
-    for (int32_t c = 0; c < f.k; ++c)
-        for (int32_t t = f.class_ptr[c]; t < f.class_ptr[c + 1]; ++t, ++s) {
+    for (int32_t c = 0; c < f.k; ++c) {
+        const size_t class_first = R.words.size();
+        const int32_t s_first = s;
+        for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t, ++s) {
+            if (R.words.size() >= (size_t)INT32_MAX / 2)
+                return fail(GOM_E_RANGE, "set records exceed 2^30 words");
+            R.roff[s] = (int32_t)R.words.size();
             const int32_t j = f.class_elems[t];
-            const int32_t b = f.ptr[j], e = f.ptr[j + 1];
+            const int32_t b = f.ptr[j], e = f.ptr[(size_t)j + 1], nm = e - b;
+            if (univariate) {
+                const int32_t u = f.vars[b];
+                const int32_t nd = g.row_ptr[(size_t)u + 1] - g.row_ptr[u];
+                R.words.insert(R.words.end(), {u, nd, 0, 0});
+                for (int32_t r = g.row_ptr[u]; r < g.row_ptr[(size_t)u + 1]; ++r) {
+                    R.words.push_back(g.col[r]);
+                    R.words.push_back(g.wt[r]);
+                }
+                pad4();
+                continue;
+            }
             for (int32_t q = b; q < e; ++q) {
                 owner[f.vars[q]] = j;
                 pos[f.vars[q]] = q - b;
             }
-            for (int32_t q = b; q < e; ++q) {
-                const int32_t u = f.vars[q];
-                R.mem_v.push_back(u);
-                R.mem_dptr.push_back((int32_t)R.dep.size());
-                for (int32_t r = g.row_ptr[u]; r < g.row_ptr[u + 1]; ++r) {
+            const bool small = nm <= kSmallSet;
+            ent.clear();
+            ends.clear();
+            for (int32_t q = 0; q < nm; ++q) {
+                const int32_t u = f.vars[b + q];
+                for (int32_t r = g.row_ptr[u]; r < g.row_ptr[(size_t)u + 1]; ++r) {
                     const int32_t v = g.col[r];
                     if (owner[v] == j) {
-                        if (pos[v] > q - b) R.dep.push_back(make_int2(~v, g.wt[r]));
+                        if (pos[v] > q)
+                            ent.push_back({small ? (int32_t)(0x80000000u | ((uint32_t)q << 28) |
+                                                             (uint32_t)pos[v])
+                                                 : ~pos[v],
+                                           g.wt[r]});
                     } else {
-                        R.dep.push_back(make_int2(v, g.wt[r]));
+                        ent.push_back({small ? (int32_t)(((uint32_t)q << 28) | (uint32_t)v) : v,
+                                       g.wt[r]});
                     }
                 }
+                ends.push_back((int32_t)ent.size());
             }
-            R.mptr[(size_t)s + 1] = (int32_t)R.mem_v.size();
+            const int32_t nd = (int32_t)ent.size();
+            R.words.push_back(nm);
+            R.words.push_back(nd);
+            if (small) {
+                for (int32_t q = 0; q < kSmallSet; ++q) R.words.push_back(q < nm ? f.vars[b + q] : -1);
+                for (int32_t q = 0; q < kSmallSet; ++q) R.words.push_back(q < nm ? ends[q] : nd);
+            } else {
+                for (int q = 0; q < 14; ++q) R.words.push_back(0);
+                for (int32_t q = 0; q < nm; ++q) R.words.push_back(f.vars[b + q]);
+                for (int32_t q = 0; q < nm; ++q) R.words.push_back(ends[q]);
+                pad4();
+            }
+            for (const auto &xw : ent) {
+                R.words.push_back(xw.first);
+                R.words.push_back(xw.second);
+            }
+            pad4();
         }
-    R.mem_dptr.push_back((int32_t)R.dep.size());
+        // Pad the class's records to one size when that costs at most a quarter more words:
+        // the kernels then locate record p at first + p * stride without reading roff.
+        const int32_t cnt = s - s_first;
+        if (cnt == 0) continue;
+        int32_t longest = 0;
+        for (int32_t q = s_first; q < s; ++q) {
+            const int32_t len =
+                (q + 1 < s ? R.roff[q + 1] : (int32_t)R.words.size()) - R.roff[q];
+            longest = std::max(longest, len);
+        }
+        const size_t used = R.words.size() - class_first;
+        if ((size_t)longest * (size_t)cnt * 4 <= used * 5) {
+            std::vector<int32_t> block(R.words.begin() + (ptrdiff_t)class_first, R.words.end());
+            R.words.resize(class_first);
+            for (int32_t q = s_first; q < s; ++q) {
+                const size_t b0 = (size_t)R.roff[q] - class_first;
+                const size_t b1 = (q + 1 < s ? (size_t)R.roff[q + 1] - class_first : block.size());
+                R.roff[q] = (int32_t)R.words.size();
+                R.words.insert(R.words.end(), block.begin() + (ptrdiff_t)b0,
+                               block.begin() + (ptrdiff_t)b1);
+                R.words.resize(R.words.size() + (size_t)longest - (b1 - b0), 0);
+            }
+            R.class_rec[c] = make_int2((int32_t)class_first, longest);
+        } else {
+            R.class_rec[c] = make_int2((int32_t)class_first, 0);
+        }
+    }
+    R.roff[S] = (int32_t)R.words.size();
+    // zero tail: the kernels fetch the first entry batches of a record together with its
+    // header, which may read up to 48 words past the end of the last record
+    for (int q = 0; q < 64; ++q) R.words.push_back(0);
+    return GOM_OK;
 }
 
 }  // namespace
@@ -180,8 +241,9 @@ struct gom_state {
     int sched = GOM_SCHED_CLASS_LAUNCH;  // schedule in use
     bool resident_ok = false;            // resident schedule fits instance and device
     int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
-    int32_t *d_mptr = nullptr, *d_mem_v = nullptr, *d_mem_dptr = nullptr;
-    int2 *d_dep = nullptr;
+    int32_t *d_roff = nullptr, *d_recs = nullptr;
+    int2 *d_crec = nullptr;
+    std::vector<int2> class_rec;  // host copy of the per-class record placement
     int32_t g_host = 0;                 // next generation index to enqueue
     int32_t g_base = 0;                 // generation at which attempted_base was set
     int64_t attempted_base = 0;
@@ -475,8 +537,12 @@ extern "C" int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop,
     int rc = check_state_args(g, f, pop);
     if (rc) return rc;
     if (!bytes) return fail(GOM_E_ARG, "gom_state_bytes: null output");
-    *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)f->vars.size(),
-                         count_deps(*g, *f)).total;
+    if (g->n >= kMaxVertexSmall)
+        return fail(GOM_E_RANGE, "gom_state_bytes: at most %d vertices", kMaxVertexSmall - 1);
+    Records R;
+    rc = build_records(*g, *f, f->max_set == 1, R);
+    if (rc) return rc;
+    *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size()).total;
     return GOM_OK;
     GUARD_END
 }
@@ -546,10 +612,9 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         r.rows = s->d_rows;
         r.fit = s->d_fit;
         r.st = s->d_st;
-        r.mptr = s->d_mptr;
-        r.mem_v = s->d_mem_v;
-        r.mem_dptr = s->d_mem_dptr;
-        r.dep = s->d_dep;
+        r.roff = s->d_roff;
+        r.recs = s->d_recs;
+        r.class_rec = s->d_crec;
         r.class_ptr = s->d_cptr;
         r.seed = s->seed;
         r.target = target;
@@ -562,7 +627,7 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         for (int32_t t = 0; t < s->k; ++t) r.order[t] = (uint16_t)perm[t];
         int rc = timing_record(s, st, true);
         if (rc) return rc;
-        HIP_TRY(launch_resident_sweep(r, s->univariate, st));
+        HIP_TRY(launch_resident_sweep(r, s->univariate ? 0 : 1, st));
         rc = timing_record(s, st, false);
         if (rc) return rc;
         return enqueue_epilogue(s, target, st, true);
@@ -572,10 +637,8 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
     a.O = s->d_O;
     a.fit = s->d_fit;
     a.st = s->d_st;
-    a.mptr = s->d_mptr;
-    a.mem_v = s->d_mem_v;
-    a.mem_dptr = s->d_mem_dptr;
-    a.dep = s->d_dep;
+    a.roff = s->d_roff;
+    a.recs = s->d_recs;
     a.seed = s->seed;
     a.target = target;
     a.N = s->N;
@@ -585,10 +648,12 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         const int32_t c = perm[t];
         a.cls = c;
         a.cbase = s->class_ptr[c];
+        a.rbase = s->class_rec[c].x;
+        a.rstride = s->class_rec[c].y;
         a.csize = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
         int rc = timing_record(s, st, true);
         if (rc) return rc;
-        HIP_TRY(launch_class_sweep(a, s->univariate, s->max_grid, st));
+        HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st));
         rc = timing_record(s, st, false);
         if (rc) return rc;
     }
@@ -634,10 +699,12 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
         return fail(GOM_E_ARG, "gom_state_init: unknown class order %d", class_order_kind);
     if ((reinterpret_cast<uintptr_t>(dev_arena) & 255) != 0)
         return fail(GOM_E_NOMEM, "gom_state_init: arena must be 256-byte aligned");
+    if (g->n >= kMaxVertexSmall)
+        return fail(GOM_E_RANGE, "gom_state_init: at most %d vertices", kMaxVertexSmall - 1);
     Records R;
-    build_records(*g, *f, R);
-    const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.mem_v.size(),
-                                 (int64_t)R.dep.size());
+    rc = build_records(*g, *f, f->max_set == 1, R);
+    if (rc) return rc;
+    const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size());
     if (arena_bytes < L.total)
         return fail(GOM_E_NOMEM, "gom_state_init: arena has %zu bytes, needs %zu", arena_bytes,
                     L.total);
@@ -667,10 +734,10 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->d_eu = (int32_t *)(s->arena + L.eu);
     s->d_ev = (int32_t *)(s->arena + L.ev);
     s->d_ew = (int32_t *)(s->arena + L.ew);
-    s->d_mptr = (int32_t *)(s->arena + L.mptr);
-    s->d_mem_v = (int32_t *)(s->arena + L.mem_v);
-    s->d_mem_dptr = (int32_t *)(s->arena + L.mem_dptr);
-    s->d_dep = (int2 *)(s->arena + L.dep);
+    s->d_roff = (int32_t *)(s->arena + L.roff);
+    s->d_recs = (int32_t *)(s->arena + L.recs);
+    s->d_crec = (int2 *)(s->arena + L.crec);
+    s->class_rec = R.class_rec;
     auto cleanup = [&](int code) {
         gom_state_free(s);
         return code;
@@ -695,11 +762,10 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
                          resident_lds_bytes(s->n) <= (size_t)lds_max;
         s->sched = s->resident_ok ? GOM_SCHED_RESIDENT : GOM_SCHED_CLASS_LAUNCH;
     }
-    if (e == hipSuccess) e = h2d(s->d_mptr, R.mptr.data(), sizeof(int32_t) * R.mptr.size());
-    if (e == hipSuccess) e = h2d(s->d_mem_v, R.mem_v.data(), sizeof(int32_t) * R.mem_v.size());
+    if (e == hipSuccess) e = h2d(s->d_roff, R.roff.data(), sizeof(int32_t) * R.roff.size());
+    if (e == hipSuccess) e = h2d(s->d_recs, R.words.data(), sizeof(int32_t) * R.words.size());
     if (e == hipSuccess)
-        e = h2d(s->d_mem_dptr, R.mem_dptr.data(), sizeof(int32_t) * R.mem_dptr.size());
-    if (e == hipSuccess) e = h2d(s->d_dep, R.dep.data(), sizeof(int2) * R.dep.size());
+        e = h2d(s->d_crec, R.class_rec.data(), sizeof(int2) * R.class_rec.size());
     if (e == hipSuccess) e = enqueue_initial_population(s, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging buffers die below
     if (e != hipSuccess)

@@ -56,20 +56,19 @@ struct alignas(64) DevState {
     int32_t pad[3];
 };
 
-// One colour-class sweep launch.  Element records are stored in class order: record s (class
-// position p of class c is s = class_start[c] + p) lists its members
-// mem_v[mptr[s] .. mptr[s+1]-1]; member m's dependent edges are dep[mem_dptr[m] ..
-// mem_dptr[m+1]-1], each {v, w}: v >= 0 is an outside neighbour, v < 0 encodes ~v, a member
-// with a larger position (an edge inside the set, listed once).
+// One colour-class sweep launch.  Set records are stored in class order: class position p of
+// class c is record s = class_start[c] + p, a block of int32 words at recs + roff[s] (layout
+// described in gom_kernels.hip).
 struct SweepArgs {
     const uint64_t *P;      // population at generation start, one word per vertex
     uint64_t *O;            // offspring, one word per vertex
     int64_t *fit;           // fitness[64]
     const DevState *st;
-    const int32_t *mptr;
-    const int32_t *mem_v;
-    const int32_t *mem_dptr;
-    const int2 *dep;
+    const int32_t *roff;    // record offsets (words), one per class position
+    const int32_t *recs;    // record words
+    int32_t rbase;          // first record word of the class
+    int32_t rstride;        // words per record when the class's records are padded to one
+                            // size, else 0 (then roff is used)
     uint64_t seed;
     int64_t target;         // generation runs only while elite_fitness < target
     int32_t N;              // population size
@@ -109,11 +108,10 @@ struct ResidentArgs {
     uint64_t *rows;         // N rows of row_words words: bit (v mod 64) of word v / 64
     int64_t *fit;
     DevState *st;
-    const int32_t *mptr;
-    const int32_t *mem_v;
-    const int32_t *mem_dptr;
-    const int2 *dep;
+    const int32_t *roff;
+    const int32_t *recs;
     const int32_t *class_ptr;
+    const int2 *class_rec;  // per class {first record word, record stride or 0}
     uint64_t seed;
     int64_t target;
     int32_t n;
@@ -133,9 +131,10 @@ hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevSta
 hipError_t launch_zero_state(int64_t *fit, DevState *st, hipStream_t s);
 hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32_t *ev,
                                const int32_t *ew, int64_t m, int N, int64_t *fit, hipStream_t s);
-hipError_t launch_class_sweep(const SweepArgs &a, bool univariate, int max_grid, hipStream_t s);
+// kind: 0 = univariate records, 1 = general records
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s);
 hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
-hipError_t launch_resident_sweep(const ResidentArgs &a, bool univariate, hipStream_t s);
+hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s);
 size_t resident_lds_bytes(int n);
 
 }  // namespace gom

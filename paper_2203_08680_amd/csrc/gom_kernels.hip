@@ -143,14 +143,206 @@ __global__ __launch_bounds__(kFitThreads) void k_full_fitness(const uint64_t *P,
 }
 
 // ------------------------------------------------------------------------------------------
+// Set records (built on the host in colour-class order, one per class position s, starting
+// at word roff[s] on a 16-byte boundary):
+//   univariate FOS:  [u, nd, 0, 0] then nd entries {v, w}: the neighbours of the set's
+//                    variable u and the edge weights
+//   small set (nm <= 7 variables): [nm, nd, u_0..u_6, end_0..end_6] then nd entries {x, w};
+//                    end_k counts the entries of members 0..k (unused slots: u = -1,
+//                    end = nd); x holds the position a of the entry's own endpoint in bits
+//                    28..30, and either the outside neighbour v (bit 31 clear) or, for an
+//                    edge inside the set (listed once, under its lower position), the other
+//                    endpoint's position b (bit 31 set) in bits 0..27
+//   large set:       [nm, nd, 0 x 14] then u_0..u_{nm-1}, end_0..end_{nm-1}, then from the
+//                    next 16-byte boundary nd entries {x, w} with x = v (outside) or ~b
+//                    (inside, b > a)
+// The partial evaluation of Section 2.2 / Algorithm 4 reads exactly these entries: the
+// subfunctions (edges) that depend on a variable of the set.
+// ------------------------------------------------------------------------------------------
+constexpr int kSmallSet = 7;
+constexpr int kBatch = 8;  // entries fetched together
+
+struct PairOut {
+    uint32_t cnt;    // eligible donors
+    bool acc;        // step accepted
+    int64_t delta;   // fitness change of the step
+};
+
+// Offspring bits of solution i in the O planes (class-launch schedule).
+struct PlaneBits {
+    const uint64_t *O;
+    uint32_t i;
+    __device__ __forceinline__ uint32_t operator()(int v) const { return bit_of(O[v], i); }
+};
+
+// Offspring bits of one solution in LDS, one byte per vertex (resident schedule).
+struct LdsBits {
+    const uint8_t *ob;
+    __device__ __forceinline__ uint32_t operator()(int v) const { return ob[v]; }
+};
+
+__device__ __forceinline__ int32_t signed_w(uint32_t same, int32_t w) { return same ? w : -w; }
+
+// GOM step (Algorithm 2) of solution i on the set whose record starts at R.  `bits` reads
+// O_i; `commit(u, flip)` is called once per member u (by every lane of a group, so it may
+// use cross-lane operations) and flips O_i[u] when `flip`.  `h` is the 16-bit donor draw,
+// `cand` the mask of possible donors (every solution but i).
+template <int KIND, class Bits, class Commit>
+__device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P, Bits bits,
+                                            Commit commit, uint64_t cand, uint32_t h,
+                                            bool neutral_ok) {
+    PairOut out{0u, false, 0};
+    const int4 h0 = *reinterpret_cast<const int4 *>(R);
+    if constexpr (KIND == 0) {
+        // one variable u: the donor always differs at u, so C = {u} whenever a donor exists
+        const int2 *E = reinterpret_cast<const int2 *>(R + 4);
+        // first batch fetched with the header (reads past a short record stay inside the
+        // buffer's zero tail; entries beyond nd are masked before use)
+        int2 en[kBatch];
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) en[t] = E[t];
+        const int u = h0.x, nd = h0.y;
+        const uint32_t ou = bits(u);
+        const uint64_t D = (P[u] ^ (0ull - (uint64_t)ou)) & cand;
+        out.cnt = (uint32_t)__popcll(D);
+        int64_t delta = 0;
+        for (int e0 = 0; e0 < nd; e0 += kBatch) {
+            if (e0 > 0) {
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) en[t] = E[e0 + t];
+            }
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                const bool ok = e0 + t < nd;
+                const int v = ok ? en[t].x : u;
+                delta += ok ? signed_w(ou == bits(v), en[t].y) : 0;
+            }
+        }
+        out.delta = delta;
+        out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+        commit(u, out.acc);
+        return out;
+    } else {
+        const int nm = h0.x, nd = h0.y;
+        if (nm <= kSmallSet) {
+            const int4 h1 = *reinterpret_cast<const int4 *>(R + 4);
+            const int4 h2 = *reinterpret_cast<const int4 *>(R + 8);
+            const int4 h3 = *reinterpret_cast<const int4 *>(R + 12);
+            const int2 *E = reinterpret_cast<const int2 *>(R + 16);
+            // first two batches fetched with the header (see the univariate case)
+            int2 en0[kBatch], en1[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                en0[t] = E[t];
+                en1[t] = E[kBatch + t];
+            }
+            const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x};
+            const int end[kSmallSet] = {h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
+            (void)end;
+            uint64_t pw[kSmallSet];
+            uint32_t om = 0;
+            uint64_t D = 0;
+#pragma unroll
+            for (int k = 0; k < kSmallSet; ++k) {
+                pw[k] = 0;
+                if (k < nm) {
+                    pw[k] = P[mem[k]];
+                    const uint32_t ok = bits(mem[k]);
+                    om |= ok << k;
+                    D |= pw[k] ^ (0ull - (uint64_t)ok);
+                }
+            }
+            D &= cand;
+            out.cnt = (uint32_t)__popcll(D);
+            const uint32_t d = out.cnt ? select_bit(D, (h * out.cnt) >> 16) : 0u;
+            uint32_t cm = 0;
+#pragma unroll
+            for (int k = 0; k < kSmallSet; ++k)
+                if (k < nm) cm |= (bit_of(pw[k], d) ^ ((om >> k) & 1u)) << k;
+            int64_t delta = 0;
+            for (int e0 = 0; e0 < nd; e0 += kBatch) {
+                int2 en[kBatch];
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t)
+                    en[t] = e0 == 0 ? en0[t] : (e0 == kBatch ? en1[t] : E[e0 + t]);
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    // an entry past nd becomes an inside edge of member 0 with itself: no flip
+                    const int x = (e0 + t < nd) ? en[t].x : (int)0x80000000;
+                    const uint32_t a = ((uint32_t)x >> 28) & 7u;
+                    const uint32_t y = (uint32_t)x & 0x0FFFFFFFu;
+                    const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
+                    uint32_t ov, flip;
+                    if (x >= 0) {
+                        ov = bits((int)y);
+                        flip = ca;
+                    } else {
+                        ov = (om >> y) & 1u;
+                        flip = ca ^ ((cm >> y) & 1u);
+                    }
+                    delta += flip ? signed_w(oa == ov, en[t].y) : 0;
+                }
+            }
+            out.delta = delta;
+            out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+#pragma unroll
+            for (int k = 0; k < kSmallSet; ++k)
+                if (k < nm) commit(mem[k], out.acc && ((cm >> k) & 1u));
+            return out;
+        } else {
+            const int32_t *mem = R + 16;
+            const int32_t *end = R + 16 + nm;
+            const int2 *E = reinterpret_cast<const int2 *>(R + ((16 + 2 * nm + 3) & ~3));
+            uint64_t D = 0;
+            for (int k = 0; k < nm; ++k) {
+                const int u = mem[k];
+                D |= P[u] ^ (0ull - (uint64_t)bits(u));
+            }
+            D &= cand;
+            out.cnt = (uint32_t)__popcll(D);
+            const uint32_t d = out.cnt ? select_bit(D, (h * out.cnt) >> 16) : 0u;
+            int64_t delta = 0;
+            int e = 0;
+            for (int k = 0; k < nm; ++k) {
+                const int u = mem[k];
+                const uint32_t ou = bits(u);
+                const uint32_t cu = bit_of(P[u], d) ^ ou;
+                for (const int e1 = end[k]; e < e1; ++e) {
+                    const int2 en = E[e];
+                    uint32_t ov, flip;
+                    if (en.x >= 0) {
+                        ov = bits(en.x);
+                        flip = cu;
+                    } else {
+                        const int vb = mem[~en.x];
+                        ov = bits(vb);
+                        flip = cu ^ (bit_of(P[vb], d) ^ ov);
+                    }
+                    delta += flip ? signed_w(ou == ov, en.y) : 0;
+                }
+            }
+            out.delta = delta;
+            out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+            for (int k = 0; k < nm; ++k) {
+                const int u = mem[k];
+                const uint32_t cu = bit_of(P[u], d) ^ bits(u);
+                commit(u, out.acc && cu);
+            }
+            return out;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // One colour class of one generation (Algorithm 3, the body of the loop over groups; the GOM
 // step of Algorithm 2 for every (solution, set) pair of the class at once).
 //
 // Mapping: a group of G lanes (G = 16, 32 or 64, the population rounded up) takes one set of
 // the class; lane i of the group is solution i.  A block of 8 waves takes a tile of
-// 8 * 64 / G consecutive class positions.  All sets of one class are independent (no shared
-// or adjacent variables), so groups never read a word that another group of the same launch
-// writes, and each O word of a set is written by exactly one lane.
+// 8 * 64 / G consecutive class positions.  With G = 64 the set's record and the population
+// words it needs are wave-uniform (scalar loads).  All sets of one class are independent (no
+// shared or adjacent variables), so groups never read a word that another group of the same
+// launch writes, and each O word of a set is written by exactly one lane.
 //
 // Per pair (solution i, set F_j at class position p):
 //   D      = solutions d != i whose P genes differ from O_i somewhere on F_j (64-bit mask,
@@ -164,11 +356,21 @@ __global__ __launch_bounds__(kFitThreads) void k_full_fitness(const uint64_t *P,
 //            change is +w if the edge was uncut, -w if it was cut
 //   accept = |D| > 0 and (delta > 0 or (delta == 0 and (always or P_i != elitist)))
 //   commit = one word store per member: O[u] ^= ballot(accept and u in C)
-// A univariate FOS (every set one variable) needs no draw: the donor always differs at that
-// variable, so C = {j} whenever D is non-empty, whichever donor is drawn.
 // Fitness deltas are summed per block and added once per solution with an int64 atomic.
 // ------------------------------------------------------------------------------------------
-template <int G, bool UNI>
+template <int G>
+struct PlaneCommit {
+    uint64_t *O;
+    int grp;
+    uint32_t i;
+    __device__ __forceinline__ void operator()(int u, bool flip) const {
+        uint64_t fm = ballot64(flip);
+        if constexpr (G < 64) fm = (fm >> (grp * G)) & ((1ull << G) - 1ull);
+        if (fm != 0 && i == 0) O[u] ^= fm;
+    }
+};
+
+template <int G, int KIND>
 __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     if (a.st->elite_fitness >= a.target) return;
     const uint64_t eq = a.st->eq;
@@ -181,7 +383,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     const uint32_t i = (uint32_t)(lane % G);
     const bool act = (int)i < a.N;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-    const uint64_t cand = popm & ~(1ull << i);
+    const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
     const bool neutral_ok = a.always || !bit_of(eq, i);
 
     __shared__ uint32_t rng[64][4];
@@ -190,10 +392,12 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
 
     int64_t facc = 0;
     uint32_t n_eval = 0, n_acc = 0;
+    const PlaneBits bits{a.O, i};
+    const PlaneCommit<G> commit{a.O, grp, i};
     const int ntiles = (a.csize + PER_TILE - 1) / PER_TILE;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int base = tile * PER_TILE;
-        if constexpr (!UNI) {
+        if constexpr (KIND != 0) {
             if (wave == 0) {
                 const int q = lane / G;
                 const int p0 = base + q * 8;
@@ -211,69 +415,19 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
         const int local = wave * GPW + grp;
         const int p = base + local;
         if (p < a.csize) {
-            const int s = a.cbase + p;
-            int m0, m1;
-            if constexpr (UNI) {
-                m0 = s;
-                m1 = s + 1;
-            } else {
-                m0 = a.mptr[s];
-                m1 = a.mptr[s + 1];
-            }
-            // Eligible donors.
-            uint64_t D = 0;
-            for (int m = m0; m < m1; ++m) {
-                const int u = a.mem_v[m];
-                D |= a.P[u] ^ (0ull - (uint64_t)bit_of(a.O[u], i));
-            }
-            D &= cand;
-            const uint32_t cnt = act ? (uint32_t)__popcll(D) : 0u;
-            uint32_t d = 0;
-            if constexpr (!UNI) {
+            uint32_t h = 0;
+            if constexpr (KIND != 0) {
                 const int f = local & 7;
-                const uint32_t h = (rng[(local >> 3) * G + (int)i][f >> 1] >> (16 * (f & 1))) &
-                                   0xFFFFu;
-                if (cnt) d = select_bit(D, (h * cnt) >> 16);
+                h = (rng[(local >> 3) * G + (int)i][f >> 1] >> (16 * (f & 1))) & 0xFFFFu;
             }
-            // Partial evaluation.
-            int64_t delta = 0;
-            for (int m = m0; m < m1; ++m) {
-                const int u = a.mem_v[m];
-                const uint32_t oq = bit_of(a.O[u], i);
-                uint32_t cq = 1u;
-                if constexpr (!UNI) cq = bit_of(a.P[u], d) ^ oq;
-                const int e1 = a.mem_dptr[m + 1];
-                for (int e = a.mem_dptr[m]; e < e1; ++e) {
-                    const int2 en = a.dep[e];
-                    uint32_t flip, ov;
-                    if (en.x >= 0) {
-                        ov = bit_of(a.O[en.x], i);
-                        flip = cq;
-                    } else {
-                        const int v = ~en.x;
-                        ov = bit_of(a.O[v], i);
-                        flip = cq ^ (bit_of(a.P[v], d) ^ ov);
-                    }
-                    const int32_t sw = (oq == ov) ? en.y : -en.y;
-                    delta += flip ? sw : 0;
-                }
-            }
-            const bool acc = cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
-            // Commit accepted steps: one word per member.
-            for (int m = m0; m < m1; ++m) {
-                const int u = a.mem_v[m];
-                const uint64_t ow = a.O[u];
-                uint32_t cq = 1u;
-                if constexpr (!UNI) cq = bit_of(a.P[u], d) ^ bit_of(ow, i);
-                uint64_t fm = ballot64(acc && cq);
-                if constexpr (G < 64) fm = (fm >> (grp * G)) & ((1ull << G) - 1ull);
-                if (fm != 0 && i == 0) a.O[u] = ow ^ fm;
-            }
-            facc += acc ? delta : 0;
-            n_eval += cnt > 0;
-            n_acc += acc;
+            const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride
+                                         : a.recs + a.roff[a.cbase + p];
+            const PairOut r = gom_pair<KIND>(R, a.P, bits, commit, cand, h, neutral_ok);
+            facc += r.acc ? r.delta : 0;
+            n_eval += r.cnt > 0;
+            n_acc += r.acc;
         }
-        if constexpr (!UNI) __syncthreads();
+        if constexpr (KIND != 0) __syncthreads();
     }
 
     red[tid] = facc;
@@ -326,16 +480,20 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpilogueArgs a) {
     const bool in = v < a.n;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     uint64_t o = 0ull;
-    if (in) {
-        if (a.rows) {
-            // resident schedule: gather bit v of every solution's row
-            const size_t wv = (size_t)(v >> 6);
-            const uint32_t sh = (uint32_t)(v & 63);
-            for (int t = 0; t < a.N; ++t)
-                o |= ((a.rows[(size_t)t * a.row_words + wv] >> sh) & 1ull) << t;
-        } else {
-            o = a.O[v];
+    if (a.rows) {
+        // resident schedule: lane t loads solution t's row word for this wave's 64 vertices;
+        // 64 ballots transpose the 64 x 64 bit block so lane b ends with vertex b's word
+        const int wv = (blockIdx.x * kEpiThreads + (tid & ~63)) >> 6;
+        const uint64_t word =
+            (lane < a.N && wv < a.row_words) ? a.rows[(size_t)lane * a.row_words + wv] : 0ull;
+#pragma unroll
+        for (int b = 0; b < 64; ++b) {
+            const uint64_t m = ballot64((word >> b) & 1ull);
+            if (lane == b) o = m;
         }
+        if (!in) o = 0ull;
+    } else if (in) {
+        o = a.O[v];
     }
     if (a.mode == kEpiGeneration && in) {
         a.P[v] = o;
@@ -392,7 +550,14 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpilogueArgs a) {
 constexpr int kResRngBytes = kResidentChunkSlots * 16;
 constexpr int kResRedBytes = 256;
 
-template <bool UNI>
+struct LdsCommit {
+    uint8_t *ob;
+    __device__ __forceinline__ void operator()(int u, bool flip) const {
+        if (flip) ob[u] ^= 1u;
+    }
+};
+
+template <int KIND>
 __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
     DevState *st = a.st;
     if (st->elite_fitness >= a.target) return;
@@ -411,15 +576,18 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
     for (int v = tid; v < a.n; v += kResidentThreads) ob[v] = (uint8_t)bit_of(a.P[v], (uint32_t)i);
     __syncthreads();
 
+    const LdsBits bits{ob};
+    const LdsCommit commit{ob};
     int64_t facc = 0;
     uint32_t n_eval = 0, n_acc = 0;
     for (int t = 0; t < a.k; ++t) {
         const int c = a.order[t];
         const int cbase = a.class_ptr[c];
         const int csize = a.class_ptr[c + 1] - cbase;
+        const int2 cr = a.class_rec[c];  // {first record word, record stride or 0}
         for (int base = 0; base < csize; base += 8 * kResidentChunkSlots) {
             const int span = min(csize - base, 8 * kResidentChunkSlots);
-            if constexpr (!UNI) {
+            if constexpr (KIND != 0) {
                 if (tid < ((span + 7) >> 3)) {
                     const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)c, (uint32_t)i,
                                            (uint32_t)((base >> 3) + tid));
@@ -431,65 +599,17 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
                 __syncthreads();
             }
             for (int q = tid; q < span; q += kResidentThreads) {
-                const int s = cbase + base + q;
-                int m0, m1;
-                if constexpr (UNI) {
-                    m0 = s;
-                    m1 = s + 1;
-                } else {
-                    m0 = a.mptr[s];
-                    m1 = a.mptr[s + 1];
-                }
-                uint64_t D = 0;
-                for (int m = m0; m < m1; ++m) {
-                    const int u = a.mem_v[m];
-                    D |= a.P[u] ^ (0ull - (uint64_t)ob[u]);
-                }
-                D &= cand;
-                const uint32_t cnt = (uint32_t)__popcll(D);
-                if (cnt == 0) continue;
-                uint32_t d = 0;
-                if constexpr (!UNI) {
+                uint32_t h = 0;
+                if constexpr (KIND != 0) {
                     const int f = q & 7;
-                    const uint32_t h = (rng[q >> 3][f >> 1] >> (16 * (f & 1))) & 0xFFFFu;
-                    d = select_bit(D, (h * cnt) >> 16);
+                    h = (rng[q >> 3][f >> 1] >> (16 * (f & 1))) & 0xFFFFu;
                 }
-                int64_t delta = 0;
-                for (int m = m0; m < m1; ++m) {
-                    const int u = a.mem_v[m];
-                    const uint32_t oq = ob[u];
-                    uint32_t cq = 1u;
-                    if constexpr (!UNI) cq = bit_of(a.P[u], d) ^ oq;
-                    const int e1 = a.mem_dptr[m + 1];
-                    for (int e = a.mem_dptr[m]; e < e1; ++e) {
-                        const int2 en = a.dep[e];
-                        uint32_t flip, ov;
-                        if (en.x >= 0) {
-                            ov = ob[en.x];
-                            flip = cq;
-                        } else {
-                            const int v = ~en.x;
-                            ov = ob[v];
-                            flip = cq ^ (bit_of(a.P[v], d) ^ ov);
-                        }
-                        const int32_t sw = (oq == ov) ? en.y : -en.y;
-                        delta += flip ? sw : 0;
-                    }
-                }
-                ++n_eval;
-                if (delta > 0 || (delta == 0 && neutral_ok)) {
-                    for (int m = m0; m < m1; ++m) {
-                        const int u = a.mem_v[m];
-                        if constexpr (UNI) {
-                            ob[u] ^= 1u;
-                        } else {
-                            const uint32_t oq = ob[u];
-                            if (bit_of(a.P[u], d) ^ oq) ob[u] = (uint8_t)(oq ^ 1u);
-                        }
-                    }
-                    facc += delta;
-                    ++n_acc;
-                }
+                const int32_t *R = cr.y ? a.recs + cr.x + (base + q) * cr.y
+                                        : a.recs + a.roff[cbase + base + q];
+                const PairOut r = gom_pair<KIND>(R, a.P, bits, commit, cand, h, neutral_ok);
+                facc += r.acc ? r.delta : 0;
+                n_eval += r.cnt > 0;
+                n_acc += r.acc;
             }
             __syncthreads();
         }
@@ -522,6 +642,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
         if (sa) atomicAdd((unsigned long long *)&st->accepted, (unsigned long long)sa);
     }
 }
+
 }  // namespace
 
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st, int n,
@@ -548,21 +669,21 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
     return hipGetLastError();
 }
 
-hipError_t launch_class_sweep(const SweepArgs &a, bool univariate, int max_grid, hipStream_t s) {
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s) {
     const int G = a.N <= 16 ? 16 : (a.N <= 32 ? 32 : 64);
     const int per_tile = 8 * (64 / G);
     int grid = (a.csize + per_tile - 1) / per_tile;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
     const dim3 gd(grid), bd(kSweepThreads);
-    if (univariate) {
-        if (G == 16) hipLaunchKernelGGL((k_class_sweep<16, true>), gd, bd, 0, s, a);
-        else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, true>), gd, bd, 0, s, a);
-        else hipLaunchKernelGGL((k_class_sweep<64, true>), gd, bd, 0, s, a);
+    if (kind == 0) {
+        if (G == 16) hipLaunchKernelGGL((k_class_sweep<16, 0>), gd, bd, 0, s, a);
+        else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, 0>), gd, bd, 0, s, a);
+        else hipLaunchKernelGGL((k_class_sweep<64, 0>), gd, bd, 0, s, a);
     } else {
-        if (G == 16) hipLaunchKernelGGL((k_class_sweep<16, false>), gd, bd, 0, s, a);
-        else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, false>), gd, bd, 0, s, a);
-        else hipLaunchKernelGGL((k_class_sweep<64, false>), gd, bd, 0, s, a);
+        if (G == 16) hipLaunchKernelGGL((k_class_sweep<16, 1>), gd, bd, 0, s, a);
+        else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, 1>), gd, bd, 0, s, a);
+        else hipLaunchKernelGGL((k_class_sweep<64, 1>), gd, bd, 0, s, a);
     }
     return hipGetLastError();
 }
@@ -571,22 +692,22 @@ size_t resident_lds_bytes(int n) {
     return (size_t)kResRngBytes + kResRedBytes + (((size_t)n + 15) & ~(size_t)15);
 }
 
-hipError_t launch_resident_sweep(const ResidentArgs &a, bool univariate, hipStream_t s) {
+hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s) {
     const size_t lds = resident_lds_bytes(a.n);
     // Raise the dynamic LDS limit of the kernel to what this launch needs (once per size).
     static size_t attr_bytes[2] = {0, 0};
-    const void *fn = univariate ? (const void *)k_resident_sweep<true>
-                                : (const void *)k_resident_sweep<false>;
-    if (lds > attr_bytes[univariate]) {
+    const void *fn = kind == 0 ? (const void *)k_resident_sweep<0>
+                               : (const void *)k_resident_sweep<1>;
+    if (lds > attr_bytes[kind]) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
-        attr_bytes[univariate] = lds;
+        attr_bytes[kind] = lds;
     }
-    if (univariate)
-        hipLaunchKernelGGL((k_resident_sweep<true>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
+    if (kind == 0)
+        hipLaunchKernelGGL((k_resident_sweep<0>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((k_resident_sweep<false>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
+        hipLaunchKernelGGL((k_resident_sweep<1>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
     return hipGetLastError();
 }
 

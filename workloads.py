@@ -128,6 +128,10 @@ def _c2():
     return torus(100, 1, 100, seed=2)
 
 
+def _t1000():
+    return torus(1000, 1, 100, seed=7)
+
+
 def _c3(d):
     return lambda: configuration_model(100_000, d, seed=3, weights="signed50")
 
@@ -138,6 +142,9 @@ WORKLOADS = {
     # 100x100 torus, weights U{1..100}, neighbourhood FOS, population 64, to optimum or 500.
     "torus100_nbhd_p64": Workload("torus100_nbhd_p64", _c2, 1, 64, 500, True),
 }
+# 1000x1000 torus (10^6 vertices), weights U{1..100}: the HBM-bound size.
+WORKLOADS["torus1000_uni_p64"] = Workload("torus1000_uni_p64", _t1000, 0, 64, 1000, True)
+WORKLOADS["torus1000_nbhd_p64"] = Workload("torus1000_nbhd_p64", _t1000, 1, 64, 1000, True)
 for _d in (3, 6, 12):
     for _k, _fn in ((0, "uni"), (1, "nbhd")):
         WORKLOADS[f"cm100k_d{_d}_{_fn}_p32"] = Workload(
