@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=20,
                     help="generations of the oracle sample for the CPU baseline")
-    ap.add_argument("--schedule", choices=("auto", "class", "resident"), default="auto",
+    ap.add_argument("--schedule", choices=("auto", "class", "resident", "bitsliced"), default="auto",
                     help="launch schedule of the generations (results are identical)")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads.WORKLOADS),
                     help="workload (default: the benchmark configuration)")
@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB (a known "
                          "byte count for scaling profiler traffic counters)")
+    ap.add_argument("--event-period", type=int, default=17,
+                    help="time every k-th sweep launch with HIP events (sampling keeps the "
+                         "events' own cost out of most launches)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="do not record HIP events around sweep launches (roofline omitted)")
     args = ap.parse_args()
@@ -146,9 +149,11 @@ def main():
     st = inst.state(pop=wl.pop, seed=1000)
     gom.gom_state_set_schedule(st, {"auto": gom.GOM_SCHED_AUTO,
                                     "class": gom.GOM_SCHED_CLASS_LAUNCH,
-                                    "resident": gom.GOM_SCHED_RESIDENT}[args.schedule])
+                                    "resident": gom.GOM_SCHED_RESIDENT,
+                                    "bitsliced": gom.GOM_SCHED_BITSLICED}[args.schedule])
     sched = gom.gom_state_get_schedule(st)
-    sched_name = "resident" if sched == gom.GOM_SCHED_RESIDENT else "class_launch"
+    sched_name = {gom.GOM_SCHED_RESIDENT: "resident", gom.GOM_SCHED_BITSLICED: "bitsliced"}.get(
+        sched, "class_launch")
     info = st.info()
     _, class_ptr, class_elems = inst.classes()
     set_ptr, set_vars = inst.fos.sets()
@@ -165,7 +170,7 @@ def main():
     torch.cuda.synchronize()
 
     if not args.no_kernel_events:
-        gom.gom_timing_enable(st, True)
+        gom.gom_timing_enable(st, args.event_period)
         gom.gom_timing_read(st)
     runs = []
     torch.cuda.synchronize()
@@ -178,7 +183,7 @@ def main():
     total = time.perf_counter() - t0
     if not args.no_kernel_events:
         sweep_ms, launches = gom.gom_timing_read(st)
-        gom.gom_timing_enable(st, False)
+        gom.gom_timing_enable(st, 0)
     if args.copy_calib_mb:
         nbytes = args.copy_calib_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -201,18 +206,18 @@ def main():
         # class launch: every class is swept once per generation, so the mean over launches
         # of the algorithmic bytes is the mean over classes; resident: one launch sweeps
         # every class of a generation
-        avg_bytes = float(cbytes.mean() if sched_name == "class_launch" else cbytes.sum())
+        avg_bytes = float(cbytes.sum() if sched_name == "resident" else cbytes.mean())
         avg_s = sweep_ms / 1e3 / launches
         achieved = avg_bytes / avg_s / 1e9
-        kname = "k_class_sweep" if sched_name == "class_launch" else "k_resident_sweep"
+        kname = {"resident": "k_resident_sweep", "bitsliced": "k_uni_swar_sweep"}.get(
+            sched_name, "k_class_sweep")
         meas = MEASURED_TRAFFIC.get((kname, args.workload))
         traffic = meas["bytes"] if meas and meas["source"] == kernel_source_hash() else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                     "traffic": traffic,
                     "traffic_profile": meas["profile"] if traffic else None,
-                    "kernel": "k_class_sweep" if sched_name == "class_launch"
-                    else "k_resident_sweep",
+                    "kernel": kname,
                     "bytes_per_launch": round(avg_bytes, 1),
                     "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches}
     cpu = None

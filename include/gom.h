@@ -197,11 +197,13 @@ int gom_state_write(gom_state *s, void *stream, const uint8_t *genes, const uint
                     int64_t elite_fitness, int32_t generation, const int64_t *counters);
 
 /*
- * Kernel timing: when enabled, a pair of HIP events brackets every colour-class sweep launch
- * on the launch stream.  gom_timing_read waits for the recorded events, returns the summed
- * elapsed milliseconds and the number of launches since the last read, and resets them.
+ * Kernel timing: with period k > 0, a pair of HIP events brackets every k-th sweep launch (the
+ * colour-class sweeps, or the resident generation sweep) on the launch stream; k = 0 turns
+ * timing off.  Sampling keeps the events' own cost out of most launches.  gom_timing_read
+ * waits for the recorded events, returns the summed elapsed milliseconds and the number of
+ * timed launches since the last read, and resets them.
  */
-int gom_timing_enable(gom_state *s, int enable);
+int gom_timing_enable(gom_state *s, int period);
 int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launches);
 
 /*
@@ -212,13 +214,19 @@ int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launche
  *                           offspring in LDS and running all classes with barriers between
  *                           them; needs n bytes of LDS per workgroup and at most
  *                           GOM_RESIDENT_MAX_CLASSES classes
- *   GOM_SCHED_AUTO          resident when it fits the device, class launch otherwise
- * GOM_E_RANGE when the resident schedule does not fit this instance or device.
+ *   GOM_SCHED_BITSLICED     one launch per colour class, lane = set, every solution of the
+ *                           set processed at once with 64-bit bitwise operations; needs a
+ *                           univariate FOS, maximum degree <= 4 and per-vertex sums of |w|
+ *                           below 2^30
+ *   GOM_SCHED_AUTO          resident when it fits the device, else bit-sliced when the
+ *                           instance qualifies, else class launch
+ * GOM_E_RANGE when the requested schedule does not fit this instance or device.
  */
-enum { GOM_SCHED_AUTO = 0, GOM_SCHED_CLASS_LAUNCH = 1, GOM_SCHED_RESIDENT = 2 };
+enum { GOM_SCHED_AUTO = 0, GOM_SCHED_CLASS_LAUNCH = 1, GOM_SCHED_RESIDENT = 2,
+       GOM_SCHED_BITSLICED = 3 };
 #define GOM_RESIDENT_MAX_CLASSES 1536
 int gom_state_set_schedule(gom_state *s, int schedule);
-/* The schedule in use (GOM_SCHED_CLASS_LAUNCH or GOM_SCHED_RESIDENT). */
+/* The schedule in use (GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT or GOM_SCHED_BITSLICED). */
 int gom_state_get_schedule(const gom_state *s, int *schedule);
 
 /* Sizes of a state: vertices, population, sets, classes, largest class. */

@@ -71,7 +71,7 @@ struct gom_fos {
 namespace {
 
 struct Layout {
-    size_t st, fit, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, total;
+    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -87,6 +87,7 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
     };
     L.st = take(sizeof(DevState));
     L.fit = take(sizeof(int64_t) * GOM_MAX_POP);
+    L.stripes = take(sizeof(Stripe) * kStripes);
     L.E = take(sizeof(uint64_t) * (size_t)((n + 63) / 64));
     L.P = take(sizeof(uint64_t) * (size_t)n);
     L.O = take(sizeof(uint64_t) * (size_t)n);
@@ -236,10 +237,13 @@ struct gom_state {
     Layout L{};
     DevState *d_st = nullptr;
     int64_t *d_fit = nullptr;
+    Stripe *d_stripes = nullptr;
     uint64_t *d_E = nullptr, *d_P = nullptr, *d_O = nullptr, *d_rows = nullptr;
     int32_t *d_cptr = nullptr;
     int sched = GOM_SCHED_CLASS_LAUNCH;  // schedule in use
     bool resident_ok = false;            // resident schedule fits instance and device
+    bool bitsliced_ok = false;           // bit-sliced schedule fits the instance
+    bool partition = false;              // every variable in exactly one set
     int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
     int32_t *d_roff = nullptr, *d_recs = nullptr;
     int2 *d_crec = nullptr;
@@ -250,7 +254,9 @@ struct gom_state {
     DevState *h_st = nullptr;           // two pinned host slots
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     int max_grid = 2048;
-    bool timing = false;
+    int timing = 0;                     // sample period of the sweep-launch events (0 = off)
+    int64_t sweep_launches = 0;         // sweep launches enqueued (for the sampling)
+    bool timing_open = false;           // a begin event is recorded, its end is due
     std::vector<hipEvent_t> tev;        // begin/end pairs
     size_t tev_used = 0;
     double t_ms = 0.0;
@@ -561,6 +567,13 @@ static std::vector<int32_t> class_order(const gom_state *s, int32_t gen) {
 
 static int timing_record(gom_state *s, hipStream_t st, bool begin) {
     if (!s->timing) return GOM_OK;
+    if (begin) {
+        if (s->sweep_launches++ % s->timing != 0) return GOM_OK;
+        s->timing_open = true;
+    } else {
+        if (!s->timing_open) return GOM_OK;
+        s->timing_open = false;
+    }
     if (begin && s->tev_used + 2 > s->tev.size()) {
         if (s->tev.size() < (size_t)(1 << 15)) {
             const size_t grow = s->tev.size() ? s->tev.size() : 256;
@@ -595,6 +608,7 @@ static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool r
     e.E = s->d_E;
     e.fit = s->d_fit;
     e.st = s->d_st;
+    e.stripes = s->d_stripes;
     e.target = target;
     e.n = s->n;
     e.N = s->N;
@@ -610,7 +624,7 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         ResidentArgs r{};
         r.P = s->d_P;
         r.rows = s->d_rows;
-        r.fit = s->d_fit;
+        r.stripes = s->d_stripes;
         r.st = s->d_st;
         r.roff = s->d_roff;
         r.recs = s->d_recs;
@@ -635,7 +649,7 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
     SweepArgs a{};
     a.P = s->d_P;
     a.O = s->d_O;
-    a.fit = s->d_fit;
+    a.stripes = s->d_stripes;
     a.st = s->d_st;
     a.roff = s->d_roff;
     a.recs = s->d_recs;
@@ -653,7 +667,10 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         a.csize = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
         int rc = timing_record(s, st, true);
         if (rc) return rc;
-        HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st));
+        if (s->sched == GOM_SCHED_BITSLICED)
+            HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st));
+        else
+            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st));
         rc = timing_record(s, st, false);
         if (rc) return rc;
     }
@@ -662,10 +679,10 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
 
 // InitializePopulation (Algorithm 3), full fitness of every solution, initial elitist.
 static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
-    hipError_t e = launch_init_population(s->d_P, s->d_O, s->d_fit, s->d_st, s->n, s->N,
-                                          s->seed, st);
+    hipError_t e = launch_init_population(s->d_P, s->d_O, s->d_fit, s->d_st, s->d_stripes, s->n,
+                                          s->N, s->seed, st);
     if (e == hipSuccess)
-        e = launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, s->N, s->d_fit, st);
+        e = launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, s->N, s->d_stripes, st);
     if (e != hipSuccess) return e;
     EpilogueArgs ea{};
     ea.P = s->d_P;
@@ -673,6 +690,7 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
     ea.E = s->d_E;
     ea.fit = s->d_fit;
     ea.st = s->d_st;
+    ea.stripes = s->d_stripes;
     ea.target = INT64_MAX;
     ea.n = s->n;
     ea.N = s->N;
@@ -684,6 +702,12 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
         s->attempted_base = 0;
     }
     return e;
+}
+
+static int auto_schedule(const gom_state *s) {
+    if (s->resident_ok) return GOM_SCHED_RESIDENT;
+    if (s->bitsliced_ok) return GOM_SCHED_BITSLICED;
+    return GOM_SCHED_CLASS_LAUNCH;
 }
 
 extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
@@ -726,6 +750,7 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->L = L;
     s->d_st = (DevState *)(s->arena + L.st);
     s->d_fit = (int64_t *)(s->arena + L.fit);
+    s->d_stripes = (Stripe *)(s->arena + L.stripes);
     s->d_E = (uint64_t *)(s->arena + L.E);
     s->d_P = (uint64_t *)(s->arena + L.P);
     s->d_O = (uint64_t *)(s->arena + L.O);
@@ -760,7 +785,16 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
             e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         s->resident_ok = e == hipSuccess && s->k <= kResidentMaxClasses &&
                          resident_lds_bytes(s->n) <= (size_t)lds_max;
-        s->sched = s->resident_ok ? GOM_SCHED_RESIDENT : GOM_SCHED_CLASS_LAUNCH;
+        int64_t max_abs = 0;
+        for (int32_t v = 0; v < g->n; ++v) {
+            int64_t t = 0;
+            for (int32_t r = g->row_ptr[v]; r < g->row_ptr[(size_t)v + 1]; ++r)
+                t += g->wt[r] < 0 ? -(int64_t)g->wt[r] : (int64_t)g->wt[r];
+            max_abs = std::max(max_abs, t);
+        }
+        s->bitsliced_ok = s->univariate && g->max_degree <= 4 && max_abs < ((int64_t)1 << 30);
+        s->partition = s->univariate && f->n_sets == g->n;
+        s->sched = auto_schedule(s);
     }
     if (e == hipSuccess) e = h2d(s->d_roff, R.roff.data(), sizeof(int32_t) * R.roff.size());
     if (e == hipSuccess) e = h2d(s->d_recs, R.words.data(), sizeof(int32_t) * R.words.size());
@@ -924,14 +958,15 @@ extern "C" int gom_state_write(gom_state *s, void *stream, const uint8_t *genes,
     HIP_TRY(hipMemcpyAsync(s->d_O, P.data(), sizeof(uint64_t) * P.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s->d_E, E.data(), sizeof(uint64_t) * E.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s->d_st, &h, sizeof(DevState), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_zero_state(s->d_fit, s->d_st, st));
-    HIP_TRY(launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, s->N, s->d_fit, st));
+    HIP_TRY(launch_zero_state(s->d_fit, s->d_stripes, st));
+    HIP_TRY(launch_full_fitness(s->d_P, s->d_eu, s->d_ev, s->d_ew, s->m, s->N, s->d_stripes, st));
     EpilogueArgs ea{};
     ea.P = s->d_P;
     ea.O = s->d_O;
     ea.E = s->d_E;
     ea.fit = s->d_fit;
     ea.st = s->d_st;
+    ea.stripes = s->d_stripes;
     ea.target = INT64_MAX;
     ea.n = s->n;
     ea.N = s->N;
@@ -945,9 +980,12 @@ extern "C" int gom_state_write(gom_state *s, void *stream, const uint8_t *genes,
     GUARD_END
 }
 
-extern "C" int gom_timing_enable(gom_state *s, int enable) {
+extern "C" int gom_timing_enable(gom_state *s, int period) {
     if (!s) return fail(GOM_E_ARG, "gom_timing_enable: null state");
-    s->timing = enable != 0;
+    if (period < 0) return fail(GOM_E_ARG, "gom_timing_enable: negative period");
+    s->timing = period;
+    s->sweep_launches = 0;
+    s->timing_open = false;
     return GOM_OK;
 }
 
@@ -974,7 +1012,13 @@ extern "C" int gom_state_set_schedule(gom_state *s, int schedule) {
     if (!s) return fail(GOM_E_ARG, "gom_state_set_schedule: null state");
     switch (schedule) {
     case GOM_SCHED_AUTO:
-        s->sched = s->resident_ok ? GOM_SCHED_RESIDENT : GOM_SCHED_CLASS_LAUNCH;
+        s->sched = auto_schedule(s);
+        return GOM_OK;
+    case GOM_SCHED_BITSLICED:
+        if (!s->bitsliced_ok)
+            return fail(GOM_E_RANGE, "gom_state_set_schedule: the bit-sliced schedule needs a "
+                        "univariate FOS, maximum degree <= 4 and per-vertex |w| sums < 2^30");
+        s->sched = schedule;
         return GOM_OK;
     case GOM_SCHED_CLASS_LAUNCH:
         s->sched = schedule;

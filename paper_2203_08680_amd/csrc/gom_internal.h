@@ -43,17 +43,28 @@ __host__ __device__ __forceinline__ U32x4 philox(uint64_t seed, uint32_t c0, uin
 constexpr uint32_t kInitStream = 0xFFFFFFFFu;   // counter (kInitStream, i, v/128, 0)
 constexpr uint32_t kOrderStream = 0xFFFFFFFFu;  // counter (g, kOrderStream, t, 0)
 
-// Per-run scalars the kernels read and the generation epilogue updates.
+// Per-run scalars.  The finalize kernel updates them once per generation.
 struct alignas(64) DevState {
     int64_t elite_fitness;   // fitness of the elitist
-    uint64_t eq;             // bit i: solution i equals the elitist (start of generation)
-    uint64_t mism;           // epilogue accumulator: solutions differing from the elitist
     int64_t evaluated;       // cumulative pairs with a differing donor
     int64_t accepted;        // cumulative accepted steps
     int32_t generation;      // generations completed
-    uint32_t blocks_done;    // epilogue arrival counter (zero between launches)
-    int32_t best;            // index of the best solution at the last epilogue
-    int32_t pad[3];
+    int32_t best;            // best solution at the last finalize (lowest index on ties)
+    int32_t new_elite;       // the last finalize replaced the elitist by solution `best`
+    int32_t active;          // the last finalize closed a generation that ran
+    int32_t pad[6];
+};
+
+// Accumulators that many blocks add into.  Device-scope atomics on one address serialise
+// (tens of ns each), so every block adds into stripe (block index mod kStripes) and the
+// finalize kernel sums the stripes.
+constexpr int kStripes = 64;
+struct alignas(64) Stripe {
+    int64_t fit[64];         // fitness change per solution
+    uint64_t evaluated;
+    uint64_t accepted;
+    uint64_t mism;           // solutions whose P differs from the elitist (vertex pass)
+    uint64_t pad[5];
 };
 
 // One colour-class sweep launch.  Set records are stored in class order: class position p of
@@ -62,7 +73,7 @@ struct alignas(64) DevState {
 struct SweepArgs {
     const uint64_t *P;      // population at generation start, one word per vertex
     uint64_t *O;            // offspring, one word per vertex
-    int64_t *fit;           // fitness[64]
+    Stripe *stripes;
     const DevState *st;
     const int32_t *roff;    // record offsets (words), one per class position
     const int32_t *recs;    // record words
@@ -79,20 +90,26 @@ struct SweepArgs {
     int32_t always;         // neutral rule: 1 = accept equal fitness always
 };
 
+// Generation end, in two launches: k_finalize (one block: fitness from the stripes, best
+// solution, elitist decision, counters, generation count) then k_vertex_pass (all vertices:
+// P <- O, elitist bits, solutions differing from the elitist into the stripes).
 struct EpilogueArgs {
     uint64_t *P;
     uint64_t *O;            // offspring planes (read; rewritten when rows is set)
     const uint64_t *rows;   // if non-null: offspring as one bit row per solution (resident
-                            // schedule); the epilogue transposes them into P and O
+                            // schedule); the vertex pass transposes them into P and O
     uint64_t *E;            // elitist bits, bit (v mod 64) of word v / 64
-    const int64_t *fit;
+    int64_t *fit;
     DevState *st;
+    Stripe *stripes;
     int64_t target;
     int32_t n;
     int32_t N;
-    int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh eq only
+    int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh flags only
     int32_t row_words;      // words per row, ceil(n / 64)
 };
+
+enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };
 
 // Resident schedule: one block per solution runs every colour class of a generation with
 // the solution's offspring genes held in LDS (one byte per vertex), classes separated by
@@ -106,8 +123,8 @@ constexpr int kResidentChunkSlots = kResidentThreads;  // Philox calls per round
 struct ResidentArgs {
     const uint64_t *P;
     uint64_t *rows;         // N rows of row_words words: bit (v mod 64) of word v / 64
-    int64_t *fit;
-    DevState *st;
+    Stripe *stripes;
+    const DevState *st;
     const int32_t *roff;
     const int32_t *recs;
     const int32_t *class_ptr;
@@ -123,18 +140,21 @@ struct ResidentArgs {
     uint16_t order[kResidentMaxClasses];  // class order of this generation
 };
 
-enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };
-
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st, int n,
-                                  int N, uint64_t seed, hipStream_t s);
-hipError_t launch_zero_state(int64_t *fit, DevState *st, hipStream_t s);
+hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
+                                  Stripe *stripes, int n, int N, uint64_t seed, hipStream_t s);
+hipError_t launch_zero_state(int64_t *fit, Stripe *stripes, hipStream_t s);
 hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32_t *ev,
-                               const int32_t *ew, int64_t m, int N, int64_t *fit, hipStream_t s);
+                               const int32_t *ew, int64_t m, int N, Stripe *stripes,
+                               hipStream_t s);
 // kind: 0 = univariate records, 1 = general records
 hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s);
-hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
+// Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
+hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
+                                 hipStream_t s);
 hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s);
+// Generation end: finalize (one block) then the vertex pass.
+hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
 size_t resident_lds_bytes(int n);
 
 }  // namespace gom

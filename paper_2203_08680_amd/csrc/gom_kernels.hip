@@ -5,20 +5,24 @@
 //          word v is gene v of solution i (bit-planes: a vertex's genes for the whole
 //          population, up to 64 solutions, travel in one 8-byte access).
 //   E      elitist genes, bit (v mod 64) of word v / 64.
-//   fit    int64 fitness per solution.
-//   records of the FOS sets in colour-class order (see SweepArgs).
+//   fit    int64 fitness per solution; stripes: per-block accumulators (see Stripe).
+//   records of the FOS sets in colour-class order (layout below).
 //
-// A generation runs under one of two schedules with identical results:
+// A generation runs under one of three schedules with identical results:
 //   class launch: one k_class_sweep launch per colour class (in the generation's class
 //     order), lane = solution, offspring in the O planes;
+//   bit-sliced:   one k_uni_swar_sweep launch per colour class, lane = set, all solutions of
+//     the set in one word (univariate FOS, degree <= 4);
 //   resident:     one k_resident_sweep launch (block = solution, offspring in LDS, all
 //     classes), offspring written back as one bit row per solution;
-// then one k_epilogue launch (P <- O, elitist update, equality flags).  Integer arithmetic
-// only, so every result is exact and independent of the order in which waves run.
+// then k_finalize (one block) and k_vertex_pass (P <- O, elitist, equality flags).  Integer
+// arithmetic only, so every result is exact and independent of the order in which waves run.
 #include "gom_internal.h"
 
 namespace gom {
 namespace {
+
+static_assert(kStripes == 64, "one stripe per lane of a wave");
 
 constexpr int kSweepThreads = 512;  // 8 waves of 64 lanes
 constexpr int kEpiThreads = 256;
@@ -60,28 +64,35 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
     return x;
 }
 
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
 // ------------------------------------------------------------------------------------------
 // Initial population (Algorithm 3, InitializePopulation): gene v of solution i is bit
 // (v mod 32) of word ((v / 32) mod 4) of Philox(seed; kInitStream, i, v / 128, 0).
 // One wave per 128 vertices: lane i draws solution i's 128 genes, then 128 ballots turn them
 // into the 128 population words, two per lane, stored coalesced.  Block 0 also clears the
-// fitness accumulators and the run scalars.
+// fitness, the stripes and the run scalars.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_init_population(uint64_t *P, uint64_t *O, int64_t *fit,
-                                                         DevState *st, int n, int N,
-                                                         uint64_t seed) {
+                                                         DevState *st, Stripe *stripes, int n,
+                                                         int N, uint64_t seed) {
     const int lane = threadIdx.x & 63;
     if (blockIdx.x == 0) {
         if (threadIdx.x < 64) fit[threadIdx.x] = 0;
+        uint64_t *sw = reinterpret_cast<uint64_t *>(stripes);
+        for (int q = threadIdx.x; q < kStripes * (int)(sizeof(Stripe) / 8); q += 256) sw[q] = 0;
         if (threadIdx.x == 0) {
             st->elite_fitness = INT64_MIN;
-            st->eq = 0;
-            st->mism = 0;
             st->evaluated = 0;
             st->accepted = 0;
             st->generation = 0;
-            st->blocks_done = 0;
             st->best = 0;
+            st->new_elite = 0;
+            st->active = 0;
         }
     }
     const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -106,12 +117,10 @@ __global__ __launch_bounds__(256) void k_init_population(uint64_t *P, uint64_t *
     if (v1 < n) { P[v1] = w1; O[v1] = w1; }
 }
 
-__global__ void k_zero_state(int64_t *fit, DevState *st) {
+__global__ __launch_bounds__(256) void k_zero_state(int64_t *fit, Stripe *stripes) {
     if (threadIdx.x < 64) fit[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-        st->mism = 0;
-        st->blocks_done = 0;
-    }
+    uint64_t *sw = reinterpret_cast<uint64_t *>(stripes);
+    for (int q = threadIdx.x; q < kStripes * (int)(sizeof(Stripe) / 8); q += 256) sw[q] = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(kFitThreads) void k_full_fitness(const uint64_t *P,
                                                               const int32_t *eu,
                                                               const int32_t *ev,
                                                               const int32_t *ew, int64_t m,
-                                                              int N, int64_t *fit) {
+                                                              int N, Stripe *stripes) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t acc = 0;
@@ -138,7 +147,9 @@ __global__ __launch_bounds__(kFitThreads) void k_full_fitness(const uint64_t *P,
         int64_t s = 0;
 #pragma unroll
         for (int w = 0; w < kFitThreads / 64; ++w) s += red[w * 64 + threadIdx.x];
-        if (s) atomicAdd((unsigned long long *)&fit[threadIdx.x], (unsigned long long)s);
+        if (s)
+            atomicAdd((unsigned long long *)&stripes[blockIdx.x % kStripes].fit[threadIdx.x],
+                      (unsigned long long)s);
     }
 }
 
@@ -339,10 +350,9 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P,
 //
 // Mapping: a group of G lanes (G = 16, 32 or 64, the population rounded up) takes one set of
 // the class; lane i of the group is solution i.  A block of 8 waves takes a tile of
-// 8 * 64 / G consecutive class positions.  With G = 64 the set's record and the population
-// words it needs are wave-uniform (scalar loads).  All sets of one class are independent (no
-// shared or adjacent variables), so groups never read a word that another group of the same
-// launch writes, and each O word of a set is written by exactly one lane.
+// 8 * 64 / G consecutive class positions.  All sets of one class are independent (no shared
+// or adjacent variables), so groups never read a word that another group of the same launch
+// writes, and each O word of a set is written by exactly one lane.
 //
 // Per pair (solution i, set F_j at class position p):
 //   D      = solutions d != i whose P genes differ from O_i somewhere on F_j (64-bit mask,
@@ -356,7 +366,7 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P,
 //            change is +w if the edge was uncut, -w if it was cut
 //   accept = |D| > 0 and (delta > 0 or (delta == 0 and (always or P_i != elitist)))
 //   commit = one word store per member: O[u] ^= ballot(accept and u in C)
-// Fitness deltas are summed per block and added once per solution with an int64 atomic.
+// Fitness changes and counts are summed per block and added to the block's stripe.
 // ------------------------------------------------------------------------------------------
 template <int G>
 struct PlaneCommit {
@@ -372,10 +382,10 @@ struct PlaneCommit {
 
 template <int G, int KIND>
 __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
-    if (a.st->elite_fitness >= a.target) return;
-    const uint64_t eq = a.st->eq;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const uint64_t mism = a.stripes[lane].mism;
+    if (a.st->elite_fitness >= a.target) return;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr int GPW = 64 / G;          // sets per wave
     constexpr int PER_TILE = 8 * GPW;    // sets per block tile (multiple of 8)
@@ -384,7 +394,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     const bool act = (int)i < a.N;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
-    const bool neutral_ok = a.always || !bit_of(eq, i);
+    const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
 
     __shared__ uint32_t rng[64][4];
     __shared__ int64_t red[kSweepThreads];
@@ -437,12 +447,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
         redc[1][wave] = ca;
     }
     __syncthreads();
+    Stripe *sp = a.stripes + (blockIdx.x % kStripes);
     if (tid < G && tid < a.N) {
         int64_t sum = 0;
         for (int w = 0; w < 8; ++w)
 #pragma unroll
             for (int g2 = 0; g2 < GPW; ++g2) sum += red[w * 64 + g2 * G + tid];
-        if (sum) atomicAdd((unsigned long long *)&a.fit[tid], (unsigned long long)sum);
+        if (sum) atomicAdd((unsigned long long *)&sp->fit[tid], (unsigned long long)sum);
     }
     if (tid == 0) {
         uint32_t se = 0, sa = 0;
@@ -450,91 +461,131 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
             se += redc[0][w];
             sa += redc[1][w];
         }
-        DevState *st = const_cast<DevState *>(a.st);
-        if (se) atomicAdd((unsigned long long *)&st->evaluated, (unsigned long long)se);
-        if (sa) atomicAdd((unsigned long long *)&st->accepted, (unsigned long long)sa);
+        if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
+        if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// Generation epilogue (Algorithm 3, P <- O; elitist kept across generations).
-//   best b = argmax fitness (lowest index on ties); the elitist becomes P_b when f_b is
-//   strictly better (mode 0), unconditionally (mode 1, initial population) or never (mode 2).
-//   Every block copies its vertices' words O -> P (mode 0), refreshes or reads the elitist
-//   bits, and ORs the solutions that differ from the elitist; the last block to arrive turns
-//   that into the equality flags used by the next generation and updates the scalars.
+// Bit-parallel sweep of one colour class for a univariate FOS on a graph of degree <= 4
+// (lane = set, all solutions of a set in one 64-bit word).
+//
+// For set {u} with edges (u, v_e, w_e), e < 4 (missing edges have w = 0):
+//   q_e    = ~(O[u] ^ O[v_e]): bit i set when u and v_e carry the same gene in O_i, so
+//            flipping u cuts the edge (+w_e); otherwise it uncuts it (-w_e)
+//   delta  of solution i depends only on the 4-bit pattern (q_0..q_3 at bit i): the lane
+//            computes the 16 pattern deltas and two 16-entry truth tables (delta > 0,
+//            delta == 0), then evaluates them on all 64 solutions at once with a tree of
+//            bitwise selects on q_0..q_3
+//   donor  exists for solution i when some other solution's P gene at u differs from
+//            O_i[u]: from the popcounts of the ones and zeros of P[u]
+//   accept = donor & (positive | (zero & not-elitist)), O[u] ^= accept
+// The donor draw is not needed: with one variable every eligible donor carries the flipped
+// gene.  Fitness changes of accepted pairs (delta of that pair recomputed from its pattern)
+// are summed per solution in LDS and added to the block's stripe.
+// PARTITION: every variable is in exactly one set, so O[u] still equals P[u] when u's set
+// is swept and P[u] need not be read.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpilogueArgs a) {
-    DevState *st = a.st;
-    const int64_t fE = st->elite_fitness;
-    if (a.mode == kEpiGeneration && fE >= a.target) return;
-    int b = 0;
-    int64_t fb = a.fit[0];
-    for (int t = 1; t < a.N; ++t) {
-        const int64_t x = a.fit[t];
-        if (x > fb) { fb = x; b = t; }
+constexpr int kSwarThreads = 256;
+
+__device__ __forceinline__ uint64_t sel64(uint64_t m, uint64_t a, uint64_t b) {
+    return (a & m) | (b & ~m);  // per bit: m ? a : b
+}
+
+// 16-entry truth table t (bit p = value for pattern p = q0 + 2 q1 + 4 q2 + 8 q3) evaluated
+// bitwise on the four masks.
+__device__ __forceinline__ uint64_t table16(uint32_t t, uint64_t q0, uint64_t q1, uint64_t q2,
+                                            uint64_t q3) {
+    uint64_t l[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t t2 = (t >> (2 * k)) & 3u;
+        l[k] = ((t2 & 1u) ? ~q0 : 0ull) | ((t2 & 2u) ? q0 : 0ull);
     }
-    const bool newE = a.mode == kEpiInit || (a.mode == kEpiGeneration && fb > fE);
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int v = blockIdx.x * kEpiThreads + tid;
-    const bool in = v < a.n;
+    uint64_t m1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m1[k] = sel64(q1, l[2 * k + 1], l[2 * k]);
+    const uint64_t m20 = sel64(q2, m1[1], m1[0]), m21 = sel64(q2, m1[3], m1[2]);
+    return sel64(q3, m21, m20);
+}
+
+template <bool PARTITION>
+__global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
+    const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
+    if (a.st->elite_fitness >= a.target) return;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-    uint64_t o = 0ull;
-    if (a.rows) {
-        // resident schedule: lane t loads solution t's row word for this wave's 64 vertices;
-        // 64 ballots transpose the 64 x 64 bit block so lane b ends with vertex b's word
-        const int wv = (blockIdx.x * kEpiThreads + (tid & ~63)) >> 6;
-        const uint64_t word =
-            (lane < a.N && wv < a.row_words) ? a.rows[(size_t)lane * a.row_words + wv] : 0ull;
+    const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
+    __shared__ unsigned long long fa[64];
+    __shared__ uint32_t redc[2][kSwarThreads / 64];
+    if (threadIdx.x < 64) fa[threadIdx.x] = 0ull;
+    __syncthreads();
+    uint32_t n_eval = 0, n_acc = 0;
+    const int stride = gridDim.x * kSwarThreads;
+    for (int p = blockIdx.x * kSwarThreads + threadIdx.x; p < a.csize; p += stride) {
+        const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride
+                                     : a.recs + a.roff[a.cbase + p];
+        const int4 h = *reinterpret_cast<const int4 *>(R);
+        const int4 e01 = *reinterpret_cast<const int4 *>(R + 4);
+        const int4 e23 = *reinterpret_cast<const int4 *>(R + 8);
+        const int u = h.x, nd = h.y;
+        const int v0 = nd > 0 ? e01.x : u, v1 = nd > 1 ? e01.z : u;
+        const int v2 = nd > 2 ? e23.x : u, v3 = nd > 3 ? e23.z : u;
+        const int w0 = nd > 0 ? e01.y : 0, w1 = nd > 1 ? e01.w : 0;
+        const int w2 = nd > 2 ? e23.y : 0, w3 = nd > 3 ? e23.w : 0;
+        const uint64_t o = a.O[u];
+        const uint64_t x = PARTITION ? o : a.P[u];
+        const uint64_t q0 = ~(o ^ a.O[v0]), q1 = ~(o ^ a.O[v1]);
+        const uint64_t q2 = ~(o ^ a.O[v2]), q3 = ~(o ^ a.O[v3]);
+        // donors: solutions with o_i = 1 need a zero of x other than i, o_i = 0 a one
+        const uint64_t ones = x & popm, zeros = ~x & popm;
+        const int co = __popcll(ones), cz = __popcll(zeros);
+        const uint64_t hz = cz >= 2 ? ~0ull : (cz == 1 ? ~zeros : 0ull);
+        const uint64_t ho = co >= 2 ? ~0ull : (co == 1 ? ~ones : 0ull);
+        const uint64_t has = ((o & hz) | (~o & ho)) & popm;
+        // pattern deltas and truth tables
+        const int base = -(w0 + w1 + w2 + w3);
+        uint32_t tp = 0, tz = 0;
 #pragma unroll
-        for (int b = 0; b < 64; ++b) {
-            const uint64_t m = ballot64((word >> b) & 1ull);
-            if (lane == b) o = m;
+        for (int pt = 0; pt < 16; ++pt) {
+            const int d = base + ((pt & 1) ? 2 * w0 : 0) + ((pt & 2) ? 2 * w1 : 0) +
+                          ((pt & 4) ? 2 * w2 : 0) + ((pt & 8) ? 2 * w3 : 0);
+            tp |= (uint32_t)(d > 0) << pt;
+            tz |= (uint32_t)(d == 0) << pt;
         }
-        if (!in) o = 0ull;
-    } else if (in) {
-        o = a.O[v];
+        const uint64_t acc =
+            (table16(tp, q0, q1, q2, q3) | (table16(tz, q0, q1, q2, q3) & nz)) & has;
+        n_eval += (uint32_t)__popcll(has);
+        n_acc += (uint32_t)__popcll(acc);
+        if (acc) {
+            a.O[u] = o ^ acc;
+            for (uint64_t m = acc; m; m &= m - 1) {
+                const uint32_t i = (uint32_t)__builtin_ctzll(m);
+                const int d = (bit_of(q0, i) ? w0 : -w0) + (bit_of(q1, i) ? w1 : -w1) +
+                              (bit_of(q2, i) ? w2 : -w2) + (bit_of(q3, i) ? w3 : -w3);
+                atomicAdd(&fa[i], (unsigned long long)(long long)d);
+            }
+        }
     }
-    if (a.mode == kEpiGeneration && in) {
-        a.P[v] = o;
-        if (a.rows) a.O[v] = o;
-    }
-    uint32_t eb;
-    if (newE) {
-        eb = in ? bit_of(o, (uint32_t)b) : 0u;
-        const uint64_t word = ballot64(eb != 0);
-        if (lane == 0 && v < a.n) a.E[v >> 6] = word;
-    } else {
-        eb = in ? bit_of(a.E[v >> 6], (uint32_t)(v & 63)) : 0u;
-    }
-    uint64_t mism = in ? ((o ^ (0ull - (uint64_t)eb)) & popm) : 0ull;
-    mism = wave_or64(mism);
-    __shared__ uint64_t sm[kEpiThreads / 64];
-    __shared__ int last;
-    if (lane == 0) sm[tid >> 6] = mism;
-    __syncthreads();
-    if (tid == 0) {
-        uint64_t mm = 0;
-#pragma unroll
-        for (int w = 0; w < kEpiThreads / 64; ++w) mm |= sm[w];
-        if (mm) atomicOr((unsigned long long *)&st->mism, (unsigned long long)mm);
-        __threadfence();
-        const uint32_t prev = atomicAdd(&st->blocks_done, 1u);
-        last = prev == gridDim.x - 1;
+    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        redc[0][wave] = ce;
+        redc[1][wave] = ca;
     }
     __syncthreads();
-    if (last && tid == 0) {
-        __threadfence();
-        const uint64_t all = atomicOr((unsigned long long *)&st->mism, 0ull);
-        st->eq = ~all & popm;
-        if (newE) st->elite_fitness = fb;
-        st->best = b;
-        if (a.mode == kEpiGeneration) st->generation += 1;
-        st->mism = 0;
-        st->blocks_done = 0;
+    Stripe *sp = a.stripes + (blockIdx.x % kStripes);
+    if ((int)threadIdx.x < a.N && fa[threadIdx.x])
+        atomicAdd((unsigned long long *)&sp->fit[threadIdx.x], fa[threadIdx.x]);
+    if (threadIdx.x == 0) {
+        uint32_t se = 0, sa = 0;
+        for (int w = 0; w < kSwarThreads / 64; ++w) {
+            se += redc[0][w];
+            sa += redc[1][w];
+        }
+        if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
+        if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
     }
 }
-
 
 // ------------------------------------------------------------------------------------------
 // Resident schedule: one block per solution i runs all colour classes of one generation.
@@ -545,7 +596,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpilogueArgs a) {
 // donors' genes from the population words P[u] and O_i from LDS.  Sets of one class never
 // touch each other's variables or neighbours, so their byte updates do not race; a block
 // barrier separates classes.  At the end the block packs O_i into a bit row (one ballot per
-// 64 vertices), adds its fitness change to fit[i] and its counts to the run counters.
+// 64 vertices) and adds its fitness change and counts to its stripe.
 // ------------------------------------------------------------------------------------------
 constexpr int kResRngBytes = kResidentChunkSlots * 16;
 constexpr int kResRedBytes = 256;
@@ -559,8 +610,8 @@ struct LdsCommit {
 
 template <int KIND>
 __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
-    DevState *st = a.st;
-    if (st->elite_fitness >= a.target) return;
+    const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
+    if (a.st->elite_fitness >= a.target) return;
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t(*rng)[4] = reinterpret_cast<uint32_t(*)[4]>(lds);
     int64_t *redf = reinterpret_cast<int64_t *>(lds + kResRngBytes);
@@ -571,7 +622,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t cand = popm & ~(1ull << i);
-    const bool neutral_ok = a.always || !bit_of(st->eq, (uint32_t)i);
+    const bool neutral_ok = a.always || bit_of(wave_or64(mism), (uint32_t)i);
 
     for (int v = tid; v < a.n; v += kResidentThreads) ob[v] = (uint8_t)bit_of(a.P[v], (uint32_t)i);
     __syncthreads();
@@ -620,8 +671,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
         const uint64_t word = ballot64(v < a.n && ob[v] != 0);
         if (lane == 0) a.rows[(size_t)i * a.row_words + (v0 >> 6)] = word;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) facc += __shfl_xor(facc, off, 64);
+    facc = wave_sum64(facc);
     const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
     if (lane == 0) {
         redf[wave] = facc;
@@ -637,35 +687,148 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
             se += redc[w];
             sa += redc[16 + w];
         }
-        a.fit[i] += sf;
-        if (se) atomicAdd((unsigned long long *)&st->evaluated, (unsigned long long)se);
-        if (sa) atomicAdd((unsigned long long *)&st->accepted, (unsigned long long)sa);
+        Stripe *sp = a.stripes + (i % kStripes);
+        if (sf) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)sf);
+        if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
+        if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Generation end (Algorithm 3: P <- O; the elitist is kept across generations), part 1, one
+// wave: fitness of solution t = previous fitness + the stripes' changes; counters; best
+// solution b (lowest index on ties); the elitist becomes P_b when f_b is strictly better
+// (mode 0), always (mode 1, initial population) or never (mode 2).  Clears the stripes.
+// A generation skipped because the target was reached leaves everything as it is.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) {
+    DevState *st = a.st;
+    const int t = threadIdx.x;
+    const int64_t fE = st->elite_fitness;
+    if (a.mode == kEpiGeneration && fE >= a.target) {
+        if (t == 0) st->active = 0;
+        return;
+    }
+    int64_t f = INT64_MIN;
+    if (t < a.N) {
+        int64_t d = 0;
+        for (int s = 0; s < kStripes; ++s) d += a.stripes[s].fit[t];
+        f = a.fit[t] + d;
+        a.fit[t] = f;
+    }
+    const int64_t ev = wave_sum64((int64_t)a.stripes[t].evaluated);
+    const int64_t ac = wave_sum64((int64_t)a.stripes[t].accepted);
+    int64_t fb = f;
+    int b = t;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t of = __shfl_xor(fb, off, 64);
+        const int ob = __shfl_xor(b, off, 64);
+        if (of > fb || (of == fb && ob < b)) {
+            fb = of;
+            b = ob;
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < kStripes; ++s) a.stripes[s].fit[t] = 0;
+    a.stripes[t].evaluated = 0;
+    a.stripes[t].accepted = 0;
+    a.stripes[t].mism = 0;
+    if (t == 0) {
+        const bool newE = a.mode == kEpiInit || (a.mode == kEpiGeneration && fb > fE);
+        st->best = b;
+        st->new_elite = newE ? 1 : 0;
+        st->active = 1;
+        if (newE) st->elite_fitness = fb;
+        if (a.mode == kEpiGeneration) st->generation += 1;
+        st->evaluated += ev;
+        st->accepted += ac;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Generation end, part 2, one thread per vertex: P <- O (mode 0; from the O planes, or from
+// the solutions' bit rows under the resident schedule, then O is refreshed too), the elitist
+// bits (rewritten from P_b when the elitist changed), and the solutions whose genes differ
+// from the elitist, OR-ed per block into the block's stripe.  The next generation's sweeps
+// read those stripes to know which solutions equal the elitist.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kEpiThreads) void k_vertex_pass(EpilogueArgs a) {
+    const DevState *st = a.st;
+    if (!st->active) return;
+    const int b = st->best;
+    const bool newE = st->new_elite != 0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int v = blockIdx.x * kEpiThreads + tid;
+    const bool in = v < a.n;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    uint64_t o = 0ull;
+    if (a.rows) {
+        // lane t loads solution t's row word for this wave's 64 vertices; 64 ballots
+        // transpose the 64 x 64 bit block so lane k ends with vertex k's word
+        const int wv = (blockIdx.x * kEpiThreads + (tid & ~63)) >> 6;
+        const uint64_t word =
+            (lane < a.N && wv < a.row_words) ? a.rows[(size_t)lane * a.row_words + wv] : 0ull;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) {
+            const uint64_t m = ballot64((word >> k) & 1ull);
+            if (lane == k) o = m;
+        }
+        if (!in) o = 0ull;
+    } else if (in) {
+        o = a.O[v];
+    }
+    if (a.mode == kEpiGeneration && in) {
+        a.P[v] = o;
+        if (a.rows) a.O[v] = o;
+    }
+    uint32_t eb;
+    if (newE) {
+        eb = in ? bit_of(o, (uint32_t)b) : 0u;
+        const uint64_t word = ballot64(eb != 0);
+        if (lane == 0 && in) a.E[v >> 6] = word;
+    } else {
+        eb = in ? bit_of(a.E[v >> 6], (uint32_t)(v & 63)) : 0u;
+    }
+    const uint64_t mism = wave_or64(in ? ((o ^ (0ull - (uint64_t)eb)) & popm) : 0ull);
+    __shared__ uint64_t sm[kEpiThreads / 64];
+    if (lane == 0) sm[tid >> 6] = mism;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t mm = 0;
+#pragma unroll
+        for (int w = 0; w < kEpiThreads / 64; ++w) mm |= sm[w];
+        if (mm)
+            atomicOr((unsigned long long *)&a.stripes[blockIdx.x % kStripes].mism,
+                     (unsigned long long)mm);
     }
 }
 
 }  // namespace
 
-hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st, int n,
-                                  int N, uint64_t seed, hipStream_t s) {
+hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
+                                  Stripe *stripes, int n, int N, uint64_t seed, hipStream_t s) {
     const int blocks128 = (n + 127) / 128;
     const int grid = (blocks128 + 3) / 4;
-    hipLaunchKernelGGL(k_init_population, dim3(grid), dim3(256), 0, s, P, O, fit, st, n, N, seed);
+    hipLaunchKernelGGL(k_init_population, dim3(grid), dim3(256), 0, s, P, O, fit, st, stripes,
+                       n, N, seed);
     return hipGetLastError();
 }
 
-hipError_t launch_zero_state(int64_t *fit, DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, fit, st);
+hipError_t launch_zero_state(int64_t *fit, Stripe *stripes, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(256), 0, s, fit, stripes);
     return hipGetLastError();
 }
 
 hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32_t *ev,
-                               const int32_t *ew, int64_t m, int N, int64_t *fit, hipStream_t s) {
+                               const int32_t *ew, int64_t m, int N, Stripe *stripes,
+                               hipStream_t s) {
     int64_t waves = (m + 15) / 16;
     int64_t grid = (waves + 3) / 4;
     if (grid > 4096) grid = 4096;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_full_fitness, dim3((unsigned)grid), dim3(kFitThreads), 0, s, P, eu, ev,
-                       ew, m, N, fit);
+                       ew, m, N, stripes);
     return hipGetLastError();
 }
 
@@ -685,6 +848,18 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStr
         else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, 1>), gd, bd, 0, s, a);
         else hipLaunchKernelGGL((k_class_sweep<64, 1>), gd, bd, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
+                                 hipStream_t s) {
+    int grid = (a.csize + kSwarThreads - 1) / kSwarThreads;
+    if (grid > max_grid) grid = max_grid;
+    if (grid < 1) return hipSuccess;
+    if (partition)
+        hipLaunchKernelGGL((k_uni_swar_sweep<true>), dim3(grid), dim3(kSwarThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_uni_swar_sweep<false>), dim3(grid), dim3(kSwarThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -712,8 +887,11 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s)
 }
 
 hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int grid = (a.n + kEpiThreads - 1) / kEpiThreads;
-    hipLaunchKernelGGL(k_epilogue, dim3(grid), dim3(kEpiThreads), 0, s, a);
+    hipLaunchKernelGGL(k_vertex_pass, dim3(grid), dim3(kEpiThreads), 0, s, a);
     return hipGetLastError();
 }
 

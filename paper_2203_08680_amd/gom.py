@@ -19,7 +19,7 @@ GOM_FOS_UNIVARIATE, GOM_FOS_NEIGHBOURHOOD = 0, 1
 GOM_NEUTRAL_PAPER, GOM_NEUTRAL_ALWAYS = 0, 1
 GOM_ORDER_RANDOM, GOM_ORDER_FIXED = 0, 1
 GOM_MAX_POP = 64
-GOM_SCHED_AUTO, GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT = 0, 1, 2
+GOM_SCHED_AUTO, GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT, GOM_SCHED_BITSLICED = 0, 1, 2, 3
 
 EXPORTED = (
     "gom_last_error", "gom_version", "mc_graph_load", "mc_graph_info", "mc_graph_csr",
@@ -317,8 +317,9 @@ def gom_state_write(s: GomState, genes, elite, elite_fitness: int, generation: i
                                  int(elite_fitness), int(generation), _ptr(cnt)))
 
 
-def gom_timing_enable(s: GomState, enable: bool = True):
-    _check(lib().gom_timing_enable(s.handle, 1 if enable else 0))
+def gom_timing_enable(s: GomState, period: int = 1):
+    """Time every `period`-th sweep launch with HIP events (0 = off)."""
+    _check(lib().gom_timing_enable(s.handle, int(period)))
 
 
 def gom_timing_read(s: GomState):

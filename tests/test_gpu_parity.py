@@ -240,3 +240,67 @@ def test_schedule_selection(cuda):
     assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_RESIDENT
     with pytest.raises(gom.GomError):
         gom.gom_state_set_schedule(st, 9)
+    g = workloads.torus(1000, 1, 100, seed=7)
+    big = gom.Instance(g.n, g.u, g.v, g.w, 0)
+    st = big.state(pop=64, seed=1)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_BITSLICED
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_schedule(st, gom.GOM_SCHED_RESIDENT)
+
+
+BITSLICED_CASES = [
+    # (label, graph maker, population, neutral rule, explicit duplicate singletons)
+    ("torus10_p16", lambda: workloads.torus(10, 1, 5, seed=1), 16, 0, False),
+    ("torus33_p64_always", lambda: workloads.torus(33, 1, 9, seed=4), 64, 1, False),
+    ("cm_d3_p5", lambda: workloads.configuration_model(2002, 3, seed=5), 5, 0, False),
+    ("cm_d4_p33", lambda: workloads.configuration_model(3000, 4, seed=6), 33, 0, False),
+    ("cm_d4_p64_dups", lambda: workloads.configuration_model(800, 4, seed=8), 64, 0, True),
+    ("cm_d3_2_p2", lambda: workloads.configuration_model(1000, 2, seed=9), 2, 0, False),
+]
+
+
+@pytest.mark.parametrize("label,maker,pop,rule,dups", BITSLICED_CASES,
+                         ids=[c[0] for c in BITSLICED_CASES])
+def test_bitsliced_univariate(cuda, label, maker, pop, rule, dups):
+    """Bit-sliced schedule (lane = set, all solutions in one word) on univariate FOS of graphs
+    with degree <= 4, negative weights included; with duplicated singletons the sets are no
+    longer a partition (the kernel then reads P as well as O)."""
+    print(f"case bitsliced {label}", flush=True)
+    g = maker()
+    if dups:
+        sets = [[v] for v in range(g.n)] + [[v] for v in range(0, g.n, 3)]
+        ptr = np.zeros(len(sets) + 1, np.int32)
+        ptr[1:] = np.cumsum([1] * len(sets))
+        vars_ = np.asarray(sum(sets, []), np.int32)
+        _, st, ref = make_pair(g, None, pop, seed=7, rule=rule, sets=(ptr, vars_),
+                               sched=gom.GOM_SCHED_BITSLICED)
+    else:
+        _, st, ref = make_pair(g, 0, pop, seed=7, rule=rule, sched=gom.GOM_SCHED_BITSLICED)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_BITSLICED
+    lockstep(st, ref, 12, f"bitsliced {label}")
+
+
+def test_bitsliced_full_size(cuda):
+    """10^5-vertex 3-regular graph (univariate) and the 1000x1000 torus (univariate, population
+    64): the first generations in full under the bit-sliced schedule."""
+    print("case bitsliced cm100k d3", flush=True)
+    g = workloads.configuration_model(100_000, 3, seed=3, weights="signed50")
+    _, st, ref = make_pair(g, 0, 32, seed=1, sched=gom.GOM_SCHED_BITSLICED)
+    lockstep(st, ref, 2, "bitsliced cm100k d3")
+    print("case bitsliced torus1000", flush=True)
+    g = workloads.torus(1000, 1, 100, seed=7)
+    _, st, ref = make_pair(g, 0, 64, seed=1, sched=gom.GOM_SCHED_BITSLICED)
+    lockstep(st, ref, 1, "bitsliced torus1000")
+
+
+def test_bitsliced_rejected_when_not_eligible(cuda):
+    g = workloads.configuration_model(500, 6, seed=2)
+    inst = gom.Instance(g.n, g.u, g.v, g.w, 0)
+    st = inst.state(pop=8, seed=1)
+    with pytest.raises(gom.GomError) as e:
+        gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+    assert e.value.code == gom.GOM_E_RANGE
+    inst = gom.Instance(g.n, g.u, g.v, g.w, 1)
+    st = inst.state(pop=8, seed=1)
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
