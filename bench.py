@@ -103,6 +103,72 @@ def cpu_baseline(g, set_ptr, set_vars, pop, gens, target):
                       "single-threaded C oracle)"}
 
 
+def run_batch_mode(args, torch, gom):
+    """Batched vs plain on a mix of independent instances (the batched configuration): all
+    instances in one lockstep batch, against the same instances run one after another, each
+    alone, with the default schedule.  Every instance reaches the same state either way."""
+    items = workloads.batch_mix(count=args.batch_count, seed=4)
+    max_gens = args.max_gens or 200
+    t0 = time.perf_counter()
+    insts = [gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
+             for it in items]
+    targets = [it.graph.total_weight if it.to_total_weight else (1 << 62) for it in items]
+    pops, seeds = [it.pop for it in items], [it.seed for it in items]
+    log(f"batch set-up: {len(items)} instances, {sum(x.n for x in insts)} vertices, "
+        f"{time.perf_counter() - t0:.1f} s")
+    # warm-up: a small batch and a small plain run load every kernel
+    wb = gom.gom_batch_init(insts[:4], pops[:4], seeds[:4], targets[:4])
+    gom.gom_batch_run(wb, 2)
+    del wb
+    batch = gom.gom_batch_init(insts, pops, seeds, targets)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, tt = gom.gom_batch_run(batch, max_gens)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ev_batch = sum(r.attempted for r in res)
+    log(f"batched: {t_batch * 1e3:.1f} ms, {ev_batch} attempted, "
+        f"reached {sum(r.reached for r in res)}")
+    states = [x.state(pop=p, seed=sd) for x, p, sd in zip(insts, pops, seeds)]
+    torch.cuda.synchronize()
+    plain_t = []
+    t0 = time.perf_counter()
+    plain = []
+    for st, tg in zip(states, targets):
+        s0 = time.perf_counter()
+        plain.append(gom.gom_run_to_target(st, tg, max_gens))
+        plain_t.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ev_plain = sum(r.attempted for r in plain)
+    same = all((a.generations, a.best, a.evaluated, a.accepted) ==
+               (b.generations, b.best, b.evaluated, b.accepted) for a, b in zip(res, plain))
+    log(f"plain: {t_plain * 1e3:.1f} ms, {ev_plain} attempted, identical results: {same}")
+    tori = [b for b, it in enumerate(items) if it.to_total_weight and res[b].reached]
+    tto_b = np.array([tt[b] for b in tori])
+    tto_p = np.array([plain_t[b] * 1e3 for b in tori])
+    line = {
+        "metric": METRIC, "value": ev_batch / t_batch, "unit": "evals/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"batch{len(items)}_tori_and_regular_1e3_1e5",
+                   "instances": len(items), "vertices": int(sum(x.n for x in insts)),
+                   "pop_range": [16, 64], "max_generations": max_gens, "mode": "batched",
+                   "schedule": "batched_resident"},
+        "plain": {"value": ev_plain / t_plain, "ms": t_plain * 1e3,
+                  "schedule": "auto per instance, one instance at a time"},
+        "batched_over_plain": (ev_batch / t_batch) / (ev_plain / t_plain),
+        "identical_results": same,
+        "time_to_optimum_ms": {
+            "instances_reached": len(tori),
+            "batched_p50": float(np.percentile(tto_b, 50)) if len(tori) else None,
+            "batched_p99": float(np.percentile(tto_b, 99)) if len(tori) else None,
+            "plain_alone_p50": float(np.percentile(tto_p, 50)) if len(tori) else None,
+            "plain_alone_p99": float(np.percentile(tto_p, 99)) if len(tori) else None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,10 +177,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=20,
                     help="generations of the oracle sample for the CPU baseline")
-    ap.add_argument("--schedule", choices=("auto", "class", "resident", "bitsliced"), default="auto",
-                    help="launch schedule of the generations (results are identical)")
+    ap.add_argument("--schedule", choices=("tuned", "auto", "class", "resident", "bitsliced"),
+                    default="tuned",
+                    help="launch schedule of the generations (results are identical); 'tuned' "
+                         "times each allowed schedule on a few generations before the warmup "
+                         "and keeps the fastest")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads.WORKLOADS),
                     help="workload (default: the benchmark configuration)")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched vs plain on the 256-instance mix instead of the default "
+                         "single-instance workload")
+    ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -140,6 +213,9 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.batch:
+        run_batch_mode(args, torch, gom)
+        return
 
     wl = workloads.WORKLOADS[args.workload]
     max_gens = args.max_gens or wl.max_gens
@@ -147,10 +223,13 @@ def main():
     target = g.total_weight if wl.to_total_weight else (1 << 62)
     inst = gom.Instance(g.n, g.u, g.v, g.w, wl.fos)
     st = inst.state(pop=wl.pop, seed=1000)
-    gom.gom_state_set_schedule(st, {"auto": gom.GOM_SCHED_AUTO,
-                                    "class": gom.GOM_SCHED_CLASS_LAUNCH,
-                                    "resident": gom.GOM_SCHED_RESIDENT,
-                                    "bitsliced": gom.GOM_SCHED_BITSLICED}[args.schedule])
+    if args.schedule == "tuned":
+        gom.gom_state_autotune(st, 3)
+    else:
+        gom.gom_state_set_schedule(st, {"auto": gom.GOM_SCHED_AUTO,
+                                        "class": gom.GOM_SCHED_CLASS_LAUNCH,
+                                        "resident": gom.GOM_SCHED_RESIDENT,
+                                        "bitsliced": gom.GOM_SCHED_BITSLICED}[args.schedule])
     sched = gom.gom_state_get_schedule(st)
     sched_name = {gom.GOM_SCHED_RESIDENT: "resident", gom.GOM_SCHED_BITSLICED: "bitsliced"}.get(
         sched, "class_launch")

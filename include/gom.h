@@ -157,8 +157,23 @@ int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t se
 int gom_state_reseed(gom_state *s, uint64_t seed, void *stream);
 
 /* Enqueue one generation (Algorithm 3: clone, every colour class in the generation's order,
- * then P <- O and the elitist update).  Asynchronous. */
+ * then P <- O and the elitist update).  Asynchronous.  If gom_debug_stop_after_class left a
+ * generation open, this finishes it (the remaining classes, then the generation end). */
 int gom_generation(gom_state *s, void *stream);
+
+/*
+ * Debugging view between two groups of Algorithm 3: start the next generation if none is open,
+ * run the colour classes of its order up to and including order position class_position, and
+ * leave it open.  While it is open, gom_state_read and gom_state_hash show the offspring O,
+ * the running fitness (generation-start fitness plus the accepted deltas so far) and running
+ * counters; the generation counter and the elitist are unchanged.  The open part runs under
+ * the class-launch schedule (bit-sliced when that is the chosen one); finishing with
+ * gom_generation gives exactly the uninterrupted generation.  Asynchronous.
+ * GOM_E_RANGE: class_position outside [0, n_classes).  GOM_E_STATE: the open generation has
+ * already run that position.  gom_run_to_target, gom_state_autotune and gom_batch_run return
+ * GOM_E_STATE while a generation is open; gom_state_write and gom_state_reseed close it.
+ */
+int gom_debug_stop_after_class(gom_state *s, int32_t class_position, void *stream);
 
 typedef struct {
     int32_t generations; /* generations run by this call */
@@ -187,6 +202,17 @@ int gom_run_to_target(gom_state *s, int64_t target, int32_t max_generations, voi
  */
 int gom_state_read(gom_state *s, void *stream, uint8_t *genes, int64_t *fitness, uint8_t *elite,
                    int64_t *elite_fitness, int32_t *generation, int64_t *counters);
+
+/*
+ * 64-bit summary of the whole state, for comparing runs generation by generation without
+ * copying populations (synchronous).  Canonical byte string: the genes solution-major (N*n
+ * bytes, 0/1), the N fitness values (8 little-endian bytes each), the elitist's n genes, the
+ * elitist fitness (8), the generation (4), attempted, evaluated, accepted (8 each) -- the
+ * values gom_state_read returns.  hash = sum modulo 2^64 over byte positions k of
+ * M(256*k + b_k), M = the output mixer of SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).
+ * The gene and elitist terms are summed on the device.
+ */
+int gom_state_hash(gom_state *s, void *stream, uint64_t *hash);
 
 /*
  * Overwrite the state (resume from a checkpoint): genes uint8[N*n] (0/1), elite uint8[n],
@@ -229,12 +255,68 @@ int gom_state_set_schedule(gom_state *s, int schedule);
 /* The schedule in use (GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT or GOM_SCHED_BITSLICED). */
 int gom_state_get_schedule(const gom_state *s, int *schedule);
 
+/*
+ * Autotuner: runs `trial_generations` generations under each schedule this instance allows
+ * (class launch, resident, bit-sliced), timing each with HIP events on `stream`, and keeps the
+ * fastest.  The trial generations are ordinary generations of the run (every schedule gives
+ * the same results), so the state advances by (number of schedules tried) x
+ * trial_generations generations.  *chosen (may be NULL) receives the schedule kept.
+ */
+int gom_state_autotune(gom_state *s, int32_t trial_generations, void *stream, int *chosen);
+
 /* Sizes of a state: vertices, population, sets, classes, largest class. */
 int gom_state_info(const gom_state *s, int32_t *n, int32_t *pop, int32_t *n_sets,
                    int32_t *n_classes, int32_t *max_class);
 
 /* Releases host resources of the state; the caller frees the arena afterwards. */
 void gom_state_free(gom_state *s);
+
+/*
+ * Batches: many independent instances (each its own graph, FOS, population and seed) run in
+ * lockstep, one generation step for all of them per group of launches:
+ *   - a sweep launch with one workgroup per (instance, solution) running every colour class
+ *     of that instance (the resident schedule; each workgroup draws its instance's class order
+ *     from the instance's seed and generation);
+ *   - a finalize launch with one wave per instance;
+ *   - a vertex-pass launch over all instances' vertices.
+ * Every instance follows exactly the trajectory it has when run alone with the same seed:
+ * batching changes when work runs, not what is computed.  Instances whose elitist has reached
+ * their target stop changing.  Every instance must fit the resident schedule (n bytes of LDS,
+ * at most GOM_RESIDENT_MAX_CLASSES classes).
+ */
+typedef struct gom_batch gom_batch;
+
+/* Device arena bytes for a batch of `count` instances (graphs[b], fos[b] coloured, pops[b]). */
+int gom_batch_bytes(int32_t count, const mc_graph *const *graphs, const gom_fos *const *fos,
+                    const int32_t *pops, size_t *bytes);
+
+/*
+ * Create a batch in the caller's device arena (256-byte aligned, >= gom_batch_bytes bytes):
+ * instance b gets population pops[b], seed seeds[b] and target targets[b] (the elitist
+ * fitness at which it stops).  Neutral rule and class order as for gom_state_init.  Host
+ * arrays are borrowed; graphs and FOS may be freed afterwards.  Synchronous.
+ * Errors: GOM_E_ARG, GOM_E_RANGE (an instance does not fit the resident schedule, population
+ * outside 2..64), GOM_E_STATE (FOS not coloured), GOM_E_NOMEM, GOM_E_DEVICE.
+ */
+int gom_batch_init(int32_t count, const mc_graph *const *graphs, const gom_fos *const *fos,
+                   const int32_t *pops, const uint64_t *seeds, const int64_t *targets,
+                   int neutral_rule, int class_order, void *dev_arena, size_t arena_bytes,
+                   void *stream, gom_batch **out);
+
+/*
+ * Run generation steps until every instance has reached its target or the batch has run
+ * max_generations steps in total.  Synchronous.  results (count entries, or NULL) as for
+ * gom_run_to_target; time_to_target_ms (count entries, or NULL): device time from the start
+ * of this call to the finalize that first reached the instance's target, or -1.
+ */
+int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream, gom_result *results,
+                  double *time_to_target_ms);
+
+/* Borrowed handle of instance `index` (for gom_state_read); valid until gom_batch_free. */
+int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);
+
+/* Releases the batch and its instances' host resources; the caller frees the arena. */
+void gom_batch_free(gom_batch *b);
 
 #ifdef __cplusplus
 }

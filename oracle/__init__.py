@@ -58,6 +58,10 @@ def lib():
     L.or_get.argtypes = [C.c_void_p, C.c_void_p, _i64p, C.c_void_p, C.POINTER(C.c_int64),
                          C.POINTER(C.c_int32), _i64p]
     L.or_set.argtypes = [C.c_void_p, _u8p, _u8p, C.c_int64, C.c_int32, _i64p]
+    L.or_stop_after_class.restype = C.c_int32
+    L.or_stop_after_class.argtypes = [C.c_void_p, C.c_int32]
+    L.or_hash.restype = C.c_uint64
+    L.or_hash.argtypes = [C.c_void_p]
     _lib = L
     return L
 
@@ -144,6 +148,15 @@ class Run:
 
     def run(self, target: int, max_gens: int) -> int:
         return int(self._L.or_run(self._h, target, max_gens))
+
+    def stop_after_class(self, pos: int):
+        """Run the generation (starting one if none is open) up to class-order position pos
+        and leave it open; state() then shows the offspring and running fitness."""
+        if self._L.or_stop_after_class(self._h, int(pos)) != 0:
+            raise ValueError(f"class position {pos} out of range or already passed")
+
+    def hash(self) -> int:
+        return int(self._L.or_hash(self._h))
 
     def classes(self):
         k = self._L.or_num_classes(self._h)

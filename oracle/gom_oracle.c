@@ -28,6 +28,13 @@
  *       every step (debug flag), hand-worked two-solution examples, invariants (monotone
  *       fitness, converged fixed point, univariate donor independence, in-class order
  *       invariance).  There are no published trajectories to compare against.
+ *   or_stop_after_class  a generation of Algorithm 3 cut after a given position of the class
+ *       order (a debugging view of the offspring between two groups).  Pinned: the literal
+ *       reading of Algorithms 3/4 stopped at the same group.
+ *   or_hash            a 64-bit summary of the state (not from the paper): the sum modulo 2^64
+ *       of SplitMix64's output mixer (Steele, Lea & Flood, OOPSLA 2014) applied to
+ *       256 * k + b_k for every byte b_k at position k of a canonical byte string.  Pinned: a
+ *       numpy evaluation of the same definition on the bytes the accessors return.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -351,6 +358,7 @@ typedef struct or_state {
     uint8_t *P, *O, *E, *eq;
     int64_t *f, fE;
     int32_t gen;
+    int32_t open_next;        /* -1, or the next class position of an unfinished generation */
     int64_t attempted, evaluated, accepted;
     int64_t debug_mismatches;
     /* scratch */
@@ -443,6 +451,7 @@ or_state *or_new(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, con
     int32_t b = best_index(s);
     memcpy(s->E, s->P + (size_t)b * n, (size_t)n);
     s->fE = s->f[b];
+    s->open_next = -1;
     return s;
 }
 
@@ -520,7 +529,8 @@ static void gom_step(or_state *s, int32_t c, int32_t p, int32_t j, int32_t i) {
  *  - after the groups, P <- O and the elitist is replaced when the best solution (lowest index
  *    on ties) is strictly better.
  */
-void or_generation(or_state *s) {
+/* Generation start: equality with the elitist, the class order, O <- P. */
+static void begin_generation(or_state *s) {
     const int32_t n = s->g.n, N = s->N;
     for (int32_t i = 0; i < N; ++i)
         s->eq[i] = memcmp(s->P + (size_t)i * n, s->E, (size_t)n) == 0;
@@ -537,25 +547,86 @@ void or_generation(or_state *s) {
         }
 
     memcpy(s->O, s->P, (size_t)N * n);
+    s->open_next = 0;
+}
+
+/* Every (solution, set) pair of the class at position t of the order. */
+static void run_class(or_state *s, int32_t t) {
+    const int32_t N = s->N;
     const int rev = (s->flags & OR_FLAG_REVERSE) != 0;
-    for (int32_t t = 0; t < s->k; ++t) {
-        int32_t c = s->perm[t];
-        int32_t size = s->class_ptr[c + 1] - s->class_ptr[c];
-        for (int32_t ii = 0; ii < N; ++ii) {
-            int32_t i = rev ? N - 1 - ii : ii;
-            for (int32_t pp = 0; pp < size; ++pp) {
-                int32_t p = rev ? size - 1 - pp : pp;
-                gom_step(s, c, p, s->class_elems[s->class_ptr[c] + p], i);
-            }
+    int32_t c = s->perm[t];
+    int32_t size = s->class_ptr[c + 1] - s->class_ptr[c];
+    for (int32_t ii = 0; ii < N; ++ii) {
+        int32_t i = rev ? N - 1 - ii : ii;
+        for (int32_t pp = 0; pp < size; ++pp) {
+            int32_t p = rev ? size - 1 - pp : pp;
+            gom_step(s, c, p, s->class_elems[s->class_ptr[c] + p], i);
         }
     }
-    memcpy(s->P, s->O, (size_t)N * n);
+}
+
+/* Generation end: P <- O, then the elitist on strict improvement. */
+static void end_generation(or_state *s) {
+    const int32_t n = s->g.n;
+    memcpy(s->P, s->O, (size_t)s->N * n);
     int32_t b = best_index(s);
     if (s->f[b] > s->fE) {
         memcpy(s->E, s->P + (size_t)b * n, (size_t)n);
         s->fE = s->f[b];
     }
     s->gen++;
+    s->open_next = -1;
+}
+
+/* One generation of Algorithm 3 (or the rest of one left open by or_stop_after_class). */
+void or_generation(or_state *s) {
+    if (s->open_next < 0) begin_generation(s);
+    for (int32_t t = s->open_next; t < s->k; ++t) run_class(s, t);
+    end_generation(s);
+}
+
+/* Start a generation if none is open, then run the classes up to order position `pos`
+   (inclusive) and leave the generation open.  Returns -1 (nothing done) when pos is out of
+   range or the open generation has already passed it. */
+int32_t or_stop_after_class(or_state *s, int32_t pos) {
+    if (pos < 0 || pos >= s->k) return -1;
+    if (s->open_next >= 0 && pos < s->open_next) return -1;
+    if (s->open_next < 0) begin_generation(s);
+    for (int32_t t = s->open_next; t <= pos; ++t) run_class(s, t);
+    s->open_next = pos + 1;
+    return 0;
+}
+
+/* The canonical byte string: per solution its n genes (the offspring while a generation is
+   open), each fitness as 8 little-endian bytes, the n elitist genes, the elitist fitness (8),
+   the generation (4), then attempted, evaluated and accepted (8 each). */
+static uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static void hash_bytes(uint64_t *h, uint64_t *k, const uint8_t *b, size_t len) {
+    for (size_t t = 0; t < len; ++t, ++*k) *h += mix64((*k << 8) | b[t]);
+}
+
+static void hash_int(uint64_t *h, uint64_t *k, uint64_t x, int bytes) {
+    for (int t = 0; t < bytes; ++t, ++*k) *h += mix64((*k << 8) | ((x >> (8 * t)) & 0xFFu));
+}
+
+uint64_t or_hash(const or_state *s) {
+    const size_t n = (size_t)s->g.n;
+    const uint8_t *X = s->open_next >= 0 ? s->O : s->P;
+    uint64_t h = 0, k = 0;
+    hash_bytes(&h, &k, X, (size_t)s->N * n);
+    for (int32_t i = 0; i < s->N; ++i) hash_int(&h, &k, (uint64_t)s->f[i], 8);
+    hash_bytes(&h, &k, s->E, n);
+    hash_int(&h, &k, (uint64_t)s->fE, 8);
+    hash_int(&h, &k, (uint64_t)(uint32_t)s->gen, 4);
+    hash_int(&h, &k, (uint64_t)s->attempted, 8);
+    hash_int(&h, &k, (uint64_t)s->evaluated, 8);
+    hash_int(&h, &k, (uint64_t)s->accepted, 8);
+    return h;
 }
 
 /* Generations until the elitist reaches target or max_gens generations have run in total;
@@ -576,12 +647,13 @@ void or_get_classes(const or_state *s, int32_t *class_ptr, int32_t *class_elems)
     memcpy(class_elems, s->class_elems, sizeof(int32_t) * (size_t)s->nsets);
 }
 
-/* genes: N x n bytes (or NULL); fitness: N; elite: n (or NULL); counters: attempted,
-   evaluated, accepted, debug mismatches. */
+/* genes: N x n bytes (or NULL; the offspring while a generation is open); fitness: N (running
+   values while a generation is open); elite: n (or NULL); counters: attempted, evaluated,
+   accepted, debug mismatches. */
 void or_get(const or_state *s, uint8_t *genes, int64_t *fitness, uint8_t *elite,
             int64_t *elite_fitness, int32_t *generation, int64_t counters[4]) {
     const size_t n = (size_t)s->g.n;
-    if (genes) memcpy(genes, s->P, (size_t)s->N * n);
+    if (genes) memcpy(genes, s->open_next >= 0 ? s->O : s->P, (size_t)s->N * n);
     if (fitness) memcpy(fitness, s->f, sizeof(int64_t) * (size_t)s->N);
     if (elite) memcpy(elite, s->E, n);
     if (elite_fitness) *elite_fitness = s->fE;
@@ -607,4 +679,5 @@ void or_set(or_state *s, const uint8_t *genes, const uint8_t *elite, int64_t eli
     s->attempted = counters[0];
     s->evaluated = counters[1];
     s->accepted = counters[2];
+    s->open_next = -1;
 }

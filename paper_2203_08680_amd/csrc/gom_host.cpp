@@ -249,6 +249,7 @@ struct gom_state {
     int2 *d_crec = nullptr;
     std::vector<int2> class_rec;  // host copy of the per-class record placement
     int32_t g_host = 0;                 // next generation index to enqueue
+    int32_t open_next = -1;             // class position where an open generation resumes
     int32_t g_base = 0;                 // generation at which attempted_base was set
     int64_t attempted_base = 0;
     DevState *h_st = nullptr;           // two pinned host slots
@@ -600,6 +601,43 @@ static int timing_record(gom_state *s, hipStream_t st, bool begin) {
 
 // Enqueue generation `gen` (Algorithm 3): every colour class in the generation's order, then
 // the epilogue.  Kernels skip their work when the elitist has already reached `target`.
+static ResidentCtx resident_ctx(const gom_state *s, int64_t target) {
+    ResidentCtx r{};
+    r.P = s->d_P;
+    r.rows = s->d_rows;
+    r.stripes = s->d_stripes;
+    r.st = s->d_st;
+    r.roff = s->d_roff;
+    r.recs = s->d_recs;
+    r.class_rec = s->d_crec;
+    r.class_ptr = s->d_cptr;
+    r.seed = s->seed;
+    r.target = target;
+    r.n = s->n;
+    r.N = s->N;
+    r.k = s->k;
+    r.always = s->rule == GOM_NEUTRAL_ALWAYS;
+    r.row_words = (s->n + 63) / 64;
+    return r;
+}
+
+static EpilogueArgs epilogue_args(const gom_state *s, int64_t target, bool rows) {
+    EpilogueArgs e{};
+    e.P = s->d_P;
+    e.O = s->d_O;
+    e.rows = rows ? s->d_rows : nullptr;
+    e.E = s->d_E;
+    e.fit = s->d_fit;
+    e.st = s->d_st;
+    e.stripes = s->d_stripes;
+    e.target = target;
+    e.n = s->n;
+    e.N = s->N;
+    e.mode = kEpiGeneration;
+    e.row_words = (s->n + 63) / 64;
+    return e;
+}
+
 static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool rows) {
     EpilogueArgs e{};
     e.P = s->d_P;
@@ -618,34 +656,10 @@ static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool r
     return GOM_OK;
 }
 
-static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStream_t st) {
-    const std::vector<int32_t> perm = class_order(s, gen);
-    if (s->sched == GOM_SCHED_RESIDENT) {
-        ResidentArgs r{};
-        r.P = s->d_P;
-        r.rows = s->d_rows;
-        r.stripes = s->d_stripes;
-        r.st = s->d_st;
-        r.roff = s->d_roff;
-        r.recs = s->d_recs;
-        r.class_rec = s->d_crec;
-        r.class_ptr = s->d_cptr;
-        r.seed = s->seed;
-        r.target = target;
-        r.n = s->n;
-        r.N = s->N;
-        r.gen = gen;
-        r.k = s->k;
-        r.always = s->rule == GOM_NEUTRAL_ALWAYS;
-        r.row_words = (s->n + 63) / 64;
-        for (int32_t t = 0; t < s->k; ++t) r.order[t] = (uint16_t)perm[t];
-        int rc = timing_record(s, st, true);
-        if (rc) return rc;
-        HIP_TRY(launch_resident_sweep(r, s->univariate ? 0 : 1, st));
-        rc = timing_record(s, st, false);
-        if (rc) return rc;
-        return enqueue_epilogue(s, target, st, true);
-    }
+// Class sweeps for order positions [t0, t1) of generation `gen` under the per-class schedules
+// (bit-sliced when chosen, else class launch).
+static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, int32_t gen,
+                               int32_t t0, int32_t t1, int64_t target, hipStream_t st) {
     SweepArgs a{};
     a.P = s->d_P;
     a.O = s->d_O;
@@ -658,7 +672,7 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
     a.N = s->N;
     a.gen = gen;
     a.always = s->rule == GOM_NEUTRAL_ALWAYS;
-    for (int32_t t = 0; t < s->k; ++t) {
+    for (int32_t t = t0; t < t1; ++t) {
         const int32_t c = perm[t];
         a.cls = c;
         a.cbase = s->class_ptr[c];
@@ -674,6 +688,33 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         rc = timing_record(s, st, false);
         if (rc) return rc;
     }
+    return GOM_OK;
+}
+
+static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStream_t st) {
+    const std::vector<int32_t> perm = class_order(s, gen);
+    if (s->open_next >= 0) {
+        // finish a generation left open by gom_debug_stop_after_class; its offspring are in
+        // the O planes, so the rest runs class by class
+        int rc = enqueue_class_range(s, perm, gen, s->open_next, s->k, target, st);
+        if (rc) return rc;
+        s->open_next = -1;
+        return enqueue_epilogue(s, target, st, false);
+    }
+    if (s->sched == GOM_SCHED_RESIDENT) {
+        ResidentArgs r{};
+        r.c = resident_ctx(s, target);
+        r.c.gen = gen;
+        for (int32_t t = 0; t < s->k; ++t) r.order[t] = (uint16_t)perm[t];
+        int rc = timing_record(s, st, true);
+        if (rc) return rc;
+        HIP_TRY(launch_resident_sweep(r, s->univariate ? 0 : 1, st));
+        rc = timing_record(s, st, false);
+        if (rc) return rc;
+        return enqueue_epilogue(s, target, st, true);
+    }
+    int rc = enqueue_class_range(s, perm, gen, 0, s->k, target, st);
+    if (rc) return rc;
     return enqueue_epilogue(s, target, st, false);
 }
 
@@ -700,6 +741,7 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
         s->g_host = 0;
         s->g_base = 0;
         s->attempted_base = 0;
+        s->open_next = -1;
     }
     return e;
 }
@@ -828,9 +870,61 @@ extern "C" int gom_generation(gom_state *s, void *stream) {
     GUARD_END
 }
 
+extern "C" int gom_debug_stop_after_class(gom_state *s, int32_t class_position, void *stream) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_debug_stop_after_class: null state");
+    if (class_position < 0 || class_position >= s->k)
+        return fail(GOM_E_RANGE, "gom_debug_stop_after_class: position %d outside [0, %d)",
+                    class_position, s->k);
+    const int32_t from = s->open_next >= 0 ? s->open_next : 0;
+    if (class_position < from)
+        return fail(GOM_E_STATE,
+                    "gom_debug_stop_after_class: the open generation is already past position %d",
+                    class_position);
+    const std::vector<int32_t> perm = class_order(s, s->g_host);
+    int rc = enqueue_class_range(s, perm, s->g_host, from, class_position + 1, INT64_MAX,
+                                 (hipStream_t)stream);
+    if (rc) return rc;
+    s->open_next = class_position + 1;
+    return GOM_OK;
+    GUARD_END
+}
+
 static int read_scalars(gom_state *s, hipStream_t st, DevState *h) {
     HIP_TRY(hipMemcpyAsync(h, s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return GOM_OK;
+}
+
+// Fitness and counters of the state.  While a generation is open the running values are the
+// stored ones plus what the class sweeps have added to the stripes so far.
+static int read_fitness_counters(gom_state *s, hipStream_t st, int64_t *fit, DevState *h,
+                                 int64_t counters[3]) {
+    HIP_TRY(hipMemcpyAsync(fit, s->d_fit, sizeof(int64_t) * (size_t)s->N, hipMemcpyDeviceToHost,
+                           st));
+    std::vector<Stripe> stripes;
+    if (s->open_next >= 0) {
+        stripes.resize(kStripes);
+        HIP_TRY(hipMemcpyAsync(stripes.data(), s->d_stripes, sizeof(Stripe) * kStripes,
+                               hipMemcpyDeviceToHost, st));
+    }
+    int rc = read_scalars(s, st, h);
+    if (rc) return rc;
+    counters[0] =
+        s->attempted_base + (int64_t)s->N * s->n_sets * (int64_t)(h->generation - s->g_base);
+    counters[1] = h->evaluated;
+    counters[2] = h->accepted;
+    if (s->open_next >= 0) {
+        for (const Stripe &sp : stripes) {
+            for (int32_t i = 0; i < s->N; ++i) fit[i] += sp.fit[i];
+            counters[1] += (int64_t)sp.evaluated;
+            counters[2] += (int64_t)sp.accepted;
+        }
+        const std::vector<int32_t> perm = class_order(s, s->g_host);
+        for (int32_t t = 0; t < s->open_next; ++t)
+            counters[0] += (int64_t)s->N *
+                           (s->class_ptr[(size_t)perm[t] + 1] - s->class_ptr[perm[t]]);
+    }
     return GOM_OK;
 }
 
@@ -838,6 +932,9 @@ extern "C" int gom_run_to_target(gom_state *s, int64_t target, int32_t max_gener
                                  void *stream, gom_result *out) {
     GUARD_BEGIN
     if (!s) return fail(GOM_E_ARG, "gom_run_to_target: null state");
+    if (s->open_next >= 0)
+        return fail(GOM_E_STATE, "gom_run_to_target: a generation is open (finish it with "
+                                 "gom_generation)");
     hipStream_t st = (hipStream_t)stream;
     int rc = read_scalars(s, st, &s->h_st[0]);
     if (rc) return rc;
@@ -896,19 +993,19 @@ extern "C" int gom_state_read(gom_state *s, void *stream, uint8_t *genes, int64_
     std::vector<uint64_t> P, E;
     int64_t fit[GOM_MAX_POP];
     if (genes) {
+        // the offspring planes while a generation is open (equal to P otherwise)
         P.resize((size_t)s->n);
-        HIP_TRY(hipMemcpyAsync(P.data(), s->d_P, sizeof(uint64_t) * (size_t)s->n,
-                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(P.data(), s->open_next >= 0 ? s->d_O : s->d_P,
+                               sizeof(uint64_t) * (size_t)s->n, hipMemcpyDeviceToHost, st));
     }
     if (elite) {
         E.resize((size_t)((s->n + 63) / 64));
         HIP_TRY(hipMemcpyAsync(E.data(), s->d_E, sizeof(uint64_t) * E.size(),
                                hipMemcpyDeviceToHost, st));
     }
-    HIP_TRY(hipMemcpyAsync(fit, s->d_fit, sizeof(int64_t) * (size_t)s->N, hipMemcpyDeviceToHost,
-                           st));
     DevState h;
-    int rc = read_scalars(s, st, &h);
+    int64_t cnt[3];
+    int rc = read_fitness_counters(s, st, fit, &h, cnt);
     if (rc) return rc;
     if (genes)
         for (int32_t i = 0; i < s->N; ++i) {
@@ -920,12 +1017,37 @@ extern "C" int gom_state_read(gom_state *s, void *stream, uint8_t *genes, int64_
     if (fitness) std::copy(fit, fit + s->N, fitness);
     if (elite_fitness) *elite_fitness = h.elite_fitness;
     if (generation) *generation = h.generation;
-    if (counters) {
-        counters[0] =
-            s->attempted_base + (int64_t)s->N * s->n_sets * (int64_t)(h.generation - s->g_base);
-        counters[1] = h.evaluated;
-        counters[2] = h.accepted;
-    }
+    if (counters) std::copy(cnt, cnt + 3, counters);
+    return GOM_OK;
+    GUARD_END
+}
+
+// Terms of the state hash for `bytes` little-endian bytes of x at positions k, k+1, ...
+static uint64_t hash_int(uint64_t &k, uint64_t x, int bytes) {
+    uint64_t h = 0;
+    for (int t = 0; t < bytes; ++t, ++k) h += mix64((k << 8) | ((x >> (8 * t)) & 0xFFu));
+    return h;
+}
+
+extern "C" int gom_state_hash(gom_state *s, void *stream, uint64_t *hash) {
+    GUARD_BEGIN
+    if (!s || !hash) return fail(GOM_E_ARG, "gom_state_hash: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t n = (uint64_t)s->n, N = (uint64_t)s->N;
+    HIP_TRY(launch_state_hash(s->open_next >= 0 ? s->d_O : s->d_P, s->d_E, s->n, s->N,
+                              N * n + 8 * N, s->d_st, st));
+    int64_t fit[GOM_MAX_POP];
+    DevState h;
+    int64_t cnt[3];
+    int rc = read_fitness_counters(s, st, fit, &h, cnt);
+    if (rc) return rc;
+    uint64_t acc = h.hash, k = N * n;
+    for (int32_t i = 0; i < s->N; ++i) acc += hash_int(k, (uint64_t)fit[i], 8);
+    k += n;  // the elitist's bytes, summed on the device
+    acc += hash_int(k, (uint64_t)h.elite_fitness, 8);
+    acc += hash_int(k, (uint64_t)(uint32_t)h.generation, 4);
+    for (int c = 0; c < 3; ++c) acc += hash_int(k, (uint64_t)cnt[c], 8);
+    *hash = acc;
     return GOM_OK;
     GUARD_END
 }
@@ -954,6 +1076,7 @@ extern "C" int gom_state_write(gom_state *s, void *stream, const uint8_t *genes,
     h.evaluated = counters[1];
     h.accepted = counters[2];
     h.generation = generation;
+    h.done_tick = -1;
     HIP_TRY(hipMemcpyAsync(s->d_P, P.data(), sizeof(uint64_t) * P.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s->d_O, P.data(), sizeof(uint64_t) * P.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s->d_E, E.data(), sizeof(uint64_t) * E.size(), hipMemcpyHostToDevice, st));
@@ -976,6 +1099,7 @@ extern "C" int gom_state_write(gom_state *s, void *stream, const uint8_t *genes,
     s->g_host = generation;
     s->g_base = generation;
     s->attempted_base = counters[0];
+    s->open_next = -1;
     return GOM_OK;
     GUARD_END
 }
@@ -1035,6 +1159,55 @@ extern "C" int gom_state_set_schedule(gom_state *s, int schedule) {
     }
 }
 
+extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void *stream,
+                                  int *chosen) {
+    GUARD_BEGIN
+    if (!s || trial_generations < 1) return fail(GOM_E_ARG, "gom_state_autotune: bad arguments");
+    if (s->open_next >= 0) return fail(GOM_E_STATE, "gom_state_autotune: a generation is open");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int> cands = {GOM_SCHED_CLASS_LAUNCH};
+    if (s->resident_ok) cands.push_back(GOM_SCHED_RESIDENT);
+    if (s->bitsliced_ok) cands.push_back(GOM_SCHED_BITSLICED);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GOM_E_DEVICE, "gom_state_autotune: %s", hipGetErrorString(he));
+    }
+    const bool timing = s->timing != 0;
+    s->timing = 0;
+    int best = s->sched, rc = GOM_OK;
+    float best_ms = 0.f;
+    for (int c : cands) {
+        s->sched = c;
+        // one untimed generation loads the schedule's kernels, then the timed ones
+        for (int32_t t = 0; t <= trial_generations && rc == GOM_OK; ++t) {
+            if (t == 1 && hipEventRecord(e0, st) != hipSuccess) rc = GOM_E_DEVICE;
+            if (rc == GOM_OK) rc = enqueue_generation(s, s->g_host, INT64_MAX, st);
+            if (rc == GOM_OK) s->g_host++;
+        }
+        if (rc == GOM_OK && hipEventRecord(e1, st) != hipSuccess) rc = GOM_E_DEVICE;
+        float ms = 0.f;
+        if (rc == GOM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = GOM_E_DEVICE;
+        if (rc != GOM_OK) break;
+        if (c == cands.front() || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->timing = timing;
+    if (rc != GOM_OK) return fail(rc, "gom_state_autotune: a trial generation failed");
+    s->sched = best;
+    if (chosen) *chosen = best;
+    return GOM_OK;
+    GUARD_END
+}
+
 extern "C" int gom_state_get_schedule(const gom_state *s, int *schedule) {
     if (!s || !schedule) return fail(GOM_E_ARG, "gom_state_get_schedule: null argument");
     *schedule = s->sched;
@@ -1059,4 +1232,249 @@ extern "C" void gom_state_free(gom_state *s) {
         if (e) (void)hipEventDestroy(e);
     if (s->h_st) (void)hipHostFree(s->h_st);
     delete s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Batches of independent instances
+// ------------------------------------------------------------------------------------------
+struct gom_batch {
+    int32_t count = 0;
+    std::vector<gom_state *> subs;      // owned
+    std::vector<int64_t> targets;
+    BatchInst *d_insts = nullptr;
+    int2 *d_blk = nullptr;
+    int32_t *d_vblk = nullptr;
+    DevState *d_snap = nullptr;         // packed copy of the instances' run scalars
+    int sweep_blocks = 0, vblocks = 0, lds_n = 0;
+    DevState *h_st = nullptr;           // pinned, 2 x count
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+    double wall_khz = 0.0;
+    int32_t g_done = 0;                 // generation steps run
+};
+
+namespace {
+struct BatchLayout {
+    std::vector<size_t> sub_off, sub_bytes;
+    size_t insts = 0, blk = 0, vblk = 0, snap = 0, total = 0;
+    int sweep_blocks = 0, vblocks = 0;
+};
+
+int batch_layout(int32_t count, const mc_graph *const *graphs, const gom_fos *const *fos,
+                 const int32_t *pops, BatchLayout &B) {
+    size_t o = 0;
+    B.sub_off.resize((size_t)count);
+    B.sub_bytes.resize((size_t)count);
+    int sweep = 0, vb = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        size_t bytes = 0;
+        int rc = gom_state_bytes(graphs[b], fos[b], pops[b], &bytes);
+        if (rc) return rc;
+        B.sub_off[(size_t)b] = o;
+        B.sub_bytes[(size_t)b] = bytes;
+        o = align_up(o + bytes);
+        sweep += pops[b];
+        vb += (graphs[b]->n + 255) / 256;
+    }
+    B.insts = o;
+    o = align_up(o + sizeof(BatchInst) * (size_t)count);
+    B.blk = o;
+    o = align_up(o + sizeof(int2) * (size_t)sweep);
+    B.vblk = o;
+    o = align_up(o + sizeof(int32_t) * (size_t)vb);
+    B.snap = o;
+    o = align_up(o + sizeof(DevState) * (size_t)count);
+    B.total = o;
+    B.sweep_blocks = sweep;
+    B.vblocks = vb;
+    return GOM_OK;
+}
+}  // namespace
+
+extern "C" int gom_batch_bytes(int32_t count, const mc_graph *const *graphs,
+                               const gom_fos *const *fos, const int32_t *pops, size_t *bytes) {
+    GUARD_BEGIN
+    if (count < 1 || !graphs || !fos || !pops || !bytes)
+        return fail(GOM_E_ARG, "gom_batch_bytes: bad arguments");
+    BatchLayout B;
+    int rc = batch_layout(count, graphs, fos, pops, B);
+    if (rc) return rc;
+    *bytes = B.total;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" void gom_batch_free(gom_batch *b) {
+    if (!b) return;
+    for (gom_state *s : b->subs) gom_state_free(s);
+    for (hipEvent_t e : b->chunk_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->h_st) (void)hipHostFree(b->h_st);
+    delete b;
+}
+
+extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
+                              const gom_fos *const *fos, const int32_t *pops,
+                              const uint64_t *seeds, const int64_t *targets, int neutral_rule,
+                              int class_order, void *dev_arena, size_t arena_bytes,
+                              void *stream, gom_batch **out) {
+    GUARD_BEGIN
+    if (count < 1 || !graphs || !fos || !pops || !seeds || !targets || !dev_arena || !out)
+        return fail(GOM_E_ARG, "gom_batch_init: bad arguments");
+    BatchLayout B;
+    int rc = batch_layout(count, graphs, fos, pops, B);
+    if (rc) return rc;
+    if (arena_bytes < B.total)
+        return fail(GOM_E_NOMEM, "gom_batch_init: arena has %zu bytes, needs %zu", arena_bytes,
+                    B.total);
+    if ((reinterpret_cast<uintptr_t>(dev_arena) & 255) != 0)
+        return fail(GOM_E_NOMEM, "gom_batch_init: arena must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char *arena = (char *)dev_arena;
+    auto *bt = new gom_batch;
+    bt->count = count;
+    bt->targets.assign(targets, targets + count);
+    auto cleanup = [&](int code) {
+        gom_batch_free(bt);
+        return code;
+    };
+    std::vector<BatchInst> insts((size_t)count);
+    std::vector<int2> blk;
+    std::vector<int32_t> vblk;
+    for (int32_t b = 0; b < count; ++b) {
+        gom_state *s = nullptr;
+        rc = gom_state_init(graphs[b], fos[b], pops[b], seeds[b], neutral_rule, class_order,
+                            arena + B.sub_off[(size_t)b], B.sub_bytes[(size_t)b], stream, &s);
+        if (rc) return cleanup(rc);
+        bt->subs.push_back(s);
+        if (!s->resident_ok)
+            return cleanup(fail(GOM_E_RANGE, "gom_batch_init: instance %d does not fit the "
+                                "resident schedule (n = %d, %d classes)", b, s->n, s->k));
+        BatchInst &I = insts[(size_t)b];
+        I.res = resident_ctx(s, targets[b]);
+        I.epi = epilogue_args(s, targets[b], true);
+        I.kind = s->univariate ? 0 : 1;
+        I.order_fixed = s->order == GOM_ORDER_FIXED;
+        I.vblock0 = (int32_t)vblk.size();
+        for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2(b, i));
+        for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back(b);
+        bt->lds_n = std::max(bt->lds_n, s->n);
+    }
+    bt->d_insts = (BatchInst *)(arena + B.insts);
+    bt->d_blk = (int2 *)(arena + B.blk);
+    bt->d_vblk = (int32_t *)(arena + B.vblk);
+    bt->d_snap = (DevState *)(arena + B.snap);
+    bt->sweep_blocks = B.sweep_blocks;
+    bt->vblocks = B.vblocks;
+    int khz = 0, dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->d_insts, insts.data(), sizeof(BatchInst) * insts.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->d_blk, blk.data(), sizeof(int2) * blk.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->d_vblk, vblk.data(), sizeof(int32_t) * vblk.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&bt->h_st, 2 * sizeof(DevState) * (size_t)count,
+                          hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->chunk_ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->chunk_ev[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return cleanup(fail(GOM_E_DEVICE, "gom_batch_init: %s", hipGetErrorString(e)));
+    bt->wall_khz = (double)khz;
+    *out = bt;
+    return GOM_OK;
+    GUARD_END
+}
+
+// Copy every instance's run scalars into pinned slot `slot` (asynchronous): a gather kernel
+// packs them next to each other, then one copy.
+static hipError_t batch_snapshot(gom_batch *b, int slot, hipStream_t st) {
+    DevState *dst = b->h_st + (size_t)slot * (size_t)b->count;
+    hipError_t e = launch_batch_gather(b->d_insts, b->count, b->d_snap, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(dst, b->d_snap, sizeof(DevState) * (size_t)b->count,
+                          hipMemcpyDeviceToHost, st);
+}
+
+static bool batch_all_done(const gom_batch *b, int slot) {
+    const DevState *h = b->h_st + (size_t)slot * (size_t)b->count;
+    for (int32_t i = 0; i < b->count; ++i)
+        if (h[i].elite_fitness < b->targets[(size_t)i]) return false;
+    return true;
+}
+
+extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream,
+                             gom_result *results, double *time_to_target_ms) {
+    GUARD_BEGIN
+    if (!b) return fail(GOM_E_ARG, "gom_batch_run: null batch");
+    for (int32_t i = 0; i < b->count; ++i)
+        if (b->subs[(size_t)i]->open_next >= 0)
+            return fail(GOM_E_STATE, "gom_batch_run: instance %d has an open generation", i);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_batch_mark(b->d_insts, b->count, st));
+    HIP_TRY(batch_snapshot(b, 0, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> g0((size_t)b->count);
+    for (int32_t i = 0; i < b->count; ++i) g0[(size_t)i] = b->h_st[i].generation;
+    constexpr int32_t kChunk = 4;
+    if (!batch_all_done(b, 0)) {
+        int32_t issued = b->g_done;
+        int slot = 0, prev = -1;
+        for (;;) {
+            const int32_t n = std::min(kChunk, max_generations - issued);
+            int cur = -1;
+            if (n > 0) {
+                for (int32_t t = 0; t < n; ++t)
+                    HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk, b->sweep_blocks,
+                                              b->d_vblk, b->vblocks, b->lds_n, st));
+                issued += n;
+                cur = slot;
+                HIP_TRY(batch_snapshot(b, cur, st));
+                HIP_TRY(hipEventRecord(b->chunk_ev[cur], st));
+                slot ^= 1;
+            }
+            if (prev >= 0) {
+                HIP_TRY(hipEventSynchronize(b->chunk_ev[prev]));
+                if (batch_all_done(b, prev)) break;
+            }
+            if (cur < 0) break;
+            prev = cur;
+        }
+        b->g_done = issued;
+    }
+    HIP_TRY(batch_snapshot(b, 0, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t i = 0; i < b->count; ++i) {
+        const DevState &h = b->h_st[i];
+        gom_state *s = b->subs[(size_t)i];
+        s->g_host = h.generation;
+        if (results) {
+            gom_result &r = results[i];
+            r.generations = h.generation - g0[(size_t)i];
+            r.reached = h.elite_fitness >= b->targets[(size_t)i];
+            r.best = h.elite_fitness;
+            r.attempted = s->attempted_base +
+                          (int64_t)s->N * s->n_sets * (int64_t)(h.generation - s->g_base);
+            r.evaluated = h.evaluated;
+            r.accepted = h.accepted;
+        }
+        if (time_to_target_ms)
+            time_to_target_ms[i] = h.done_tick >= 0 && b->wall_khz > 0
+                                       ? (double)(h.done_tick - h.start_tick) / b->wall_khz
+                                       : -1.0;
+    }
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_batch_state(gom_batch *b, int32_t index, gom_state **state) {
+    if (!b || !state || index < 0 || index >= b->count)
+        return fail(GOM_E_ARG, "gom_batch_state: bad arguments");
+    *state = b->subs[(size_t)index];
+    return GOM_OK;
 }

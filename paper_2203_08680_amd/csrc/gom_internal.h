@@ -38,6 +38,14 @@ __host__ __device__ __forceinline__ U32x4 philox(uint64_t seed, uint32_t c0, uin
     return {x0, x1, x2, x3};
 }
 
+// Output mixer of SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the state hash is the sum
+// modulo 2^64 of mix64(256 k + b_k) over the bytes b_k of a canonical byte string.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // Counter word values that keep the three Philox streams apart: generation indices and class
 // indices are below 0xFFFFFFFF.
 constexpr uint32_t kInitStream = 0xFFFFFFFFu;   // counter (kInitStream, i, v/128, 0)
@@ -52,7 +60,9 @@ struct alignas(64) DevState {
     int32_t best;            // best solution at the last finalize (lowest index on ties)
     int32_t new_elite;       // the last finalize replaced the elitist by solution `best`
     int32_t active;          // the last finalize closed a generation that ran
-    int32_t pad[6];
+    int64_t start_tick;      // device wall clock at the start of a batch run
+    int64_t done_tick;       // device wall clock when the elitist reached the target (or -1)
+    uint64_t hash;           // accumulator of the state hash's gene and elitist terms
 };
 
 // Accumulators that many blocks add into.  Device-scope atomics on one address serialise
@@ -120,7 +130,7 @@ constexpr int kResidentThreads = 1024;
 constexpr int kResidentMaxClasses = 1536;
 constexpr int kResidentChunkSlots = kResidentThreads;  // Philox calls per round (8 sets each)
 
-struct ResidentArgs {
+struct ResidentCtx {
     const uint64_t *P;
     uint64_t *rows;         // N rows of row_words words: bit (v mod 64) of word v / 64
     Stripe *stripes;
@@ -133,12 +143,32 @@ struct ResidentArgs {
     int64_t target;
     int32_t n;
     int32_t N;
-    int32_t gen;
+    int32_t gen;            // generation index (single-state launches)
     int32_t k;
     int32_t always;
     int32_t row_words;
+};
+
+struct ResidentArgs {
+    ResidentCtx c;
     uint16_t order[kResidentMaxClasses];  // class order of this generation
 };
+
+// Batch of independent instances run in lockstep: one launch per generation step for each of
+// the sweep (one block per (instance, solution)), the finalize (one wave per instance) and the
+// vertex pass (blocks of every instance's vertices).  Instances whose elitist has reached
+// their target skip their work.
+struct BatchInst {
+    ResidentCtx res;
+    EpilogueArgs epi;
+    int32_t kind;           // 0 univariate records, 1 general
+    int32_t order_fixed;    // class order ascending instead of shuffled
+    int32_t vblock0;        // first vertex-pass block of the instance
+    int32_t pad;
+};
+
+// Dynamic LDS of the batched sweep before the resident part: class order and draws.
+constexpr int kBatchOrderBytes = 4 * kResidentMaxClasses;
 
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
@@ -153,6 +183,18 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStr
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
                                  hipStream_t s);
 hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s);
+// Batched generation step over `count` instances: sweep grid = sum of populations (blk[b] =
+// {instance, solution}), vertex-pass grid = vblocks (vblk[b] = instance); lds_n = the largest
+// instance's vertex count.
+hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
+                             const int32_t *vblk, int vblocks, int lds_n, hipStream_t s);
+hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s);
+// Pack every instance's DevState into out[count].
+hipError_t launch_batch_gather(const BatchInst *insts, int count, DevState *out, hipStream_t s);
+// State hash, gene and elitist terms: st->hash <- sum over v of the terms of bit i of X[v] at
+// byte position i*n + v (every solution i < N) and of the elitist bit v at position ebase + v.
+hipError_t launch_state_hash(const uint64_t *X, const uint64_t *E, int n, int N, uint64_t ebase,
+                             DevState *st, hipStream_t s);
 // Generation end: finalize (one block) then the vertex pass.
 hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
 size_t resident_lds_bytes(int n);

@@ -24,7 +24,7 @@ namespace {
 
 static_assert(kStripes == 64, "one stripe per lane of a wave");
 
-constexpr int kSweepThreads = 512;  // 8 waves of 64 lanes
+constexpr int kSweepThreads = 256;  // 4 waves of 64 lanes
 constexpr int kEpiThreads = 256;
 constexpr int kFitThreads = 256;
 
@@ -93,6 +93,8 @@ __global__ __launch_bounds__(256) void k_init_population(uint64_t *P, uint64_t *
             st->best = 0;
             st->new_elite = 0;
             st->active = 0;
+            st->start_tick = 0;
+            st->done_tick = -1;
         }
     }
     const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -198,20 +200,50 @@ __device__ __forceinline__ int32_t signed_w(uint32_t same, int32_t w) { return s
 // O_i; `commit(u, flip)` is called once per member u (by every lane of a group, so it may
 // use cross-lane operations) and flips O_i[u] when `flip`.  `h` is the 16-bit donor draw,
 // `cand` the mask of possible donors (every solution but i).
+// The first words of a record: the header and the first entry batches (8 entries for a
+// univariate record, 16 for a small set), fetched together so a kernel can issue them before
+// it waits for anything else.  Reads past a short record stay inside the buffer's zero tail;
+// entries beyond nd are masked before use.
+struct Head {
+    int4 h0, h1, h2, h3;
+    int2 en0[kBatch], en1[kBatch];
+};
+
+template <int KIND>
+__device__ __forceinline__ Head load_head(const int32_t *R) {
+    Head hd;
+    const int4 *R4 = reinterpret_cast<const int4 *>(R);
+    hd.h0 = R4[0];
+    if constexpr (KIND == 0) {
+        const int2 *E = reinterpret_cast<const int2 *>(R + 4);
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) hd.en0[t] = E[t];
+    } else {
+        hd.h1 = R4[1];
+        hd.h2 = R4[2];
+        hd.h3 = R4[3];
+        const int2 *E = reinterpret_cast<const int2 *>(R + 16);
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) {
+            hd.en0[t] = E[t];
+            hd.en1[t] = E[kBatch + t];
+        }
+    }
+    return hd;
+}
+
 template <int KIND, class Bits, class Commit>
-__device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P, Bits bits,
-                                            Commit commit, uint64_t cand, uint32_t h,
+__device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, const uint64_t *P,
+                                            Bits bits, Commit commit, uint64_t cand, uint32_t h,
                                             bool neutral_ok) {
     PairOut out{0u, false, 0};
-    const int4 h0 = *reinterpret_cast<const int4 *>(R);
+    const int4 h0 = hd.h0;
     if constexpr (KIND == 0) {
         // one variable u: the donor always differs at u, so C = {u} whenever a donor exists
         const int2 *E = reinterpret_cast<const int2 *>(R + 4);
-        // first batch fetched with the header (reads past a short record stay inside the
-        // buffer's zero tail; entries beyond nd are masked before use)
         int2 en[kBatch];
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) en[t] = E[t];
+        for (int t = 0; t < kBatch; ++t) en[t] = hd.en0[t];
         const int u = h0.x, nd = h0.y;
         const uint32_t ou = bits(u);
         const uint64_t D = (P[u] ^ (0ull - (uint64_t)ou)) & cand;
@@ -236,17 +268,9 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P,
     } else {
         const int nm = h0.x, nd = h0.y;
         if (nm <= kSmallSet) {
-            const int4 h1 = *reinterpret_cast<const int4 *>(R + 4);
-            const int4 h2 = *reinterpret_cast<const int4 *>(R + 8);
-            const int4 h3 = *reinterpret_cast<const int4 *>(R + 12);
+            const int4 h1 = hd.h1, h2 = hd.h2, h3 = hd.h3;
             const int2 *E = reinterpret_cast<const int2 *>(R + 16);
-            // first two batches fetched with the header (see the univariate case)
-            int2 en0[kBatch], en1[kBatch];
-#pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                en0[t] = E[t];
-                en1[t] = E[kBatch + t];
-            }
+            const int2 *en0 = hd.en0, *en1 = hd.en1;
             const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x};
             const int end[kSmallSet] = {h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
             (void)end;
@@ -349,16 +373,16 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P,
 // step of Algorithm 2 for every (solution, set) pair of the class at once).
 //
 // Mapping: a group of G lanes (G = 16, 32 or 64, the population rounded up) takes one set of
-// the class; lane i of the group is solution i.  A block of 8 waves takes a tile of
-// 8 * 64 / G consecutive class positions.  All sets of one class are independent (no shared
-// or adjacent variables), so groups never read a word that another group of the same launch
-// writes, and each O word of a set is written by exactly one lane.
+// the class; lane i of the group is solution i.  Waves work independently (no block
+// barriers): wave w takes class positions w * 64/G .. + 64/G - 1, then strides by the number
+// of waves in the grid.  All sets of one class are independent (no shared or adjacent
+// variables), so groups never read a word that another group of the same launch writes, and
+// each O word of a set is written by exactly one lane.
 //
 // Per pair (solution i, set F_j at class position p):
 //   D      = solutions d != i whose P genes differ from O_i somewhere on F_j (64-bit mask,
 //            OR over the members of (P[u] xor broadcast(O_i[u])))
-//   h      = 16-bit field (p mod 8) of Philox(seed; g, c, i, p / 8); the block draws the 64
-//            calls of a tile once (wave 0) and shares them through LDS
+//   h      = 16-bit field (p mod 8) of Philox(seed; g, c, i, p / 8), drawn by the lane
 //   donor  = the r-th set bit of D with r = (h * |D|) >> 16
 //   C      = members u where the donor's gene differs from O_i[u]
 //   delta  = sum over the set's dependent edges of the change of the cut: an outside edge
@@ -366,7 +390,7 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const uint64_t *P,
 //            change is +w if the edge was uncut, -w if it was cut
 //   accept = |D| > 0 and (delta > 0 or (delta == 0 and (always or P_i != elitist)))
 //   commit = one word store per member: O[u] ^= ballot(accept and u in C)
-// Fitness changes and counts are summed per block and added to the block's stripe.
+// Fitness changes and counts are summed per wave and added to the wave's stripe.
 // ------------------------------------------------------------------------------------------
 template <int G>
 struct PlaneCommit {
@@ -382,87 +406,66 @@ struct PlaneCommit {
 
 template <int G, int KIND>
 __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const uint64_t mism = a.stripes[lane].mism;
-    if (a.st->elite_fitness >= a.target) return;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr int GPW = 64 / G;          // sets per wave
-    constexpr int PER_TILE = 8 * GPW;    // sets per block tile (multiple of 8)
+    const int lane = threadIdx.x & 63;
     const int grp = lane / G;
     const uint32_t i = (uint32_t)(lane % G);
+    const int gw = blockIdx.x * (kSweepThreads / 64) + (int)(threadIdx.x >> 6);  // global wave
+    const int nwaves = gridDim.x * (kSweepThreads / 64);
+    auto record = [&](int p) {
+        return a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p];
+    };
+    // issue the first record's loads together with the run-state loads
+    const uint64_t mism = a.stripes[lane].mism;
+    const int64_t elite_fitness = a.st->elite_fitness;
+    int p = gw * GPW + grp;
+    const int32_t *R = record(p < a.csize ? p : 0);
+    Head hd = load_head<KIND>(R);
+    if (elite_fitness >= a.target) return;
     const bool act = (int)i < a.N;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
     const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
 
-    __shared__ uint32_t rng[64][4];
-    __shared__ int64_t red[kSweepThreads];
-    __shared__ uint32_t redc[2][8];
-
     int64_t facc = 0;
     uint32_t n_eval = 0, n_acc = 0;
     const PlaneBits bits{a.O, i};
     const PlaneCommit<G> commit{a.O, grp, i};
-    const int ntiles = (a.csize + PER_TILE - 1) / PER_TILE;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int base = tile * PER_TILE;
-        if constexpr (KIND != 0) {
-            if (wave == 0) {
-                const int q = lane / G;
-                const int p0 = base + q * 8;
-                if (p0 < a.csize) {
-                    const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls,
-                                           (uint32_t)(lane % G), (uint32_t)(p0 >> 3));
-                    rng[lane][0] = r.x;
-                    rng[lane][1] = r.y;
-                    rng[lane][2] = r.z;
-                    rng[lane][3] = r.w;
-                }
-            }
-            __syncthreads();
+    const int nwt = (a.csize + GPW - 1) / GPW;  // wave tiles
+    for (int wt = gw; wt < nwt; wt += nwaves) {
+        if (wt != gw) {
+            p = wt * GPW + grp;
+            R = record(p < a.csize ? p : 0);
+            hd = load_head<KIND>(R);
         }
-        const int local = wave * GPW + grp;
-        const int p = base + local;
         if (p < a.csize) {
             uint32_t h = 0;
             if constexpr (KIND != 0) {
-                const int f = local & 7;
-                h = (rng[(local >> 3) * G + (int)i][f >> 1] >> (16 * (f & 1))) & 0xFFFFu;
+                // each lane draws its own call; the 8 positions of a chunk share the counter
+                const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i,
+                                       (uint32_t)(p >> 3));
+                const int f = p & 7;
+                const uint32_t w = (f >> 1) == 0 ? r.x : (f >> 1) == 1 ? r.y
+                                 : (f >> 1) == 2 ? r.z : r.w;
+                h = (w >> (16 * (f & 1))) & 0xFFFFu;
             }
-            const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride
-                                         : a.recs + a.roff[a.cbase + p];
-            const PairOut r = gom_pair<KIND>(R, a.P, bits, commit, cand, h, neutral_ok);
+            const PairOut r = gom_pair<KIND>(R, hd, a.P, bits, commit, cand, h, neutral_ok);
             facc += r.acc ? r.delta : 0;
             n_eval += r.cnt > 0;
             n_acc += r.acc;
         }
-        if constexpr (KIND != 0) __syncthreads();
     }
 
-    red[tid] = facc;
-    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
-    if (lane == 0) {
-        redc[0][wave] = ce;
-        redc[1][wave] = ca;
-    }
-    __syncthreads();
-    Stripe *sp = a.stripes + (blockIdx.x % kStripes);
-    if (tid < G && tid < a.N) {
-        int64_t sum = 0;
-        for (int w = 0; w < 8; ++w)
+    // per-wave results into stripe (global wave index mod kStripes)
 #pragma unroll
-            for (int g2 = 0; g2 < GPW; ++g2) sum += red[w * 64 + g2 * G + tid];
-        if (sum) atomicAdd((unsigned long long *)&sp->fit[tid], (unsigned long long)sum);
-    }
-    if (tid == 0) {
-        uint32_t se = 0, sa = 0;
-        for (int w = 0; w < 8; ++w) {
-            se += redc[0][w];
-            sa += redc[1][w];
-        }
-        if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
-        if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
+    for (int off = 32; off >= G; off >>= 1) facc += __shfl_xor(facc, off, 64);
+    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
+    Stripe *sp = a.stripes + (gw % kStripes);
+    if (lane < G && act && facc)
+        atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
+    if (lane == 0) {
+        if (ce) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)ce);
+        if (ca) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)ca);
     }
 }
 
@@ -609,16 +612,15 @@ struct LdsCommit {
 };
 
 template <int KIND>
-__global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
+__device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16_t *order,
+                                              int gen, int i, uint8_t *lds) {
     const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
     if (a.st->elite_fitness >= a.target) return;
-    extern __shared__ __align__(16) uint8_t lds[];
     uint32_t(*rng)[4] = reinterpret_cast<uint32_t(*)[4]>(lds);
     int64_t *redf = reinterpret_cast<int64_t *>(lds + kResRngBytes);
     uint32_t *redc = reinterpret_cast<uint32_t *>(lds + kResRngBytes + 128);
     uint8_t *ob = lds + kResRngBytes + kResRedBytes;
 
-    const int i = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t cand = popm & ~(1ull << i);
@@ -632,15 +634,21 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
     int64_t facc = 0;
     uint32_t n_eval = 0, n_acc = 0;
     for (int t = 0; t < a.k; ++t) {
-        const int c = a.order[t];
+        const int c = order[t];
         const int cbase = a.class_ptr[c];
         const int csize = a.class_ptr[c + 1] - cbase;
         const int2 cr = a.class_rec[c];  // {first record word, record stride or 0}
+        auto record = [&](int p) {
+            return cr.y ? a.recs + cr.x + p * cr.y : a.recs + a.roff[cbase + p];
+        };
         for (int base = 0; base < csize; base += 8 * kResidentChunkSlots) {
             const int span = min(csize - base, 8 * kResidentChunkSlots);
+            // issue this thread's first record of the round before the draws and the barrier
+            const int32_t *R = record(base + (tid < span ? tid : 0));
+            Head hd = load_head<KIND>(R);
             if constexpr (KIND != 0) {
                 if (tid < ((span + 7) >> 3)) {
-                    const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)c, (uint32_t)i,
+                    const U32x4 r = philox(a.seed, (uint32_t)gen, (uint32_t)c, (uint32_t)i,
                                            (uint32_t)((base >> 3) + tid));
                     rng[tid][0] = r.x;
                     rng[tid][1] = r.y;
@@ -655,9 +663,11 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
                     const int f = q & 7;
                     h = (rng[q >> 3][f >> 1] >> (16 * (f & 1))) & 0xFFFFu;
                 }
-                const int32_t *R = cr.y ? a.recs + cr.x + (base + q) * cr.y
-                                        : a.recs + a.roff[cbase + base + q];
-                const PairOut r = gom_pair<KIND>(R, a.P, bits, commit, cand, h, neutral_ok);
+                if (q != tid) {
+                    R = record(base + q);
+                    hd = load_head<KIND>(R);
+                }
+                const PairOut r = gom_pair<KIND>(R, hd, a.P, bits, commit, cand, h, neutral_ok);
                 facc += r.acc ? r.delta : 0;
                 n_eval += r.cnt > 0;
                 n_acc += r.acc;
@@ -694,6 +704,12 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
     }
 }
 
+template <int KIND>
+__global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    resident_body<KIND>(a.c, a.order, a.c.gen, blockIdx.x, lds);
+}
+
 // ------------------------------------------------------------------------------------------
 // Generation end (Algorithm 3: P <- O; the elitist is kept across generations), part 1, one
 // wave: fitness of solution t = previous fitness + the stripes' changes; counters; best
@@ -701,7 +717,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
 // (mode 0), always (mode 1, initial population) or never (mode 2).  Clears the stripes.
 // A generation skipped because the target was reached leaves everything as it is.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) {
+__device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     DevState *st = a.st;
     const int t = threadIdx.x;
     const int64_t fE = st->elite_fitness;
@@ -712,6 +728,7 @@ __global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) {
     int64_t f = INT64_MIN;
     if (t < a.N) {
         int64_t d = 0;
+#pragma unroll 16
         for (int s = 0; s < kStripes; ++s) d += a.stripes[s].fit[t];
         f = a.fit[t] + d;
         a.fit[t] = f;
@@ -730,6 +747,7 @@ __global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) {
         }
     }
     __syncthreads();
+#pragma unroll 16
     for (int s = 0; s < kStripes; ++s) a.stripes[s].fit[t] = 0;
     a.stripes[t].evaluated = 0;
     a.stripes[t].accepted = 0;
@@ -743,8 +761,11 @@ __global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) {
         if (a.mode == kEpiGeneration) st->generation += 1;
         st->evaluated += ev;
         st->accepted += ac;
+        if (newE && fb >= a.target && st->done_tick < 0) st->done_tick = (int64_t)wall_clock64();
     }
 }
+
+__global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) { finalize_body(a); }
 
 // ------------------------------------------------------------------------------------------
 // Generation end, part 2, one thread per vertex: P <- O (mode 0; from the O planes, or from
@@ -753,20 +774,20 @@ __global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) {
 // from the elitist, OR-ed per block into the block's stripe.  The next generation's sweeps
 // read those stripes to know which solutions equal the elitist.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kEpiThreads) void k_vertex_pass(EpilogueArgs a) {
+__device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
     const DevState *st = a.st;
     if (!st->active) return;
     const int b = st->best;
     const bool newE = st->new_elite != 0;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int v = blockIdx.x * kEpiThreads + tid;
+    const int v = vblock * kEpiThreads + tid;
     const bool in = v < a.n;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     uint64_t o = 0ull;
     if (a.rows) {
         // lane t loads solution t's row word for this wave's 64 vertices; 64 ballots
         // transpose the 64 x 64 bit block so lane k ends with vertex k's word
-        const int wv = (blockIdx.x * kEpiThreads + (tid & ~63)) >> 6;
+        const int wv = (vblock * kEpiThreads + (tid & ~63)) >> 6;
         const uint64_t word =
             (lane < a.N && wv < a.row_words) ? a.rows[(size_t)lane * a.row_words + wv] : 0ull;
 #pragma unroll
@@ -799,12 +820,113 @@ __global__ __launch_bounds__(kEpiThreads) void k_vertex_pass(EpilogueArgs a) {
 #pragma unroll
         for (int w = 0; w < kEpiThreads / 64; ++w) mm |= sm[w];
         if (mm)
-            atomicOr((unsigned long long *)&a.stripes[blockIdx.x % kStripes].mism,
+            atomicOr((unsigned long long *)&a.stripes[vblock % kStripes].mism,
                      (unsigned long long)mm);
     }
 }
 
+__global__ __launch_bounds__(kEpiThreads) void k_vertex_pass(EpilogueArgs a) {
+    vertex_body(a, blockIdx.x);
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched generation step.  The sweep block for (instance b, solution i) first draws the
+// instance's class order for its current generation (Fisher-Yates with the order stream:
+// the draws in parallel, the swaps by one thread), then runs the resident sweep.  The
+// finalize and vertex-pass blocks find their instance through the block maps.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kResidentThreads) void k_batch_sweep(const BatchInst *insts,
+                                                                 const int2 *blk) {
+    extern __shared__ __align__(16) uint8_t lds_all[];
+    uint16_t *order = reinterpret_cast<uint16_t *>(lds_all);
+    uint16_t *draw = order + kResidentMaxClasses;
+    const int2 bi = blk[blockIdx.x];
+    const BatchInst *I = insts + bi.x;
+    const ResidentCtx a = I->res;
+    if (a.st->elite_fitness >= a.target) return;
+    const int gen = a.st->generation;
+    const bool fixed = I->order_fixed != 0;
+    for (int t = threadIdx.x; t < a.k; t += kResidentThreads) {
+        order[t] = (uint16_t)t;
+        if (!fixed && t >= 1) {
+            const U32x4 r = philox(a.seed, (uint32_t)gen, kOrderStream, (uint32_t)t, 0u);
+            draw[t] = (uint16_t)(((uint64_t)r.x * (uint64_t)(t + 1)) >> 32);
+        }
+    }
+    __syncthreads();
+    if (!fixed && threadIdx.x == 0)
+        for (int t = a.k - 1; t >= 1; --t) {
+            const uint16_t x = order[t];
+            order[t] = order[draw[t]];
+            order[draw[t]] = x;
+        }
+    __syncthreads();
+    if (I->kind == 0)
+        resident_body<0>(a, order, gen, bi.y, lds_all + kBatchOrderBytes);
+    else
+        resident_body<1>(a, order, gen, bi.y, lds_all + kBatchOrderBytes);
+}
+
+__global__ __launch_bounds__(64) void k_batch_finalize(const BatchInst *insts) {
+    finalize_body(insts[blockIdx.x].epi);
+}
+
+__global__ __launch_bounds__(kEpiThreads) void k_batch_vertex(const BatchInst *insts,
+                                                              const int32_t *vblk) {
+    const BatchInst *I = insts + vblk[blockIdx.x];
+    vertex_body(I->epi, (int)blockIdx.x - I->vblock0);
+}
+
+// Start of a batch run: every instance's start tick, and its done tick if the target is
+// already reached.
+__global__ void k_batch_mark(const BatchInst *insts, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    DevState *st = insts[t].epi.st;
+    const int64_t now = (int64_t)wall_clock64();
+    st->start_tick = now;
+    st->done_tick = st->elite_fitness >= insts[t].epi.target ? now : -1;
+}
+
+// State hash terms of the genes (solution i, vertex v at byte i*n + v) and of the elitist
+// bits (byte ebase + v); per-wave sums, one atomic add per wave (the sum is modulo 2^64, so the
+// order of the adds does not change it).
+__global__ __launch_bounds__(256) void k_state_hash(const uint64_t *X, const uint64_t *E, int n,
+                                                   int N, uint64_t ebase, DevState *st) {
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    uint64_t h = 0;
+    if (v < n) {
+        const uint64_t x = X[v];
+        for (int i = 0; i < N; ++i)
+            h += mix64((((uint64_t)i * (uint64_t)n + (uint64_t)v) << 8) | ((x >> i) & 1ull));
+        const uint64_t e = (E[v >> 6] >> (v & 63)) & 1ull;
+        h += mix64(((ebase + (uint64_t)v) << 8) | e);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&st->hash, (unsigned long long)h);
+}
+
+__global__ void k_hash_zero(DevState *st) { st->hash = 0; }
+
+__global__ void k_batch_gather(const BatchInst *insts, int count, DevState *out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) out[t] = *insts[t].epi.st;
+}
+
 }  // namespace
+
+hipError_t launch_state_hash(const uint64_t *X, const uint64_t *E, int n, int N, uint64_t ebase,
+                             DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_hash_zero, dim3(1), dim3(1), 0, s, st);
+    hipLaunchKernelGGL(k_state_hash, dim3((n + 255) / 256), dim3(256), 0, s, X, E, n, N, ebase, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const BatchInst *insts, int count, DevState *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_gather, dim3((count + 63) / 64), dim3(64), 0, s, insts, count, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
                                   Stripe *stripes, int n, int N, uint64_t seed, hipStream_t s) {
@@ -834,7 +956,7 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
 
 hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s) {
     const int G = a.N <= 16 ? 16 : (a.N <= 32 ? 32 : 64);
-    const int per_tile = 8 * (64 / G);
+    const int per_tile = (kSweepThreads / 64) * (64 / G);  // sets per block
     int grid = (a.csize + per_tile - 1) / per_tile;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
@@ -868,7 +990,7 @@ size_t resident_lds_bytes(int n) {
 }
 
 hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s) {
-    const size_t lds = resident_lds_bytes(a.n);
+    const size_t lds = resident_lds_bytes(a.c.n);
     // Raise the dynamic LDS limit of the kernel to what this launch needs (once per size).
     static size_t attr_bytes[2] = {0, 0};
     const void *fn = kind == 0 ? (const void *)k_resident_sweep<0>
@@ -880,9 +1002,35 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s)
         attr_bytes[kind] = lds;
     }
     if (kind == 0)
-        hipLaunchKernelGGL((k_resident_sweep<0>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
+        hipLaunchKernelGGL((k_resident_sweep<0>), dim3(a.c.N), dim3(kResidentThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((k_resident_sweep<1>), dim3(a.N), dim3(kResidentThreads), lds, s, a);
+        hipLaunchKernelGGL((k_resident_sweep<1>), dim3(a.c.N), dim3(kResidentThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
+                             const int32_t *vblk, int vblocks, int lds_n, hipStream_t s) {
+    const size_t lds = (size_t)kBatchOrderBytes + resident_lds_bytes(lds_n);
+    static size_t attr_bytes = 0;
+    if (lds > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch_sweep,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_bytes = lds;
+    }
+    hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_blocks), dim3(kResidentThreads), lds, s, insts,
+                       blk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(64), 0, s, insts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_vertex, dim3(vblocks), dim3(kEpiThreads), 0, s, insts, vblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_mark, dim3((count + 255) / 256), dim3(256), 0, s, insts, count);
     return hipGetLastError();
 }
 

@@ -27,7 +27,9 @@ EXPORTED = (
     "gom_fos_free", "gom_colour", "gom_colour_get", "gom_state_bytes", "gom_state_init",
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
-    "gom_state_info", "gom_state_free",
+    "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash",
+    "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
+    "gom_batch_state", "gom_batch_free",
 )
 
 
@@ -86,8 +88,17 @@ def lib() -> C.CDLL:
         "gom_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
         "gom_state_set_schedule": (C.c_int, [_vp, C.c_int]),
         "gom_state_get_schedule": (C.c_int, [_vp, _P(C.c_int)]),
+        "gom_state_autotune": (C.c_int, [_vp, _i32, _vp, _P(C.c_int)]),
+        "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
+        "gom_state_hash": (C.c_int, [_vp, _vp, _P(C.c_uint64)]),
         "gom_state_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
         "gom_state_free": (None, [_vp]),
+        "gom_batch_bytes": (C.c_int, [_i32, _vp, _vp, _vp, _P(_sz)]),
+        "gom_batch_init": (C.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, _vp, _sz,
+                                     _vp, _P(_vp)]),
+        "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+        "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
+        "gom_batch_free": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -238,6 +249,9 @@ class GomState:
         self.close()
 
     def close(self):
+        if getattr(self, "_borrowed", False):
+            self.handle = None
+            return
         if getattr(self, "handle", None) and _lib is not None:
             _lib.gom_state_free(self.handle)
             self.handle = None
@@ -339,6 +353,27 @@ def gom_state_get_schedule(s: GomState) -> int:
     return v.value
 
 
+def gom_state_autotune(s: GomState, trial_generations: int = 3, stream=None) -> int:
+    """Time each allowed schedule on real generations and keep the fastest; returns it."""
+    v = C.c_int()
+    _check(lib().gom_state_autotune(s.handle, int(trial_generations), _stream_handle(stream),
+                                    C.byref(v)))
+    return v.value
+
+
+def gom_debug_stop_after_class(s: GomState, class_position: int, stream=None) -> None:
+    """Run the next generation up to class-order position class_position and leave it open."""
+    _check(lib().gom_debug_stop_after_class(s.handle, int(class_position),
+                                            _stream_handle(stream)))
+
+
+def gom_state_hash(s: GomState, stream=None) -> int:
+    """64-bit hash of the state (genes, fitness, elitist, generation, counters)."""
+    v = C.c_uint64()
+    _check(lib().gom_state_hash(s.handle, _stream_handle(stream), C.byref(v)))
+    return int(v.value)
+
+
 def gom_version() -> int:
     return int(lib().gom_version())
 
@@ -366,3 +401,79 @@ class Instance:
               class_order: int = GOM_ORDER_RANDOM, device=None, stream=None) -> GomState:
         return gom_state_init(self.graph, self.fos, pop, seed, neutral_rule, class_order,
                               device, stream)
+
+
+# ------------------------------------------------------------------------------------------
+# Batches of independent instances
+# ------------------------------------------------------------------------------------------
+class GomBatch:
+    """Owned gom_batch handle plus the torch tensor holding its device arena."""
+
+    def __init__(self, handle: int, arena, instances, pops):
+        self.handle = handle
+        self.arena = arena
+        self.instances = instances  # keep the graphs/FOS alive with the batch
+        self.pops = list(pops)
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gom_batch_free(self.handle)
+            self.handle = None
+
+    def state(self, index: int) -> "GomState":
+        h = _vp()
+        _check(lib().gom_batch_state(self.handle, int(index), C.byref(h)))
+        st = GomState.__new__(GomState)
+        st.handle, st.arena, st.n, st.pop = h.value, None, self.instances[index].n, \
+            self.pops[index]
+        st._borrowed = True
+        return st
+
+
+def _handles(objs):
+    arr = (C.c_void_p * len(objs))(*[o.handle for o in objs])
+    return arr
+
+
+def gom_batch_bytes(instances, pops) -> int:
+    b = _sz()
+    pops = np.ascontiguousarray(pops, np.int32)
+    _check(lib().gom_batch_bytes(len(instances), _handles([x.graph for x in instances]),
+                                 _handles([x.fos for x in instances]), _ptr(pops), C.byref(b)))
+    return b.value
+
+
+def gom_batch_init(instances, pops, seeds, targets, neutral_rule: int = GOM_NEUTRAL_PAPER,
+                   class_order: int = GOM_ORDER_RANDOM, device=None, stream=None) -> GomBatch:
+    """instances: list of Instance (graph + coloured FOS)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    pops = np.ascontiguousarray(pops, np.int32)
+    seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    targets = np.ascontiguousarray(targets, np.int64)
+    nbytes = gom_batch_bytes(instances, pops)
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    off = (-arena.data_ptr()) % 256
+    h = _vp()
+    with torch.cuda.device(dev):
+        _check(lib().gom_batch_init(len(instances), _handles([x.graph for x in instances]),
+                                    _handles([x.fos for x in instances]), _ptr(pops),
+                                    _ptr(seeds), _ptr(targets), int(neutral_rule),
+                                    int(class_order), arena.data_ptr() + off, nbytes,
+                                    _stream_handle(stream), C.byref(h)))
+    return GomBatch(h.value, arena, list(instances), pops)
+
+
+def gom_batch_run(b: GomBatch, max_generations: int, stream=None):
+    """(list of RunResult, numpy array of time-to-target milliseconds, -1 if not reached)."""
+    n = len(b.instances)
+    res = (gom_result * n)()
+    tt = np.zeros(n, np.float64)
+    _check(lib().gom_batch_run(b.handle, int(max_generations), _stream_handle(stream), res,
+                               _ptr(tt)))
+    out = [RunResult(r.generations, bool(r.reached), r.best, r.attempted, r.evaluated,
+                     r.accepted) for r in res]
+    return out, tt

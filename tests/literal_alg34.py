@@ -72,11 +72,13 @@ class LiteralParGomea:
                 perm[t], perm[r] = perm[r], perm[t]
         return perm
 
-    def generation(self):
+    def generation(self, stop_after=None):
+        """One generation.  With stop_after = t, a copy of (O, f, evaluated, accepted) taken
+        right after the group at order position t is kept in self.mid."""
         N, g = self.N, self.g
         eq = np.array([np.array_equal(self.P[i], self.E) for i in range(N)])
         O = self.P.copy()                                        # Clone(P)
-        for c in self.group_order():
+        for t, c in enumerate(self.group_order()):
             G = self.classes[c]
             # DetermineAndInsertDonorGenes
             Op = O.copy()
@@ -122,6 +124,8 @@ class LiteralParGomea:
                         self.f[i] += delta[p, i]
             self.evaluated += int(has.sum())
             self.accepted += int(M.sum())
+            if t == stop_after:
+                self.mid = (O.copy(), self.f.copy(), self.evaluated, self.accepted)
         self.P = O                                               # P <- O
         b = int(np.argmax(self.f))
         if self.f[b] > self.fE:

@@ -248,6 +248,91 @@ def test_schedule_selection(cuda):
         gom.gom_state_set_schedule(st, gom.GOM_SCHED_RESIDENT)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_autotune_generations_are_ordinary(cuda, kind):
+    """The autotuner's trial generations are ordinary generations: afterwards the state equals
+    the oracle's after the same number of generations, and later generations under the chosen
+    schedule stay equal."""
+    print(f"case autotune kind={kind}", flush=True)
+    g = workloads.torus(20, 1, 9, seed=3)
+    _, st, ref = make_pair(g, kind, 24, 5)
+    chosen = gom.gom_state_autotune(st, 2)
+    allowed = {gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT}
+    if kind == 0:
+        allowed.add(gom.GOM_SCHED_BITSLICED)
+    assert chosen in allowed and gom.gom_state_get_schedule(st) == chosen
+    done = gom.gom_state_read(st, genes=False)["generation"]
+    assert done == 3 * len(allowed)
+    for _ in range(done):
+        ref.generation()
+    assert_same(gom.gom_state_read(st), ref.state(), "after autotune")
+    lockstep(st, ref, 3, "after autotune")
+
+
+STOP_CASES = [
+    # (label, graph maker, FOS kind, population, schedule)
+    ("torus20_nbhd_class", lambda: workloads.torus(20, 1, 9, seed=3), 1, 24,
+     gom.GOM_SCHED_CLASS_LAUNCH),
+    ("torus20_nbhd_resident", lambda: workloads.torus(20, 1, 9, seed=3), 1, 24,
+     gom.GOM_SCHED_RESIDENT),
+    ("cm_d5_nbhd_resident", lambda: workloads.configuration_model(300, 5, seed=8), 1, 37,
+     gom.GOM_SCHED_RESIDENT),
+    ("torus20_uni_bitsliced", lambda: workloads.torus(20, 1, 9, seed=3), 0, 64,
+     gom.GOM_SCHED_BITSLICED),
+    ("cm_d3_uni_class", lambda: workloads.configuration_model(500, 3, seed=2), 0, 5,
+     gom.GOM_SCHED_CLASS_LAUNCH),
+]
+
+
+@pytest.mark.parametrize("label,maker,kind,pop,sched", STOP_CASES,
+                         ids=[c[0] for c in STOP_CASES])
+def test_debug_stop_after_class(cuda, label, maker, kind, pop, sched):
+    """Generations cut after a class position: the offspring, running fitness and counters
+    (and the state hash) equal the oracle's cut at the same position; finishing the
+    generation equals the oracle's; the chosen schedule resumes afterwards."""
+    print(f"case stop_after_class {label}", flush=True)
+    g = maker()
+    _, st, ref = make_pair(g, kind, pop, 7, sched=sched)
+    cp, _ = ref.classes()
+    k = len(cp) - 1
+    for gen in range(4):
+        stops = [gen % k] if gen % 2 == 0 else sorted({0, k // 2, k - 1})
+        for pos in stops:
+            gom.gom_debug_stop_after_class(st, pos)
+            ref.stop_after_class(pos)
+            assert_same(gom.gom_state_read(st), ref.state(), f"{label} gen {gen} stop {pos}")
+            assert gom.gom_state_hash(st) == ref.hash(), f"{label} gen {gen} stop {pos} hash"
+        if k > 1 and stops[-1] > 0:
+            with pytest.raises(gom.GomError):
+                gom.gom_debug_stop_after_class(st, stops[-1] - 1)
+            with pytest.raises(gom.GomError):
+                gom.gom_run_to_target(st, 1 << 62, 100)
+        gom.gom_generation(st)
+        ref.generation()
+        assert_same(gom.gom_state_read(st), ref.state(), f"{label} gen {gen} end")
+        assert gom.gom_state_hash(st) == ref.hash()
+        assert gom.gom_state_get_schedule(st) == sched
+    with pytest.raises(gom.GomError):
+        gom.gom_debug_stop_after_class(st, k)
+    lockstep(st, ref, 2, f"{label} after stops")
+
+
+def test_state_hash_full_size(cuda):
+    """Per-generation hashes at the full 10^5-vertex size (no population copies) equal the
+    oracle's."""
+    print("case hash cm100k_d3_uni_p32", flush=True)
+    g = workloads.configuration_model(100_000, 3, seed=3)
+    _, st, ref = make_pair(g, 0, 32, 2)
+    assert gom.gom_state_hash(st) == ref.hash()
+    for gen in range(4):
+        gom.gom_generation(st)
+        ref.generation()
+        assert gom.gom_state_hash(st) == ref.hash(), gen
+    gom.gom_debug_stop_after_class(st, 1)
+    ref.stop_after_class(1)
+    assert gom.gom_state_hash(st) == ref.hash()
+
+
 BITSLICED_CASES = [
     # (label, graph maker, population, neutral rule, explicit duplicate singletons)
     ("torus10_p16", lambda: workloads.torus(10, 1, 5, seed=1), 16, 0, False),
@@ -304,3 +389,52 @@ def test_bitsliced_rejected_when_not_eligible(cuda):
     st = inst.state(pop=8, seed=1)
     with pytest.raises(gom.GomError):
         gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+
+
+def _batch_setup(items):
+    insts = [gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
+             for it in items]
+    targets = [it.graph.total_weight if it.to_total_weight else (1 << 62) for it in items]
+    return insts, targets
+
+
+def test_batch_each_instance_equals_its_solo_run(cuda):
+    """A batch of mixed instances (tori and random graphs, both FOS kinds, populations 16-64)
+    run in lockstep: every instance ends exactly where its solo run (same seed, same target,
+    same generation limit) ends, and the small ones match the oracle."""
+    print("case batch vs solo", flush=True)
+    items = workloads.batch_mix(count=10, seed=11, n_lo=60, n_hi=3000)
+    insts, targets = _batch_setup(items)
+    max_gens = 12
+    batch = gom.gom_batch_init(insts, [it.pop for it in items], [it.seed for it in items],
+                               targets)
+    res, tt = gom.gom_batch_run(batch, max_gens)
+    for b, it in enumerate(items):
+        st = insts[b].state(pop=it.pop, seed=it.seed)
+        r = gom.gom_run_to_target(st, targets[b], max_gens)
+        a, s = gom.gom_state_read(batch.state(b)), gom.gom_state_read(st)
+        assert_same(a, s, f"batch instance {b} vs solo")
+        assert (res[b].generations, res[b].reached, res[b].best) == (r.generations, r.reached,
+                                                                    r.best)
+        assert res[b].reached == (tt[b] >= 0)
+        if it.graph.n <= 400:
+            ptr, vars_ = oracle.fos(it.graph, it.fos)
+            ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=it.seed)
+            ref.run(targets[b], max_gens)
+            assert_same(a, ref.state(), f"batch instance {b} vs oracle")
+
+
+def test_batch_continues_across_calls(cuda):
+    """Two gom_batch_run calls of 4 and 6 steps equal one of 10."""
+    print("case batch continue", flush=True)
+    items = workloads.batch_mix(count=6, seed=12, n_lo=200, n_hi=2000)
+    insts, targets = _batch_setup(items)
+    pops, seeds = [it.pop for it in items], [it.seed for it in items]
+    b1 = gom.gom_batch_init(insts, pops, seeds, targets)
+    gom.gom_batch_run(b1, 4)
+    gom.gom_batch_run(b1, 10)
+    b2 = gom.gom_batch_init(insts, pops, seeds, targets)
+    gom.gom_batch_run(b2, 10)
+    for b in range(len(items)):
+        assert_same(gom.gom_state_read(b1.state(b)), gom.gom_state_read(b2.state(b)),
+                    f"instance {b}")

@@ -278,6 +278,99 @@ def test_oracle_equals_literal_algorithm_3_4(n, d, kind, pop, rule, order):
         assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted)
 
 
+@pytest.mark.parametrize("n,d,kind,pop,order", [(12, 3, 1, 5, 0), (16, 4, 0, 4, 0),
+                                                 (18, 5, 1, 9, 1)])
+def test_stop_after_class_equals_literal_groups(n, d, kind, pop, order):
+    """A generation cut after each class position shows the literal reading's offspring,
+    running fitness and counters after the same group; finishing it equals an uncut
+    generation."""
+    g = workloads.configuration_model(n, d, seed=n + 100 * d, weights="signed50")
+    ptr, vars_ = oracle.fos(g, kind)
+    run = oracle.Run(g, ptr, vars_, pop=pop, seed=n * pop, order=order)
+    whole = oracle.Run(g, ptr, vars_, pop=pop, seed=n * pop, order=order)
+    cp, ce = run.classes()
+    k = len(cp) - 1
+    classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(k)]
+    for gen in range(4):
+        for t in range(k):
+            lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=n * pop, order=order,
+                                  P=run.state()["genes"])
+            s0 = run.state()
+            lit.E, lit.fE, lit.gen = s0["elite"].copy(), s0["elite_fitness"], s0["generation"]
+            lit.evaluated, lit.accepted = s0["evaluated"], s0["accepted"]
+            lit.generation(stop_after=t)
+            probe = oracle.Run(g, ptr, vars_, pop=pop, seed=n * pop, order=order)
+            probe.set_state(s0["genes"], s0["elite"], s0["elite_fitness"], s0["generation"],
+                            [s0["attempted"], s0["evaluated"], s0["accepted"]])
+            probe.stop_after_class(t)
+            m = probe.state()
+            O, f, ev, ac = lit.mid
+            assert np.array_equal(m["genes"], O), (gen, t)
+            assert m["fitness"].tolist() == f.tolist(), (gen, t)
+            assert (m["evaluated"], m["accepted"]) == (ev, ac), (gen, t)
+            assert m["generation"] == s0["generation"]
+            probe.generation()
+            lit2 = probe.state()
+            assert np.array_equal(lit2["genes"], lit.P) and lit2["fitness"].tolist() == lit.f.tolist()
+        run.stop_after_class(gen % k)
+        with pytest.raises(ValueError):
+            run.stop_after_class(k)
+        if gen % k > 0:
+            with pytest.raises(ValueError):
+                run.stop_after_class(gen % k - 1)
+        run.generation()
+        whole.generation()
+        a, b = run.state(), whole.state()
+        for key in ("genes", "fitness", "elite", "elite_fitness", "generation", "attempted",
+                    "evaluated", "accepted"):
+            assert np.array_equal(a[key], b[key]), (gen, key)
+
+
+def _hash_definition(s):
+    """The state hash from its definition, over the bytes the accessors return: the sum
+    modulo 2^64 of SplitMix64's output mixer of 256 k + b_k over the canonical string."""
+    def le(x, nbytes):
+        return list(int(x & ((1 << (8 * nbytes)) - 1)).to_bytes(nbytes, "little"))
+    parts = [s["genes"].reshape(-1).astype(np.uint64)]
+    parts.append(np.array([b for f in s["fitness"].tolist() for b in le(f, 8)], np.uint64))
+    parts.append(s["elite"].astype(np.uint64))
+    tail = le(s["elite_fitness"], 8) + le(s["generation"], 4)
+    for key in ("attempted", "evaluated", "accepted"):
+        tail += le(s[key], 8)
+    parts.append(np.array(tail, np.uint64))
+    b = np.concatenate(parts)
+    z = (np.arange(b.shape[0], dtype=np.uint64) << np.uint64(8)) | b
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+        return int(z.sum(dtype=np.uint64))
+
+
+def test_state_hash_definition():
+    """The oracle's state hash equals its definition at the start, mid-generation and after
+    generations, and changes when any part of the state changes."""
+    g = workloads.torus(6, 1, 9, seed=3)
+    ptr, vars_ = oracle.fos(g, 1)
+    run = oracle.Run(g, ptr, vars_, pop=7, seed=11)
+    seen = set()
+    for step in range(5):
+        s = run.state()
+        assert run.hash() == _hash_definition(s), step
+        seen.add(run.hash())
+        if step % 2:
+            run.generation()
+        else:
+            run.stop_after_class(0)
+    assert len(seen) == 5
+    s = run.state()
+    genes = s["genes"].copy()
+    genes[3, 5] ^= 1
+    run.set_state(genes, s["elite"], s["elite_fitness"], s["generation"],
+                  [s["attempted"], s["evaluated"], s["accepted"]])
+    assert run.hash() == _hash_definition(run.state()) and run.hash() not in seen
+
+
 def test_initial_population_rule():
     g = workloads.torus(12, 1, 3, seed=2)
     ptr, vars_ = oracle.fos(g, 0)

@@ -149,3 +149,36 @@ for _d in (3, 6, 12):
     for _k, _fn in ((0, "uni"), (1, "nbhd")):
         WORKLOADS[f"cm100k_d{_d}_{_fn}_p32"] = Workload(
             f"cm100k_d{_d}_{_fn}_p32", _c3(_d), _k, 32, 200, False)
+
+
+@dataclass(frozen=True)
+class BatchItem:
+    graph: Graph
+    fos: int
+    pop: int
+    seed: int
+    to_total_weight: bool
+
+
+def batch_mix(count: int = 256, seed: int = 4, n_lo: float = 1e3, n_hi: float = 1e5):
+    """Many independent instances for batched runs: n log-uniform in [n_lo, n_hi]; even
+    positions are L x L tori (L = n's square root rounded to an even number, >= 4), odd ones
+    configuration-model graphs of degree 4 and 8 alternately; weights uniform in [1, 100];
+    populations uniform in [16, 64]; univariate and neighbourhood FOS alternate in pairs.
+    Tori have the total weight as their optimum (even torus, positive weights)."""
+    rng = np.random.default_rng(seed)
+    items = []
+    for k in range(count):
+        n = int(round(10 ** rng.uniform(np.log10(n_lo), np.log10(n_hi))))
+        pop = int(rng.integers(16, 65))
+        fos = 0 if k % 4 < 2 else 1
+        if k % 2 == 0:
+            L = max(4, 2 * int(round(np.sqrt(n) / 2)))
+            g = torus(L, 1, 100, seed=10_000 + k)
+            items.append(BatchItem(g, fos, pop, 1 + k, True))
+        else:
+            d = 4 if (k // 2) % 2 == 0 else 8
+            g = configuration_model(n + (n * d) % 2, d, seed=10_000 + k, weights="uniform",
+                                    w_lo=1, w_hi=100)
+            items.append(BatchItem(g, fos, pop, 1 + k, False))
+    return items
