@@ -141,8 +141,8 @@ int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop, size_t *by
  * The instance data are copied into the arena; g and f may be freed afterwards.  The initial
  * population (uniform random genes), its fitness and the elitist are computed on the device.
  * Returns after the device work of the initialisation has completed.
- * Errors: GOM_E_ARG, GOM_E_RANGE, GOM_E_STATE (f not coloured), GOM_E_NOMEM (arena too small
- * or misaligned), GOM_E_DEVICE.
+ * Errors: GOM_E_ARG, GOM_E_RANGE (pop outside 2..GOM_MAX_POP, or n >= 2^27 vertices),
+ * GOM_E_STATE (f not coloured), GOM_E_NOMEM (arena too small or misaligned), GOM_E_DEVICE.
  */
 int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
                    int neutral_rule, int class_order, void *dev_arena, size_t arena_bytes,

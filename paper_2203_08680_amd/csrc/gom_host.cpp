@@ -113,8 +113,9 @@ struct Records {
     std::vector<int2> class_rec;  // per class {first word, stride or 0}
 };
 
-constexpr int kSmallSet = 7;
-constexpr int32_t kMaxVertexSmall = 1 << 28;
+constexpr int kSmallSet = 14;         // members held in a small record's header
+constexpr int kSmallPosShift = 27;    // bits 27..30 of a small entry: member position
+constexpr int32_t kMaxVertexSmall = 1 << kSmallPosShift;  // vertex limit of a state
 
 int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records &R) {
     const int32_t S = f.n_sets;
@@ -161,12 +162,15 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
                     const int32_t v = g.col[r];
                     if (owner[v] == j) {
                         if (pos[v] > q)
-                            ent.push_back({small ? (int32_t)(0x80000000u | ((uint32_t)q << 28) |
+                            ent.push_back({small ? (int32_t)(0x80000000u |
+                                                             ((uint32_t)q << kSmallPosShift) |
                                                              (uint32_t)pos[v])
                                                  : ~pos[v],
                                            g.wt[r]});
                     } else {
-                        ent.push_back({small ? (int32_t)(((uint32_t)q << 28) | (uint32_t)v) : v,
+                        ent.push_back({small ? (int32_t)(((uint32_t)q << kSmallPosShift) |
+                                                         (uint32_t)v)
+                                             : v,
                                        g.wt[r]});
                     }
                 }
@@ -177,7 +181,6 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
             R.words.push_back(nd);
             if (small) {
                 for (int32_t q = 0; q < kSmallSet; ++q) R.words.push_back(q < nm ? f.vars[b + q] : -1);
-                for (int32_t q = 0; q < kSmallSet; ++q) R.words.push_back(q < nm ? ends[q] : nd);
             } else {
                 for (int q = 0; q < 14; ++q) R.words.push_back(0);
                 for (int32_t q = 0; q < nm; ++q) R.words.push_back(f.vars[b + q]);

@@ -160,19 +160,20 @@ __global__ __launch_bounds__(kFitThreads) void k_full_fitness(const uint64_t *P,
 // at word roff[s] on a 16-byte boundary):
 //   univariate FOS:  [u, nd, 0, 0] then nd entries {v, w}: the neighbours of the set's
 //                    variable u and the edge weights
-//   small set (nm <= 7 variables): [nm, nd, u_0..u_6, end_0..end_6] then nd entries {x, w};
-//                    end_k counts the entries of members 0..k (unused slots: u = -1,
-//                    end = nd); x holds the position a of the entry's own endpoint in bits
-//                    28..30, and either the outside neighbour v (bit 31 clear) or, for an
-//                    edge inside the set (listed once, under its lower position), the other
-//                    endpoint's position b (bit 31 set) in bits 0..27
+//   small set (nm <= 14 variables, n < 2^27): [nm, nd, u_0..u_13] then nd entries {x, w}
+//                    (unused member slots hold -1); x holds the position a of the entry's
+//                    own endpoint in bits 27..30, and either the outside neighbour v (bit 31
+//                    clear) or, for an edge inside the set (listed once, under its lower
+//                    position), the other endpoint's position b (bit 31 set) in bits 0..26
 //   large set:       [nm, nd, 0 x 14] then u_0..u_{nm-1}, end_0..end_{nm-1}, then from the
 //                    next 16-byte boundary nd entries {x, w} with x = v (outside) or ~b
 //                    (inside, b > a)
 // The partial evaluation of Section 2.2 / Algorithm 4 reads exactly these entries: the
 // subfunctions (edges) that depend on a variable of the set.
 // ------------------------------------------------------------------------------------------
-constexpr int kSmallSet = 7;
+constexpr int kSmallSet = 14;
+constexpr int kSmallPosShift = 27;
+constexpr uint32_t kSmallIdx = (1u << kSmallPosShift) - 1u;
 constexpr int kBatch = 8;  // entries fetched together
 
 struct PairOut {
@@ -270,10 +271,18 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
         if (nm <= kSmallSet) {
             const int4 h1 = hd.h1, h2 = hd.h2, h3 = hd.h3;
             const int2 *E = reinterpret_cast<const int2 *>(R + 16);
-            const int2 *en0 = hd.en0, *en1 = hd.en1;
-            const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x};
-            const int end[kSmallSet] = {h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
-            (void)end;
+            const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
+                                        h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
+            // the O bits at the first two entry batches' far ends, loaded up front with the
+            // members' words.  Prefetched words past nd belong to the next record, so those
+            // entries read vertex 0 instead; an inside entry's b is below nm <= n, so every
+            // index is a vertex and the loads need no branch
+            uint32_t ov0[kBatch], ov1[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                ov0[t] = bits((int)((uint32_t)(t < nd ? hd.en0[t].x : 0) & kSmallIdx));
+                ov1[t] = bits((int)((uint32_t)(kBatch + t < nd ? hd.en1[t].x : 0) & kSmallIdx));
+            }
             uint64_t pw[kSmallSet];
             uint32_t om = 0;
             uint64_t D = 0;
@@ -294,29 +303,34 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
 #pragma unroll
             for (int k = 0; k < kSmallSet; ++k)
                 if (k < nm) cm |= (bit_of(pw[k], d) ^ ((om >> k) & 1u)) << k;
+            // change of one dependent edge: x holds the member position a of its own end,
+            // and the outside vertex v (bit 31 clear) or the inside end's position b
+            auto edge = [&](int e, int2 en, uint32_t ovx) -> int64_t {
+                const int x = e < nd ? en.x : (int)0x80000000;  // past nd: a = b = 0, no flip
+                const uint32_t a = ((uint32_t)x >> kSmallPosShift) & 15u;
+                const uint32_t y = (uint32_t)x & kSmallIdx;
+                const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
+                const bool inside = x < 0;
+                const uint32_t ov = inside ? (om >> y) & 1u : ovx;
+                const uint32_t flip = inside ? ca ^ ((cm >> y) & 1u) : ca;
+                return flip ? signed_w(oa == ov, en.y) : 0;
+            };
             int64_t delta = 0;
-            for (int e0 = 0; e0 < nd; e0 += kBatch) {
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                delta += edge(t, hd.en0[t], ov0[t]);
+                delta += edge(kBatch + t, hd.en1[t], ov1[t]);
+            }
+            for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
                 int2 en[kBatch];
+                uint32_t ov[kBatch];
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) en[t] = E[e0 + t];
 #pragma unroll
                 for (int t = 0; t < kBatch; ++t)
-                    en[t] = e0 == 0 ? en0[t] : (e0 == kBatch ? en1[t] : E[e0 + t]);
+                    ov[t] = bits((int)((uint32_t)(e0 + t < nd ? en[t].x : 0) & kSmallIdx));
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) {
-                    // an entry past nd becomes an inside edge of member 0 with itself: no flip
-                    const int x = (e0 + t < nd) ? en[t].x : (int)0x80000000;
-                    const uint32_t a = ((uint32_t)x >> 28) & 7u;
-                    const uint32_t y = (uint32_t)x & 0x0FFFFFFFu;
-                    const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
-                    uint32_t ov, flip;
-                    if (x >= 0) {
-                        ov = bits((int)y);
-                        flip = ca;
-                    } else {
-                        ov = (om >> y) & 1u;
-                        flip = ca ^ ((cm >> y) & 1u);
-                    }
-                    delta += flip ? signed_w(oa == ov, en[t].y) : 0;
-                }
+                for (int t = 0; t < kBatch; ++t) delta += edge(e0 + t, en[t], ov[t]);
             }
             out.delta = delta;
             out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));

@@ -88,6 +88,8 @@ RAGGED = [
     (1024, 4, 0, 64, 0, 0),
     (513, 12, 1, 64, 0, 0),
     (640, 2, 1, 31, 0, 0),
+    (301, 13, 1, 20, 0, 0),   # 14-member sets: the largest inline-member record
+    (300, 16, 1, 40, 1, 0),   # 17-member sets: the general record layout
 ]
 
 
@@ -121,6 +123,24 @@ def test_explicit_overlapping_sets(cuda, sched):
     vars_ = np.concatenate([np.asarray(s, np.int32) for s in sets])
     _, st, ref = make_pair(g, None, 24, seed=3, sets=(ptr, vars_), sched=sched)
     lockstep(st, ref, 10, "explicit sets")
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_explicit_large_sets(cuda, sched):
+    """Overlapping sets of 12 to 40 members (either side of the inline-member record limit)
+    beside the univariate sets."""
+    print(f"case explicit large sets sched={sched}", flush=True)
+    g = workloads.configuration_model(600, 5, seed=12, weights="signed50")
+    rng = np.random.default_rng(6)
+    sets = [[v] for v in range(g.n)]
+    for _ in range(60):
+        size = int(rng.integers(12, 41))
+        sets.append(sorted(rng.choice(g.n, size=size, replace=False).tolist()))
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(s) for s in sets])
+    vars_ = np.concatenate([np.asarray(s, np.int32) for s in sets])
+    _, st, ref = make_pair(g, None, 45, seed=4, sets=(ptr, vars_), sched=sched)
+    lockstep(st, ref, 8, "explicit large sets")
 
 
 @pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
