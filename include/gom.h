@@ -223,9 +223,10 @@ int gom_state_write(gom_state *s, void *stream, const uint8_t *genes, const uint
                     int64_t elite_fitness, int32_t generation, const int64_t *counters);
 
 /*
- * Kernel timing: with period k > 0, a pair of HIP events brackets every k-th sweep launch (the
- * colour-class sweeps, or the resident generation sweep) on the launch stream; k = 0 turns
- * timing off.  Sampling keeps the events' own cost out of most launches.  gom_timing_read
+ * Kernel timing: with period k > 0, every k-th sweep launch (the colour-class sweeps, or the
+ * resident generation sweep) records a pair of HIP events with its own dispatch
+ * (hipExtLaunchKernelGGL), so the elapsed time is the kernel's execution from its start to
+ * its end on the device; k = 0 turns timing off.  gom_timing_read
  * waits for the recorded events, returns the summed elapsed milliseconds and the number of
  * timed launches since the last read, and resets them.
  */

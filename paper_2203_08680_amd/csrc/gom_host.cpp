@@ -245,6 +245,8 @@ struct gom_state {
     int32_t *d_cptr = nullptr;
     int sched = GOM_SCHED_CLASS_LAUNCH;  // schedule in use
     bool resident_ok = false;            // resident schedule fits instance and device
+    bool resident_plds = false;          // ... with a copy of P in LDS as well
+    size_t lds_max = 0;                  // LDS bytes a block may use on the device
     bool bitsliced_ok = false;           // bit-sliced schedule fits the instance
     bool partition = false;              // every variable in exactly one set
     int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
@@ -260,7 +262,6 @@ struct gom_state {
     int max_grid = 2048;
     int timing = 0;                     // sample period of the sweep-launch events (0 = off)
     int64_t sweep_launches = 0;         // sweep launches enqueued (for the sampling)
-    bool timing_open = false;           // a begin event is recorded, its end is due
     std::vector<hipEvent_t> tev;        // begin/end pairs
     size_t tev_used = 0;
     double t_ms = 0.0;
@@ -569,16 +570,13 @@ static std::vector<int32_t> class_order(const gom_state *s, int32_t gen) {
     return perm;
 }
 
-static int timing_record(gom_state *s, hipStream_t st, bool begin) {
+// Sampled kernel timing: every `timing`-th sweep launch gets a pair of events that the launch
+// records with its own dispatch.
+static int timing_events(gom_state *s, KernelEvents *ev) {
+    *ev = KernelEvents{};
     if (!s->timing) return GOM_OK;
-    if (begin) {
-        if (s->sweep_launches++ % s->timing != 0) return GOM_OK;
-        s->timing_open = true;
-    } else {
-        if (!s->timing_open) return GOM_OK;
-        s->timing_open = false;
-    }
-    if (begin && s->tev_used + 2 > s->tev.size()) {
+    if (s->sweep_launches++ % s->timing != 0) return GOM_OK;
+    if (s->tev_used + 2 > s->tev.size()) {
         if (s->tev.size() < (size_t)(1 << 15)) {
             const size_t grow = s->tev.size() ? s->tev.size() : 256;
             for (size_t q = 0; q < grow; ++q) {
@@ -598,7 +596,8 @@ static int timing_record(gom_state *s, hipStream_t st, bool begin) {
             s->tev_used = 0;
         }
     }
-    HIP_TRY(hipEventRecord(s->tev[s->tev_used++], st));
+    ev->start = s->tev[s->tev_used++];
+    ev->stop = s->tev[s->tev_used++];
     return GOM_OK;
 }
 
@@ -682,14 +681,13 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         a.rbase = s->class_rec[c].x;
         a.rstride = s->class_rec[c].y;
         a.csize = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
-        int rc = timing_record(s, st, true);
+        KernelEvents ev;
+        int rc = timing_events(s, &ev);
         if (rc) return rc;
         if (s->sched == GOM_SCHED_BITSLICED)
-            HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st));
+            HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st, ev));
         else
-            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st));
-        rc = timing_record(s, st, false);
-        if (rc) return rc;
+            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st, ev));
     }
     return GOM_OK;
 }
@@ -709,11 +707,10 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         r.c = resident_ctx(s, target);
         r.c.gen = gen;
         for (int32_t t = 0; t < s->k; ++t) r.order[t] = (uint16_t)perm[t];
-        int rc = timing_record(s, st, true);
+        KernelEvents ev;
+        int rc = timing_events(s, &ev);
         if (rc) return rc;
-        HIP_TRY(launch_resident_sweep(r, s->univariate ? 0 : 1, st));
-        rc = timing_record(s, st, false);
-        if (rc) return rc;
+        HIP_TRY(launch_resident_sweep(r, s->univariate ? 0 : 1, s->resident_plds, st, ev));
         return enqueue_epilogue(s, target, st, true);
     }
     int rc = enqueue_class_range(s, perm, gen, 0, s->k, target, st);
@@ -828,8 +825,10 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
         e = hipGetDevice(&dev);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        s->lds_max = (size_t)lds_max;
         s->resident_ok = e == hipSuccess && s->k <= kResidentMaxClasses &&
-                         resident_lds_bytes(s->n) <= (size_t)lds_max;
+                         resident_lds_bytes(s->n, false) <= s->lds_max;
+        s->resident_plds = s->resident_ok && resident_lds_bytes(s->n, true) <= s->lds_max;
         int64_t max_abs = 0;
         for (int32_t v = 0; v < g->n; ++v) {
             int64_t t = 0;
@@ -1112,7 +1111,6 @@ extern "C" int gom_timing_enable(gom_state *s, int period) {
     if (period < 0) return fail(GOM_E_ARG, "gom_timing_enable: negative period");
     s->timing = period;
     s->sweep_launches = 0;
-    s->timing_open = false;
     return GOM_OK;
 }
 
@@ -1154,7 +1152,7 @@ extern "C" int gom_state_set_schedule(gom_state *s, int schedule) {
         if (!s->resident_ok)
             return fail(GOM_E_RANGE, "gom_state_set_schedule: resident schedule needs %zu bytes "
                         "of LDS and at most %d classes (instance: %d classes)",
-                        resident_lds_bytes(s->n), kResidentMaxClasses, s->k);
+                        resident_lds_bytes(s->n, false), kResidentMaxClasses, s->k);
         s->sched = schedule;
         return GOM_OK;
     default:
@@ -1248,7 +1246,8 @@ struct gom_batch {
     int2 *d_blk = nullptr;
     int32_t *d_vblk = nullptr;
     DevState *d_snap = nullptr;         // packed copy of the instances' run scalars
-    int sweep_blocks = 0, vblocks = 0, lds_n = 0;
+    int sweep_blocks = 0, vblocks = 0;
+    size_t lds = 0;                     // dynamic LDS bytes of a sweep block
     DevState *h_st = nullptr;           // pinned, 2 x count
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     double wall_khz = 0.0;
@@ -1349,10 +1348,13 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
                             arena + B.sub_off[(size_t)b], B.sub_bytes[(size_t)b], stream, &s);
         if (rc) return cleanup(rc);
         bt->subs.push_back(s);
-        if (!s->resident_ok)
+        const size_t need = kBatchOrderBytes + resident_lds_bytes(s->n, false);
+        if (!s->resident_ok || need > s->lds_max)
             return cleanup(fail(GOM_E_RANGE, "gom_batch_init: instance %d does not fit the "
                                 "resident schedule (n = %d, %d classes)", b, s->n, s->k));
+        const bool plds = kBatchOrderBytes + resident_lds_bytes(s->n, true) <= s->lds_max;
         BatchInst &I = insts[(size_t)b];
+        I.plds = plds ? 1 : 0;
         I.res = resident_ctx(s, targets[b]);
         I.epi = epilogue_args(s, targets[b], true);
         I.kind = s->univariate ? 0 : 1;
@@ -1360,7 +1362,7 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
         I.vblock0 = (int32_t)vblk.size();
         for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2(b, i));
         for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back(b);
-        bt->lds_n = std::max(bt->lds_n, s->n);
+        bt->lds = std::max(bt->lds, kBatchOrderBytes + resident_lds_bytes(s->n, plds));
     }
     bt->d_insts = (BatchInst *)(arena + B.insts);
     bt->d_blk = (int2 *)(arena + B.blk);
@@ -1434,7 +1436,7 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
             if (n > 0) {
                 for (int32_t t = 0; t < n; ++t)
                     HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk, b->sweep_blocks,
-                                              b->d_vblk, b->vblocks, b->lds_n, st));
+                                              b->d_vblk, b->vblocks, b->lds, st));
                 issued += n;
                 cur = slot;
                 HIP_TRY(batch_snapshot(b, cur, st));

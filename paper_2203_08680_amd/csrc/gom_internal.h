@@ -164,11 +164,17 @@ struct BatchInst {
     int32_t kind;           // 0 univariate records, 1 general
     int32_t order_fixed;    // class order ascending instead of shuffled
     int32_t vblock0;        // first vertex-pass block of the instance
-    int32_t pad;
+    int32_t plds;           // the sweep keeps a copy of P in LDS
 };
 
 // Dynamic LDS of the batched sweep before the resident part: class order and draws.
 constexpr int kBatchOrderBytes = 4 * kResidentMaxClasses;
+
+// Optional pair of events that a launch records with its own dispatch (start and end of the
+// kernel's execution, as the profiler sees it); both null for a plain launch.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
@@ -178,16 +184,19 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
                                const int32_t *ew, int64_t m, int N, Stripe *stripes,
                                hipStream_t s);
 // kind: 0 = univariate records, 1 = general records
-hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s);
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s,
+                              KernelEvents ev = {});
 // Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
-                                 hipStream_t s);
-hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s);
+                                 hipStream_t s, KernelEvents ev = {});
+// plds: keep a copy of P in LDS (needs resident_lds_bytes(n, true) of LDS).
+hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hipStream_t s,
+                                 KernelEvents ev = {});
 // Batched generation step over `count` instances: sweep grid = sum of populations (blk[b] =
-// {instance, solution}), vertex-pass grid = vblocks (vblk[b] = instance); lds_n = the largest
-// instance's vertex count.
+// {instance, solution}), vertex-pass grid = vblocks (vblk[b] = instance); lds = dynamic LDS
+// bytes of a sweep block (kBatchOrderBytes + the largest instance's resident bytes).
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, int lds_n, hipStream_t s);
+                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s);
 hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s);
 // Pack every instance's DevState into out[count].
 hipError_t launch_batch_gather(const BatchInst *insts, int count, DevState *out, hipStream_t s);
@@ -197,6 +206,7 @@ hipError_t launch_state_hash(const uint64_t *X, const uint64_t *E, int n, int N,
                              DevState *st, hipStream_t s);
 // Generation end: finalize (one block) then the vertex pass.
 hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
-size_t resident_lds_bytes(int n);
+// Dynamic LDS bytes of the resident sweep for n vertices, with or without the P copy.
+size_t resident_lds_bytes(int n, bool plds);
 
 }  // namespace gom

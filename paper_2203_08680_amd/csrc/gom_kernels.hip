@@ -17,6 +17,8 @@
 //     classes), offspring written back as one bit row per solution;
 // then k_finalize (one block) and k_vertex_pass (P <- O, elitist, equality flags).  Integer
 // arithmetic only, so every result is exact and independent of the order in which waves run.
+#include <hip/hip_ext.h>
+
 #include "gom_internal.h"
 
 namespace gom {
@@ -210,38 +212,46 @@ struct Head {
     int2 en0[kBatch], en1[kBatch];
 };
 
-template <int KIND>
-__device__ __forceinline__ Head load_head(const int32_t *R) {
+// Record reader: a record's words are consecutive, read with vector loads.
+struct AosRec {
+    const int32_t *R;
+    __device__ __forceinline__ int32_t w(int k) const { return R[k]; }
+    __device__ __forceinline__ int4 q(int k) const {
+        return reinterpret_cast<const int4 *>(R)[k];
+    }
+    __device__ __forceinline__ int2 e(int base, int t) const {
+        return reinterpret_cast<const int2 *>(R + base)[t];
+    }
+};
+
+template <int KIND, class Rec>
+__device__ __forceinline__ Head load_head(const Rec &R) {
     Head hd;
-    const int4 *R4 = reinterpret_cast<const int4 *>(R);
-    hd.h0 = R4[0];
+    hd.h0 = R.q(0);
     if constexpr (KIND == 0) {
-        const int2 *E = reinterpret_cast<const int2 *>(R + 4);
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) hd.en0[t] = E[t];
+        for (int t = 0; t < kBatch; ++t) hd.en0[t] = R.e(4, t);
     } else {
-        hd.h1 = R4[1];
-        hd.h2 = R4[2];
-        hd.h3 = R4[3];
-        const int2 *E = reinterpret_cast<const int2 *>(R + 16);
+        hd.h1 = R.q(1);
+        hd.h2 = R.q(2);
+        hd.h3 = R.q(3);
 #pragma unroll
         for (int t = 0; t < kBatch; ++t) {
-            hd.en0[t] = E[t];
-            hd.en1[t] = E[kBatch + t];
+            hd.en0[t] = R.e(16, t);
+            hd.en1[t] = R.e(16, kBatch + t);
         }
     }
     return hd;
 }
 
-template <int KIND, class Bits, class Commit>
-__device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, const uint64_t *P,
+template <int KIND, class Rec, class Bits, class Commit>
+__device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const uint64_t *P,
                                             Bits bits, Commit commit, uint64_t cand, uint32_t h,
                                             bool neutral_ok) {
     PairOut out{0u, false, 0};
     const int4 h0 = hd.h0;
     if constexpr (KIND == 0) {
         // one variable u: the donor always differs at u, so C = {u} whenever a donor exists
-        const int2 *E = reinterpret_cast<const int2 *>(R + 4);
         int2 en[kBatch];
 #pragma unroll
         for (int t = 0; t < kBatch; ++t) en[t] = hd.en0[t];
@@ -253,7 +263,7 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
         for (int e0 = 0; e0 < nd; e0 += kBatch) {
             if (e0 > 0) {
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) en[t] = E[e0 + t];
+                for (int t = 0; t < kBatch; ++t) en[t] = R.e(4, e0 + t);
             }
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
@@ -270,7 +280,6 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
         const int nm = h0.x, nd = h0.y;
         if (nm <= kSmallSet) {
             const int4 h1 = hd.h1, h2 = hd.h2, h3 = hd.h3;
-            const int2 *E = reinterpret_cast<const int2 *>(R + 16);
             const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
                                         h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
             // the O bits at the first two entry batches' far ends, loaded up front with the
@@ -325,7 +334,7 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
                 int2 en[kBatch];
                 uint32_t ov[kBatch];
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) en[t] = E[e0 + t];
+                for (int t = 0; t < kBatch; ++t) en[t] = R.e(16, e0 + t);
 #pragma unroll
                 for (int t = 0; t < kBatch; ++t)
                     ov[t] = bits((int)((uint32_t)(e0 + t < nd ? en[t].x : 0) & kSmallIdx));
@@ -339,12 +348,12 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
                 if (k < nm) commit(mem[k], out.acc && ((cm >> k) & 1u));
             return out;
         } else {
-            const int32_t *mem = R + 16;
-            const int32_t *end = R + 16 + nm;
-            const int2 *E = reinterpret_cast<const int2 *>(R + ((16 + 2 * nm + 3) & ~3));
+            // members at words 16.., their entry ends at 16 + nm.., entries from the next
+            // 4-word boundary
+            const int eb = (16 + 2 * nm + 3) & ~3;
             uint64_t D = 0;
             for (int k = 0; k < nm; ++k) {
-                const int u = mem[k];
+                const int u = R.w(16 + k);
                 D |= P[u] ^ (0ull - (uint64_t)bits(u));
             }
             D &= cand;
@@ -353,17 +362,17 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
             int64_t delta = 0;
             int e = 0;
             for (int k = 0; k < nm; ++k) {
-                const int u = mem[k];
+                const int u = R.w(16 + k);
                 const uint32_t ou = bits(u);
                 const uint32_t cu = bit_of(P[u], d) ^ ou;
-                for (const int e1 = end[k]; e < e1; ++e) {
-                    const int2 en = E[e];
+                for (const int e1 = R.w(16 + nm + k); e < e1; ++e) {
+                    const int2 en = R.e(eb, e);
                     uint32_t ov, flip;
                     if (en.x >= 0) {
                         ov = bits(en.x);
                         flip = cu;
                     } else {
-                        const int vb = mem[~en.x];
+                        const int vb = R.w(16 + ~en.x);
                         ov = bits(vb);
                         flip = cu ^ (bit_of(P[vb], d) ^ ov);
                     }
@@ -373,7 +382,7 @@ __device__ __forceinline__ PairOut gom_pair(const int32_t *R, const Head &hd, co
             out.delta = delta;
             out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
             for (int k = 0; k < nm; ++k) {
-                const int u = mem[k];
+                const int u = R.w(16 + k);
                 const uint32_t cu = bit_of(P[u], d) ^ bits(u);
                 commit(u, out.acc && cu);
             }
@@ -427,13 +436,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     const int gw = blockIdx.x * (kSweepThreads / 64) + (int)(threadIdx.x >> 6);  // global wave
     const int nwaves = gridDim.x * (kSweepThreads / 64);
     auto record = [&](int p) {
-        return a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p];
+        return AosRec{a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p]};
     };
     // issue the first record's loads together with the run-state loads
     const uint64_t mism = a.stripes[lane].mism;
     const int64_t elite_fitness = a.st->elite_fitness;
     int p = gw * GPW + grp;
-    const int32_t *R = record(p < a.csize ? p : 0);
+    AosRec R = record(p < a.csize ? p : 0);
     Head hd = load_head<KIND>(R);
     if (elite_fitness >= a.target) return;
     const bool act = (int)i < a.N;
@@ -618,6 +627,11 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
 constexpr int kResRngBytes = kResidentChunkSlots * 16;
 constexpr int kResRedBytes = 256;
 
+// LDS bytes of the P copy (16-byte multiple).
+__host__ __device__ __forceinline__ size_t resident_words_bytes(int n) {
+    return ((size_t)n * 8 + 15) & ~(size_t)15;
+}
+
 struct LdsCommit {
     uint8_t *ob;
     __device__ __forceinline__ void operator()(int u, bool flip) const {
@@ -625,7 +639,9 @@ struct LdsCommit {
     }
 };
 
-template <int KIND>
+// PLDS: the block also copies the population words P into LDS (8 bytes per vertex), so the
+// donors' genes are read from LDS instead of global memory.
+template <int KIND, bool PLDS>
 __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16_t *order,
                                               int gen, int i, uint8_t *lds) {
     const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
@@ -633,14 +649,20 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
     uint32_t(*rng)[4] = reinterpret_cast<uint32_t(*)[4]>(lds);
     int64_t *redf = reinterpret_cast<int64_t *>(lds + kResRngBytes);
     uint32_t *redc = reinterpret_cast<uint32_t *>(lds + kResRngBytes + 128);
-    uint8_t *ob = lds + kResRngBytes + kResRedBytes;
+    uint64_t *pl = reinterpret_cast<uint64_t *>(lds + kResRngBytes + kResRedBytes);
+    uint8_t *ob = lds + kResRngBytes + kResRedBytes + (PLDS ? resident_words_bytes(a.n) : 0);
+    const uint64_t *P = PLDS ? pl : a.P;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t cand = popm & ~(1ull << i);
     const bool neutral_ok = a.always || bit_of(wave_or64(mism), (uint32_t)i);
 
-    for (int v = tid; v < a.n; v += kResidentThreads) ob[v] = (uint8_t)bit_of(a.P[v], (uint32_t)i);
+    for (int v = tid; v < a.n; v += kResidentThreads) {
+        const uint64_t w = a.P[v];
+        if constexpr (PLDS) pl[v] = w;
+        ob[v] = (uint8_t)bit_of(w, (uint32_t)i);
+    }
     __syncthreads();
 
     const LdsBits bits{ob};
@@ -653,12 +675,12 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
         const int csize = a.class_ptr[c + 1] - cbase;
         const int2 cr = a.class_rec[c];  // {first record word, record stride or 0}
         auto record = [&](int p) {
-            return cr.y ? a.recs + cr.x + p * cr.y : a.recs + a.roff[cbase + p];
+            return AosRec{cr.y ? a.recs + cr.x + p * cr.y : a.recs + a.roff[cbase + p]};
         };
         for (int base = 0; base < csize; base += 8 * kResidentChunkSlots) {
             const int span = min(csize - base, 8 * kResidentChunkSlots);
             // issue this thread's first record of the round before the draws and the barrier
-            const int32_t *R = record(base + (tid < span ? tid : 0));
+            AosRec R = record(base + (tid < span ? tid : 0));
             Head hd = load_head<KIND>(R);
             if constexpr (KIND != 0) {
                 if (tid < ((span + 7) >> 3)) {
@@ -681,7 +703,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
                     R = record(base + q);
                     hd = load_head<KIND>(R);
                 }
-                const PairOut r = gom_pair<KIND>(R, hd, a.P, bits, commit, cand, h, neutral_ok);
+                const PairOut r = gom_pair<KIND>(R, hd, P, bits, commit, cand, h, neutral_ok);
                 facc += r.acc ? r.delta : 0;
                 n_eval += r.cnt > 0;
                 n_acc += r.acc;
@@ -718,10 +740,10 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
     }
 }
 
-template <int KIND>
+template <int KIND, bool PLDS>
 __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    resident_body<KIND>(a.c, a.order, a.c.gen, blockIdx.x, lds);
+    resident_body<KIND, PLDS>(a.c, a.order, a.c.gen, blockIdx.x, lds);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -875,10 +897,18 @@ __global__ __launch_bounds__(kResidentThreads) void k_batch_sweep(const BatchIns
             order[draw[t]] = x;
         }
     __syncthreads();
-    if (I->kind == 0)
-        resident_body<0>(a, order, gen, bi.y, lds_all + kBatchOrderBytes);
-    else
-        resident_body<1>(a, order, gen, bi.y, lds_all + kBatchOrderBytes);
+    uint8_t *lds = lds_all + kBatchOrderBytes;
+    if (I->kind == 0) {
+        if (I->plds)
+            resident_body<0, true>(a, order, gen, bi.y, lds);
+        else
+            resident_body<0, false>(a, order, gen, bi.y, lds);
+    } else {
+        if (I->plds)
+            resident_body<1, true>(a, order, gen, bi.y, lds);
+        else
+            resident_body<1, false>(a, order, gen, bi.y, lds);
+    }
 }
 
 __global__ __launch_bounds__(64) void k_batch_finalize(const BatchInst *insts) {
@@ -968,7 +998,19 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
     return hipGetLastError();
 }
 
-hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s) {
+// Launch through hipExtLaunchKernelGGL when events are given: they take the dispatch's own
+// start and end timestamps.
+template <class K, class... Args>
+static void launch_timed(K kernel, dim3 gd, dim3 bd, size_t lds, hipStream_t s, KernelEvents ev,
+                         Args... args) {
+    if (ev.start)
+        hipExtLaunchKernelGGL(kernel, gd, bd, (uint32_t)lds, s, ev.start, ev.stop, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, gd, bd, lds, s, args...);
+}
+
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s,
+                              KernelEvents ev) {
     const int G = a.N <= 16 ? 16 : (a.N <= 32 ? 32 : 64);
     const int per_tile = (kSweepThreads / 64) * (64 / G);  // sets per block
     int grid = (a.csize + per_tile - 1) / per_tile;
@@ -976,55 +1018,59 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStr
     if (grid < 1) return hipSuccess;
     const dim3 gd(grid), bd(kSweepThreads);
     if (kind == 0) {
-        if (G == 16) hipLaunchKernelGGL((k_class_sweep<16, 0>), gd, bd, 0, s, a);
-        else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, 0>), gd, bd, 0, s, a);
-        else hipLaunchKernelGGL((k_class_sweep<64, 0>), gd, bd, 0, s, a);
+        if (G == 16) launch_timed(k_class_sweep<16, 0>, gd, bd, 0, s, ev, a);
+        else if (G == 32) launch_timed(k_class_sweep<32, 0>, gd, bd, 0, s, ev, a);
+        else launch_timed(k_class_sweep<64, 0>, gd, bd, 0, s, ev, a);
     } else {
-        if (G == 16) hipLaunchKernelGGL((k_class_sweep<16, 1>), gd, bd, 0, s, a);
-        else if (G == 32) hipLaunchKernelGGL((k_class_sweep<32, 1>), gd, bd, 0, s, a);
-        else hipLaunchKernelGGL((k_class_sweep<64, 1>), gd, bd, 0, s, a);
+        if (G == 16) launch_timed(k_class_sweep<16, 1>, gd, bd, 0, s, ev, a);
+        else if (G == 32) launch_timed(k_class_sweep<32, 1>, gd, bd, 0, s, ev, a);
+        else launch_timed(k_class_sweep<64, 1>, gd, bd, 0, s, ev, a);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
-                                 hipStream_t s) {
+                                 hipStream_t s, KernelEvents ev) {
     int grid = (a.csize + kSwarThreads - 1) / kSwarThreads;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
     if (partition)
-        hipLaunchKernelGGL((k_uni_swar_sweep<true>), dim3(grid), dim3(kSwarThreads), 0, s, a);
+        launch_timed(k_uni_swar_sweep<true>, dim3(grid), dim3(kSwarThreads), 0, s, ev, a);
     else
-        hipLaunchKernelGGL((k_uni_swar_sweep<false>), dim3(grid), dim3(kSwarThreads), 0, s, a);
+        launch_timed(k_uni_swar_sweep<false>, dim3(grid), dim3(kSwarThreads), 0, s, ev, a);
     return hipGetLastError();
 }
 
-size_t resident_lds_bytes(int n) {
-    return (size_t)kResRngBytes + kResRedBytes + (((size_t)n + 15) & ~(size_t)15);
+size_t resident_lds_bytes(int n, bool plds) {
+    return (size_t)kResRngBytes + kResRedBytes + (plds ? resident_words_bytes(n) : 0) +
+           (((size_t)n + 15) & ~(size_t)15);
 }
 
-hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, hipStream_t s) {
-    const size_t lds = resident_lds_bytes(a.c.n);
+template <int KIND, bool PLDS>
+static hipError_t launch_resident_t(const ResidentArgs &a, hipStream_t s, KernelEvents ev) {
+    const size_t lds = resident_lds_bytes(a.c.n, PLDS);
     // Raise the dynamic LDS limit of the kernel to what this launch needs (once per size).
-    static size_t attr_bytes[2] = {0, 0};
-    const void *fn = kind == 0 ? (const void *)k_resident_sweep<0>
-                               : (const void *)k_resident_sweep<1>;
-    if (lds > attr_bytes[kind]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+    static size_t attr_bytes = 0;
+    if (lds > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_resident_sweep<KIND, PLDS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        attr_bytes[kind] = lds;
+        attr_bytes = lds;
     }
-    if (kind == 0)
-        hipLaunchKernelGGL((k_resident_sweep<0>), dim3(a.c.N), dim3(kResidentThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_resident_sweep<1>), dim3(a.c.N), dim3(kResidentThreads), lds, s, a);
+    launch_timed(k_resident_sweep<KIND, PLDS>, dim3(a.c.N), dim3(kResidentThreads), lds, s, ev,
+                 a);
     return hipGetLastError();
+}
+
+hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hipStream_t s,
+                                 KernelEvents ev) {
+    if (kind == 0)
+        return plds ? launch_resident_t<0, true>(a, s, ev) : launch_resident_t<0, false>(a, s, ev);
+    return plds ? launch_resident_t<1, true>(a, s, ev) : launch_resident_t<1, false>(a, s, ev);
 }
 
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, int lds_n, hipStream_t s) {
-    const size_t lds = (size_t)kBatchOrderBytes + resident_lds_bytes(lds_n);
+                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s) {
     static size_t attr_bytes = 0;
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k_batch_sweep,
