@@ -45,12 +45,15 @@ WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_50
 # roofline.traffic only while the sources still hash the same; the summaries and commands are
 # in profiles/.
 MEASURED_TRAFFIC = {
-    ("k_resident_sweep", "torus100_nbhd_p64"): {
-        "bytes": 16226343, "source": "d34832e2e496c372",
-        "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
     ("k_class_sweep", "torus100_nbhd_p64"): {
-        "bytes": 900751, "source": "d34832e2e496c372",
+        "bytes": 1462885, "source": "351dd256348274e6",
         "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
+    ("k_resident_sweep", "torus100_nbhd_p64"): {
+        "bytes": 19122731, "source": "351dd256348274e6",
+        "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
+    ("k_uni_swar_sweep", "torus1000_uni_p64"): {
+        "bytes": 50502069, "source": "351dd256348274e6",
+        "profile": "profiles/k_uni_swar_sweep_torus1000_uni_p64.md"},
 }
 
 
@@ -175,7 +178,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-gens", type=int, default=20,
+    ap.add_argument("--cpu-gens", type=int, default=40,
                     help="generations of the oracle sample for the CPU baseline")
     ap.add_argument("--schedule", choices=("tuned", "auto", "class", "resident", "bitsliced"),
                     default="tuned",
@@ -193,10 +196,10 @@ def main():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB (a known "
                          "byte count for scaling profiler traffic counters)")
-    ap.add_argument("--event-period", type=int, default=17,
+    ap.add_argument("--event-period", type=int, default=0,
                     help="inside the timed region, time every k-th sweep launch with HIP "
-                         "events recorded by its own dispatch (reported beside the timing "
-                         "pass, which times every launch of one extra run)")
+                         "events recorded by its own dispatch (0: none; reported beside the "
+                         "timing pass, which times every launch of one extra run)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="do not record HIP events around sweep launches (roofline omitted)")
     args = ap.parse_args()
@@ -249,7 +252,7 @@ def main():
         log(f"warmup {w}: generations {r.generations} reached {r.reached}")
     torch.cuda.synchronize()
 
-    if not args.no_kernel_events:
+    if not args.no_kernel_events and args.event_period > 0:
         gom.gom_timing_enable(st, args.event_period)
         gom.gom_timing_read(st)
     runs = []

@@ -19,6 +19,8 @@
 // arithmetic only, so every result is exact and independent of the order in which waves run.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "gom_internal.h"
 
 namespace gom {
@@ -221,6 +223,24 @@ struct AosRec {
     }
     __device__ __forceinline__ int2 e(int base, int t) const {
         return reinterpret_cast<const int2 *>(R + base)[t];
+    }
+};
+
+// Reader for a record that every lane of the wave reads (class launch with one set per wave):
+// each loaded word is made wave-uniform, so the record's decoding runs on the scalar unit.
+struct UniformAosRec {
+    const int32_t *R;
+    __device__ __forceinline__ static int32_t u(int32_t x) {
+        return __builtin_amdgcn_readfirstlane(x);
+    }
+    __device__ __forceinline__ int32_t w(int k) const { return u(R[k]); }
+    __device__ __forceinline__ int4 q(int k) const {
+        const int4 v = reinterpret_cast<const int4 *>(R)[k];
+        return make_int4(u(v.x), u(v.y), u(v.z), u(v.w));
+    }
+    __device__ __forceinline__ int2 e(int base, int t) const {
+        const int2 v = reinterpret_cast<const int2 *>(R + base)[t];
+        return make_int2(u(v.x), u(v.y));
     }
 };
 
@@ -435,14 +455,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     const uint32_t i = (uint32_t)(lane % G);
     const int gw = blockIdx.x * (kSweepThreads / 64) + (int)(threadIdx.x >> 6);  // global wave
     const int nwaves = gridDim.x * (kSweepThreads / 64);
+    // one set per wave (G = 64): the record is wave-uniform
+    using Rec = std::conditional_t<G == 64, UniformAosRec, AosRec>;
     auto record = [&](int p) {
-        return AosRec{a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p]};
+        return Rec{a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p]};
     };
     // issue the first record's loads together with the run-state loads
     const uint64_t mism = a.stripes[lane].mism;
     const int64_t elite_fitness = a.st->elite_fitness;
     int p = gw * GPW + grp;
-    AosRec R = record(p < a.csize ? p : 0);
+    if constexpr (G == 64) p = __builtin_amdgcn_readfirstlane(p);
+    Rec R = record(p < a.csize ? p : 0);
     Head hd = load_head<KIND>(R);
     if (elite_fitness >= a.target) return;
     const bool act = (int)i < a.N;
@@ -458,6 +481,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     for (int wt = gw; wt < nwt; wt += nwaves) {
         if (wt != gw) {
             p = wt * GPW + grp;
+            if constexpr (G == 64) p = __builtin_amdgcn_readfirstlane(p);
             R = record(p < a.csize ? p : 0);
             hd = load_head<KIND>(R);
         }
