@@ -98,6 +98,22 @@ int gom_fos_build(const mc_graph *g, int kind, gom_fos **out);
 int gom_fos_from_sets(const mc_graph *g, int32_t n_sets, const int32_t *ptr,
                       const int32_t *vars, gom_fos **out);
 
+/*
+ * Fixed linkage tree (Section 4.1, the Linkage Tree built with UPGMA; with a bound, the
+ * Bounded Fixed Linkage Tree; Section 6.1 uses the graph's weights as the similarity).
+ * Similarity of two variables = |w| of the edge between them, 0 without an edge; similarity of
+ * two clusters = the average over all member pairs.  Starting from the n single variables,
+ * UPGMA repeatedly merges a pair of clusters with the largest average similarity, ties broken
+ * by the smaller combined size, then by the lower cluster ids (variables are clusters
+ * 0..n-1, merged clusters get n, n+1, ... in creation order).  bound > 0: only pairs whose
+ * union has at most `bound` variables may merge, and the tree stops when none is left;
+ * bound = 0: no limit.  The set of all n variables is never added.
+ * Sets: set v = {v} for v < n, then the merged clusters in creation order, members
+ * ascending.  Every set above the variables is the union of exactly two earlier sets.
+ * Errors: GOM_E_ARG (null, bound = 1 or negative).
+ */
+int gom_fos_build_lt(const mc_graph *g, int32_t bound, gom_fos **out);
+
 /* FOS sizes: number of sets, total members, largest set.  Outputs may be NULL. */
 int gom_fos_info(const gom_fos *f, int32_t *n_sets, int64_t *n_members, int32_t *max_set);
 

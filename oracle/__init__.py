@@ -58,6 +58,9 @@ def lib():
     L.or_get.argtypes = [C.c_void_p, C.c_void_p, _i64p, C.c_void_p, C.POINTER(C.c_int64),
                          C.POINTER(C.c_int32), _i64p]
     L.or_set.argtypes = [C.c_void_p, _u8p, _u8p, C.c_int64, C.c_int32, _i64p]
+    L.or_linkage_tree.restype = C.c_int32
+    L.or_linkage_tree.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _i32p, C.c_int32, _i32p,
+                                  _i32p]
     L.or_stop_after_class.restype = C.c_int32
     L.or_stop_after_class.argtypes = [C.c_void_p, C.c_int32]
     L.or_hash.restype = C.c_uint64
@@ -91,6 +94,17 @@ def fos(g, kind: int):
     lib().or_fos_build(g.n, g.m, g.u, g.v, kind, ptr,
                        vars_.ctypes.data_as(C.c_void_p))
     return ptr, vars_[:total]
+
+
+def linkage_tree(g, bound: int = 0):
+    """UPGMA linkage tree on |w| (bound 0 = unbounded): (set_ptr, set_vars)."""
+    n = g.n
+    ptr = np.zeros(2 * n, np.int32)
+    vars_ = np.zeros(n * n, np.int32)
+    k = lib().or_linkage_tree(n, g.m, g.u, g.v, g.w, int(bound), ptr, vars_)
+    if k < 0:
+        raise ValueError("or_linkage_tree failed")
+    return ptr[:k + 1].copy(), vars_[:ptr[k]].copy()
 
 
 def lmig_pairwise(g, set_ptr, set_vars):

@@ -28,6 +28,12 @@
  *       every step (debug flag), hand-worked two-solution examples, invariants (monotone
  *       fitness, converged fixed point, univariate donor independence, in-class order
  *       invariance).  There are no published trajectories to compare against.
+ *   or_linkage_tree    Section 4.1: the Linkage Tree by UPGMA (pairwise merges of the two
+ *       clusters with the largest average similarity), optionally bounded in set size (the
+ *       Bounded Fixed Linkage Tree); Section 6.1 takes the graph's weights as the similarity.
+ *       Dense similarity matrix, every pair rescanned at every merge.  Pinned: the tree of
+ *       Fig. 2 from weights chosen to produce it, merge-by-merge maximality against an
+ *       exact recomputation, non-increasing merge similarities, tree structure, bound.
  *   or_stop_after_class  a generation of Algorithm 3 cut after a given position of the class
  *       order (a debugging view of the offspring between two groups).  Pinned: the literal
  *       reading of Algorithms 3/4 stopped at the same group.
@@ -337,6 +343,93 @@ int32_t or_colour(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, in
     int32_t k = colour_sets(&g, nsets, set_ptr, set_vars, colour_out, degree_out);
     graph_free(&g);
     return k;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Linkage tree by UPGMA (Section 4.1).  Readings where the paper is silent:
+ *   - similarity of variables a, b = |w(a, b)|, 0 without an edge (Section 6.1 uses the
+ *     weights as the similarity; the sign of a weight does not make two variables less
+ *     dependent);
+ *   - ties between pairs with equal average similarity: smaller combined size first, then the
+ *     pair with the lower smaller cluster id, then the lower larger id; the variables are
+ *     clusters 0..n-1 and each merge creates the next id;
+ *   - bounded: only pairs whose union has at most `bound` variables are candidates; the tree
+ *     stops when no candidate is left (pairs of average 0 are candidates too);
+ *   - the union of all variables is not a set of the tree.
+ * Output: sets 0..n-1 are the variables, then one set per merge in merge order, members
+ * ascending.  Returns the number of sets, or -1 on bad input or allocation failure.
+ * set_ptr needs 2n entries, set_vars n*n (enough for any tree).
+ * ---------------------------------------------------------------------------------------- */
+int32_t or_linkage_tree(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                        const int32_t *ew, int32_t bound, int32_t *set_ptr,
+                        int32_t *set_vars) {
+    if (n < 1 || bound < 0 || bound == 1) return -1;
+    const int64_t cap = bound ? bound : n;
+    int64_t *S = calloc((size_t)n * (size_t)n, sizeof(int64_t));
+    int32_t *cid = malloc(sizeof(int32_t) * (size_t)n);  /* cluster id of each variable */
+    int32_t *size = malloc(sizeof(int32_t) * (size_t)(2 * n));
+    char *alive = calloc((size_t)(2 * n), 1);
+    if (!S || !cid || !size || !alive) {
+        free(S); free(cid); free(size); free(alive);
+        return -1;
+    }
+    for (int64_t e = 0; e < m; ++e) {
+        int64_t w = ew[e] < 0 ? -(int64_t)ew[e] : (int64_t)ew[e];
+        S[(size_t)eu[e] * n + ev[e]] += w;
+        S[(size_t)ev[e] * n + eu[e]] += w;
+    }
+    set_ptr[0] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        cid[v] = v;
+        size[v] = 1;
+        alive[v] = 1;
+        set_vars[v] = v;
+        set_ptr[v + 1] = v + 1;
+    }
+    int32_t next = n;
+    for (;;) {
+        /* best allowed pair (i < j): largest W / (|i| |j|), then smallest size sum, then the
+           smallest (i, j) */
+        int32_t bi = -1, bj = -1;
+        int64_t bW = 0, bsz = 1, bsum = 0;
+        for (int32_t i = 0; i < next; ++i) {
+            if (!alive[i]) continue;
+            for (int32_t j = i + 1; j < next; ++j) {
+                if (!alive[j]) continue;
+                int64_t sum = (int64_t)size[i] + size[j];
+                if (sum > cap || sum >= n) continue;
+                int64_t W = 0; /* summed similarity over member pairs */
+                for (int32_t a = 0; a < n; ++a) {
+                    if (cid[a] != i) continue;
+                    for (int32_t b = 0; b < n; ++b)
+                        if (cid[b] == j) W += S[(size_t)a * n + b];
+                }
+                int64_t sz = (int64_t)size[i] * size[j];
+                int better;
+                if (bi < 0) {
+                    better = 1;
+                } else {
+                    __int128 x = (__int128)W * bsz, y = (__int128)bW * sz;
+                    better = x > y || (x == y && sum < bsum);
+                }
+                if (better) { bi = i; bj = j; bW = W; bsz = sz; bsum = sum; }
+            }
+        }
+        if (bi < 0) break;
+        int32_t c = next++;
+        size[c] = size[bi] + size[bj];
+        alive[c] = 1;
+        alive[bi] = alive[bj] = 0;
+        int32_t at = set_ptr[c];
+        for (int32_t a = 0; a < n; ++a)
+            if (cid[a] == bi || cid[a] == bj) {
+                cid[a] = c;
+                set_vars[at++] = a;
+            }
+        set_ptr[c + 1] = at;
+    }
+    free(S); free(cid); free(size); free(alive);
+    return next;
 }
 
 /* ------------------------------------------------------------------------------------------

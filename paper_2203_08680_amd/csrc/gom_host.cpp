@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <queue>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace gom;
@@ -424,6 +426,147 @@ extern "C" int gom_fos_from_sets(const mc_graph *g, int32_t n_sets, const int32_
             return fail(GOM_E_ARG, "gom_fos_from_sets: variable %d is in no set (FOS must be "
                                    "complete)", x);
         }
+    *out = f;
+    return GOM_OK;
+    GUARD_END
+}
+
+// ------------------------------------------------------------------------------------------
+// Fixed linkage tree (Section 4.1): UPGMA over the variables, with the absolute edge weight as
+// the similarity of two variables (0 when they share no edge).  Clusters are merged pair by
+// pair, always a pair with the largest average similarity between their members; ties go to
+// the smaller combined size, then to the lower cluster ids (variables are clusters 0..n-1,
+// merged clusters get n, n+1, ... in creation order).  With a bound, only pairs whose union
+// has at most `bound` members may merge, and the tree stops when no such pair is left.  The
+// set of all variables is not part of the tree.
+//
+// Two clusters that share no edge have average similarity 0, and every pair that shares one
+// has a positive average, so the merges run in two phases: first the pairs with a positive
+// average, from a heap of candidate pairs (a pair's summed similarity never changes while
+// both are unmerged, so stale entries are only those of merged clusters); then, when no
+// allowed positive pair is left, pairs of average 0, for which the tie rule picks the two
+// smallest clusters by (size, id).
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct LtCand {
+    int64_t W;    // summed similarity between the two clusters
+    int64_t sz;   // size product
+    int32_t sum;  // size sum
+    int32_t lo, hi;
+};
+
+// a ranks below b: smaller average, then larger size sum, then larger ids
+struct LtLess {
+    bool operator()(const LtCand &a, const LtCand &b) const {
+        const __int128 x = (__int128)a.W * b.sz, y = (__int128)b.W * a.sz;
+        if (x != y) return x < y;
+        if (a.sum != b.sum) return a.sum > b.sum;
+        if (a.lo != b.lo) return a.lo > b.lo;
+        return a.hi > b.hi;
+    }
+};
+
+}  // namespace
+
+extern "C" int gom_fos_build_lt(const mc_graph *g, int32_t bound, gom_fos **out) {
+    GUARD_BEGIN
+    if (!g || !out) return fail(GOM_E_ARG, "gom_fos_build_lt: null argument");
+    if (bound < 0 || bound == 1) return fail(GOM_E_ARG, "gom_fos_build_lt: bound must be 0 or >= 2");
+    const int32_t n = g->n;
+    const int64_t cap = bound ? bound : (int64_t)n;  // largest allowed set
+    std::vector<int32_t> size((size_t)n), parent_a, parent_b;
+    std::vector<char> alive((size_t)n, 1);
+    std::vector<std::unordered_map<int32_t, int64_t>> W((size_t)n);
+    for (int32_t v = 0; v < n; ++v) {
+        size[v] = 1;
+        for (int32_t r = g->row_ptr[v]; r < g->row_ptr[(size_t)v + 1]; ++r) {
+            const int64_t w = g->wt[r] < 0 ? -(int64_t)g->wt[r] : (int64_t)g->wt[r];
+            if (w) W[v][g->col[r]] += w;
+        }
+    }
+    std::priority_queue<LtCand, std::vector<LtCand>, LtLess> heap;
+    auto push = [&](int32_t a, int32_t b, int64_t w) {
+        const int64_t sum = (int64_t)size[a] + size[b];
+        if (w <= 0 || sum > cap) return;
+        heap.push({w, (int64_t)size[a] * size[b], (int32_t)sum, std::min(a, b), std::max(a, b)});
+    };
+    for (int32_t v = 0; v < n; ++v)
+        for (const auto &kv : W[v])
+            if (kv.first > v) push(v, kv.first, kv.second);
+    int32_t n_alive = n;
+    auto merge = [&](int32_t a, int32_t b) {
+        const int32_t c = (int32_t)size.size();
+        size.push_back(size[a] + size[b]);
+        alive.push_back(1);
+        alive[a] = alive[b] = 0;
+        parent_a.push_back(a);
+        parent_b.push_back(b);
+        W.emplace_back();
+        std::unordered_map<int32_t, int64_t> &wc = W.back();
+        for (int32_t x : {a, b}) {
+            for (const auto &kv : W[x])
+                if (alive[kv.first]) wc[kv.first] += kv.second;
+            std::unordered_map<int32_t, int64_t>().swap(W[x]);
+        }
+        for (const auto &kv : wc) {
+            W[kv.first].erase(a);
+            W[kv.first].erase(b);
+            W[kv.first][c] = kv.second;
+            push(c, kv.first, kv.second);
+        }
+        --n_alive;
+    };
+    // the merge that would join every variable is never made
+    auto root = [&](int32_t a, int32_t b) { return (int64_t)size[a] + size[b] >= n; };
+    bool stop = false;
+    while (!heap.empty() && n_alive > 1) {
+        const LtCand t = heap.top();
+        heap.pop();
+        if (!alive[t.lo] || !alive[t.hi]) continue;
+        if (root(t.lo, t.hi)) {
+            stop = true;
+            break;
+        }
+        merge(t.lo, t.hi);
+    }
+    if (!stop && n_alive > 1) {
+        // average 0 for every remaining allowed pair: two smallest clusters by (size, id)
+        using SI = std::pair<int32_t, int32_t>;
+        std::priority_queue<SI, std::vector<SI>, std::greater<SI>> small;
+        for (int32_t c = 0; c < (int32_t)size.size(); ++c)
+            if (alive[c]) small.push({size[c], c});
+        while (small.size() >= 2) {
+            const SI x = small.top();
+            small.pop();
+            const SI y = small.top();
+            if ((int64_t)x.first + y.first > cap || root(x.second, y.second)) break;
+            small.pop();
+            merge(std::min(x.second, y.second), std::max(x.second, y.second));
+            small.push({size.back(), (int32_t)size.size() - 1});
+        }
+    }
+    // sets: the variables, then the merged clusters in creation order (members ascending)
+    auto *f = new gom_fos;
+    f->n_vars = n;
+    const int32_t total = (int32_t)size.size();
+    f->n_sets = total;
+    f->ptr.assign((size_t)total + 1, 0);
+    std::vector<int32_t> first((size_t)total), len((size_t)total);
+    for (int32_t v = 0; v < n; ++v) {
+        f->vars.push_back(v);
+        f->ptr[(size_t)v + 1] = v + 1;
+    }
+    for (int32_t c = n; c < total; ++c) {
+        std::vector<int32_t> mem;
+        for (int32_t part : {parent_a[(size_t)(c - n)], parent_b[(size_t)(c - n)]})
+            mem.insert(mem.end(), f->vars.begin() + f->ptr[part], f->vars.begin() + f->ptr[(size_t)part + 1]);
+        std::sort(mem.begin(), mem.end());
+        f->vars.insert(f->vars.end(), mem.begin(), mem.end());
+        f->ptr[(size_t)c + 1] = (int32_t)f->vars.size();
+        f->max_set = std::max(f->max_set, (int32_t)mem.size());
+    }
+    f->max_set = std::max(f->max_set, (int32_t)1);
     *out = f;
     return GOM_OK;
     GUARD_END

@@ -23,7 +23,8 @@ GOM_SCHED_AUTO, GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT, GOM_SCHED_BITSLICED 
 
 EXPORTED = (
     "gom_last_error", "gom_version", "mc_graph_load", "mc_graph_info", "mc_graph_csr",
-    "mc_graph_free", "gom_fos_build", "gom_fos_from_sets", "gom_fos_info", "gom_fos_get",
+    "mc_graph_free", "gom_fos_build", "gom_fos_from_sets", "gom_fos_build_lt", "gom_fos_info",
+    "gom_fos_get",
     "gom_fos_free", "gom_colour", "gom_colour_get", "gom_state_bytes", "gom_state_init",
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
@@ -89,6 +90,7 @@ def lib() -> C.CDLL:
         "gom_state_set_schedule": (C.c_int, [_vp, C.c_int]),
         "gom_state_get_schedule": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_autotune": (C.c_int, [_vp, _i32, _vp, _P(C.c_int)]),
+        "gom_fos_build_lt": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
         "gom_state_hash": (C.c_int, [_vp, _vp, _P(C.c_uint64)]),
         "gom_state_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
@@ -199,6 +201,13 @@ class GomFos:
 def gom_fos_build(g: McGraph, kind: int) -> GomFos:
     h = _vp()
     _check(lib().gom_fos_build(g.handle, int(kind), C.byref(h)))
+    return GomFos(h.value)
+
+
+def gom_fos_build_lt(g: McGraph, bound: int = 0) -> GomFos:
+    """Fixed linkage tree by UPGMA on |w| (bound > 0: bounded; 0: full tree)."""
+    h = _vp()
+    _check(lib().gom_fos_build_lt(g.handle, int(bound), C.byref(h)))
     return GomFos(h.value)
 
 
@@ -384,10 +393,15 @@ def gom_version() -> int:
 class Instance:
     """A loaded graph with its coloured FOS, ready to create states from."""
 
-    def __init__(self, n: int, u, v, w, fos_kind: int | None = None, sets=None):
+    def __init__(self, n: int, u, v, w, fos_kind: int | None = None, sets=None,
+                 lt_bound: int | None = None):
+        """FOS: explicit `sets` (ptr, vars), a linkage tree when lt_bound is given (0 = full
+        tree), else the built-in kind."""
         self.graph = mc_graph_load(n, u, v, w)
         if sets is not None:
             self.fos = gom_fos_from_sets(self.graph, sets[0], sets[1])
+        elif lt_bound is not None:
+            self.fos = gom_fos_build_lt(self.graph, lt_bound)
         else:
             self.fos = gom_fos_build(self.graph, fos_kind)
         self.k = gom_colour(self.graph, self.fos)

@@ -289,6 +289,30 @@ def test_autotune_generations_are_ordinary(cuda, kind):
     lockstep(st, ref, 3, "after autotune")
 
 
+LT_RUNS = [
+    # (label, graph maker, bound (0 = full tree), population)
+    ("torus8_full", lambda: workloads.torus(8, 1, 9, seed=4), 0, 20),
+    ("torus12_bound10", lambda: workloads.torus(12, 1, 100, seed=5), 10, 33),
+    ("cm150_full", lambda: workloads.configuration_model(150, 3, seed=7), 0, 17),
+    ("cm200_bound100", lambda: workloads.configuration_model(200, 5, seed=8), 100, 64),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+@pytest.mark.parametrize("label,maker,bound,pop", LT_RUNS, ids=[c[0] for c in LT_RUNS])
+def test_linkage_tree_fos(cuda, label, maker, bound, pop, sched):
+    """GOM over a fixed (bounded) linkage tree: the library builds its tree, the oracle its
+    own; every generation equal."""
+    print(f"case linkage tree {label} sched={sched}", flush=True)
+    g = maker()
+    inst = gom.Instance(g.n, g.u, g.v, g.w, lt_bound=bound)
+    st = inst.state(pop=pop, seed=pop + bound)
+    gom.gom_state_set_schedule(st, sched)
+    ptr, vars_ = oracle.linkage_tree(g, bound)
+    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=pop + bound)
+    lockstep(st, ref, 6, label)
+
+
 STOP_CASES = [
     # (label, graph maker, FOS kind, population, schedule)
     ("torus20_nbhd_class", lambda: workloads.torus(20, 1, 9, seed=3), 1, 24,

@@ -83,6 +83,51 @@ def test_fos_builders_match_oracle(gomlib):
         gom.gom_fos_build(h, 7)
 
 
+LT_CASES = [
+    (lambda: workloads.torus(4, 1, 9, seed=4), 0),
+    (lambda: workloads.torus(12, 1, 100, seed=5), 0),
+    (lambda: workloads.torus(12, 1, 1, seed=5), 0),       # equal weights: the tie rules decide
+    (lambda: workloads.torus(16, 1, 100, seed=6), 10),
+    (lambda: workloads.torus(16, 1, 3, seed=6), 3),
+    (lambda: workloads.configuration_model(150, 3, seed=7), 0),
+    (lambda: workloads.configuration_model(200, 5, seed=8), 100),
+    (lambda: workloads.configuration_model(200, 5, seed=9), 2),
+    (lambda: workloads.from_edges(12, [(0, 1), (2, 3), (3, 4), (6, 7), (9, 10)],
+                                  [3, -3, 7, 1, 2]), 0),   # several components
+    (lambda: workloads.from_edges(12, [(0, 1), (2, 3), (3, 4), (6, 7), (9, 10)],
+                                  [3, -3, 7, 1, 2]), 5),
+]
+
+
+@pytest.mark.parametrize("maker,bound", LT_CASES)
+def test_linkage_tree_equals_oracle(gomlib, maker, bound):
+    """The library's UPGMA linkage tree (sparse, heap of candidate pairs) equals the oracle's
+    (dense, every pair rescanned), set by set and in order."""
+    g = maker()
+    h = gom.mc_graph_load(g.n, g.u, g.v, g.w)
+    f = gom.gom_fos_build_lt(h, bound)
+    p, v = f.sets()
+    op, ov = oracle.linkage_tree(g, bound)
+    assert np.array_equal(p, op) and np.array_equal(v, ov)
+    assert f.info()["max_set"] == max(np.diff(op))
+
+
+def test_linkage_tree_errors_and_large_sizes(gomlib):
+    h = gom.mc_graph_load(4, [0, 1, 2], [1, 2, 3])
+    for b in (1, -3):
+        with pytest.raises(gom.GomError) as e:
+            gom.gom_fos_build_lt(h, b)
+        assert e.value.code == gom.GOM_E_ARG
+    # 10^5-vertex random graph: sizes and structure only (the oracle is dense)
+    g = workloads.configuration_model(100_000, 4, seed=3, weights="uniform")
+    h = gom.mc_graph_load(g.n, g.u, g.v, g.w)
+    for bound in (10, 100):
+        p, v = gom.gom_fos_build_lt(h, bound).sets()
+        sizes = np.diff(p)
+        assert sizes.max() <= bound and np.all(sizes[:g.n] == 1)
+        assert np.array_equal(v[:g.n], np.arange(g.n))
+
+
 def test_fos_from_sets_validation(gomlib):
     h = gom.mc_graph_load(4, [0, 1, 2], [1, 2, 3])
     for ptr, vars_ in (([0, 2, 3], [0, 1, 2]),          # vertex 3 in no set

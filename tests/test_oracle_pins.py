@@ -371,6 +371,101 @@ def test_state_hash_definition():
     assert run.hash() == _hash_definition(run.state()) and run.hash() not in seen
 
 
+def _read_lt_fixture(name):
+    n, edges, sets = 0, [], []
+    for line in open(os.path.join(GOLDEN, name)):
+        t = line.split()
+        if not t or t[0].startswith("#"):
+            continue
+        if t[0] == "n":
+            n = int(t[1])
+        elif t[0] == "edge":
+            edges.append((int(t[1]), int(t[2]), int(t[3])))
+        elif t[0] == "set":
+            sets.append([int(x) for x in t[1:]])
+    e = np.array(edges, np.int64)
+    g = workloads.from_edges(n, e[:, :2], e[:, 2])
+    return g, sets
+
+
+def _lt_sets(ptr, vars_):
+    return [vars_[ptr[j]:ptr[j + 1]].tolist() for j in range(len(ptr) - 1)]
+
+
+@pytest.mark.parametrize("name", ["fig2_linkage_tree.txt", "two_cliques_linkage_tree.txt"])
+def test_linkage_tree_fixtures(name):
+    """The Fig. 2 tree from weights that must produce it, and a hand-derived tree that
+    exercises both tie rules."""
+    g, expected = _read_lt_fixture(name)
+    ptr, vars_ = oracle.linkage_tree(g, 0)
+    assert _lt_sets(ptr, vars_) == expected
+
+
+def _check_upgma(g, ptr, vars_, bound):
+    """Brute-force check of a linkage tree against its definition: every merged set is the
+    union of two clusters alive at that point, every merge takes a pair of largest average
+    similarity (exact fractions over all allowed pairs, ties by size sum then ids), merge
+    similarities never increase (average linkage is reducible), the bound holds, and at the
+    end no allowed pair is left."""
+    from fractions import Fraction
+    n = g.n
+    S = np.zeros((n, n), np.int64)
+    for a, b, w in zip(g.u, g.v, g.w):
+        S[a, b] += abs(int(w))
+        S[b, a] += abs(int(w))
+    cap = bound if bound else n
+    sets = _lt_sets(ptr, vars_)
+    assert sets[:n] == [[v] for v in range(n)]
+    clusters = {v: [v] for v in range(n)}
+    last = None
+    for c in range(n, len(sets)):
+        alive = sorted(clusters)
+        best = None
+        for x in range(len(alive)):
+            for y in range(x + 1, len(alive)):
+                i, j = alive[x], alive[y]
+                A, B = clusters[i], clusters[j]
+                tot = len(A) + len(B)
+                if tot > cap or tot >= n:
+                    continue
+                key = (-Fraction(int(S[np.ix_(A, B)].sum()), len(A) * len(B)), tot, i, j)
+                if best is None or key < best:
+                    best = key
+        assert best is not None, "a merge was made with no allowed pair"
+        i, j = best[2], best[3]
+        assert sorted(clusters[i] + clusters[j]) == sets[c], f"merge {c}"
+        if last is not None:
+            assert -best[0] <= last, "merge similarity increased"
+        last = -best[0]
+        clusters[c] = sets[c]
+        del clusters[i], clusters[j]
+        assert len(sets[c]) <= cap
+    alive = sorted(clusters)
+    for x in range(len(alive)):
+        for y in range(x + 1, len(alive)):
+            tot = len(clusters[alive[x]]) + len(clusters[alive[y]])
+            assert tot > cap or tot >= n, "the tree stopped with an allowed pair left"
+    if not bound:
+        assert len(sets) == 2 * n - 2
+
+
+@pytest.mark.parametrize("maker,bound", [
+    (lambda: workloads.torus(5, 1, 4, seed=3), 0),
+    (lambda: workloads.torus(6, 1, 1, seed=1), 0),          # all weights equal: ties decide
+    (lambda: workloads.configuration_model(24, 3, seed=2), 0),
+    (lambda: workloads.configuration_model(30, 4, seed=5), 5),
+    (lambda: workloads.torus(6, 1, 9, seed=2), 3),
+    (lambda: workloads.from_edges(9, [(0, 1), (1, 2), (3, 4), (5, 6), (6, 7)],
+                                  [4, -6, 2, 1, 1]), 0),  # disconnected, a negative weight
+    (lambda: workloads.from_edges(9, [(0, 1), (1, 2), (3, 4), (5, 6), (6, 7)],
+                                  [4, -6, 2, 1, 1]), 4),
+])
+def test_linkage_tree_is_upgma(maker, bound):
+    g = maker()
+    ptr, vars_ = oracle.linkage_tree(g, bound)
+    _check_upgma(g, ptr, vars_, bound)
+
+
 def test_initial_population_rule():
     g = workloads.torus(12, 1, 3, seed=2)
     ptr, vars_ = oracle.fos(g, 0)

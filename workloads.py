@@ -105,7 +105,8 @@ def from_edges(n: int, edges, weights=None, name: str = "") -> Graph:
     return _as_graph(n, e[:, 0], e[:, 1], w, name)
 
 
-# Fully-specified workloads.  FOS kind: 0 = univariate, 1 = neighbourhood {v} U N(v).
+# Fully-specified workloads.  FOS kind: 0 = univariate, 1 = neighbourhood {v} U N(v),
+# 2 = linkage tree by UPGMA on |w| with set sizes up to lt_bound (0 = the full tree).
 @dataclass(frozen=True)
 class Workload:
     name: str
@@ -115,6 +116,7 @@ class Workload:
     max_gens: int
     to_total_weight: bool  # run until the elite reaches the total weight (bipartite tori)
     seeds: tuple = (1, 2, 3, 4, 5)
+    lt_bound: int = 0
 
     def graph(self) -> Graph:
         return self.graph_fn()
@@ -145,6 +147,10 @@ WORKLOADS = {
 # 1000x1000 torus (10^6 vertices), weights U{1..100}: the HBM-bound size.
 WORKLOADS["torus1000_uni_p64"] = Workload("torus1000_uni_p64", _t1000, 0, 64, 1000, True)
 WORKLOADS["torus1000_nbhd_p64"] = Workload("torus1000_nbhd_p64", _t1000, 1, 64, 1000, True)
+# 100x100 torus with fixed linkage trees: the full tree and trees bounded to 10 and 100.
+for _b in (0, 10, 100):
+    _name = f"torus100_bflt{_b}_p64" if _b else "torus100_flt_p64"
+    WORKLOADS[_name] = Workload(_name, _c2, 2, 64, 500, True, lt_bound=_b)
 for _d in (3, 6, 12):
     for _k, _fn in ((0, "uni"), (1, "nbhd")):
         WORKLOADS[f"cm100k_d{_d}_{_fn}_p32"] = Workload(
