@@ -335,6 +335,60 @@ int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);
 /* Releases the batch and its instances' host resources; the caller frees the arena. */
 void gom_batch_free(gom_batch *b);
 
+/* ------------------------------------------------------------------------------------------
+ * Serving loop with continuous batching.  Jobs (a graph, a coloured FOS, a population size, a
+ * seed, a target and a generation limit) are submitted at any time and wait in a queue; each
+ * step admits queued jobs first come first served while their states fit in the server's
+ * arena (the HBM budget), advances every admitted job by a chunk of 4 generations, and
+ * retires the jobs that reached their target or their generation limit, freeing their
+ * memory.  Admitted jobs that fit the resident schedule share the batched lockstep launches;
+ * larger ones run their own schedule on the same stream.  A job's random numbers depend on
+ * its seed alone, so its result equals that of gom_run_to_target on a fresh state with the
+ * same arguments, whatever else runs beside it.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct gom_server gom_server;
+
+typedef struct {
+    int64_t job;          /* id from gom_server_submit */
+    int32_t generations;  /* generations run */
+    int32_t reached;      /* 1 if the elitist fitness reached the target */
+    int64_t best;         /* elitist fitness */
+    int64_t attempted, evaluated, accepted;
+    uint64_t hash;        /* gom_state_hash of the final state */
+    double submit_ms, admit_ms, done_ms;  /* host clock, ms since gom_server_create; done_ms
+                                             is when the step that found it finished ended */
+} gom_job_result;
+
+/*
+ * dev_arena: caller-owned device memory (256-byte aligned) that holds the job tables for up
+ * to max_jobs admitted jobs and, in the rest, the admitted jobs' states (first-fit).  stream:
+ * all the server's work is enqueued there.  Errors: GOM_E_ARG, GOM_E_NOMEM (misaligned, or
+ * no room beyond the tables), GOM_E_DEVICE.
+ */
+int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t max_jobs, void *stream,
+                      gom_server **out);
+
+/* Queue a job.  g and f (coloured) are borrowed: keep them alive until the job's result has
+ * been returned.  *job receives its id (0, 1, ...).  Errors: as gom_state_bytes, GOM_E_NOMEM
+ * if the job could never fit the arena, GOM_E_ARG. */
+int gom_server_submit(gom_server *s, const mc_graph *g, const gom_fos *f, int32_t pop,
+                      uint64_t seed, int64_t target, int32_t max_generations,
+                      int neutral_rule, int class_order, int64_t *job);
+
+/* One step: admit, run a chunk of generations, retire.  Synchronous.  Outputs may be NULL. */
+int gom_server_step(gom_server *s, int32_t *n_active, int32_t *n_queued);
+
+/* Move up to `capacity` finished jobs' results into out (in retirement order); *n receives
+ * the number moved. */
+int gom_server_results(gom_server *s, gom_job_result *out, int32_t capacity, int32_t *n);
+
+/* Admitted jobs, queued jobs, admitted jobs in the batched launches, free arena bytes. */
+int gom_server_info(const gom_server *s, int32_t *n_active, int32_t *n_queued,
+                    int32_t *n_batched, size_t *free_bytes);
+
+/* Waits for the stream and releases the server (jobs still admitted are dropped). */
+void gom_server_free(gom_server *s);
+
 #ifdef __cplusplus
 }
 #endif

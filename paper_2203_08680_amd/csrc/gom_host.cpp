@@ -5,9 +5,12 @@
 #include "gom_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <queue>
 #include <string>
@@ -784,20 +787,7 @@ static EpilogueArgs epilogue_args(const gom_state *s, int64_t target, bool rows)
 }
 
 static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool rows) {
-    EpilogueArgs e{};
-    e.P = s->d_P;
-    e.O = s->d_O;
-    e.rows = rows ? s->d_rows : nullptr;
-    e.E = s->d_E;
-    e.fit = s->d_fit;
-    e.st = s->d_st;
-    e.stripes = s->d_stripes;
-    e.target = target;
-    e.n = s->n;
-    e.N = s->N;
-    e.mode = kEpiGeneration;
-    e.row_words = (s->n + 63) / 64;
-    HIP_TRY(launch_epilogue(e, st));
+    HIP_TRY(launch_epilogue(epilogue_args(s, target, rows), st));
     return GOM_OK;
 }
 
@@ -1625,4 +1615,343 @@ extern "C" int gom_batch_state(gom_batch *b, int32_t index, gom_state **state) {
         return fail(GOM_E_ARG, "gom_batch_state: bad arguments");
     *state = b->subs[(size_t)index];
     return GOM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Serving loop: jobs arrive at any time, are admitted first come first served while their
+// states fit in the server's arena, and advance together one chunk of generations per step.
+// Jobs that fit the resident schedule share the batched lockstep launches (each with its own
+// generation index, target and generation limit); the others run their own schedule on the
+// same stream.  A job's random numbers depend only on its seed, so its result does not
+// depend on what else is running.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct ServerJob {
+    int64_t id = 0;
+    const mc_graph *g = nullptr;
+    const gom_fos *f = nullptr;
+    int32_t pop = 0, max_gens = 0;
+    uint64_t seed = 0;
+    int64_t target = 0;
+    int rule = 0, order = 0;
+    size_t bytes = 0, off = 0;
+    gom_state *s = nullptr;
+    bool batched = false;
+    double submit_ms = 0.0, admit_ms = 0.0;
+};
+
+// Fixed-size tables of the batched launch, in the first bytes of the arena.
+struct ServerAux {
+    size_t insts = 0, snap = 0, blk = 0, vblk = 0, total = 0;
+};
+
+constexpr int32_t kServerMaxVBlocks = 544;  // vertex-pass blocks of the largest batched job
+
+ServerAux server_aux(int32_t max_jobs) {
+    ServerAux A;
+    size_t o = 0;
+    A.insts = o;
+    o = align_up(o + sizeof(BatchInst) * (size_t)max_jobs);
+    A.snap = o;
+    o = align_up(o + sizeof(DevState) * (size_t)max_jobs);
+    A.blk = o;
+    o = align_up(o + sizeof(int2) * (size_t)max_jobs * GOM_MAX_POP);
+    A.vblk = o;
+    o = align_up(o + sizeof(int32_t) * (size_t)max_jobs * kServerMaxVBlocks);
+    A.total = o;
+    return A;
+}
+
+}  // namespace
+
+struct gom_server {
+    char *arena = nullptr;
+    size_t bytes = 0;
+    int32_t max_jobs = 0, chunk = 4;
+    hipStream_t st = nullptr;
+    ServerAux A;
+    std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
+    std::deque<ServerJob> queue;
+    std::vector<ServerJob> active;        // batched jobs first after a rebuild
+    std::vector<gom_job_result> done;
+    int64_t next_id = 0;
+    bool dirty = true;
+    int32_t n_batched = 0;
+    int sweep_blocks = 0, vblocks = 0;
+    size_t lds = 0;
+    DevState *h_snap = nullptr;           // pinned, max_jobs
+    std::chrono::steady_clock::time_point t0;
+
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    }
+    bool alloc(size_t need, size_t *off) {
+        need = align_up(need);
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second < need) continue;
+            *off = it->first;
+            const size_t rest = it->second - need, at = it->first + need;
+            free_blocks.erase(it);
+            if (rest) free_blocks[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t size) {
+        size = align_up(size);
+        auto it = free_blocks.emplace(off, size).first;
+        auto next = std::next(it);
+        if (next != free_blocks.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_blocks.erase(next);
+        }
+        if (it != free_blocks.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_blocks.erase(it);
+            }
+        }
+    }
+};
+
+extern "C" int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t max_jobs,
+                                 void *stream, gom_server **out) {
+    GUARD_BEGIN
+    if (!dev_arena || !out || max_jobs < 1) return fail(GOM_E_ARG, "gom_server_create: bad arguments");
+    if ((reinterpret_cast<uintptr_t>(dev_arena) & 255) != 0)
+        return fail(GOM_E_NOMEM, "gom_server_create: arena must be 256-byte aligned");
+    const ServerAux A = server_aux(max_jobs);
+    if (arena_bytes <= A.total)
+        return fail(GOM_E_NOMEM, "gom_server_create: arena has %zu bytes, the job tables alone "
+                    "need %zu", arena_bytes, A.total);
+    auto *sv = new gom_server;
+    sv->arena = (char *)dev_arena;
+    sv->bytes = arena_bytes;
+    sv->max_jobs = max_jobs;
+    sv->st = (hipStream_t)stream;
+    sv->A = A;
+    sv->free_blocks[A.total] = arena_bytes - A.total;
+    sv->t0 = std::chrono::steady_clock::now();
+    hipError_t e = hipHostMalloc((void **)&sv->h_snap, sizeof(DevState) * (size_t)max_jobs,
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete sv;
+        return fail(GOM_E_DEVICE, "gom_server_create: %s", hipGetErrorString(e));
+    }
+    *out = sv;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_server_submit(gom_server *sv, const mc_graph *g, const gom_fos *f,
+                                 int32_t pop, uint64_t seed, int64_t target,
+                                 int32_t max_generations, int neutral_rule, int class_order,
+                                 int64_t *job) {
+    GUARD_BEGIN
+    if (!sv || !g || !f || !job || max_generations < 0)
+        return fail(GOM_E_ARG, "gom_server_submit: bad arguments");
+    ServerJob J;
+    int rc = gom_state_bytes(g, f, pop, &J.bytes);
+    if (rc) return rc;
+    if (align_up(J.bytes) > sv->bytes - sv->A.total)
+        return fail(GOM_E_NOMEM, "gom_server_submit: the job needs %zu bytes, more than the "
+                    "whole arena", J.bytes);
+    if (neutral_rule != GOM_NEUTRAL_PAPER && neutral_rule != GOM_NEUTRAL_ALWAYS)
+        return fail(GOM_E_ARG, "gom_server_submit: unknown neutral rule %d", neutral_rule);
+    if (class_order != GOM_ORDER_RANDOM && class_order != GOM_ORDER_FIXED)
+        return fail(GOM_E_ARG, "gom_server_submit: unknown class order %d", class_order);
+    J.id = sv->next_id++;
+    J.g = g;
+    J.f = f;
+    J.pop = pop;
+    J.seed = seed;
+    J.target = target;
+    J.max_gens = max_generations;
+    J.rule = neutral_rule;
+    J.order = class_order;
+    J.submit_ms = sv->now_ms();
+    sv->queue.push_back(J);
+    *job = J.id;
+    return GOM_OK;
+    GUARD_END
+}
+
+namespace {
+
+// Final result of a job from its run scalars (a fresh state: generation 0 at admission).
+gom_job_result server_result(gom_server *sv, const ServerJob &J, const DevState &h) {
+    gom_job_result r{};
+    r.job = J.id;
+    r.generations = h.generation;
+    r.reached = h.elite_fitness >= J.target ? 1 : 0;
+    r.best = h.elite_fitness;
+    r.attempted = (int64_t)J.s->N * J.s->n_sets * (int64_t)h.generation;
+    r.evaluated = h.evaluated;
+    r.accepted = h.accepted;
+    r.submit_ms = J.submit_ms;
+    r.admit_ms = J.admit_ms;
+    r.done_ms = sv->now_ms();
+    return r;
+}
+
+// Tables of the batched launch for the active jobs (batched ones first); the stream must be
+// idle (no launch may still read the old tables).
+int server_rebuild(gom_server *sv) {
+    std::stable_partition(sv->active.begin(), sv->active.end(),
+                          [](const ServerJob &J) { return J.batched; });
+    std::vector<BatchInst> insts(sv->active.size());
+    std::vector<int2> blk;
+    std::vector<int32_t> vblk;
+    sv->n_batched = 0;
+    sv->lds = 0;
+    for (size_t b = 0; b < sv->active.size(); ++b) {
+        const ServerJob &J = sv->active[b];
+        gom_state *s = J.s;
+        BatchInst &I = insts[b];
+        I.res = resident_ctx(s, J.target);
+        I.epi = epilogue_args(s, J.target, true);
+        I.epi.gen_limit = J.max_gens;
+        I.kind = s->univariate ? 0 : 1;
+        I.order_fixed = s->order == GOM_ORDER_FIXED;
+        if (!J.batched) continue;
+        ++sv->n_batched;
+        const bool plds = kBatchOrderBytes + resident_lds_bytes(s->n, true) <= s->lds_max;
+        I.plds = plds ? 1 : 0;
+        I.vblock0 = (int32_t)vblk.size();
+        for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2((int)b, i));
+        for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back((int32_t)b);
+        sv->lds = std::max(sv->lds, kBatchOrderBytes + resident_lds_bytes(s->n, plds));
+    }
+    sv->sweep_blocks = (int)blk.size();
+    sv->vblocks = (int)vblk.size();
+    hipStream_t st = sv->st;
+    if (!insts.empty())
+        HIP_TRY(hipMemcpyAsync(sv->arena + sv->A.insts, insts.data(),
+                               sizeof(BatchInst) * insts.size(), hipMemcpyHostToDevice, st));
+    if (!blk.empty())
+        HIP_TRY(hipMemcpyAsync(sv->arena + sv->A.blk, blk.data(), sizeof(int2) * blk.size(),
+                               hipMemcpyHostToDevice, st));
+    if (!vblk.empty())
+        HIP_TRY(hipMemcpyAsync(sv->arena + sv->A.vblk, vblk.data(),
+                               sizeof(int32_t) * vblk.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the host tables die here
+    sv->dirty = false;
+    return GOM_OK;
+}
+
+}  // namespace
+
+extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_queued) {
+    GUARD_BEGIN
+    if (!sv) return fail(GOM_E_ARG, "gom_server_step: null server");
+    hipStream_t st = sv->st;
+    // admission, first come first served
+    while (!sv->queue.empty() && (int32_t)sv->active.size() < sv->max_jobs) {
+        ServerJob &J = sv->queue.front();
+        size_t off = 0;
+        if (!sv->alloc(J.bytes, &off)) break;
+        gom_state *s = nullptr;
+        int rc = gom_state_init(J.g, J.f, J.pop, J.seed, J.rule, J.order, sv->arena + off,
+                                align_up(J.bytes), st, &s);
+        if (rc) {
+            sv->release(off, J.bytes);
+            return rc;
+        }
+        J.s = s;
+        J.off = off;
+        J.batched = s->resident_ok &&
+                    kBatchOrderBytes + resident_lds_bytes(s->n, false) <= s->lds_max &&
+                    (s->n + 255) / 256 <= kServerMaxVBlocks;
+        J.admit_ms = sv->now_ms();
+        sv->active.push_back(J);
+        sv->queue.pop_front();
+        sv->dirty = true;
+    }
+    if (sv->dirty) {
+        int rc = server_rebuild(sv);
+        if (rc) return rc;
+    }
+    const int32_t na = (int32_t)sv->active.size();
+    if (na > 0) {
+        BatchInst *d_insts = (BatchInst *)(sv->arena + sv->A.insts);
+        for (int32_t t = 0; t < sv->chunk; ++t) {
+            if (sv->n_batched > 0)
+                HIP_TRY(launch_batch_step(d_insts, sv->n_batched,
+                                          (const int2 *)(sv->arena + sv->A.blk), sv->sweep_blocks,
+                                          (const int32_t *)(sv->arena + sv->A.vblk),
+                                          sv->vblocks, sv->lds, st));
+            for (int32_t b = sv->n_batched; b < na; ++b) {
+                ServerJob &J = sv->active[(size_t)b];
+                if (J.s->g_host >= J.max_gens) continue;
+                int rc = enqueue_generation(J.s, J.s->g_host, J.target, st);
+                if (rc) return rc;
+                J.s->g_host++;
+            }
+        }
+        DevState *d_snap = (DevState *)(sv->arena + sv->A.snap);
+        HIP_TRY(launch_batch_gather(d_insts, na, d_snap, st));
+        HIP_TRY(hipMemcpyAsync(sv->h_snap, d_snap, sizeof(DevState) * (size_t)na,
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<ServerJob> keep;
+        for (int32_t b = 0; b < na; ++b) {
+            ServerJob &J = sv->active[(size_t)b];
+            const DevState &h = sv->h_snap[b];
+            if (h.elite_fitness < J.target && h.generation < J.max_gens) {
+                keep.push_back(J);
+                continue;
+            }
+            gom_job_result r = server_result(sv, J, h);
+            int rc = gom_state_hash(J.s, st, &r.hash);
+            if (rc) return rc;
+            sv->done.push_back(r);
+            gom_state_free(J.s);
+            sv->release(J.off, J.bytes);
+            sv->dirty = true;
+        }
+        sv->active.swap(keep);
+    }
+    if (n_active) *n_active = (int32_t)sv->active.size();
+    if (n_queued) *n_queued = (int32_t)sv->queue.size();
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_server_results(gom_server *sv, gom_job_result *out, int32_t capacity,
+                                  int32_t *n) {
+    if (!sv || !n || (capacity > 0 && !out)) return fail(GOM_E_ARG, "gom_server_results: bad arguments");
+    const int32_t k = std::min<int32_t>(capacity, (int32_t)sv->done.size());
+    std::copy(sv->done.begin(), sv->done.begin() + k, out);
+    sv->done.erase(sv->done.begin(), sv->done.begin() + k);
+    *n = k;
+    return GOM_OK;
+}
+
+extern "C" int gom_server_info(const gom_server *sv, int32_t *n_active, int32_t *n_queued,
+                               int32_t *n_batched, size_t *free_bytes) {
+    if (!sv) return fail(GOM_E_ARG, "gom_server_info: null server");
+    if (n_active) *n_active = (int32_t)sv->active.size();
+    if (n_queued) *n_queued = (int32_t)sv->queue.size();
+    if (n_batched) {
+        int32_t c = 0;
+        for (const ServerJob &J : sv->active) c += J.batched;
+        *n_batched = c;
+    }
+    if (free_bytes) {
+        size_t t = 0;
+        for (const auto &kv : sv->free_blocks) t += kv.second;
+        *free_bytes = t;
+    }
+    return GOM_OK;
+}
+
+extern "C" void gom_server_free(gom_server *sv) {
+    if (!sv) return;
+    if (sv->st) (void)hipStreamSynchronize(sv->st);
+    for (ServerJob &J : sv->active) gom_state_free(J.s);
+    if (sv->h_snap) (void)hipHostFree(sv->h_snap);
+    delete sv;
 }

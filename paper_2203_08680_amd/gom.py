@@ -30,7 +30,8 @@ EXPORTED = (
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
-    "gom_batch_state", "gom_batch_free",
+    "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
+    "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
 )
 
 
@@ -43,6 +44,13 @@ class GomError(RuntimeError):
 class gom_result(C.Structure):
     _fields_ = [("generations", C.c_int32), ("reached", C.c_int32), ("best", C.c_int64),
                 ("attempted", C.c_int64), ("evaluated", C.c_int64), ("accepted", C.c_int64)]
+
+
+class gom_job_result(C.Structure):
+    _fields_ = [("job", C.c_int64), ("generations", C.c_int32), ("reached", C.c_int32),
+                ("best", C.c_int64), ("attempted", C.c_int64), ("evaluated", C.c_int64),
+                ("accepted", C.c_int64), ("hash", C.c_uint64), ("submit_ms", C.c_double),
+                ("admit_ms", C.c_double), ("done_ms", C.c_double)]
 
 
 _lib = None
@@ -101,6 +109,13 @@ def lib() -> C.CDLL:
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_batch_free": (None, [_vp]),
+        "gom_server_create": (C.c_int, [_vp, _sz, _i32, _vp, _P(_vp)]),
+        "gom_server_submit": (C.c_int, [_vp, _vp, _vp, _i32, _u64, _i64, _i32, C.c_int, C.c_int,
+                                        _P(_i64)]),
+        "gom_server_step": (C.c_int, [_vp, _P(_i32), _P(_i32)]),
+        "gom_server_results": (C.c_int, [_vp, _vp, _i32, _P(_i32)]),
+        "gom_server_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_sz)]),
+        "gom_server_free": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -491,3 +506,68 @@ def gom_batch_run(b: GomBatch, max_generations: int, stream=None):
     out = [RunResult(r.generations, bool(r.reached), r.best, r.attempted, r.evaluated,
                      r.accepted) for r in res]
     return out, tt
+
+
+# ------------------------------------------------------------------------------------------
+# Serving loop
+# ------------------------------------------------------------------------------------------
+class GomServer:
+    """Owned gom_server handle, its device arena (a torch tensor) and the instances of the
+    jobs submitted to it (kept alive until their results have been taken)."""
+
+    def __init__(self, arena_bytes: int, max_jobs: int = 256, device=None, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
+        off = (-self.arena.data_ptr()) % 256
+        self._stream = _stream_handle(stream)
+        self._jobs = {}
+        h = _vp()
+        _check(lib().gom_server_create(self.arena.data_ptr() + off, int(arena_bytes),
+                                       int(max_jobs), self._stream, C.byref(h)))
+        self.handle = h.value
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gom_server_free(self.handle)
+            self.handle = None
+
+    def submit(self, inst: "Instance", pop: int, seed: int, target: int, max_generations: int,
+               neutral_rule: int = GOM_NEUTRAL_PAPER,
+               class_order: int = GOM_ORDER_RANDOM) -> int:
+        j = _i64()
+        _check(lib().gom_server_submit(self.handle, inst.graph.handle, inst.fos.handle,
+                                       int(pop), int(seed) & (2**64 - 1), int(target),
+                                       int(max_generations), int(neutral_rule),
+                                       int(class_order), C.byref(j)))
+        self._jobs[j.value] = inst
+        return j.value
+
+    def step(self):
+        """Admit, run a chunk of generations, retire; returns (active, queued)."""
+        a, q = _i32(), _i32()
+        _check(lib().gom_server_step(self.handle, C.byref(a), C.byref(q)))
+        return a.value, q.value
+
+    def results(self, capacity: int = 1024):
+        buf = (gom_job_result * capacity)()
+        n = _i32()
+        _check(lib().gom_server_results(self.handle, buf, int(capacity), C.byref(n)))
+        out = []
+        for r in buf[:n.value]:
+            out.append({"job": r.job, "generations": r.generations, "reached": bool(r.reached),
+                        "best": r.best, "attempted": r.attempted, "evaluated": r.evaluated,
+                        "accepted": r.accepted, "hash": r.hash, "submit_ms": r.submit_ms,
+                        "admit_ms": r.admit_ms, "done_ms": r.done_ms})
+            self._jobs.pop(r.job, None)
+        return out
+
+    def info(self):
+        a, q, b, fb = _i32(), _i32(), _i32(), _sz()
+        _check(lib().gom_server_info(self.handle, C.byref(a), C.byref(q), C.byref(b),
+                                     C.byref(fb)))
+        return {"active": a.value, "queued": q.value, "batched": b.value,
+                "free_bytes": fb.value}

@@ -482,3 +482,51 @@ def test_batch_continues_across_calls(cuda):
     for b in range(len(items)):
         assert_same(gom.gom_state_read(b1.state(b)), gom.gom_state_read(b2.state(b)),
                     f"instance {b}")
+
+
+def test_server_jobs_equal_solo_runs(cuda):
+    """Jobs submitted at different times to a server whose arena holds only a few at once:
+    each job's result and final state hash equal those of its solo run, including a job too
+    large for the resident schedule (run beside the batched ones), generation limits that end
+    inside a chunk, and a job whose target is met at the start."""
+    print("case server vs solo", flush=True)
+    items = workloads.batch_mix(count=8, seed=13, n_lo=100, n_hi=3000)
+    jobs = []
+    for k, it in enumerate(items):
+        inst = gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
+        tg = it.graph.total_weight if it.to_total_weight else (1 << 62)
+        jobs.append((inst, it.pop, it.seed, tg, 6 + k))
+    big = workloads.torus(400, 1, 100, seed=21)          # 160 000 vertices: not resident
+    jobs.insert(3, (gom.Instance(big.n, big.u, big.v, big.w, 0), 64, 99, big.total_weight, 9))
+    small = workloads.torus(6, 1, 3, seed=2)
+    jobs.append((gom.Instance(small.n, small.u, small.v, small.w, 1), 8, 5, 0, 50))
+    need = [gom.gom_state_bytes(x.graph, x.fos, p) for x, p, _, _, _ in jobs]
+    # the job tables (about 25 kB for 8 jobs), the large job and the largest other one:
+    # later jobs have to wait for memory
+    arena = (64 << 10) + need[3] + max(need[:3] + need[4:])
+    srv = gom.GomServer(arena, max_jobs=8)
+    ids = [srv.submit(*jobs[k]) for k in range(4)]
+    seen_queue = False
+    for _ in range(2):
+        a, q = srv.step()
+        seen_queue |= q > 0
+    ids += [srv.submit(*jobs[k]) for k in range(4, len(jobs))]
+    res = {}
+    for _ in range(400):
+        a, q = srv.step()
+        seen_queue |= q > 0
+        for r in srv.results():
+            res[r["job"]] = r
+        if a == 0 and q == 0:
+            break
+    assert sorted(res) == sorted(ids)
+    assert seen_queue, "the arena never made a job wait"
+    for jid, (inst, pop, seed, tg, mg) in zip(ids, jobs):
+        st = inst.state(pop=pop, seed=seed)
+        r = gom.gom_run_to_target(st, tg, mg)
+        got = res[jid]
+        assert (got["generations"], got["reached"], got["best"], got["attempted"],
+                got["evaluated"], got["accepted"]) == (r.generations, r.reached, r.best,
+                                                       r.attempted, r.evaluated, r.accepted), jid
+        assert got["hash"] == gom.gom_state_hash(st), jid
+        assert got["submit_ms"] <= got["admit_ms"] <= got["done_ms"]
