@@ -174,6 +174,111 @@ def run_batch_mode(args, torch, gom):
     print(json.dumps(line), flush=True)
 
 
+def run_serve_mode(args, torch, gom):
+    """Serving loop on a Poisson stream of jobs: every job alone first (its service time, and
+    the result it must reproduce), then the stream at an arrival rate of 0.7 x the plain
+    capacity through the serving loop.  Time to solution is from arrival to completion; the
+    plain figure is a first-come-first-served queue of the same arrivals with the measured
+    solo service times."""
+    sizes = tuple(args.serve_sizes.split(","))
+    jobs = workloads.serve_stream(count=args.serve_jobs, seed=5, max_gens=args.serve_max_gens,
+                                  sizes=sizes)
+    t0 = time.perf_counter()
+    insts = [gom.Instance(j.graph.n, j.graph.u, j.graph.v, j.graph.w, j.fos) for j in jobs]
+    log(f"serve set-up: {len(jobs)} jobs, {sum(x.n for x in insts)} vertices, "
+        f"{time.perf_counter() - t0:.1f} s")
+    # warm-up: one small job alone and through a server
+    w = workloads.torus(16, 1, 9, seed=1)
+    wi = gom.Instance(w.n, w.u, w.v, w.w, 1)
+    gom.gom_run_to_target(wi.state(pop=16, seed=1), w.total_weight, 4)
+    ws = gom.GomServer(64 << 20, max_jobs=4, streams=args.serve_streams)
+    ws.submit(wi, 16, 1, w.total_weight, 4)
+    while ws.step() != (0, 0):
+        pass
+    ws.close()
+    # plain: each job alone, one after another
+    solo, service = [], []
+    for x, j in zip(insts, jobs):
+        st = x.state(pop=j.pop, seed=j.seed)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        r = gom.gom_run_to_target(st, j.target, j.max_gens)
+        service.append(time.perf_counter() - s0)
+        solo.append((r, gom.gom_state_hash(st)))
+        del st
+    service = np.array(service)
+    capacity = len(jobs) / service.sum()
+    rate = args.serve_load * capacity
+    arrivals = workloads.poisson_arrivals(len(jobs), rate, seed=5)
+    finish, plain_tts = 0.0, []
+    for a, sv in zip(arrivals, service):
+        finish = max(a, finish) + sv
+        plain_tts.append(finish - a)
+    log(f"plain: capacity {capacity:.2f} jobs/s, arrival rate {rate:.2f} jobs/s")
+    # served: the same arrivals through the serving loop
+    arena_bytes = int(args.serve_arena_gb * (1 << 30))
+    srv = gom.GomServer(arena_bytes, max_jobs=256, streams=args.serve_streams)
+    start = time.perf_counter()
+    nxt, ids, res = 0, {}, {}
+    while len(res) < len(jobs):
+        now = time.perf_counter() - start
+        while nxt < len(jobs) and arrivals[nxt] <= now:
+            j = jobs[nxt]
+            ids[srv.submit(insts[nxt], j.pop, j.seed, j.target, j.max_gens)] = nxt
+            nxt += 1
+        a, q = srv.step()
+        for r in srv.results():
+            res[ids[r["job"]]] = (r, time.perf_counter() - start)
+        if a == 0 and q == 0 and nxt < len(jobs):
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - start)))
+    makespan = time.perf_counter() - start
+    served_tts = [res[k][1] - arrivals[k] for k in range(len(jobs))]
+
+    def same_as_solo(res):
+        return all((res[k][0]["generations"], res[k][0]["best"], res[k][0]["evaluated"],
+                    res[k][0]["accepted"], res[k][0]["hash"]) ==
+                   (solo[k][0].generations, solo[k][0].best, solo[k][0].evaluated,
+                    solo[k][0].accepted, solo[k][1]) for k in range(len(jobs)))
+
+    same = same_as_solo(res)
+    attempted = sum(r.attempted for r, _ in solo)
+    log(f"served: makespan {makespan:.2f} s, identical results: {same}")
+    # saturated: every job submitted at once (capacity of the serving loop)
+    ids, res2 = {}, {}
+    start = time.perf_counter()
+    for k, j in enumerate(jobs):
+        ids[srv.submit(insts[k], j.pop, j.seed, j.target, j.max_gens)] = k
+    while len(res2) < len(jobs):
+        srv.step()
+        for r in srv.results():
+            res2[ids[r["job"]]] = (r, time.perf_counter() - start)
+    saturated = time.perf_counter() - start
+    same2 = same_as_solo(res2)
+    log(f"saturated: all {len(jobs)} jobs in {saturated:.2f} s (alone one after another: "
+        f"{service.sum():.2f} s), identical results: {same2}")
+    pct = lambda x, q: float(np.percentile(np.array(x) * 1e3, q))
+    line = {
+        "metric": METRIC, "value": attempted / makespan, "unit": "evals/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": makespan * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"serve{len(jobs)}_tori_and_regular_{'_'.join(sizes)}",
+                   "jobs": len(jobs), "max_generations": args.serve_max_gens,
+                   "arrival_rate_jobs_per_s": rate, "load": args.serve_load,
+                   "arena_bytes": arena_bytes, "streams": args.serve_streams,
+                   "mode": "served"},
+        "time_to_solution_ms": {"served_p50": pct(served_tts, 50),
+                                "served_p99": pct(served_tts, 99),
+                                "plain_fifo_p50": pct(plain_tts, 50),
+                                "plain_fifo_p99": pct(plain_tts, 99)},
+        "plain": {"capacity_jobs_per_s": capacity, "service_ms_total": service.sum() * 1e3,
+                  "value": attempted / service.sum()},
+        "saturated": {"served_ms": saturated * 1e3, "value": attempted / saturated,
+                      "served_over_plain": service.sum() / saturated},
+        "identical_results": same and same2,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +298,18 @@ def main():
                     help="batched vs plain on the 256-instance mix instead of the default "
                          "single-instance workload")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving loop on a Poisson stream of jobs instead of the default "
+                         "single-instance workload")
+    ap.add_argument("--serve-jobs", type=int, default=60)
+    ap.add_argument("--serve-max-gens", type=int, default=200)
+    ap.add_argument("--serve-sizes", default="small,medium",
+                    help="size classes of the job stream: small (10^4 vertices), medium "
+                         "(10^5), large (10^6; host set-up of up to 30 s per job)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the measured plain capacity")
+    ap.add_argument("--serve-arena-gb", type=float, default=32.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -221,6 +338,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batch:
         run_batch_mode(args, torch, gom)
+        return
+    if args.serve:
+        run_serve_mode(args, torch, gom)
         return
 
     wl = workloads.WORKLOADS[args.workload]

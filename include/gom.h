@@ -337,14 +337,15 @@ void gom_batch_free(gom_batch *b);
 
 /* ------------------------------------------------------------------------------------------
  * Serving loop with continuous batching.  Jobs (a graph, a coloured FOS, a population size, a
- * seed, a target and a generation limit) are submitted at any time and wait in a queue; each
- * step admits queued jobs first come first served while their states fit in the server's
- * arena (the HBM budget), advances every admitted job by a chunk of 4 generations, and
- * retires the jobs that reached their target or their generation limit, freeing their
- * memory.  Admitted jobs that fit the resident schedule share the batched lockstep launches;
- * larger ones run their own schedule on the same stream.  A job's random numbers depend on
- * its seed alone, so its result equals that of gom_run_to_target on a fresh state with the
- * same arguments, whatever else runs beside it.
+ * seed, a target and a generation limit) are submitted at any time and wait in a queue.
+ * gom_server_step admits queued jobs first come first served while their states fit in the
+ * server's arena (the HBM budget), and moves every admitted job forward without waiting for
+ * the others: each job runs on one of the server's streams (the least loaded at admission),
+ * a chunk of 4 generations at a time under the schedule gom_state_init chose for it, and as
+ * soon as a chunk has finished the job is retired (target or generation limit reached; its
+ * memory is freed) or given its next chunk.  Jobs on different streams overlap on the device.
+ * A job's random numbers depend on its seed alone, so its result equals that of
+ * gom_run_to_target on a fresh state with the same arguments, whatever else runs beside it.
  * ------------------------------------------------------------------------------------------ */
 typedef struct gom_server gom_server;
 
@@ -356,16 +357,16 @@ typedef struct {
     int64_t attempted, evaluated, accepted;
     uint64_t hash;        /* gom_state_hash of the final state */
     double submit_ms, admit_ms, done_ms;  /* host clock, ms since gom_server_create; done_ms
-                                             is when the step that found it finished ended */
+                                             is when a step found the job finished */
 } gom_job_result;
 
 /*
- * dev_arena: caller-owned device memory (256-byte aligned) that holds the job tables for up
- * to max_jobs admitted jobs and, in the rest, the admitted jobs' states (first-fit).  stream:
- * all the server's work is enqueued there.  Errors: GOM_E_ARG, GOM_E_NOMEM (misaligned, or
- * no room beyond the tables), GOM_E_DEVICE.
+ * dev_arena: caller-owned device memory (256-byte aligned) in which admitted jobs' states are
+ * placed first-fit.  max_jobs: most jobs admitted at once.  streams: number of streams the
+ * server creates for its jobs (1..16, default priority).  Errors: GOM_E_ARG, GOM_E_NOMEM
+ * (misaligned or too small), GOM_E_DEVICE.
  */
-int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t max_jobs, void *stream,
+int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t max_jobs, int32_t streams,
                       gom_server **out);
 
 /* Queue a job.  g and f (coloured) are borrowed: keep them alive until the job's result has
@@ -375,18 +376,19 @@ int gom_server_submit(gom_server *s, const mc_graph *g, const gom_fos *f, int32_
                       uint64_t seed, int64_t target, int32_t max_generations,
                       int neutral_rule, int class_order, int64_t *job);
 
-/* One step: admit, run a chunk of generations, retire.  Synchronous.  Outputs may be NULL. */
+/* One pass: admit what fits, retire or continue every job whose chunk has finished.  Returns
+ * without waiting for running chunks (call it in a loop).  Outputs may be NULL. */
 int gom_server_step(gom_server *s, int32_t *n_active, int32_t *n_queued);
 
 /* Move up to `capacity` finished jobs' results into out (in retirement order); *n receives
  * the number moved. */
 int gom_server_results(gom_server *s, gom_job_result *out, int32_t capacity, int32_t *n);
 
-/* Admitted jobs, queued jobs, admitted jobs in the batched launches, free arena bytes. */
+/* Admitted jobs, queued jobs, streams, free arena bytes.  Outputs may be NULL. */
 int gom_server_info(const gom_server *s, int32_t *n_active, int32_t *n_queued,
-                    int32_t *n_batched, size_t *free_bytes);
+                    int32_t *n_streams, size_t *free_bytes);
 
-/* Waits for the stream and releases the server (jobs still admitted are dropped). */
+/* Waits for the server's streams and releases it (jobs still admitted are dropped). */
 void gom_server_free(gom_server *s);
 
 #ifdef __cplusplus

@@ -1619,11 +1619,11 @@ extern "C" int gom_batch_state(gom_batch *b, int32_t index, gom_state **state) {
 
 // ------------------------------------------------------------------------------------------
 // Serving loop: jobs arrive at any time, are admitted first come first served while their
-// states fit in the server's arena, and advance together one chunk of generations per step.
-// Jobs that fit the resident schedule share the batched lockstep launches (each with its own
-// generation index, target and generation limit); the others run their own schedule on the
-// same stream.  A job's random numbers depend only on its seed, so its result does not
-// depend on what else is running.
+// states fit in the server's arena, and advance independently: each admitted job runs on one
+// of a few streams (the least loaded at admission), a chunk of generations at a time, and its
+// next chunk is enqueued as soon as the previous chunk's run scalars have reached the host.
+// Jobs on different streams overlap on the device.  A job's random numbers depend only on
+// its seed, so its result does not depend on what else is running.
 // ------------------------------------------------------------------------------------------
 namespace {
 
@@ -1637,31 +1637,10 @@ struct ServerJob {
     int rule = 0, order = 0;
     size_t bytes = 0, off = 0;
     gom_state *s = nullptr;
-    bool batched = false;
+    int lane = 0;
+    bool in_flight = false;   // a chunk and its snapshot are enqueued
     double submit_ms = 0.0, admit_ms = 0.0;
 };
-
-// Fixed-size tables of the batched launch, in the first bytes of the arena.
-struct ServerAux {
-    size_t insts = 0, snap = 0, blk = 0, vblk = 0, total = 0;
-};
-
-constexpr int32_t kServerMaxVBlocks = 544;  // vertex-pass blocks of the largest batched job
-
-ServerAux server_aux(int32_t max_jobs) {
-    ServerAux A;
-    size_t o = 0;
-    A.insts = o;
-    o = align_up(o + sizeof(BatchInst) * (size_t)max_jobs);
-    A.snap = o;
-    o = align_up(o + sizeof(DevState) * (size_t)max_jobs);
-    A.blk = o;
-    o = align_up(o + sizeof(int2) * (size_t)max_jobs * GOM_MAX_POP);
-    A.vblk = o;
-    o = align_up(o + sizeof(int32_t) * (size_t)max_jobs * kServerMaxVBlocks);
-    A.total = o;
-    return A;
-}
 
 }  // namespace
 
@@ -1669,18 +1648,13 @@ struct gom_server {
     char *arena = nullptr;
     size_t bytes = 0;
     int32_t max_jobs = 0, chunk = 4;
-    hipStream_t st = nullptr;
-    ServerAux A;
+    std::vector<hipStream_t> lanes;       // owned streams (default priority)
+    std::vector<int32_t> lane_jobs;
     std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
     std::deque<ServerJob> queue;
-    std::vector<ServerJob> active;        // batched jobs first after a rebuild
+    std::vector<ServerJob> active;
     std::vector<gom_job_result> done;
     int64_t next_id = 0;
-    bool dirty = true;
-    int32_t n_batched = 0;
-    int sweep_blocks = 0, vblocks = 0;
-    size_t lds = 0;
-    DevState *h_snap = nullptr;           // pinned, max_jobs
     std::chrono::steady_clock::time_point t0;
 
     double now_ms() const {
@@ -1717,30 +1691,38 @@ struct gom_server {
     }
 };
 
+extern "C" void gom_server_free(gom_server *sv) {
+    if (!sv) return;
+    for (hipStream_t q : sv->lanes) (void)hipStreamSynchronize(q);
+    for (ServerJob &J : sv->active) gom_state_free(J.s);
+    for (hipStream_t q : sv->lanes) (void)hipStreamDestroy(q);
+    delete sv;
+}
+
 extern "C" int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t max_jobs,
-                                 void *stream, gom_server **out) {
+                                 int32_t streams, gom_server **out) {
     GUARD_BEGIN
-    if (!dev_arena || !out || max_jobs < 1) return fail(GOM_E_ARG, "gom_server_create: bad arguments");
+    if (!dev_arena || !out || max_jobs < 1 || streams < 1 || streams > 16)
+        return fail(GOM_E_ARG, "gom_server_create: bad arguments");
     if ((reinterpret_cast<uintptr_t>(dev_arena) & 255) != 0)
         return fail(GOM_E_NOMEM, "gom_server_create: arena must be 256-byte aligned");
-    const ServerAux A = server_aux(max_jobs);
-    if (arena_bytes <= A.total)
-        return fail(GOM_E_NOMEM, "gom_server_create: arena has %zu bytes, the job tables alone "
-                    "need %zu", arena_bytes, A.total);
+    if (arena_bytes < 256) return fail(GOM_E_NOMEM, "gom_server_create: arena too small");
     auto *sv = new gom_server;
     sv->arena = (char *)dev_arena;
-    sv->bytes = arena_bytes;
+    sv->bytes = arena_bytes & ~(size_t)255;
     sv->max_jobs = max_jobs;
-    sv->st = (hipStream_t)stream;
-    sv->A = A;
-    sv->free_blocks[A.total] = arena_bytes - A.total;
+    sv->free_blocks[0] = sv->bytes;
     sv->t0 = std::chrono::steady_clock::now();
-    hipError_t e = hipHostMalloc((void **)&sv->h_snap, sizeof(DevState) * (size_t)max_jobs,
-                                 hipHostMallocDefault);
-    if (e != hipSuccess) {
-        delete sv;
-        return fail(GOM_E_DEVICE, "gom_server_create: %s", hipGetErrorString(e));
+    for (int32_t q = 0; q < streams; ++q) {
+        hipStream_t h = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&h, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            gom_server_free(sv);
+            return fail(GOM_E_DEVICE, "gom_server_create: %s", hipGetErrorString(e));
+        }
+        sv->lanes.push_back(h);
     }
+    sv->lane_jobs.assign((size_t)streams, 0);
     *out = sv;
     return GOM_OK;
     GUARD_END
@@ -1756,7 +1738,7 @@ extern "C" int gom_server_submit(gom_server *sv, const mc_graph *g, const gom_fo
     ServerJob J;
     int rc = gom_state_bytes(g, f, pop, &J.bytes);
     if (rc) return rc;
-    if (align_up(J.bytes) > sv->bytes - sv->A.total)
+    if (align_up(J.bytes) > sv->bytes)
         return fail(GOM_E_NOMEM, "gom_server_submit: the job needs %zu bytes, more than the "
                     "whole arena", J.bytes);
     if (neutral_rule != GOM_NEUTRAL_PAPER && neutral_rule != GOM_NEUTRAL_ALWAYS)
@@ -1781,64 +1763,19 @@ extern "C" int gom_server_submit(gom_server *sv, const mc_graph *g, const gom_fo
 
 namespace {
 
-// Final result of a job from its run scalars (a fresh state: generation 0 at admission).
-gom_job_result server_result(gom_server *sv, const ServerJob &J, const DevState &h) {
-    gom_job_result r{};
-    r.job = J.id;
-    r.generations = h.generation;
-    r.reached = h.elite_fitness >= J.target ? 1 : 0;
-    r.best = h.elite_fitness;
-    r.attempted = (int64_t)J.s->N * J.s->n_sets * (int64_t)h.generation;
-    r.evaluated = h.evaluated;
-    r.accepted = h.accepted;
-    r.submit_ms = J.submit_ms;
-    r.admit_ms = J.admit_ms;
-    r.done_ms = sv->now_ms();
-    return r;
-}
-
-// Tables of the batched launch for the active jobs (batched ones first); the stream must be
-// idle (no launch may still read the old tables).
-int server_rebuild(gom_server *sv) {
-    std::stable_partition(sv->active.begin(), sv->active.end(),
-                          [](const ServerJob &J) { return J.batched; });
-    std::vector<BatchInst> insts(sv->active.size());
-    std::vector<int2> blk;
-    std::vector<int32_t> vblk;
-    sv->n_batched = 0;
-    sv->lds = 0;
-    for (size_t b = 0; b < sv->active.size(); ++b) {
-        const ServerJob &J = sv->active[b];
-        gom_state *s = J.s;
-        BatchInst &I = insts[b];
-        I.res = resident_ctx(s, J.target);
-        I.epi = epilogue_args(s, J.target, true);
-        I.epi.gen_limit = J.max_gens;
-        I.kind = s->univariate ? 0 : 1;
-        I.order_fixed = s->order == GOM_ORDER_FIXED;
-        if (!J.batched) continue;
-        ++sv->n_batched;
-        const bool plds = kBatchOrderBytes + resident_lds_bytes(s->n, true) <= s->lds_max;
-        I.plds = plds ? 1 : 0;
-        I.vblock0 = (int32_t)vblk.size();
-        for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2((int)b, i));
-        for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back((int32_t)b);
-        sv->lds = std::max(sv->lds, kBatchOrderBytes + resident_lds_bytes(s->n, plds));
+// Enqueue the job's next chunk of generations and the copy of its run scalars.
+int server_issue(gom_server *sv, ServerJob &J) {
+    gom_state *s = J.s;
+    hipStream_t q = sv->lanes[(size_t)J.lane];
+    const int32_t n = std::min(sv->chunk, J.max_gens - s->g_host);
+    for (int32_t t = 0; t < n; ++t) {
+        int rc = enqueue_generation(s, s->g_host, J.target, q);
+        if (rc) return rc;
+        s->g_host++;
     }
-    sv->sweep_blocks = (int)blk.size();
-    sv->vblocks = (int)vblk.size();
-    hipStream_t st = sv->st;
-    if (!insts.empty())
-        HIP_TRY(hipMemcpyAsync(sv->arena + sv->A.insts, insts.data(),
-                               sizeof(BatchInst) * insts.size(), hipMemcpyHostToDevice, st));
-    if (!blk.empty())
-        HIP_TRY(hipMemcpyAsync(sv->arena + sv->A.blk, blk.data(), sizeof(int2) * blk.size(),
-                               hipMemcpyHostToDevice, st));
-    if (!vblk.empty())
-        HIP_TRY(hipMemcpyAsync(sv->arena + sv->A.vblk, vblk.data(),
-                               sizeof(int32_t) * vblk.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));  // the host tables die here
-    sv->dirty = false;
+    HIP_TRY(hipMemcpyAsync(&s->h_st[0], s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, q));
+    HIP_TRY(hipEventRecord(s->chunk_ev[0], q));
+    J.in_flight = true;
     return GOM_OK;
 }
 
@@ -1847,73 +1784,68 @@ int server_rebuild(gom_server *sv) {
 extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_queued) {
     GUARD_BEGIN
     if (!sv) return fail(GOM_E_ARG, "gom_server_step: null server");
-    hipStream_t st = sv->st;
     // admission, first come first served
     while (!sv->queue.empty() && (int32_t)sv->active.size() < sv->max_jobs) {
         ServerJob &J = sv->queue.front();
         size_t off = 0;
         if (!sv->alloc(J.bytes, &off)) break;
+        int lane = 0;
+        for (int q = 1; q < (int)sv->lanes.size(); ++q)
+            if (sv->lane_jobs[(size_t)q] < sv->lane_jobs[(size_t)lane]) lane = q;
         gom_state *s = nullptr;
         int rc = gom_state_init(J.g, J.f, J.pop, J.seed, J.rule, J.order, sv->arena + off,
-                                align_up(J.bytes), st, &s);
+                                align_up(J.bytes), sv->lanes[(size_t)lane], &s);
         if (rc) {
             sv->release(off, J.bytes);
             return rc;
         }
         J.s = s;
         J.off = off;
-        J.batched = s->resident_ok &&
-                    kBatchOrderBytes + resident_lds_bytes(s->n, false) <= s->lds_max &&
-                    (s->n + 255) / 256 <= kServerMaxVBlocks;
+        J.lane = lane;
+        sv->lane_jobs[(size_t)lane]++;
         J.admit_ms = sv->now_ms();
         sv->active.push_back(J);
         sv->queue.pop_front();
-        sv->dirty = true;
-    }
-    if (sv->dirty) {
-        int rc = server_rebuild(sv);
+        rc = server_issue(sv, sv->active.back());
         if (rc) return rc;
     }
-    const int32_t na = (int32_t)sv->active.size();
-    if (na > 0) {
-        BatchInst *d_insts = (BatchInst *)(sv->arena + sv->A.insts);
-        for (int32_t t = 0; t < sv->chunk; ++t) {
-            if (sv->n_batched > 0)
-                HIP_TRY(launch_batch_step(d_insts, sv->n_batched,
-                                          (const int2 *)(sv->arena + sv->A.blk), sv->sweep_blocks,
-                                          (const int32_t *)(sv->arena + sv->A.vblk),
-                                          sv->vblocks, sv->lds, st));
-            for (int32_t b = sv->n_batched; b < na; ++b) {
-                ServerJob &J = sv->active[(size_t)b];
-                if (J.s->g_host >= J.max_gens) continue;
-                int rc = enqueue_generation(J.s, J.s->g_host, J.target, st);
-                if (rc) return rc;
-                J.s->g_host++;
-            }
+    // progress: every job whose chunk has finished is retired or given its next chunk
+    std::vector<ServerJob> keep;
+    keep.reserve(sv->active.size());
+    for (ServerJob &J : sv->active) {
+        gom_state *s = J.s;
+        const hipError_t qe = hipEventQuery(s->chunk_ev[0]);
+        if (qe == hipErrorNotReady) {
+            keep.push_back(J);
+            continue;
         }
-        DevState *d_snap = (DevState *)(sv->arena + sv->A.snap);
-        HIP_TRY(launch_batch_gather(d_insts, na, d_snap, st));
-        HIP_TRY(hipMemcpyAsync(sv->h_snap, d_snap, sizeof(DevState) * (size_t)na,
-                               hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        std::vector<ServerJob> keep;
-        for (int32_t b = 0; b < na; ++b) {
-            ServerJob &J = sv->active[(size_t)b];
-            const DevState &h = sv->h_snap[b];
-            if (h.elite_fitness < J.target && h.generation < J.max_gens) {
-                keep.push_back(J);
-                continue;
-            }
-            gom_job_result r = server_result(sv, J, h);
-            int rc = gom_state_hash(J.s, st, &r.hash);
+        HIP_TRY(qe);
+        const DevState h = s->h_st[0];
+        if (h.elite_fitness < J.target && h.generation < J.max_gens) {
+            int rc = server_issue(sv, J);
             if (rc) return rc;
-            sv->done.push_back(r);
-            gom_state_free(J.s);
-            sv->release(J.off, J.bytes);
-            sv->dirty = true;
+            keep.push_back(J);
+            continue;
         }
-        sv->active.swap(keep);
+        gom_job_result r{};
+        r.job = J.id;
+        r.generations = h.generation;
+        r.reached = h.elite_fitness >= J.target ? 1 : 0;
+        r.best = h.elite_fitness;
+        r.attempted = (int64_t)s->N * s->n_sets * (int64_t)h.generation;
+        r.evaluated = h.evaluated;
+        r.accepted = h.accepted;
+        r.submit_ms = J.submit_ms;
+        r.admit_ms = J.admit_ms;
+        r.done_ms = sv->now_ms();
+        int rc = gom_state_hash(s, sv->lanes[(size_t)J.lane], &r.hash);
+        if (rc) return rc;
+        sv->done.push_back(r);
+        gom_state_free(s);
+        sv->release(J.off, J.bytes);
+        sv->lane_jobs[(size_t)J.lane]--;
     }
+    sv->active.swap(keep);
     if (n_active) *n_active = (int32_t)sv->active.size();
     if (n_queued) *n_queued = (int32_t)sv->queue.size();
     return GOM_OK;
@@ -1931,27 +1863,15 @@ extern "C" int gom_server_results(gom_server *sv, gom_job_result *out, int32_t c
 }
 
 extern "C" int gom_server_info(const gom_server *sv, int32_t *n_active, int32_t *n_queued,
-                               int32_t *n_batched, size_t *free_bytes) {
+                               int32_t *n_streams, size_t *free_bytes) {
     if (!sv) return fail(GOM_E_ARG, "gom_server_info: null server");
     if (n_active) *n_active = (int32_t)sv->active.size();
     if (n_queued) *n_queued = (int32_t)sv->queue.size();
-    if (n_batched) {
-        int32_t c = 0;
-        for (const ServerJob &J : sv->active) c += J.batched;
-        *n_batched = c;
-    }
+    if (n_streams) *n_streams = (int32_t)sv->lanes.size();
     if (free_bytes) {
         size_t t = 0;
         for (const auto &kv : sv->free_blocks) t += kv.second;
         *free_bytes = t;
     }
     return GOM_OK;
-}
-
-extern "C" void gom_server_free(gom_server *sv) {
-    if (!sv) return;
-    if (sv->st) (void)hipStreamSynchronize(sv->st);
-    for (ServerJob &J : sv->active) gom_state_free(J.s);
-    if (sv->h_snap) (void)hipHostFree(sv->h_snap);
-    delete sv;
 }

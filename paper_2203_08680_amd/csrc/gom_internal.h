@@ -117,7 +117,6 @@ struct EpilogueArgs {
     int32_t N;
     int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh flags only
     int32_t row_words;      // words per row, ceil(n / 64)
-    int32_t gen_limit = INT32_MAX;  // batched runs: no generation once this many have run
 };
 
 enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };

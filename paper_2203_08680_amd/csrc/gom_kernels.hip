@@ -781,7 +781,7 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     DevState *st = a.st;
     const int t = threadIdx.x;
     const int64_t fE = st->elite_fitness;
-    if (a.mode == kEpiGeneration && (fE >= a.target || st->generation >= a.gen_limit)) {
+    if (a.mode == kEpiGeneration && fE >= a.target) {
         if (t == 0) st->active = 0;
         return;
     }
@@ -905,7 +905,6 @@ __global__ __launch_bounds__(kResidentThreads) void k_batch_sweep(const BatchIns
     const ResidentCtx a = I->res;
     if (a.st->elite_fitness >= a.target) return;
     const int gen = a.st->generation;
-    if (gen >= I->epi.gen_limit) return;
     const bool fixed = I->order_fixed != 0;
     for (int t = threadIdx.x; t < a.k; t += kResidentThreads) {
         order[t] = (uint16_t)t;

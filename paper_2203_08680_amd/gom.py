@@ -109,7 +109,7 @@ def lib() -> C.CDLL:
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_batch_free": (None, [_vp]),
-        "gom_server_create": (C.c_int, [_vp, _sz, _i32, _vp, _P(_vp)]),
+        "gom_server_create": (C.c_int, [_vp, _sz, _i32, _i32, _P(_vp)]),
         "gom_server_submit": (C.c_int, [_vp, _vp, _vp, _i32, _u64, _i64, _i32, C.c_int, C.c_int,
                                         _P(_i64)]),
         "gom_server_step": (C.c_int, [_vp, _P(_i32), _P(_i32)]),
@@ -515,16 +515,17 @@ class GomServer:
     """Owned gom_server handle, its device arena (a torch tensor) and the instances of the
     jobs submitted to it (kept alive until their results have been taken)."""
 
-    def __init__(self, arena_bytes: int, max_jobs: int = 256, device=None, stream=None):
+    def __init__(self, arena_bytes: int, max_jobs: int = 256, streams: int = 4, device=None):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
         self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
         off = (-self.arena.data_ptr()) % 256
-        self._stream = _stream_handle(stream)
         self._jobs = {}
         h = _vp()
-        _check(lib().gom_server_create(self.arena.data_ptr() + off, int(arena_bytes),
-                                       int(max_jobs), self._stream, C.byref(h)))
+        torch.cuda.synchronize(dev)  # the arena's allocation is ordered before the server's work
+        with torch.cuda.device(dev):
+            _check(lib().gom_server_create(self.arena.data_ptr() + off, int(arena_bytes),
+                                           int(max_jobs), int(streams), C.byref(h)))
         self.handle = h.value
 
     def __del__(self):
@@ -547,7 +548,8 @@ class GomServer:
         return j.value
 
     def step(self):
-        """Admit, run a chunk of generations, retire; returns (active, queued)."""
+        """Admit what fits, retire or continue finished chunks; returns (active, queued)
+        without waiting for running chunks."""
         a, q = _i32(), _i32()
         _check(lib().gom_server_step(self.handle, C.byref(a), C.byref(q)))
         return a.value, q.value
@@ -569,5 +571,5 @@ class GomServer:
         a, q, b, fb = _i32(), _i32(), _i32(), _sz()
         _check(lib().gom_server_info(self.handle, C.byref(a), C.byref(q), C.byref(b),
                                      C.byref(fb)))
-        return {"active": a.value, "queued": q.value, "batched": b.value,
+        return {"active": a.value, "queued": q.value, "streams": b.value,
                 "free_bytes": fb.value}

@@ -188,3 +188,47 @@ def batch_mix(count: int = 256, seed: int = 4, n_lo: float = 1e3, n_hi: float = 
                                     w_lo=1, w_hi=100)
             items.append(BatchItem(g, fos, pop, 1 + k, False))
     return items
+
+
+@dataclass(frozen=True)
+class ServeJob:
+    graph: Graph
+    fos: int
+    pop: int
+    seed: int
+    target: int           # total weight for tori (their optimum), else unreachable
+    max_gens: int
+
+
+def serve_stream(count: int = 200, seed: int = 5, max_gens: int = 1000,
+                 sizes=("small", "medium", "large")):
+    """Jobs of the serving workload: L x L tori with L in {100, 316, 1000} or configuration-
+    model graphs with n in {10^4, 10^5, 10^6} and degree uniform in {4..8}, weights uniform in
+    [1, 100], population 64; univariate and neighbourhood FOS alternate; tori run to their
+    total weight (their optimum), the others to the generation limit.  `sizes` restricts the
+    three size classes (small = 10^4 vertices, medium = 10^5, large = 10^6)."""
+    rng = np.random.default_rng(seed)
+    side = {"small": 100, "medium": 316, "large": 1000}
+    verts = {"small": 10_000, "medium": 100_000, "large": 1_000_000}
+    jobs = []
+    for k in range(count):
+        size = sizes[int(rng.integers(0, len(sizes)))]
+        fos = k % 2
+        gseed = 20_000 + k
+        if rng.integers(0, 2) == 0:
+            g = torus(side[size], 1, 100, seed=gseed)
+            target = g.total_weight
+        else:
+            d = int(rng.integers(4, 9))
+            n = verts[size]
+            g = configuration_model(n + (n * d) % 2, d, seed=gseed, weights="uniform",
+                                    w_lo=1, w_hi=100)
+            target = 1 << 62
+        jobs.append(ServeJob(g, fos, 64, 1000 + k, target, max_gens))
+    return jobs
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed + 1)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
