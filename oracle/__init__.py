@@ -16,7 +16,7 @@ _lib = None
 
 NEUTRAL_PAPER, NEUTRAL_ALWAYS = 0, 1
 ORDER_RANDOM, ORDER_FIXED = 0, 1
-FLAG_DEBUG, FLAG_REVERSE = 1, 2
+FLAG_DEBUG, FLAG_REVERSE, FLAG_FI = 1, 2, 4
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")

@@ -437,7 +437,7 @@ int32_t or_linkage_tree(int32_t n, int64_t m, const int32_t *eu, const int32_t *
  * ---------------------------------------------------------------------------------------- */
 enum { OR_NEUTRAL_PAPER = 0, OR_NEUTRAL_ALWAYS = 1 };
 enum { OR_ORDER_RANDOM = 0, OR_ORDER_FIXED = 1 };
-enum { OR_FLAG_DEBUG = 1, OR_FLAG_REVERSE = 2 };
+enum { OR_FLAG_DEBUG = 1, OR_FLAG_REVERSE = 2, OR_FLAG_FI = 4 };
 
 typedef struct or_state {
     or_graph g;
@@ -448,7 +448,7 @@ typedef struct or_state {
     int32_t N;
     uint64_t seed, donor_seed;
     int rule, order, flags;
-    uint8_t *P, *O, *E, *eq;
+    uint8_t *P, *O, *E, *eq, *acc_any;
     int64_t *f, fE;
     int32_t gen;
     int32_t open_next;        /* -1, or the next class position of an unfinished generation */
@@ -464,7 +464,7 @@ void or_free(or_state *s) {
     if (!s) return;
     graph_free(&s->g);
     free(s->set_ptr); free(s->set_vars); free(s->class_ptr); free(s->class_elems);
-    free(s->P); free(s->O); free(s->E); free(s->eq); free(s->f);
+    free(s->P); free(s->O); free(s->E); free(s->eq); free(s->acc_any); free(s->f);
     free(s->donors); free(s->perm); free(s->vstamp); free(s->estamp);
     free(s);
 }
@@ -506,13 +506,14 @@ or_state *or_new(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, con
     s->O = malloc(genes);
     s->E = malloc((size_t)n);
     s->eq = malloc((size_t)pop);
+    s->acc_any = calloc((size_t)pop, 1);
     s->f = malloc(sizeof(int64_t) * (size_t)pop);
     s->donors = malloc(sizeof(int32_t) * (size_t)pop);
     s->vstamp = malloc(sizeof(int32_t) * (size_t)n);
     s->estamp = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
     int32_t *colour = malloc(sizeof(int32_t) * (size_t)nsets);
-    if (!s->P || !s->O || !s->E || !s->eq || !s->f || !s->donors || !s->vstamp || !s->estamp ||
-        !colour) { free(colour); or_free(s); return NULL; }
+    if (!s->P || !s->O || !s->E || !s->eq || !s->acc_any || !s->f || !s->donors ||
+        !s->vstamp || !s->estamp || !colour) { free(colour); or_free(s); return NULL; }
     for (int32_t v = 0; v < n; ++v) s->vstamp[v] = -1;
     for (int64_t e = 0; e < m; ++e) s->estamp[e] = -1;
     s->stamp = 0;
@@ -549,6 +550,49 @@ or_state *or_new(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, con
 }
 
 /* One GOM step (Algorithm 2) for solution i and set j at position p of class c. */
+/* Insert donor genes D[F_j] into O_i when the partial evaluation (Section 2.2, Algorithm 4)
+   allows it: every subfunction (edge) that depends on a variable of F_j is evaluated before
+   and after the insertion.  Accepts improvements, and equal fitness unless P_i equals the
+   elitist (or always, under the ALWAYS rule).  *delta receives the change; returns whether
+   the step was accepted. */
+static int try_insert(or_state *s, int32_t i, int32_t j, const uint8_t *D, int64_t *delta_out) {
+    const int32_t n = s->g.n;
+    uint8_t *Oi = s->O + (size_t)i * n;
+    const int32_t *F = s->set_vars + s->set_ptr[j];
+    const int32_t sz = s->set_ptr[j + 1] - s->set_ptr[j];
+    int32_t tag = ++s->stamp;
+    for (int32_t q = 0; q < sz; ++q) s->vstamp[F[q]] = tag;
+    int64_t delta = 0;
+    for (int32_t q = 0; q < sz; ++q) {
+        int32_t u = F[q];
+        for (int64_t t = s->g.inc_ptr[u]; t < s->g.inc_ptr[u + 1]; ++t) {
+            int64_t e = s->g.inc[t];
+            if (s->estamp[e] == tag) continue;
+            s->estamp[e] = tag;
+            int32_t a = s->g.eu[e], b = s->g.ev[e];
+            uint8_t xa = Oi[a], xb = Oi[b];
+            uint8_t ya = s->vstamp[a] == tag ? D[a] : xa;
+            uint8_t yb = s->vstamp[b] == tag ? D[b] : xb;
+            int64_t before = xa != xb ? s->g.ew[e] : 0;
+            int64_t after = ya != yb ? s->g.ew[e] : 0;
+            delta += after - before;
+        }
+    }
+    int accept = delta > 0 || (delta == 0 && (s->rule == OR_NEUTRAL_ALWAYS || !s->eq[i]));
+    if (accept) {
+        for (int32_t q = 0; q < sz; ++q) Oi[F[q]] = D[F[q]];
+        s->f[i] += delta;
+        s->accepted++;
+    }
+    if (s->flags & OR_FLAG_DEBUG) {
+        int64_t full = or_maxcut(n, s->g.m, s->g.eu, s->g.ev, s->g.ew, Oi);
+        if (full != s->f[i]) s->debug_mismatches++;
+    }
+    *delta_out = delta;
+    return accept;
+}
+
+/* One GOM step (Algorithm 2) for solution i and set j at position p of class c. */
 static void gom_step(or_state *s, int32_t c, int32_t p, int32_t j, int32_t i) {
     const int32_t n = s->g.n;
     uint8_t *Oi = s->O + (size_t)i * n;
@@ -573,39 +617,41 @@ static void gom_step(or_state *s, int32_t c, int32_t p, int32_t j, int32_t i) {
     draw4(s->donor_seed, (uint32_t)s->gen, (uint32_t)c, (uint32_t)i, (uint32_t)(p >> 3), out);
     uint32_t h = (out[(p & 7) >> 1] >> (16 * (p & 1))) & 0xFFFFu;
     int32_t d = s->donors[((uint64_t)h * (uint64_t)nd) >> 16];
-    const uint8_t *Pd = s->P + (size_t)d * n;
+    int64_t delta;
+    if (try_insert(s, i, j, s->P + (size_t)d * n, &delta)) s->acc_any[i] = 1;
+}
 
-    /* Partial evaluation (Section 2.2, Algorithm 4): every subfunction (edge) that depends on
-       a variable of F_j is evaluated before and after inserting the donor genes. */
-    int32_t tag = ++s->stamp;
-    for (int32_t q = 0; q < sz; ++q) s->vstamp[F[q]] = tag;
-    int64_t delta = 0;
-    for (int32_t q = 0; q < sz; ++q) {
-        int32_t u = F[q];
-        for (int64_t t = s->g.inc_ptr[u]; t < s->g.inc_ptr[u + 1]; ++t) {
-            int64_t e = s->g.inc[t];
-            if (s->estamp[e] == tag) continue;
-            s->estamp[e] = tag;
-            int32_t a = s->g.eu[e], b = s->g.ev[e];
-            uint8_t xa = Oi[a], xb = Oi[b];
-            uint8_t ya = s->vstamp[a] == tag ? Pd[a] : xa;
-            uint8_t yb = s->vstamp[b] == tag ? Pd[b] : xb;
-            int64_t before = xa != xb ? s->g.ew[e] : 0;
-            int64_t after = ya != yb ? s->g.ew[e] : 0;
-            delta += after - before;
+/* Forced improvement, in a form that runs class by class (Section 4 describes the serial
+   procedure; Section 5.4 leaves a parallel form open).  For every solution that had no
+   accepted GOM step in this generation: GOM steps with the elitist (of the generation start)
+   as the donor, over the classes in the generation's order, all sets of a class together;
+   the solution stops after the first class in which a step raised its fitness.  A solution
+   that never improved becomes a copy of the elitist.  With one set per class this is the
+   serial procedure visiting the sets in class order. */
+static void forced_improvement(or_state *s) {
+    const int32_t n = s->g.n;
+    for (int32_t i = 0; i < s->N; ++i) {
+        if (s->acc_any[i]) continue;
+        int improved = 0;
+        for (int32_t t = 0; t < s->k && !improved; ++t) {
+            int32_t c = s->perm[t];
+            for (int32_t q = s->class_ptr[c]; q < s->class_ptr[c + 1]; ++q) {
+                int32_t j = s->class_elems[q];
+                const int32_t *F = s->set_vars + s->set_ptr[j];
+                const int32_t sz = s->set_ptr[j + 1] - s->set_ptr[j];
+                const uint8_t *Oi = s->O + (size_t)i * n;
+                int differs = 0;
+                for (int32_t r = 0; r < sz; ++r) differs |= s->E[F[r]] != Oi[F[r]];
+                if (!differs) continue;
+                s->evaluated++;
+                int64_t delta;
+                if (try_insert(s, i, j, s->E, &delta) && delta > 0) improved = 1;
+            }
         }
-    }
-
-    /* Accept improvements; accept equal fitness unless P_i equals the elitist. */
-    int accept = delta > 0 || (delta == 0 && (s->rule == OR_NEUTRAL_ALWAYS || !s->eq[i]));
-    if (accept) {
-        for (int32_t q = 0; q < sz; ++q) Oi[F[q]] = Pd[F[q]];
-        s->f[i] += delta;
-        s->accepted++;
-    }
-    if (s->flags & OR_FLAG_DEBUG) {
-        int64_t full = or_maxcut(n, s->g.m, s->g.eu, s->g.ev, s->g.ew, Oi);
-        if (full != s->f[i]) s->debug_mismatches++;
+        if (!improved) {
+            memcpy(s->O + (size_t)i * n, s->E, (size_t)n);
+            s->f[i] = s->fE;
+        }
     }
 }
 
@@ -618,7 +664,8 @@ static void gom_step(or_state *s, int32_t c, int32_t p, int32_t j, int32_t i) {
  *    Fisher-Yates shuffle (FIXED order: ascending class index);
  *  - within a group, every (solution, set) pair is one GOM step; the groups' independence
  *    makes their order irrelevant (the REVERSE flag visits them backwards to check that);
- *  - no forced improvement (Section 5.4);
+ *  - no forced improvement (Section 5.4) unless the FI flag asks for the class-by-class form
+ *    of forced_improvement, run after the groups;
  *  - after the groups, P <- O and the elitist is replaced when the best solution (lowest index
  *    on ties) is strictly better.
  */
@@ -640,6 +687,7 @@ static void begin_generation(or_state *s) {
         }
 
     memcpy(s->O, s->P, (size_t)N * n);
+    memset(s->acc_any, 0, (size_t)N);
     s->open_next = 0;
 }
 
@@ -675,6 +723,7 @@ static void end_generation(or_state *s) {
 void or_generation(or_state *s) {
     if (s->open_next < 0) begin_generation(s);
     for (int32_t t = s->open_next; t < s->k; ++t) run_class(s, t);
+    if (s->flags & OR_FLAG_FI) forced_improvement(s);
     end_generation(s);
 }
 

@@ -36,7 +36,11 @@ def initial_population(n, N, seed):
 
 
 class LiteralParGomea:
-    def __init__(self, g, set_ptr, set_vars, classes, N, seed, rule=0, order=0, P=None):
+    def __init__(self, g, set_ptr, set_vars, classes, N, seed, rule=0, order=0, P=None,
+                 fi=False, fi_stop_on_accept=False):
+        self.fi = fi
+        self.fi_stop_on_accept = fi_stop_on_accept  # a wrong reading, kept to find cases
+        # where it differs from the paper's (stop at the first step that raises fitness)
         self.g = g
         self.sets = [np.asarray(set_vars[set_ptr[j]:set_ptr[j + 1]]) for j in
                      range(len(set_ptr) - 1)]
@@ -78,7 +82,9 @@ class LiteralParGomea:
         N, g = self.N, self.g
         eq = np.array([np.array_equal(self.P[i], self.E) for i in range(N)])
         O = self.P.copy()                                        # Clone(P)
-        for t, c in enumerate(self.group_order()):
+        improved_any = np.zeros(N, dtype=bool)
+        order = self.group_order()
+        for t, c in enumerate(order):
             G = self.classes[c]
             # DetermineAndInsertDonorGenes
             Op = O.copy()
@@ -124,10 +130,46 @@ class LiteralParGomea:
                         self.f[i] += delta[p, i]
             self.evaluated += int(has.sum())
             self.accepted += int(M.sum())
+            improved_any |= M.any(axis=0)
             if t == stop_after:
                 self.mid = (O.copy(), self.f.copy(), self.evaluated, self.accepted)
+        if self.fi:
+            self.forced_improvement(O, eq, improved_any, order)
         self.P = O                                               # P <- O
         b = int(np.argmax(self.f))
         if self.f[b] > self.fE:
             self.E, self.fE = self.P[b].copy(), int(self.f[b])
         self.gen += 1
+
+    def forced_improvement(self, O, eq, improved_any, order):
+        """ApplyForcedImprovement as the paper describes the serial procedure (Section 4): a
+        solution with no accepted variation in this generation undergoes GOM with the
+        elitist as donor, set after set (here in the generation's group order, sets of a
+        group ascending); the first step that raises its fitness ends the procedure; if none
+        does, a copy of the elitist takes its place."""
+        for i in range(self.N):
+            if improved_any[i]:
+                continue
+            done = False
+            for c in order:
+                for j in self.classes[c]:
+                    F = self.sets[j]
+                    if np.array_equal(O[i, F], self.E[F]):
+                        continue
+                    self.evaluated += 1
+                    trial = O[i].copy()
+                    trial[F] = self.E[F]
+                    delta = self.fitness(trial) - self.fitness(O[i])
+                    if delta > 0 or (delta == 0 and (self.rule == 1 or not eq[i])):
+                        O[i] = trial
+                        self.f[i] += delta
+                        self.accepted += 1
+                    if delta > 0 or (self.fi_stop_on_accept and delta == 0 and
+                                     (self.rule == 1 or not eq[i])):
+                        done = True
+                        break
+                if done:
+                    break
+            if not done:
+                O[i] = self.E
+                self.f[i] = self.fE

@@ -466,6 +466,111 @@ def test_linkage_tree_is_upgma(maker, bound):
     _check_upgma(g, ptr, vars_, bound)
 
 
+def _complete_graph(n, seed, unit=False):
+    """K_n with weights +-U{1..9} (or all 1): with univariate sets every pair of sets is
+    dependent, so every colour class holds a single set.  With unit weights and n odd a flip
+    often leaves the cut unchanged, so neutral steps occur."""
+    rng = np.random.default_rng(seed)
+    e = np.array([(a, b) for a in range(n) for b in range(a + 1, n)])
+    w = np.ones(e.shape[0], np.int64) if unit else workloads.signed_uniform(rng, e.shape[0], 9)
+    return workloads.from_edges(n, e, w)
+
+
+def _overlapping_sets(n):
+    """Singletons, cyclic pairs and triples: on a complete graph all of them conflict."""
+    sets = [[u] for u in range(n)] + [sorted([u, (u + 1) % n]) for u in range(n)] + \
+        [sorted([u, (u + 2) % n, (u + 3) % n]) for u in range(0, n, 2)]
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(x) for x in sets])
+    return ptr, np.concatenate([np.asarray(x, np.int32) for x in sets])
+
+
+@pytest.mark.parametrize("n,seed", [(6, 6), (6, 10), (8, 38), (8, 42)])
+def test_forced_improvement_stops_at_improvement_not_at_acceptance(n, seed):
+    """Instances (complete graphs with weights +-1 and overlapping sets, one set per class)
+    on which a neutral accepted step precedes the first improving one during forced
+    improvement: stopping at the first accepted step would give a different population.  The
+    oracle follows the paper's rule (stop at the first step that raises fitness)."""
+    rng = np.random.default_rng(seed)
+    e = np.array([(a, b) for a in range(n) for b in range(a + 1, n)])
+    g = workloads.from_edges(n, e, rng.choice([-1, 1], size=e.shape[0]))
+    ptr, vars_ = _overlapping_sets(n)
+    pop = 4 + seed % 3
+    run = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, flags=oracle.FLAG_FI)
+    cp, ce = run.classes()
+    assert np.all(np.diff(cp) == 1)
+    classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(len(cp) - 1)]
+    lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=seed, fi=True)
+    wrong = LiteralParGomea(g, ptr, vars_, classes, pop, seed=seed, fi=True,
+                            fi_stop_on_accept=True)
+    readings_differ = False
+    for gen in range(10):
+        run.generation()
+        lit.generation()
+        wrong.generation()
+        s = run.state()
+        assert np.array_equal(s["genes"], lit.P), gen
+        assert s["fitness"].tolist() == lit.f.tolist(), gen
+        assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted), gen
+        readings_differ |= not np.array_equal(lit.P, wrong.P)
+    assert readings_differ
+
+
+@pytest.mark.parametrize("n,pop,rule,seed", [(7, 5, 0, 1), (8, 6, 1, 2), (9, 4, 0, 3),
+                                             (6, 8, 0, 4)])
+def test_forced_improvement_equals_serial_with_one_set_per_class(n, pop, rule, seed):
+    """With one set per class, the class-by-class forced improvement is the serial procedure
+    of Section 4 (the literal reading stops at the first improving step)."""
+    g = _complete_graph(n, seed)
+    ptr, vars_ = oracle.fos(g, 0)
+    run = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule, flags=oracle.FLAG_FI)
+    cp, ce = run.classes()
+    assert np.all(np.diff(cp) == 1)
+    classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(len(cp) - 1)]
+    lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=seed, rule=rule, fi=True)
+    plain = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule)
+    differs = False
+    for gen in range(8):
+        run.generation()
+        lit.generation()
+        plain.generation()
+        s = run.state()
+        assert np.array_equal(s["genes"], lit.P), gen
+        assert s["fitness"].tolist() == lit.f.tolist(), gen
+        assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted), gen
+        assert np.array_equal(s["elite"], lit.E) and s["elite_fitness"] == lit.fE
+        differs |= not np.array_equal(s["genes"], plain.state()["genes"])
+    assert differs, "forced improvement never changed anything"
+
+
+@pytest.mark.parametrize("n,d,kind,pop", [(40, 3, 1, 10), (60, 4, 0, 12), (50, 5, 1, 7)])
+def test_forced_improvement_invariants(n, d, kind, pop):
+    """On graphs with several sets per class: full re-evaluation agrees with every partial
+    delta (debug flag), fitness never falls, and each solution that made no accepted GOM step
+    ends either fitter than it started or equal to the elitist."""
+    g = workloads.configuration_model(n, d, seed=n + d, weights="signed50")
+    ptr, vars_ = oracle.fos(g, kind)
+    run = oracle.Run(g, ptr, vars_, pop=pop, seed=5, flags=oracle.FLAG_FI | oracle.FLAG_DEBUG)
+    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=5)
+    for gen in range(10):
+        s0 = run.state()
+        ref.set_state(s0["genes"], s0["elite"], s0["elite_fitness"], s0["generation"],
+                      [s0["attempted"], s0["evaluated"], s0["accepted"]])
+        ref.generation()
+        run.generation()
+        s1, r1 = run.state(), ref.state()
+        assert s1["debug_mismatches"] == 0
+        assert np.all(s1["fitness"] >= s0["fitness"]), gen
+        for i in range(pop):
+            if r1["fitness"][i] == s0["fitness"][i] and \
+                    np.array_equal(r1["genes"][i], s0["genes"][i]):
+                # no accepted step without FI (same draws), so FI ran for solution i
+                assert s1["fitness"][i] > s0["fitness"][i] or \
+                    np.array_equal(s1["genes"][i], s0["elite"]), (gen, i)
+            else:
+                assert np.array_equal(s1["genes"][i], r1["genes"][i]), (gen, i)
+
+
 def test_initial_population_rule():
     g = workloads.torus(12, 1, 3, seed=2)
     ptr, vars_ = oracle.fos(g, 0)
