@@ -92,12 +92,12 @@ def class_sweep_bytes(csr, set_ptr, set_vars, class_ptr, class_elems, pop):
     return np.array(out)
 
 
-def cpu_baseline(g, fos_kind, pop, gens, target):
+def cpu_baseline(g, fos_kind, pop, gens, target, fi=False):
     """The oracle, unchanged, on seed 1's first `gens` generations of the same workload; the
     oracle builds its own FOS (and colouring) from the graph."""
     import oracle
     set_ptr, set_vars = oracle.fos(g, fos_kind)
-    run = oracle.Run(g, set_ptr, set_vars, pop=pop, seed=1)
+    run = oracle.Run(g, set_ptr, set_vars, pop=pop, seed=1, flags=oracle.FLAG_FI if fi else 0)
     t0 = time.perf_counter()
     ran = run.run(target, gens)
     dt = time.perf_counter() - t0
@@ -312,6 +312,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
+    ap.add_argument("--fi", action="store_true",
+                    help="forced improvement after each generation's classes")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB (a known "
                          "byte count for scaling profiler traffic counters)")
@@ -350,6 +352,8 @@ def main():
     inst = gom.Instance(g.n, g.u, g.v, g.w, wl.fos,
                         lt_bound=wl.lt_bound if wl.fos == 2 else None)
     st = inst.state(pop=wl.pop, seed=1000)
+    if args.fi:
+        gom.gom_state_set_fi(st, True)
     if args.schedule == "tuned":
         gom.gom_state_autotune(st, 3)
     else:
@@ -448,7 +452,8 @@ def main():
             log("cpu baseline: not run (the oracle's dense linkage-tree build does not scale "
                 "to this size)")
         else:
-            cpu = cpu_baseline(g, wl.fos, wl.pop, min(args.cpu_gens, max_gens), target)
+            cpu = cpu_baseline(g, wl.fos, wl.pop, min(args.cpu_gens, max_gens), target,
+                               fi=args.fi)
             log(f"cpu baseline: {cpu}")
 
     line = {
@@ -463,7 +468,8 @@ def main():
                    "pop": wl.pop, "max_generations": max_gens,
                    "target": target if wl.to_total_weight else None,
                    "classes": info["n_classes"], "seeds": list(range(1, args.steps + 1)),
-                   "mode": "plain", "schedule": sched_name},
+                   "mode": "plain", "schedule": sched_name,
+                   "forced_improvement": bool(args.fi)},
         "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,
         "reached": len(tto), "generations_total": gens,
         "us_per_generation": total * 1e6 / max(gens, 1),

@@ -273,6 +273,20 @@ int gom_state_set_schedule(gom_state *s, int schedule);
 int gom_state_get_schedule(const gom_state *s, int *schedule);
 
 /*
+ * Forced improvement (Section 4 describes the serial procedure; Section 5.4 leaves a parallel
+ * form open), off by default as in the paper's parallel GOMEA.  When on, after each
+ * generation's classes every solution that had no accepted GOM step takes GOM steps with the
+ * elitist (of the generation start) as donor, class by class in the generation's order, all
+ * sets of a class together; it stops after the first class in which its fitness rose, and is
+ * replaced by a copy of the elitist if it never did.  With one set per class this is the
+ * serial procedure.  These steps count in `evaluated` and `accepted` (not in `attempted`).
+ * The bit-sliced schedule has no forced improvement: turning it on moves a bit-sliced state
+ * to the automatic choice among the others.  GOM_E_STATE while a generation is open.
+ */
+int gom_state_set_fi(gom_state *s, int enabled);
+int gom_state_get_fi(const gom_state *s, int *enabled);
+
+/*
  * Autotuner: runs `trial_generations` generations under each schedule this instance allows
  * (class launch, resident, bit-sliced), timing each with HIP events on `stream`, and keeps the
  * fastest.  The trial generations are ordinary generations of the run (every schedule gives

@@ -254,6 +254,7 @@ struct gom_state {
     size_t lds_max = 0;                  // LDS bytes a block may use on the device
     bool bitsliced_ok = false;           // bit-sliced schedule fits the instance
     bool partition = false;              // every variable in exactly one set
+    bool fi = false;                     // forced improvement after each generation's classes
     int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
     int32_t *d_roff = nullptr, *d_recs = nullptr;
     int2 *d_crec = nullptr;
@@ -766,6 +767,8 @@ static ResidentCtx resident_ctx(const gom_state *s, int64_t target) {
     r.k = s->k;
     r.always = s->rule == GOM_NEUTRAL_ALWAYS;
     r.row_words = (s->n + 63) / 64;
+    r.fi = s->fi ? 1 : 0;
+    r.E = s->d_E;
     return r;
 }
 
@@ -783,6 +786,7 @@ static EpilogueArgs epilogue_args(const gom_state *s, int64_t target, bool rows)
     e.N = s->N;
     e.mode = kEpiGeneration;
     e.row_words = (s->n + 63) / 64;
+    e.fi = s->fi ? 1 : 0;
     return e;
 }
 
@@ -794,8 +798,11 @@ static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool r
 // Class sweeps for order positions [t0, t1) of generation `gen` under the per-class schedules
 // (bit-sliced when chosen, else class launch).
 static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, int32_t gen,
-                               int32_t t0, int32_t t1, int64_t target, hipStream_t st) {
+                               int32_t t0, int32_t t1, int64_t target, hipStream_t st,
+                               bool forced = false) {
     SweepArgs a{};
+    a.mode = forced ? kSweepFi : (s->fi ? kSweepGomTrack : kSweepGom);
+    a.E = s->d_E;
     a.P = s->d_P;
     a.O = s->d_O;
     a.stripes = s->d_stripes;
@@ -815,9 +822,9 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         a.rstride = s->class_rec[c].y;
         a.csize = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
         KernelEvents ev;
-        int rc = timing_events(s, &ev);
+        int rc = forced ? GOM_OK : timing_events(s, &ev);
         if (rc) return rc;
-        if (s->sched == GOM_SCHED_BITSLICED)
+        if (s->sched == GOM_SCHED_BITSLICED && !forced)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st, ev));
         else
             HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st, ev));
@@ -831,6 +838,7 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         // finish a generation left open by gom_debug_stop_after_class; its offspring are in
         // the O planes, so the rest runs class by class
         int rc = enqueue_class_range(s, perm, gen, s->open_next, s->k, target, st);
+        if (rc == GOM_OK && s->fi) rc = enqueue_class_range(s, perm, gen, 0, s->k, target, st, true);
         if (rc) return rc;
         s->open_next = -1;
         return enqueue_epilogue(s, target, st, false);
@@ -847,6 +855,8 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         return enqueue_epilogue(s, target, st, true);
     }
     int rc = enqueue_class_range(s, perm, gen, 0, s->k, target, st);
+    // forced improvement: the classes again, with the elitist as donor
+    if (rc == GOM_OK && s->fi) rc = enqueue_class_range(s, perm, gen, 0, s->k, target, st, true);
     if (rc) return rc;
     return enqueue_epilogue(s, target, st, false);
 }
@@ -881,7 +891,7 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
 
 static int auto_schedule(const gom_state *s) {
     if (s->resident_ok) return GOM_SCHED_RESIDENT;
-    if (s->bitsliced_ok) return GOM_SCHED_BITSLICED;
+    if (s->bitsliced_ok && !s->fi) return GOM_SCHED_BITSLICED;
     return GOM_SCHED_CLASS_LAUNCH;
 }
 
@@ -1276,6 +1286,9 @@ extern "C" int gom_state_set_schedule(gom_state *s, int schedule) {
         if (!s->bitsliced_ok)
             return fail(GOM_E_RANGE, "gom_state_set_schedule: the bit-sliced schedule needs a "
                         "univariate FOS, maximum degree <= 4 and per-vertex |w| sums < 2^30");
+        if (s->fi)
+            return fail(GOM_E_RANGE, "gom_state_set_schedule: the bit-sliced schedule has no "
+                        "forced improvement");
         s->sched = schedule;
         return GOM_OK;
     case GOM_SCHED_CLASS_LAUNCH:
@@ -1301,7 +1314,7 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
     hipStream_t st = (hipStream_t)stream;
     std::vector<int> cands = {GOM_SCHED_CLASS_LAUNCH};
     if (s->resident_ok) cands.push_back(GOM_SCHED_RESIDENT);
-    if (s->bitsliced_ok) cands.push_back(GOM_SCHED_BITSLICED);
+    if (s->bitsliced_ok && !s->fi) cands.push_back(GOM_SCHED_BITSLICED);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -1340,6 +1353,20 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
     if (chosen) *chosen = best;
     return GOM_OK;
     GUARD_END
+}
+
+extern "C" int gom_state_set_fi(gom_state *s, int enabled) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_fi: null state");
+    if (s->open_next >= 0) return fail(GOM_E_STATE, "gom_state_set_fi: a generation is open");
+    s->fi = enabled != 0;
+    if (s->fi && s->sched == GOM_SCHED_BITSLICED) s->sched = auto_schedule(s);
+    return GOM_OK;
+}
+
+extern "C" int gom_state_get_fi(const gom_state *s, int *enabled) {
+    if (!s || !enabled) return fail(GOM_E_ARG, "gom_state_get_fi: null argument");
+    *enabled = s->fi ? 1 : 0;
+    return GOM_OK;
 }
 
 extern "C" int gom_state_get_schedule(const gom_state *s, int *schedule) {

@@ -63,6 +63,8 @@ struct alignas(64) DevState {
     int64_t start_tick;      // device wall clock at the start of a batch run
     int64_t done_tick;       // device wall clock when the elitist reached the target (or -1)
     uint64_t hash;           // accumulator of the state hash's gene and elitist terms
+    uint64_t fi_fail;        // solutions the last generation's forced improvement replaced
+                             // by the elitist
 };
 
 // Accumulators that many blocks add into.  Device-scope atomics on one address serialise
@@ -74,8 +76,14 @@ struct alignas(64) Stripe {
     uint64_t evaluated;
     uint64_t accepted;
     uint64_t mism;           // solutions whose P differs from the elitist (vertex pass)
-    uint64_t pad[5];
+    uint64_t acc;            // solutions with an accepted GOM step in this generation
+    uint64_t fimp;           // solutions whose forced improvement raised their fitness
+    uint64_t pad[3];
 };
+
+// Sweep modes: a GOM sweep, a GOM sweep that also records which solutions accepted a step
+// (forced improvement on), and a forced-improvement sweep (the elitist as donor).
+enum { kSweepGom = 0, kSweepGomTrack = 1, kSweepFi = 2 };
 
 // One colour-class sweep launch.  Set records are stored in class order: class position p of
 // class c is record s = class_start[c] + p, a block of int32 words at recs + roff[s] (layout
@@ -98,6 +106,8 @@ struct SweepArgs {
     int32_t cbase;          // first record of the class
     int32_t csize;          // number of sets in the class
     int32_t always;         // neutral rule: 1 = accept equal fitness always
+    int32_t mode;           // kSweepGom, kSweepGomTrack or kSweepFi
+    const uint64_t *E;      // elitist bits (forced improvement)
 };
 
 // Generation end, in two launches: k_finalize (one block: fitness from the stripes, best
@@ -117,6 +127,8 @@ struct EpilogueArgs {
     int32_t N;
     int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh flags only
     int32_t row_words;      // words per row, ceil(n / 64)
+    int32_t fi;             // forced improvement on: replace the solutions that it did not
+                            // improve by the elitist
 };
 
 enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };
@@ -147,6 +159,8 @@ struct ResidentCtx {
     int32_t k;
     int32_t always;
     int32_t row_words;
+    int32_t fi;             // forced improvement after the classes
+    const uint64_t *E;      // elitist bits
 };
 
 struct ResidentArgs {

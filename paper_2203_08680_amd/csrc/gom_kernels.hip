@@ -186,6 +186,28 @@ struct PairOut {
     int64_t delta;   // fitness change of the step
 };
 
+// Donor words for forced improvement: every "solution" carries the elitist's gene, so the
+// donor mask is all ones where the elitist differs from O_i and the chosen donor is the
+// elitist.
+struct EliteWords {
+    const uint64_t *E;
+    __device__ __forceinline__ uint64_t operator[](int v) const {
+        return 0ull - ((E[v >> 6] >> (v & 63)) & 1ull);
+    }
+};
+
+// Solutions set in a wave's per-lane flag (lane = group * G + solution).
+template <int G>
+__device__ __forceinline__ uint64_t solution_mask(bool flag) {
+    uint64_t m = ballot64(flag);
+    if constexpr (G < 64) {
+#pragma unroll
+        for (int g = 1; g < 64 / G; ++g) m |= m >> (g * G);
+        m &= (1ull << G) - 1ull;
+    }
+    return m;
+}
+
 // Offspring bits of solution i in the O planes (class-launch schedule).
 struct PlaneBits {
     const uint64_t *O;
@@ -264,8 +286,8 @@ __device__ __forceinline__ Head load_head(const Rec &R) {
     return hd;
 }
 
-template <int KIND, class Rec, class Bits, class Commit>
-__device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const uint64_t *P,
+template <int KIND, class Rec, class Words, class Bits, class Commit>
+__device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const Words &P,
                                             Bits bits, Commit commit, uint64_t cand, uint32_t h,
                                             bool neutral_ok) {
     PairOut out{0u, false, 0};
@@ -462,6 +484,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     };
     // issue the first record's loads together with the run-state loads
     const uint64_t mism = a.stripes[lane].mism;
+    const uint64_t acc_prev = a.mode == kSweepFi ? a.stripes[lane].acc : 0ull;
+    const uint64_t fimp_prev = a.mode == kSweepFi ? a.stripes[lane].fimp : 0ull;
     const int64_t elite_fitness = a.st->elite_fitness;
     int p = gw * GPW + grp;
     if constexpr (G == 64) p = __builtin_amdgcn_readfirstlane(p);
@@ -470,11 +494,19 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     if (elite_fitness >= a.target) return;
     const bool act = (int)i < a.N;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-    const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
+    uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
     const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
+    if (a.mode == kSweepFi) {
+        // forced improvement: solutions without an accepted step and not yet improved; the
+        // elitist is the only donor
+        const uint64_t todo = popm & ~wave_or64(acc_prev) & ~wave_or64(fimp_prev);
+        if (todo == 0) return;
+        cand = act && bit_of(todo, i) ? ~0ull : 0ull;
+    }
 
     int64_t facc = 0;
     uint32_t n_eval = 0, n_acc = 0;
+    bool flag = false;  // GOM: an accepted step; forced improvement: a step that improved
     const PlaneBits bits{a.O, i};
     const PlaneCommit<G> commit{a.O, grp, i};
     const int nwt = (a.csize + GPW - 1) / GPW;  // wave tiles
@@ -486,17 +518,24 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
             hd = load_head<KIND>(R);
         }
         if (p < a.csize) {
-            uint32_t h = 0;
-            if constexpr (KIND != 0) {
-                // each lane draws its own call; the 8 positions of a chunk share the counter
-                const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i,
-                                       (uint32_t)(p >> 3));
-                const int f = p & 7;
-                const uint32_t w = (f >> 1) == 0 ? r.x : (f >> 1) == 1 ? r.y
-                                 : (f >> 1) == 2 ? r.z : r.w;
-                h = (w >> (16 * (f & 1))) & 0xFFFFu;
+            PairOut r;
+            if (a.mode == kSweepFi) {
+                r = gom_pair<KIND>(R, hd, EliteWords{a.E}, bits, commit, cand, 0u, neutral_ok);
+                flag |= r.acc && r.delta > 0;
+            } else {
+                uint32_t h = 0;
+                if constexpr (KIND != 0) {
+                    // each lane draws its own call; the 8 positions of a chunk share it
+                    const U32x4 q = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i,
+                                           (uint32_t)(p >> 3));
+                    const int f = p & 7;
+                    const uint32_t w = (f >> 1) == 0 ? q.x : (f >> 1) == 1 ? q.y
+                                     : (f >> 1) == 2 ? q.z : q.w;
+                    h = (w >> (16 * (f & 1))) & 0xFFFFu;
+                }
+                r = gom_pair<KIND>(R, hd, a.P, bits, commit, cand, h, neutral_ok);
+                flag |= r.acc;
             }
-            const PairOut r = gom_pair<KIND>(R, hd, a.P, bits, commit, cand, h, neutral_ok);
             facc += r.acc ? r.delta : 0;
             n_eval += r.cnt > 0;
             n_acc += r.acc;
@@ -510,9 +549,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
     Stripe *sp = a.stripes + (gw % kStripes);
     if (lane < G && act && facc)
         atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
+    const uint64_t fm = a.mode != kSweepGom ? solution_mask<G>(flag && act) : 0ull;
     if (lane == 0) {
         if (ce) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)ce);
         if (ca) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)ca);
+        if (fm)
+            atomicOr((unsigned long long *)(a.mode == kSweepFi ? &sp->fimp : &sp->acc),
+                     (unsigned long long)fm);
     }
 }
 
@@ -649,7 +692,7 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
 // 64 vertices) and adds its fitness change and counts to its stripe.
 // ------------------------------------------------------------------------------------------
 constexpr int kResRngBytes = kResidentChunkSlots * 16;
-constexpr int kResRedBytes = 256;
+constexpr int kResRedBytes = 272;  // 16 wave sums (int64), 32 counts, 2 flags, padding
 
 // LDS bytes of the P copy (16-byte multiple).
 __host__ __device__ __forceinline__ size_t resident_words_bytes(int n) {
@@ -736,6 +779,36 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
         }
     }
 
+    // forced improvement when no GOM step of this solution was accepted: the classes again,
+    // in the same order, with the elitist as donor, until a class raises the fitness
+    bool any_acc = false, improved = false;
+    if (a.fi) {
+        uint32_t *flags = redc + 32;  // [0]: accepted steps, [1]: an improving step
+        if (tid == 0) flags[0] = flags[1] = 0u;
+        __syncthreads();
+        if (n_acc) atomicOr(&flags[0], 1u);
+        __syncthreads();
+        any_acc = flags[0] != 0u;
+        const EliteWords ew{a.E};
+        for (int t = 0; t < a.k && !any_acc && !improved; ++t) {
+            const int c = order[t];
+            const int cbase = a.class_ptr[c];
+            const int csize = a.class_ptr[c + 1] - cbase;
+            const int2 cr = a.class_rec[c];
+            for (int q = tid; q < csize; q += kResidentThreads) {
+                const AosRec R{cr.y ? a.recs + cr.x + q * cr.y : a.recs + a.roff[cbase + q]};
+                const Head hd = load_head<KIND>(R);
+                const PairOut r = gom_pair<KIND>(R, hd, ew, bits, commit, ~0ull, 0u, neutral_ok);
+                facc += r.acc ? r.delta : 0;
+                n_eval += r.cnt > 0;
+                n_acc += r.acc;
+                if (r.acc && r.delta > 0) atomicOr(&flags[1], 1u);
+            }
+            __syncthreads();
+            improved = flags[1] != 0u;
+        }
+    }
+
     for (int v0 = wave * 64; v0 < a.n; v0 += kResidentThreads) {
         const int v = v0 + lane;
         const uint64_t word = ballot64(v < a.n && ob[v] != 0);
@@ -761,6 +834,8 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
         if (sf) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)sf);
         if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
         if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
+        if (any_acc) atomicOr((unsigned long long *)&sp->acc, 1ull << i);
+        if (improved) atomicOr((unsigned long long *)&sp->fimp, 1ull << i);
     }
 }
 
@@ -785,12 +860,18 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
         if (t == 0) st->active = 0;
         return;
     }
+    // forced improvement: the solutions it ran for and did not improve become the elitist
+    uint64_t fail = 0;
+    if (a.fi && a.mode == kEpiGeneration) {
+        const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+        fail = popm & ~wave_or64(a.stripes[t].acc) & ~wave_or64(a.stripes[t].fimp);
+    }
     int64_t f = INT64_MIN;
     if (t < a.N) {
         int64_t d = 0;
 #pragma unroll 16
         for (int s = 0; s < kStripes; ++s) d += a.stripes[s].fit[t];
-        f = a.fit[t] + d;
+        f = bit_of(fail, (uint32_t)t) ? fE : a.fit[t] + d;
         a.fit[t] = f;
     }
     const int64_t ev = wave_sum64((int64_t)a.stripes[t].evaluated);
@@ -812,7 +893,10 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     a.stripes[t].evaluated = 0;
     a.stripes[t].accepted = 0;
     a.stripes[t].mism = 0;
+    a.stripes[t].acc = 0;
+    a.stripes[t].fimp = 0;
     if (t == 0) {
+        st->fi_fail = fail;
         const bool newE = a.mode == kEpiInit || (a.mode == kEpiGeneration && fb > fE);
         st->best = b;
         st->new_elite = newE ? 1 : 0;
@@ -860,8 +944,13 @@ __device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
         o = a.O[v];
     }
     if (a.mode == kEpiGeneration && in) {
+        const uint64_t fail = st->fi_fail;
+        if (fail) {  // copies of the elitist (its bits before this generation's update)
+            const uint64_t eo = 0ull - (uint64_t)bit_of(a.E[v >> 6], (uint32_t)(v & 63));
+            o = (o & ~fail) | (eo & fail);
+        }
         a.P[v] = o;
-        if (a.rows) a.O[v] = o;
+        if (a.rows || fail) a.O[v] = o;
     }
     uint32_t eb;
     if (newE) {

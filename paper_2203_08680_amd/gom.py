@@ -28,7 +28,8 @@ EXPORTED = (
     "gom_fos_free", "gom_colour", "gom_colour_get", "gom_state_bytes", "gom_state_init",
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
-    "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash",
+    "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
+    "gom_state_get_fi",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
     "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
@@ -99,6 +100,8 @@ def lib() -> C.CDLL:
         "gom_state_get_schedule": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_autotune": (C.c_int, [_vp, _i32, _vp, _P(C.c_int)]),
         "gom_fos_build_lt": (C.c_int, [_vp, _i32, _P(_vp)]),
+        "gom_state_set_fi": (C.c_int, [_vp, C.c_int]),
+        "gom_state_get_fi": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
         "gom_state_hash": (C.c_int, [_vp, _vp, _P(C.c_uint64)]),
         "gom_state_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
@@ -396,6 +399,17 @@ def gom_state_hash(s: GomState, stream=None) -> int:
     v = C.c_uint64()
     _check(lib().gom_state_hash(s.handle, _stream_handle(stream), C.byref(v)))
     return int(v.value)
+
+
+def gom_state_set_fi(s: GomState, enabled: bool = True) -> None:
+    """Forced improvement after each generation's classes (off by default)."""
+    _check(lib().gom_state_set_fi(s.handle, int(bool(enabled))))
+
+
+def gom_state_get_fi(s: GomState) -> bool:
+    v = C.c_int()
+    _check(lib().gom_state_get_fi(s.handle, C.byref(v)))
+    return bool(v.value)
 
 
 def gom_version() -> int:

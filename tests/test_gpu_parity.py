@@ -34,7 +34,8 @@ SCHEDS = [gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT]
 SCHED_IDS = ["class_launch", "resident"]
 
 
-def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None, sched=gom.GOM_SCHED_AUTO):
+def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None, sched=gom.GOM_SCHED_AUTO,
+              fi=False):
     if sets is None:
         ptr, vars_ = oracle.fos(g, kind)
         inst = gom.Instance(g.n, g.u, g.v, g.w, kind)
@@ -42,8 +43,11 @@ def make_pair(g, kind, pop, seed, rule=0, order=0, sets=None, sched=gom.GOM_SCHE
         ptr, vars_ = sets
         inst = gom.Instance(g.n, g.u, g.v, g.w, sets=sets)
     st = inst.state(pop=pop, seed=seed, neutral_rule=rule, class_order=order)
+    if fi:
+        gom.gom_state_set_fi(st, True)
     gom.gom_state_set_schedule(st, sched)
-    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule, order=order)
+    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule, order=order,
+                     flags=oracle.FLAG_FI if fi else 0)
     return inst, st, ref
 
 
@@ -313,6 +317,73 @@ def test_linkage_tree_fos(cuda, label, maker, bound, pop, sched):
     ptr, vars_ = oracle.linkage_tree(g, bound)
     ref = oracle.Run(g, ptr, vars_, pop=pop, seed=pop + bound)
     lockstep(st, ref, 6, label)
+
+
+def _kn_overlapping(n, seed):
+    rng = np.random.default_rng(seed)
+    e = np.array([(a, b) for a in range(n) for b in range(a + 1, n)])
+    g = workloads.from_edges(n, e, rng.choice([-1, 1], size=e.shape[0]))
+    sets = [[u] for u in range(n)] + [sorted([u, (u + 1) % n]) for u in range(n)] + \
+        [sorted([u, (u + 2) % n, (u + 3) % n]) for u in range(0, n, 2)]
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(x) for x in sets])
+    return g, (ptr, np.concatenate([np.asarray(x, np.int32) for x in sets]))
+
+
+FI_CASES = [
+    # (label, maker -> (graph, kind or None, sets or None), population, rule)
+    ("kn8_overlapping", lambda: (*_kn_overlapping(8, 38)[:1], None, _kn_overlapping(8, 38)[1]),
+     6, 0),
+    ("torus10_nbhd", lambda: (workloads.torus(10, 1, 5, seed=1), 1, None), 16, 0),
+    ("cm300_d4_uni", lambda: (workloads.configuration_model(300, 4, seed=3), 0, None), 24, 0),
+    ("cm200_d6_nbhd_always", lambda: (workloads.configuration_model(200, 6, seed=4), 1, None),
+     40, 1),
+    ("torus16_uni_p64", lambda: (workloads.torus(16, 1, 9, seed=5), 0, None), 64, 0),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+@pytest.mark.parametrize("label,maker,pop,rule", FI_CASES, ids=[c[0] for c in FI_CASES])
+def test_forced_improvement(cuda, label, maker, pop, rule, sched):
+    """Forced improvement after each generation's classes: every generation equal to the
+    oracle's, and it changes the run (compared with the same seed without it)."""
+    print(f"case forced improvement {label} sched={sched}", flush=True)
+    g, kind, sets = maker()
+    _, st, ref = make_pair(g, kind, pop, 9, rule=rule, sets=sets, sched=sched, fi=True)
+    assert gom.gom_state_get_fi(st)
+    lockstep(st, ref, 12, f"fi {label}")
+    _, plain, _ = make_pair(g, kind, pop, 9, rule=rule, sets=sets, sched=sched)
+    for _ in range(12):
+        gom.gom_generation(plain)
+    assert not np.array_equal(gom.gom_state_read(plain)["genes"],
+                              gom.gom_state_read(st)["genes"])
+
+
+def test_forced_improvement_with_cut_generations_and_schedules(cuda):
+    """Forced improvement after a generation cut at a class position, under the class-launch
+    and resident schedules in turn; the bit-sliced schedule is left when it is turned on."""
+    print("case forced improvement with stops", flush=True)
+    g = workloads.torus(12, 1, 9, seed=6)
+    _, st, ref = make_pair(g, 0, 32, 4, fi=True)
+    assert gom.gom_state_get_schedule(st) != gom.GOM_SCHED_BITSLICED
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+    k = len(ref.classes()[0]) - 1
+    for gen in range(8):
+        gom.gom_state_set_schedule(st, [gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT][gen % 2])
+        if gen % 3 == 0:
+            gom.gom_debug_stop_after_class(st, gen % k)
+            ref.stop_after_class(gen % k)
+            assert_same(gom.gom_state_read(st), ref.state(), f"fi stop gen {gen}")
+        gom.gom_generation(st)
+        ref.generation()
+        assert_same(gom.gom_state_read(st), ref.state(), f"fi gen {gen}")
+    g2 = workloads.torus(12, 1, 9, seed=6)
+    inst = gom.Instance(g2.n, g2.u, g2.v, g2.w, 0)
+    st2 = inst.state(pop=8, seed=1)
+    gom.gom_state_set_schedule(st2, gom.GOM_SCHED_BITSLICED)
+    gom.gom_state_set_fi(st2, True)
+    assert gom.gom_state_get_schedule(st2) != gom.GOM_SCHED_BITSLICED
 
 
 STOP_CASES = [
