@@ -312,6 +312,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
+    ap.add_argument("--block", type=int, default=0,
+                    help="class-launch block size (with --schedule class; 0 = default)")
     ap.add_argument("--fi", action="store_true",
                     help="forced improvement after each generation's classes")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -355,12 +357,14 @@ def main():
     if args.fi:
         gom.gom_state_set_fi(st, True)
     if args.schedule == "tuned":
-        gom.gom_state_autotune(st, 3)
+        gom.gom_state_autotune(st, 10)
     else:
         gom.gom_state_set_schedule(st, {"auto": gom.GOM_SCHED_AUTO,
                                         "class": gom.GOM_SCHED_CLASS_LAUNCH,
                                         "resident": gom.GOM_SCHED_RESIDENT,
                                         "bitsliced": gom.GOM_SCHED_BITSLICED}[args.schedule])
+    if args.block:
+        gom.gom_state_set_block(st, args.block)
     sched = gom.gom_state_get_schedule(st)
     sched_name = {gom.GOM_SCHED_RESIDENT: "resident", gom.GOM_SCHED_BITSLICED: "bitsliced"}.get(
         sched, "class_launch")
@@ -469,6 +473,7 @@ def main():
                    "target": target if wl.to_total_weight else None,
                    "classes": info["n_classes"], "seeds": list(range(1, args.steps + 1)),
                    "mode": "plain", "schedule": sched_name,
+                   "class_sweep_block": gom.gom_state_get_block(st),
                    "forced_improvement": bool(args.fi)},
         "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,
         "reached": len(tto), "generations_total": gens,

@@ -286,12 +286,19 @@ int gom_state_get_schedule(const gom_state *s, int *schedule);
 int gom_state_set_fi(gom_state *s, int enabled);
 int gom_state_get_fi(const gom_state *s, int *enabled);
 
+/* Block size of the class-launch sweeps: 64..512 threads, a multiple of 64 (default 256).
+ * GOM_E_RANGE otherwise.  Results do not depend on it. */
+int gom_state_set_block(gom_state *s, int threads);
+int gom_state_get_block(const gom_state *s, int *threads);
+
 /*
- * Autotuner: runs `trial_generations` generations under each schedule this instance allows
- * (class launch, resident, bit-sliced), timing each with HIP events on `stream`, and keeps the
- * fastest.  The trial generations are ordinary generations of the run (every schedule gives
- * the same results), so the state advances by (number of schedules tried) x
- * trial_generations generations.  *chosen (may be NULL) receives the schedule kept.
+ * Autotuner: for every candidate this instance allows (class launch with blocks of 64, 128,
+ * 256 and 512 threads, resident, bit-sliced), one untimed generation and then
+ * `trial_generations` generations timed with HIP events on `stream`; two interleaved rounds;
+ * keeps the candidate (schedule and block size) with the fastest round.  The trial
+ * generations are ordinary generations of the run (every schedule gives the same results), so
+ * the state advances by 2 x (candidates) x (trial_generations + 1) generations.  *chosen (may
+ * be NULL) receives the schedule kept.
  */
 int gom_state_autotune(gom_state *s, int32_t trial_generations, void *stream, int *chosen);
 

@@ -266,6 +266,7 @@ struct gom_state {
     DevState *h_st = nullptr;           // two pinned host slots
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     int max_grid = 2048;
+    int sweep_threads = 256;            // class-launch block size (64..512)
     int timing = 0;                     // sample period of the sweep-launch events (0 = off)
     int64_t sweep_launches = 0;         // sweep launches enqueued (for the sampling)
     std::vector<hipEvent_t> tev;        // begin/end pairs
@@ -827,7 +828,8 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         if (s->sched == GOM_SCHED_BITSLICED && !forced)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st, ev));
         else
-            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, st, ev));
+            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, s->sweep_threads,
+                                       st, ev));
     }
     return GOM_OK;
 }
@@ -1312,9 +1314,11 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
     if (!s || trial_generations < 1) return fail(GOM_E_ARG, "gom_state_autotune: bad arguments");
     if (s->open_next >= 0) return fail(GOM_E_STATE, "gom_state_autotune: a generation is open");
     hipStream_t st = (hipStream_t)stream;
-    std::vector<int> cands = {GOM_SCHED_CLASS_LAUNCH};
-    if (s->resident_ok) cands.push_back(GOM_SCHED_RESIDENT);
-    if (s->bitsliced_ok && !s->fi) cands.push_back(GOM_SCHED_BITSLICED);
+    // (schedule, class-launch block size)
+    std::vector<std::pair<int, int>> cands;
+    for (int t : {64, 128, 256, 512}) cands.push_back({GOM_SCHED_CLASS_LAUNCH, t});
+    if (s->resident_ok) cands.push_back({GOM_SCHED_RESIDENT, s->sweep_threads});
+    if (s->bitsliced_ok && !s->fi) cands.push_back({GOM_SCHED_BITSLICED, s->sweep_threads});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -1324,35 +1328,59 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
     }
     const bool timing = s->timing != 0;
     s->timing = 0;
-    int best = s->sched, rc = GOM_OK;
-    float best_ms = 0.f;
-    for (int c : cands) {
-        s->sched = c;
-        // one untimed generation loads the schedule's kernels, then the timed ones
-        for (int32_t t = 0; t <= trial_generations && rc == GOM_OK; ++t) {
-            if (t == 1 && hipEventRecord(e0, st) != hipSuccess) rc = GOM_E_DEVICE;
-            if (rc == GOM_OK) rc = enqueue_generation(s, s->g_host, INT64_MAX, st);
-            if (rc == GOM_OK) s->g_host++;
-        }
-        if (rc == GOM_OK && hipEventRecord(e1, st) != hipSuccess) rc = GOM_E_DEVICE;
-        float ms = 0.f;
-        if (rc == GOM_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = GOM_E_DEVICE;
-        if (rc != GOM_OK) break;
-        if (c == cands.front() || ms < best_ms) {
-            best_ms = ms;
-            best = c;
+    // two interleaved rounds; each candidate keeps its faster round
+    constexpr int kRounds = 2;
+    std::vector<float> cand_ms(cands.size(), 0.f);
+    int rc = GOM_OK;
+    for (int round = 0; round < kRounds && rc == GOM_OK; ++round) {
+        for (size_t ci = 0; ci < cands.size() && rc == GOM_OK; ++ci) {
+            s->sched = cands[ci].first;
+            s->sweep_threads = cands[ci].second;
+            // one untimed generation loads the schedule's kernels, then the timed ones
+            for (int32_t t = 0; t <= trial_generations && rc == GOM_OK; ++t) {
+                if (t == 1 && hipEventRecord(e0, st) != hipSuccess) rc = GOM_E_DEVICE;
+                if (rc == GOM_OK) rc = enqueue_generation(s, s->g_host, INT64_MAX, st);
+                if (rc == GOM_OK) s->g_host++;
+            }
+            if (rc == GOM_OK && hipEventRecord(e1, st) != hipSuccess) rc = GOM_E_DEVICE;
+            float ms = 0.f;
+            if (rc == GOM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = GOM_E_DEVICE;
+            if (rc == GOM_OK && (round == 0 || ms < cand_ms[ci])) cand_ms[ci] = ms;
         }
     }
+    std::pair<int, int> best = cands.front();
+    float best_ms = cand_ms.front();
+    for (size_t ci = 1; ci < cands.size(); ++ci)
+        if (cand_ms[ci] < best_ms) {
+            best_ms = cand_ms[ci];
+            best = cands[ci];
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     s->timing = timing;
     if (rc != GOM_OK) return fail(rc, "gom_state_autotune: a trial generation failed");
-    s->sched = best;
-    if (chosen) *chosen = best;
+    s->sched = best.first;
+    s->sweep_threads = best.second;
+    if (chosen) *chosen = best.first;
     return GOM_OK;
     GUARD_END
+}
+
+extern "C" int gom_state_set_block(gom_state *s, int threads) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_block: null state");
+    if (threads < 64 || threads > 512 || threads % 64)
+        return fail(GOM_E_RANGE, "gom_state_set_block: %d threads (64..512, a multiple of 64)",
+                    threads);
+    s->sweep_threads = threads;
+    return GOM_OK;
+}
+
+extern "C" int gom_state_get_block(const gom_state *s, int *threads) {
+    if (!s || !threads) return fail(GOM_E_ARG, "gom_state_get_block: null argument");
+    *threads = s->sweep_threads;
+    return GOM_OK;
 }
 
 extern "C" int gom_state_set_fi(gom_state *s, int enabled) {

@@ -198,8 +198,9 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
                                const int32_t *ew, int64_t m, int N, Stripe *stripes,
                                hipStream_t s);
 // kind: 0 = univariate records, 1 = general records
-hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s,
-                              KernelEvents ev = {});
+// threads: block size, a multiple of 64 up to 512
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int threads,
+                              hipStream_t s, KernelEvents ev = {});
 // Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
                                  hipStream_t s, KernelEvents ev = {});

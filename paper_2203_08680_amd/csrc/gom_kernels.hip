@@ -28,7 +28,7 @@ namespace {
 
 static_assert(kStripes == 64, "one stripe per lane of a wave");
 
-constexpr int kSweepThreads = 256;  // 4 waves of 64 lanes
+constexpr int kSweepMaxThreads = 512;  // class sweep blocks: 64 to 512 threads
 constexpr int kEpiThreads = 256;
 constexpr int kFitThreads = 256;
 
@@ -210,6 +210,7 @@ __device__ __forceinline__ uint64_t solution_mask(bool flag) {
 
 // Offspring bits of solution i in the O planes (class-launch schedule).
 struct PlaneBits {
+    static constexpr bool kLocal = false;  // reads go to global memory
     const uint64_t *O;
     uint32_t i;
     __device__ __forceinline__ uint32_t operator()(int v) const { return bit_of(O[v], i); }
@@ -217,6 +218,7 @@ struct PlaneBits {
 
 // Offspring bits of one solution in LDS, one byte per vertex (resident schedule).
 struct LdsBits {
+    static constexpr bool kLocal = true;   // reads go to LDS: cheap to repeat
     const uint8_t *ob;
     __device__ __forceinline__ uint32_t operator()(int v) const { return ob[v]; }
 };
@@ -328,23 +330,32 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
             // members' words.  Prefetched words past nd belong to the next record, so those
             // entries read vertex 0 instead; an inside entry's b is below nm <= n, so every
             // index is a vertex and the loads need no branch
-            uint32_t ov0[kBatch], ov1[kBatch];
+            // With bits in LDS (resident schedule) the words and bits are read again where
+            // they are needed instead of being held in registers (1024-thread blocks have
+            // 128 registers per lane).
+            constexpr bool LOCAL = Bits::kLocal;
+            auto far_end = [&](int e, int2 en) {
+                return bits((int)((uint32_t)(e < nd ? en.x : 0) & kSmallIdx));
+            };
+            uint32_t ov0[LOCAL ? 1 : kBatch], ov1[LOCAL ? 1 : kBatch];
+            if constexpr (!LOCAL) {
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                ov0[t] = bits((int)((uint32_t)(t < nd ? hd.en0[t].x : 0) & kSmallIdx));
-                ov1[t] = bits((int)((uint32_t)(kBatch + t < nd ? hd.en1[t].x : 0) & kSmallIdx));
+                for (int t = 0; t < kBatch; ++t) {
+                    ov0[t] = far_end(t, hd.en0[t]);
+                    ov1[t] = far_end(kBatch + t, hd.en1[t]);
+                }
             }
-            uint64_t pw[kSmallSet];
+            uint64_t pw[LOCAL ? 1 : kSmallSet];
             uint32_t om = 0;
             uint64_t D = 0;
 #pragma unroll
             for (int k = 0; k < kSmallSet; ++k) {
-                pw[k] = 0;
                 if (k < nm) {
-                    pw[k] = P[mem[k]];
+                    const uint64_t w = P[mem[k]];
+                    if constexpr (!LOCAL) pw[k] = w;
                     const uint32_t ok = bits(mem[k]);
                     om |= ok << k;
-                    D |= pw[k] ^ (0ull - (uint64_t)ok);
+                    D |= w ^ (0ull - (uint64_t)ok);
                 }
             }
             D &= cand;
@@ -353,7 +364,12 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
             uint32_t cm = 0;
 #pragma unroll
             for (int k = 0; k < kSmallSet; ++k)
-                if (k < nm) cm |= (bit_of(pw[k], d) ^ ((om >> k) & 1u)) << k;
+                if (k < nm) {
+                    uint64_t w;
+                    if constexpr (LOCAL) w = P[mem[k]];
+                    else w = pw[k];
+                    cm |= (bit_of(w, d) ^ ((om >> k) & 1u)) << k;
+                }
             // change of one dependent edge: x holds the member position a of its own end,
             // and the outside vertex v (bit 31 clear) or the inside end's position b
             auto edge = [&](int e, int2 en, uint32_t ovx) -> int64_t {
@@ -369,8 +385,13 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
             int64_t delta = 0;
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
-                delta += edge(t, hd.en0[t], ov0[t]);
-                delta += edge(kBatch + t, hd.en1[t], ov1[t]);
+                if constexpr (LOCAL) {
+                    delta += edge(t, hd.en0[t], far_end(t, hd.en0[t]));
+                    delta += edge(kBatch + t, hd.en1[t], far_end(kBatch + t, hd.en1[t]));
+                } else {
+                    delta += edge(t, hd.en0[t], ov0[t]);
+                    delta += edge(kBatch + t, hd.en1[t], ov1[t]);
+                }
             }
             for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
                 int2 en[kBatch];
@@ -470,13 +491,14 @@ struct PlaneCommit {
 };
 
 template <int G, int KIND>
-__global__ __launch_bounds__(kSweepThreads) void k_class_sweep(SweepArgs a) {
+__global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     constexpr int GPW = 64 / G;          // sets per wave
     const int lane = threadIdx.x & 63;
     const int grp = lane / G;
     const uint32_t i = (uint32_t)(lane % G);
-    const int gw = blockIdx.x * (kSweepThreads / 64) + (int)(threadIdx.x >> 6);  // global wave
-    const int nwaves = gridDim.x * (kSweepThreads / 64);
+    const int wpb = (int)(blockDim.x >> 6);                        // waves per block
+    const int gw = blockIdx.x * wpb + (int)(threadIdx.x >> 6);     // global wave
+    const int nwaves = gridDim.x * wpb;
     // one set per wave (G = 64): the record is wave-uniform
     using Rec = std::conditional_t<G == 64, UniformAosRec, AosRec>;
     auto record = [&](int p) {
@@ -1122,14 +1144,15 @@ static void launch_timed(K kernel, dim3 gd, dim3 bd, size_t lds, hipStream_t s, 
         hipLaunchKernelGGL(kernel, gd, bd, lds, s, args...);
 }
 
-hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, hipStream_t s,
-                              KernelEvents ev) {
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int threads,
+                              hipStream_t s, KernelEvents ev) {
+    if (threads < 64 || threads > kSweepMaxThreads || threads % 64) return hipErrorInvalidValue;
     const int G = a.N <= 16 ? 16 : (a.N <= 32 ? 32 : 64);
-    const int per_tile = (kSweepThreads / 64) * (64 / G);  // sets per block
+    const int per_tile = (threads / 64) * (64 / G);  // sets per block
     int grid = (a.csize + per_tile - 1) / per_tile;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
-    const dim3 gd(grid), bd(kSweepThreads);
+    const dim3 gd(grid), bd(threads);
     if (kind == 0) {
         if (G == 16) launch_timed(k_class_sweep<16, 0>, gd, bd, 0, s, ev, a);
         else if (G == 32) launch_timed(k_class_sweep<32, 0>, gd, bd, 0, s, ev, a);

@@ -29,7 +29,7 @@ EXPORTED = (
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
-    "gom_state_get_fi",
+    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
     "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
@@ -101,6 +101,8 @@ def lib() -> C.CDLL:
         "gom_state_autotune": (C.c_int, [_vp, _i32, _vp, _P(C.c_int)]),
         "gom_fos_build_lt": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_state_set_fi": (C.c_int, [_vp, C.c_int]),
+        "gom_state_set_block": (C.c_int, [_vp, C.c_int]),
+        "gom_state_get_block": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_get_fi": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
         "gom_state_hash": (C.c_int, [_vp, _vp, _P(C.c_uint64)]),
@@ -399,6 +401,17 @@ def gom_state_hash(s: GomState, stream=None) -> int:
     v = C.c_uint64()
     _check(lib().gom_state_hash(s.handle, _stream_handle(stream), C.byref(v)))
     return int(v.value)
+
+
+def gom_state_set_block(s: GomState, threads: int) -> None:
+    """Block size of the class-launch sweeps (64..512, a multiple of 64)."""
+    _check(lib().gom_state_set_block(s.handle, int(threads)))
+
+
+def gom_state_get_block(s: GomState) -> int:
+    v = C.c_int()
+    _check(lib().gom_state_get_block(s.handle, C.byref(v)))
+    return v.value
 
 
 def gom_state_set_fi(s: GomState, enabled: bool = True) -> None:

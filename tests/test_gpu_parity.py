@@ -288,7 +288,10 @@ def test_autotune_generations_are_ordinary(cuda, kind):
         allowed.add(gom.GOM_SCHED_BITSLICED)
     assert chosen in allowed and gom.gom_state_get_schedule(st) == chosen
     done = gom.gom_state_read(st, genes=False)["generation"]
-    assert done == 3 * len(allowed)
+    # class launch is tried with blocks of 64, 128, 256 and 512 threads; two rounds of one
+    # untimed and two timed generations per candidate
+    assert done == 2 * 3 * (len(allowed) + 3)
+    assert gom.gom_state_get_block(st) in (64, 128, 256, 512)
     for _ in range(done):
         ref.generation()
     assert_same(gom.gom_state_read(st), ref.state(), "after autotune")
@@ -448,6 +451,22 @@ def test_state_hash_full_size(cuda):
     gom.gom_debug_stop_after_class(st, 1)
     ref.stop_after_class(1)
     assert gom.gom_state_hash(st) == ref.hash()
+
+
+@pytest.mark.parametrize("threads", [64, 128, 512])
+@pytest.mark.parametrize("n,d,kind,pop", [(1001, 4, 1, 64), (997, 6, 1, 17), (1500, 3, 0, 5)])
+def test_class_launch_block_sizes(cuda, threads, n, d, kind, pop):
+    """The class-launch sweeps give the same results at every block size."""
+    print(f"case block size {threads} n={n} d={d} kind={kind} pop={pop}", flush=True)
+    if (n * d) % 2:
+        n += 1
+    g = workloads.configuration_model(n, d, seed=n + d)
+    _, st, ref = make_pair(g, kind, pop, 3, sched=gom.GOM_SCHED_CLASS_LAUNCH)
+    gom.gom_state_set_block(st, threads)
+    assert gom.gom_state_get_block(st) == threads
+    lockstep(st, ref, 5, f"block {threads}")
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_block(st, 96)
 
 
 BITSLICED_CASES = [
