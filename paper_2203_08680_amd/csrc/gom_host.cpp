@@ -146,7 +146,24 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
             if (univariate) {
                 const int32_t u = f.vars[b];
                 const int32_t nd = g.row_ptr[(size_t)u + 1] - g.row_ptr[u];
-                R.words.insert(R.words.end(), {u, nd, 0, 0});
+                // with at most 4 edges: the bit-sliced sweep's truth tables, bit p of the low
+                // half = (flip gain > 0), of the high half = (gain == 0), for the pattern p of
+                // edges whose far end carries the same gene (bit e set: edge e gains +w_e)
+                uint32_t tables = 0;
+                if (nd <= 4) {
+                    int64_t wl[4] = {0, 0, 0, 0}, tot = 0;
+                    for (int32_t e = 0; e < nd; ++e) {
+                        wl[e] = g.wt[(size_t)g.row_ptr[u] + e];
+                        tot += wl[e];
+                    }
+                    for (uint32_t pt = 0; pt < 16; ++pt) {
+                        int64_t d = -tot;
+                        for (int e = 0; e < 4; ++e)
+                            if (pt >> e & 1u) d += 2 * wl[e];
+                        tables |= (uint32_t)(d > 0) << pt | (uint32_t)(d == 0) << (pt + 16);
+                    }
+                }
+                R.words.insert(R.words.end(), {u, nd, (int32_t)tables, 0});
                 for (int32_t r = g.row_ptr[u]; r < g.row_ptr[(size_t)u + 1]; ++r) {
                     R.words.push_back(g.col[r]);
                     R.words.push_back(g.wt[r]);

@@ -56,6 +56,17 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t x, uint32_t r) {
     return base;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD b mod 8), and each
+// XCD has its own L2.  xcd_tile maps block b to a logical tile so that every XCD works on one
+// contiguous range of tiles: neighbouring sets share population words, which are then
+// fetched into one L2 instead of several.  A bijection on [0, G).
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    constexpr int kXcds = 8;
+    const int x = b % kXcds, q = b / kXcds;
+    const int per = G / kXcds, rem = G % kXcds;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
@@ -162,8 +173,10 @@ __global__ __launch_bounds__(kFitThreads) void k_full_fitness(const uint64_t *P,
 // ------------------------------------------------------------------------------------------
 // Set records (built on the host in colour-class order, one per class position s, starting
 // at word roff[s] on a 16-byte boundary):
-//   univariate FOS:  [u, nd, 0, 0] then nd entries {v, w}: the neighbours of the set's
-//                    variable u and the edge weights
+//   univariate FOS:  [u, nd, tables, 0] then nd entries {v, w}: the neighbours of the set's
+//                    variable u and the edge weights; for nd <= 4, `tables` holds the
+//                    bit-sliced sweep's truth tables (low 16 bits: flip gain > 0, high 16
+//                    bits: gain == 0, bit p for the pattern p of same-gene far ends)
 //   small set (nm <= 14 variables, n < 2^27): [nm, nd, u_0..u_13] then nd entries {x, w}
 //                    (unused member slots hold -1); x holds the position a of the entry's
 //                    own endpoint in bits 27..30, and either the outside neighbour v (bit 31
@@ -497,7 +510,8 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     const int grp = lane / G;
     const uint32_t i = (uint32_t)(lane % G);
     const int wpb = (int)(blockDim.x >> 6);                        // waves per block
-    const int gw = blockIdx.x * wpb + (int)(threadIdx.x >> 6);     // global wave
+    const int gw = xcd_tile((int)blockIdx.x, (int)gridDim.x) * wpb +
+                   (int)(threadIdx.x >> 6);                        // global wave (tile order)
     const int nwaves = gridDim.x * wpb;
     // one set per wave (G = 64): the record is wave-uniform
     using Rec = std::conditional_t<G == 64, UniformAosRec, AosRec>;
@@ -588,10 +602,10 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
 // For set {u} with edges (u, v_e, w_e), e < 4 (missing edges have w = 0):
 //   q_e    = ~(O[u] ^ O[v_e]): bit i set when u and v_e carry the same gene in O_i, so
 //            flipping u cuts the edge (+w_e); otherwise it uncuts it (-w_e)
-//   delta  of solution i depends only on the 4-bit pattern (q_0..q_3 at bit i): the lane
-//            computes the 16 pattern deltas and two 16-entry truth tables (delta > 0,
-//            delta == 0), then evaluates them on all 64 solutions at once with a tree of
-//            bitwise selects on q_0..q_3
+//   delta  of solution i depends only on the 4-bit pattern (q_0..q_3 at bit i): the record
+//            carries two 16-entry truth tables over the patterns (delta > 0, delta == 0),
+//            computed from the set's weights when the record was built; the lane evaluates
+//            them on all 64 solutions at once with a tree of bitwise selects on q_0..q_3
 //   donor  exists for solution i when some other solution's P gene at u differs from
 //            O_i[u]: from the popcounts of the ones and zeros of P[u]
 //   accept = donor & (positive | (zero & not-elitist)), O[u] ^= accept
@@ -636,7 +650,8 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
     __syncthreads();
     uint32_t n_eval = 0, n_acc = 0;
     const int stride = gridDim.x * kSwarThreads;
-    for (int p = blockIdx.x * kSwarThreads + threadIdx.x; p < a.csize; p += stride) {
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    for (int p = tile * kSwarThreads + threadIdx.x; p < a.csize; p += stride) {
         const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride
                                      : a.recs + a.roff[a.cbase + p];
         const int4 h = *reinterpret_cast<const int4 *>(R);
@@ -657,16 +672,8 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
         const uint64_t hz = cz >= 2 ? ~0ull : (cz == 1 ? ~zeros : 0ull);
         const uint64_t ho = co >= 2 ? ~0ull : (co == 1 ? ~ones : 0ull);
         const uint64_t has = ((o & hz) | (~o & ho)) & popm;
-        // pattern deltas and truth tables
-        const int base = -(w0 + w1 + w2 + w3);
-        uint32_t tp = 0, tz = 0;
-#pragma unroll
-        for (int pt = 0; pt < 16; ++pt) {
-            const int d = base + ((pt & 1) ? 2 * w0 : 0) + ((pt & 2) ? 2 * w1 : 0) +
-                          ((pt & 4) ? 2 * w2 : 0) + ((pt & 8) ? 2 * w3 : 0);
-            tp |= (uint32_t)(d > 0) << pt;
-            tz |= (uint32_t)(d == 0) << pt;
-        }
+        // truth tables over the 16 patterns, precomputed with the record (third header word)
+        const uint32_t tp = (uint32_t)h.z & 0xFFFFu, tz = (uint32_t)h.z >> 16;
         const uint64_t acc =
             (table16(tp, q0, q1, q2, q3) | (table16(tz, q0, q1, q2, q3) & nz)) & has;
         n_eval += (uint32_t)__popcll(has);
