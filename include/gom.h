@@ -357,6 +357,42 @@ int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);
 void gom_batch_free(gom_batch *b);
 
 /* ------------------------------------------------------------------------------------------
+ * Interleaved Multi-start Scheme (Section 6.3).  Level i (1-based) is a population of
+ * n_base * 2^(i-1) solutions with seed `seed + i - 1`.  A step runs one generation of level
+ * 1 and, whenever level i has then completed a multiple of c_ims generations, one generation
+ * of level i + 1 (created, in its own part of the arena, when it first runs), up to
+ * max_levels levels.  The run ends after the step in which some level's elitist reaches
+ * `target`, or when max_total_generations generations have run.  Synchronous (the elitists
+ * are read after every step).
+ * ------------------------------------------------------------------------------------------ */
+#define GOM_IMS_MAX_LEVELS 8
+
+typedef struct {
+    int32_t levels;             /* levels created */
+    int32_t steps;              /* steps run */
+    int32_t total_generations;  /* generations over all levels */
+    int32_t reached;            /* 1 if some level's elitist reached the target */
+    int64_t best;               /* best elitist fitness over the levels */
+    int32_t best_level;         /* its level (1-based; the lowest on ties) */
+    int32_t generations[GOM_IMS_MAX_LEVELS];  /* per level */
+    int64_t evaluated, accepted;  /* summed over the levels */
+} gom_ims_result;
+
+/* Arena bytes for max_levels levels.  GOM_E_RANGE if n_base * 2^(max_levels-1) exceeds
+ * GOM_MAX_POP; GOM_E_ARG for max_levels outside 1..GOM_IMS_MAX_LEVELS or n_base < 2. */
+int gom_ims_bytes(const mc_graph *g, const gom_fos *f, int32_t n_base, int32_t max_levels,
+                  size_t *bytes);
+
+/* Run the scheme on (g, f coloured).  forced_improvement: 0/1 for every level.  states:
+ * NULL, or an array of max_levels handles that receives the levels' states (NULL where a
+ * level was not created); the caller then owns them (gom_state_free), and their memory is
+ * in dev_arena. */
+int gom_ims_run(const mc_graph *g, const gom_fos *f, int32_t n_base, int32_t c_ims,
+                int32_t max_levels, uint64_t seed, int neutral_rule, int forced_improvement,
+                int64_t target, int32_t max_total_generations, void *dev_arena,
+                size_t arena_bytes, void *stream, gom_ims_result *out, gom_state **states);
+
+/* ------------------------------------------------------------------------------------------
  * Serving loop with continuous batching.  Jobs (a graph, a coloured FOS, a population size, a
  * seed, a target and a generation limit) are submitted at any time and wait in a queue.
  * gom_server_step admits queued jobs first come first served while their states fit in the

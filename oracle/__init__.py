@@ -198,3 +198,41 @@ class Run:
         self._L.or_set(self._h, np.ascontiguousarray(genes, np.uint8).reshape(-1),
                        np.ascontiguousarray(elite, np.uint8), int(elite_fitness),
                        int(generation), np.asarray(counters[:3], np.int64))
+
+
+def ims_run(g, set_ptr, set_vars, n_base: int, c_ims: int, max_levels: int, seed: int,
+            target: int, max_total_generations: int, rule: int = NEUTRAL_PAPER,
+            flags: int = 0):
+    """Interleaved Multi-start Scheme (Section 6.3) over oracle runs.  Population P_i (i =
+    1, 2, ...) has n_base * 2^(i-1) solutions and seed `seed + i - 1`; a step runs one
+    generation of P_1, and whenever P_i has then completed a multiple of c_ims generations
+    it continues with one generation of P_(i+1) (created at its first generation), up to
+    max_levels populations.  The run stops after the step in which some population's elitist
+    reaches `target`, or as soon as max_total_generations generations have run.
+    Returns (runs, order): the Run of every level created and the list of levels (1-based)
+    in the order their generations ran."""
+    runs, order = [], []
+    total = 0
+
+    def reached():
+        return any(r.state(genes=False)["elite_fitness"] >= target for r in runs)
+
+    def step(i):
+        nonlocal total
+        if total >= max_total_generations:
+            return
+        if len(runs) < i:
+            runs.append(Run(g, set_ptr, set_vars, pop=n_base << (i - 1), seed=seed + i - 1,
+                            rule=rule, flags=flags))
+            if runs[-1].state(genes=False)["elite_fitness"] >= target:
+                return
+        runs[i - 1].generation()
+        order.append(i)
+        total += 1
+        gens = runs[i - 1].state(genes=False)["generation"]
+        if gens % c_ims == 0 and i < max_levels:
+            step(i + 1)
+
+    while total < max_total_generations and not (runs and reached()):
+        step(1)
+    return runs, order

@@ -76,13 +76,13 @@ struct gom_fos {
 namespace {
 
 struct Layout {
-    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, total;
+    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, coop, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
-                   int64_t rec_words) {
+                   int64_t rec_words, int64_t n_coop) {
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -104,6 +104,7 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
     L.ew = take(sizeof(int32_t) * (size_t)m);
     L.roff = take(sizeof(int32_t) * (size_t)(n_sets + 1));
     L.recs = take(sizeof(int32_t) * (size_t)rec_words);
+    L.coop = take(sizeof(int32_t) * (size_t)n_coop);
     L.total = o;
     return L;
 }
@@ -121,6 +122,30 @@ struct Records {
 constexpr int kSmallSet = 14;         // members held in a small record's header
 constexpr int kSmallPosShift = 27;    // bits 27..30 of a small entry: member position
 constexpr int32_t kMaxVertexSmall = 1 << kSmallPosShift;  // vertex limit of a state
+
+// Class positions of the sets swept by a whole block (general FOS only): pos[ptr[c] ..
+// ptr[c+1]) for class c, and the largest of them per class.
+struct CoopSets {
+    std::vector<int32_t> ptr, pos, max_members;
+};
+
+CoopSets coop_sets(const gom_fos &f, bool univariate) {
+    CoopSets C;
+    C.ptr.assign((size_t)f.k + 1, 0);
+    C.max_members.assign((size_t)f.k, 0);
+    for (int32_t c = 0; c < f.k; ++c) {
+        if (!univariate)
+            for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t) {
+                const int32_t j = f.class_elems[t];
+                const int32_t nm = f.ptr[(size_t)j + 1] - f.ptr[j];
+                if (nm < kCoopMinMembers || nm > kCoopMaxMembers) continue;
+                C.pos.push_back(t - f.class_ptr[c]);
+                C.max_members[c] = std::max(C.max_members[c], nm);
+            }
+        C.ptr[(size_t)c + 1] = (int32_t)C.pos.size();
+    }
+    return C;
+}
 
 int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records &R) {
     const int32_t S = f.n_sets;
@@ -276,6 +301,8 @@ struct gom_state {
     int32_t *d_roff = nullptr, *d_recs = nullptr;
     int2 *d_crec = nullptr;
     std::vector<int2> class_rec;  // host copy of the per-class record placement
+    std::vector<int32_t> coop_ptr, coop_max;  // large sets per class (block-cooperative)
+    int32_t *d_coop = nullptr;                // their class positions
     int32_t g_host = 0;                 // next generation index to enqueue
     int32_t open_next = -1;             // class position where an open generation resumes
     int32_t g_base = 0;                 // generation at which attempted_base was set
@@ -718,7 +745,9 @@ extern "C" int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop,
     Records R;
     rc = build_records(*g, *f, f->max_set == 1, R);
     if (rc) return rc;
-    *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size()).total;
+    const CoopSets CS = coop_sets(*f, f->max_set == 1);
+    *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
+                         (int64_t)CS.pos.size()).total;
     return GOM_OK;
     GUARD_END
 }
@@ -842,11 +871,19 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         KernelEvents ev;
         int rc = forced ? GOM_OK : timing_events(s, &ev);
         if (rc) return rc;
+        const int32_t nl = s->coop_ptr[(size_t)c + 1] - s->coop_ptr[c];
+        a.coop = nl > 0 ? 1 : 0;
         if (s->sched == GOM_SCHED_BITSLICED && !forced)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st, ev));
         else
             HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, s->sweep_threads,
                                        st, ev));
+        if (nl > 0) {
+            SweepArgs b = a;
+            b.n_large = nl;
+            b.large_pos = s->d_coop + s->coop_ptr[c];
+            HIP_TRY(launch_large_set_sweep(b, s->coop_max[c], st));
+        }
     }
     return GOM_OK;
 }
@@ -932,7 +969,9 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     Records R;
     rc = build_records(*g, *f, f->max_set == 1, R);
     if (rc) return rc;
-    const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size());
+    const CoopSets CS = coop_sets(*f, f->max_set == 1);
+    const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
+                                 (int64_t)CS.pos.size());
     if (arena_bytes < L.total)
         return fail(GOM_E_NOMEM, "gom_state_init: arena has %zu bytes, needs %zu", arena_bytes,
                     L.total);
@@ -967,6 +1006,9 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->d_recs = (int32_t *)(s->arena + L.recs);
     s->d_crec = (int2 *)(s->arena + L.crec);
     s->class_rec = R.class_rec;
+    s->coop_ptr = CS.ptr;
+    s->coop_max = CS.max_members;
+    s->d_coop = (int32_t *)(s->arena + L.coop);
     auto cleanup = [&](int code) {
         gom_state_free(s);
         return code;
@@ -1006,6 +1048,7 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     if (e == hipSuccess) e = h2d(s->d_recs, R.words.data(), sizeof(int32_t) * R.words.size());
     if (e == hipSuccess)
         e = h2d(s->d_crec, R.class_rec.data(), sizeof(int2) * R.class_rec.size());
+    if (e == hipSuccess) e = h2d(s->d_coop, CS.pos.data(), sizeof(int32_t) * CS.pos.size());
     if (e == hipSuccess) e = enqueue_initial_population(s, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging buffers die below
     if (e != hipSuccess)
@@ -1946,4 +1989,139 @@ extern "C" int gom_server_info(const gom_server *sv, int32_t *n_active, int32_t 
         *free_bytes = t;
     }
     return GOM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Interleaved Multi-start Scheme (Section 6.3): populations of n_base * 2^(i-1) solutions,
+// level i seeded with seed + i - 1, each in its own part of the arena; a step runs one
+// generation of level 1 and, whenever level i has then completed a multiple of c_ims
+// generations, one generation of level i + 1 (created at its first generation).  The run
+// ends after the step in which some level's elitist reached the target, or when the
+// generation budget is spent.  The populations are independent, so each level's trajectory
+// is that of its own solo run.
+// ------------------------------------------------------------------------------------------
+extern "C" int gom_ims_bytes(const mc_graph *g, const gom_fos *f, int32_t n_base,
+                             int32_t max_levels, size_t *bytes) {
+    GUARD_BEGIN
+    if (!g || !f || !bytes || max_levels < 1 || max_levels > GOM_IMS_MAX_LEVELS || n_base < 2)
+        return fail(GOM_E_ARG, "gom_ims_bytes: bad arguments");
+    if (((int64_t)n_base << (max_levels - 1)) > GOM_MAX_POP)
+        return fail(GOM_E_RANGE, "gom_ims_bytes: the largest level would hold %lld solutions "
+                    "(at most %d)", (long long)((int64_t)n_base << (max_levels - 1)), GOM_MAX_POP);
+    size_t o = 0;
+    for (int32_t l = 0; l < max_levels; ++l) {
+        size_t b = 0;
+        int rc = gom_state_bytes(g, f, n_base << l, &b);
+        if (rc) return rc;
+        o = align_up(o + b);
+    }
+    *bytes = o;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_ims_run(const mc_graph *g, const gom_fos *f, int32_t n_base, int32_t c_ims,
+                           int32_t max_levels, uint64_t seed, int neutral_rule,
+                           int forced_improvement, int64_t target,
+                           int32_t max_total_generations, void *dev_arena, size_t arena_bytes,
+                           void *stream, gom_ims_result *out, gom_state **states) {
+    GUARD_BEGIN
+    size_t need = 0;
+    int rc = gom_ims_bytes(g, f, n_base, max_levels, &need);
+    if (rc) return rc;
+    if (!out || !dev_arena || c_ims < 1 || max_total_generations < 0)
+        return fail(GOM_E_ARG, "gom_ims_run: bad arguments");
+    if (arena_bytes < need)
+        return fail(GOM_E_NOMEM, "gom_ims_run: arena has %zu bytes, needs %zu", arena_bytes,
+                    need);
+    hipStream_t st = (hipStream_t)stream;
+    char *arena = (char *)dev_arena;
+    std::vector<gom_state *> lv;
+    std::vector<size_t> off((size_t)max_levels, 0);
+    for (int32_t l = 1; l < max_levels; ++l) {
+        size_t b = 0;
+        rc = gom_state_bytes(g, f, n_base << (l - 1), &b);
+        if (rc) return rc;
+        off[(size_t)l] = align_up(off[(size_t)l - 1] + b);
+    }
+    auto cleanup = [&](int code) {
+        for (gom_state *s : lv) gom_state_free(s);
+        return code;
+    };
+    std::vector<int64_t> elite;  // elitist fitness per level after its last generation
+    int32_t total = 0, steps = 0;
+    bool stop = false;
+    // the recursive step of the scheme, written as a loop over levels
+    auto step = [&]() -> int {
+        for (int32_t i = 1; i <= max_levels; ++i) {
+            if (total >= max_total_generations) return GOM_OK;
+            if ((int32_t)lv.size() < i) {
+                size_t b = 0;
+                int r = gom_state_bytes(g, f, n_base << (i - 1), &b);
+                gom_state *s = nullptr;
+                if (r == GOM_OK)
+                    r = gom_state_init(g, f, n_base << (i - 1), seed + (uint64_t)(i - 1),
+                                       neutral_rule, GOM_ORDER_RANDOM, arena + off[(size_t)i - 1],
+                                       b, stream, &s);
+                if (r == GOM_OK && forced_improvement) r = gom_state_set_fi(s, 1);
+                if (r) {
+                    if (s) gom_state_free(s);
+                    return r;
+                }
+                lv.push_back(s);
+                DevState h;
+                r = read_scalars(s, st, &h);
+                if (r) return r;
+                elite.push_back(h.elite_fitness);
+                if (h.elite_fitness >= target) {
+                    stop = true;
+                    return GOM_OK;
+                }
+            }
+            gom_state *s = lv[(size_t)i - 1];
+            int r = enqueue_generation(s, s->g_host, INT64_MAX, st);
+            if (r) return r;
+            s->g_host++;
+            ++total;
+            DevState h;
+            r = read_scalars(s, st, &h);
+            if (r) return r;
+            elite[(size_t)i - 1] = h.elite_fitness;
+            if (h.generation % c_ims != 0) return GOM_OK;
+        }
+        return GOM_OK;
+    };
+    while (total < max_total_generations && !stop) {
+        rc = step();
+        if (rc) return cleanup(rc);
+        ++steps;
+        for (int64_t e : elite) stop |= e >= target;
+    }
+    gom_ims_result r{};
+    r.levels = (int32_t)lv.size();
+    r.steps = steps;
+    r.total_generations = total;
+    r.best = INT64_MIN;
+    for (size_t l = 0; l < lv.size(); ++l) {
+        DevState h;
+        rc = read_scalars(lv[l], st, &h);
+        if (rc) return cleanup(rc);
+        r.generations[l] = h.generation;
+        r.evaluated += h.evaluated;
+        r.accepted += h.accepted;
+        if (h.elite_fitness > r.best) {
+            r.best = h.elite_fitness;
+            r.best_level = (int32_t)l + 1;
+        }
+    }
+    r.reached = lv.empty() ? 0 : (r.best >= target ? 1 : 0);
+    *out = r;
+    if (states) {
+        for (int32_t l = 0; l < max_levels; ++l)
+            states[l] = l < (int32_t)lv.size() ? lv[(size_t)l] : nullptr;
+    } else {
+        for (gom_state *s : lv) gom_state_free(s);
+    }
+    return GOM_OK;
+    GUARD_END
 }

@@ -553,7 +553,12 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
             R = record(p < a.csize ? p : 0);
             hd = load_head<KIND>(R);
         }
-        if (p < a.csize) {
+        bool take = p < a.csize;
+        if constexpr (KIND != 0) {
+            const int nm = hd.h0.x;
+            if (a.coop && nm >= kCoopMinMembers && nm <= kCoopMaxMembers) take = false;
+        }
+        if (take) {
             PairOut r;
             if (a.mode == kSweepFi) {
                 r = gom_pair<KIND>(R, hd, EliteWords{a.E}, bits, commit, cand, 0u, neutral_ok);
@@ -593,6 +598,142 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
             atomicOr((unsigned long long *)(a.mode == kSweepFi ? &sp->fimp : &sp->acc),
                      (unsigned long long)fm);
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Block-cooperative sweep of one large set (general record layout) for every solution at
+// once: block = set, lane = solution, the block's waves split the set's members.
+//   1. D_i = OR over members u of (P[u] xor broadcast(O_i[u])), reduced over the waves; the
+//      first wave picks each solution's donor from its 16-bit Philox field (the set's class
+//      position p, as in the other sweeps)
+//   2. per member k: the mask of solutions whose donor changes u_k, kept in LDS (cmw[k])
+//   3. delta_i over the set's dependent edges (each member's entries, members split over
+//      the waves; an inside edge changes when exactly one end changes), reduced over waves
+//   4. accept as in the other sweeps; each wave commits its members: O[u] ^= cmw & accepted
+// Forced improvement (mode kSweepFi): the elitist is the donor.  Sets of one class are
+// independent, so blocks never touch each other's words.
+// ------------------------------------------------------------------------------------------
+constexpr int kCoopThreads = 512;
+
+__global__ __launch_bounds__(kCoopThreads) void k_large_set_sweep(SweepArgs a) {
+    extern __shared__ uint64_t cmw[];
+    constexpr int W = kCoopThreads / 64;
+    __shared__ uint64_t red[W][64];
+    __shared__ int64_t redd[W][64];
+    __shared__ uint32_t sel[64];
+    __shared__ uint64_t accm_s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t i = (uint32_t)lane;
+    const int p = a.large_pos[blockIdx.x];
+    const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p];
+    const uint64_t mism = a.stripes[lane].mism;
+    const uint64_t acc_prev = a.mode == kSweepFi ? a.stripes[lane].acc : 0ull;
+    const uint64_t fimp_prev = a.mode == kSweepFi ? a.stripes[lane].fimp : 0ull;
+    if (a.st->elite_fitness >= a.target) return;
+    const int nm = R[0];
+    const int32_t *mem = R + 16;
+    const int32_t *end = R + 16 + nm;
+    const int2 *E = reinterpret_cast<const int2 *>(R + ((16 + 2 * nm + 3) & ~3));
+    const bool act = (int)i < a.N;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
+    const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
+    const bool fi = a.mode == kSweepFi;
+    if (fi) {
+        const uint64_t todo = popm & ~wave_or64(acc_prev) & ~wave_or64(fimp_prev);
+        if (todo == 0) return;  // uniform over the block
+        cand = act && bit_of(todo, i) ? ~0ull : 0ull;
+    }
+    const EliteWords ew{a.E};
+    auto donor_word = [&](int u) { return fi ? ew[u] : a.P[u]; };
+
+    // 1. eligible donors
+    uint64_t D = 0;
+    for (int k = w; k < nm; k += W) {
+        const int u = mem[k];
+        D |= donor_word(u) ^ (0ull - (uint64_t)bit_of(a.O[u], i));
+    }
+    red[w][lane] = D;
+    __syncthreads();
+    uint32_t cnt = 0, d = 0;
+    if (w == 0) {
+        D = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) D |= red[q][lane];
+        D &= cand;
+        cnt = (uint32_t)__popcll(D);
+        uint32_t h = 0;
+        if (!fi) {
+            const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i,
+                                   (uint32_t)(p >> 3));
+            const int f = p & 7;
+            const uint32_t x = (f >> 1) == 0 ? r.x : (f >> 1) == 1 ? r.y : (f >> 1) == 2 ? r.z : r.w;
+            h = (x >> (16 * (f & 1))) & 0xFFFFu;
+        }
+        d = cnt ? select_bit(D, (h * cnt) >> 16) : 0u;
+        sel[lane] = d;
+        red[0][lane] = cnt;  // reused: donor counts
+    }
+    __syncthreads();
+    d = sel[lane];
+    cnt = (uint32_t)red[0][lane];
+    // 2. change masks per member
+    for (int k = w; k < nm; k += W) {
+        const int u = mem[k];
+        const uint32_t flip = bit_of(donor_word(u), d) ^ bit_of(a.O[u], i);
+        const uint64_t m = ballot64(flip != 0 && cnt > 0);
+        if (lane == 0) cmw[k] = m;
+    }
+    __syncthreads();
+    // 3. fitness change over the dependent edges
+    int64_t dl = 0;
+    for (int k = w; k < nm; k += W) {
+        const int u = mem[k];
+        const uint32_t oa = bit_of(a.O[u], i), ca = bit_of(cmw[k], i);
+        for (int e = k ? end[k - 1] : 0, e1 = end[k]; e < e1; ++e) {
+            const int2 en = E[e];
+            uint32_t ov, flip;
+            if (en.x >= 0) {
+                ov = bit_of(a.O[en.x], i);
+                flip = ca;
+            } else {
+                const int b = ~en.x;
+                ov = bit_of(a.O[mem[b]], i);
+                flip = ca ^ bit_of(cmw[b], i);
+            }
+            dl += flip ? signed_w(oa == ov, en.y) : 0;
+        }
+    }
+    redd[w][lane] = dl;
+    __syncthreads();
+    if (w == 0) {
+        int64_t delta = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) delta += redd[q][lane];
+        const bool acc = cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+        const uint64_t am = ballot64(acc);
+        if (lane == 0) accm_s = am;
+        Stripe *sp = a.stripes + (blockIdx.x % kStripes);
+        if (acc && delta) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)delta);
+        const uint64_t ev = ballot64(cnt > 0);
+        const uint64_t flag = a.mode == kSweepGom ? 0ull
+                              : fi ? ballot64(acc && delta > 0) : am;
+        if (lane == 0) {
+            if (ev) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)__popcll(ev));
+            if (am) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)__popcll(am));
+            if (flag)
+                atomicOr((unsigned long long *)(fi ? &sp->fimp : &sp->acc),
+                         (unsigned long long)flag);
+        }
+    }
+    __syncthreads();
+    // 4. commit
+    const uint64_t am = accm_s;
+    if (am)
+        for (int k = w; k < nm; k += W) {
+            const uint64_t m = cmw[k] & am;
+            if (m && lane == 0) a.O[mem[k]] ^= m;
+        }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1169,6 +1310,21 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
         else if (G == 32) launch_timed(k_class_sweep<32, 1>, gd, bd, 0, s, ev, a);
         else launch_timed(k_class_sweep<64, 1>, gd, bd, 0, s, ev, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, hipStream_t s) {
+    if (a.n_large < 1) return hipSuccess;
+    if (max_members < 1 || max_members > kCoopMaxMembers) return hipErrorInvalidValue;
+    const size_t lds = sizeof(uint64_t) * (size_t)max_members;
+    static size_t attr_bytes = 0;
+    if (lds > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_large_set_sweep,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_bytes = lds;
+    }
+    hipLaunchKernelGGL(k_large_set_sweep, dim3(a.n_large), dim3(kCoopThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ EXPORTED = (
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
-    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block",
+    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_ims_bytes",
+    "gom_ims_run",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
     "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
@@ -45,6 +46,16 @@ class GomError(RuntimeError):
 class gom_result(C.Structure):
     _fields_ = [("generations", C.c_int32), ("reached", C.c_int32), ("best", C.c_int64),
                 ("attempted", C.c_int64), ("evaluated", C.c_int64), ("accepted", C.c_int64)]
+
+
+GOM_IMS_MAX_LEVELS = 8
+
+
+class gom_ims_result(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("steps", C.c_int32), ("total_generations", C.c_int32),
+                ("reached", C.c_int32), ("best", C.c_int64), ("best_level", C.c_int32),
+                ("generations", C.c_int32 * GOM_IMS_MAX_LEVELS), ("evaluated", C.c_int64),
+                ("accepted", C.c_int64)]
 
 
 class gom_job_result(C.Structure):
@@ -102,6 +113,9 @@ def lib() -> C.CDLL:
         "gom_fos_build_lt": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_state_set_fi": (C.c_int, [_vp, C.c_int]),
         "gom_state_set_block": (C.c_int, [_vp, C.c_int]),
+        "gom_ims_bytes": (C.c_int, [_vp, _vp, _i32, _i32, _P(_sz)]),
+        "gom_ims_run": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _u64, C.c_int, C.c_int, _i64,
+                                  _i32, _vp, _sz, _vp, _vp, _vp]),
         "gom_state_get_block": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_get_fi": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
@@ -600,3 +614,42 @@ class GomServer:
                                      C.byref(fb)))
         return {"active": a.value, "queued": q.value, "streams": b.value,
                 "free_bytes": fb.value}
+
+
+# ------------------------------------------------------------------------------------------
+# Interleaved multi-start scheme
+# ------------------------------------------------------------------------------------------
+def gom_ims_run(inst: "Instance", n_base: int, c_ims: int, max_levels: int, seed: int,
+                target: int, max_total_generations: int, neutral_rule: int = GOM_NEUTRAL_PAPER,
+                forced_improvement: bool = False, device=None, stream=None):
+    """(result dict, list of the levels' GomState, None for levels not created)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    b = _sz()
+    _check(lib().gom_ims_bytes(inst.graph.handle, inst.fos.handle, int(n_base),
+                               int(max_levels), C.byref(b)))
+    arena = torch.empty(b.value + 256, dtype=torch.uint8, device=dev)
+    off = (-arena.data_ptr()) % 256
+    res = gom_ims_result()
+    hs = (C.c_void_p * int(max_levels))()
+    with torch.cuda.device(dev):
+        _check(lib().gom_ims_run(inst.graph.handle, inst.fos.handle, int(n_base), int(c_ims),
+                                 int(max_levels), int(seed) & (2**64 - 1), int(neutral_rule),
+                                 int(bool(forced_improvement)), int(target),
+                                 int(max_total_generations), arena.data_ptr() + off, b.value,
+                                 _stream_handle(stream), C.byref(res), hs))
+    states = []
+    for lvl in range(int(max_levels)):
+        h = hs[lvl]
+        if not h:
+            states.append(None)
+            continue
+        st = GomState.__new__(GomState)
+        st.handle, st.arena, st.n, st.pop = h, arena, inst.n, n_base << lvl
+        st._borrowed = False
+        states.append(st)
+    out = {"levels": res.levels, "steps": res.steps, "total_generations": res.total_generations,
+           "reached": bool(res.reached), "best": res.best, "best_level": res.best_level,
+           "generations": list(res.generations)[:res.levels], "evaluated": res.evaluated,
+           "accepted": res.accepted}
+    return out, states

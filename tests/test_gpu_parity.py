@@ -150,6 +150,26 @@ def test_explicit_large_sets(cuda, sched):
 
 
 @pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+@pytest.mark.parametrize("pop,fi", [(64, False), (17, False), (40, True)])
+def test_block_cooperative_large_sets(cuda, sched, pop, fi):
+    """Sets of 65 to 2000 members (swept by a whole block under class launch) beside
+    singletons and small sets, with and without forced improvement."""
+    print(f"case large sets pop={pop} fi={fi} sched={sched}", flush=True)
+    g = workloads.configuration_model(2500, 4, seed=21, weights="signed50")
+    rng = np.random.default_rng(22)
+    sets = [[v] for v in range(g.n)]
+    for size in list(rng.integers(65, 600, size=24)) + [1200, 2000, 64, 66]:
+        sets.append(sorted(rng.choice(g.n, size=int(size), replace=False).tolist()))
+    for _ in range(20):
+        sets.append(sorted(rng.choice(g.n, size=int(rng.integers(2, 14)), replace=False).tolist()))
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(x) for x in sets])
+    vars_ = np.concatenate([np.asarray(x, np.int32) for x in sets])
+    _, st, ref = make_pair(g, None, pop, seed=5, sets=(ptr, vars_), sched=sched, fi=fi)
+    lockstep(st, ref, 4, f"large sets pop {pop}")
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("d,kind", [(3, 0), (3, 1), (6, 0), (6, 1), (12, 0), (12, 1)])
 def test_cm100k_full_size(cuda, d, kind, sched):
     """Random d-regular graphs, n = 100000, weights +-U{1..50}, population 32: the full
@@ -387,6 +407,40 @@ def test_forced_improvement_with_cut_generations_and_schedules(cuda):
     gom.gom_state_set_schedule(st2, gom.GOM_SCHED_BITSLICED)
     gom.gom_state_set_fi(st2, True)
     assert gom.gom_state_get_schedule(st2) != gom.GOM_SCHED_BITSLICED
+
+
+IMS_CASES = [
+    # (label, graph maker, FOS kind, n_base, c_ims, levels, to total weight, budget, FI)
+    ("torus8_nbhd_to_optimum", lambda: workloads.torus(8, 1, 9, seed=3), 1, 4, 2, 3, True,
+     300, False),
+    ("cm300_uni_budget", lambda: workloads.configuration_model(300, 4, seed=5), 0, 16, 4, 3,
+     False, 40, False),
+    ("torus10_uni_fi", lambda: workloads.torus(10, 1, 5, seed=1), 0, 8, 3, 4, True, 120, True),
+]
+
+
+@pytest.mark.parametrize("label,maker,kind,n_base,c_ims,levels,to_opt,budget,fi", IMS_CASES,
+                         ids=[c[0] for c in IMS_CASES])
+def test_ims_equals_oracle(cuda, label, maker, kind, n_base, c_ims, levels, to_opt, budget,
+                           fi):
+    """The interleaved multi-start scheme: the same levels, generation counts and final
+    populations as the oracle's scheme."""
+    print(f"case ims {label}", flush=True)
+    g = maker()
+    target = g.total_weight if to_opt else 1 << 62
+    inst = gom.Instance(g.n, g.u, g.v, g.w, kind)
+    res, states = gom.gom_ims_run(inst, n_base, c_ims, levels, 11, target, budget,
+                                  forced_improvement=fi)
+    ptr, vars_ = oracle.fos(g, kind)
+    runs, order = oracle.ims_run(g, ptr, vars_, n_base, c_ims, levels, 11, target, budget,
+                                 flags=oracle.FLAG_FI if fi else 0)
+    assert res["levels"] == len(runs)
+    assert res["total_generations"] == len(order)
+    assert res["generations"] == [order.count(lvl + 1) for lvl in range(len(runs))]
+    for lvl, r in enumerate(runs):
+        assert_same(gom.gom_state_read(states[lvl]), r.state(), f"{label} level {lvl + 1}")
+    best = max(r.state(genes=False)["elite_fitness"] for r in runs)
+    assert res["best"] == best and res["reached"] == (best >= target)
 
 
 STOP_CASES = [

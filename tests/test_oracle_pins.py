@@ -571,6 +571,45 @@ def test_forced_improvement_invariants(n, d, kind, pop):
                 assert np.array_equal(s1["genes"][i], r1["genes"][i]), (gen, i)
 
 
+def test_ims_generation_order():
+    """The interleaving of the multi-start scheme against a hand-derived order, and each
+    level's population size and seed."""
+    spec = {}
+    for line in open(os.path.join(GOLDEN, "ims_order.txt")):
+        t = line.split()
+        if t and not t[0].startswith("#"):
+            spec[t[0]] = [int(x) for x in t[1:]]
+    g = workloads.torus(6, 1, 9, seed=2)
+    ptr, vars_ = oracle.fos(g, 0)
+    runs, order = oracle.ims_run(g, ptr, vars_, n_base=4, c_ims=spec["c"][0],
+                                 max_levels=spec["levels"][0], seed=7, target=1 << 62,
+                                 max_total_generations=len(spec["order"]))
+    assert order == spec["order"]
+    assert [r.N for r in runs] == [4, 8, 16]
+    for lvl, r in enumerate(runs, start=1):
+        alone = oracle.Run(g, ptr, vars_, pop=4 << (lvl - 1), seed=7 + lvl - 1)
+        for _ in range(order.count(lvl)):
+            alone.generation()
+        assert np.array_equal(alone.state()["genes"], r.state()["genes"]), lvl
+
+
+def test_ims_stops_at_target():
+    """The scheme stops after the step in which some level's elitist reaches the target."""
+    g = workloads.torus(6, 1, 9, seed=2)
+    ptr, vars_ = oracle.fos(g, 1)
+    runs, order = oracle.ims_run(g, ptr, vars_, n_base=4, c_ims=4, max_levels=3, seed=3,
+                                 target=g.total_weight, max_total_generations=500)
+    best = [r.state(genes=False)["elite_fitness"] for r in runs]
+    assert max(best) >= g.total_weight and len(order) < 500
+    # one step earlier no level had reached it: rerun with the budget cut before the last step
+    last_step = len(order) - 1
+    while last_step > 0 and order[last_step] != 1:
+        last_step -= 1
+    runs2, order2 = oracle.ims_run(g, ptr, vars_, n_base=4, c_ims=4, max_levels=3, seed=3,
+                                   target=g.total_weight, max_total_generations=last_step)
+    assert max(r.state(genes=False)["elite_fitness"] for r in runs2) < g.total_weight
+
+
 def test_initial_population_rule():
     g = workloads.torus(12, 1, 3, seed=2)
     ptr, vars_ = oracle.fos(g, 0)

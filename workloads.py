@@ -147,6 +147,9 @@ WORKLOADS = {
 # 1000x1000 torus (10^6 vertices), weights U{1..100}: the HBM-bound size.
 WORKLOADS["torus1000_uni_p64"] = Workload("torus1000_uni_p64", _t1000, 0, 64, 1000, True)
 WORKLOADS["torus1000_nbhd_p64"] = Workload("torus1000_nbhd_p64", _t1000, 1, 64, 1000, True)
+# 32x32 torus, weights U{1..100}, neighbourhood FOS: small enough to reach its optimum.
+WORKLOADS["torus32_nbhd_p64"] = Workload("torus32_nbhd_p64", lambda: torus(32, 1, 100, seed=8),
+                                         1, 64, 500, True)
 # 100x100 torus with fixed linkage trees: the full tree and trees bounded to 10 and 100.
 for _b in (0, 10, 100):
     _name = f"torus100_bflt{_b}_p64" if _b else "torus100_flt_p64"
