@@ -123,27 +123,32 @@ constexpr int kSmallSet = 14;         // members held in a small record's header
 constexpr int kSmallPosShift = 27;    // bits 27..30 of a small entry: member position
 constexpr int32_t kMaxVertexSmall = 1 << kSmallPosShift;  // vertex limit of a state
 
-// Class positions of the sets swept by a whole block (general FOS only): pos[ptr[c] ..
-// ptr[c+1]) for class c, and the largest of them per class.
+// Class positions of the sets swept by a whole block (general FOS only), per class in two
+// groups: sets of up to kCoopSmallBlock members (256-thread blocks), then larger ones
+// (1024-thread blocks).  Group g of class c: pos[ptr[2c + g] .. ptr[2c + g + 1]); the
+// largest set of each group in max_members[2c + g].
 struct CoopSets {
     std::vector<int32_t> ptr, pos, max_members;
 };
 
 CoopSets coop_sets(const gom_fos &f, bool univariate) {
     CoopSets C;
-    C.ptr.assign((size_t)f.k + 1, 0);
-    C.max_members.assign((size_t)f.k, 0);
-    for (int32_t c = 0; c < f.k; ++c) {
-        if (!univariate)
-            for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t) {
-                const int32_t j = f.class_elems[t];
-                const int32_t nm = f.ptr[(size_t)j + 1] - f.ptr[j];
-                if (nm < kCoopMinMembers || nm > kCoopMaxMembers) continue;
-                C.pos.push_back(t - f.class_ptr[c]);
-                C.max_members[c] = std::max(C.max_members[c], nm);
-            }
-        C.ptr[(size_t)c + 1] = (int32_t)C.pos.size();
-    }
+    C.ptr.assign(2 * (size_t)f.k + 1, 0);
+    C.max_members.assign(2 * (size_t)f.k, 0);
+    for (int32_t c = 0; c < f.k; ++c)
+        for (int grp = 0; grp < 2; ++grp) {
+            if (!univariate)
+                for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t) {
+                    const int32_t j = f.class_elems[t];
+                    const int32_t nm = f.ptr[(size_t)j + 1] - f.ptr[j];
+                    if (nm < kCoopMinMembers || nm > kCoopMaxMembers) continue;
+                    if ((nm > kCoopSmallBlock) != (grp == 1)) continue;
+                    C.pos.push_back(t - f.class_ptr[c]);
+                    C.max_members[2 * (size_t)c + grp] =
+                        std::max(C.max_members[2 * (size_t)c + grp], nm);
+                }
+            C.ptr[2 * (size_t)c + grp + 1] = (int32_t)C.pos.size();
+        }
     return C;
 }
 
@@ -871,18 +876,21 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         KernelEvents ev;
         int rc = forced ? GOM_OK : timing_events(s, &ev);
         if (rc) return rc;
-        const int32_t nl = s->coop_ptr[(size_t)c + 1] - s->coop_ptr[c];
+        const int32_t nl = s->coop_ptr[2 * (size_t)c + 2] - s->coop_ptr[2 * (size_t)c];
         a.coop = nl > 0 ? 1 : 0;
         if (s->sched == GOM_SCHED_BITSLICED && !forced)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st, ev));
         else
             HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, s->sweep_threads,
                                        st, ev));
-        if (nl > 0) {
+        for (int grp = 0; grp < 2; ++grp) {
+            const size_t q = 2 * (size_t)c + grp;
             SweepArgs b = a;
-            b.n_large = nl;
-            b.large_pos = s->d_coop + s->coop_ptr[c];
-            HIP_TRY(launch_large_set_sweep(b, s->coop_max[c], st));
+            b.n_large = s->coop_ptr[q + 1] - s->coop_ptr[q];
+            if (b.n_large == 0) continue;
+            b.large_pos = s->d_coop + s->coop_ptr[q];
+            b.coop_cap = s->coop_max[q];
+            HIP_TRY(launch_large_set_sweep(b, s->coop_max[q], grp ? 1024 : kCoopSmallBlock, st));
         }
     }
     return GOM_OK;

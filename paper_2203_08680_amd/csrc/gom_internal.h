@@ -110,14 +110,17 @@ struct SweepArgs {
     const uint64_t *E;      // elitist bits (forced improvement)
     int32_t coop;           // sets of kCoopMinMembers..kCoopMaxMembers members are left to
                             // the block-cooperative sweep (class launch, general FOS)
-    int32_t n_large;        // block-cooperative sweep: number of such sets in the class
+    int32_t n_large;        // block-cooperative sweep: number of such sets in the launch
     const int32_t *large_pos;  // ... and their class positions
+    int32_t coop_cap;       // ... LDS words reserved per member array (the largest set)
 };
 
-// Sets at least this large are swept by a whole block (members split over its waves, one
-// flip mask per member in LDS), up to the LDS capacity for those masks.
-constexpr int kCoopMinMembers = 65;
-constexpr int kCoopMaxMembers = 16384;
+// Sets larger than the inline-member records are swept by a whole block (members split over
+// its waves, a change mask and the offspring word of every member in LDS), up to the LDS
+// capacity for those arrays; blocks of 256 threads up to kCoopSmallBlock members, else 1024.
+constexpr int kCoopMinMembers = 15;
+constexpr int kCoopMaxMembers = 8192;
+constexpr int kCoopSmallBlock = 256;
 
 // Generation end, in two launches: k_finalize (one block: fitness from the stripes, best
 // solution, elitist decision, counters, generation count) then k_vertex_pass (all vertices:
@@ -213,7 +216,8 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
 // Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
 // Block-cooperative sweep of the large sets of one class (a.n_large blocks); max_members:
 // the largest of them (dynamic LDS of 8 bytes per member).
-hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, hipStream_t s);
+hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threads,
+                                  hipStream_t s);
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
                                  hipStream_t s, KernelEvents ev = {});
 // plds: keep a copy of P in LDS (needs resident_lds_bytes(n, true) of LDS).

@@ -613,13 +613,16 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
 // Forced improvement (mode kSweepFi): the elitist is the donor.  Sets of one class are
 // independent, so blocks never touch each other's words.
 // ------------------------------------------------------------------------------------------
-constexpr int kCoopThreads = 512;
+constexpr int kCoopMaxThreads = 1024;
+constexpr int kCoopUnroll = 4;   // members per wave and step
+constexpr int kCoopEdges = 8;    // entries of a member fetched together
 
-__global__ __launch_bounds__(kCoopThreads) void k_large_set_sweep(SweepArgs a) {
-    extern __shared__ uint64_t cmw[];
-    constexpr int W = kCoopThreads / 64;
-    __shared__ uint64_t red[W][64];
-    __shared__ int64_t redd[W][64];
+__global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a) {
+    extern __shared__ uint64_t cmw[];        // change masks, then offspring words (om)
+    uint64_t *om = cmw + a.coop_cap;
+    const int W = (int)(blockDim.x >> 6);
+    __shared__ uint64_t red[kCoopMaxThreads / 64][64];
+    __shared__ int64_t redd[kCoopMaxThreads / 64][64];
     __shared__ uint32_t sel[64];
     __shared__ uint64_t accm_s;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -647,18 +650,28 @@ __global__ __launch_bounds__(kCoopThreads) void k_large_set_sweep(SweepArgs a) {
     const EliteWords ew{a.E};
     auto donor_word = [&](int u) { return fi ? ew[u] : a.P[u]; };
 
+    // Members are taken kCoopUnroll at a time by each wave (chunks k0 .. k0 + 3), so that
+    // the loads of several members are in flight together.
     // 1. eligible donors
     uint64_t D = 0;
-    for (int k = w; k < nm; k += W) {
-        const int u = mem[k];
-        D |= donor_word(u) ^ (0ull - (uint64_t)bit_of(a.O[u], i));
+    for (int k0 = w * kCoopUnroll; k0 < nm; k0 += W * kCoopUnroll) {
+#pragma unroll
+        for (int c = 0; c < kCoopUnroll; ++c) {
+            const int k = k0 + c;
+            const int u = mem[k < nm ? k : 0];
+            const uint64_t o = a.O[u];
+            const uint64_t t = donor_word(u) ^ (0ull - (uint64_t)bit_of(o, i));
+            if (k < nm) {
+                D |= t;
+                if (lane == 0) om[k] = o;
+            }
+        }
     }
     red[w][lane] = D;
     __syncthreads();
     uint32_t cnt = 0, d = 0;
     if (w == 0) {
         D = 0;
-#pragma unroll
         for (int q = 0; q < W; ++q) D |= red[q][lane];
         D &= cand;
         cnt = (uint32_t)__popcll(D);
@@ -678,37 +691,52 @@ __global__ __launch_bounds__(kCoopThreads) void k_large_set_sweep(SweepArgs a) {
     d = sel[lane];
     cnt = (uint32_t)red[0][lane];
     // 2. change masks per member
-    for (int k = w; k < nm; k += W) {
-        const int u = mem[k];
-        const uint32_t flip = bit_of(donor_word(u), d) ^ bit_of(a.O[u], i);
-        const uint64_t m = ballot64(flip != 0 && cnt > 0);
-        if (lane == 0) cmw[k] = m;
+    for (int k0 = w * kCoopUnroll; k0 < nm; k0 += W * kCoopUnroll) {
+#pragma unroll
+        for (int c = 0; c < kCoopUnroll; ++c) {
+            const int k = k0 + c;
+            const int kk = k < nm ? k : 0;
+            const uint32_t flip = bit_of(donor_word(mem[kk]), d) ^ bit_of(om[kk], i);
+            const uint64_t m = ballot64(flip != 0 && cnt > 0);
+            if (lane == 0 && k < nm) cmw[k] = m;
+        }
     }
     __syncthreads();
-    // 3. fitness change over the dependent edges
+    // 3. fitness change over the dependent edges: each member's first kCoopEdges entries
+    // are fetched together (masked past the member's end), longer lists continue in a loop
     int64_t dl = 0;
-    for (int k = w; k < nm; k += W) {
-        const int u = mem[k];
-        const uint32_t oa = bit_of(a.O[u], i), ca = bit_of(cmw[k], i);
-        for (int e = k ? end[k - 1] : 0, e1 = end[k]; e < e1; ++e) {
-            const int2 en = E[e];
-            uint32_t ov, flip;
-            if (en.x >= 0) {
-                ov = bit_of(a.O[en.x], i);
-                flip = ca;
-            } else {
-                const int b = ~en.x;
-                ov = bit_of(a.O[mem[b]], i);
-                flip = ca ^ bit_of(cmw[b], i);
+    auto edge = [&](int2 en, uint32_t oa, uint32_t ca) -> int64_t {
+        uint32_t ov, flip;
+        if (en.x >= 0) {
+            ov = bit_of(a.O[en.x], i);
+            flip = ca;
+        } else {
+            const int b = ~en.x;
+            ov = bit_of(om[b], i);
+            flip = ca ^ bit_of(cmw[b], i);
+        }
+        return flip ? signed_w(oa == ov, en.y) : 0;
+    };
+    for (int k0 = w * kCoopUnroll; k0 < nm; k0 += W * kCoopUnroll) {
+#pragma unroll
+        for (int c = 0; c < kCoopUnroll; ++c) {
+            const int k = k0 + c;
+            if (k >= nm) break;
+            const uint32_t oa = bit_of(om[k], i), ca = bit_of(cmw[k], i);
+            const int e0 = k ? end[k - 1] : 0, e1 = end[k];
+#pragma unroll
+            for (int t = 0; t < kCoopEdges; ++t) {
+                const int e = e0 + t;
+                const int2 en = E[e < e1 ? e : e0];
+                if (e < e1) dl += edge(en, oa, ca);
             }
-            dl += flip ? signed_w(oa == ov, en.y) : 0;
+            for (int e = e0 + kCoopEdges; e < e1; ++e) dl += edge(E[e], oa, ca);
         }
     }
     redd[w][lane] = dl;
     __syncthreads();
     if (w == 0) {
         int64_t delta = 0;
-#pragma unroll
         for (int q = 0; q < W; ++q) delta += redd[q][lane];
         const bool acc = cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
         const uint64_t am = ballot64(acc);
@@ -730,9 +758,9 @@ __global__ __launch_bounds__(kCoopThreads) void k_large_set_sweep(SweepArgs a) {
     // 4. commit
     const uint64_t am = accm_s;
     if (am)
-        for (int k = w; k < nm; k += W) {
+        for (int k = threadIdx.x; k < nm; k += (int)blockDim.x) {
             const uint64_t m = cmw[k] & am;
-            if (m && lane == 0) a.O[mem[k]] ^= m;
+            if (m) a.O[mem[k]] ^= m;
         }
 }
 
@@ -1313,10 +1341,13 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
     return hipGetLastError();
 }
 
-hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, hipStream_t s) {
+hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threads,
+                                  hipStream_t s) {
     if (a.n_large < 1) return hipSuccess;
-    if (max_members < 1 || max_members > kCoopMaxMembers) return hipErrorInvalidValue;
-    const size_t lds = sizeof(uint64_t) * (size_t)max_members;
+    if (max_members < 1 || max_members > kCoopMaxMembers || a.coop_cap < max_members ||
+        threads < 64 || threads > kCoopMaxThreads || threads % 64)
+        return hipErrorInvalidValue;
+    const size_t lds = 2 * sizeof(uint64_t) * (size_t)a.coop_cap;
     static size_t attr_bytes = 0;
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k_large_set_sweep,
@@ -1324,7 +1355,7 @@ hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, hipStream
         if (e != hipSuccess) return e;
         attr_bytes = lds;
     }
-    hipLaunchKernelGGL(k_large_set_sweep, dim3(a.n_large), dim3(kCoopThreads), lds, s, a);
+    hipLaunchKernelGGL(k_large_set_sweep, dim3(a.n_large), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
