@@ -76,13 +76,13 @@ struct gom_fos {
 namespace {
 
 struct Layout {
-    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, coop, total;
+    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, coop, sw, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
-                   int64_t rec_words, int64_t n_coop) {
+                   int64_t rec_words, int64_t n_coop, int64_t sw_words) {
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -105,6 +105,7 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
     L.roff = take(sizeof(int32_t) * (size_t)(n_sets + 1));
     L.recs = take(sizeof(int32_t) * (size_t)rec_words);
     L.coop = take(sizeof(int32_t) * (size_t)n_coop);
+    L.sw = take(sizeof(int32_t) * (size_t)sw_words);
     L.total = o;
     return L;
 }
@@ -152,6 +153,65 @@ CoopSets coop_sets(const gom_fos &f, bool univariate) {
     return C;
 }
 
+// Truth tables of a univariate set {u} with at most 4 edges, for the bit-sliced sweep: bit p
+// of the low half = (flip gain > 0), of the high half = (gain == 0), for the pattern p of
+// edges whose far end carries the same gene (bit e set: edge e gains +w_e).  Edges beyond the
+// vertex's degree have weight 0.
+uint32_t uni_tables(const mc_graph &g, int32_t u) {
+    const int32_t nd = g.row_ptr[(size_t)u + 1] - g.row_ptr[u];
+    if (nd > 4) return 0;
+    int64_t wl[4] = {0, 0, 0, 0}, tot = 0;
+    for (int32_t e = 0; e < nd; ++e) {
+        wl[e] = g.wt[(size_t)g.row_ptr[u] + e];
+        tot += wl[e];
+    }
+    uint32_t tables = 0;
+    for (uint32_t pt = 0; pt < 16; ++pt) {
+        int64_t d = -tot;
+        for (int e = 0; e < 4; ++e)
+            if (pt >> e & 1u) d += 2 * wl[e];
+        tables |= (uint32_t)(d > 0) << pt | (uint32_t)(d == 0) << (pt + 16);
+    }
+    return tables;
+}
+
+// The bit-sliced schedule handles univariate FOS on graphs of degree <= 4 whose per-vertex
+// sums of |w| stay below 2^30 (its per-solution gains are int32).
+bool swar_eligible(const mc_graph &g, const gom_fos &f) {
+    if (f.max_set != 1 || g.max_degree > 4) return false;
+    int64_t max_abs = 0;
+    for (int32_t v = 0; v < g.n; ++v) {
+        int64_t t = 0;
+        for (int32_t r = g.row_ptr[v]; r < g.row_ptr[(size_t)v + 1]; ++r)
+            t += g.wt[r] < 0 ? -(int64_t)g.wt[r] : (int64_t)g.wt[r];
+        max_abs = std::max(max_abs, t);
+    }
+    return max_abs < ((int64_t)1 << 30);
+}
+
+int32_t swar_stride(int32_t n_sets) { return (n_sets + 63) & ~63; }
+
+// The bit-sliced sweep's table (kSwRows arrays of swar_stride words, entry s = class position
+// s of the colour classes in order): u, its truth tables, its neighbours (u itself where the
+// vertex has fewer than 4), their weights (0 there).
+std::vector<int32_t> build_swar(const mc_graph &g, const gom_fos &f) {
+    const size_t ss = (size_t)swar_stride(f.n_sets);
+    std::vector<int32_t> T(kSwRows * ss, 0);
+    int32_t s = 0;
+    for (int32_t c = 0; c < f.k; ++c)
+        for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t, ++s) {
+            const int32_t u = f.vars[f.ptr[f.class_elems[t]]];
+            T[kSwU * ss + s] = u;
+            T[kSwTables * ss + s] = (int32_t)uni_tables(g, u);
+            const int32_t r0 = g.row_ptr[u], nd = g.row_ptr[(size_t)u + 1] - r0;
+            for (int e = 0; e < 4; ++e) {
+                T[(kSwV + e) * ss + s] = e < nd ? g.col[(size_t)r0 + e] : u;
+                T[(kSwW + e) * ss + s] = e < nd ? g.wt[(size_t)r0 + e] : 0;
+            }
+        }
+    return T;
+}
+
 int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records &R) {
     const int32_t S = f.n_sets;
     std::vector<int32_t> pos((size_t)g.n, -1), owner((size_t)g.n, -1);
@@ -176,24 +236,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
             if (univariate) {
                 const int32_t u = f.vars[b];
                 const int32_t nd = g.row_ptr[(size_t)u + 1] - g.row_ptr[u];
-                // with at most 4 edges: the bit-sliced sweep's truth tables, bit p of the low
-                // half = (flip gain > 0), of the high half = (gain == 0), for the pattern p of
-                // edges whose far end carries the same gene (bit e set: edge e gains +w_e)
-                uint32_t tables = 0;
-                if (nd <= 4) {
-                    int64_t wl[4] = {0, 0, 0, 0}, tot = 0;
-                    for (int32_t e = 0; e < nd; ++e) {
-                        wl[e] = g.wt[(size_t)g.row_ptr[u] + e];
-                        tot += wl[e];
-                    }
-                    for (uint32_t pt = 0; pt < 16; ++pt) {
-                        int64_t d = -tot;
-                        for (int e = 0; e < 4; ++e)
-                            if (pt >> e & 1u) d += 2 * wl[e];
-                        tables |= (uint32_t)(d > 0) << pt | (uint32_t)(d == 0) << (pt + 16);
-                    }
-                }
-                R.words.insert(R.words.end(), {u, nd, (int32_t)tables, 0});
+                R.words.insert(R.words.end(), {u, nd, 0, 0});
                 for (int32_t r = g.row_ptr[u]; r < g.row_ptr[(size_t)u + 1]; ++r) {
                     R.words.push_back(g.col[r]);
                     R.words.push_back(g.wt[r]);
@@ -308,6 +351,8 @@ struct gom_state {
     std::vector<int2> class_rec;  // host copy of the per-class record placement
     std::vector<int32_t> coop_ptr, coop_max;  // large sets per class (block-cooperative)
     int32_t *d_coop = nullptr;                // their class positions
+    int32_t *d_sw = nullptr;                  // bit-sliced sweep table (when eligible)
+    int32_t sw_stride = 0;
     int32_t g_host = 0;                 // next generation index to enqueue
     int32_t open_next = -1;             // class position where an open generation resumes
     int32_t g_base = 0;                 // generation at which attempted_base was set
@@ -751,8 +796,9 @@ extern "C" int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop,
     rc = build_records(*g, *f, f->max_set == 1, R);
     if (rc) return rc;
     const CoopSets CS = coop_sets(*f, f->max_set == 1);
+    const int64_t sw_words = swar_eligible(*g, *f) ? (int64_t)kSwRows * swar_stride(f->n_sets) : 0;
     *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
-                         (int64_t)CS.pos.size()).total;
+                         (int64_t)CS.pos.size(), sw_words).total;
     return GOM_OK;
     GUARD_END
 }
@@ -861,6 +907,8 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
     a.st = s->d_st;
     a.roff = s->d_roff;
     a.recs = s->d_recs;
+    a.sw = s->d_sw;
+    a.sw_stride = s->sw_stride;
     a.seed = s->seed;
     a.target = target;
     a.N = s->N;
@@ -978,8 +1026,10 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     rc = build_records(*g, *f, f->max_set == 1, R);
     if (rc) return rc;
     const CoopSets CS = coop_sets(*f, f->max_set == 1);
+    const bool swar = swar_eligible(*g, *f);
+    const std::vector<int32_t> SW = swar ? build_swar(*g, *f) : std::vector<int32_t>();
     const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
-                                 (int64_t)CS.pos.size());
+                                 (int64_t)CS.pos.size(), (int64_t)SW.size());
     if (arena_bytes < L.total)
         return fail(GOM_E_NOMEM, "gom_state_init: arena has %zu bytes, needs %zu", arena_bytes,
                     L.total);
@@ -1017,6 +1067,8 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->coop_ptr = CS.ptr;
     s->coop_max = CS.max_members;
     s->d_coop = (int32_t *)(s->arena + L.coop);
+    s->d_sw = (int32_t *)(s->arena + L.sw);
+    s->sw_stride = swar_stride(f->n_sets);
     auto cleanup = [&](int code) {
         gom_state_free(s);
         return code;
@@ -1041,14 +1093,7 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
         s->resident_ok = e == hipSuccess && s->k <= kResidentMaxClasses &&
                          resident_lds_bytes(s->n, false) <= s->lds_max;
         s->resident_plds = s->resident_ok && resident_lds_bytes(s->n, true) <= s->lds_max;
-        int64_t max_abs = 0;
-        for (int32_t v = 0; v < g->n; ++v) {
-            int64_t t = 0;
-            for (int32_t r = g->row_ptr[v]; r < g->row_ptr[(size_t)v + 1]; ++r)
-                t += g->wt[r] < 0 ? -(int64_t)g->wt[r] : (int64_t)g->wt[r];
-            max_abs = std::max(max_abs, t);
-        }
-        s->bitsliced_ok = s->univariate && g->max_degree <= 4 && max_abs < ((int64_t)1 << 30);
+        s->bitsliced_ok = swar;
         s->partition = s->univariate && f->n_sets == g->n;
         s->sched = auto_schedule(s);
     }
@@ -1057,6 +1102,7 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     if (e == hipSuccess)
         e = h2d(s->d_crec, R.class_rec.data(), sizeof(int2) * R.class_rec.size());
     if (e == hipSuccess) e = h2d(s->d_coop, CS.pos.data(), sizeof(int32_t) * CS.pos.size());
+    if (e == hipSuccess) e = h2d(s->d_sw, SW.data(), sizeof(int32_t) * SW.size());
     if (e == hipSuccess) e = enqueue_initial_population(s, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging buffers die below
     if (e != hipSuccess)

@@ -113,7 +113,15 @@ struct SweepArgs {
     int32_t n_large;        // block-cooperative sweep: number of such sets in the launch
     const int32_t *large_pos;  // ... and their class positions
     int32_t coop_cap;       // ... LDS words reserved per member array (the largest set)
+    const int32_t *sw;      // bit-sliced sweep table (univariate FOS, degree <= 4): kSwRows
+                            // arrays of sw_stride words, entry s = class position s
+    int32_t sw_stride;
 };
+
+// The bit-sliced sweep's per-set table, one array per row so every load is coalesced: the
+// variable u, its truth tables, its (up to 4) neighbours, then their edge weights.  A missing
+// neighbour is u itself with weight 0.
+enum { kSwU = 0, kSwTables = 1, kSwV = 2, kSwW = 6, kSwRows = 10 };
 
 // Sets larger than the inline-member records are swept by a whole block (members split over
 // its waves, a change mask and the offspring word of every member in LDS), up to the LDS

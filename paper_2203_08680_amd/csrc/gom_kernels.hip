@@ -67,22 +67,60 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return x * per + (x < rem ? x : rem) + q;
 }
 
-__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
+// Wave reductions with a wave-uniform result.  Each of the four 16-lane rows is reduced by
+// DPP rotations of 1, 2, 4 and 8 lanes (after step k every lane holds its row's 2^k-lane
+// cyclic window, so after the fourth step the whole row, each lane counted once); the rows'
+// results are then read from lanes 0, 16, 32 and 48.  Every lane of the wave must be active.
+constexpr int kDppRor1 = 0x121, kDppRor2 = 0x122, kDppRor4 = 0x124, kDppRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t read_lane(uint32_t x, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+
+__device__ __forceinline__ uint32_t row_or32(uint32_t x) {
+    x |= dpp_u32<kDppRor1>(x);
+    x |= dpp_u32<kDppRor2>(x);
+    x |= dpp_u32<kDppRor4>(x);
+    x |= dpp_u32<kDppRor8>(x);
     return x;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+    const uint32_t lo = row_or32((uint32_t)x), hi = row_or32((uint32_t)(x >> 32));
+    const uint32_t l = read_lane(lo, 0) | read_lane(lo, 16) | read_lane(lo, 32) | read_lane(lo, 48);
+    const uint32_t h = read_lane(hi, 0) | read_lane(hi, 16) | read_lane(hi, 32) | read_lane(hi, 48);
+    return ((uint64_t)h << 32) | l;
 }
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp_u32<kDppRor1>(x);
+    x += dpp_u32<kDppRor2>(x);
+    x += dpp_u32<kDppRor4>(x);
+    x += dpp_u32<kDppRor8>(x);
+    return read_lane(x, 0) + read_lane(x, 16) + read_lane(x, 32) + read_lane(x, 48);
 }
 
-__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+    return ((uint64_t)dpp_u32<CTRL>((uint32_t)(x >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)x);
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+    uint64_t x = (uint64_t)v;  // two's complement: the sum modulo 2^64 is the int64 sum
+    x += dpp_u64<kDppRor1>(x);
+    x += dpp_u64<kDppRor2>(x);
+    x += dpp_u64<kDppRor4>(x);
+    x += dpp_u64<kDppRor8>(x);
+    uint64_t s = 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    for (int r = 0; r < 64; r += 16)
+        s += ((uint64_t)read_lane((uint32_t)(x >> 32), r) << 32) | read_lane((uint32_t)x, r);
+    return (int64_t)s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -221,6 +259,22 @@ __device__ __forceinline__ uint64_t solution_mask(bool flag) {
     return m;
 }
 
+// A load through the constant address space.  With a wave-uniform address the backend turns
+// it into a scalar load (into SGPRs, through the scalar cache, no lane broadcast).  Only for
+// memory that no kernel writes while another reads it (the set records).
+template <class T>
+__device__ __forceinline__ T const_load(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+__device__ __forceinline__ int4 const_load(const int4 *p) {
+    const int32_t *q = reinterpret_cast<const int32_t *>(p);
+    return make_int4(const_load(q), const_load(q + 1), const_load(q + 2), const_load(q + 3));
+}
+__device__ __forceinline__ int2 const_load(const int2 *p) {
+    const int32_t *q = reinterpret_cast<const int32_t *>(p);
+    return make_int2(const_load(q), const_load(q + 1));
+}
+
 // Offspring bits of solution i in the O planes (class-launch schedule).
 struct PlaneBits {
     static constexpr bool kLocal = false;  // reads go to global memory
@@ -264,20 +318,16 @@ struct AosRec {
 };
 
 // Reader for a record that every lane of the wave reads (class launch with one set per wave):
-// each loaded word is made wave-uniform, so the record's decoding runs on the scalar unit.
+// the record address is wave-uniform, so its words are scalar loads and its decoding runs on
+// the scalar unit.
 struct UniformAosRec {
     const int32_t *R;
-    __device__ __forceinline__ static int32_t u(int32_t x) {
-        return __builtin_amdgcn_readfirstlane(x);
-    }
-    __device__ __forceinline__ int32_t w(int k) const { return u(R[k]); }
+    __device__ __forceinline__ int32_t w(int k) const { return const_load(R + k); }
     __device__ __forceinline__ int4 q(int k) const {
-        const int4 v = reinterpret_cast<const int4 *>(R)[k];
-        return make_int4(u(v.x), u(v.y), u(v.z), u(v.w));
+        return const_load(reinterpret_cast<const int4 *>(R) + k);
     }
     __device__ __forceinline__ int2 e(int base, int t) const {
-        const int2 v = reinterpret_cast<const int2 *>(R + base)[t];
-        return make_int2(u(v.x), u(v.y));
+        return const_load(reinterpret_cast<const int2 *>(R + base) + t);
     }
 };
 
@@ -503,7 +553,7 @@ struct PlaneCommit {
     }
 };
 
-template <int G, int KIND>
+template <int G, int KIND, bool FI>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     constexpr int GPW = 64 / G;          // sets per wave
     const int lane = threadIdx.x & 63;
@@ -513,54 +563,56 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     const int gw = xcd_tile((int)blockIdx.x, (int)gridDim.x) * wpb +
                    (int)(threadIdx.x >> 6);                        // global wave (tile order)
     const int nwaves = gridDim.x * wpb;
-    // one set per wave (G = 64): the record is wave-uniform
-    using Rec = std::conditional_t<G == 64, UniformAosRec, AosRec>;
+    // one set per wave (G = 64): the record is wave-uniform (scalar loads); with several sets
+    // per wave it is read with per-lane vector loads
+    constexpr bool U = G == 64;
+    using Rec = std::conditional_t<U, UniformAosRec, AosRec>;
     auto record = [&](int p) {
         return Rec{a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p]};
     };
-    // issue the first record's loads together with the run-state loads
-    const uint64_t mism = a.stripes[lane].mism;
-    const uint64_t acc_prev = a.mode == kSweepFi ? a.stripes[lane].acc : 0ull;
-    const uint64_t fimp_prev = a.mode == kSweepFi ? a.stripes[lane].fimp : 0ull;
-    const int64_t elite_fitness = a.st->elite_fitness;
-    int p = gw * GPW + grp;
-    if constexpr (G == 64) p = __builtin_amdgcn_readfirstlane(p);
+    auto position = [&](int wt) {
+        const int q = wt * GPW + grp;
+        return U ? __builtin_amdgcn_readfirstlane(q) : q;
+    };
+    // the first record's loads are issued before anything waits: the run-state loads and the
+    // stripe reductions below overlap with them
+    int p = position(gw);
     Rec R = record(p < a.csize ? p : 0);
     Head hd = load_head<KIND>(R);
-    if (elite_fitness >= a.target) return;
+    // (no branch before the loop: it would split the block and delay the record loads)
+    const uint64_t mism = a.stripes[lane].mism;
+    const int64_t elite_fitness = a.st->elite_fitness;
     const bool act = (int)i < a.N;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
-    const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
-    if (a.mode == kSweepFi) {
+    const bool neutral_ok = (a.always != 0) | (bit_of(wave_or64(mism), i) != 0);
+    // a finished run (elitist at the target) and a forced-improvement sweep with nothing
+    // left to do skip the loop; both conditions are wave-uniform
+    bool live = elite_fitness < a.target;
+    if constexpr (FI) {
         // forced improvement: solutions without an accepted step and not yet improved; the
         // elitist is the only donor
-        const uint64_t todo = popm & ~wave_or64(acc_prev) & ~wave_or64(fimp_prev);
-        if (todo == 0) return;
+        const uint64_t todo = popm & ~wave_or64(a.stripes[lane].acc) &
+                              ~wave_or64(a.stripes[lane].fimp);
+        live = live && todo != 0;
         cand = act && bit_of(todo, i) ? ~0ull : 0ull;
     }
 
     int64_t facc = 0;
-    uint32_t n_eval = 0, n_acc = 0;
+    uint32_t n_eval = 0, n_acc = 0;  // wave totals (from ballots, wave-uniform)
     bool flag = false;  // GOM: an accepted step; forced improvement: a step that improved
     const PlaneBits bits{a.O, i};
     const PlaneCommit<G> commit{a.O, grp, i};
     const int nwt = (a.csize + GPW - 1) / GPW;  // wave tiles
-    for (int wt = gw; wt < nwt; wt += nwaves) {
-        if (wt != gw) {
-            p = wt * GPW + grp;
-            if constexpr (G == 64) p = __builtin_amdgcn_readfirstlane(p);
-            R = record(p < a.csize ? p : 0);
-            hd = load_head<KIND>(R);
-        }
+    for (int wt = gw; live && wt < nwt;) {
         bool take = p < a.csize;
         if constexpr (KIND != 0) {
             const int nm = hd.h0.x;
             if (a.coop && nm >= kCoopMinMembers && nm <= kCoopMaxMembers) take = false;
         }
+        PairOut r{0u, false, 0};
         if (take) {
-            PairOut r;
-            if (a.mode == kSweepFi) {
+            if constexpr (FI) {
                 r = gom_pair<KIND>(R, hd, EliteWords{a.E}, bits, commit, cand, 0u, neutral_ok);
                 flag |= r.acc && r.delta > 0;
             } else {
@@ -578,15 +630,21 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
                 flag |= r.acc;
             }
             facc += r.acc ? r.delta : 0;
-            n_eval += r.cnt > 0;
-            n_acc += r.acc;
+        }
+        n_eval += (uint32_t)__popcll(ballot64(r.cnt > 0));
+        n_acc += (uint32_t)__popcll(ballot64(r.acc));
+        wt += nwaves;
+        if (wt < nwt) {
+            p = position(wt);
+            R = record(p < a.csize ? p : 0);
+            hd = load_head<KIND>(R);
         }
     }
 
     // per-wave results into stripe (global wave index mod kStripes)
 #pragma unroll
     for (int off = 32; off >= G; off >>= 1) facc += __shfl_xor(facc, off, 64);
-    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
+    const uint32_t ce = n_eval, ca = n_acc;
     Stripe *sp = a.stripes + (gw % kStripes);
     if (lane < G && act && facc)
         atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
@@ -595,8 +653,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
         if (ce) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)ce);
         if (ca) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)ca);
         if (fm)
-            atomicOr((unsigned long long *)(a.mode == kSweepFi ? &sp->fimp : &sp->acc),
-                     (unsigned long long)fm);
+            atomicOr((unsigned long long *)(FI ? &sp->fimp : &sp->acc), (unsigned long long)fm);
     }
 }
 
@@ -771,9 +828,9 @@ __global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a
 // For set {u} with edges (u, v_e, w_e), e < 4 (missing edges have w = 0):
 //   q_e    = ~(O[u] ^ O[v_e]): bit i set when u and v_e carry the same gene in O_i, so
 //            flipping u cuts the edge (+w_e); otherwise it uncuts it (-w_e)
-//   delta  of solution i depends only on the 4-bit pattern (q_0..q_3 at bit i): the record
-//            carries two 16-entry truth tables over the patterns (delta > 0, delta == 0),
-//            computed from the set's weights when the record was built; the lane evaluates
+//   delta  of solution i depends only on the 4-bit pattern (q_0..q_3 at bit i): the set's
+//            table entry carries two 16-entry truth tables over the patterns (delta > 0,
+//            delta == 0), computed from the set's weights on the host; the lane evaluates
 //            them on all 64 solutions at once with a tree of bitwise selects on q_0..q_3
 //   donor  exists for solution i when some other solution's P gene at u differs from
 //            O_i[u]: from the popcounts of the ones and zeros of P[u]
@@ -783,6 +840,9 @@ __global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a
 // are summed per solution in LDS and added to the block's stripe.
 // PARTITION: every variable is in exactly one set, so O[u] still equals P[u] when u's set
 // is swept and P[u] need not be read.
+// The sets come from the bit-sliced table (one array per field, entry = class position), so a
+// lane reads 24 bytes (u, tables, four neighbours) with six coalesced loads; the weights are
+// read only when one of the lane's solutions accepts.
 // ------------------------------------------------------------------------------------------
 constexpr int kSwarThreads = 256;
 
@@ -809,28 +869,38 @@ __device__ __forceinline__ uint64_t table16(uint32_t t, uint64_t q0, uint64_t q1
 
 template <bool PARTITION>
 __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
+    const int stride = gridDim.x * kSwarThreads;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const size_t ss = (size_t)a.sw_stride;
+    // the first set's table entry is loaded before anything waits (the run-state loads and
+    // the block barrier below overlap with it); positions past the class read a valid entry
+    // of the table and are not used
+    int p = tile * kSwarThreads + threadIdx.x;
+    struct Entry {
+        int u, v0, v1, v2, v3;
+        uint32_t tab;
+    };
+    auto entry = [&](int q) {
+        const int32_t *T = a.sw + a.cbase + (q < a.csize ? q : 0);
+        return Entry{T[kSwU * ss], T[kSwV * ss], T[(kSwV + 1) * ss], T[(kSwV + 2) * ss],
+                     T[(kSwV + 3) * ss], (uint32_t)T[kSwTables * ss]};
+    };
+    Entry en = entry(p);
     const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
-    if (a.st->elite_fitness >= a.target) return;
+    const bool live = a.st->elite_fitness < a.target;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
     __shared__ unsigned long long fa[64];
     __shared__ uint32_t redc[2][kSwarThreads / 64];
     if (threadIdx.x < 64) fa[threadIdx.x] = 0ull;
     __syncthreads();
+    if (!live) return;  // uniform over the grid
     uint32_t n_eval = 0, n_acc = 0;
-    const int stride = gridDim.x * kSwarThreads;
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    for (int p = tile * kSwarThreads + threadIdx.x; p < a.csize; p += stride) {
-        const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride
-                                     : a.recs + a.roff[a.cbase + p];
-        const int4 h = *reinterpret_cast<const int4 *>(R);
-        const int4 e01 = *reinterpret_cast<const int4 *>(R + 4);
-        const int4 e23 = *reinterpret_cast<const int4 *>(R + 8);
-        const int u = h.x, nd = h.y;
-        const int v0 = nd > 0 ? e01.x : u, v1 = nd > 1 ? e01.z : u;
-        const int v2 = nd > 2 ? e23.x : u, v3 = nd > 3 ? e23.z : u;
-        const int w0 = nd > 0 ? e01.y : 0, w1 = nd > 1 ? e01.w : 0;
-        const int w2 = nd > 2 ? e23.y : 0, w3 = nd > 3 ? e23.w : 0;
+    for (; p < a.csize; p += stride) {
+        if (p != tile * kSwarThreads + (int)threadIdx.x) en = entry(p);
+        const int32_t *T = a.sw + a.cbase + p;
+        const int u = en.u, v0 = en.v0, v1 = en.v1, v2 = en.v2, v3 = en.v3;
+        const uint32_t tab = en.tab;
         const uint64_t o = a.O[u];
         const uint64_t x = PARTITION ? o : a.P[u];
         const uint64_t q0 = ~(o ^ a.O[v0]), q1 = ~(o ^ a.O[v1]);
@@ -841,14 +911,18 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
         const uint64_t hz = cz >= 2 ? ~0ull : (cz == 1 ? ~zeros : 0ull);
         const uint64_t ho = co >= 2 ? ~0ull : (co == 1 ? ~ones : 0ull);
         const uint64_t has = ((o & hz) | (~o & ho)) & popm;
-        // truth tables over the 16 patterns, precomputed with the record (third header word)
-        const uint32_t tp = (uint32_t)h.z & 0xFFFFu, tz = (uint32_t)h.z >> 16;
+        // truth tables over the 16 patterns, precomputed on the host
+        const uint32_t tp = tab & 0xFFFFu, tz = tab >> 16;
         const uint64_t acc =
             (table16(tp, q0, q1, q2, q3) | (table16(tz, q0, q1, q2, q3) & nz)) & has;
         n_eval += (uint32_t)__popcll(has);
         n_acc += (uint32_t)__popcll(acc);
         if (acc) {
             a.O[u] = o ^ acc;
+            // the weights are needed only here: loading them with the entry for every set
+            // costs more than this extra round trip for the sets that accept
+            const int w0 = T[kSwW * ss], w1 = T[(kSwW + 1) * ss];
+            const int w2 = T[(kSwW + 2) * ss], w3 = T[(kSwW + 3) * ss];
             for (uint64_t m = acc; m; m &= m - 1) {
                 const uint32_t i = (uint32_t)__builtin_ctzll(m);
                 const int d = (bit_of(q0, i) ? w0 : -w0) + (bit_of(q1, i) ? w1 : -w1) +
@@ -1053,6 +1127,13 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
 __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     DevState *st = a.st;
     const int t = threadIdx.x;
+    // every load is issued before the first wait: one round trip
+    int64_t d = 0;
+#pragma unroll
+    for (int s = 0; s < kStripes; ++s) d += a.stripes[s].fit[t];
+    const int64_t fit_t = a.fit[t];
+    const uint64_t s_ev = a.stripes[t].evaluated, s_ac = a.stripes[t].accepted;
+    const uint64_t s_acc = a.stripes[t].acc, s_fimp = a.stripes[t].fimp;
     const int64_t fE = st->elite_fitness;
     if (a.mode == kEpiGeneration && fE >= a.target) {
         if (t == 0) st->active = 0;
@@ -1062,18 +1143,15 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     uint64_t fail = 0;
     if (a.fi && a.mode == kEpiGeneration) {
         const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-        fail = popm & ~wave_or64(a.stripes[t].acc) & ~wave_or64(a.stripes[t].fimp);
+        fail = popm & ~wave_or64(s_acc) & ~wave_or64(s_fimp);
     }
     int64_t f = INT64_MIN;
     if (t < a.N) {
-        int64_t d = 0;
-#pragma unroll 16
-        for (int s = 0; s < kStripes; ++s) d += a.stripes[s].fit[t];
-        f = bit_of(fail, (uint32_t)t) ? fE : a.fit[t] + d;
+        f = bit_of(fail, (uint32_t)t) ? fE : fit_t + d;
         a.fit[t] = f;
     }
-    const int64_t ev = wave_sum64((int64_t)a.stripes[t].evaluated);
-    const int64_t ac = wave_sum64((int64_t)a.stripes[t].accepted);
+    const int64_t ev = wave_sum64((int64_t)s_ev);
+    const int64_t ac = wave_sum64((int64_t)s_ac);
     int64_t fb = f;
     int b = t;
 #pragma unroll
@@ -1118,12 +1196,15 @@ __global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) { finalize_body
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
     const DevState *st = a.st;
-    if (!st->active) return;
-    const int b = st->best;
-    const bool newE = st->new_elite != 0;
     const int tid = threadIdx.x, lane = tid & 63;
     const int v = vblock * kEpiThreads + tid;
     const bool in = v < a.n;
+    // the vertex's words are loaded together with the run scalars (no wait in between)
+    const uint64_t o_plane = a.O[in ? v : 0];
+    const uint64_t e_word = a.E[(in ? v : 0) >> 6];
+    if (!st->active) return;
+    const int b = st->best;
+    const bool newE = st->new_elite != 0;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     uint64_t o = 0ull;
     if (a.rows) {
@@ -1139,12 +1220,12 @@ __device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
         }
         if (!in) o = 0ull;
     } else if (in) {
-        o = a.O[v];
+        o = o_plane;
     }
     if (a.mode == kEpiGeneration && in) {
         const uint64_t fail = st->fi_fail;
         if (fail) {  // copies of the elitist (its bits before this generation's update)
-            const uint64_t eo = 0ull - (uint64_t)bit_of(a.E[v >> 6], (uint32_t)(v & 63));
+            const uint64_t eo = 0ull - (uint64_t)bit_of(e_word, (uint32_t)(v & 63));
             o = (o & ~fail) | (eo & fail);
         }
         a.P[v] = o;
@@ -1156,7 +1237,7 @@ __device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
         const uint64_t word = ballot64(eb != 0);
         if (lane == 0 && in) a.E[v >> 6] = word;
     } else {
-        eb = in ? bit_of(a.E[v >> 6], (uint32_t)(v & 63)) : 0u;
+        eb = in ? bit_of(e_word, (uint32_t)(v & 63)) : 0u;
     }
     const uint64_t mism = wave_or64(in ? ((o ^ (0ull - (uint64_t)eb)) & popm) : 0ull);
     __shared__ uint64_t sm[kEpiThreads / 64];
@@ -1329,15 +1410,20 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
     const dim3 gd(grid), bd(threads);
-    if (kind == 0) {
-        if (G == 16) launch_timed(k_class_sweep<16, 0>, gd, bd, 0, s, ev, a);
-        else if (G == 32) launch_timed(k_class_sweep<32, 0>, gd, bd, 0, s, ev, a);
-        else launch_timed(k_class_sweep<64, 0>, gd, bd, 0, s, ev, a);
-    } else {
-        if (G == 16) launch_timed(k_class_sweep<16, 1>, gd, bd, 0, s, ev, a);
-        else if (G == 32) launch_timed(k_class_sweep<32, 1>, gd, bd, 0, s, ev, a);
-        else launch_timed(k_class_sweep<64, 1>, gd, bd, 0, s, ev, a);
-    }
+    auto go = [&](auto fi) {
+        constexpr bool FI = decltype(fi)::value;
+        if (kind == 0) {
+            if (G == 16) launch_timed(k_class_sweep<16, 0, FI>, gd, bd, 0, s, ev, a);
+            else if (G == 32) launch_timed(k_class_sweep<32, 0, FI>, gd, bd, 0, s, ev, a);
+            else launch_timed(k_class_sweep<64, 0, FI>, gd, bd, 0, s, ev, a);
+        } else {
+            if (G == 16) launch_timed(k_class_sweep<16, 1, FI>, gd, bd, 0, s, ev, a);
+            else if (G == 32) launch_timed(k_class_sweep<32, 1, FI>, gd, bd, 0, s, ev, a);
+            else launch_timed(k_class_sweep<64, 1, FI>, gd, bd, 0, s, ev, a);
+        }
+    };
+    if (a.mode == kSweepFi) go(std::true_type{});
+    else go(std::false_type{});
     return hipGetLastError();
 }
 
