@@ -126,6 +126,7 @@ def run_batch_mode(args, torch, gom):
     gom.gom_batch_run(wb, 2)
     del wb
     batch = gom.gom_batch_init(insts, pops, seeds, targets)
+    gom.gom_batch_set_graph(batch, args.batch_graph == "on")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res, tt = gom.gom_batch_run(batch, max_gens)
@@ -159,7 +160,9 @@ def run_batch_mode(args, torch, gom):
         "config": {"workload": f"batch{len(items)}_tori_and_regular_1e3_1e5",
                    "instances": len(items), "vertices": int(sum(x.n for x in insts)),
                    "pop_range": [16, 64], "max_generations": max_gens, "mode": "batched",
-                   "schedule": "batched_resident"},
+                   "schedule": "batched_resident",
+                   "generation_steps": ("hip_graph_chunks_of_4" if args.batch_graph == "on"
+                                        else "direct_launches")},
         "plain": {"value": ev_plain / t_plain, "ms": t_plain * 1e3,
                   "schedule": "auto per instance, one instance at a time"},
         "batched_over_plain": (ev_batch / t_batch) / (ev_plain / t_plain),
@@ -342,6 +345,8 @@ def main():
                     help="batched vs plain on the 256-instance mix instead of the default "
                          "single-instance workload")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
+                    help="batched steps as captured HIP graph chunks (default) or direct launches")
     ap.add_argument("--ims", action="store_true",
                     help="interleaved multi-start scheme (levels of 16, 32, 64) on the chosen "
                          "workload")

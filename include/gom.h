@@ -350,6 +350,17 @@ int gom_batch_init(int32_t count, const mc_graph *const *graphs, const gom_fos *
 int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream, gom_result *results,
                   double *time_to_target_ms);
 
+/*
+ * How gom_batch_run enqueues its generation steps: as one captured HIP graph per chunk of 4
+ * steps (enabled != 0, the default) or as separate kernel launches (enabled == 0).  The graph
+ * holds the chunk's 12 kernels (sweep, finalize and vertex pass of each step) and the gather
+ * of the instances' run scalars; it is captured on a private stream the first time it is
+ * needed and replayed on the caller's stream.  Chunks shorter than 4 steps (the end of a
+ * generation budget) are always launched directly.  Results are identical either way.
+ * Errors: GOM_E_ARG (null batch).
+ */
+int gom_batch_set_graph(gom_batch *b, int enabled);
+
 /* Borrowed handle of instance `index` (for gom_state_read); valid until gom_batch_free. */
 int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);
 

@@ -1554,6 +1554,10 @@ struct gom_batch {
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     double wall_khz = 0.0;
     int32_t g_done = 0;                 // generation steps run
+    bool use_graph = true;              // chunks of kBatchChunk steps as a captured graph
+    hipStream_t cap = nullptr;          // private stream the graph is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -1612,6 +1616,9 @@ extern "C" void gom_batch_free(gom_batch *b) {
     for (gom_state *s : b->subs) gom_state_free(s);
     for (hipEvent_t e : b->chunk_ev)
         if (e) (void)hipEventDestroy(e);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->h_st) (void)hipHostFree(b->h_st);
     delete b;
 }
@@ -1708,6 +1715,36 @@ static hipError_t batch_snapshot(gom_batch *b, int slot, hipStream_t st) {
                           hipMemcpyDeviceToHost, st);
 }
 
+// One chunk of generation steps and the gather of the run scalars, captured once as a graph.
+static hipError_t batch_chunk_graph(gom_batch *b, int32_t steps) {
+    if (b->graph_exec) return hipSuccess;
+    hipError_t e = prepare_batch_step(b->lds);
+    if (e == hipSuccess && !b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int32_t t = 0; t < steps && le == hipSuccess; ++t)
+        le = launch_batch_step(b->d_insts, b->count, b->d_blk, b->sweep_blocks, b->d_vblk,
+                               b->vblocks, b->lds, b->cap);
+    if (le == hipSuccess) le = launch_batch_gather(b->d_insts, b->count, b->d_snap, b->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap, &g);  // always ends the capture
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le != hipSuccess ? le : e;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    b->graph = g;
+    b->graph_exec = x;
+    return hipSuccess;
+}
+
 static bool batch_all_done(const gom_batch *b, int slot) {
     const DevState *h = b->h_st + (size_t)slot * (size_t)b->count;
     for (int32_t i = 0; i < b->count; ++i)
@@ -1736,12 +1773,21 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
             const int32_t n = std::min(kChunk, max_generations - issued);
             int cur = -1;
             if (n > 0) {
-                for (int32_t t = 0; t < n; ++t)
-                    HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk, b->sweep_blocks,
-                                              b->d_vblk, b->vblocks, b->lds, st));
-                issued += n;
                 cur = slot;
-                HIP_TRY(batch_snapshot(b, cur, st));
+                if (n == kChunk && b->use_graph) {
+                    HIP_TRY(batch_chunk_graph(b, kChunk));
+                    HIP_TRY(hipGraphLaunch(b->graph_exec, st));
+                    HIP_TRY(hipMemcpyAsync(b->h_st + (size_t)cur * (size_t)b->count, b->d_snap,
+                                           sizeof(DevState) * (size_t)b->count,
+                                           hipMemcpyDeviceToHost, st));
+                } else {
+                    for (int32_t t = 0; t < n; ++t)
+                        HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk,
+                                                  b->sweep_blocks, b->d_vblk, b->vblocks, b->lds,
+                                                  st));
+                    HIP_TRY(batch_snapshot(b, cur, st));
+                }
+                issued += n;
                 HIP_TRY(hipEventRecord(b->chunk_ev[cur], st));
                 slot ^= 1;
             }
@@ -1777,6 +1823,12 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
     }
     return GOM_OK;
     GUARD_END
+}
+
+extern "C" int gom_batch_set_graph(gom_batch *b, int enabled) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_set_graph: null batch");
+    b->use_graph = enabled != 0;
+    return GOM_OK;
 }
 
 extern "C" int gom_batch_state(gom_batch *b, int32_t index, gom_state **state) {

@@ -234,6 +234,9 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
 // Batched generation step over `count` instances: sweep grid = sum of populations (blk[b] =
 // {instance, solution}), vertex-pass grid = vblocks (vblk[b] = instance); lds = dynamic LDS
 // bytes of a sweep block (kBatchOrderBytes + the largest instance's resident bytes).
+// Allows k_batch_sweep blocks `lds` bytes of dynamic LDS (once per size; not a stream
+// operation, so it is done before a step is captured into a graph).
+hipError_t prepare_batch_step(size_t lds);
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
                              const int32_t *vblk, int vblocks, size_t lds, hipStream_t s);
 hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s);

@@ -1485,8 +1485,7 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
     return plds ? launch_resident_t<1, true>(a, s, ev) : launch_resident_t<1, false>(a, s, ev);
 }
 
-hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s) {
+hipError_t prepare_batch_step(size_t lds) {
     static size_t attr_bytes = 0;
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k_batch_sweep,
@@ -1494,6 +1493,13 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
         if (e != hipSuccess) return e;
         attr_bytes = lds;
     }
+    return hipSuccess;
+}
+
+hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
+                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s) {
+    hipError_t pe = prepare_batch_step(lds);
+    if (pe != hipSuccess) return pe;
     hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_blocks), dim3(kResidentThreads), lds, s, insts,
                        blk);
     hipError_t e = hipGetLastError();

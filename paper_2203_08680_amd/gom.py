@@ -32,7 +32,7 @@ EXPORTED = (
     "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_ims_bytes",
     "gom_ims_run",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
-    "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
+    "gom_batch_set_graph", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
 )
 
@@ -126,6 +126,7 @@ def lib() -> C.CDLL:
         "gom_batch_init": (C.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, _vp, _sz,
                                      _vp, _P(_vp)]),
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+        "gom_batch_set_graph": (C.c_int, [_vp, C.c_int]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_batch_free": (None, [_vp]),
         "gom_server_create": (C.c_int, [_vp, _sz, _i32, _i32, _P(_vp)]),
@@ -547,6 +548,12 @@ def gom_batch_run(b: GomBatch, max_generations: int, stream=None):
     out = [RunResult(r.generations, bool(r.reached), r.best, r.attempted, r.evaluated,
                      r.accepted) for r in res]
     return out, tt
+
+
+def gom_batch_set_graph(b: GomBatch, enabled: bool = True) -> None:
+    """Run gom_batch_run's chunks of 4 steps as a captured HIP graph (default) or as separate
+    launches."""
+    _check(lib().gom_batch_set_graph(b.handle, 1 if enabled else 0))
 
 
 # ------------------------------------------------------------------------------------------

@@ -630,6 +630,40 @@ def test_batch_continues_across_calls(cuda):
                     f"instance {b}")
 
 
+def test_batch_graph_replays_equal_direct_launches(cuda):
+    """gom_batch_run with its chunks replayed from a captured HIP graph against the same batch
+    with direct launches: after every call (one replay each, with other device work and host
+    reads between the replays) every instance is identical, and the small ones match the
+    oracle at the end."""
+    print("case batch graph replays", flush=True)
+    items = workloads.batch_mix(count=6, seed=14, n_lo=60, n_hi=2500)
+    insts, targets = _batch_setup(items)
+    pops, seeds = [it.pop for it in items], [it.seed for it in items]
+    bg = gom.gom_batch_init(insts, pops, seeds, targets)
+    bd = gom.gom_batch_init(insts, pops, seeds, targets)
+    gom.gom_batch_set_graph(bd, False)
+    other = insts[0].state(pop=pops[0], seed=77)
+    for call in range(1, 6):
+        rg, _ = gom.gom_batch_run(bg, 4 * call)
+        gom.gom_generation(other)  # eager work on the device between the replays
+        rd, _ = gom.gom_batch_run(bd, 4 * call)
+        for b in range(len(items)):
+            assert_same(gom.gom_state_read(bg.state(b)), gom.gom_state_read(bd.state(b)),
+                        f"replay {call}, instance {b}")
+            assert (rg[b].generations, rg[b].best) == (rd[b].generations, rd[b].best)
+    # a budget that ends inside a chunk takes the direct path for the remainder
+    gom.gom_batch_run(bg, 22)
+    gom.gom_batch_run(bd, 22)
+    for b, it in enumerate(items):
+        a = gom.gom_state_read(bg.state(b))
+        assert_same(a, gom.gom_state_read(bd.state(b)), f"after 22 steps, instance {b}")
+        if it.graph.n <= 400:
+            ptr, vars_ = oracle.fos(it.graph, it.fos)
+            ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=it.seed)
+            ref.run(targets[b], 22)
+            assert_same(a, ref.state(), f"graph batch instance {b} vs oracle")
+
+
 def test_server_jobs_equal_solo_runs(cuda):
     """Jobs submitted at different times to a server whose arena holds only a few at once:
     each job's result and final state hash equal those of its solo run, including a job too
