@@ -351,6 +351,92 @@ __device__ __forceinline__ Head load_head(const Rec &R) {
     return hd;
 }
 
+// Change of one dependent edge of a small-set record (entry e of nd): x holds the member
+// position a of its own end, and the outside vertex v (bit 31 clear) or the inside end's
+// position b; ovx is O_i at the outside end.  om / cm: O_i bits / changed members by position.
+__device__ __forceinline__ int64_t small_edge(int e, int nd, int2 en, uint32_t ovx, uint32_t om,
+                                              uint32_t cm) {
+    const int x = e < nd ? en.x : (int)0x80000000;  // past nd: a = b = 0, no flip
+    const uint32_t a = ((uint32_t)x >> kSmallPosShift) & 15u;
+    const uint32_t y = (uint32_t)x & kSmallIdx;
+    const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
+    const bool inside = x < 0;
+    const uint32_t ov = inside ? (om >> y) & 1u : ovx;
+    const uint32_t flip = inside ? ca ^ ((cm >> y) & 1u) : ca;
+    return flip ? signed_w(oa == ov, en.y) : 0;
+}
+
+// GOM step on a small set (at most M member slots, M >= nm) with the offspring in the O
+// planes (class launch).  Every word the step needs is loaded before the first is used, so
+// the loads are in flight together: the population and offspring words of the member slots
+// (a slot past nm reads the first member again and is masked out) and the offspring words at
+// the far ends of the first two entry batches (entries past nd read vertex 0).  The commit
+// writes each changed member's new word from the word already loaded.
+template <int M, class Rec, class Words, class Commit>
+__device__ __forceinline__ PairOut small_pair_planes(const Rec &R, const Head &hd, const Words &P,
+                                                     const PlaneBits &bits, Commit commit,
+                                                     uint64_t cand, uint32_t h, bool neutral_ok) {
+    PairOut out{0u, false, 0};
+    const int4 h0 = hd.h0, h1 = hd.h1, h2 = hd.h2, h3 = hd.h3;
+    const int nm = h0.x, nd = h0.y;
+    const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
+                                h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
+    auto far_index = [&](int e, int2 en) {
+        return (int)((uint32_t)(e < nd ? en.x : 0) & kSmallIdx);
+    };
+    uint64_t pw[M], ow[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int u = k < nm ? mem[k] : mem[0];
+        pw[k] = P[u];
+        ow[k] = bits.O[u];
+    }
+    uint32_t ov0[kBatch], ov1[kBatch];
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        ov0[t] = bits(far_index(t, hd.en0[t]));
+        ov1[t] = bits(far_index(kBatch + t, hd.en1[t]));
+    }
+    uint32_t om = 0;
+    uint64_t D = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const uint32_t ok = bit_of(ow[k], bits.i);
+        const uint64_t diff = pw[k] ^ (0ull - (uint64_t)ok);
+        om |= (k < nm ? ok : 0u) << k;
+        D |= k < nm ? diff : 0ull;
+    }
+    D &= cand;
+    out.cnt = (uint32_t)__popcll(D);
+    const uint32_t d = out.cnt ? select_bit(D, (h * out.cnt) >> 16) : 0u;
+    uint32_t cm = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        cm |= (k < nm ? bit_of(pw[k], d) ^ ((om >> k) & 1u) : 0u) << k;
+    int64_t delta = 0;
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        delta += small_edge(t, nd, hd.en0[t], ov0[t], om, cm);
+        delta += small_edge(kBatch + t, nd, hd.en1[t], ov1[t], om, cm);
+    }
+    for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
+        int2 en[kBatch];
+        uint32_t ov[kBatch];
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) en[t] = R.e(16, e0 + t);
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) ov[t] = bits(far_index(e0 + t, en[t]));
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) delta += small_edge(e0 + t, nd, en[t], ov[t], om, cm);
+    }
+    out.delta = delta;
+    out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if (k < nm) commit.store(mem[k], out.acc && ((cm >> k) & 1u), ow[k]);
+    return out;
+}
+
 template <int KIND, class Rec, class Words, class Bits, class Commit>
 __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const Words &P,
                                             Bits bits, Commit commit, uint64_t cand, uint32_t h,
@@ -386,36 +472,30 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
     } else {
         const int nm = h0.x, nd = h0.y;
         if (nm <= kSmallSet) {
+            if constexpr (!Bits::kLocal) {
+                // class launch: sets of up to 8 members (the torus neighbourhoods, degree <= 7)
+                // load 8 member slots, larger ones all 14
+                if (nm <= 8)
+                    return small_pair_planes<8>(R, hd, P, bits, commit, cand, h, neutral_ok);
+                return small_pair_planes<kSmallSet>(R, hd, P, bits, commit, cand, h,
+                                                    neutral_ok);
+            } else {
+            // resident schedule: bits in LDS, read again where they are needed instead of
+            // being held in registers (1024-thread blocks have 128 registers per lane)
             const int4 h1 = hd.h1, h2 = hd.h2, h3 = hd.h3;
             const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
                                         h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
-            // the O bits at the first two entry batches' far ends, loaded up front with the
-            // members' words.  Prefetched words past nd belong to the next record, so those
-            // entries read vertex 0 instead; an inside entry's b is below nm <= n, so every
-            // index is a vertex and the loads need no branch
-            // With bits in LDS (resident schedule) the words and bits are read again where
-            // they are needed instead of being held in registers (1024-thread blocks have
-            // 128 registers per lane).
-            constexpr bool LOCAL = Bits::kLocal;
+            // entries past nd belong to the next record and read vertex 0 instead; an inside
+            // entry's b is below nm <= n, so every index is a vertex
             auto far_end = [&](int e, int2 en) {
                 return bits((int)((uint32_t)(e < nd ? en.x : 0) & kSmallIdx));
             };
-            uint32_t ov0[LOCAL ? 1 : kBatch], ov1[LOCAL ? 1 : kBatch];
-            if constexpr (!LOCAL) {
-#pragma unroll
-                for (int t = 0; t < kBatch; ++t) {
-                    ov0[t] = far_end(t, hd.en0[t]);
-                    ov1[t] = far_end(kBatch + t, hd.en1[t]);
-                }
-            }
-            uint64_t pw[LOCAL ? 1 : kSmallSet];
             uint32_t om = 0;
             uint64_t D = 0;
 #pragma unroll
             for (int k = 0; k < kSmallSet; ++k) {
                 if (k < nm) {
                     const uint64_t w = P[mem[k]];
-                    if constexpr (!LOCAL) pw[k] = w;
                     const uint32_t ok = bits(mem[k]);
                     om |= ok << k;
                     D |= w ^ (0ull - (uint64_t)ok);
@@ -427,45 +507,20 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
             uint32_t cm = 0;
 #pragma unroll
             for (int k = 0; k < kSmallSet; ++k)
-                if (k < nm) {
-                    uint64_t w;
-                    if constexpr (LOCAL) w = P[mem[k]];
-                    else w = pw[k];
-                    cm |= (bit_of(w, d) ^ ((om >> k) & 1u)) << k;
-                }
-            // change of one dependent edge: x holds the member position a of its own end,
-            // and the outside vertex v (bit 31 clear) or the inside end's position b
-            auto edge = [&](int e, int2 en, uint32_t ovx) -> int64_t {
-                const int x = e < nd ? en.x : (int)0x80000000;  // past nd: a = b = 0, no flip
-                const uint32_t a = ((uint32_t)x >> kSmallPosShift) & 15u;
-                const uint32_t y = (uint32_t)x & kSmallIdx;
-                const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
-                const bool inside = x < 0;
-                const uint32_t ov = inside ? (om >> y) & 1u : ovx;
-                const uint32_t flip = inside ? ca ^ ((cm >> y) & 1u) : ca;
-                return flip ? signed_w(oa == ov, en.y) : 0;
-            };
+                if (k < nm) cm |= (bit_of(P[mem[k]], d) ^ ((om >> k) & 1u)) << k;
             int64_t delta = 0;
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
-                if constexpr (LOCAL) {
-                    delta += edge(t, hd.en0[t], far_end(t, hd.en0[t]));
-                    delta += edge(kBatch + t, hd.en1[t], far_end(kBatch + t, hd.en1[t]));
-                } else {
-                    delta += edge(t, hd.en0[t], ov0[t]);
-                    delta += edge(kBatch + t, hd.en1[t], ov1[t]);
-                }
+                delta += small_edge(t, nd, hd.en0[t], far_end(t, hd.en0[t]), om, cm);
+                delta += small_edge(kBatch + t, nd, hd.en1[t], far_end(kBatch + t, hd.en1[t]),
+                                    om, cm);
             }
             for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
-                int2 en[kBatch];
-                uint32_t ov[kBatch];
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) en[t] = R.e(16, e0 + t);
-#pragma unroll
-                for (int t = 0; t < kBatch; ++t)
-                    ov[t] = bits((int)((uint32_t)(e0 + t < nd ? en[t].x : 0) & kSmallIdx));
-#pragma unroll
-                for (int t = 0; t < kBatch; ++t) delta += edge(e0 + t, en[t], ov[t]);
+                for (int t = 0; t < kBatch; ++t) {
+                    const int2 en = R.e(16, e0 + t);
+                    delta += small_edge(e0 + t, nd, en, far_end(e0 + t, en), om, cm);
+                }
             }
             out.delta = delta;
             out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
@@ -473,6 +528,7 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
             for (int k = 0; k < kSmallSet; ++k)
                 if (k < nm) commit(mem[k], out.acc && ((cm >> k) & 1u));
             return out;
+            }
         } else {
             // members at words 16.., their entry ends at 16 + nm.., entries from the next
             // 4-word boundary
@@ -550,6 +606,12 @@ struct PlaneCommit {
         uint64_t fm = ballot64(flip);
         if constexpr (G < 64) fm = (fm >> (grp * G)) & ((1ull << G) - 1ull);
         if (fm != 0 && i == 0) O[u] ^= fm;
+    }
+    // the same from the word the group already loaded: no other group writes u in this class
+    __device__ __forceinline__ void store(int u, bool flip, uint64_t old) const {
+        uint64_t fm = ballot64(flip);
+        if constexpr (G < 64) fm = (fm >> (grp * G)) & ((1ull << G) - 1ull);
+        if (fm != 0 && i == 0) O[u] = old ^ fm;
     }
 };
 
