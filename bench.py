@@ -345,6 +345,8 @@ def main():
                     help="batched vs plain on the 256-instance mix instead of the default "
                          "single-instance workload")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="plain mode: skip the comparison with the same seeds run as one batch")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
                     help="batched steps as captured HIP graph chunks (default) or direct launches")
     ap.add_argument("--ims", action="store_true",
@@ -478,6 +480,8 @@ def main():
     gens = sum(r.generations for r, _ in runs)
     tto = [dt * 1e3 for r, dt in runs if r.reached]
     value = attempted / total
+    batched = None if args.fi or args.no_batched else batched_compare(
+        args, torch, gom, inst, wl.pop, target, max_gens, [r for r, _ in runs], value)
     roofline = None
     if not args.no_kernel_events and launches:
         # class launch: every class is swept once per generation, so the mean over launches
@@ -534,8 +538,41 @@ def main():
         "reached": len(tto), "generations_total": gens,
         "us_per_generation": total * 1e6 / max(gens, 1),
         "roofline": roofline, "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_compare(args, torch, gom, inst, pop, target, max_gens, plain, plain_value):
+    """The plain runs' seeds again, as one lockstep batch of instances (the batched engine):
+    evaluations per second, time to optimum per seed, and whether every result is identical
+    to its plain run.  None when the instance does not fit the batched (resident) schedule."""
+    seeds = list(range(1, len(plain) + 1))
+    try:
+        wb = gom.gom_batch_init([inst], [pop], [999], [target])
+        gom.gom_batch_run(wb, 2)
+        del wb
+        b = gom.gom_batch_init([inst] * len(seeds), [pop] * len(seeds), seeds,
+                               [target] * len(seeds))
+    except gom.GomError as e:
+        log(f"batched comparison: not run ({e})")
+        return None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, tt = gom.gom_batch_run(b, max_gens)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    same = all((a.generations, a.reached, a.best, a.attempted, a.evaluated, a.accepted) ==
+               (p.generations, p.reached, p.best, p.attempted, p.evaluated, p.accepted)
+               for a, p in zip(res, plain))
+    value = sum(r.attempted for r in res) / dt
+    reached = [float(t) for r, t in zip(res, tt) if r.reached]
+    log(f"batched: {len(seeds)} seeds in one batch, {dt * 1e3:.1f} ms, identical: {same}")
+    return {"value": value, "ms": dt * 1e3, "instances": len(seeds),
+            "schedule": "batched_resident", "identical_results": same,
+            "batched_over_plain": value / plain_value,
+            "time_to_optimum_ms_median": float(np.median(reached)) if reached else None,
+            "reached": len(reached)}
 
 
 if __name__ == "__main__":
