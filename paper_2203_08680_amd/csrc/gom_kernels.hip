@@ -481,12 +481,12 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
                                                     neutral_ok);
             } else {
             // resident schedule: bits in LDS, read again where they are needed instead of
-            // being held in registers (1024-thread blocks have 128 registers per lane)
+            // being held in registers (1024-thread blocks have 128 registers per lane).
+            // Entries past nd belong to the next record and read vertex 0 instead; an inside
+            // entry's b is below nm <= n, so every index is a vertex and no load needs a branch
             const int4 h1 = hd.h1, h2 = hd.h2, h3 = hd.h3;
             const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
                                         h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
-            // entries past nd belong to the next record and read vertex 0 instead; an inside
-            // entry's b is below nm <= n, so every index is a vertex
             auto far_end = [&](int e, int2 en) {
                 return bits((int)((uint32_t)(e < nd ? en.x : 0) & kSmallIdx));
             };
@@ -515,12 +515,17 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
                 delta += small_edge(kBatch + t, nd, hd.en1[t], far_end(kBatch + t, hd.en1[t]),
                                     om, cm);
             }
+            // further entries a batch at a time: the batch's loads, then its far-end bits
             for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
+                int2 en[kBatch];
+                uint32_t ov[kBatch];
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) {
-                    const int2 en = R.e(16, e0 + t);
-                    delta += small_edge(e0 + t, nd, en, far_end(e0 + t, en), om, cm);
-                }
+                for (int t = 0; t < kBatch; ++t) en[t] = R.e(16, e0 + t);
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) ov[t] = far_end(e0 + t, en[t]);
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t)
+                    delta += small_edge(e0 + t, nd, en[t], ov[t], om, cm);
             }
             out.delta = delta;
             out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));

@@ -531,6 +531,12 @@ BITSLICED_CASES = [
     ("cm_d4_p33", lambda: workloads.configuration_model(3000, 4, seed=6), 33, 0, False),
     ("cm_d4_p64_dups", lambda: workloads.configuration_model(800, 4, seed=8), 64, 0, True),
     ("cm_d3_2_p2", lambda: workloads.configuration_model(1000, 2, seed=9), 2, 0, False),
+    # weights beyond int8 (the table's full-word weights) and at the int8 limits (packed)
+    ("torus12_p64_w1e5", lambda: workloads.torus(12, 1, 100_000, seed=10), 64, 0, False),
+    ("cm_d4_p40_wide", lambda: workloads.configuration_model(
+        1500, 4, seed=11, weights="uniform", w_lo=-30_000, w_hi=30_000), 40, 1, False),
+    ("cm_d4_p64_int8_ends", lambda: workloads.configuration_model(
+        1200, 4, seed=12, weights="uniform", w_lo=-128, w_hi=127), 64, 0, False),
 ]
 
 
