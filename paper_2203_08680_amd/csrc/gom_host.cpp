@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -76,13 +77,14 @@ struct gom_fos {
 namespace {
 
 struct Layout {
-    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, coop, sw, total;
+    size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, coop, sw, smap,
+        split, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
-                   int64_t rec_words, int64_t n_coop, int64_t sw_words) {
+                   int64_t rec_words, int64_t n_coop, int64_t sw_words, int64_t n_smap) {
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -106,6 +108,8 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
     L.recs = take(sizeof(int32_t) * (size_t)rec_words);
     L.coop = take(sizeof(int32_t) * (size_t)n_coop);
     L.sw = take(sizeof(int32_t) * (size_t)sw_words);
+    L.smap = take(sizeof(int4) * (size_t)n_smap);
+    L.split = take(n_smap ? kSplitScratchBytes : 0);
     L.total = o;
     return L;
 }
@@ -127,17 +131,25 @@ constexpr int32_t kMaxVertexSmall = 1 << kSmallPosShift;  // vertex limit of a s
 // Class positions of the sets swept by a whole block (general FOS only), per class in two
 // groups: sets of up to kCoopSmallBlock members (256-thread blocks), then larger ones
 // (1024-thread blocks).  Group g of class c: pos[ptr[2c + g] .. ptr[2c + g + 1]); the
-// largest set of each group in max_members[2c + g].
+// largest set of each group in max_members[2c + g].  A group of fewer than kSplitBelow sets
+// takes the split sweep instead (split[q] set): its blocks, one per chunk of kSplitMembers
+// members, are smap[smap_ptr[q] .. smap_ptr[q + 1]) = {slot (the set's index in the group),
+// class position, first member, 0}.
 struct CoopSets {
-    std::vector<int32_t> ptr, pos, max_members;
+    std::vector<int32_t> ptr, pos, max_members, smap_ptr;
+    std::vector<uint8_t> split;
+    std::vector<int4> smap;
 };
 
 CoopSets coop_sets(const gom_fos &f, bool univariate) {
     CoopSets C;
     C.ptr.assign(2 * (size_t)f.k + 1, 0);
     C.max_members.assign(2 * (size_t)f.k, 0);
+    C.smap_ptr.assign(2 * (size_t)f.k + 1, 0);
+    C.split.assign(2 * (size_t)f.k, 0);
     for (int32_t c = 0; c < f.k; ++c)
         for (int grp = 0; grp < 2; ++grp) {
+            const size_t q = 2 * (size_t)c + grp;
             if (!univariate)
                 for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t) {
                     const int32_t j = f.class_elems[t];
@@ -145,10 +157,21 @@ CoopSets coop_sets(const gom_fos &f, bool univariate) {
                     if (nm < kCoopMinMembers || nm > kCoopMaxMembers) continue;
                     if ((nm > kCoopSmallBlock) != (grp == 1)) continue;
                     C.pos.push_back(t - f.class_ptr[c]);
-                    C.max_members[2 * (size_t)c + grp] =
-                        std::max(C.max_members[2 * (size_t)c + grp], nm);
+                    C.max_members[q] = std::max(C.max_members[q], nm);
                 }
-            C.ptr[2 * (size_t)c + grp + 1] = (int32_t)C.pos.size();
+            C.ptr[q + 1] = (int32_t)C.pos.size();
+            const int32_t n_large = C.ptr[q + 1] - C.ptr[q];
+            if (n_large > 0 && n_large < kSplitBelow) {
+                C.split[q] = 1;
+                for (int32_t slot = 0; slot < n_large; ++slot) {
+                    const int32_t p = C.pos[(size_t)C.ptr[q] + slot];
+                    const int32_t j = f.class_elems[(size_t)f.class_ptr[c] + p];
+                    const int32_t nm = f.ptr[(size_t)j + 1] - f.ptr[j];
+                    for (int32_t k0 = 0; k0 < nm; k0 += kSplitMembers)
+                        C.smap.push_back(make_int4(slot, p, k0, 0));
+                }
+            }
+            C.smap_ptr[q + 1] = (int32_t)C.smap.size();
         }
     return C;
 }
@@ -353,6 +376,12 @@ struct gom_state {
     int32_t *d_coop = nullptr;                // their class positions
     int32_t *d_sw = nullptr;                  // bit-sliced sweep table (when eligible)
     int32_t sw_stride = 0;
+    std::vector<uint8_t> split;               // per class group: split sweep (few large sets)
+    std::vector<int32_t> smap_ptr;            // ... its blocks in d_smap
+    int4 *d_smap = nullptr;
+    uint64_t *d_split_D = nullptr;            // split sweep scratch (per slot)
+    int64_t *d_split_delta = nullptr;
+    int32_t *d_split_sel = nullptr;
     int32_t g_host = 0;                 // next generation index to enqueue
     int32_t open_next = -1;             // class position where an open generation resumes
     int32_t g_base = 0;                 // generation at which attempted_base was set
@@ -798,7 +827,7 @@ extern "C" int gom_state_bytes(const mc_graph *g, const gom_fos *f, int32_t pop,
     const CoopSets CS = coop_sets(*f, f->max_set == 1);
     const int64_t sw_words = swar_eligible(*g, *f) ? (int64_t)kSwRows * swar_stride(f->n_sets) : 0;
     *bytes = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
-                         (int64_t)CS.pos.size(), sw_words).total;
+                         (int64_t)CS.pos.size(), sw_words, (int64_t)CS.smap.size()).total;
     return GOM_OK;
     GUARD_END
 }
@@ -848,6 +877,12 @@ static int timing_events(gom_state *s, KernelEvents *ev) {
 
 // Enqueue generation `gen` (Algorithm 3): every colour class in the generation's order, then
 // the epilogue.  Kernels skip their work when the elitist has already reached `target`.
+// Device address of the state's forced-improvement records (DevState::fi_at).
+static uint32_t *fi_at_ptr(const gom_state *s) {
+    return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s->d_st) +
+                                        offsetof(DevState, fi_at));
+}
+
 static ResidentCtx resident_ctx(const gom_state *s, int64_t target) {
     ResidentCtx r{};
     r.P = s->d_P;
@@ -867,6 +902,7 @@ static ResidentCtx resident_ctx(const gom_state *s, int64_t target) {
     r.row_words = (s->n + 63) / 64;
     r.fi = s->fi ? 1 : 0;
     r.E = s->d_E;
+    r.fi_at = fi_at_ptr(s);
     return r;
 }
 
@@ -909,6 +945,7 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
     a.recs = s->d_recs;
     a.sw = s->d_sw;
     a.sw_stride = s->sw_stride;
+    a.fi_at = fi_at_ptr(s);
     a.seed = s->seed;
     a.target = target;
     a.N = s->N;
@@ -917,6 +954,7 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
     for (int32_t t = t0; t < t1; ++t) {
         const int32_t c = perm[t];
         a.cls = c;
+        a.fi_pos = t;
         a.cbase = s->class_ptr[c];
         a.rbase = s->class_rec[c].x;
         a.rstride = s->class_rec[c].y;
@@ -936,6 +974,15 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
             SweepArgs b = a;
             b.n_large = s->coop_ptr[q + 1] - s->coop_ptr[q];
             if (b.n_large == 0) continue;
+            if (s->split[q]) {
+                b.smap = s->d_smap + s->smap_ptr[q];
+                b.n_smap = s->smap_ptr[q + 1] - s->smap_ptr[q];
+                b.split_D = s->d_split_D;
+                b.split_delta = s->d_split_delta;
+                b.split_sel = s->d_split_sel;
+                HIP_TRY(launch_split_sweep(b, st));
+                continue;
+            }
             b.large_pos = s->d_coop + s->coop_ptr[q];
             b.coop_cap = s->coop_max[q];
             HIP_TRY(launch_large_set_sweep(b, s->coop_max[q], grp ? 1024 : kCoopSmallBlock, st));
@@ -1029,7 +1076,8 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     const bool swar = swar_eligible(*g, *f);
     const std::vector<int32_t> SW = swar ? build_swar(*g, *f) : std::vector<int32_t>();
     const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
-                                 (int64_t)CS.pos.size(), (int64_t)SW.size());
+                                 (int64_t)CS.pos.size(), (int64_t)SW.size(),
+                                 (int64_t)CS.smap.size());
     if (arena_bytes < L.total)
         return fail(GOM_E_NOMEM, "gom_state_init: arena has %zu bytes, needs %zu", arena_bytes,
                     L.total);
@@ -1068,6 +1116,12 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->coop_max = CS.max_members;
     s->d_coop = (int32_t *)(s->arena + L.coop);
     s->d_sw = (int32_t *)(s->arena + L.sw);
+    s->split = CS.split;
+    s->smap_ptr = CS.smap_ptr;
+    s->d_smap = (int4 *)(s->arena + L.smap);
+    s->d_split_D = (uint64_t *)(s->arena + L.split);
+    s->d_split_delta = (int64_t *)(s->arena + L.split + (size_t)kSplitBelow * 64 * 8);
+    s->d_split_sel = (int32_t *)(s->arena + L.split + (size_t)kSplitBelow * 64 * 16);
     s->sw_stride = swar_stride(f->n_sets);
     auto cleanup = [&](int code) {
         gom_state_free(s);
@@ -1103,6 +1157,9 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
         e = h2d(s->d_crec, R.class_rec.data(), sizeof(int2) * R.class_rec.size());
     if (e == hipSuccess) e = h2d(s->d_coop, CS.pos.data(), sizeof(int32_t) * CS.pos.size());
     if (e == hipSuccess) e = h2d(s->d_sw, SW.data(), sizeof(int32_t) * SW.size());
+    if (e == hipSuccess) e = h2d(s->d_smap, CS.smap.data(), sizeof(int4) * CS.smap.size());
+    if (e == hipSuccess && !CS.smap.empty())  // the split sweep's scratch starts cleared
+        e = hipMemsetAsync(s->arena + L.split, 0, kSplitScratchBytes, st);
     if (e == hipSuccess) e = enqueue_initial_population(s, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging buffers die below
     if (e != hipSuccess)

@@ -65,7 +65,16 @@ struct alignas(64) DevState {
     uint64_t hash;           // accumulator of the state hash's gene and elitist terms
     uint64_t fi_fail;        // solutions the last generation's forced improvement replaced
                              // by the elitist
+    uint32_t fi_at[64];      // forced improvement of this generation: 0 while solution i has
+                             // not improved, else kFiBase - t for the first class position t
+                             // (in the generation's order) at which a step raised its fitness
 };
+
+// A solution's forced improvement stops after the first class in which it improved, so a
+// sweep at class position t skips solution i when fi_at[i] > kFiBase - t (it improved at an
+// earlier position) and records an improvement by an atomic max of kFiBase - t: steps of
+// the same class never see each other's records.
+constexpr uint32_t kFiBase = 1u << 20;
 
 // Accumulators that many blocks add into.  Device-scope atomics on one address serialise
 // (tens of ns each), so every block adds into stripe (block index mod kStripes) and the
@@ -77,8 +86,7 @@ struct alignas(64) Stripe {
     uint64_t accepted;
     uint64_t mism;           // solutions whose P differs from the elitist (vertex pass)
     uint64_t acc;            // solutions with an accepted GOM step in this generation
-    uint64_t fimp;           // solutions whose forced improvement raised their fitness
-    uint64_t pad[3];
+    uint64_t pad[4];
 };
 
 // Sweep modes: a GOM sweep, a GOM sweep that also records which solutions accepted a step
@@ -113,10 +121,30 @@ struct SweepArgs {
     int32_t n_large;        // block-cooperative sweep: number of such sets in the launch
     const int32_t *large_pos;  // ... and their class positions
     int32_t coop_cap;       // ... LDS words reserved per member array (the largest set)
+    uint32_t *fi_at;        // DevState::fi_at of the state (forced improvement)
+    int32_t fi_pos;         // forced-improvement sweep: class position in the order
     const int32_t *sw;      // bit-sliced sweep table (univariate FOS, degree <= 4): kSwRows
                             // arrays of sw_stride words, entry s = class position s
     int32_t sw_stride;
+    // split sweep of the large sets of one group (few sets): one block per chunk of
+    // kSplitMembers members, {slot, class position, first member, 0} per block, and per slot
+    // (the set's index in the group) 64 donor masks, 64 fitness changes, 64 donor choices
+    const int4 *smap;
+    int32_t n_smap;
+    uint64_t *split_D;
+    int64_t *split_delta;
+    int32_t *split_sel;
 };
+
+// Groups of fewer than kSplitBelow large sets take the split sweep (three launches whose
+// blocks each handle kSplitMembers members of one set) instead of one block per set.
+constexpr int kSplitBelow = 128;
+constexpr int kSplitMembers = 16;
+// The split sweep's scratch: 64 donor masks, 64 fitness changes and 64 donor choices for each
+// of kSplitBelow slots (the sets of one group), cleared at state initialization and left
+// cleared by every sweep.
+constexpr size_t kSplitScratchBytes =
+    (size_t)kSplitBelow * 64 * (sizeof(uint64_t) + sizeof(int64_t) + sizeof(int32_t));
 
 // The bit-sliced sweep's per-set table, one array per row so every load is coalesced: the
 // variable u, its truth tables, its (up to 4) neighbours, then their edge weights.  A missing
@@ -181,6 +209,7 @@ struct ResidentCtx {
     int32_t row_words;
     int32_t fi;             // forced improvement after the classes
     const uint64_t *E;      // elitist bits
+    uint32_t *fi_at;        // DevState::fi_at of the state
 };
 
 struct ResidentArgs {
@@ -224,6 +253,7 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
 // Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
 // Block-cooperative sweep of the large sets of one class (a.n_large blocks); max_members:
 // the largest of them (dynamic LDS of 8 bytes per member).
+hipError_t launch_split_sweep(const SweepArgs &a, hipStream_t s);
 hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threads,
                                   hipStream_t s);
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,

@@ -123,6 +123,12 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
     return (int64_t)s;
 }
 
+// Solutions (bit i) whose forced improvement raised their fitness at a class position before
+// pos in this generation (lane i reads solution i's record; every lane must be active).
+__device__ __forceinline__ uint64_t fi_done_before(const uint32_t *fi_at, int pos) {
+    return ballot64(fi_at[threadIdx.x & 63] > kFiBase - (uint32_t)pos);
+}
+
 // ------------------------------------------------------------------------------------------
 // Initial population (Algorithm 3, InitializePopulation): gene v of solution i is bit
 // (v mod 32) of word ((v / 32) mod 4) of Philox(seed; kInitStream, i, v / 128, 0).
@@ -660,7 +666,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
         // forced improvement: solutions without an accepted step and not yet improved; the
         // elitist is the only donor
         const uint64_t todo = popm & ~wave_or64(a.stripes[lane].acc) &
-                              ~wave_or64(a.stripes[lane].fimp);
+                              ~fi_done_before(a.fi_at, a.fi_pos);
         live = live && todo != 0;
         cand = act && bit_of(todo, i) ? ~0ull : 0ull;
     }
@@ -715,12 +721,13 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     Stripe *sp = a.stripes + (gw % kStripes);
     if (lane < G && act && facc)
         atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
-    const uint64_t fm = a.mode != kSweepGom ? solution_mask<G>(flag && act) : 0ull;
+    const uint64_t fm = a.mode == kSweepGomTrack ? solution_mask<G>(flag && act) : 0ull;
+    // every group's lanes record their own solutions' improvements (i = lane mod G)
+    if (FI && act && flag) atomicMax(&a.fi_at[i], kFiBase - (uint32_t)a.fi_pos);
     if (lane == 0) {
         if (ce) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)ce);
         if (ca) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)ca);
-        if (fm)
-            atomicOr((unsigned long long *)(FI ? &sp->fimp : &sp->acc), (unsigned long long)fm);
+        if (fm) atomicOr((unsigned long long *)&sp->acc, (unsigned long long)fm);
     }
 }
 
@@ -755,7 +762,6 @@ __global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a
     const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p];
     const uint64_t mism = a.stripes[lane].mism;
     const uint64_t acc_prev = a.mode == kSweepFi ? a.stripes[lane].acc : 0ull;
-    const uint64_t fimp_prev = a.mode == kSweepFi ? a.stripes[lane].fimp : 0ull;
     if (a.st->elite_fitness >= a.target) return;
     const int nm = R[0];
     const int32_t *mem = R + 16;
@@ -767,7 +773,7 @@ __global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a
     const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
     const bool fi = a.mode == kSweepFi;
     if (fi) {
-        const uint64_t todo = popm & ~wave_or64(acc_prev) & ~wave_or64(fimp_prev);
+        const uint64_t todo = popm & ~wave_or64(acc_prev) & ~fi_done_before(a.fi_at, a.fi_pos);
         if (todo == 0) return;  // uniform over the block
         cand = act && bit_of(todo, i) ? ~0ull : 0ull;
     }
@@ -868,14 +874,12 @@ __global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a
         Stripe *sp = a.stripes + (blockIdx.x % kStripes);
         if (acc && delta) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)delta);
         const uint64_t ev = ballot64(cnt > 0);
-        const uint64_t flag = a.mode == kSweepGom ? 0ull
-                              : fi ? ballot64(acc && delta > 0) : am;
+        if (fi && acc && delta > 0) atomicMax(&a.fi_at[i], kFiBase - (uint32_t)a.fi_pos);
         if (lane == 0) {
             if (ev) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)__popcll(ev));
             if (am) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)__popcll(am));
-            if (flag)
-                atomicOr((unsigned long long *)(fi ? &sp->fimp : &sp->acc),
-                         (unsigned long long)flag);
+            if (a.mode == kSweepGomTrack && am)
+                atomicOr((unsigned long long *)&sp->acc, (unsigned long long)am);
         }
     }
     __syncthreads();
@@ -886,6 +890,188 @@ __global__ __launch_bounds__(kCoopMaxThreads) void k_large_set_sweep(SweepArgs a
             const uint64_t m = cmw[k] & am;
             if (m) a.O[mem[k]] ^= m;
         }
+}
+
+// ------------------------------------------------------------------------------------------
+// Split sweep of a few large sets (general record layout): the members of each set are cut
+// into chunks of kSplitMembers, one 256-thread block per chunk (lane = solution, each wave
+// kSplitPerWave members), so that a class holding a handful of sets of thousands of members
+// still spreads over the device.  Three launches, the steps of the block-cooperative sweep
+// with the set-wide reductions in global memory (per slot = the set's index in its group):
+//   1. k_split_donors: D_i = OR over the chunk's members of (P[u] xor broadcast(O_i[u])),
+//      OR-ed into split_D; the first chunk's block clears the set's split_delta
+//   2. k_split_delta: every block draws the donors from split_D (16-bit Philox field of the
+//      set's class position, as in the other sweeps) and sums the change of its members'
+//      dependent edges into split_delta (an inside edge changes when exactly one end changes;
+//      the other end's change is recomputed from its words); the first chunk's block stores
+//      the donor choices in split_sel
+//   3. k_split_commit: acceptance per solution from split_sel and split_delta, each block
+//      commits its members (O[u] ^= changed & accepted); the first chunk's block adds the
+//      set's fitness changes and counts to a stripe and clears the set's split_D
+// OR and integer sums do not depend on the order of the atomic updates, so the result equals
+// the one-block sweep.  Forced improvement (mode kSweepFi): the elitist is the donor.
+// ------------------------------------------------------------------------------------------
+constexpr int kSplitThreads = 256;
+constexpr int kSplitWaves = kSplitThreads / 64;
+constexpr int kSplitPerWave = kSplitMembers / kSplitWaves;
+static_assert(kSplitPerWave * kSplitWaves == kSplitMembers, "members per block");
+
+struct SplitBlock {
+    int slot, p, k0, nm;
+    const int32_t *mem, *end;
+    const int2 *E;
+};
+
+__device__ __forceinline__ SplitBlock split_block(const SweepArgs &a) {
+    const int4 m = a.smap[blockIdx.x];
+    const int32_t *R = a.rstride ? a.recs + a.rbase + m.y * a.rstride
+                                 : a.recs + a.roff[a.cbase + m.y];
+    const int nm = R[0];
+    return SplitBlock{m.x, m.y, m.z, nm, R + 16, R + 16 + nm,
+                      reinterpret_cast<const int2 *>(R + ((16 + 2 * nm + 3) & ~3))};
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_split_donors(SweepArgs a) {
+    __shared__ uint64_t red[kSplitWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t i = (uint32_t)lane;
+    const SplitBlock sb = split_block(a);
+    if (a.st->elite_fitness >= a.target) return;  // uniform over the grid
+    const bool fi = a.mode == kSweepFi;
+    const EliteWords ew{a.E};
+    uint64_t D = 0;
+#pragma unroll
+    for (int c = 0; c < kSplitPerWave; ++c) {
+        const int k = sb.k0 + w * kSplitPerWave + c;
+        const int u = sb.mem[k < sb.nm ? k : 0];
+        const uint64_t o = a.O[u];
+        const uint64_t t = (fi ? ew[u] : a.P[u]) ^ (0ull - (uint64_t)bit_of(o, i));
+        if (k < sb.nm) D |= t;
+    }
+    red[w][lane] = D;
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int q = 1; q < kSplitWaves; ++q) D |= red[q][lane];
+        if (D) atomicOr((unsigned long long *)&a.split_D[sb.slot * 64 + lane],
+                        (unsigned long long)D);
+        if (sb.k0 == 0) a.split_delta[sb.slot * 64 + lane] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_split_delta(SweepArgs a) {
+    __shared__ int64_t red[kSplitWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t i = (uint32_t)lane;
+    const SplitBlock sb = split_block(a);
+    const uint64_t Dall = a.split_D[sb.slot * 64 + lane];
+    const uint64_t acc_prev = a.stripes[lane].acc;
+    if (a.st->elite_fitness >= a.target) return;
+    const bool fi = a.mode == kSweepFi;
+    const bool act = (int)i < a.N;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
+    if (fi) {
+        const uint64_t todo = popm & ~wave_or64(acc_prev) & ~fi_done_before(a.fi_at, a.fi_pos);
+        cand = act && bit_of(todo, i) ? ~0ull : 0ull;
+    }
+    const uint64_t D = Dall & cand;
+    const uint32_t cnt = (uint32_t)__popcll(D);
+    uint32_t h = 0;
+    if (!fi) {
+        const U32x4 r = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i, (uint32_t)(sb.p >> 3));
+        const int f = sb.p & 7;
+        const uint32_t x = (f >> 1) == 0 ? r.x : (f >> 1) == 1 ? r.y : (f >> 1) == 2 ? r.z : r.w;
+        h = (x >> (16 * (f & 1))) & 0xFFFFu;
+    }
+    const uint32_t d = cnt ? select_bit(D, (h * cnt) >> 16) : 0u;
+    if (sb.k0 == 0 && w == 0)
+        a.split_sel[sb.slot * 64 + lane] = (int32_t)(d | (cnt ? 0x10000u : 0u));
+    const EliteWords ew{a.E};
+    // does the step of solution i change vertex u (O_i[u] in o)?
+    auto changes = [&](int u, uint64_t o) -> uint32_t {
+        return cnt ? bit_of(fi ? ew[u] : a.P[u], d) ^ bit_of(o, i) : 0u;
+    };
+    auto edge = [&](int2 en, uint32_t oa, uint32_t ca) -> int64_t {
+        uint32_t ov, flip;
+        if (en.x >= 0) {
+            ov = bit_of(a.O[en.x], i);
+            flip = ca;
+        } else {
+            const int ub = sb.mem[~en.x];
+            const uint64_t ob = a.O[ub];
+            ov = bit_of(ob, i);
+            flip = ca ^ changes(ub, ob);
+        }
+        return flip ? signed_w(oa == ov, en.y) : 0;
+    };
+    int64_t dl = 0;
+#pragma unroll
+    for (int c = 0; c < kSplitPerWave; ++c) {
+        const int k = sb.k0 + w * kSplitPerWave + c;
+        if (k >= sb.nm) break;  // uniform over the wave
+        const int u = sb.mem[k];
+        const uint64_t o = a.O[u];
+        const uint32_t oa = bit_of(o, i), ca = changes(u, o);
+        const int e0 = k ? sb.end[k - 1] : 0, e1 = sb.end[k];
+        // the member's first kCoopEdges entries together (masked past its end)
+#pragma unroll
+        for (int t = 0; t < kCoopEdges; ++t) {
+            const int e = e0 + t;
+            const int2 en = sb.E[e < e1 ? e : e0];
+            if (e < e1) dl += edge(en, oa, ca);
+        }
+        for (int e = e0 + kCoopEdges; e < e1; ++e) dl += edge(sb.E[e], oa, ca);
+    }
+    red[w][lane] = dl;
+    __syncthreads();
+    if (w == 0) {
+        int64_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kSplitWaves; ++q) s += red[q][lane];
+        if (s) atomicAdd((unsigned long long *)&a.split_delta[sb.slot * 64 + lane],
+                         (unsigned long long)s);
+    }
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_split_commit(SweepArgs a) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t i = (uint32_t)lane;
+    const SplitBlock sb = split_block(a);
+    const uint64_t mism = a.stripes[lane].mism;
+    const int32_t sel = a.split_sel[sb.slot * 64 + lane];
+    const int64_t delta = a.split_delta[sb.slot * 64 + lane];
+    if (a.st->elite_fitness >= a.target) return;
+    const bool fi = a.mode == kSweepFi;
+    const bool neutral_ok = a.always || bit_of(wave_or64(mism), i);
+    const uint32_t d = (uint32_t)sel & 0xFFFFu;
+    const bool has = ((uint32_t)sel >> 16) != 0u;
+    const bool acc = has && (delta > 0 || (delta == 0 && neutral_ok));
+    const uint64_t am = ballot64(acc);
+    const EliteWords ew{a.E};
+#pragma unroll
+    for (int c = 0; c < kSplitPerWave; ++c) {
+        const int k = sb.k0 + w * kSplitPerWave + c;
+        if (k >= sb.nm) break;  // uniform over the wave
+        const int u = sb.mem[k];
+        const uint64_t o = a.O[u];
+        const bool flip = has && (bit_of(fi ? ew[u] : a.P[u], d) ^ bit_of(o, i)) != 0u;
+        const uint64_t m = ballot64(flip) & am;
+        if (lane == 0 && m) a.O[u] = o ^ m;  // only this block touches u
+    }
+    if (sb.k0 == 0 && w == 0) {
+        Stripe *sp = a.stripes + (sb.slot % kStripes);
+        if (acc && delta) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)delta);
+        const uint64_t ev = ballot64(has);
+        if (fi && acc && delta > 0) atomicMax(&a.fi_at[i], kFiBase - (uint32_t)a.fi_pos);
+        if (lane == 0) {
+            if (ev) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)__popcll(ev));
+            if (am) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)__popcll(am));
+            if (a.mode == kSweepGomTrack && am)
+                atomicOr((unsigned long long *)&sp->acc, (unsigned long long)am);
+        }
+        a.split_D[sb.slot * 64 + lane] = 0;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1174,7 +1360,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
         if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
         if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
         if (any_acc) atomicOr((unsigned long long *)&sp->acc, 1ull << i);
-        if (improved) atomicOr((unsigned long long *)&sp->fimp, 1ull << i);
+        if (improved) a.fi_at[i] = kFiBase;  // one block per solution: any nonzero record
     }
 }
 
@@ -1200,7 +1386,8 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     for (int s = 0; s < kStripes; ++s) d += a.stripes[s].fit[t];
     const int64_t fit_t = a.fit[t];
     const uint64_t s_ev = a.stripes[t].evaluated, s_ac = a.stripes[t].accepted;
-    const uint64_t s_acc = a.stripes[t].acc, s_fimp = a.stripes[t].fimp;
+    const uint64_t s_acc = a.stripes[t].acc;
+    const uint32_t fi_at = st->fi_at[t];
     const int64_t fE = st->elite_fitness;
     if (a.mode == kEpiGeneration && fE >= a.target) {
         if (t == 0) st->active = 0;
@@ -1210,7 +1397,7 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     uint64_t fail = 0;
     if (a.fi && a.mode == kEpiGeneration) {
         const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-        fail = popm & ~wave_or64(s_acc) & ~wave_or64(s_fimp);
+        fail = popm & ~wave_or64(s_acc) & ~ballot64(fi_at != 0u);
     }
     int64_t f = INT64_MIN;
     if (t < a.N) {
@@ -1237,7 +1424,7 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     a.stripes[t].accepted = 0;
     a.stripes[t].mism = 0;
     a.stripes[t].acc = 0;
-    a.stripes[t].fimp = 0;
+    st->fi_at[t] = 0u;
     if (t == 0) {
         st->fi_fail = fail;
         const bool newE = a.mode == kEpiInit || (a.mode == kEpiGeneration && fb > fE);
@@ -1491,6 +1678,19 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
     };
     if (a.mode == kSweepFi) go(std::true_type{});
     else go(std::false_type{});
+    return hipGetLastError();
+}
+
+hipError_t launch_split_sweep(const SweepArgs &a, hipStream_t s) {
+    if (a.n_smap < 1) return hipSuccess;
+    const dim3 gd(a.n_smap), bd(kSplitThreads);
+    hipLaunchKernelGGL(k_split_donors, gd, bd, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_delta, gd, bd, 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_commit, gd, bd, 0, s, a);
     return hipGetLastError();
 }
 

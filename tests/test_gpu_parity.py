@@ -382,6 +382,33 @@ def test_forced_improvement(cuda, label, maker, pop, rule, sched):
                               gom.gom_state_read(st)["genes"])
 
 
+LT_FI_RUNS = [
+    # (label, graph maker, bound (0 = full tree), population, seed, generations): classes that
+    # hold both small sets and sets of 15 or more members, with forced improvement running
+    # often.  cm90_d4_bound40_p8 was found by search: there a solution improves on a small set
+    # of a class and a forced step on a large set of the same class is accepted as well, so a
+    # sweep that stopped the solution inside the class would give a different generation 3
+    ("torus10_full_p8", lambda: workloads.torus(10, 1, 9, seed=3), 0, 8, 5, 40),
+    ("torus12_bound40_p12", lambda: workloads.torus(12, 1, 50, seed=6), 40, 12, 5, 40),
+    ("cm120_full_p6", lambda: workloads.configuration_model(120, 3, seed=2), 0, 6, 5, 40),
+    ("cm90_d4_bound40_p8", lambda: workloads.configuration_model(90, 4, seed=94), 40, 8, 1, 12),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+@pytest.mark.parametrize("label,maker,bound,pop,seed,gens", LT_FI_RUNS,
+                         ids=[c[0] for c in LT_FI_RUNS])
+def test_forced_improvement_linkage_tree(cuda, label, maker, bound, pop, seed, gens, sched):
+    """Forced improvement over linkage trees: within a class, a solution that improved on one
+    set is still tried on every other set of the class (it stops only after the class), also
+    when the class's sets are swept by different kernels."""
+    print(f"case forced improvement linkage tree {label} sched={sched}", flush=True)
+    g = maker()
+    ptr, vars_ = oracle.linkage_tree(g, bound)
+    _, st, ref = make_pair(g, None, pop, seed, sets=(ptr, vars_), sched=sched, fi=True)
+    lockstep(st, ref, gens, f"fi lt {label}")
+
+
 def test_forced_improvement_with_cut_generations_and_schedules(cuda):
     """Forced improvement after a generation cut at a class position, under the class-launch
     and resident schedules in turn; the bit-sliced schedule is left when it is turned on."""
