@@ -131,10 +131,11 @@ constexpr int32_t kMaxVertexSmall = 1 << kSmallPosShift;  // vertex limit of a s
 // Class positions of the sets swept by a whole block (general FOS only), per class in two
 // groups: sets of up to kCoopSmallBlock members (256-thread blocks), then larger ones
 // (1024-thread blocks).  Group g of class c: pos[ptr[2c + g] .. ptr[2c + g + 1]); the
-// largest set of each group in max_members[2c + g].  A group of fewer than kSplitBelow sets
-// takes the split sweep instead (split[q] set): its blocks, one per chunk of kSplitMembers
-// members, are smap[smap_ptr[q] .. smap_ptr[q + 1]) = {slot (the set's index in the group),
-// class position, first member, 0}.
+// largest set of each group in max_members[2c + g].  A class with fewer than kSplitBelow
+// large sets in its two groups together takes the split sweep for all of them instead
+// (split[c] set): its blocks, one per chunk of kSplitMembers members, are
+// smap[smap_ptr[c] .. smap_ptr[c + 1]) = {slot (the set's index among the class's large
+// sets), class position, first member, 0}.
 struct CoopSets {
     std::vector<int32_t> ptr, pos, max_members, smap_ptr;
     std::vector<uint8_t> split;
@@ -145,9 +146,9 @@ CoopSets coop_sets(const gom_fos &f, bool univariate) {
     CoopSets C;
     C.ptr.assign(2 * (size_t)f.k + 1, 0);
     C.max_members.assign(2 * (size_t)f.k, 0);
-    C.smap_ptr.assign(2 * (size_t)f.k + 1, 0);
-    C.split.assign(2 * (size_t)f.k, 0);
-    for (int32_t c = 0; c < f.k; ++c)
+    C.smap_ptr.assign((size_t)f.k + 1, 0);
+    C.split.assign((size_t)f.k, 0);
+    for (int32_t c = 0; c < f.k; ++c) {
         for (int grp = 0; grp < 2; ++grp) {
             const size_t q = 2 * (size_t)c + grp;
             if (!univariate)
@@ -160,19 +161,20 @@ CoopSets coop_sets(const gom_fos &f, bool univariate) {
                     C.max_members[q] = std::max(C.max_members[q], nm);
                 }
             C.ptr[q + 1] = (int32_t)C.pos.size();
-            const int32_t n_large = C.ptr[q + 1] - C.ptr[q];
-            if (n_large > 0 && n_large < kSplitBelow) {
-                C.split[q] = 1;
-                for (int32_t slot = 0; slot < n_large; ++slot) {
-                    const int32_t p = C.pos[(size_t)C.ptr[q] + slot];
-                    const int32_t j = f.class_elems[(size_t)f.class_ptr[c] + p];
-                    const int32_t nm = f.ptr[(size_t)j + 1] - f.ptr[j];
-                    for (int32_t k0 = 0; k0 < nm; k0 += kSplitMembers)
-                        C.smap.push_back(make_int4(slot, p, k0, 0));
-                }
-            }
-            C.smap_ptr[q + 1] = (int32_t)C.smap.size();
         }
+        const int32_t first = C.ptr[2 * (size_t)c], n_large = C.ptr[2 * (size_t)c + 2] - first;
+        if (n_large > 0 && n_large < kSplitBelow) {
+            C.split[c] = 1;
+            for (int32_t slot = 0; slot < n_large; ++slot) {
+                const int32_t p = C.pos[(size_t)first + slot];
+                const int32_t j = f.class_elems[(size_t)f.class_ptr[c] + p];
+                const int32_t nm = f.ptr[(size_t)j + 1] - f.ptr[j];
+                for (int32_t k0 = 0; k0 < nm; k0 += kSplitMembers)
+                    C.smap.push_back(make_int4(slot, p, k0, 0));
+            }
+        }
+        C.smap_ptr[(size_t)c + 1] = (int32_t)C.smap.size();
+    }
     return C;
 }
 
@@ -376,7 +378,7 @@ struct gom_state {
     int32_t *d_coop = nullptr;                // their class positions
     int32_t *d_sw = nullptr;                  // bit-sliced sweep table (when eligible)
     int32_t sw_stride = 0;
-    std::vector<uint8_t> split;               // per class group: split sweep (few large sets)
+    std::vector<uint8_t> split;               // per class: split sweep (few large sets)
     std::vector<int32_t> smap_ptr;            // ... its blocks in d_smap
     int4 *d_smap = nullptr;
     uint64_t *d_split_D = nullptr;            // split sweep scratch (per slot)
@@ -969,20 +971,21 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         else
             HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, s->sweep_threads,
                                        st, ev));
+        if (s->split[c]) {  // every large set of the class in one split sweep
+            SweepArgs b = a;
+            b.smap = s->d_smap + s->smap_ptr[c];
+            b.n_smap = s->smap_ptr[(size_t)c + 1] - s->smap_ptr[c];
+            b.split_D = s->d_split_D;
+            b.split_delta = s->d_split_delta;
+            b.split_sel = s->d_split_sel;
+            HIP_TRY(launch_split_sweep(b, st));
+            continue;
+        }
         for (int grp = 0; grp < 2; ++grp) {
             const size_t q = 2 * (size_t)c + grp;
             SweepArgs b = a;
             b.n_large = s->coop_ptr[q + 1] - s->coop_ptr[q];
             if (b.n_large == 0) continue;
-            if (s->split[q]) {
-                b.smap = s->d_smap + s->smap_ptr[q];
-                b.n_smap = s->smap_ptr[q + 1] - s->smap_ptr[q];
-                b.split_D = s->d_split_D;
-                b.split_delta = s->d_split_delta;
-                b.split_sel = s->d_split_sel;
-                HIP_TRY(launch_split_sweep(b, st));
-                continue;
-            }
             b.large_pos = s->d_coop + s->coop_ptr[q];
             b.coop_cap = s->coop_max[q];
             HIP_TRY(launch_large_set_sweep(b, s->coop_max[q], grp ? 1024 : kCoopSmallBlock, st));
