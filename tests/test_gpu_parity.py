@@ -169,6 +169,44 @@ def test_block_cooperative_large_sets(cuda, sched, pop, fi):
     lockstep(st, ref, 4, f"large sets pop {pop}")
 
 
+def _components_with_sets(specs, seed):
+    """A graph of disjoint random regular components and, per component, one set of its
+    first `size` vertices, beside every vertex's singleton: the sets share no variable and no
+    edge, so the colouring puts them all in one class.  specs: (count, component vertices,
+    degree, set size range)."""
+    rng = np.random.default_rng(seed)
+    us, vs, ws, sets, base = [], [], [], [], 0
+    for count, nc, d, (lo, hi) in specs:
+        for _ in range(count):
+            c = workloads.configuration_model(nc, d, seed=int(rng.integers(1 << 30)))
+            us.append(c.u + base)
+            vs.append(c.v + base)
+            ws.append(c.w)
+            sets.append(list(range(base, base + int(rng.integers(lo, hi + 1)))))
+            base += nc
+    g = workloads._as_graph(base, np.concatenate(us), np.concatenate(vs), np.concatenate(ws),
+                            "components")
+    sets = [[v] for v in range(g.n)] + sets
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(x) for x in sets])
+    return g, (ptr, np.concatenate([np.asarray(x, np.int32) for x in sets]))
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+@pytest.mark.parametrize("pop,fi", [(40, False), (24, True)])
+def test_many_large_sets_in_one_class(cuda, sched, pop, fi):
+    """A class of 270 large sets (140 of 20-30 members, 130 of 270-300): enough for one block
+    per set (the split sweep takes classes with fewer than 128), with and without forced
+    improvement."""
+    print(f"case many large sets pop={pop} fi={fi} sched={sched}", flush=True)
+    g, sets = _components_with_sets([(140, 40, 4, (20, 30)), (130, 320, 3, (270, 300))], 31)
+    _, st, ref = make_pair(g, None, pop, seed=6, sets=sets, sched=sched, fi=fi)
+    cp, ce = ref.classes()
+    sizes = np.diff(sets[0])
+    assert max(int((sizes[ce[cp[c]:cp[c + 1]]] >= 15).sum()) for c in range(len(cp) - 1)) >= 128
+    lockstep(st, ref, 3, f"many large sets pop {pop}")
+
+
 @pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("d,kind", [(3, 0), (3, 1), (6, 0), (6, 1), (12, 0), (12, 1)])
 def test_cm100k_full_size(cuda, d, kind, sched):
