@@ -63,6 +63,8 @@ def lib():
                                   _i32p]
     L.or_stop_after_class.restype = C.c_int32
     L.or_stop_after_class.argtypes = [C.c_void_p, C.c_int32]
+    L.or_local_search.restype = C.c_int32
+    L.or_local_search.argtypes = [C.c_void_p, C.c_int32]
     L.or_hash.restype = C.c_uint64
     L.or_hash.argtypes = [C.c_void_p]
     _lib = L
@@ -171,6 +173,15 @@ class Run:
 
     def hash(self) -> int:
         return int(self._L.or_hash(self._h))
+
+    def local_search(self, max_passes: int = 1 << 30) -> int:
+        """Colouring-parallel local search on the population (univariate FOS, between
+        generations): improving single-bit flips a colour class at a time until a pass flips
+        nothing or max_passes passes ran.  Returns the passes run."""
+        r = self._L.or_local_search(self._h, int(max_passes))
+        if r < 0:
+            raise ValueError("local search needs a univariate FOS and no open generation")
+        return r
 
     def classes(self):
         k = self._L.or_num_classes(self._h)

@@ -34,6 +34,11 @@
  *       Dense similarity matrix, every pair rescanned at every merge.  Pinned: the tree of
  *       Fig. 2 from weights chosen to produce it, merge-by-merge maximality against an
  *       exact recomputation, non-increasing merge similarities, tree structure, bound.
+ *   or_local_search    the colouring-parallel local search of the paper's conclusion (future
+ *       work there): improving single-bit flips, a colour class of the graph at a time.
+ *       Pinned: every solution ends at a local optimum (brute force over all single flips),
+ *       fitness equals the full evaluation, a literal reading that computes a class's gains
+ *       first and flips them together agrees pass by pass, a second search changes nothing.
  *   or_stop_after_class  a generation of Algorithm 3 cut after a given position of the class
  *       order (a debugging view of the offspring between two groups).  Pinned: the literal
  *       reading of Algorithms 3/4 stopped at the same group.
@@ -725,6 +730,58 @@ void or_generation(or_state *s) {
     for (int32_t t = s->open_next; t < s->k; ++t) run_class(s, t);
     if (s->flags & OR_FLAG_FI) forced_improvement(s);
     end_generation(s);
+}
+
+/*
+ * Colouring-parallel local search: the hybrid that the paper's conclusion names as future work
+ * (graph colouring yields sets of independent variables, so single-bit flips of one colour
+ * class can be made together).  Defined for a univariate FOS, whose colour classes are the
+ * colour classes of the graph itself.  Reading: for every solution of the population, a pass
+ * visits the classes in ascending class index and flips each variable of the class whose
+ * flip strictly raises the solution's fitness (variables of one class share no edge, so the
+ * order inside a class does not matter); passes repeat until one flips nothing anywhere or
+ * max_passes have run.  Then P <- O and the elitist is replaced when the best solution
+ * (lowest index on ties) is strictly better, as at a generation end; the generation and the
+ * GOM counters do not change.  Returns the passes run, or -1 when the FOS is not univariate
+ * or a generation is open.
+ */
+int32_t or_local_search(or_state *s, int32_t max_passes) {
+    if (s->open_next >= 0 || max_passes < 0) return -1;
+    for (int32_t j = 0; j < s->nsets; ++j)
+        if (s->set_ptr[j + 1] - s->set_ptr[j] != 1) return -1;
+    const int32_t n = s->g.n;
+    memcpy(s->O, s->P, (size_t)s->N * n);  /* between generations the offspring is P */
+    int32_t passes = 0;
+    while (passes < max_passes) {
+        int any = 0;
+        for (int32_t c = 0; c < s->k; ++c)
+            for (int32_t i = 0; i < s->N; ++i) {
+                uint8_t *Oi = s->O + (size_t)i * n;
+                for (int32_t q = s->class_ptr[c]; q < s->class_ptr[c + 1]; ++q) {
+                    const int32_t u = s->set_vars[s->set_ptr[s->class_elems[q]]];
+                    int64_t gain = 0;
+                    for (int64_t t = s->g.inc_ptr[u]; t < s->g.inc_ptr[u + 1]; ++t) {
+                        const int64_t e = s->g.inc[t];
+                        const int32_t v = s->g.eu[e] == u ? s->g.ev[e] : s->g.eu[e];
+                        gain += Oi[u] == Oi[v] ? (int64_t)s->g.ew[e] : -(int64_t)s->g.ew[e];
+                    }
+                    if (gain > 0) {
+                        Oi[u] ^= 1u;
+                        s->f[i] += gain;
+                        any = 1;
+                    }
+                }
+            }
+        ++passes;
+        if (!any) break;
+    }
+    memcpy(s->P, s->O, (size_t)s->N * n);
+    const int32_t b = best_index(s);
+    if (s->f[b] > s->fE) {
+        memcpy(s->E, s->P + (size_t)b * n, (size_t)n);
+        s->fE = s->f[b];
+    }
+    return passes;
 }
 
 /* Start a generation if none is open, then run the classes up to order position `pos`

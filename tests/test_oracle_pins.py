@@ -726,3 +726,107 @@ def test_target_checked_before_first_generation():
     ptr, vars_ = oracle.fos(g, 0)
     run = oracle.Run(g, ptr, vars_, pop=4, seed=1)
     assert run.run(run.state()["elite_fitness"], 50) == 0
+
+
+# ------------------------------------------------------------------------------------------
+# Colouring-parallel local search (the hybrid named as future work in the paper's conclusion)
+# ------------------------------------------------------------------------------------------
+LS_GRAPHS = [
+    ("torus6_w9", lambda: workloads.torus(6, 1, 9, seed=2)),
+    ("torus8_unit", lambda: workloads.torus(8, 1, 1, seed=3)),          # many zero gains
+    ("cm40_d3_signed", lambda: workloads.configuration_model(40, 3, seed=4)),
+    ("cm60_d5_signed", lambda: workloads.configuration_model(60, 5, seed=5)),
+]
+
+
+def _ls_run(g, pop, seed, gens):
+    ptr, vars_ = oracle.fos(g, 0)
+    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed)
+    for _ in range(gens):
+        ref.generation()
+    return ref
+
+
+def _gain(g, x, u):
+    """Change of the cut when vertex u flips, from the objective itself."""
+    y = x.copy()
+    y[u] ^= 1
+    return oracle.maxcut(g, y) - oracle.maxcut(g, x)
+
+
+@pytest.mark.parametrize("label,maker", LS_GRAPHS, ids=[c[0] for c in LS_GRAPHS])
+def test_local_search_ends_at_local_optima(label, maker):
+    """After an unlimited search every solution is a local optimum (no single flip raises
+    the cut, checked with the objective), its fitness is the full evaluation, no fitness fell,
+    and the elitist is the best solution if that one is strictly better than before."""
+    g = maker()
+    ref = _ls_run(g, 8, 3, 2)
+    before = ref.state()
+    passes = ref.local_search(10_000)
+    after = ref.state()
+    assert 1 <= passes < 10_000  # strict improvements only: the search ends
+    for i in range(8):
+        x = after["genes"][i]
+        assert after["fitness"][i] == oracle.maxcut(g, x)
+        assert after["fitness"][i] >= before["fitness"][i]
+        assert all(_gain(g, x, u) <= 0 for u in range(g.n))
+    best = int(after["fitness"].max())
+    assert after["elite_fitness"] == max(best, before["elite_fitness"])
+    if best > before["elite_fitness"]:
+        b = int(np.argmax(after["fitness"]))  # lowest index among the best
+        assert np.array_equal(after["elite"], after["genes"][b])
+    for key in ("generation", "attempted", "evaluated", "accepted"):
+        assert after[key] == before[key]
+
+
+def _literal_local_search(g, classes, genes, max_passes):
+    """A literal reading: per pass, per class in ascending index, per solution, first the
+    gains of every variable of the class (from the objective), then every improving flip at
+    once.  Returns (genes, passes)."""
+    x = genes.copy()
+    cp, ce = classes
+    passes = 0
+    while passes < max_passes:
+        any_flip = False
+        for c in range(len(cp) - 1):
+            members = [int(u) for u in ce[cp[c]:cp[c + 1]]]  # univariate: set j = {j}
+            for i in range(x.shape[0]):
+                gains = [_gain(g, x[i], u) for u in members]
+                for u, d in zip(members, gains):
+                    if d > 0:
+                        x[i, u] ^= 1
+                        any_flip = True
+        passes += 1
+        if not any_flip:
+            break
+    return x, passes
+
+
+@pytest.mark.parametrize("label,maker", LS_GRAPHS, ids=[c[0] for c in LS_GRAPHS])
+@pytest.mark.parametrize("max_passes", [1, 2, 3, 50])
+def test_local_search_equals_literal_reading(label, maker, max_passes):
+    """The oracle's search (flips inside a class one after another) equals the literal
+    reading (a class's gains first, then its flips together) pass by pass, in genes and in
+    the number of passes."""
+    g = maker()
+    ref = _ls_run(g, 6, 5, 1)
+    start = ref.state()["genes"]
+    want, want_passes = _literal_local_search(g, ref.classes(), start, max_passes)
+    got_passes = ref.local_search(max_passes)
+    assert got_passes == want_passes
+    assert np.array_equal(ref.state()["genes"], want)
+
+
+def test_local_search_second_search_is_idle_and_needs_univariate():
+    g = workloads.torus(6, 1, 9, seed=2)
+    ref = _ls_run(g, 5, 2, 3)
+    assert ref.local_search(10_000) < 10_000
+    s1 = ref.state()
+    assert ref.local_search(10_000) == 1
+    s2 = ref.state()
+    for key in ("genes", "fitness", "elite", "elite_fitness"):
+        assert np.array_equal(np.asarray(s1[key]), np.asarray(s2[key]))
+    ptr, vars_ = oracle.fos(g, 1)
+    nb = oracle.Run(g, ptr, vars_, pop=4, seed=1)
+    with pytest.raises(ValueError):
+        nb.local_search()
