@@ -191,6 +191,23 @@ int gom_generation(gom_state *s, void *stream);
  */
 int gom_debug_stop_after_class(gom_state *s, int32_t class_position, void *stream);
 
+/*
+ * Colouring-parallel local search, the hybrid that the paper's conclusion names as future work
+ * (colour classes are sets of independent variables, so their single-bit flips can be made
+ * together).  For a state whose FOS is univariate (its colour classes are then those of the
+ * graph), between generations: for every solution, a pass visits the colour classes in
+ * ascending class index and flips each variable of the class whose flip strictly raises the
+ * solution's fitness; passes repeat until one flips nothing in any solution or max_passes
+ * passes have run.  Then the population is the searched one and the elitist is replaced when
+ * the best solution (lowest index on ties) is strictly better, as at a generation end.  The
+ * generation counter and the attempted/evaluated/accepted counters do not change.
+ * Synchronous (one read-back per pass).  *passes (may be NULL): the passes run, counting the
+ * last one that flipped nothing.
+ * Errors: GOM_E_ARG (null state, max_passes < 0), GOM_E_STATE (FOS not univariate, or a
+ * generation left open by gom_debug_stop_after_class), GOM_E_DEVICE.
+ */
+int gom_local_search(gom_state *s, int32_t max_passes, void *stream, int32_t *passes);
+
 typedef struct {
     int32_t generations; /* generations run by this call */
     int32_t reached;     /* 1 if the elitist fitness is >= target */

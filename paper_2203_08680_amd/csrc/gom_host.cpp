@@ -1211,6 +1211,55 @@ extern "C" int gom_debug_stop_after_class(gom_state *s, int32_t class_position, 
     GUARD_END
 }
 
+// Colouring-parallel local search (declared in gom.h): passes of one k_ls_sweep launch per
+// colour class in ascending class index, a read-back of the flip flag after each pass, then
+// the generation-end epilogue without a generation count.
+extern "C" int gom_local_search(gom_state *s, int32_t max_passes, void *stream,
+                                int32_t *passes_out) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_local_search: null state");
+    if (max_passes < 0) return fail(GOM_E_ARG, "gom_local_search: max_passes %d < 0", max_passes);
+    if (!s->univariate)
+        return fail(GOM_E_STATE, "gom_local_search: the state's FOS is not univariate");
+    if (s->open_next >= 0)
+        return fail(GOM_E_STATE, "gom_local_search: a generation is open");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *d_any = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s->d_st) +
+                                                   offsetof(DevState, ls_any));
+    SweepArgs a{};
+    a.O = s->d_O;
+    a.stripes = s->d_stripes;
+    a.st = s->d_st;
+    a.roff = s->d_roff;
+    a.recs = s->d_recs;
+    a.N = s->N;
+    a.ls_any = d_any;
+    int32_t passes = 0;
+    while (passes < max_passes) {
+        HIP_TRY(hipMemsetAsync(d_any, 0, sizeof(uint32_t), st));
+        for (int32_t c = 0; c < s->k; ++c) {
+            a.cls = c;
+            a.cbase = s->class_ptr[c];
+            a.rbase = s->class_rec[c].x;
+            a.rstride = s->class_rec[c].y;
+            a.csize = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
+            HIP_TRY(launch_ls_sweep(a, s->max_grid, st));
+        }
+        HIP_TRY(hipMemcpyAsync(&s->h_st[0].ls_any, d_any, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ++passes;
+        if (!s->h_st[0].ls_any) break;
+    }
+    EpilogueArgs e = epilogue_args(s, INT64_MAX, false);
+    e.mode = kEpiLocalSearch;
+    HIP_TRY(launch_epilogue(e, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (passes_out) *passes_out = passes;
+    return GOM_OK;
+    GUARD_END
+}
+
 static int read_scalars(gom_state *s, hipStream_t st, DevState *h) {
     HIP_TRY(hipMemcpyAsync(h, s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -65,6 +65,8 @@ struct alignas(64) DevState {
     uint64_t hash;           // accumulator of the state hash's gene and elitist terms
     uint64_t fi_fail;        // solutions the last generation's forced improvement replaced
                              // by the elitist
+    uint32_t ls_any;         // local search: a flip happened in the current pass
+    uint32_t pad0;
     uint32_t fi_at[64];      // forced improvement of this generation: 0 while solution i has
                              // not improved, else kFiBase - t for the first class position t
                              // (in the generation's order) at which a step raised its fitness
@@ -123,6 +125,7 @@ struct SweepArgs {
     int32_t coop_cap;       // ... LDS words reserved per member array (the largest set)
     uint32_t *fi_at;        // DevState::fi_at of the state (forced improvement)
     int32_t fi_pos;         // forced-improvement sweep: class position in the order
+    uint32_t *ls_any;       // DevState::ls_any of the state (local search)
     const int32_t *sw;      // bit-sliced sweep table (univariate FOS, degree <= 4): kSwRows
                             // arrays of sw_stride words, entry s = class position s
     int32_t sw_stride;
@@ -173,13 +176,15 @@ struct EpilogueArgs {
     int64_t target;
     int32_t n;
     int32_t N;
-    int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh flags only
+    int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh flags only,
+                            // 3: end of a local search (P <- O, elitist on strict
+                            // improvement, no generation counted)
     int32_t row_words;      // words per row, ceil(n / 64)
     int32_t fi;             // forced improvement on: replace the solutions that it did not
                             // improve by the elitist
 };
 
-enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2 };
+enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2, kEpiLocalSearch = 3 };
 
 // Resident schedule: one block per solution runs every colour class of a generation with
 // the solution's offspring genes held in LDS (one byte per vertex), classes separated by
@@ -254,6 +259,8 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
 // Block-cooperative sweep of the large sets of one class (a.n_large blocks); max_members:
 // the largest of them (dynamic LDS of 8 bytes per member).
 hipError_t launch_split_sweep(const SweepArgs &a, hipStream_t s);
+// One colour class of the local search (univariate FOS records).
+hipError_t launch_ls_sweep(const SweepArgs &a, int max_grid, hipStream_t s);
 hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threads,
                                   hipStream_t s);
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,

@@ -1075,6 +1075,59 @@ __global__ __launch_bounds__(kSplitThreads) void k_split_commit(SweepArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Colouring-parallel local search, one colour class of a univariate FOS (the hybrid that the
+// paper's conclusion names as future work).  Wave = set {u} (class positions strided over the
+// grid's waves, XCD-contiguous), lane = solution i:
+//   gain_i = sum over u's edges (u, v, w) of (+w if O_i[u] == O_i[v], else -w)
+//   every solution with gain_i > 0 flips u: one word store O[u] ^= ballot(gain > 0)
+// Sets of one class share no variable and no edge, so no wave reads a word that another
+// writes.  The gains of the flips go to the wave's stripe; any flip sets ls_any.
+// ------------------------------------------------------------------------------------------
+constexpr int kLsThreads = 256;
+
+__global__ __launch_bounds__(kLsThreads) void k_ls_sweep(SweepArgs a) {
+    constexpr int wpb = kLsThreads / 64;
+    const int lane = threadIdx.x & 63;
+    const uint32_t i = (uint32_t)lane;
+    const int gw = xcd_tile((int)blockIdx.x, (int)gridDim.x) * wpb + (int)(threadIdx.x >> 6);
+    const int nwaves = (int)gridDim.x * wpb;
+    const bool act = (int)i < a.N;
+    int64_t facc = 0;
+    bool any = false;
+    for (int p = gw; p < a.csize; p += nwaves) {  // uniform over the wave
+        const int32_t *R = a.rstride ? a.recs + a.rbase + p * a.rstride
+                                     : a.recs + a.roff[a.cbase + p];
+        const int u = __builtin_amdgcn_readfirstlane(R[0]);
+        const int nd = __builtin_amdgcn_readfirstlane(R[1]);
+        const int2 *en = reinterpret_cast<const int2 *>(R + 4);
+        const uint64_t ow = a.O[u];
+        const uint32_t ou = bit_of(ow, i);
+        int64_t gain = 0;
+        for (int e0 = 0; e0 < nd; e0 += kBatch) {
+            int2 x[kBatch];
+            uint32_t ov[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t)
+                if (e0 + t < nd) x[t] = en[e0 + t];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t)
+                if (e0 + t < nd) ov[t] = bit_of(a.O[x[t].x], i);
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t)
+                if (e0 + t < nd) gain += signed_w(ou == ov[t], x[t].y);
+        }
+        const bool flip = act && gain > 0;
+        const uint64_t m = ballot64(flip);
+        if (lane == 0 && m) a.O[u] = ow ^ m;
+        facc += flip ? gain : 0;
+        any |= m != 0;
+    }
+    Stripe *sp = a.stripes + (gw % kStripes);
+    if (act && facc) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
+    if (any && lane == 0) atomicOr(a.ls_any, 1u);
+}
+
+// ------------------------------------------------------------------------------------------
 // Bit-parallel sweep of one colour class for a univariate FOS on a graph of degree <= 4
 // (lane = set, all solutions of a set in one 64-bit word).
 //
@@ -1427,7 +1480,8 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     st->fi_at[t] = 0u;
     if (t == 0) {
         st->fi_fail = fail;
-        const bool newE = a.mode == kEpiInit || (a.mode == kEpiGeneration && fb > fE);
+        const bool newE = a.mode == kEpiInit ||
+                      ((a.mode == kEpiGeneration || a.mode == kEpiLocalSearch) && fb > fE);
         st->best = b;
         st->new_elite = newE ? 1 : 0;
         st->active = 1;
@@ -1476,7 +1530,7 @@ __device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
     } else if (in) {
         o = o_plane;
     }
-    if (a.mode == kEpiGeneration && in) {
+    if ((a.mode == kEpiGeneration || a.mode == kEpiLocalSearch) && in) {
         const uint64_t fail = st->fi_fail;
         if (fail) {  // copies of the elitist (its bits before this generation's update)
             const uint64_t eo = 0ull - (uint64_t)bit_of(e_word, (uint32_t)(v & 63));
@@ -1678,6 +1732,14 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
     };
     if (a.mode == kSweepFi) go(std::true_type{});
     else go(std::false_type{});
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_sweep(const SweepArgs &a, int max_grid, hipStream_t s) {
+    int grid = (a.csize + kLsThreads / 64 - 1) / (kLsThreads / 64);
+    if (grid > max_grid) grid = max_grid;
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ls_sweep, dim3(grid), dim3(kLsThreads), 0, s, a);
     return hipGetLastError();
 }
 

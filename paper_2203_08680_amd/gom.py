@@ -29,7 +29,8 @@ EXPORTED = (
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
-    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_ims_bytes",
+    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_local_search",
+    "gom_ims_bytes",
     "gom_ims_run",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
     "gom_batch_set_graph", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
@@ -127,6 +128,7 @@ def lib() -> C.CDLL:
                                      _vp, _P(_vp)]),
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
         "gom_batch_set_graph": (C.c_int, [_vp, C.c_int]),
+        "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_batch_free": (None, [_vp]),
         "gom_server_create": (C.c_int, [_vp, _sz, _i32, _i32, _P(_vp)]),
@@ -409,6 +411,15 @@ def gom_debug_stop_after_class(s: GomState, class_position: int, stream=None) ->
     """Run the next generation up to class-order position class_position and leave it open."""
     _check(lib().gom_debug_stop_after_class(s.handle, int(class_position),
                                             _stream_handle(stream)))
+
+
+def gom_local_search(s: GomState, max_passes: int = 1 << 30, stream=None) -> int:
+    """Colouring-parallel local search on the population (univariate FOS, between
+    generations); returns the passes run."""
+    n = _i32()
+    _check(lib().gom_local_search(s.handle, int(max_passes), _stream_handle(stream),
+                                  C.byref(n)))
+    return int(n.value)
 
 
 def gom_state_hash(s: GomState, stream=None) -> int:

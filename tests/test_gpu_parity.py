@@ -447,6 +447,57 @@ def test_forced_improvement_linkage_tree(cuda, label, maker, bound, pop, seed, g
     lockstep(st, ref, gens, f"fi lt {label}")
 
 
+LS_CASES = [
+    # (label, graph maker, population, schedule)
+    ("torus10_p16_class", lambda: workloads.torus(10, 1, 5, seed=1), 16, gom.GOM_SCHED_CLASS_LAUNCH),
+    ("torus10_p16_resident", lambda: workloads.torus(10, 1, 5, seed=1), 16, gom.GOM_SCHED_RESIDENT),
+    ("torus12_unit_p64_bitsliced", lambda: workloads.torus(12, 1, 1, seed=2), 64,
+     gom.GOM_SCHED_BITSLICED),
+    ("cm500_d5_p33_class", lambda: workloads.configuration_model(500, 5, seed=7), 33,
+     gom.GOM_SCHED_CLASS_LAUNCH),
+    ("cm3000_d3_p64_resident", lambda: workloads.configuration_model(3000, 3, seed=8), 64,
+     gom.GOM_SCHED_RESIDENT),
+]
+
+
+@pytest.mark.parametrize("label,maker,pop,sched", LS_CASES, ids=[c[0] for c in LS_CASES])
+def test_local_search_equals_oracle(cuda, label, maker, pop, sched):
+    """Colouring-parallel local search between generations: with a pass limit of 1 and 2,
+    then unlimited, interleaved with generations; after each step the state equals the
+    oracle's and the number of passes agrees."""
+    print(f"case local search {label}", flush=True)
+    g = maker()
+    _, st, ref = make_pair(g, 0, pop, 3, sched=sched)
+    for step, limit in enumerate((1, 2, None, None, 1)):
+        gom.gom_generation(st)
+        ref.generation()
+        want = ref.local_search(10_000 if limit is None else limit)
+        got = gom.gom_local_search(st, 10_000 if limit is None else limit)
+        assert got == want, f"{label} step {step}: passes {got} vs {want}"
+        assert_same(gom.gom_state_read(st), ref.state(), f"{label} step {step}")
+    # zero passes changes nothing; at local optima a search is one idle pass
+    h = gom.gom_state_hash(st)
+    assert gom.gom_local_search(st, 0) == 0
+    assert gom.gom_state_hash(st) == h
+    assert gom.gom_local_search(st, 10_000) < 10_000
+    h = gom.gom_state_hash(st)
+    assert gom.gom_local_search(st) == 1
+    assert gom.gom_state_hash(st) == h
+
+
+def test_local_search_errors(cuda):
+    g = workloads.torus(8, 1, 5, seed=1)
+    _, st, _ = make_pair(g, 1, 8, 1)  # neighbourhood FOS
+    with pytest.raises(gom.GomError):
+        gom.gom_local_search(st, 3)
+    _, su, _ = make_pair(g, 0, 8, 1)
+    with pytest.raises(gom.GomError):
+        gom.gom_local_search(su, -1)
+    gom.gom_debug_stop_after_class(su, 0)
+    with pytest.raises(gom.GomError):  # a generation is open
+        gom.gom_local_search(su, 3)
+
+
 def test_forced_improvement_with_cut_generations_and_schedules(cuda):
     """Forced improvement after a generation cut at a class position, under the class-launch
     and resident schedules in turn; the bit-sliced schedule is left when it is turned on."""
