@@ -345,6 +345,9 @@ def main():
                     help="batched vs plain on the 256-instance mix instead of the default "
                          "single-instance workload")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--local-search", action="store_true",
+                    help="plain mode, univariate FOS: the colouring-parallel local search after "
+                         "every generation (the hybrid); reports time to optimum")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain mode: skip the comparison with the same seeds run as one batch")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
@@ -431,9 +434,22 @@ def main():
     cbytes = class_sweep_bytes(inst.graph.csr(), set_ptr, set_vars, class_ptr, class_elems,
                                wl.pop)
 
+    ls_passes = [0]
+
     def one_run(seed):
         gom.gom_state_reseed(st, seed)
-        return gom.gom_run_to_target(st, target, max_gens)
+        if not args.local_search:
+            return gom.gom_run_to_target(st, target, max_gens)
+        # hybrid: a generation, then the colouring-parallel local search, until the target
+        # or the generation limit (the search is synchronous, so the check costs nothing more)
+        gens = 0
+        r = gom.gom_run_to_target(st, target, 0)
+        while not r.reached and gens < max_gens:
+            gom.gom_generation(st)
+            ls_passes[0] += gom.gom_local_search(st)
+            gens += 1
+            r = gom.gom_run_to_target(st, target, 0)
+        return gom.RunResult(gens, r.reached, r.best, r.attempted, r.evaluated, r.accepted)
 
     for w in range(args.warmup):
         r = one_run(1000 + w)
@@ -480,7 +496,7 @@ def main():
     gens = sum(r.generations for r, _ in runs)
     tto = [dt * 1e3 for r, dt in runs if r.reached]
     value = attempted / total
-    batched = None if args.fi or args.no_batched else batched_compare(
+    batched = None if args.fi or args.no_batched or args.local_search else batched_compare(
         args, torch, gom, inst, wl.pop, target, max_gens, [r for r, _ in runs], value)
     roofline = None
     if not args.no_kernel_events and launches:
@@ -533,12 +549,14 @@ def main():
                    "classes": info["n_classes"], "seeds": list(range(1, args.steps + 1)),
                    "mode": "plain", "schedule": sched_name,
                    "class_sweep_block": gom.gom_state_get_block(st),
-                   "forced_improvement": bool(args.fi)},
+                   "forced_improvement": bool(args.fi),
+                   "local_search_after_each_generation": bool(args.local_search)},
         "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,
         "reached": len(tto), "generations_total": gens,
         "us_per_generation": total * 1e6 / max(gens, 1),
         "roofline": roofline, "cpu_baseline": cpu,
         "batched": batched,
+        "local_search_passes": ls_passes[0] if args.local_search else None,
     }
     print(json.dumps(line), flush=True)
 

@@ -147,6 +147,9 @@ WORKLOADS = {
 # 1000x1000 torus (10^6 vertices), weights U{1..100}: the HBM-bound size.
 WORKLOADS["torus1000_uni_p64"] = Workload("torus1000_uni_p64", _t1000, 0, 64, 1000, True)
 WORKLOADS["torus1000_nbhd_p64"] = Workload("torus1000_nbhd_p64", _t1000, 1, 64, 1000, True)
+# 100x100 torus, weights U{1..100}, univariate FOS (the graph's own colouring: the classes of
+# the colouring-parallel local search).
+WORKLOADS["torus100_uni_p64"] = Workload("torus100_uni_p64", _c2, 0, 64, 500, True)
 # 32x32 torus, weights U{1..100}, neighbourhood FOS: small enough to reach its optimum.
 WORKLOADS["torus32_nbhd_p64"] = Workload("torus32_nbhd_p64", lambda: torus(32, 1, 100, seed=8),
                                          1, 64, 500, True)
