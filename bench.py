@@ -46,13 +46,13 @@ WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_50
 # in profiles/.
 MEASURED_TRAFFIC = {
     ("k_class_sweep", "torus100_nbhd_p64"): {
-        "bytes": 1087536, "source": "8ddf3f7e140552f9",
+        "bytes": 1087536, "source": "6272e7f7455cb080",
         "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
     ("k_resident_sweep", "torus100_nbhd_p64"): {
-        "bytes": 16373989, "source": "8ddf3f7e140552f9",
+        "bytes": 16384322, "source": "6272e7f7455cb080",
         "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
     ("k_uni_swar_sweep", "torus1000_uni_p64"): {
-        "bytes": 24141023, "source": "8ddf3f7e140552f9",
+        "bytes": 24142278, "source": "6272e7f7455cb080",
         "profile": "profiles/k_uni_swar_sweep_torus1000_uni_p64.md"},
 }
 
