@@ -10,13 +10,18 @@
 //
 // A generation runs under one of three schedules with identical results:
 //   class launch: one k_class_sweep launch per colour class (in the generation's class
-//     order), lane = solution, offspring in the O planes;
+//     order), lane = solution, offspring in the O planes; a class's sets of 15 to 8192
+//     members go to the split sweep (k_split_donors, k_split_delta, k_split_commit: blocks
+//     of 16-member chunks) when the class holds fewer than 128 of them, else to
+//     k_large_set_sweep (one block per set);
 //   bit-sliced:   one k_uni_swar_sweep launch per colour class, lane = set, all solutions of
 //     the set in one word (univariate FOS, degree <= 4);
 //   resident:     one k_resident_sweep launch (block = solution, offspring in LDS, all
 //     classes), offspring written back as one bit row per solution;
-// then k_finalize (one block) and k_vertex_pass (P <- O, elitist, equality flags).  Integer
-// arithmetic only, so every result is exact and independent of the order in which waves run.
+// then k_finalize (one block) and k_vertex_pass (P <- O, elitist, equality flags).  Also:
+// k_batch_* (many instances in lockstep), k_ls_sweep (the colouring-parallel local search),
+// k_state_hash.  Integer arithmetic only, so every result is exact and independent of the
+// order in which waves run.
 #include <hip/hip_ext.h>
 
 #include <type_traits>

@@ -193,6 +193,23 @@ def _components_with_sets(specs, seed):
 
 
 @pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
+def test_set_above_cooperative_limit(cuda, sched):
+    """A set of 9500 members (above the 8192 of the block sweeps, so swept by the per-lane
+    path) beside sets of 8192 and 15 members and the singletons."""
+    print(f"case set above the cooperative limit sched={sched}", flush=True)
+    g = workloads.configuration_model(12_000, 3, seed=41, weights="signed50")
+    rng = np.random.default_rng(42)
+    sets = [[v] for v in range(g.n)]
+    for size in (9500, 8192, 15):
+        sets.append(sorted(rng.choice(g.n, size=size, replace=False).tolist()))
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(x) for x in sets])
+    vars_ = np.concatenate([np.asarray(x, np.int32) for x in sets])
+    _, st, ref = make_pair(g, None, 16, seed=8, sets=(ptr, vars_), sched=sched)
+    lockstep(st, ref, 2, "set above the cooperative limit")
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=SCHED_IDS)
 @pytest.mark.parametrize("pop,fi", [(40, False), (24, True)])
 def test_many_large_sets_in_one_class(cuda, sched, pop, fi):
     """A class of 270 large sets (140 of 20-30 members, 130 of 270-300): enough for one block
