@@ -65,6 +65,9 @@ def lib():
     L.or_stop_after_class.argtypes = [C.c_void_p, C.c_int32]
     L.or_local_search.restype = C.c_int32
     L.or_local_search.argtypes = [C.c_void_p, C.c_int32]
+    L.or_iterated_local_search.restype = C.c_int32
+    L.or_iterated_local_search.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                           C.c_int32]
     L.or_hash.restype = C.c_uint64
     L.or_hash.argtypes = [C.c_void_p]
     _lib = L
@@ -181,6 +184,18 @@ class Run:
         r = self._L.or_local_search(self._h, int(max_passes))
         if r < 0:
             raise ValueError("local search needs a univariate FOS and no open generation")
+        return r
+
+    def iterated_local_search(self, round0: int, rounds: int, flips: int,
+                              max_passes: int = 1 << 30) -> int:
+        """Iterated local search, rounds round0 .. round0 + rounds - 1: per round and solution
+        `flips` random single-bit flips, the local search, and the result kept when it is not
+        worse.  Returns the passes summed over the rounds."""
+        r = self._L.or_iterated_local_search(self._h, int(round0), int(rounds), int(flips),
+                                             int(max_passes))
+        if r < 0:
+            raise ValueError("iterated local search needs a univariate FOS, no open "
+                             "generation and arguments in range")
         return r
 
     def classes(self):

@@ -39,6 +39,12 @@
  *       Pinned: every solution ends at a local optimum (brute force over all single flips),
  *       fitness equals the full evaluation, a literal reading that computes a class's gains
  *       first and flips them together agrees pass by pass, a second search changes nothing.
+ *   or_iterated_local_search  the iterated form of that search (also named as future work
+ *       there): per round a perturbation of random single-bit flips, the search, and a keep-
+ *       or-revert decision per solution.  Pinned: the flipped variable of a one-flip round
+ *       against the definition of the draw, a literal reading built on the literal search,
+ *       zero-flip rounds equal the plain search, invariants (full-evaluation fitness, no
+ *       solution gets worse, local optima kept, counters unchanged).
  *   or_stop_after_class  a generation of Algorithm 3 cut after a given position of the class
  *       order (a debugging view of the offspring between two groups).  Pinned: the literal
  *       reading of Algorithms 3/4 stopped at the same group.
@@ -745,12 +751,23 @@ void or_generation(or_state *s) {
  * GOM counters do not change.  Returns the passes run, or -1 when the FOS is not univariate
  * or a generation is open.
  */
-int32_t or_local_search(or_state *s, int32_t max_passes) {
-    if (s->open_next >= 0 || max_passes < 0) return -1;
-    for (int32_t j = 0; j < s->nsets; ++j)
-        if (s->set_ptr[j + 1] - s->set_ptr[j] != 1) return -1;
+/* Change of solution i's cut when variable u of O_i flips: an uncut incident edge becomes
+   cut (+w), a cut one uncut (-w). */
+static int64_t flip_gain(const or_state *s, const uint8_t *Oi, int32_t u) {
+    int64_t gain = 0;
+    for (int64_t t = s->g.inc_ptr[u]; t < s->g.inc_ptr[u + 1]; ++t) {
+        const int64_t e = s->g.inc[t];
+        const int32_t v = s->g.eu[e] == u ? s->g.ev[e] : s->g.eu[e];
+        gain += Oi[u] == Oi[v] ? (int64_t)s->g.ew[e] : -(int64_t)s->g.ew[e];
+    }
+    return gain;
+}
+
+/* Passes of the local search over the offspring O with fitness `fit`: per pass the classes
+   in ascending index, per class every solution, per variable of the class the flip when it
+   strictly raises the cut.  Returns the number of passes. */
+static int32_t ls_passes(or_state *s, int64_t *fit, int32_t max_passes) {
     const int32_t n = s->g.n;
-    memcpy(s->O, s->P, (size_t)s->N * n);  /* between generations the offspring is P */
     int32_t passes = 0;
     while (passes < max_passes) {
         int any = 0;
@@ -759,15 +776,10 @@ int32_t or_local_search(or_state *s, int32_t max_passes) {
                 uint8_t *Oi = s->O + (size_t)i * n;
                 for (int32_t q = s->class_ptr[c]; q < s->class_ptr[c + 1]; ++q) {
                     const int32_t u = s->set_vars[s->set_ptr[s->class_elems[q]]];
-                    int64_t gain = 0;
-                    for (int64_t t = s->g.inc_ptr[u]; t < s->g.inc_ptr[u + 1]; ++t) {
-                        const int64_t e = s->g.inc[t];
-                        const int32_t v = s->g.eu[e] == u ? s->g.ev[e] : s->g.eu[e];
-                        gain += Oi[u] == Oi[v] ? (int64_t)s->g.ew[e] : -(int64_t)s->g.ew[e];
-                    }
+                    const int64_t gain = flip_gain(s, Oi, u);
                     if (gain > 0) {
                         Oi[u] ^= 1u;
-                        s->f[i] += gain;
+                        fit[i] += gain;
                         any = 1;
                     }
                 }
@@ -775,13 +787,79 @@ int32_t or_local_search(or_state *s, int32_t max_passes) {
         ++passes;
         if (!any) break;
     }
-    memcpy(s->P, s->O, (size_t)s->N * n);
+    return passes;
+}
+
+static void update_elitist(or_state *s) {
     const int32_t b = best_index(s);
     if (s->f[b] > s->fE) {
-        memcpy(s->E, s->P + (size_t)b * n, (size_t)n);
+        memcpy(s->E, s->P + (size_t)b * s->g.n, (size_t)s->g.n);
         s->fE = s->f[b];
     }
+}
+
+static int univariate_fos(const or_state *s) {
+    for (int32_t j = 0; j < s->nsets; ++j)
+        if (s->set_ptr[j + 1] - s->set_ptr[j] != 1) return 0;
+    return 1;
+}
+
+int32_t or_local_search(or_state *s, int32_t max_passes) {
+    if (s->open_next >= 0 || max_passes < 0 || !univariate_fos(s)) return -1;
+    memcpy(s->O, s->P, (size_t)s->N * s->g.n);  /* between generations the offspring is P */
+    const int32_t passes = ls_passes(s, s->f, max_passes);
+    memcpy(s->P, s->O, (size_t)s->N * s->g.n);
+    update_elitist(s);
     return passes;
+}
+
+/* Iterated local search, rounds round0 .. round0 + rounds - 1.  A round, for every solution
+   i at once:
+     perturbation: for t = 0 .. flips - 1, the word t mod 4 of
+       Philox(seed, (generation, 0xFFFFFFFE, i, 16 r + t / 4)), scaled to a class position
+       q = (word * |F|) >> 32, names the set at position q of the class-ordered list; its
+       variable flips in a copy of P_i (one after another, the fitness following each flip);
+     search: passes of the local search over the copies (as or_local_search);
+     acceptance: solution i takes its copy when the copy's fitness is at least f_i, else it
+       stays as it was;
+   then the elitist updates as at a generation end.  The generation and the GOM counters do
+   not change.  Returns the passes summed over the rounds, or -1 (nothing done) for a
+   non-univariate FOS, an open generation or arguments out of range. */
+int32_t or_iterated_local_search(or_state *s, int32_t round0, int32_t rounds, int32_t flips,
+                                 int32_t max_passes) {
+    if (s->open_next >= 0 || !univariate_fos(s) || round0 < 0 || rounds < 0 ||
+        (int64_t)round0 + rounds > (1 << 27) || flips < 0 || flips > 64 || max_passes < 0)
+        return -1;
+    const int32_t n = s->g.n;
+    int64_t *fo = malloc(sizeof(int64_t) * (size_t)s->N);
+    if (!fo) return -1;
+    int32_t total = 0;
+    for (int32_t r = round0; r < round0 + rounds; ++r) {
+        memcpy(s->O, s->P, (size_t)s->N * n);
+        for (int32_t i = 0; i < s->N; ++i) {
+            uint8_t *Oi = s->O + (size_t)i * n;
+            fo[i] = s->f[i];
+            for (int32_t t = 0; t < flips; ++t) {
+                uint32_t out[4];
+                draw4(s->seed, (uint32_t)s->gen, 0xFFFFFFFEu, (uint32_t)i,
+                      (uint32_t)r * 16u + (uint32_t)t / 4u, out);
+                const int32_t q = (int32_t)(((uint64_t)out[t % 4] * (uint64_t)s->nsets) >> 32);
+                const int32_t u = s->set_vars[s->set_ptr[s->class_elems[q]]];
+                fo[i] += flip_gain(s, Oi, u);
+                Oi[u] ^= 1u;
+            }
+        }
+        total += ls_passes(s, fo, max_passes);
+        for (int32_t i = 0; i < s->N; ++i)
+            if (fo[i] >= s->f[i]) {
+                memcpy(s->P + (size_t)i * n, s->O + (size_t)i * n, (size_t)n);
+                s->f[i] = fo[i];
+            }
+        update_elitist(s);
+    }
+    memcpy(s->O, s->P, (size_t)s->N * n);
+    free(fo);
+    return total;
 }
 
 /* Start a generation if none is open, then run the classes up to order position `pos`

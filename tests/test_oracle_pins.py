@@ -830,3 +830,135 @@ def test_local_search_second_search_is_idle_and_needs_univariate():
     nb = oracle.Run(g, ptr, vars_, pop=4, seed=1)
     with pytest.raises(ValueError):
         nb.local_search()
+
+
+# ------------------------------------------------------------------------------------------
+# Iterated local search (perturbation, search, keep-or-revert per solution)
+# ------------------------------------------------------------------------------------------
+def _perturbation_vars(seed, gen, i, r, flips, n_sets, classes, ptr, vars_):
+    """The variables a round's perturbation flips in solution i, from the draw's definition:
+    word t mod 4 of Philox4x32(key = seed, counter = (gen, 0xFFFFFFFE, i, 16 r + t // 4))
+    scaled to a class position, then that position's set."""
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    _, ce = classes
+    out = []
+    for t in range(flips):
+        word = int(oracle.philox4x32(key, (gen, 0xFFFFFFFE, i, 16 * r + t // 4))[t % 4])
+        q = (word * n_sets) >> 32
+        out.append(int(vars_[ptr[int(ce[q])]]))
+    return out
+
+
+@pytest.mark.parametrize("flips,round0,gens", [(1, 0, 0), (1, 3, 1), (5, 2, 0), (9, 0, 2)])
+def test_iterated_local_search_perturbation_follows_the_draw(flips, round0, gens):
+    """With no search passes a round is the perturbation and the acceptance alone: every
+    solution either carries exactly the drawn flips (when that does not lower its cut,
+    checked with the objective) or is unchanged."""
+    g = workloads.configuration_model(30, 3, seed=6)
+    ptr, vars_ = oracle.fos(g, 0)
+    seed = (7 << 32) | 11
+    ref = oracle.Run(g, ptr, vars_, pop=24, seed=seed)
+    for _ in range(gens):
+        ref.generation()
+    before = ref.state()
+    assert ref.iterated_local_search(round0, 1, flips, max_passes=0) == 0
+    after = ref.state()
+    changed = 0
+    for i in range(24):
+        x = before["genes"][i].copy()
+        for u in _perturbation_vars(seed, int(before["generation"]), i, round0, flips,
+                                    g.n, ref.classes(), ptr, vars_):
+            x[u] ^= 1
+        want = x if oracle.maxcut(g, x) >= oracle.maxcut(g, before["genes"][i]) \
+            else before["genes"][i]
+        assert np.array_equal(after["genes"][i], want)
+        assert after["fitness"][i] == oracle.maxcut(g, want)
+        changed += not np.array_equal(want, before["genes"][i])
+    assert changed > 0
+
+
+def _literal_iterated_local_search(g, ref, genes, elite_f, seed, gen, round0, rounds, flips,
+                                   max_passes):
+    ptr, vars_ = ref.set_ptr, ref.set_vars
+    x = genes.copy()
+    total = 0
+    for r in range(round0, round0 + rounds):
+        cand = x.copy()
+        for i in range(x.shape[0]):
+            for u in _perturbation_vars(seed, gen, i, r, flips, g.n, ref.classes(), ptr,
+                                        vars_):
+                cand[i, u] ^= 1
+        cand, p = _literal_local_search(g, ref.classes(), cand, max_passes)
+        total += p
+        for i in range(x.shape[0]):
+            if oracle.maxcut(g, cand[i]) >= oracle.maxcut(g, x[i]):
+                x[i] = cand[i]
+        fit = [oracle.maxcut(g, xi) for xi in x]
+        elite_f = max(elite_f, max(fit))
+    return x, total, elite_f
+
+
+@pytest.mark.parametrize("label,maker", LS_GRAPHS, ids=[c[0] for c in LS_GRAPHS])
+@pytest.mark.parametrize("rounds,flips,max_passes", [(1, 3, 50), (4, 2, 50), (3, 7, 1),
+                                                     (2, 64, 2)])
+def test_iterated_local_search_equals_literal_reading(label, maker, rounds, flips,
+                                                      max_passes):
+    """The oracle's iterated search equals a literal reading built on the literal local
+    search (a class's gains first, then its flips together), in genes, summed passes and
+    elitist fitness."""
+    g = maker()
+    ref = _ls_run(g, 6, 9, 1)
+    s0 = ref.state()
+    want, want_passes, want_ef = _literal_iterated_local_search(
+        g, ref, s0["genes"], int(s0["elite_fitness"]), 9, int(s0["generation"]), 1, rounds,
+        flips, max_passes)
+    assert ref.iterated_local_search(1, rounds, flips, max_passes) == want_passes
+    s1 = ref.state()
+    assert np.array_equal(s1["genes"], want)
+    assert s1["elite_fitness"] == want_ef
+
+
+@pytest.mark.parametrize("label,maker", LS_GRAPHS, ids=[c[0] for c in LS_GRAPHS])
+def test_iterated_local_search_invariants(label, maker):
+    """From local optima: every solution stays a local optimum (unlimited passes), no solution
+    gets worse, fitness is the full evaluation, the elitist is the best when that one is
+    strictly better, and the generation and GOM counters do not change."""
+    g = maker()
+    ref = _ls_run(g, 8, 4, 2)
+    ref.local_search()
+    before = ref.state()
+    ref.iterated_local_search(0, 6, 3)
+    after = ref.state()
+    for i in range(8):
+        x = after["genes"][i]
+        assert after["fitness"][i] == oracle.maxcut(g, x)
+        assert after["fitness"][i] >= before["fitness"][i]
+        assert all(_gain(g, x, u) <= 0 for u in range(g.n))
+    best = int(after["fitness"].max())
+    assert after["elite_fitness"] == max(best, before["elite_fitness"])
+    if best > before["elite_fitness"]:
+        assert np.array_equal(after["elite"], after["genes"][int(np.argmax(after["fitness"]))])
+    for key in ("generation", "attempted", "evaluated", "accepted"):
+        assert after[key] == before[key]
+
+
+def test_iterated_local_search_zero_flips_and_round_ranges():
+    """Zero-flip rounds are the plain search followed by idle one-pass rounds; rounds a..b
+    then b..c equal rounds a..c; the FOS must be univariate and the arguments in range."""
+    g = workloads.torus(6, 1, 9, seed=2)
+    a, b = _ls_run(g, 5, 2, 3), _ls_run(g, 5, 2, 3)
+    p = b.local_search()
+    assert a.iterated_local_search(0, 3, 0) == p + 2
+    for key in ("genes", "fitness", "elite", "elite_fitness"):
+        assert np.array_equal(np.asarray(a.state()[key]), np.asarray(b.state()[key]))
+    c, d = _ls_run(g, 5, 2, 3), _ls_run(g, 5, 2, 3)
+    pc = c.iterated_local_search(2, 5, 4)
+    pd = d.iterated_local_search(2, 2, 4) + d.iterated_local_search(4, 3, 4)
+    assert pc == pd
+    assert np.array_equal(c.state()["genes"], d.state()["genes"])
+    for args in ((-1, 1, 1), (0, -1, 1), (0, 1, 65), (0, 1, -1), ((1 << 27), 1, 1)):
+        with pytest.raises(ValueError):
+            c.iterated_local_search(*args)
+    ptr, vars_ = oracle.fos(g, 1)
+    with pytest.raises(ValueError):
+        oracle.Run(g, ptr, vars_, pop=4, seed=1).iterated_local_search(0, 1, 1)
