@@ -46,13 +46,13 @@ WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_50
 # in profiles/.
 MEASURED_TRAFFIC = {
     ("k_class_sweep", "torus100_nbhd_p64"): {
-        "bytes": 1087536, "source": "6272e7f7455cb080",
+        "bytes": 1083442, "source": "ee0cfe341b9c4a55",
         "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
     ("k_resident_sweep", "torus100_nbhd_p64"): {
-        "bytes": 16384322, "source": "6272e7f7455cb080",
+        "bytes": 16390442, "source": "ee0cfe341b9c4a55",
         "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
     ("k_uni_swar_sweep", "torus1000_uni_p64"): {
-        "bytes": 24142278, "source": "6272e7f7455cb080",
+        "bytes": 24131616, "source": "ee0cfe341b9c4a55",
         "profile": "profiles/k_uni_swar_sweep_torus1000_uni_p64.md"},
 }
 
@@ -348,6 +348,9 @@ def main():
     ap.add_argument("--local-search", action="store_true",
                     help="plain mode, univariate FOS: the colouring-parallel local search after "
                          "every generation (the hybrid); reports time to optimum")
+    ap.add_argument("--ils", type=int, nargs=2, metavar=("ROUNDS", "FLIPS"), default=None,
+                    help="with --local-search: after each search, the iterated local search "
+                         "(ROUNDS rounds of FLIPS drawn flips per solution)")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain mode: skip the comparison with the same seeds run as one batch")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
@@ -388,6 +391,8 @@ def main():
               "(independent instances would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
+    if args.ils and not args.local_search:
+        ap.error("--ils needs --local-search")
 
     import torch
     from paper_2203_08680_amd import build as gbuild
@@ -447,6 +452,8 @@ def main():
         while not r.reached and gens < max_gens:
             gom.gom_generation(st)
             ls_passes[0] += gom.gom_local_search(st)
+            if args.ils:
+                ls_passes[0] += gom.gom_iterated_local_search(st, 0, args.ils[0], args.ils[1])
             gens += 1
             r = gom.gom_run_to_target(st, target, 0)
         return gom.RunResult(gens, r.reached, r.best, r.attempted, r.evaluated, r.accepted)
@@ -550,7 +557,9 @@ def main():
                    "mode": "plain", "schedule": sched_name,
                    "class_sweep_block": gom.gom_state_get_block(st),
                    "forced_improvement": bool(args.fi),
-                   "local_search_after_each_generation": bool(args.local_search)},
+                   "local_search_after_each_generation": bool(args.local_search),
+                   "iterated_local_search": ({"rounds": args.ils[0], "flips": args.ils[1]}
+                                             if args.ils else None)},
         "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,
         "reached": len(tto), "generations_total": gens,
         "us_per_generation": total * 1e6 / max(gens, 1),

@@ -208,6 +208,27 @@ int gom_debug_stop_after_class(gom_state *s, int32_t class_position, void *strea
  */
 int gom_local_search(gom_state *s, int32_t max_passes, void *stream, int32_t *passes);
 
+/*
+ * Iterated local search around the search above (the conclusion's "(iterated)" hybrid; the
+ * paper gives no procedure, so this is one reading of it).  Rounds round0 .. round0+rounds-1,
+ * each for every solution i at once:
+ *   perturbation: for t = 0 .. flips-1, word (t mod 4) of Philox4x32-10(key = seed, counter =
+ *     (generation, 0xFFFFFFFE, i, 16 r + t / 4)) scaled to q = (word * n_sets) >> 32 names
+ *     the set at position q of the colour-class order (classes in index order, sets ascending
+ *     within a class); its variable flips in a copy of solution i, one flip after another;
+ *   search: the passes of gom_local_search on the copies (at most max_passes);
+ *   acceptance: solution i becomes its copy unless the copy's fitness is below its own;
+ * then the elitist is replaced when the best solution is strictly better.  The generation and
+ * the attempted/evaluated/accepted counters do not change.  Rounds are numbered so that
+ * rounds [a, b) then [b, c) equal rounds [a, c); the same rounds at the same generation draw
+ * the same flips.  Synchronous.  *passes (may be NULL): search passes summed over the rounds.
+ * Errors: GOM_E_ARG (null state, round0 < 0, rounds < 0, round0 + rounds > 2^27, flips
+ * outside 0..64, max_passes < 0), GOM_E_STATE (FOS not univariate, or a generation left open),
+ * GOM_E_DEVICE.
+ */
+int gom_iterated_local_search(gom_state *s, int32_t round0, int32_t rounds, int32_t flips,
+                              int32_t max_passes, void *stream, int32_t *passes);
+
 typedef struct {
     int32_t generations; /* generations run by this call */
     int32_t reached;     /* 1 if the elitist fitness is >= target */

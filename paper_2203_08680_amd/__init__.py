@@ -11,7 +11,7 @@ from .gom import (  # noqa: F401
     GOM_SCHED_CLASS_LAUNCH, GOM_SCHED_RESIDENT, GomBatch, GomError, GomServer, Instance,
     gom_batch_init, gom_batch_run, gom_batch_set_graph, gom_colour, gom_colour_get, gom_debug_stop_after_class,
     gom_fos_build, gom_fos_build_lt, gom_fos_from_sets, gom_generation, gom_ims_run,
-    gom_local_search,
+    gom_iterated_local_search, gom_local_search,
     gom_run_to_target,
     gom_state_autotune, gom_state_bytes, gom_state_get_block, gom_state_get_fi, gom_state_get_schedule, gom_state_hash, gom_state_init,
     gom_state_read, gom_state_reseed, gom_state_set_block, gom_state_set_fi, gom_state_set_schedule, gom_state_write,

@@ -1211,19 +1211,12 @@ extern "C" int gom_debug_stop_after_class(gom_state *s, int32_t class_position, 
     GUARD_END
 }
 
-// Colouring-parallel local search (declared in gom.h): passes of one k_ls_sweep launch per
-// colour class in ascending class index, a read-back of the flip flag after each pass, then
-// the generation-end epilogue without a generation count.
-extern "C" int gom_local_search(gom_state *s, int32_t max_passes, void *stream,
-                                int32_t *passes_out) {
-    GUARD_BEGIN
-    if (!s) return fail(GOM_E_ARG, "gom_local_search: null state");
-    if (max_passes < 0) return fail(GOM_E_ARG, "gom_local_search: max_passes %d < 0", max_passes);
-    if (!s->univariate)
-        return fail(GOM_E_STATE, "gom_local_search: the state's FOS is not univariate");
-    if (s->open_next >= 0)
-        return fail(GOM_E_STATE, "gom_local_search: a generation is open");
-    hipStream_t st = (hipStream_t)stream;
+static int read_scalars(gom_state *s, hipStream_t st, DevState *h);
+
+// Passes of the colouring-parallel local search over the O planes: one k_ls_sweep launch per
+// colour class in ascending class index, then a read-back of the flip flag; the passes stop
+// after one that flipped nothing, or at max_passes.
+static int ls_pass_loop(gom_state *s, int32_t max_passes, hipStream_t st, int32_t *passes_out) {
     uint32_t *d_any = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s->d_st) +
                                                    offsetof(DevState, ls_any));
     SweepArgs a{};
@@ -1251,11 +1244,81 @@ extern "C" int gom_local_search(gom_state *s, int32_t max_passes, void *stream,
         ++passes;
         if (!s->h_st[0].ls_any) break;
     }
+    *passes_out = passes;
+    return GOM_OK;
+}
+
+// Colouring-parallel local search (declared in gom.h): the pass loop above, then the
+// generation-end epilogue without a generation count.
+extern "C" int gom_local_search(gom_state *s, int32_t max_passes, void *stream,
+                                int32_t *passes_out) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_local_search: null state");
+    if (max_passes < 0) return fail(GOM_E_ARG, "gom_local_search: max_passes %d < 0", max_passes);
+    if (!s->univariate)
+        return fail(GOM_E_STATE, "gom_local_search: the state's FOS is not univariate");
+    if (s->open_next >= 0)
+        return fail(GOM_E_STATE, "gom_local_search: a generation is open");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t passes = 0;
+    int rc = ls_pass_loop(s, max_passes, st, &passes);
+    if (rc) return rc;
     EpilogueArgs e = epilogue_args(s, INT64_MAX, false);
     e.mode = kEpiLocalSearch;
     HIP_TRY(launch_epilogue(e, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (passes_out) *passes_out = passes;
+    return GOM_OK;
+    GUARD_END
+}
+
+// Iterated local search (declared in gom.h): per round one k_perturb launch (the flips go
+// into O, their gains into a stripe), the pass loop, and the epilogue in its iterated mode
+// (each solution keeps the round's result unless its fitness fell, then P <- O).
+extern "C" int gom_iterated_local_search(gom_state *s, int32_t round0, int32_t rounds,
+                                         int32_t flips, int32_t max_passes, void *stream,
+                                         int32_t *passes_out) {
+    GUARD_BEGIN
+    if (!s) return fail(GOM_E_ARG, "gom_iterated_local_search: null state");
+    if (round0 < 0 || rounds < 0 || (int64_t)round0 + rounds > kMaxPerturbRounds)
+        return fail(GOM_E_ARG, "gom_iterated_local_search: rounds [%d, %d + %d) outside "
+                    "[0, 2^27)", round0, round0, rounds);
+    if (flips < 0 || flips > 64)
+        return fail(GOM_E_ARG, "gom_iterated_local_search: flips %d outside 0..64", flips);
+    if (max_passes < 0)
+        return fail(GOM_E_ARG, "gom_iterated_local_search: max_passes %d < 0", max_passes);
+    if (!s->univariate)
+        return fail(GOM_E_STATE, "gom_iterated_local_search: the state's FOS is not univariate");
+    if (s->open_next >= 0)
+        return fail(GOM_E_STATE, "gom_iterated_local_search: a generation is open");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = read_scalars(s, st, &s->h_st[0]);
+    if (rc) return rc;
+    PerturbArgs pa{};
+    pa.P = s->d_P;
+    pa.O = s->d_O;
+    pa.recs = s->d_recs;
+    pa.roff = s->d_roff;
+    pa.stripes = s->d_stripes;
+    pa.seed = s->seed;
+    pa.gen = s->h_st[0].generation;
+    pa.flips = flips;
+    pa.n_sets = s->n_sets;
+    pa.N = s->N;
+    EpilogueArgs e = epilogue_args(s, INT64_MAX, false);
+    e.mode = kEpiIterated;
+    int32_t total = 0;
+    for (int32_t r = round0; r < round0 + rounds; ++r) {
+        pa.round = r;
+        HIP_TRY(launch_perturb(pa, st));
+        int32_t passes = 0;
+        rc = ls_pass_loop(s, max_passes, st, &passes);
+        if (rc) return rc;
+        total += passes;
+        HIP_TRY(launch_epilogue(e, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (passes_out) *passes_out = total;
     return GOM_OK;
     GUARD_END
 }

@@ -46,10 +46,12 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Counter word values that keep the three Philox streams apart: generation indices and class
-// indices are below 0xFFFFFFFF.
+// Counter word values that keep the Philox streams apart: generation indices are below
+// 0xFFFFFFFF and class indices below 0xFFFFFFFE.
 constexpr uint32_t kInitStream = 0xFFFFFFFFu;   // counter (kInitStream, i, v/128, 0)
 constexpr uint32_t kOrderStream = 0xFFFFFFFFu;  // counter (g, kOrderStream, t, 0)
+constexpr uint32_t kPerturbStream = 0xFFFFFFFEu;  // counter (g, kPerturbStream, i, 16r + t/4)
+constexpr int32_t kMaxPerturbRounds = 1 << 27;     // 16 r + t/4 stays below 2^32
 
 // Per-run scalars.  The finalize kernel updates them once per generation.
 struct alignas(64) DevState {
@@ -70,6 +72,8 @@ struct alignas(64) DevState {
     uint32_t fi_at[64];      // forced improvement of this generation: 0 while solution i has
                              // not improved, else kFiBase - t for the first class position t
                              // (in the generation's order) at which a step raised its fitness
+    uint64_t ils_rej;        // iterated local search: solutions whose last round ended worse
+                             // than they started (they return to P)
 };
 
 // A solution's forced improvement stops after the first class in which it improved, so a
@@ -164,6 +168,22 @@ constexpr int kCoopSmallBlock = 256;
 // Generation end, in two launches: k_finalize (one block: fitness from the stripes, best
 // solution, elitist decision, counters, generation count) then k_vertex_pass (all vertices:
 // P <- O, elitist bits, solutions differing from the elitist into the stripes).
+// One round's perturbation of the iterated local search (univariate FOS): solution i flips
+// `flips` drawn variables in O, one after another.
+struct PerturbArgs {
+    const uint64_t *P;      // population planes (equal to O when the round starts; not written)
+    uint64_t *O;            // offspring planes: the flips go here
+    const int32_t *recs;    // set records; record of class position q at word roff[q]
+    const int32_t *roff;
+    Stripe *stripes;        // the flips' fitness changes go to stripe 0
+    uint64_t seed;
+    int32_t gen;            // generation count, first counter word of the draws
+    int32_t round;          // round index r
+    int32_t flips;          // flips per solution, 0..64
+    int32_t n_sets;         // |F| (class positions 0..n_sets-1)
+    int32_t N;
+};
+
 struct EpilogueArgs {
     uint64_t *P;
     uint64_t *O;            // offspring planes (read; rewritten when rows is set)
@@ -178,13 +198,15 @@ struct EpilogueArgs {
     int32_t N;
     int32_t mode;           // 0: generation end, 1: initial elitist, 2: refresh flags only,
                             // 3: end of a local search (P <- O, elitist on strict
-                            // improvement, no generation counted)
+                            // improvement, no generation counted), 4: end of an iterated
+                            // local search round (as 3, but a solution whose fitness fell
+                            // keeps P)
     int32_t row_words;      // words per row, ceil(n / 64)
     int32_t fi;             // forced improvement on: replace the solutions that it did not
                             // improve by the elitist
 };
 
-enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2, kEpiLocalSearch = 3 };
+enum { kEpiGeneration = 0, kEpiInit = 1, kEpiRefresh = 2, kEpiLocalSearch = 3, kEpiIterated = 4 };
 
 // Resident schedule: one block per solution runs every colour class of a generation with
 // the solution's offspring genes held in LDS (one byte per vertex), classes separated by
@@ -261,6 +283,7 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
 hipError_t launch_split_sweep(const SweepArgs &a, hipStream_t s);
 // One colour class of the local search (univariate FOS records).
 hipError_t launch_ls_sweep(const SweepArgs &a, int max_grid, hipStream_t s);
+hipError_t launch_perturb(const PerturbArgs &a, hipStream_t s);
 hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threads,
                                   hipStream_t s);
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,

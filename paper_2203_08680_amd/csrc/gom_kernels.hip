@@ -20,7 +20,7 @@
 //     classes), offspring written back as one bit row per solution;
 // then k_finalize (one block) and k_vertex_pass (P <- O, elitist, equality flags).  Also:
 // k_batch_* (many instances in lockstep), k_ls_sweep (the colouring-parallel local search),
-// k_state_hash.  Integer arithmetic only, so every result is exact and independent of the
+// k_perturb (its iterated form's perturbation), k_state_hash.  Integer arithmetic only, so every result is exact and independent of the
 // order in which waves run.
 #include <hip/hip_ext.h>
 
@@ -1133,6 +1133,52 @@ __global__ __launch_bounds__(kLsThreads) void k_ls_sweep(SweepArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Perturbation of one round of the iterated local search, one wave, lane = solution i.  Flip
+// t < flips: word t mod 4 of Philox(seed; g, kPerturbStream, i, 16 r + t / 4), scaled to a
+// class position q = (word * |F|) >> 32, names a set; its variable u flips in O_i and the
+// flip's gain (against the genes after the earlier flips) adds to the solution's fitness
+// change.  Genes are read from P, which the round leaves alone (O equals P when it starts),
+// with the lane's earlier flips (its own column of an LDS list) applied on top, so no lane
+// reads a word that is being written.  The flips go into O by atomic XOR: two lanes may flip
+// the same word.
+// ------------------------------------------------------------------------------------------
+constexpr int kPerturbMaxFlips = 64;
+
+__global__ __launch_bounds__(64) void k_perturb(PerturbArgs a) {
+    __shared__ int32_t done[kPerturbMaxFlips][64];
+    const int lane = threadIdx.x;
+    if (lane >= a.N) return;
+    const uint32_t i = (uint32_t)lane;
+    auto gene = [&](int v, int flipped) {
+        uint32_t b = bit_of(a.P[v], i);
+        for (int s = 0; s < flipped; ++s) b ^= (uint32_t)(done[s][lane] == v);
+        return b;
+    };
+    int64_t d = 0;
+    U32x4 r{};
+    for (int t = 0; t < a.flips; ++t) {
+        if ((t & 3) == 0)
+            r = philox(a.seed, (uint32_t)a.gen, kPerturbStream, i,
+                       (uint32_t)a.round * 16u + (uint32_t)(t >> 2));
+        const uint32_t w = (t & 3) == 0 ? r.x : (t & 3) == 1 ? r.y : (t & 3) == 2 ? r.z : r.w;
+        const int q = (int)(((uint64_t)w * (uint64_t)a.n_sets) >> 32);
+        const int32_t *R = a.recs + a.roff[q];
+        const int u = R[0], nd = R[1];
+        const int2 *en = reinterpret_cast<const int2 *>(R + 4);
+        const uint32_t ou = gene(u, t);
+        int64_t gain = 0;
+        for (int e = 0; e < nd; ++e) {
+            const int2 x = en[e];
+            gain += signed_w(ou == gene(x.x, t), x.y);
+        }
+        d += gain;
+        done[t][lane] = u;
+        atomicXor((unsigned long long *)&a.O[u], 1ull << i);
+    }
+    if (d) atomicAdd((unsigned long long *)&a.stripes[0].fit[i], (unsigned long long)d);
+}
+
+// ------------------------------------------------------------------------------------------
 // Bit-parallel sweep of one colour class for a univariate FOS on a graph of degree <= 4
 // (lane = set, all solutions of a set in one 64-bit word).
 //
@@ -1432,8 +1478,10 @@ __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArg
 // Generation end (Algorithm 3: P <- O; the elitist is kept across generations), part 1, one
 // wave: fitness of solution t = previous fitness + the stripes' changes; counters; best
 // solution b (lowest index on ties); the elitist becomes P_b when f_b is strictly better
-// (mode 0), always (mode 1, initial population) or never (mode 2).  Clears the stripes.
-// A generation skipped because the target was reached leaves everything as it is.
+// (modes 0, 3, 4), always (mode 1, initial population) or never (mode 2).  In mode 4 (end
+// of an iterated-local-search round) a solution whose change is negative keeps its previous
+// fitness and is marked to keep its P genes.  Clears the stripes.  A generation skipped
+// because the target was reached leaves everything as it is.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     DevState *st = a.st;
@@ -1457,9 +1505,11 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
         const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
         fail = popm & ~wave_or64(s_acc) & ~ballot64(fi_at != 0u);
     }
+    // iterated local search: a solution whose round lowered its fitness keeps P
+    const uint64_t rej = a.mode == kEpiIterated ? ballot64(t < a.N && d < 0) : 0ull;
     int64_t f = INT64_MIN;
     if (t < a.N) {
-        f = bit_of(fail, (uint32_t)t) ? fE : fit_t + d;
+        f = bit_of(fail, (uint32_t)t) ? fE : bit_of(rej, (uint32_t)t) ? fit_t : fit_t + d;
         a.fit[t] = f;
     }
     const int64_t ev = wave_sum64((int64_t)s_ev);
@@ -1485,8 +1535,10 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
     st->fi_at[t] = 0u;
     if (t == 0) {
         st->fi_fail = fail;
+        st->ils_rej = rej;
         const bool newE = a.mode == kEpiInit ||
-                      ((a.mode == kEpiGeneration || a.mode == kEpiLocalSearch) && fb > fE);
+                      ((a.mode == kEpiGeneration || a.mode == kEpiLocalSearch ||
+                        a.mode == kEpiIterated) && fb > fE);
         st->best = b;
         st->new_elite = newE ? 1 : 0;
         st->active = 1;
@@ -1501,8 +1553,9 @@ __device__ __forceinline__ void finalize_body(const EpilogueArgs &a) {
 __global__ __launch_bounds__(64) void k_finalize(EpilogueArgs a) { finalize_body(a); }
 
 // ------------------------------------------------------------------------------------------
-// Generation end, part 2, one thread per vertex: P <- O (mode 0; from the O planes, or from
-// the solutions' bit rows under the resident schedule, then O is refreshed too), the elitist
+// Generation end, part 2, one thread per vertex: P <- O (modes 0 and 3; from the O planes,
+// or from the solutions' bit rows under the resident schedule, then O is refreshed too; in
+// mode 4 the solutions marked by the finalize take P back into O instead), the elitist
 // bits (rewritten from P_b when the elitist changed), and the solutions whose genes differ
 // from the elitist, OR-ed per block into the block's stripe.  The next generation's sweeps
 // read those stripes to know which solutions equal the elitist.
@@ -1543,6 +1596,13 @@ __device__ __forceinline__ void vertex_body(const EpilogueArgs &a, int vblock) {
         }
         a.P[v] = o;
         if (a.rows || fail) a.O[v] = o;
+    } else if (a.mode == kEpiIterated && in) {
+        const uint64_t rej = st->ils_rej;
+        if (rej) {  // solutions that return to P
+            o = (o & ~rej) | (a.P[v] & rej);
+            a.O[v] = o;
+        }
+        a.P[v] = o;
     }
     uint32_t eb;
     if (newE) {
@@ -1745,6 +1805,14 @@ hipError_t launch_ls_sweep(const SweepArgs &a, int max_grid, hipStream_t s) {
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL(k_ls_sweep, dim3(grid), dim3(kLsThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_perturb(const PerturbArgs &a, hipStream_t s) {
+    if (a.flips < 1) return hipSuccess;
+    if (a.flips > kPerturbMaxFlips || a.N < 1 || a.N > 64 || a.n_sets < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_perturb, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

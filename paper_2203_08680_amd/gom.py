@@ -30,6 +30,7 @@ EXPORTED = (
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
     "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_local_search",
+    "gom_iterated_local_search",
     "gom_ims_bytes",
     "gom_ims_run",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
@@ -129,6 +130,7 @@ def lib() -> C.CDLL:
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
         "gom_batch_set_graph": (C.c_int, [_vp, C.c_int]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
+        "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
         "gom_batch_free": (None, [_vp]),
         "gom_server_create": (C.c_int, [_vp, _sz, _i32, _i32, _P(_vp)]),
@@ -419,6 +421,18 @@ def gom_local_search(s: GomState, max_passes: int = 1 << 30, stream=None) -> int
     n = _i32()
     _check(lib().gom_local_search(s.handle, int(max_passes), _stream_handle(stream),
                                   C.byref(n)))
+    return int(n.value)
+
+
+def gom_iterated_local_search(s: GomState, round0: int, rounds: int, flips: int,
+                              max_passes: int = 1 << 30, stream=None) -> int:
+    """Iterated local search (univariate FOS, between generations): rounds round0 ..
+    round0 + rounds - 1 of drawn single-bit flips, the local search, and keep-unless-worse per
+    solution; returns the search passes summed over the rounds."""
+    n = _i32()
+    _check(lib().gom_iterated_local_search(s.handle, int(round0), int(rounds), int(flips),
+                                           int(max_passes), _stream_handle(stream),
+                                           C.byref(n)))
     return int(n.value)
 
 

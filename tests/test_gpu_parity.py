@@ -515,6 +515,52 @@ def test_local_search_errors(cuda):
         gom.gom_local_search(su, 3)
 
 
+ILS_CASES = LS_CASES + [
+    ("torus100_p64_bitsliced", lambda: workloads.torus(100, 1, 100, seed=2), 64,
+     gom.GOM_SCHED_BITSLICED),
+]
+# (round0, rounds, flips, max_passes) after each of a run's generations
+ILS_STEPS = [(0, 1, 1, 0), (1, 3, 4, 10_000), (4, 2, 64, 2), (0, 2, 0, 10_000), (6, 1, 13, 1)]
+
+
+@pytest.mark.parametrize("label,maker,pop,sched", ILS_CASES, ids=[c[0] for c in ILS_CASES])
+def test_iterated_local_search_equals_oracle(cuda, label, maker, pop, sched):
+    """Iterated local search between generations (perturbation only, full searches, the
+    largest perturbation with a pass limit, zero flips, one pass): after each call the state
+    equals the oracle's and the summed passes agree; zero rounds change nothing."""
+    print(f"case iterated local search {label}", flush=True)
+    g = maker()
+    _, st, ref = make_pair(g, 0, pop, 5, sched=sched)
+    for step, (r0, rounds, flips, limit) in enumerate(ILS_STEPS):
+        gom.gom_generation(st)
+        ref.generation()
+        want = ref.iterated_local_search(r0, rounds, flips, limit)
+        got = gom.gom_iterated_local_search(st, r0, rounds, flips, limit)
+        assert got == want, f"{label} step {step}: passes {got} vs {want}"
+        assert_same(gom.gom_state_read(st), ref.state(), f"{label} ils step {step}")
+    h = gom.gom_state_hash(st)
+    assert gom.gom_iterated_local_search(st, 3, 0, 5) == 0
+    assert gom.gom_state_hash(st) == h
+    gom.gom_generation(st)  # the generations after a search still match
+    ref.generation()
+    assert_same(gom.gom_state_read(st), ref.state(), f"{label} generation after the search")
+
+
+def test_iterated_local_search_errors(cuda):
+    g = workloads.torus(8, 1, 5, seed=1)
+    _, st, _ = make_pair(g, 1, 8, 1)  # neighbourhood FOS
+    with pytest.raises(gom.GomError):
+        gom.gom_iterated_local_search(st, 0, 1, 1)
+    _, su, _ = make_pair(g, 0, 8, 1)
+    for args in ((-1, 1, 1, 5), (0, -1, 1, 5), (0, 1, 65, 5), (0, 1, -1, 5), (0, 1, 1, -1),
+                 ((1 << 27) - 1, 2, 1, 5)):
+        with pytest.raises(gom.GomError):
+            gom.gom_iterated_local_search(su, *args)
+    gom.gom_debug_stop_after_class(su, 0)
+    with pytest.raises(gom.GomError):  # a generation is open
+        gom.gom_iterated_local_search(su, 0, 1, 1)
+
+
 def test_forced_improvement_with_cut_generations_and_schedules(cuda):
     """Forced improvement after a generation cut at a class position, under the class-launch
     and resident schedules in turn; the bit-sliced schedule is left when it is turned on."""
