@@ -202,7 +202,9 @@ uint32_t uni_tables(const mc_graph &g, int32_t u) {
 
 // The bit-sliced schedule handles univariate FOS on graphs of degree <= 4 whose per-vertex
 // sums of |w| stay below 2^30 (its per-solution gains are int32).
-bool swar_eligible(const mc_graph &g, const gom_fos &f) {
+// max_abs_out (may be null): the largest sum of |w| over a vertex's edges, a bound on the
+// size of one flip's fitness change.
+bool swar_eligible(const mc_graph &g, const gom_fos &f, int64_t *max_abs_out = nullptr) {
     if (f.max_set != 1 || g.max_degree > 4) return false;
     int64_t max_abs = 0;
     for (int32_t v = 0; v < g.n; ++v) {
@@ -211,6 +213,7 @@ bool swar_eligible(const mc_graph &g, const gom_fos &f) {
             t += g.wt[r] < 0 ? -(int64_t)g.wt[r] : (int64_t)g.wt[r];
         max_abs = std::max(max_abs, t);
     }
+    if (max_abs_out) *max_abs_out = max_abs;
     return max_abs < ((int64_t)1 << 30);
 }
 
@@ -368,6 +371,7 @@ struct gom_state {
     bool resident_plds = false;          // ... with a copy of P in LDS as well
     size_t lds_max = 0;                  // LDS bytes a block may use on the device
     bool bitsliced_ok = false;           // bit-sliced schedule fits the instance
+    bool swar_narrow = false;            // its per-block fitness sums fit in int32
     bool partition = false;              // every variable in exactly one set
     bool fi = false;                     // forced improvement after each generation's classes
     int32_t *d_eu = nullptr, *d_ev = nullptr, *d_ew = nullptr;
@@ -967,7 +971,7 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         const int32_t nl = s->coop_ptr[2 * (size_t)c + 2] - s->coop_ptr[2 * (size_t)c];
         a.coop = nl > 0 ? 1 : 0;
         if (s->sched == GOM_SCHED_BITSLICED && !forced)
-            HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->max_grid, st, ev));
+            HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->swar_narrow, s->max_grid, st, ev));
         else
             HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, s->sweep_threads,
                                        st, ev));
@@ -1076,7 +1080,8 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     rc = build_records(*g, *f, f->max_set == 1, R);
     if (rc) return rc;
     const CoopSets CS = coop_sets(*f, f->max_set == 1);
-    const bool swar = swar_eligible(*g, *f);
+    int64_t swar_abs = 0;
+    const bool swar = swar_eligible(*g, *f, &swar_abs);
     const std::vector<int32_t> SW = swar ? build_swar(*g, *f) : std::vector<int32_t>();
     const Layout L = make_layout(g->n, g->m, f->n_sets, f->k, pop, (int64_t)R.words.size(),
                                  (int64_t)CS.pos.size(), (int64_t)SW.size(),
@@ -1151,6 +1156,11 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
                          resident_lds_bytes(s->n, false) <= s->lds_max;
         s->resident_plds = s->resident_ok && resident_lds_bytes(s->n, true) <= s->lds_max;
         s->bitsliced_ok = swar;
+        // a block sums the changes of at most 256 threads x (sets per thread) flips per solution
+        const int64_t per_thread =
+            ((int64_t)s->max_class + (int64_t)s->max_grid * kSwarThreads - 1) /
+            ((int64_t)s->max_grid * kSwarThreads);
+        s->swar_narrow = swar && swar_abs * kSwarThreads * per_thread < ((int64_t)1 << 31);
         s->partition = s->univariate && f->n_sets == g->n;
         s->sched = auto_schedule(s);
     }

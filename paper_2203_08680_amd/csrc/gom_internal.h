@@ -286,8 +286,10 @@ hipError_t launch_ls_sweep(const SweepArgs &a, int max_grid, hipStream_t s);
 hipError_t launch_perturb(const PerturbArgs &a, hipStream_t s);
 hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threads,
                                   hipStream_t s);
-hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
+// narrow: the host has checked that a block's per-solution fitness sums fit in int32.
+hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow, int max_grid,
                                  hipStream_t s, KernelEvents ev = {});
+constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
 // plds: keep a copy of P in LDS (needs resident_lds_bytes(n, true) of LDS).
 hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hipStream_t s,
                                  KernelEvents ev = {});

@@ -1201,21 +1201,28 @@ __global__ __launch_bounds__(64) void k_perturb(PerturbArgs a) {
 // lane reads 24 bytes (u, tables, four neighbours) with six coalesced loads; the weights are
 // read only when one of the lane's solutions accepts.
 // ------------------------------------------------------------------------------------------
-constexpr int kSwarThreads = 256;
 
 __device__ __forceinline__ uint64_t sel64(uint64_t m, uint64_t a, uint64_t b) {
     return (a & m) | (b & ~m);  // per bit: m ? a : b
 }
 
+// All ones when bit b of t is set, else zero (one signed bit-field extract).
+__device__ __forceinline__ uint32_t bit_mask32(uint32_t t, int b) {
+    return (uint32_t)(((int32_t)(t << (31 - b))) >> 31);
+}
+
 // 16-entry truth table t (bit p = value for pattern p = q0 + 2 q1 + 4 q2 + 8 q3) evaluated
-// bitwise on the four masks.
+// bitwise on the four masks.  Leaf k covers patterns 2k (q0 = 0) and 2k + 1 (q0 = 1): with
+// their table bits spread to all-ones/zero words A and B it is (q0 & B) | (~q0 & A), one
+// bit-field insert per 32-bit half; then a select tree on q1, q2, q3.
 __device__ __forceinline__ uint64_t table16(uint32_t t, uint64_t q0, uint64_t q1, uint64_t q2,
                                             uint64_t q3) {
+    const uint32_t q0l = (uint32_t)q0, q0h = (uint32_t)(q0 >> 32);
     uint64_t l[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t t2 = (t >> (2 * k)) & 3u;
-        l[k] = ((t2 & 1u) ? ~q0 : 0ull) | ((t2 & 2u) ? q0 : 0ull);
+        const uint32_t A = bit_mask32(t, 2 * k), B = bit_mask32(t, 2 * k + 1);
+        l[k] = (uint64_t)((q0l & B) | (~q0l & A)) | ((uint64_t)((q0h & B) | (~q0h & A)) << 32);
     }
     uint64_t m1[4];
 #pragma unroll
@@ -1224,8 +1231,11 @@ __device__ __forceinline__ uint64_t table16(uint32_t t, uint64_t q0, uint64_t q1
     return sel64(q3, m21, m20);
 }
 
-template <bool PARTITION>
+// NARROW: the block's per-solution fitness sums fit in int32 (the host checks the weights'
+// bound), so they are kept as 32-bit LDS counters; else 64-bit.
+template <bool PARTITION, bool NARROW>
 __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
+    using Acc = std::conditional_t<NARROW, int, unsigned long long>;
     const int stride = gridDim.x * kSwarThreads;
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const size_t ss = (size_t)a.sw_stride;
@@ -1247,12 +1257,25 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
     const bool live = a.st->elite_fitness < a.target;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
     const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
-    __shared__ unsigned long long fa[64];
+    __shared__ Acc fa[64];
     __shared__ uint32_t redc[2][kSwarThreads / 64];
-    if (threadIdx.x < 64) fa[threadIdx.x] = 0ull;
+    if (threadIdx.x < 64) fa[threadIdx.x] = 0;
     __syncthreads();
     if (!live) return;  // uniform over the grid
     uint32_t n_eval = 0, n_acc = 0;
+    // change of solution base + j for every set bit j of m (one 32-bit half of the accepted
+    // mask): 2 * (sum of w_k over the edges that become cut) - (sum of all four w_k)
+    auto add_flips = [&](uint32_t m, int base, uint32_t h0, uint32_t h1, uint32_t h2,
+                         uint32_t h3, int w0, int w1, int w2, int w3, int wsum) {
+        for (; m; m &= m - 1) {
+            const uint32_t j = (uint32_t)__builtin_ctz(m);
+            // bit j of h spread to all ones or zero (signed bit-field extract)
+            auto spread = [&](uint32_t h) { return __builtin_amdgcn_sbfe((int)h, j, 1u); };
+            const int cut = (w0 & spread(h0)) + (w1 & spread(h1)) + (w2 & spread(h2)) +
+                            (w3 & spread(h3));
+            atomicAdd(&fa[base + (int)j], (Acc)(2 * cut - wsum));
+        }
+    };
     for (; p < a.csize; p += stride) {
         if (p != tile * kSwarThreads + (int)threadIdx.x) en = entry(p);
         const int32_t *T = a.sw + a.cbase + p;
@@ -1280,12 +1303,11 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
             // costs more than this extra round trip for the sets that accept
             const int w0 = T[kSwW * ss], w1 = T[(kSwW + 1) * ss];
             const int w2 = T[(kSwW + 2) * ss], w3 = T[(kSwW + 3) * ss];
-            for (uint64_t m = acc; m; m &= m - 1) {
-                const uint32_t i = (uint32_t)__builtin_ctzll(m);
-                const int d = (bit_of(q0, i) ? w0 : -w0) + (bit_of(q1, i) ? w1 : -w1) +
-                              (bit_of(q2, i) ? w2 : -w2) + (bit_of(q3, i) ? w3 : -w3);
-                atomicAdd(&fa[i], (unsigned long long)(long long)d);
-            }
+            const int wsum = w0 + w1 + w2 + w3;
+            add_flips((uint32_t)acc, 0, (uint32_t)q0, (uint32_t)q1, (uint32_t)q2,
+                      (uint32_t)q3, w0, w1, w2, w3, wsum);
+            add_flips((uint32_t)(acc >> 32), 32, (uint32_t)(q0 >> 32), (uint32_t)(q1 >> 32),
+                      (uint32_t)(q2 >> 32), (uint32_t)(q3 >> 32), w0, w1, w2, w3, wsum);
         }
     }
     const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
@@ -1297,7 +1319,8 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
     __syncthreads();
     Stripe *sp = a.stripes + (blockIdx.x % kStripes);
     if ((int)threadIdx.x < a.N && fa[threadIdx.x])
-        atomicAdd((unsigned long long *)&sp->fit[threadIdx.x], fa[threadIdx.x]);
+        atomicAdd((unsigned long long *)&sp->fit[threadIdx.x],
+                  (unsigned long long)(long long)fa[threadIdx.x]);
     if (threadIdx.x == 0) {
         uint32_t se = 0, sa = 0;
         for (int w = 0; w < kSwarThreads / 64; ++w) {
@@ -1847,15 +1870,16 @@ hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threa
     return hipGetLastError();
 }
 
-hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, int max_grid,
+hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow, int max_grid,
                                  hipStream_t s, KernelEvents ev) {
     int grid = (a.csize + kSwarThreads - 1) / kSwarThreads;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
-    if (partition)
-        launch_timed(k_uni_swar_sweep<true>, dim3(grid), dim3(kSwarThreads), 0, s, ev, a);
-    else
-        launch_timed(k_uni_swar_sweep<false>, dim3(grid), dim3(kSwarThreads), 0, s, ev, a);
+    const dim3 gd(grid), bd(kSwarThreads);
+    if (partition && narrow) launch_timed(k_uni_swar_sweep<true, true>, gd, bd, 0, s, ev, a);
+    else if (partition) launch_timed(k_uni_swar_sweep<true, false>, gd, bd, 0, s, ev, a);
+    else if (narrow) launch_timed(k_uni_swar_sweep<false, true>, gd, bd, 0, s, ev, a);
+    else launch_timed(k_uni_swar_sweep<false, false>, gd, bd, 0, s, ev, a);
     return hipGetLastError();
 }
 

@@ -716,6 +716,10 @@ BITSLICED_CASES = [
         1500, 4, seed=11, weights="uniform", w_lo=-30_000, w_hi=30_000), 40, 1, False),
     ("cm_d4_p64_int8_ends", lambda: workloads.configuration_model(
         1200, 4, seed=12, weights="uniform", w_lo=-128, w_hi=127), 64, 0, False),
+    # weights up to 2^27: a block's per-solution sums can pass 2^31 (64-bit block counters)
+    ("torus12_p64_w2e27", lambda: workloads.torus(12, 1, 1 << 27, seed=13), 64, 0, False),
+    ("cm_d4_p48_signed_2e27", lambda: workloads.configuration_model(
+        1000, 4, seed=14, weights="uniform", w_lo=-(1 << 27), w_hi=1 << 27), 48, 1, False),
 ]
 
 
