@@ -121,7 +121,8 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
 // the kernels' fixed-size header reads stay inside the buffer.
 struct Records {
     std::vector<int32_t> roff, words;
-    std::vector<int2> class_rec;  // per class {first word, stride or 0}
+    std::vector<int2> class_rec;        // per class {first word, stride or 0}
+    std::vector<int32_t> class_entries;  // per class: most dependent-edge entries of a record
 };
 
 constexpr int kSmallSet = 14;         // members held in a small record's header
@@ -251,6 +252,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
     std::vector<std::pair<int32_t, int32_t>> ent;  // (x, w)
     std::vector<int32_t> ends;
     R.class_rec.assign((size_t)f.k, make_int2(0, 0));
+    R.class_entries.assign((size_t)f.k, 0);
     int32_t s = 0;
     for (int32_t c = 0; c < f.k; ++c) {
         const size_t class_first = R.words.size();
@@ -264,6 +266,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
             if (univariate) {
                 const int32_t u = f.vars[b];
                 const int32_t nd = g.row_ptr[(size_t)u + 1] - g.row_ptr[u];
+                R.class_entries[c] = std::max(R.class_entries[c], nd);
                 R.words.insert(R.words.end(), {u, nd, 0, 0});
                 for (int32_t r = g.row_ptr[u]; r < g.row_ptr[(size_t)u + 1]; ++r) {
                     R.words.push_back(g.col[r]);
@@ -300,6 +303,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
                 ends.push_back((int32_t)ent.size());
             }
             const int32_t nd = (int32_t)ent.size();
+            R.class_entries[c] = std::max(R.class_entries[c], nd);
             R.words.push_back(nm);
             R.words.push_back(nd);
             if (small) {
@@ -378,6 +382,7 @@ struct gom_state {
     int32_t *d_roff = nullptr, *d_recs = nullptr;
     int2 *d_crec = nullptr;
     std::vector<int2> class_rec;  // host copy of the per-class record placement
+    std::vector<int32_t> class_entries;  // per class: most entries of one of its records
     std::vector<int32_t> coop_ptr, coop_max;  // large sets per class (block-cooperative)
     int32_t *d_coop = nullptr;                // their class positions
     int32_t *d_sw = nullptr;                  // bit-sliced sweep table (when eligible)
@@ -973,8 +978,9 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         if (s->sched == GOM_SCHED_BITSLICED && !forced)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->swar_narrow, s->max_grid, st, ev));
         else
-            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1, s->max_grid, s->sweep_threads,
-                                       st, ev));
+            HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1,
+                                       s->class_entries[c] <= kShortRecordEntries, s->max_grid,
+                                       s->sweep_threads, st, ev));
         if (s->split[c]) {  // every large set of the class in one split sweep
             SweepArgs b = a;
             b.smap = s->d_smap + s->smap_ptr[c];
@@ -1120,6 +1126,7 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     s->d_recs = (int32_t *)(s->arena + L.recs);
     s->d_crec = (int2 *)(s->arena + L.crec);
     s->class_rec = R.class_rec;
+    s->class_entries = R.class_entries;
     s->coop_ptr = CS.ptr;
     s->coop_max = CS.max_members;
     s->d_coop = (int32_t *)(s->arena + L.coop);

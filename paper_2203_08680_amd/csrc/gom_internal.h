@@ -275,8 +275,11 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
                                hipStream_t s);
 // kind: 0 = univariate records, 1 = general records
 // threads: block size, a multiple of 64 up to 512
-hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int threads,
-                              hipStream_t s, KernelEvents ev = {});
+// short_records: every record of the class has at most kShortRecordEntries entries (the
+// one-set-per-wave sweep then fetches them 4 at a time).
+constexpr int kShortRecordEntries = 16;
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, int max_grid,
+                              int threads, hipStream_t s, KernelEvents ev = {});
 // Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
 // Block-cooperative sweep of the large sets of one class (a.n_large blocks); max_members:
 // the largest of them (dynamic LDS of 8 bytes per member).

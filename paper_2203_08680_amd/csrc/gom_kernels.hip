@@ -311,10 +311,13 @@ __device__ __forceinline__ int32_t signed_w(uint32_t same, int32_t w) { return s
 // univariate record, 16 for a small set), fetched together so a kernel can issue them before
 // it waits for anything else.  Reads past a short record stay inside the buffer's zero tail;
 // entries beyond nd are masked before use.
-struct Head {
+// A record's first words: header, then two batches of B entries.
+template <int B>
+struct HeadT {
     int4 h0, h1, h2, h3;
-    int2 en0[kBatch], en1[kBatch];
+    int2 en0[B], en1[B];
 };
+using Head = HeadT<kBatch>;
 
 // Record reader: a record's words are consecutive, read with vector loads.
 struct AosRec {
@@ -342,21 +345,21 @@ struct UniformAosRec {
     }
 };
 
-template <int KIND, class Rec>
-__device__ __forceinline__ Head load_head(const Rec &R) {
-    Head hd;
+template <int KIND, int B = kBatch, class Rec>
+__device__ __forceinline__ HeadT<B> load_head(const Rec &R) {
+    HeadT<B> hd;
     hd.h0 = R.q(0);
     if constexpr (KIND == 0) {
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) hd.en0[t] = R.e(4, t);
+        for (int t = 0; t < B; ++t) hd.en0[t] = R.e(4, t);
     } else {
         hd.h1 = R.q(1);
         hd.h2 = R.q(2);
         hd.h3 = R.q(3);
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) {
+        for (int t = 0; t < B; ++t) {
             hd.en0[t] = R.e(16, t);
-            hd.en1[t] = R.e(16, kBatch + t);
+            hd.en1[t] = R.e(16, B + t);
         }
     }
     return hd;
@@ -383,8 +386,8 @@ __device__ __forceinline__ int64_t small_edge(int e, int nd, int2 en, uint32_t o
 // (a slot past nm reads the first member again and is masked out) and the offspring words at
 // the far ends of the first two entry batches (entries past nd read vertex 0).  The commit
 // writes each changed member's new word from the word already loaded.
-template <int M, class Rec, class Words, class Commit>
-__device__ __forceinline__ PairOut small_pair_planes(const Rec &R, const Head &hd, const Words &P,
+template <int M, int B, class Rec, class Words, class Commit>
+__device__ __forceinline__ PairOut small_pair_planes(const Rec &R, const HeadT<B> &hd, const Words &P,
                                                      const PlaneBits &bits, Commit commit,
                                                      uint64_t cand, uint32_t h, bool neutral_ok) {
     PairOut out{0u, false, 0};
@@ -402,11 +405,11 @@ __device__ __forceinline__ PairOut small_pair_planes(const Rec &R, const Head &h
         pw[k] = P[u];
         ow[k] = bits.O[u];
     }
-    uint32_t ov0[kBatch], ov1[kBatch];
+    uint32_t ov0[B], ov1[B];
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
+    for (int t = 0; t < B; ++t) {
         ov0[t] = bits(far_index(t, hd.en0[t]));
-        ov1[t] = bits(far_index(kBatch + t, hd.en1[t]));
+        ov1[t] = bits(far_index(B + t, hd.en1[t]));
     }
     uint32_t om = 0;
     uint64_t D = 0;
@@ -426,19 +429,19 @@ __device__ __forceinline__ PairOut small_pair_planes(const Rec &R, const Head &h
         cm |= (k < nm ? bit_of(pw[k], d) ^ ((om >> k) & 1u) : 0u) << k;
     int64_t delta = 0;
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
+    for (int t = 0; t < B; ++t) {
         delta += small_edge(t, nd, hd.en0[t], ov0[t], om, cm);
-        delta += small_edge(kBatch + t, nd, hd.en1[t], ov1[t], om, cm);
+        delta += small_edge(B + t, nd, hd.en1[t], ov1[t], om, cm);
     }
-    for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
-        int2 en[kBatch];
-        uint32_t ov[kBatch];
+    for (int e0 = 2 * B; e0 < nd; e0 += B) {
+        int2 en[B];
+        uint32_t ov[B];
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) en[t] = R.e(16, e0 + t);
+        for (int t = 0; t < B; ++t) en[t] = R.e(16, e0 + t);
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) ov[t] = bits(far_index(e0 + t, en[t]));
+        for (int t = 0; t < B; ++t) ov[t] = bits(far_index(e0 + t, en[t]));
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) delta += small_edge(e0 + t, nd, en[t], ov[t], om, cm);
+        for (int t = 0; t < B; ++t) delta += small_edge(e0 + t, nd, en[t], ov[t], om, cm);
     }
     out.delta = delta;
     out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
@@ -448,29 +451,29 @@ __device__ __forceinline__ PairOut small_pair_planes(const Rec &R, const Head &h
     return out;
 }
 
-template <int KIND, class Rec, class Words, class Bits, class Commit>
-__device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const Words &P,
+template <int KIND, int B, class Rec, class Words, class Bits, class Commit>
+__device__ __forceinline__ PairOut gom_pair(const Rec &R, const HeadT<B> &hd, const Words &P,
                                             Bits bits, Commit commit, uint64_t cand, uint32_t h,
                                             bool neutral_ok) {
     PairOut out{0u, false, 0};
     const int4 h0 = hd.h0;
     if constexpr (KIND == 0) {
         // one variable u: the donor always differs at u, so C = {u} whenever a donor exists
-        int2 en[kBatch];
+        int2 en[B];
 #pragma unroll
-        for (int t = 0; t < kBatch; ++t) en[t] = hd.en0[t];
+        for (int t = 0; t < B; ++t) en[t] = hd.en0[t];
         const int u = h0.x, nd = h0.y;
         const uint32_t ou = bits(u);
         const uint64_t D = (P[u] ^ (0ull - (uint64_t)ou)) & cand;
         out.cnt = (uint32_t)__popcll(D);
         int64_t delta = 0;
-        for (int e0 = 0; e0 < nd; e0 += kBatch) {
+        for (int e0 = 0; e0 < nd; e0 += B) {
             if (e0 > 0) {
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) en[t] = R.e(4, e0 + t);
+                for (int t = 0; t < B; ++t) en[t] = R.e(4, e0 + t);
             }
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
+            for (int t = 0; t < B; ++t) {
                 const bool ok = e0 + t < nd;
                 const int v = ok ? en[t].x : u;
                 delta += ok ? signed_w(ou == bits(v), en[t].y) : 0;
@@ -521,21 +524,21 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const Head &hd, const 
                 if (k < nm) cm |= (bit_of(P[mem[k]], d) ^ ((om >> k) & 1u)) << k;
             int64_t delta = 0;
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
+            for (int t = 0; t < B; ++t) {
                 delta += small_edge(t, nd, hd.en0[t], far_end(t, hd.en0[t]), om, cm);
-                delta += small_edge(kBatch + t, nd, hd.en1[t], far_end(kBatch + t, hd.en1[t]),
+                delta += small_edge(B + t, nd, hd.en1[t], far_end(B + t, hd.en1[t]),
                                     om, cm);
             }
             // further entries a batch at a time: the batch's loads, then its far-end bits
-            for (int e0 = 2 * kBatch; e0 < nd; e0 += kBatch) {
-                int2 en[kBatch];
-                uint32_t ov[kBatch];
+            for (int e0 = 2 * B; e0 < nd; e0 += B) {
+                int2 en[B];
+                uint32_t ov[B];
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) en[t] = R.e(16, e0 + t);
+                for (int t = 0; t < B; ++t) en[t] = R.e(16, e0 + t);
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) ov[t] = far_end(e0 + t, en[t]);
+                for (int t = 0; t < B; ++t) ov[t] = far_end(e0 + t, en[t]);
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t)
+                for (int t = 0; t < B; ++t)
                     delta += small_edge(e0 + t, nd, en[t], ov[t], om, cm);
             }
             out.delta = delta;
@@ -631,7 +634,9 @@ struct PlaneCommit {
     }
 };
 
-template <int G, int KIND, bool FI>
+// B: record entries fetched per batch (4 for classes whose records have at most 16 entries:
+// fewer scalar registers live, fewer spills; else 8).
+template <int G, int KIND, bool FI, int B>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     constexpr int GPW = 64 / G;          // sets per wave
     const int lane = threadIdx.x & 63;
@@ -656,7 +661,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     // stripe reductions below overlap with them
     int p = position(gw);
     Rec R = record(p < a.csize ? p : 0);
-    Head hd = load_head<KIND>(R);
+    HeadT<B> hd = load_head<KIND, B>(R);
     // (no branch before the loop: it would split the block and delay the record loads)
     const uint64_t mism = a.stripes[lane].mism;
     const int64_t elite_fitness = a.st->elite_fitness;
@@ -715,7 +720,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
         if (wt < nwt) {
             p = position(wt);
             R = record(p < a.csize ? p : 0);
-            hd = load_head<KIND>(R);
+            hd = load_head<KIND, B>(R);
         }
     }
 
@@ -1797,8 +1802,8 @@ static void launch_timed(K kernel, dim3 gd, dim3 bd, size_t lds, hipStream_t s, 
         hipLaunchKernelGGL(kernel, gd, bd, lds, s, args...);
 }
 
-hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int threads,
-                              hipStream_t s, KernelEvents ev) {
+hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, int max_grid,
+                              int threads, hipStream_t s, KernelEvents ev) {
     if (threads < 64 || threads > kSweepMaxThreads || threads % 64) return hipErrorInvalidValue;
     const int G = a.N <= 16 ? 16 : (a.N <= 32 ? 32 : 64);
     const int per_tile = (threads / 64) * (64 / G);  // sets per block
@@ -1808,14 +1813,18 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, int max_grid, int th
     const dim3 gd(grid), bd(threads);
     auto go = [&](auto fi) {
         constexpr bool FI = decltype(fi)::value;
+        // several sets per wave (G < 64) read records with vector loads: no scalar registers
+        // to save, so they keep the batch of 8
         if (kind == 0) {
-            if (G == 16) launch_timed(k_class_sweep<16, 0, FI>, gd, bd, 0, s, ev, a);
-            else if (G == 32) launch_timed(k_class_sweep<32, 0, FI>, gd, bd, 0, s, ev, a);
-            else launch_timed(k_class_sweep<64, 0, FI>, gd, bd, 0, s, ev, a);
+            if (G == 16) launch_timed(k_class_sweep<16, 0, FI, 8>, gd, bd, 0, s, ev, a);
+            else if (G == 32) launch_timed(k_class_sweep<32, 0, FI, 8>, gd, bd, 0, s, ev, a);
+            else if (short_records) launch_timed(k_class_sweep<64, 0, FI, 4>, gd, bd, 0, s, ev, a);
+            else launch_timed(k_class_sweep<64, 0, FI, 8>, gd, bd, 0, s, ev, a);
         } else {
-            if (G == 16) launch_timed(k_class_sweep<16, 1, FI>, gd, bd, 0, s, ev, a);
-            else if (G == 32) launch_timed(k_class_sweep<32, 1, FI>, gd, bd, 0, s, ev, a);
-            else launch_timed(k_class_sweep<64, 1, FI>, gd, bd, 0, s, ev, a);
+            if (G == 16) launch_timed(k_class_sweep<16, 1, FI, 8>, gd, bd, 0, s, ev, a);
+            else if (G == 32) launch_timed(k_class_sweep<32, 1, FI, 8>, gd, bd, 0, s, ev, a);
+            else if (short_records) launch_timed(k_class_sweep<64, 1, FI, 4>, gd, bd, 0, s, ev, a);
+            else launch_timed(k_class_sweep<64, 1, FI, 8>, gd, bd, 0, s, ev, a);
         }
     };
     if (a.mode == kSweepFi) go(std::true_type{});

@@ -518,6 +518,10 @@ def test_local_search_errors(cuda):
 ILS_CASES = LS_CASES + [
     ("torus100_p64_bitsliced", lambda: workloads.torus(100, 1, 100, seed=2), 64,
      gom.GOM_SCHED_BITSLICED),
+    # 16 variables against up to 64 flips: variables drawn again and again flip back
+    ("torus4_p2_class", lambda: workloads.torus(4, 1, 9, seed=3), 2, gom.GOM_SCHED_CLASS_LAUNCH),
+    ("torus4_p64_resident", lambda: workloads.torus(4, 1, 9, seed=3), 64,
+     gom.GOM_SCHED_RESIDENT),
 ]
 # (round0, rounds, flips, max_passes) after each of a run's generations
 ILS_STEPS = [(0, 1, 1, 0), (1, 3, 4, 10_000), (4, 2, 64, 2), (0, 2, 0, 10_000), (6, 1, 13, 1)]
