@@ -487,8 +487,11 @@ __device__ __forceinline__ PairOut gom_pair(const Rec &R, const HeadT<B> &hd, co
         const int nm = h0.x, nd = h0.y;
         if (nm <= kSmallSet) {
             if constexpr (!Bits::kLocal) {
-                // class launch: sets of up to 5 members (neighbourhoods of degree <= 4, the
-                // torus's) load 5 member slots, up to 8 members 8, larger ones all 14
+                // class launch: sets of up to 4 and 5 members (neighbourhoods of degree 3 and
+                // 4, the torus's) load 4 and 5 member slots, up to 8 members 8, larger ones all
+                // 14
+                if (nm <= 4)
+                    return small_pair_planes<4>(R, hd, P, bits, commit, cand, h, neutral_ok);
                 if (nm <= 5)
                     return small_pair_planes<5>(R, hd, P, bits, commit, cand, h, neutral_ok);
                 if (nm <= 8)
