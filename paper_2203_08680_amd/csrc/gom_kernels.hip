@@ -24,6 +24,8 @@
 // order in which waves run.
 #include <hip/hip_ext.h>
 
+#include <atomic>
+#include <mutex>
 #include <type_traits>
 
 #include "gom_internal.h"
@@ -1807,6 +1809,28 @@ static void launch_timed(K kernel, dim3 gd, dim3 bd, size_t lds, hipStream_t s, 
         hipLaunchKernelGGL(kernel, gd, bd, lds, s, args...);
 }
 
+// Raise kernel K's dynamic LDS limit on the current device to at least `bytes`.  The limit is
+// a per-device function attribute, so the largest size already set is kept per device; the
+// check is lock-free and the update runs under a mutex, so host threads may launch at once.
+constexpr int kMaxDevices = 64;
+
+template <auto K>
+static hipError_t raise_lds_limit(size_t bytes) {
+    static std::atomic<size_t> done[kMaxDevices];
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (bytes <= done[dev].load(std::memory_order_acquire)) return hipSuccess;
+    std::lock_guard<std::mutex> lock(mu);
+    if (bytes <= done[dev].load(std::memory_order_relaxed)) return hipSuccess;
+    e = hipFuncSetAttribute((const void *)K, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes);
+    if (e == hipSuccess) done[dev].store(bytes, std::memory_order_release);
+    return e;
+}
+
 hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, int max_grid,
                               int threads, hipStream_t s, KernelEvents ev) {
     if (threads < 64 || threads > kSweepMaxThreads || threads % 64) return hipErrorInvalidValue;
@@ -1873,13 +1897,8 @@ hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threa
         threads < 64 || threads > kCoopMaxThreads || threads % 64)
         return hipErrorInvalidValue;
     const size_t lds = 2 * sizeof(uint64_t) * (size_t)a.coop_cap;
-    static size_t attr_bytes = 0;
-    if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_large_set_sweep,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = raise_lds_limit<k_large_set_sweep>(lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_large_set_sweep, dim3(a.n_large), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
@@ -1905,14 +1924,8 @@ size_t resident_lds_bytes(int n, bool plds) {
 template <int KIND, bool PLDS>
 static hipError_t launch_resident_t(const ResidentArgs &a, hipStream_t s, KernelEvents ev) {
     const size_t lds = resident_lds_bytes(a.c.n, PLDS);
-    // Raise the dynamic LDS limit of the kernel to what this launch needs (once per size).
-    static size_t attr_bytes = 0;
-    if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_resident_sweep<KIND, PLDS>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = raise_lds_limit<k_resident_sweep<KIND, PLDS>>(lds);
+    if (e != hipSuccess) return e;
     launch_timed(k_resident_sweep<KIND, PLDS>, dim3(a.c.N), dim3(kResidentThreads), lds, s, ev,
                  a);
     return hipGetLastError();
@@ -1925,16 +1938,7 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
     return plds ? launch_resident_t<1, true>(a, s, ev) : launch_resident_t<1, false>(a, s, ev);
 }
 
-hipError_t prepare_batch_step(size_t lds) {
-    static size_t attr_bytes = 0;
-    if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_batch_sweep,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
-    return hipSuccess;
-}
+hipError_t prepare_batch_step(size_t lds) { return raise_lds_limit<k_batch_sweep>(lds); }
 
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
                              const int32_t *vblk, int vblocks, size_t lds, hipStream_t s) {
