@@ -46,13 +46,13 @@ WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_50
 # in profiles/.
 MEASURED_TRAFFIC = {
     ("k_class_sweep", "torus100_nbhd_p64"): {
-        "bytes": 1030201, "source": "65b76b4d41dc8adc",
+        "bytes": 1030201, "source": "1fea3fa46b78b064",
         "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
     ("k_resident_sweep", "torus100_nbhd_p64"): {
-        "bytes": 16374121, "source": "65b76b4d41dc8adc",
+        "bytes": 16374068, "source": "1fea3fa46b78b064",
         "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
     ("k_uni_swar_sweep", "torus1000_uni_p64"): {
-        "bytes": 24140723, "source": "65b76b4d41dc8adc",
+        "bytes": 24140655, "source": "1fea3fa46b78b064",
         "profile": "profiles/k_uni_swar_sweep_torus1000_uni_p64.md"},
 }
 
