@@ -13,6 +13,8 @@
  *  - On failure, outputs are left untouched and handles are unchanged.
  *  - Host arrays passed in are borrowed for the duration of the call (copied when kept).
  *  - Handles are owned by the caller and released with the matching *_free call.
+ *  - Calls on different handles may run on different host threads at the same time; calls
+ *    on one handle (and on the states of one batch or server) must not overlap.
  *  - Device memory is owned by the caller: a state lives inside a caller-provided device
  *    arena of gom_state_bytes() bytes (for example a torch uint8 tensor).  The library never
  *    allocates device memory.  `stream` is a hipStream_t passed as void* (NULL = the default
