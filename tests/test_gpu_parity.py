@@ -904,3 +904,50 @@ def test_server_jobs_equal_solo_runs(cuda):
                                                        r.attempted, r.evaluated, r.accepted), jid
         assert got["hash"] == gom.gom_state_hash(st), jid
         assert got["submit_ms"] <= got["admit_ms"] <= got["done_ms"]
+
+
+def _two_vertices():
+    return workloads.from_edges(2, [(0, 1)], [7], name="two_vertices")
+
+
+def _isolated_vertices():
+    """A 3-regular graph on 20 vertices spread over 60 (vertex 3k); the other 40 have no
+    edges, so their univariate steps always have delta 0."""
+    h = workloads.configuration_model(20, 3, seed=21)
+    return workloads.from_edges(60, np.stack([3 * h.u, 3 * h.v], axis=1), h.w,
+                                name="isolated_vertices")
+
+
+def _star40():
+    """Hub 0 joined to 40 leaves with signed weights: its neighbourhood set has 41 members
+    and meets every other set."""
+    w = [k - 21 if k <= 20 else k - 20 for k in range(1, 41)]
+    return workloads.from_edges(41, [(0, k) for k in range(1, 41)], w, name="star40")
+
+
+DEGENERATE_CASES = [
+    ("two_vertices_uni_p2", _two_vertices, 0, 2),
+    ("two_vertices_nbhd_p64", _two_vertices, 1, 64),
+    ("isolated_uni_p33", _isolated_vertices, 0, 33),
+    ("isolated_nbhd_p64", _isolated_vertices, 1, 64),
+    ("star40_uni_p17", _star40, 0, 17),
+    ("star40_nbhd_p64", _star40, 1, 64),
+]
+
+
+@pytest.mark.parametrize("label,maker,kind,pop", DEGENERATE_CASES,
+                         ids=[c[0] for c in DEGENERATE_CASES])
+def test_degenerate_graphs(cuda, label, maker, kind, pop):
+    """The smallest graph (one edge), vertices without edges, and a star whose hub set meets
+    every other set (one set per class under the neighbourhood FOS), under every schedule
+    that accepts the instance."""
+    g = maker()
+    scheds = [gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT]
+    if kind == 0 and int(np.max(np.bincount(np.concatenate([g.u, g.v]), minlength=g.n))) <= 4:
+        scheds.append(gom.GOM_SCHED_BITSLICED)
+    for sched in scheds:
+        print(f"case degenerate {label} sched={sched}", flush=True)
+        for seed in (1, 2):
+            _, st, ref = make_pair(g, kind, pop, seed=seed, sched=sched)
+            assert gom.gom_state_get_schedule(st) == sched
+            lockstep(st, ref, 10, f"degenerate {label} sched {sched} seed {seed}")
