@@ -65,10 +65,10 @@ int gom_version(void);
  *   n_vertices  number of vertices (>= 1)
  *   n_edges     number of edges m (>= 1, 2m < 2^31)
  *   u, v        host int32[m] endpoints, each in [0, n_vertices)
- *   w           host int32[m] weights (any sign); NULL = all weights 1
+ *   w           host int32[m] weights (any sign, |w| <= 2^31 - 1); NULL = all weights 1
  *   out         receives the new handle
- * Errors: GOM_E_ARG (null), GOM_E_RANGE (n < 1, m < 1, 2m >= 2^31), GOM_E_GRAPH (endpoint out
- * of range, u == v, the same unordered pair twice).
+ * Errors: GOM_E_ARG (null), GOM_E_RANGE (n < 1, m < 1, 2m >= 2^31, a weight of -2^31),
+ * GOM_E_GRAPH (endpoint out of range, u == v, the same unordered pair twice).
  * The graph is stored as CSR with each row sorted by neighbour id; total weight in int64.
  */
 int mc_graph_load(int32_t n_vertices, int64_t n_edges, const int32_t *u, const int32_t *v,

@@ -429,6 +429,10 @@ extern "C" int mc_graph_load(int32_t n, int64_t m, const int32_t *u, const int32
                         (long long)e);
         if (u[e] == v[e])
             return fail(GOM_E_GRAPH, "mc_graph_load: edge %lld is a self-loop", (long long)e);
+        // a step negates the weight of an edge it uncuts, so -w must be an int32 too
+        if (w && w[e] == INT32_MIN)
+            return fail(GOM_E_RANGE, "mc_graph_load: edge %lld has weight -2^31 (|w| must be "
+                        "below 2^31)", (long long)e);
     }
     auto *g = new mc_graph;
     g->n = n;

@@ -925,7 +925,26 @@ def _star40():
     return workloads.from_edges(41, [(0, k) for k in range(1, 41)], w, name="star40")
 
 
+def _extreme_weights():
+    """Weights at the ends of the int32 range (+-(2^31 - 1)) on a 4-regular graph: single
+    deltas reach 4 (2^31 - 1) and fitness sums pass 2^40."""
+    return workloads.configuration_model(600, 4, seed=23, weights="uniform",
+                                         w_lo=-(1 << 31) + 1, w_hi=(1 << 31) - 1)
+
+
+def _extreme_weights_ends():
+    """Every weight is +(2^31 - 1) or -(2^31 - 1)."""
+    g = workloads.configuration_model(400, 3, seed=24)
+    return workloads.from_edges(400, np.stack([g.u, g.v], axis=1),
+                                np.where(g.w > 0, (1 << 31) - 1, -(1 << 31) + 1),
+                                name="extreme_weight_ends")
+
+
 DEGENERATE_CASES = [
+    ("extreme_weights_uni_p64", _extreme_weights, 0, 64),
+    ("extreme_weights_nbhd_p40", _extreme_weights, 1, 40),
+    ("extreme_weight_ends_uni_p64", _extreme_weights_ends, 0, 64),
+    ("extreme_weight_ends_nbhd_p64", _extreme_weights_ends, 1, 64),
     ("two_vertices_uni_p2", _two_vertices, 0, 2),
     ("two_vertices_nbhd_p64", _two_vertices, 1, 64),
     ("isolated_uni_p33", _isolated_vertices, 0, 33),
@@ -943,7 +962,10 @@ def test_degenerate_graphs(cuda, label, maker, kind, pop):
     that accepts the instance."""
     g = maker()
     scheds = [gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT]
-    if kind == 0 and int(np.max(np.bincount(np.concatenate([g.u, g.v]), minlength=g.n))) <= 4:
+    ends = np.concatenate([g.u, g.v])
+    abs_sum = np.bincount(ends, weights=np.abs(np.concatenate([g.w, g.w])).astype(np.float64),
+                          minlength=g.n)
+    if kind == 0 and np.bincount(ends, minlength=g.n).max() <= 4 and abs_sum.max() < 2.0**30:
         scheds.append(gom.GOM_SCHED_BITSLICED)
     for sched in scheds:
         print(f"case degenerate {label} sched={sched}", flush=True)

@@ -49,6 +49,13 @@ def test_graph_validation(gomlib):
         gom.mc_graph_load(0, [0], [1], [1])
     assert e.value.code == gom.GOM_E_RANGE
     assert "n_vertices" in gomlib.gom_last_error().decode()
+    # -2^31 has no int32 negation; the rest of the int32 range loads
+    with pytest.raises(gom.GomError) as e:
+        gom.mc_graph_load(3, [0, 1], [1, 2], [5, -(1 << 31)])
+    assert e.value.code == gom.GOM_E_RANGE
+    assert "weight" in gomlib.gom_last_error().decode()
+    g = gom.mc_graph_load(3, [0, 1], [1, 2], [(1 << 31) - 1, -(1 << 31) + 1])
+    assert g.info()["total_weight"] == 0
 
 
 def test_graph_csr_and_info(gomlib):
