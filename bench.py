@@ -112,7 +112,9 @@ def run_batch_mode(args, torch, gom):
     """Batched vs plain on a mix of independent instances (the batched configuration): all
     instances in one lockstep batch, against the same instances run one after another, each
     alone, with the default schedule.  Every instance reaches the same state either way."""
-    items = workloads.batch_mix(count=args.batch_count, seed=4)
+    n_lo, n_hi = args.batch_n_range
+    n_label = "1e3_1e5" if (n_lo, n_hi) == (1e3, 1e5) else f"{n_lo:g}_{n_hi:g}"
+    items = workloads.batch_mix(count=args.batch_count, seed=4, n_lo=n_lo, n_hi=n_hi)
     max_gens = args.max_gens or 200
     t0 = time.perf_counter()
     insts = [gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
@@ -153,11 +155,14 @@ def run_batch_mode(args, torch, gom):
     tori = [b for b, it in enumerate(items) if it.to_total_weight and res[b].reached]
     tto_b = np.array([tt[b] for b in tori])
     tto_p = np.array([plain_t[b] * 1e3 for b in tori])
+    # in the plain loop an instance reaches its optimum only after every earlier instance's run
+    loop_t = np.cumsum(plain_t) * 1e3
+    tto_loop = np.array([loop_t[b] for b in tori])
     line = {
         "metric": METRIC, "value": ev_batch / t_batch, "unit": "evals/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": f"batch{len(items)}_tori_and_regular_1e3_1e5",
+        "config": {"workload": f"batch{len(items)}_tori_and_regular_{n_label}",
                    "instances": len(items), "vertices": int(sum(x.n for x in insts)),
                    "pop_range": [16, 64], "max_generations": max_gens, "mode": "batched",
                    "schedule": "batched_resident",
@@ -172,7 +177,9 @@ def run_batch_mode(args, torch, gom):
             "batched_p50": float(np.percentile(tto_b, 50)) if len(tori) else None,
             "batched_p99": float(np.percentile(tto_b, 99)) if len(tori) else None,
             "plain_alone_p50": float(np.percentile(tto_p, 50)) if len(tori) else None,
-            "plain_alone_p99": float(np.percentile(tto_p, 99)) if len(tori) else None},
+            "plain_alone_p99": float(np.percentile(tto_p, 99)) if len(tori) else None,
+            "plain_loop_p50": float(np.percentile(tto_loop, 50)) if len(tori) else None,
+            "plain_loop_p99": float(np.percentile(tto_loop, 99)) if len(tori) else None},
     }
     print(json.dumps(line), flush=True)
 
@@ -345,6 +352,9 @@ def main():
                     help="batched vs plain on the 256-instance mix instead of the default "
                          "single-instance workload")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-n-range", type=float, nargs=2, metavar=("LO", "HI"),
+                    default=(1e3, 1e5),
+                    help="vertex-count range of the batched mix (log-uniform; default 1e3 1e5)")
     ap.add_argument("--local-search", action="store_true",
                     help="plain mode, univariate FOS: the colouring-parallel local search after "
                          "every generation (the hybrid); reports time to optimum")
