@@ -241,16 +241,27 @@ typedef struct {
 } gom_result;
 
 /*
- * Run generations until the elitist fitness is >= target or the state has run
- * max_generations generations in total (the target is also tested before the first one).
+ * The generation loop of Algorithm 3 with a stopping rule: run generations until the elitist
+ * fitness is >= target or the state has run max_generations generations in total (the target
+ * is also tested before the first one).  Section 6.4 measures the time until the known
+ * optimum is reached, and Section 6.5 runs under a limit; target and max_generations are
+ * those two conditions (the paper uses wall-clock limits; a generation count is used here so
+ * that runs are reproducible).
  * Synchronous: returns when the device work has finished.  Generations are enqueued ahead in
  * small chunks; a generation enqueued after the target was reached does nothing on the device.
+ * out (may be NULL) receives the generations run and the cumulative counters.
+ * A max_generations at or below the generations already run runs none.
+ * Errors: GOM_E_ARG (null state), GOM_E_STATE (a generation left open by
+ * gom_debug_stop_after_class), GOM_E_DEVICE.
  */
 int gom_run_to_target(gom_state *s, int64_t target, int32_t max_generations, void *stream,
                       gom_result *out);
 
 /*
- * Copy the state to the host (synchronous):
+ * Copy the state to the host (synchronous): the population P of Algorithm 3 (between
+ * generations; the offspring O while gom_debug_stop_after_class holds a generation open), the
+ * fitness of every solution (Section 6.2 objective), the elitist of Section 4 (the best
+ * solution found so far) with its fitness, the generation counter and the step counters:
  *   genes         uint8[N * n] solution-major (genes[i*n + v]) or NULL
  *   fitness       int64[N] or NULL
  *   elite         uint8[n] or NULL; elite_fitness, generation: or NULL
@@ -258,6 +269,8 @@ int gom_run_to_target(gom_state *s, int64_t target, int32_t max_generations, voi
  */
 int gom_state_read(gom_state *s, void *stream, uint8_t *genes, int64_t *fitness, uint8_t *elite,
                    int64_t *elite_fitness, int32_t *generation, int64_t *counters);
+/* Errors: GOM_E_ARG (null state), GOM_E_DEVICE (a copy failed; outputs may then be partly
+ * written). */
 
 /*
  * 64-bit summary of the whole state, for comparing runs generation by generation without
@@ -466,6 +479,8 @@ typedef struct {
     uint64_t hash;        /* gom_state_hash of the final state */
     double submit_ms, admit_ms, done_ms;  /* host clock, ms since gom_server_create; done_ms
                                              is when a step found the job finished */
+    int32_t status;       /* GOM_OK, or the error that kept the job from starting (its state
+                             could not be created); the other fields are then 0 */
 } gom_job_result;
 
 /*
@@ -485,7 +500,10 @@ int gom_server_submit(gom_server *s, const mc_graph *g, const gom_fos *f, int32_
                       int neutral_rule, int class_order, int64_t *job);
 
 /* One pass: admit what fits, retire or continue every job whose chunk has finished.  Returns
- * without waiting for running chunks (call it in a loop).  Outputs may be NULL. */
+ * without waiting for running chunks (call it in a loop).  Outputs may be NULL.  A job whose
+ * state cannot be created at admission leaves the queue with a result whose status is the
+ * error.  On a device error the pass stops and returns GOM_E_DEVICE; jobs it had already
+ * retired keep their results and the others stay admitted. */
 int gom_server_step(gom_server *s, int32_t *n_active, int32_t *n_queued);
 
 /* Move up to `capacity` finished jobs' results into out (in retirement order); *n receives

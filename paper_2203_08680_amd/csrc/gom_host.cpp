@@ -3,6 +3,7 @@
 // driver behind the C ABI declared in include/gom.h.
 #include "../../include/gom.h"
 #include "gom_internal.h"
+#include "gom_arena.h"
 
 #include <algorithm>
 #include <chrono>
@@ -413,7 +414,7 @@ struct gom_state {
 // Graph
 // ------------------------------------------------------------------------------------------
 extern "C" const char *gom_last_error(void) { return g_err.c_str(); }
-extern "C" int gom_version(void) { return 1; }
+extern "C" int gom_version(void) { return 2; }
 
 extern "C" int mc_graph_load(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
                              const int32_t *w, mc_graph **out) {
@@ -2053,6 +2054,7 @@ struct ServerJob {
     gom_state *s = nullptr;
     int lane = 0;
     bool in_flight = false;   // a chunk and its snapshot are enqueued
+    bool retired = false;     // finished: result recorded, state and memory released
     double submit_ms = 0.0, admit_ms = 0.0;
 };
 
@@ -2064,7 +2066,7 @@ struct gom_server {
     int32_t max_jobs = 0, chunk = 4;
     std::vector<hipStream_t> lanes;       // owned streams (default priority)
     std::vector<int32_t> lane_jobs;
-    std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
+    ArenaBlocks blocks;                   // first-fit, coalescing
     std::deque<ServerJob> queue;
     std::vector<ServerJob> active;
     std::vector<gom_job_result> done;
@@ -2075,40 +2077,13 @@ struct gom_server {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
             .count();
     }
-    bool alloc(size_t need, size_t *off) {
-        need = align_up(need);
-        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
-            if (it->second < need) continue;
-            *off = it->first;
-            const size_t rest = it->second - need, at = it->first + need;
-            free_blocks.erase(it);
-            if (rest) free_blocks[at] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t size) {
-        size = align_up(size);
-        auto it = free_blocks.emplace(off, size).first;
-        auto next = std::next(it);
-        if (next != free_blocks.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_blocks.erase(next);
-        }
-        if (it != free_blocks.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_blocks.erase(it);
-            }
-        }
-    }
 };
 
 extern "C" void gom_server_free(gom_server *sv) {
     if (!sv) return;
     for (hipStream_t q : sv->lanes) (void)hipStreamSynchronize(q);
-    for (ServerJob &J : sv->active) gom_state_free(J.s);
+    for (ServerJob &J : sv->active)
+        if (!J.retired) gom_state_free(J.s);
     for (hipStream_t q : sv->lanes) (void)hipStreamDestroy(q);
     delete sv;
 }
@@ -2125,7 +2100,7 @@ extern "C" int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t ma
     sv->arena = (char *)dev_arena;
     sv->bytes = arena_bytes & ~(size_t)255;
     sv->max_jobs = max_jobs;
-    sv->free_blocks[0] = sv->bytes;
+    sv->blocks.reset(sv->bytes);
     sv->t0 = std::chrono::steady_clock::now();
     for (int32_t q = 0; q < streams; ++q) {
         hipStream_t h = nullptr;
@@ -2202,7 +2177,7 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
     while (!sv->queue.empty() && (int32_t)sv->active.size() < sv->max_jobs) {
         ServerJob &J = sv->queue.front();
         size_t off = 0;
-        if (!sv->alloc(J.bytes, &off)) break;
+        if (!sv->blocks.alloc(J.bytes, &off)) break;
         int lane = 0;
         for (int q = 1; q < (int)sv->lanes.size(); ++q)
             if (sv->lane_jobs[(size_t)q] < sv->lane_jobs[(size_t)lane]) lane = q;
@@ -2210,8 +2185,17 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
         int rc = gom_state_init(J.g, J.f, J.pop, J.seed, J.rule, J.order, sv->arena + off,
                                 align_up(J.bytes), sv->lanes[(size_t)lane], &s);
         if (rc) {
-            sv->release(off, J.bytes);
-            return rc;
+            // the job cannot start: it leaves the queue with a failed result, so that the
+            // jobs behind it are still admitted
+            sv->blocks.release(off, J.bytes);
+            gom_job_result r{};
+            r.job = J.id;
+            r.status = rc;
+            r.submit_ms = J.submit_ms;
+            r.admit_ms = r.done_ms = sv->now_ms();
+            sv->done.push_back(r);
+            sv->queue.pop_front();
+            continue;
         }
         J.s = s;
         J.off = off;
@@ -2223,26 +2207,23 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
         rc = server_issue(sv, sv->active.back());
         if (rc) return rc;
     }
-    // progress: every job whose chunk has finished is retired or given its next chunk
-    std::vector<ServerJob> keep;
-    keep.reserve(sv->active.size());
+    // progress: every job whose chunk has finished is retired or given its next chunk; a
+    // retired job is marked at once and leaves the active list however this pass ends
+    RetiredSweep<ServerJob> sweep{sv->active};
     for (ServerJob &J : sv->active) {
         gom_state *s = J.s;
         const hipError_t qe = hipEventQuery(s->chunk_ev[0]);
-        if (qe == hipErrorNotReady) {
-            keep.push_back(J);
-            continue;
-        }
+        if (qe == hipErrorNotReady) continue;
         HIP_TRY(qe);
         const DevState h = s->h_st[0];
         if (h.elite_fitness < J.target && h.generation < J.max_gens) {
             int rc = server_issue(sv, J);
             if (rc) return rc;
-            keep.push_back(J);
             continue;
         }
         gom_job_result r{};
         r.job = J.id;
+        r.status = GOM_OK;
         r.generations = h.generation;
         r.reached = h.elite_fitness >= J.target ? 1 : 0;
         r.best = h.elite_fitness;
@@ -2256,11 +2237,13 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
         if (rc) return rc;
         sv->done.push_back(r);
         gom_state_free(s);
-        sv->release(J.off, J.bytes);
+        J.s = nullptr;
+        J.retired = true;
+        sv->blocks.release(J.off, J.bytes);
         sv->lane_jobs[(size_t)J.lane]--;
     }
-    sv->active.swap(keep);
-    if (n_active) *n_active = (int32_t)sv->active.size();
+    if (n_active) *n_active = (int32_t)sv->active.size() - (int32_t)std::count_if(
+        sv->active.begin(), sv->active.end(), [](const ServerJob &J) { return J.retired; });
     if (n_queued) *n_queued = (int32_t)sv->queue.size();
     return GOM_OK;
     GUARD_END
@@ -2282,11 +2265,7 @@ extern "C" int gom_server_info(const gom_server *sv, int32_t *n_active, int32_t 
     if (n_active) *n_active = (int32_t)sv->active.size();
     if (n_queued) *n_queued = (int32_t)sv->queue.size();
     if (n_streams) *n_streams = (int32_t)sv->lanes.size();
-    if (free_bytes) {
-        size_t t = 0;
-        for (const auto &kv : sv->free_blocks) t += kv.second;
-        *free_bytes = t;
-    }
+    if (free_bytes) *free_bytes = sv->blocks.free_bytes();
     return GOM_OK;
 }
 

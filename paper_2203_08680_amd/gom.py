@@ -64,7 +64,7 @@ class gom_job_result(C.Structure):
     _fields_ = [("job", C.c_int64), ("generations", C.c_int32), ("reached", C.c_int32),
                 ("best", C.c_int64), ("attempted", C.c_int64), ("evaluated", C.c_int64),
                 ("accepted", C.c_int64), ("hash", C.c_uint64), ("submit_ms", C.c_double),
-                ("admit_ms", C.c_double), ("done_ms", C.c_double)]
+                ("admit_ms", C.c_double), ("done_ms", C.c_double), ("status", C.c_int32)]
 
 
 _lib = None
@@ -636,7 +636,7 @@ class GomServer:
             out.append({"job": r.job, "generations": r.generations, "reached": bool(r.reached),
                         "best": r.best, "attempted": r.attempted, "evaluated": r.evaluated,
                         "accepted": r.accepted, "hash": r.hash, "submit_ms": r.submit_ms,
-                        "admit_ms": r.admit_ms, "done_ms": r.done_ms})
+                        "admit_ms": r.admit_ms, "done_ms": r.done_ms, "status": r.status})
             self._jobs.pop(r.job, None)
         return out
 

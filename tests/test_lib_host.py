@@ -29,7 +29,7 @@ def test_library_exports_every_declared_entry_point(gomlib):
     for name in names:
         assert hasattr(gomlib, name), name
     assert set(names) == set(gom.EXPORTED)
-    assert gom.gom_version() == 1
+    assert gom.gom_version() == 2
 
 
 def test_graph_validation(gomlib):

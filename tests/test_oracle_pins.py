@@ -2,8 +2,8 @@
 
 Each test ties one oracle function to something outside itself: a library routine (numpy's
 Philox), the paper's own formula or worked example (Figures 1-3), closed forms and brute
-force, hand-worked generations, an independent literal reading of Algorithms 3/4, or an
-invariant the method guarantees.
+force, hand-worked generations, an independent whole-class reference that evaluates every
+trial in full (tests/class_at_once.py), or an invariant the method guarantees.
 """
 import itertools
 import os
@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workloads
-from literal_alg34 import LiteralParGomea, initial_population
+from class_at_once import ClassAtOnceGomea, initial_population
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -34,6 +34,22 @@ def test_philox4x64_matches_numpy(key, ctr):
         c[1] = (c[1] + 1) % 2**64
     got = oracle.philox4x64(key, c)
     assert [int(x) for x in got] == [int(x) for x in want]
+
+
+@pytest.mark.parametrize("key,ctr,want", [
+    ((0x00000000, 0x00000000), (0x00000000, 0x00000000, 0x00000000, 0x00000000),
+     (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff, 0xffffffff), (0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff),
+     (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0xa4093822, 0x299f31d0), (0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+])
+def test_philox4x32_known_answers(key, ctr, want):
+    """Philox4x32-10 against the published known-answer vectors of the Random123 distribution
+    (Salmon, Moraes, Dror & Shaw, SC'11): all-zero key and counter, all-ones, and the
+    pi-digit vector.  These fix the 4x32 multipliers and Weyl constants, which the 4x64
+    comparison with numpy does not reach."""
+    assert tuple(int(x) for x in oracle.philox4x32(key, ctr)) == want
 
 
 def test_philox4x32_bits_balanced_and_counter_sensitive():
@@ -257,31 +273,33 @@ def test_hand_worked_generation(case):
 @pytest.mark.parametrize("n,d,kind,pop,rule,order", [
     (12, 3, 1, 5, 0, 0), (16, 4, 0, 4, 0, 0), (14, 3, 1, 7, 1, 0), (20, 2, 1, 3, 0, 1),
     (18, 5, 1, 9, 0, 0)])
-def test_oracle_equals_literal_algorithm_3_4(n, d, kind, pop, rule, order):
-    """The step-at-a-time oracle against the literal whole-group reading of Algorithms 3/4
-    (O' insertion, keyed dependent-subfunction sums, M_IMP, reset/insert), every generation."""
+def test_oracle_equals_class_at_once_reference(n, d, kind, pop, rule, order):
+    """The step-at-a-time oracle (partial deltas, one step after another inside a class)
+    against the whole-class reference (every pair of a class decided on the class-start
+    offspring with the objective evaluated in full, then applied together), every
+    generation."""
     g = workloads.configuration_model(n, d, seed=n + 100 * d, weights="signed50")
     ptr, vars_ = oracle.fos(g, kind)
     run = oracle.Run(g, ptr, vars_, pop=pop, seed=n * pop, rule=rule, order=order)
     cp, ce = run.classes()
     classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(len(cp) - 1)]
-    lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=n * pop, rule=rule, order=order)
+    cao = ClassAtOnceGomea(g, ptr, vars_, classes, pop, seed=n * pop, rule=rule, order=order)
     s = run.state()
-    assert np.array_equal(s["genes"], lit.P)
+    assert np.array_equal(s["genes"], cao.P)
     for gen in range(6):
         run.generation()
-        lit.generation()
+        cao.generation()
         s = run.state()
-        assert np.array_equal(s["genes"], lit.P), gen
-        assert s["fitness"].tolist() == lit.f.tolist(), gen
-        assert np.array_equal(s["elite"], lit.E) and s["elite_fitness"] == lit.fE
-        assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted)
+        assert np.array_equal(s["genes"], cao.P), gen
+        assert s["fitness"].tolist() == cao.f.tolist(), gen
+        assert np.array_equal(s["elite"], cao.E) and s["elite_fitness"] == cao.fE
+        assert (s["evaluated"], s["accepted"]) == (cao.evaluated, cao.accepted)
 
 
 @pytest.mark.parametrize("n,d,kind,pop,order", [(12, 3, 1, 5, 0), (16, 4, 0, 4, 0),
                                                  (18, 5, 1, 9, 1)])
-def test_stop_after_class_equals_literal_groups(n, d, kind, pop, order):
-    """A generation cut after each class position shows the literal reading's offspring,
+def test_stop_after_class_equals_class_at_once(n, d, kind, pop, order):
+    """A generation cut after each class position shows the whole-class reference's offspring,
     running fitness and counters after the same group; finishing it equals an uncut
     generation."""
     g = workloads.configuration_model(n, d, seed=n + 100 * d, weights="signed50")
@@ -293,25 +311,25 @@ def test_stop_after_class_equals_literal_groups(n, d, kind, pop, order):
     classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(k)]
     for gen in range(4):
         for t in range(k):
-            lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=n * pop, order=order,
+            cao = ClassAtOnceGomea(g, ptr, vars_, classes, pop, seed=n * pop, order=order,
                                   P=run.state()["genes"])
             s0 = run.state()
-            lit.E, lit.fE, lit.gen = s0["elite"].copy(), s0["elite_fitness"], s0["generation"]
-            lit.evaluated, lit.accepted = s0["evaluated"], s0["accepted"]
-            lit.generation(stop_after=t)
+            cao.E, cao.fE, cao.gen = s0["elite"].copy(), s0["elite_fitness"], s0["generation"]
+            cao.evaluated, cao.accepted = s0["evaluated"], s0["accepted"]
+            cao.generation(stop_after=t)
             probe = oracle.Run(g, ptr, vars_, pop=pop, seed=n * pop, order=order)
             probe.set_state(s0["genes"], s0["elite"], s0["elite_fitness"], s0["generation"],
                             [s0["attempted"], s0["evaluated"], s0["accepted"]])
             probe.stop_after_class(t)
             m = probe.state()
-            O, f, ev, ac = lit.mid
+            O, f, ev, ac = cao.mid
             assert np.array_equal(m["genes"], O), (gen, t)
             assert m["fitness"].tolist() == f.tolist(), (gen, t)
             assert (m["evaluated"], m["accepted"]) == (ev, ac), (gen, t)
             assert m["generation"] == s0["generation"]
             probe.generation()
             lit2 = probe.state()
-            assert np.array_equal(lit2["genes"], lit.P) and lit2["fitness"].tolist() == lit.f.tolist()
+            assert np.array_equal(lit2["genes"], cao.P) and lit2["fitness"].tolist() == cao.f.tolist()
         run.stop_after_class(gen % k)
         with pytest.raises(ValueError):
             run.stop_after_class(k)
@@ -500,19 +518,19 @@ def test_forced_improvement_stops_at_improvement_not_at_acceptance(n, seed):
     cp, ce = run.classes()
     assert np.all(np.diff(cp) == 1)
     classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(len(cp) - 1)]
-    lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=seed, fi=True)
-    wrong = LiteralParGomea(g, ptr, vars_, classes, pop, seed=seed, fi=True,
+    cao = ClassAtOnceGomea(g, ptr, vars_, classes, pop, seed=seed, fi=True)
+    wrong = ClassAtOnceGomea(g, ptr, vars_, classes, pop, seed=seed, fi=True,
                             fi_stop_on_accept=True)
     readings_differ = False
     for gen in range(10):
         run.generation()
-        lit.generation()
+        cao.generation()
         wrong.generation()
         s = run.state()
-        assert np.array_equal(s["genes"], lit.P), gen
-        assert s["fitness"].tolist() == lit.f.tolist(), gen
-        assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted), gen
-        readings_differ |= not np.array_equal(lit.P, wrong.P)
+        assert np.array_equal(s["genes"], cao.P), gen
+        assert s["fitness"].tolist() == cao.f.tolist(), gen
+        assert (s["evaluated"], s["accepted"]) == (cao.evaluated, cao.accepted), gen
+        readings_differ |= not np.array_equal(cao.P, wrong.P)
     assert readings_differ
 
 
@@ -520,25 +538,25 @@ def test_forced_improvement_stops_at_improvement_not_at_acceptance(n, seed):
                                              (6, 8, 0, 4)])
 def test_forced_improvement_equals_serial_with_one_set_per_class(n, pop, rule, seed):
     """With one set per class, the class-by-class forced improvement is the serial procedure
-    of Section 4 (the literal reading stops at the first improving step)."""
+    of Section 4 (the whole-class reference stops at the first improving step)."""
     g = _complete_graph(n, seed)
     ptr, vars_ = oracle.fos(g, 0)
     run = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule, flags=oracle.FLAG_FI)
     cp, ce = run.classes()
     assert np.all(np.diff(cp) == 1)
     classes = [ce[cp[c]:cp[c + 1]].tolist() for c in range(len(cp) - 1)]
-    lit = LiteralParGomea(g, ptr, vars_, classes, pop, seed=seed, rule=rule, fi=True)
+    cao = ClassAtOnceGomea(g, ptr, vars_, classes, pop, seed=seed, rule=rule, fi=True)
     plain = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, rule=rule)
     differs = False
     for gen in range(8):
         run.generation()
-        lit.generation()
+        cao.generation()
         plain.generation()
         s = run.state()
-        assert np.array_equal(s["genes"], lit.P), gen
-        assert s["fitness"].tolist() == lit.f.tolist(), gen
-        assert (s["evaluated"], s["accepted"]) == (lit.evaluated, lit.accepted), gen
-        assert np.array_equal(s["elite"], lit.E) and s["elite_fitness"] == lit.fE
+        assert np.array_equal(s["genes"], cao.P), gen
+        assert s["fitness"].tolist() == cao.f.tolist(), gen
+        assert (s["evaluated"], s["accepted"]) == (cao.evaluated, cao.accepted), gen
+        assert np.array_equal(s["elite"], cao.E) and s["elite_fitness"] == cao.fE
         differs |= not np.array_equal(s["genes"], plain.state()["genes"])
     assert differs, "forced improvement never changed anything"
 
