@@ -70,6 +70,8 @@ def lib():
                                            C.c_int32]
     L.or_hash.restype = C.c_uint64
     L.or_hash.argtypes = [C.c_void_p]
+    L.or_set_workers.restype = C.c_int32
+    L.or_set_workers.argtypes = [C.c_void_p, C.c_int32]
     _lib = L
     return L
 
@@ -139,7 +141,8 @@ class Run:
     """One oracle run of parallel GOM (Algorithm 3) on graph g with the given FOS."""
 
     def __init__(self, g, set_ptr, set_vars, pop: int, seed: int, rule: int = NEUTRAL_PAPER,
-                 order: int = ORDER_RANDOM, flags: int = 0, donor_salt: int = 0):
+                 order: int = ORDER_RANDOM, flags: int = 0, donor_salt: int = 0,
+                 workers: int = 1):
         self._L = lib()
         self.g = g
         self.set_ptr = np.ascontiguousarray(set_ptr, np.int32)
@@ -150,6 +153,16 @@ class Run:
         if not h:
             raise RuntimeError("or_new failed")
         self._h = h
+        if workers != 1:
+            self.set_workers(workers)
+
+    def set_workers(self, workers: int) -> int:
+        """Spread the solutions of each colour class over `workers` threads (results do not
+        change).  Returns the number in use."""
+        r = int(self._L.or_set_workers(self._h, int(workers)))
+        if r < 0:
+            raise MemoryError("or_set_workers: out of memory")
+        return r
 
     def close(self):
         if self._h:

@@ -14,16 +14,18 @@ SRC = os.path.join(HERE, "gom_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles (portable -O2, no -march=native: the library travels to other hosts)."""
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", SRC, "-o", tmp]
+def build(verbose: bool = False, out: str = LIB, native: bool = False) -> str:
+    """Always recompiles.  The in-tree library is portable -O2 (it travels to other hosts);
+    native=True adds -march=native for a copy built on the host that times it.  OpenMP spreads
+    a colour class's solutions over threads when a run asks for more than one worker."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-Wno-unused-parameter", *(["-march=native"] if native else []), SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -12,7 +12,8 @@
  * What each function follows (sections, equations and algorithms of the paper):
  *   or_philox4x32_10 / or_philox4x64_10  counter-based RNG of Salmon, Moraes, Dror & Shaw,
  *       "Parallel random numbers: as easy as 1, 2, 3" (SC'11); the paper names no RNG.
- *       Pinned: the 4x64 instance against numpy.random.Philox (same round template).
+ *       Pinned: the published known-answer vectors of Philox4x32-10 (Random123
+ *       distribution), and the 4x64 instance against numpy.random.Philox.
  *   or_maxcut          Section 6.2, the Max-Cut objective: sum of weights of edges whose
  *       endpoints are on different sides.  Pinned: brute force, closed forms.
  *   or_fos_build       Section 4.1 (a FOS is a family of variable subsets that covers every
@@ -25,7 +26,8 @@
  *   or_new/or_generation/or_run   Algorithm 3 (Par-GOMEA) with the step of Algorithm 2 (GOM)
  *       and the partial evaluation of Algorithm 4 / Section 2.2, under the readings listed
  *       at the top of or_generation.  Pinned: partial delta equals full re-evaluation after
- *       every step (debug flag), hand-worked two-solution examples, invariants (monotone
+ *       every step (debug flag), the whole-class reference with full evaluations,
+ *       hand-worked two-solution examples, invariants (monotone
  *       fitness, converged fixed point, univariate donor independence, in-class order
  *       invariance).  There are no published trajectories to compare against.
  *   or_linkage_tree    Section 4.1: the Linkage Tree by UPGMA (pairwise merges of the two
@@ -46,8 +48,9 @@
  *       zero-flip rounds equal the plain search, invariants (full-evaluation fitness, no
  *       solution gets worse, local optima kept, counters unchanged).
  *   or_stop_after_class  a generation of Algorithm 3 cut after a given position of the class
- *       order (a debugging view of the offspring between two groups).  Pinned: the literal
- *       reading of Algorithms 3/4 stopped at the same group.
+ *       order (a debugging view of the offspring between two groups).  Pinned: the
+ *       whole-class reference (every pair of a class decided on the class-start offspring,
+ *       full evaluations) stopped after the same class.
  *   or_hash            a 64-bit summary of the state (not from the paper): the sum modulo 2^64
  *       of SplitMix64's output mixer (Steele, Lea & Flood, OOPSLA 2014) applied to
  *       256 * k + b_k for every byte b_k at position k of a canonical byte string.  Pinned: a
@@ -56,6 +59,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------------------------
  * Philox (SC'11): a Feistel-like network over 4 words; each round multiplies words 0 and 2
@@ -465,19 +471,93 @@ typedef struct or_state {
     int32_t open_next;        /* -1, or the next class position of an unfinished generation */
     int64_t attempted, evaluated, accepted;
     int64_t debug_mismatches;
-    /* scratch */
-    int32_t *donors, *perm, *vstamp;
+    int32_t *perm;
+    /* working memory: one block per worker thread (one unless or_set_workers asks for more) */
+    int32_t nwork;
+    struct or_work *work;
+} or_state;
+
+/* Working memory of one worker: the donor list of a step, stamps that mark the vertices and
+   edges a step touches, and the step counters it adds up (folded into the state after each
+   class). */
+typedef struct or_work {
+    int32_t *donors, *vstamp;
     int64_t *estamp;
     int32_t stamp;
-} or_state;
+    int64_t attempted, evaluated, accepted, debug_mismatches;
+} or_work;
+
+static void work_free(or_work *w) {
+    free(w->donors); free(w->vstamp); free(w->estamp);
+    memset(w, 0, sizeof(*w));
+}
+
+static int work_init(or_work *w, int32_t n, int64_t m, int32_t pop) {
+    memset(w, 0, sizeof(*w));
+    w->donors = malloc(sizeof(int32_t) * (size_t)pop);
+    w->vstamp = malloc(sizeof(int32_t) * (size_t)n);
+    w->estamp = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    if (!w->donors || !w->vstamp || !w->estamp) { work_free(w); return -1; }
+    for (int32_t v = 0; v < n; ++v) w->vstamp[v] = -1;
+    for (int64_t e = 0; e < m; ++e) w->estamp[e] = -1;
+    return 0;
+}
+
+/* Add the workers' step counters to the state's and clear them. */
+static void fold_counters(or_state *s) {
+    for (int32_t t = 0; t < s->nwork; ++t) {
+        or_work *w = &s->work[t];
+        s->attempted += w->attempted;
+        s->evaluated += w->evaluated;
+        s->accepted += w->accepted;
+        s->debug_mismatches += w->debug_mismatches;
+        w->attempted = w->evaluated = w->accepted = w->debug_mismatches = 0;
+    }
+}
+
+static int worker_id(void) {
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
 
 void or_free(or_state *s) {
     if (!s) return;
     graph_free(&s->g);
     free(s->set_ptr); free(s->set_vars); free(s->class_ptr); free(s->class_elems);
     free(s->P); free(s->O); free(s->E); free(s->eq); free(s->acc_any); free(s->f);
-    free(s->donors); free(s->perm); free(s->vstamp); free(s->estamp);
+    free(s->perm);
+    for (int32_t t = 0; t < s->nwork; ++t) work_free(&s->work[t]);
+    free(s->work);
     free(s);
+}
+
+/* Number of worker threads over which the solutions of a class are spread (1 = serial).
+   The solutions of a class only write their own offspring and fitness and read the
+   generation-start population, so the result is the same for any number.  Returns the
+   number set (1 without OpenMP), or -1 when memory ran out (the state is then unchanged). */
+int32_t or_set_workers(or_state *s, int32_t nwork) {
+#ifndef _OPENMP
+    nwork = 1;
+#endif
+    if (nwork < 1) nwork = 1;
+    if (nwork == s->nwork) return nwork;
+    or_work *w = calloc((size_t)nwork, sizeof(or_work));
+    if (!w) return -1;
+    for (int32_t t = 0; t < nwork; ++t)
+        if (work_init(&w[t], s->g.n, s->g.m, s->N)) {
+            for (int32_t u = 0; u < t; ++u) work_free(&w[u]);
+            free(w);
+            return -1;
+        }
+    fold_counters(s);
+    for (int32_t t = 0; t < s->nwork; ++t) work_free(&s->work[t]);
+    free(s->work);
+    s->work = w;
+    s->nwork = nwork;
+    return nwork;
 }
 
 static void full_fitness_all(or_state *s) {
@@ -519,15 +599,13 @@ or_state *or_new(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, con
     s->eq = malloc((size_t)pop);
     s->acc_any = calloc((size_t)pop, 1);
     s->f = malloc(sizeof(int64_t) * (size_t)pop);
-    s->donors = malloc(sizeof(int32_t) * (size_t)pop);
-    s->vstamp = malloc(sizeof(int32_t) * (size_t)n);
-    s->estamp = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    s->work = calloc(1, sizeof(or_work));
     int32_t *colour = malloc(sizeof(int32_t) * (size_t)nsets);
-    if (!s->P || !s->O || !s->E || !s->eq || !s->acc_any || !s->f || !s->donors ||
-        !s->vstamp || !s->estamp || !colour) { free(colour); or_free(s); return NULL; }
-    for (int32_t v = 0; v < n; ++v) s->vstamp[v] = -1;
-    for (int64_t e = 0; e < m; ++e) s->estamp[e] = -1;
-    s->stamp = 0;
+    if (!s->P || !s->O || !s->E || !s->eq || !s->acc_any || !s->f || !s->work || !colour) {
+        free(colour); or_free(s); return NULL;
+    }
+    if (work_init(&s->work[0], n, m, pop)) { free(colour); or_free(s); return NULL; }
+    s->nwork = 1;
 
     /* Groups G_1..G_k: colour classes, members ascending by set index. */
     s->k = colour_sets(&s->g, nsets, s->set_ptr, s->set_vars, colour, NULL);
@@ -566,24 +644,25 @@ or_state *or_new(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, con
    and after the insertion.  Accepts improvements, and equal fitness unless P_i equals the
    elitist (or always, under the ALWAYS rule).  *delta receives the change; returns whether
    the step was accepted. */
-static int try_insert(or_state *s, int32_t i, int32_t j, const uint8_t *D, int64_t *delta_out) {
+static int try_insert(or_state *s, or_work *w, int32_t i, int32_t j, const uint8_t *D,
+                      int64_t *delta_out) {
     const int32_t n = s->g.n;
     uint8_t *Oi = s->O + (size_t)i * n;
     const int32_t *F = s->set_vars + s->set_ptr[j];
     const int32_t sz = s->set_ptr[j + 1] - s->set_ptr[j];
-    int32_t tag = ++s->stamp;
-    for (int32_t q = 0; q < sz; ++q) s->vstamp[F[q]] = tag;
+    int32_t tag = ++w->stamp;
+    for (int32_t q = 0; q < sz; ++q) w->vstamp[F[q]] = tag;
     int64_t delta = 0;
     for (int32_t q = 0; q < sz; ++q) {
         int32_t u = F[q];
         for (int64_t t = s->g.inc_ptr[u]; t < s->g.inc_ptr[u + 1]; ++t) {
             int64_t e = s->g.inc[t];
-            if (s->estamp[e] == tag) continue;
-            s->estamp[e] = tag;
+            if (w->estamp[e] == tag) continue;
+            w->estamp[e] = tag;
             int32_t a = s->g.eu[e], b = s->g.ev[e];
             uint8_t xa = Oi[a], xb = Oi[b];
-            uint8_t ya = s->vstamp[a] == tag ? D[a] : xa;
-            uint8_t yb = s->vstamp[b] == tag ? D[b] : xb;
+            uint8_t ya = w->vstamp[a] == tag ? D[a] : xa;
+            uint8_t yb = w->vstamp[b] == tag ? D[b] : xb;
             int64_t before = xa != xb ? s->g.ew[e] : 0;
             int64_t after = ya != yb ? s->g.ew[e] : 0;
             delta += after - before;
@@ -593,23 +672,23 @@ static int try_insert(or_state *s, int32_t i, int32_t j, const uint8_t *D, int64
     if (accept) {
         for (int32_t q = 0; q < sz; ++q) Oi[F[q]] = D[F[q]];
         s->f[i] += delta;
-        s->accepted++;
+        w->accepted++;
     }
     if (s->flags & OR_FLAG_DEBUG) {
         int64_t full = or_maxcut(n, s->g.m, s->g.eu, s->g.ev, s->g.ew, Oi);
-        if (full != s->f[i]) s->debug_mismatches++;
+        if (full != s->f[i]) w->debug_mismatches++;
     }
     *delta_out = delta;
     return accept;
 }
 
 /* One GOM step (Algorithm 2) for solution i and set j at position p of class c. */
-static void gom_step(or_state *s, int32_t c, int32_t p, int32_t j, int32_t i) {
+static void gom_step(or_state *s, or_work *w, int32_t c, int32_t p, int32_t j, int32_t i) {
     const int32_t n = s->g.n;
     uint8_t *Oi = s->O + (size_t)i * n;
     const int32_t *F = s->set_vars + s->set_ptr[j];
     const int32_t sz = s->set_ptr[j + 1] - s->set_ptr[j];
-    s->attempted++;
+    w->attempted++;
 
     /* SelectDonorFromPopulation: candidates are the other members of the population P (as
        it was at the start of the generation) whose genes on F_j differ from those of O_i. */
@@ -618,18 +697,18 @@ static void gom_step(or_state *s, int32_t c, int32_t p, int32_t j, int32_t i) {
         if (d == i) continue;
         const uint8_t *Pd = s->P + (size_t)d * n;
         for (int32_t q = 0; q < sz; ++q)
-            if (Pd[F[q]] != Oi[F[q]]) { s->donors[nd++] = d; break; }
+            if (Pd[F[q]] != Oi[F[q]]) { w->donors[nd++] = d; break; }
     }
     if (nd == 0) return; /* no donor differs: this step is skipped */
-    s->evaluated++;
+    w->evaluated++;
 
     /* Uniform choice among the nd candidates from a 16-bit Philox field. */
     uint32_t out[4];
     draw4(s->donor_seed, (uint32_t)s->gen, (uint32_t)c, (uint32_t)i, (uint32_t)(p >> 3), out);
     uint32_t h = (out[(p & 7) >> 1] >> (16 * (p & 1))) & 0xFFFFu;
-    int32_t d = s->donors[((uint64_t)h * (uint64_t)nd) >> 16];
+    int32_t d = w->donors[((uint64_t)h * (uint64_t)nd) >> 16];
     int64_t delta;
-    if (try_insert(s, i, j, s->P + (size_t)d * n, &delta)) s->acc_any[i] = 1;
+    if (try_insert(s, w, i, j, s->P + (size_t)d * n, &delta)) s->acc_any[i] = 1;
 }
 
 /* Forced improvement, in a form that runs class by class (Section 4 describes the serial
@@ -656,7 +735,7 @@ static void forced_improvement(or_state *s) {
                 if (!differs) continue;
                 s->evaluated++;
                 int64_t delta;
-                if (try_insert(s, i, j, s->E, &delta) && delta > 0) improved = 1;
+                if (try_insert(s, &s->work[0], i, j, s->E, &delta) && delta > 0) improved = 1;
             }
         }
         if (!improved) {
@@ -664,6 +743,7 @@ static void forced_improvement(or_state *s) {
             s->f[i] = s->fE;
         }
     }
+    fold_counters(s);
 }
 
 /*
@@ -702,19 +782,24 @@ static void begin_generation(or_state *s) {
     s->open_next = 0;
 }
 
-/* Every (solution, set) pair of the class at position t of the order. */
+/* Every (solution, set) pair of the class at position t of the order.  A solution's steps
+   write only its own offspring, fitness and flag and read the generation-start population, so
+   the solutions may be spread over worker threads. */
 static void run_class(or_state *s, int32_t t) {
     const int32_t N = s->N;
     const int rev = (s->flags & OR_FLAG_REVERSE) != 0;
     int32_t c = s->perm[t];
     int32_t size = s->class_ptr[c + 1] - s->class_ptr[c];
+#pragma omp parallel for num_threads(s->nwork) schedule(static) if (s->nwork > 1)
     for (int32_t ii = 0; ii < N; ++ii) {
+        or_work *w = &s->work[worker_id()];
         int32_t i = rev ? N - 1 - ii : ii;
         for (int32_t pp = 0; pp < size; ++pp) {
             int32_t p = rev ? size - 1 - pp : pp;
-            gom_step(s, c, p, s->class_elems[s->class_ptr[c] + p], i);
+            gom_step(s, w, c, p, s->class_elems[s->class_ptr[c] + p], i);
         }
     }
+    fold_counters(s);
 }
 
 /* Generation end: P <- O, then the elitist on strict improvement. */

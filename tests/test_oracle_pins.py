@@ -980,3 +980,23 @@ def test_iterated_local_search_zero_flips_and_round_ranges():
     ptr, vars_ = oracle.fos(g, 1)
     with pytest.raises(ValueError):
         oracle.Run(g, ptr, vars_, pop=4, seed=1).iterated_local_search(0, 1, 1)
+
+
+@pytest.mark.parametrize("kind,pop,flags", [(1, 33, 0), (0, 64, oracle.FLAG_DEBUG),
+                                             (1, 17, oracle.FLAG_FI | oracle.FLAG_DEBUG)])
+def test_oracle_workers_do_not_change_the_run(kind, pop, flags):
+    """Solutions of a class spread over several worker threads: the same states and hashes as
+    one worker, every generation (a class's solutions write only their own offspring)."""
+    g = workloads.torus(20, 1, 100, seed=5)
+    ptr, vars_ = oracle.fos(g, kind)
+    runs = [oracle.Run(g, ptr, vars_, pop=pop, seed=9, flags=flags, workers=w) for w in (1, 3, 8)]
+    for gen in range(8):
+        for r in runs:
+            r.generation()
+        states = [r.state() for r in runs]
+        for s in states[1:]:
+            for key in ("genes", "fitness", "elite", "elite_fitness", "generation", "attempted",
+                        "evaluated", "accepted", "debug_mismatches"):
+                assert np.array_equal(np.asarray(s[key]), np.asarray(states[0][key])), (gen, key)
+        assert len({r.hash() for r in runs}) == 1
+        assert states[0]["debug_mismatches"] == 0
