@@ -1,20 +1,24 @@
-"""Benchmark: parallel GOM partial evaluations per second and time-to-optimum on one MI355X.
+"""Benchmark: parallel GOM partial evaluations per second and time-to-optimum on one MI355X,
+batched against plain.
 
-Workload: plain GOM (one instance per launch sequence) on a 100x100 torus (n = 10,000,
-m = 20,000), int32 weights uniform in [1, 100], neighbourhood FOS ({v} plus its 4
-neighbours), population 64, run until the elitist reaches the total weight (the optimum of a
-bipartite torus) or 500 generations; int64 fitness.
+Default line (the batched configuration): 256 independent Max-Cut instances with n
+log-uniform in [10^3, 10^5] (even positions L x L tori, odd positions random 4- and 8-regular
+graphs), weights uniform in [1, 100], populations uniform in [16, 64], univariate and
+neighbourhood FOS alternating in pairs, run in one lockstep batch (one sweep, one finalize and
+one vertex-pass launch per generation step, replayed from captured HIP graphs) until every
+torus reaches its total weight or 200 generations.
 
-A step is one whole run of the hot path: a fresh initial population on the device (new seed),
-its fitness and elitist, then generations until the target or the limit.  Timed steps use
-seeds 1..K.  `value` = attempted partial evaluations (population x FOS sets x generations,
-summed over the steps) per second of the timed region; time-to-optimum per run is reported
-beside it.
+A step is one batched run of the whole mix from fresh initial populations (new seeds per
+step).  `value` = attempted partial evaluations (population x FOS sets x generations, summed
+over instances and steps) per second of the timed region.  Beside it: the plain loop (the
+first timed step's seeds, one instance after another, each alone, with the default schedule),
+whether every result is identical (counters and state hashes), time to optimum, the roofline
+of the batched sweep kernel (algorithmic bytes of every instance-generation over the summed
+launch times, from HIP events recorded by each launch's dispatch in one more run after the
+timed region) and the CPU oracle timed on a bounded sample of the mix.
 
-Also reported: the roofline of the dominant kernel (the colour-class sweep: algorithmic bytes
-per launch over its mean execution time, from HIP events that every sweep launch of one extra
-run right after the timed steps records with its own dispatch) and the CPU oracle timed on a
-bounded sample of the same workload on the host.
+Other modes: --workload NAME (plain GOM on one instance per launch sequence, e.g.
+torus100_nbhd_p64), --serve (the serving loop), --ims (interleaved multistart).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -108,10 +112,108 @@ def cpu_baseline(g, fos_kind, pop, gens, target, fi=False):
                       "single-threaded C oracle)"}
 
 
+def instance_bytes(inst, pop):
+    """Algorithmic bytes of one generation of one instance (every class swept once)."""
+    _, class_ptr, class_elems = inst.classes()
+    set_ptr, set_vars = inst.fos.sets()
+    return float(class_sweep_bytes(inst.graph.csr(), set_ptr, set_vars, class_ptr, class_elems,
+                                   pop).sum())
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_mix(items, seeds, count, gens):
+    """The oracle, unchanged, built with -march=native on this host, on the first `count`
+    instances of the mix for `gens` generations each (the seeds of the first timed step), its
+    colour classes' solutions spread over every host core (up to 16)."""
+    import tempfile
+    import oracle
+    workers = max(1, min(16, os.cpu_count() or 1))
+    native = True
+    try:
+        oracle.use_native_build(os.path.join(tempfile.gettempdir(),
+                                             f"liboracle_native_{os.getpid()}.so"))
+    except Exception as e:  # a compiler without -march=native: the portable in-tree build
+        native = False
+        log(f"cpu baseline: native build failed ({e}); portable build used")
+    attempted, dt, used = 0, 0.0, 1
+    for it, sd in zip(items[:count], seeds[:count]):
+        set_ptr, set_vars = oracle.fos(it.graph, it.fos)
+        run = oracle.Run(it.graph, set_ptr, set_vars, pop=it.pop, seed=int(sd))
+        used = run.set_workers(workers)
+        tg = it.graph.total_weight if it.to_total_weight else (1 << 62)
+        t0 = time.perf_counter()
+        run.run(tg, gens)
+        dt += time.perf_counter() - t0
+        attempted += run.state(genes=False)["attempted"]
+        run.close()
+    return {"value": attempted / dt, "unit": "evals/s", "cores": used, "kind": "oracle",
+            "sample": f"first {count} instances of the mix (the first timed step's seeds), "
+                      f"{gens} generations each: {attempted} attempted partial evaluations in "
+                      f"{dt:.2f} s; each colour class's solutions spread over {used} threads "
+                      "(results independent of the thread count)",
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count(),
+            "build": "gcc -O2 -fopenmp" + (" -march=native" if native else "")}
+
+
+def step_seeds(items, k):
+    """Seeds of timed step k (k >= 0); warm-up steps use k < 0.  Distinct per instance and
+    step."""
+    return [(k + 2) * 100_000 + b for b in range(len(items))]
+
+
+def small_mix_time_to_optimum(torch, gom, count, max_gens):
+    """Time to optimum on a mix of small instances that reach it: tori of 6x6 to 12x12 and
+    random 4/8-regular graphs of 36 to 144 vertices, batched against the plain loop, with
+    identical results."""
+    items = workloads.batch_mix(count=count, seed=4, n_lo=36, n_hi=144)
+    insts = [gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
+             for it in items]
+    targets = [it.graph.total_weight if it.to_total_weight else (1 << 62) for it in items]
+    pops, seeds = [it.pop for it in items], [it.seed for it in items]
+    batch = gom.gom_batch_init(insts, pops, seeds, targets)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, tt = gom.gom_batch_run(batch, max_gens)
+    t_batch = time.perf_counter() - t0
+    plain_t, plain = [], []
+    for x, p, sd, tg in zip(insts, pops, seeds, targets):
+        st = x.state(pop=p, seed=sd)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        plain.append(gom.gom_run_to_target(st, tg, max_gens))
+        plain_t.append(time.perf_counter() - s0)
+    same = all((a.generations, a.reached, a.best, a.evaluated, a.accepted) ==
+               (b.generations, b.reached, b.best, b.evaluated, b.accepted)
+               for a, b in zip(res, plain))
+    tori = [b for b, it in enumerate(items) if it.to_total_weight and res[b].reached]
+    loop_t = np.cumsum(plain_t) * 1e3
+    q = lambda x, p: float(np.percentile(np.asarray(x), p)) if len(x) else None
+    return {"workload": f"batch{count}_tori_and_regular_36_144", "max_generations": max_gens,
+            "tori_reached": len(tori), "identical_results": same,
+            "batched_ms": t_batch * 1e3, "plain_loop_ms": float(loop_t[-1]),
+            "batched_p50": q([tt[b] for b in tori], 50), "batched_p99": q([tt[b] for b in tori], 99),
+            "plain_loop_p50": q([loop_t[b] for b in tori], 50),
+            "plain_loop_p99": q([loop_t[b] for b in tori], 99),
+            "plain_alone_p50": q([plain_t[b] * 1e3 for b in tori], 50),
+            "plain_alone_p99": q([plain_t[b] * 1e3 for b in tori], 99)}
+
+
 def run_batch_mode(args, torch, gom):
-    """Batched vs plain on a mix of independent instances (the batched configuration): all
-    instances in one lockstep batch, against the same instances run one after another, each
-    alone, with the default schedule.  Every instance reaches the same state either way."""
+    """Batched vs plain on the 256-instance mix (the default line).  A step is one batched run
+    of the whole mix: fresh initial populations (new seeds), then lockstep generations until
+    every instance has reached its target or the generation limit.  The plain leg runs the
+    first timed step's seeds one instance after another, each alone; results must be
+    identical (counters and state hashes)."""
     n_lo, n_hi = args.batch_n_range
     n_label = "1e3_1e5" if (n_lo, n_hi) == (1e3, 1e5) else f"{n_lo:g}_{n_hi:g}"
     items = workloads.batch_mix(count=args.batch_count, seed=4, n_lo=n_lo, n_hi=n_hi)
@@ -120,66 +222,138 @@ def run_batch_mode(args, torch, gom):
     insts = [gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
              for it in items]
     targets = [it.graph.total_weight if it.to_total_weight else (1 << 62) for it in items]
-    pops, seeds = [it.pop for it in items], [it.seed for it in items]
-    log(f"batch set-up: {len(items)} instances, {sum(x.n for x in insts)} vertices, "
-        f"{time.perf_counter() - t0:.1f} s")
-    # warm-up: a small batch and a small plain run load every kernel
-    wb = gom.gom_batch_init(insts[:4], pops[:4], seeds[:4], targets[:4])
-    gom.gom_batch_run(wb, 2)
-    del wb
-    batch = gom.gom_batch_init(insts, pops, seeds, targets)
+    pops = [it.pop for it in items]
+    t_setup = time.perf_counter() - t0
+    log(f"batch set-up: {len(items)} instances, {sum(x.n for x in insts)} vertices, graphs, "
+        f"FOS and colourings in {t_setup:.1f} s")
+    t0 = time.perf_counter()
+    batch = gom.gom_batch_init(insts, pops, step_seeds(items, 0), targets)
     gom.gom_batch_set_graph(batch, args.batch_graph == "on")
+    log(f"batch states: {time.perf_counter() - t0:.1f} s")
+
+    def one_step(k):
+        gom.gom_batch_reseed(batch, step_seeds(items, k))
+        return gom.gom_batch_run(batch, max_gens)
+
+    for w in range(args.warmup):
+        res, _ = one_step(-1 - w)
+        log(f"warmup {w}: {sum(r.generations for r in res)} instance-generations")
+    steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res, tt = gom.gom_batch_run(batch, max_gens)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    ev_batch = sum(r.attempted for r in res)
-    log(f"batched: {t_batch * 1e3:.1f} ms, {ev_batch} attempted, "
-        f"reached {sum(r.reached for r in res)}")
-    states = [x.state(pop=p, seed=sd) for x, p, sd in zip(insts, pops, seeds)]
-    torch.cuda.synchronize()
-    plain_t = []
-    t0 = time.perf_counter()
-    plain = []
-    for st, tg in zip(states, targets):
+    for k in range(args.steps):
         s0 = time.perf_counter()
+        res, tt = one_step(k)
+        steps.append((res, tt, time.perf_counter() - s0))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    attempted = sum(r.attempted for res, _, _ in steps for r in res)
+    evaluated = sum(r.evaluated for res, _, _ in steps for r in res)
+    for k, (res, tt, dt) in enumerate(steps):
+        log(f"step {k}: {dt * 1e3:.1f} ms, {sum(r.attempted for r in res)} attempted, "
+            f"reached {sum(r.reached for r in res)}")
+
+    # kernel-timing pass after the timed region: the first timed step's seeds again, every
+    # sweep launch timed with HIP events recorded by its own dispatch (direct launches)
+    gom.gom_batch_timing_enable(batch, True)
+    gom.gom_batch_timing_read(batch)
+    res_t, _ = one_step(0)
+    sweep_ms, launches = gom.gom_batch_timing_read(batch)
+    gom.gom_batch_timing_enable(batch, False)
+    batch_hash = [gom.gom_state_hash(batch.state(b)) for b in range(len(items))]
+    same_timed = all((a.generations, a.best, a.evaluated, a.accepted) ==
+                     (b.generations, b.best, b.evaluated, b.accepted)
+                     for a, b in zip(res_t, steps[0][0]))
+
+    # plain leg: the same seeds, one instance after another, each alone
+    seeds0 = step_seeds(items, 0)
+    plain, plain_t, plain_hash = [], [], []
+    t0 = time.perf_counter()
+    for x, p, sd, tg in zip(insts, pops, seeds0, targets):
+        st = x.state(pop=p, seed=sd)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        gom.gom_state_reseed(st, sd)
         plain.append(gom.gom_run_to_target(st, tg, max_gens))
         plain_t.append(time.perf_counter() - s0)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+        plain_hash.append(gom.gom_state_hash(st))
+        del st
+    t_plain = sum(plain_t)
     ev_plain = sum(r.attempted for r in plain)
-    same = all((a.generations, a.best, a.evaluated, a.accepted) ==
-               (b.generations, b.best, b.evaluated, b.accepted) for a, b in zip(res, plain))
-    log(f"plain: {t_plain * 1e3:.1f} ms, {ev_plain} attempted, identical results: {same}")
-    tori = [b for b, it in enumerate(items) if it.to_total_weight and res[b].reached]
-    tto_b = np.array([tt[b] for b in tori])
-    tto_p = np.array([plain_t[b] * 1e3 for b in tori])
-    # in the plain loop an instance reaches its optimum only after every earlier instance's run
+    same = same_timed and all(
+        (a.generations, a.reached, a.best, a.attempted, a.evaluated, a.accepted, ha) ==
+        (b.generations, b.reached, b.best, b.attempted, b.evaluated, b.accepted, hb)
+        for a, b, ha, hb in zip(steps[0][0], plain, batch_hash, plain_hash))
+    log(f"plain: {t_plain * 1e3:.1f} ms for the first step's seeds, identical results: {same}")
+
+    value = attempted / total
+    plain_value = ev_plain / t_plain
+    res0, tt0, t_step0 = steps[0]
+    tori = [b for b, it in enumerate(items) if it.to_total_weight and res0[b].reached]
     loop_t = np.cumsum(plain_t) * 1e3
-    tto_loop = np.array([loop_t[b] for b in tori])
+    q = lambda x, p: float(np.percentile(np.asarray(x), p)) if len(x) else None
+
+    # roofline of the batched sweep: the algorithmic bytes of every instance-generation the
+    # timing pass ran, over the summed sweep time
+    roofline = None
+    if launches:
+        ib = [instance_bytes(x, p) for x, p in zip(insts, pops)]
+        total_bytes = float(sum(ib[b] * res_t[b].generations for b in range(len(items))))
+        achieved = total_bytes / (sweep_ms / 1e3) / 1e9
+        meas = MEASURED_TRAFFIC.get(("k_batch_sweep", "batch256_mix"))
+        traffic = meas["bytes"] if meas and meas["source"] == kernel_source_hash() else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                    "traffic": traffic,
+                    "traffic_profile": meas["profile"] if traffic else None,
+                    "kernel": "k_batch_sweep",
+                    "bytes_per_launch": round(total_bytes / launches, 1),
+                    "avg_launch_us": round(sweep_ms / launches * 1e3, 3), "launches": launches,
+                    "timing": "every sweep launch of one more batched run (the first timed "
+                              "step's seeds) after the timed region, HIP events recorded by "
+                              "the dispatch"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_mix(items, seeds0, args.cpu_instances, args.cpu_gens)
+        log(f"cpu baseline: {cpu}")
+    small = None if args.no_small_mix else small_mix_time_to_optimum(torch, gom, 256, 300)
+    if small:
+        log(f"small mix: {small}")
     line = {
-        "metric": METRIC, "value": ev_batch / t_batch, "unit": "evals/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
         "config": {"workload": f"batch{len(items)}_tori_and_regular_{n_label}",
                    "instances": len(items), "vertices": int(sum(x.n for x in insts)),
-                   "pop_range": [16, 64], "max_generations": max_gens, "mode": "batched",
-                   "schedule": "batched_resident",
+                   "pop_range": [16, 64], "max_generations": max_gens,
+                   "fos": "univariate and neighbourhood alternating in pairs",
+                   "mode": "batched", "schedule": "batched_resident",
                    "generation_steps": ("hip_graph_chunks_of_4" if args.batch_graph == "on"
-                                        else "direct_launches")},
-        "plain": {"value": ev_plain / t_plain, "ms": t_plain * 1e3,
+                                        else "direct_launches"),
+                   "step": "fresh populations (new seeds) and a batched run of the whole mix "
+                           "to every target or the generation limit"},
+        "evaluated_per_s": evaluated / total,
+        "plain": {"value": plain_value, "ms": t_plain * 1e3,
+                  "seeds": "the first timed step's",
                   "schedule": "auto per instance, one instance at a time"},
-        "batched_over_plain": (ev_batch / t_batch) / (ev_plain / t_plain),
+        "batched_over_plain": value / plain_value,
         "identical_results": same,
         "time_to_optimum_ms": {
             "instances_reached": len(tori),
-            "batched_p50": float(np.percentile(tto_b, 50)) if len(tori) else None,
-            "batched_p99": float(np.percentile(tto_b, 99)) if len(tori) else None,
-            "plain_alone_p50": float(np.percentile(tto_p, 50)) if len(tori) else None,
-            "plain_alone_p99": float(np.percentile(tto_p, 99)) if len(tori) else None,
-            "plain_loop_p50": float(np.percentile(tto_loop, 50)) if len(tori) else None,
-            "plain_loop_p99": float(np.percentile(tto_loop, 99)) if len(tori) else None},
+            "batched_p50": q([tt0[b] for b in tori], 50),
+            "batched_p99": q([tt0[b] for b in tori], 99),
+            "plain_loop_p50": q([loop_t[b] for b in tori], 50),
+            "plain_loop_p99": q([loop_t[b] for b in tori], 99),
+            "plain_alone_p50": q([plain_t[b] * 1e3 for b in tori], 50),
+            "plain_alone_p99": q([plain_t[b] * 1e3 for b in tori], 99),
+            "note": None if tori else
+            f"no torus of this mix reaches its total weight within {max_gens} generations "
+            "in either mode (the pinned method without forced improvement stalls below the "
+            "optimum on tori of 16x16 and larger); see time_to_optimum_small_mix"},
+        "time_to_optimum_small_mix": small,
+        "set_up_s": t_setup,
+        "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -339,18 +513,23 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-gens", type=int, default=40,
-                    help="generations of the oracle sample for the CPU baseline")
+    ap.add_argument("--cpu-gens", type=int, default=None,
+                    help="generations of the oracle sample for the CPU baseline (default: 10 "
+                         "per instance for the batched mix, 40 for a single workload)")
+    ap.add_argument("--cpu-instances", type=int, default=8,
+                    help="instances of the batched mix in the oracle sample")
+    ap.add_argument("--no-small-mix", action="store_true",
+                    help="batched mode: skip the time-to-optimum comparison on the mix of "
+                         "small instances")
     ap.add_argument("--schedule", choices=("tuned", "auto", "class", "resident", "bitsliced"),
                     default="tuned",
                     help="launch schedule of the generations (results are identical); 'tuned' "
                          "times each allowed schedule on a few generations before the warmup "
                          "and keeps the fastest")
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads.WORKLOADS),
-                    help="workload (default: the benchmark configuration)")
+    ap.add_argument("--workload", default=None, choices=sorted(workloads.WORKLOADS),
+                    help="plain GOM on this single workload instead of the batched mix")
     ap.add_argument("--batch", action="store_true",
-                    help="batched vs plain on the 256-instance mix instead of the default "
-                         "single-instance workload")
+                    help="batched vs plain on the mix (the default when no workload is named)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-n-range", type=float, nargs=2, metavar=("LO", "HI"),
                     default=(1e3, 1e5),
@@ -412,15 +591,19 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
-    if args.batch:
-        run_batch_mode(args, torch, gom)
-        return
     if args.serve:
         run_serve_mode(args, torch, gom)
         return
     if args.ims:
+        args.workload = args.workload or DEFAULT_WORKLOAD
         run_ims_mode(args, torch, gom)
         return
+    if args.batch or (args.workload is None and not args.local_search):
+        args.cpu_gens = args.cpu_gens or 10
+        run_batch_mode(args, torch, gom)
+        return
+    args.cpu_gens = args.cpu_gens or 40
+    args.workload = args.workload or DEFAULT_WORKLOAD
 
     wl = workloads.WORKLOADS[args.workload]
     max_gens = args.max_gens or wl.max_gens

@@ -414,6 +414,25 @@ int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream, gom_resul
  */
 int gom_batch_set_graph(gom_batch *b, int enabled);
 
+/*
+ * Restart every instance from a fresh initial population (Algorithm 3, InitializePopulation:
+ * the set-up step a0) drawn with seeds[b] (count entries, borrowed): population, full
+ * fitness, elitist, generation 0 and zero counters, as gom_state_init would leave them.  The
+ * step budget of gom_batch_run counts from 0 again.  Synchronous.
+ * Errors: GOM_E_ARG, GOM_E_STATE (an instance has an open generation), GOM_E_DEVICE.
+ */
+int gom_batch_reseed(gom_batch *b, const uint64_t *seeds, void *stream);
+
+/*
+ * Kernel timing of the batched sweep: while enabled, gom_batch_run launches every step
+ * directly (no graph) and the sweep launch of each step records a pair of HIP events with its
+ * own dispatch.  gom_batch_timing_read waits for the recorded pairs and returns the summed
+ * sweep time (ms) and the number of timed launches since the previous read, then resets both.
+ * Errors: GOM_E_ARG, GOM_E_DEVICE.
+ */
+int gom_batch_timing_enable(gom_batch *b, int enabled);
+int gom_batch_timing_read(gom_batch *b, double *sweep_ms_total, int64_t *sweep_launches);
+
 /* Borrowed handle of instance `index` (for gom_state_read); valid until gom_batch_free. */
 int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);
 

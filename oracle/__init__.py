@@ -25,14 +25,28 @@ _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
-def lib():
-    """Load oracle/liboracle.so, compiling it first only when it is missing."""
+def use_native_build(path: str) -> str:
+    """Compile a copy of the oracle with -march=native at `path` and load it instead of the
+    in-tree portable library (for timing on the host that runs it).  Must come before the
+    first use of the oracle in the process."""
+    global _lib
+    if _lib is not None:
+        raise RuntimeError("use_native_build: the oracle library is already loaded")
+    _build.build(out=path, native=True)
+    lib(path)
+    return path
+
+
+def lib(path: str | None = None):
+    """Load oracle/liboracle.so (or `path`), compiling it first only when it is missing."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
-        _build.build()
-    L = C.CDLL(_build.LIB)
+    if path is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+    L = C.CDLL(path)
     L.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     L.or_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
     L.or_maxcut.restype = C.c_int64

@@ -1752,6 +1752,12 @@ struct gom_batch {
     hipStream_t cap = nullptr;          // private stream the graph is captured on
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    std::vector<BatchInst> h_insts;     // host copy of the instance table
+    bool timing = false;                // every sweep launch records a pair of events
+    std::vector<hipEvent_t> tev;        // event pool of the timed sweep launches
+    size_t tev_used = 0;
+    double t_ms = 0.0;                  // folded sweep time and launch count
+    int64_t t_launches = 0;
 };
 
 namespace {
@@ -1810,6 +1816,7 @@ extern "C" void gom_batch_free(gom_batch *b) {
     for (gom_state *s : b->subs) gom_state_free(s);
     for (hipEvent_t e : b->chunk_ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->tev) (void)hipEventDestroy(e);
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -1894,6 +1901,7 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
     if (e != hipSuccess)
         return cleanup(fail(GOM_E_DEVICE, "gom_batch_init: %s", hipGetErrorString(e)));
     bt->wall_khz = (double)khz;
+    bt->h_insts = std::move(insts);
     *out = bt;
     return GOM_OK;
     GUARD_END
@@ -1946,6 +1954,84 @@ static bool batch_all_done(const gom_batch *b, int slot) {
     return true;
 }
 
+// Events of the next timed sweep launch (timing on), from the batch's pool; when the pool is
+// full, the recorded pairs are folded into the running total first.
+static int batch_timing_events(gom_batch *b, KernelEvents *ev) {
+    *ev = KernelEvents{};
+    if (!b->timing) return GOM_OK;
+    if (b->tev_used + 2 > b->tev.size()) {
+        if (b->tev.size() < (size_t)(1 << 12)) {
+            const size_t grow = b->tev.size() ? b->tev.size() : 64;
+            for (size_t q = 0; q < grow; ++q) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                b->tev.push_back(e);
+            }
+        } else {
+            for (size_t q = 0; q + 1 < b->tev_used; q += 2) {
+                float ms = 0.f;
+                HIP_TRY(hipEventSynchronize(b->tev[q + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, b->tev[q], b->tev[q + 1]));
+                b->t_ms += ms;
+                b->t_launches++;
+            }
+            b->tev_used = 0;
+        }
+    }
+    ev->start = b->tev[b->tev_used++];
+    ev->stop = b->tev[b->tev_used++];
+    return GOM_OK;
+}
+
+extern "C" int gom_batch_timing_enable(gom_batch *b, int enabled) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_timing_enable: null batch");
+    b->timing = enabled != 0;
+    return GOM_OK;
+}
+
+extern "C" int gom_batch_timing_read(gom_batch *b, double *sweep_ms_total,
+                                     int64_t *sweep_launches) {
+    GUARD_BEGIN
+    if (!b) return fail(GOM_E_ARG, "gom_batch_timing_read: null batch");
+    for (size_t q = 0; q + 1 < b->tev_used; q += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventSynchronize(b->tev[q + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, b->tev[q], b->tev[q + 1]));
+        b->t_ms += ms;
+        b->t_launches++;
+    }
+    b->tev_used = 0;
+    if (sweep_ms_total) *sweep_ms_total = b->t_ms;
+    if (sweep_launches) *sweep_launches = b->t_launches;
+    b->t_ms = 0.0;
+    b->t_launches = 0;
+    return GOM_OK;
+    GUARD_END
+}
+
+extern "C" int gom_batch_reseed(gom_batch *b, const uint64_t *seeds, void *stream) {
+    GUARD_BEGIN
+    if (!b || !seeds) return fail(GOM_E_ARG, "gom_batch_reseed: bad arguments");
+    for (int32_t i = 0; i < b->count; ++i)
+        if (b->subs[(size_t)i]->open_next >= 0)
+            return fail(GOM_E_STATE, "gom_batch_reseed: instance %d has an open generation", i);
+    hipStream_t st = (hipStream_t)stream;
+    // the previous upload of the table may still read it: wait before rewriting it
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t i = 0; i < b->count; ++i) {
+        gom_state *s = b->subs[(size_t)i];
+        s->seed = seeds[i];
+        HIP_TRY(enqueue_initial_population(s, st));
+        b->h_insts[(size_t)i].res.seed = seeds[i];
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_insts, b->h_insts.data(), sizeof(BatchInst) * b->h_insts.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    b->g_done = 0;
+    return GOM_OK;
+    GUARD_END
+}
+
 extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream,
                              gom_result *results, double *time_to_target_ms) {
     GUARD_BEGIN
@@ -1968,17 +2054,21 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
             int cur = -1;
             if (n > 0) {
                 cur = slot;
-                if (n == kChunk && b->use_graph) {
+                if (n == kChunk && b->use_graph && !b->timing) {
                     HIP_TRY(batch_chunk_graph(b, kChunk));
                     HIP_TRY(hipGraphLaunch(b->graph_exec, st));
                     HIP_TRY(hipMemcpyAsync(b->h_st + (size_t)cur * (size_t)b->count, b->d_snap,
                                            sizeof(DevState) * (size_t)b->count,
                                            hipMemcpyDeviceToHost, st));
                 } else {
-                    for (int32_t t = 0; t < n; ++t)
+                    for (int32_t t = 0; t < n; ++t) {
+                        KernelEvents ev;
+                        const int rc = batch_timing_events(b, &ev);
+                        if (rc) return rc;
                         HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk,
                                                   b->sweep_blocks, b->d_vblk, b->vblocks, b->lds,
-                                                  st));
+                                                  st, ev));
+                    }
                     HIP_TRY(batch_snapshot(b, cur, st));
                 }
                 issued += n;

@@ -302,8 +302,10 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
 // Allows k_batch_sweep blocks `lds` bytes of dynamic LDS (once per size; not a stream
 // operation, so it is done before a step is captured into a graph).
 hipError_t prepare_batch_step(size_t lds);
+// ev: optional events around the sweep launch.
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s);
+                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s,
+                             KernelEvents ev = {});
 hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s);
 // Pack every instance's DevState into out[count].
 hipError_t launch_batch_gather(const BatchInst *insts, int count, DevState *out, hipStream_t s);

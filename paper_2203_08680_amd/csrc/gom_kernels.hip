@@ -1941,11 +1941,12 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
 hipError_t prepare_batch_step(size_t lds) { return raise_lds_limit<k_batch_sweep>(lds); }
 
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s) {
+                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s,
+                             KernelEvents ev) {
     hipError_t pe = prepare_batch_step(lds);
     if (pe != hipSuccess) return pe;
-    hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_blocks), dim3(kResidentThreads), lds, s, insts,
-                       blk);
+    launch_timed(k_batch_sweep, dim3(sweep_blocks), dim3(kResidentThreads), lds, s, ev, insts,
+                 blk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(64), 0, s, insts);

@@ -34,7 +34,8 @@ EXPORTED = (
     "gom_ims_bytes",
     "gom_ims_run",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
-    "gom_batch_set_graph", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
+    "gom_batch_set_graph", "gom_batch_reseed", "gom_batch_timing_enable",
+    "gom_batch_timing_read", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
 )
 
@@ -129,6 +130,9 @@ def lib() -> C.CDLL:
                                      _vp, _P(_vp)]),
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
         "gom_batch_set_graph": (C.c_int, [_vp, C.c_int]),
+        "gom_batch_reseed": (C.c_int, [_vp, _vp, _vp]),
+        "gom_batch_timing_enable": (C.c_int, [_vp, C.c_int]),
+        "gom_batch_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
@@ -573,6 +577,25 @@ def gom_batch_run(b: GomBatch, max_generations: int, stream=None):
     out = [RunResult(r.generations, bool(r.reached), r.best, r.attempted, r.evaluated,
                      r.accepted) for r in res]
     return out, tt
+
+
+def gom_batch_reseed(b: GomBatch, seeds, stream=None) -> None:
+    """Fresh initial populations for every instance (seeds[b]); the step budget restarts."""
+    seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    if seeds.shape[0] != len(b.instances):
+        raise ValueError("gom_batch_reseed: one seed per instance")
+    _check(lib().gom_batch_reseed(b.handle, _ptr(seeds), _stream_handle(stream)))
+
+
+def gom_batch_timing_enable(b: GomBatch, enabled: bool = True) -> None:
+    _check(lib().gom_batch_timing_enable(b.handle, 1 if enabled else 0))
+
+
+def gom_batch_timing_read(b: GomBatch):
+    """(summed sweep milliseconds, timed sweep launches) since the previous read."""
+    ms, n = C.c_double(), _i64()
+    _check(lib().gom_batch_timing_read(b.handle, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def gom_batch_set_graph(b: GomBatch, enabled: bool = True) -> None:

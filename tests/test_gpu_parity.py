@@ -4,6 +4,7 @@ Every comparison is exact (integer genes, fitness, elitist and counters): the me
 floating point, so the bar is bit-exactness.  Each case prints its name first so a failing
 GPU step can be identified from the log.
 """
+import os
 import time
 
 import numpy as np
@@ -17,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 KEYS = ("genes", "fitness", "elite", "elite_fitness", "generation", "attempted", "evaluated",
         "accepted")
+WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
 def assert_same(a, b, where):
@@ -823,6 +825,37 @@ def test_batch_continues_across_calls(cuda):
                     f"instance {b}")
 
 
+def test_batch_reseed_and_timing(cuda):
+    """gom_batch_reseed after a run equals a fresh batch with the new seeds, also when the
+    steps run with per-launch timing events; the timing read reports one launch per step."""
+    print("case batch reseed and timing", flush=True)
+    items = workloads.batch_mix(count=6, seed=15, n_lo=60, n_hi=2000)
+    insts, targets = _batch_setup(items)
+    pops = [it.pop for it in items]
+    seeds_a = [it.seed for it in items]
+    seeds_b = [500 + it.seed for it in items]
+    b1 = gom.gom_batch_init(insts, pops, seeds_a, targets)
+    gom.gom_batch_run(b1, 8)
+    gom.gom_batch_reseed(b1, seeds_b)
+    gom.gom_batch_timing_enable(b1, True)
+    r1, _ = gom.gom_batch_run(b1, 10)
+    ms, launches = gom.gom_batch_timing_read(b1)
+    assert launches == max(r.generations for r in r1) and ms > 0
+    assert gom.gom_batch_timing_read(b1) == (0.0, 0)
+    b2 = gom.gom_batch_init(insts, pops, seeds_b, targets)
+    r2, _ = gom.gom_batch_run(b2, 10)
+    for b, it in enumerate(items):
+        a = gom.gom_state_read(b1.state(b))
+        assert_same(a, gom.gom_state_read(b2.state(b)), f"reseeded instance {b}")
+        assert (r1[b].generations, r1[b].best, r1[b].attempted, r1[b].evaluated) == \
+            (r2[b].generations, r2[b].best, r2[b].attempted, r2[b].evaluated)
+        if it.graph.n <= 400:
+            ptr, vars_ = oracle.fos(it.graph, it.fos)
+            ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=seeds_b[b])
+            ref.run(targets[b], 10)
+            assert_same(a, ref.state(), f"reseeded instance {b} vs oracle")
+
+
 def test_batch_graph_replays_equal_direct_launches(cuda):
     """gom_batch_run with its chunks replayed from a captured HIP graph against the same batch
     with direct launches: after every call (one replay each, with other device work and host
@@ -859,9 +892,10 @@ def test_batch_graph_replays_equal_direct_launches(cuda):
 
 def test_server_jobs_equal_solo_runs(cuda):
     """Jobs submitted at different times to a server whose arena holds only a few at once:
-    each job's result and final state hash equal those of its solo run, including a job too
-    large for the resident schedule (run beside the batched ones), generation limits that end
-    inside a chunk, and a job whose target is met at the start."""
+    each job's result and final state hash equal those of its solo run and of the oracle's
+    run of the same job, including a job too large for the resident schedule (run beside the
+    batched ones), generation limits that end inside a chunk, and a job whose target is met at
+    the start."""
     print("case server vs solo", flush=True)
     items = workloads.batch_mix(count=8, seed=13, n_lo=100, n_hi=3000)
     jobs = []
@@ -873,6 +907,9 @@ def test_server_jobs_equal_solo_runs(cuda):
     jobs.insert(3, (gom.Instance(big.n, big.u, big.v, big.w, 0), 64, 99, big.total_weight, 9))
     small = workloads.torus(6, 1, 3, seed=2)
     jobs.append((gom.Instance(small.n, small.u, small.v, small.w, 1), 8, 5, 0, 50))
+    graphs = [(it.graph, it.fos) for it in items]
+    graphs.insert(3, (big, 0))
+    graphs.append((small, 1))
     need = [gom.gom_state_bytes(x.graph, x.fos, p) for x, p, _, _, _ in jobs]
     # the job tables (about 25 kB for 8 jobs), the large job and the largest other one:
     # later jobs have to wait for memory
@@ -904,6 +941,16 @@ def test_server_jobs_equal_solo_runs(cuda):
                                                        r.attempted, r.evaluated, r.accepted), jid
         assert got["hash"] == gom.gom_state_hash(st), jid
         assert got["submit_ms"] <= got["admit_ms"] <= got["done_ms"]
+    # every served job's final state is also the oracle's run of the same job
+    for jid, (inst, pop, seed, tg, mg), (g, kind) in zip(ids, jobs, graphs):
+        ptr, vars_ = oracle.fos(g, kind)
+        ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, workers=WORKERS)
+        ran = ref.run(tg, mg)
+        s = ref.state(genes=False)
+        got = res[jid]
+        assert (got["generations"], got["best"], got["evaluated"], got["accepted"]) == \
+            (ran, s["elite_fitness"], s["evaluated"], s["accepted"]), f"job {jid} vs oracle"
+        assert got["hash"] == ref.hash(), f"job {jid}: hash differs from the oracle's"
 
 
 def _two_vertices():

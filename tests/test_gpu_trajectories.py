@@ -1,0 +1,141 @@
+"""GPU parity over whole trajectories: the configured workloads run for their full generation
+budgets (or, where the oracle needs minutes per generation, a stated prefix), with the state
+hash (every gene, fitness, elitist and counter) compared to the oracle's after EVERY
+generation and the full state compared at checkpoints.
+
+One oracle run per workload serves several GPU states in lockstep (one per launch schedule),
+since every schedule must follow the same trajectory.  The oracle spreads each colour class's
+solutions over host threads; its results do not depend on their number.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2203_08680_amd import gom
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("genes", "fitness", "elite", "elite_fitness", "generation", "attempted", "evaluated",
+        "accepted")
+WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def assert_same(a, b, where):
+    for key in KEYS:
+        x, y = np.asarray(a[key]), np.asarray(b[key])
+        if not np.array_equal(x, y):
+            if key == "genes":
+                bad = np.argwhere(x != y)
+                raise AssertionError(f"{where}: genes differ at {len(bad)} places, first "
+                                     f"(solution, vertex) {bad[:5].tolist()}")
+            raise AssertionError(f"{where}: {key} differs: gpu {x} oracle {y}")
+
+
+def _states(inst, pop, seed, scheds):
+    out = []
+    for sched, block in scheds:
+        st = inst.state(pop=pop, seed=seed)
+        gom.gom_state_set_schedule(st, sched)
+        if block:
+            gom.gom_state_set_block(st, block)
+        out.append((f"sched {sched} block {block}", st))
+    return out
+
+
+def _trajectory(label, g, kind, pop, seed, gens, scheds, full_every, target=None):
+    """Run the oracle and one GPU state per schedule for `gens` generations (or until the
+    target), comparing hashes after every generation and full states every `full_every`."""
+    print(f"case trajectory {label}: {gens} generations, schedules {scheds}", flush=True)
+    ptr, vars_ = oracle.fos(g, kind)
+    inst = gom.Instance(g.n, g.u, g.v, g.w, kind)
+    states = _states(inst, pop, seed, scheds)
+    ref = oracle.Run(g, ptr, vars_, pop=pop, seed=seed, workers=WORKERS)
+    h = ref.hash()
+    for name, st in states:
+        assert gom.gom_state_hash(st) == h, f"{label} {name}: initial state"
+    for gen in range(gens):
+        ref.generation()
+        h = ref.hash()
+        full = (gen + 1) % full_every == 0 or gen == gens - 1
+        b = ref.state(genes=full) if full else None
+        for name, st in states:
+            gom.gom_generation(st)
+            got = gom.gom_state_hash(st)
+            if got != h or full:
+                a = gom.gom_state_read(st, genes=full)
+                if b is None:
+                    b = ref.state(genes=False)
+                    a["genes"] = b["genes"] = None
+                assert_same(a, b, f"{label} {name} generation {gen}")
+                assert got == h, f"{label} {name} generation {gen}: hash differs"
+        if target is not None and ref.state(genes=False)["elite_fitness"] >= target:
+            print(f"  {label}: target reached after generation {gen}", flush=True)
+            break
+    return ref
+
+
+def test_c2_full_trajectory():
+    """100x100 torus, neighbourhood FOS, population 64, seed 1: the whole 500-generation run
+    of the benchmark workload, under the class-launch schedule with 64-thread blocks (the
+    benchmark's tuned choice), 256-thread blocks and the resident schedule."""
+    g = workloads.torus(100, 1, 100, seed=2)
+    scheds = [(gom.GOM_SCHED_CLASS_LAUNCH, 64), (gom.GOM_SCHED_CLASS_LAUNCH, 256),
+              (gom.GOM_SCHED_RESIDENT, 0)]
+    _trajectory("torus100 nbhd p64 seed 1", g, 1, 64, 1, 500, scheds, 50,
+                target=g.total_weight)
+
+
+def test_c2_batched_trajectory_checkpoints():
+    """The same run and two more seeds as one lockstep batch: every instance's hash equals
+    the oracle's at generations 50, 100, ..., 500."""
+    print("case batched torus100 nbhd p64 seeds 1-3", flush=True)
+    g = workloads.torus(100, 1, 100, seed=2)
+    ptr, vars_ = oracle.fos(g, 1)
+    inst = gom.Instance(g.n, g.u, g.v, g.w, 1)
+    seeds = [1, 2, 3]
+    b = gom.gom_batch_init([inst] * 3, [64] * 3, seeds, [g.total_weight] * 3)
+    refs = [oracle.Run(g, ptr, vars_, pop=64, seed=s, workers=WORKERS) for s in seeds]
+    for stop in range(50, 501, 50):
+        gom.gom_batch_run(b, stop)
+        for k, ref in enumerate(refs):
+            ref.run(g.total_weight, stop - ref.state(genes=False)["generation"])
+            assert gom.gom_state_hash(b.state(k)) == ref.hash(), (seeds[k], stop)
+    for k, ref in enumerate(refs):
+        assert_same(gom.gom_state_read(b.state(k)), ref.state(), f"batched seed {seeds[k]}")
+
+
+def test_c3_d3_univariate_200_generations():
+    """Random 3-regular graph, n = 10^5, weights +-U{1..50}, univariate FOS, population 32:
+    all 200 generations under class launch, the bit-sliced sweep and the resident schedule."""
+    g = workloads.configuration_model(100_000, 3, seed=3, weights="signed50")
+    scheds = [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_BITSLICED, 0),
+              (gom.GOM_SCHED_RESIDENT, 0)]
+    _trajectory("cm100k d3 uni p32", g, 0, 32, 1, 200, scheds, 50)
+
+
+@pytest.mark.parametrize("d,gens", [(3, 20), (6, 20), (12, 5)])
+def test_c3_neighbourhood_prefix(d, gens):
+    """Random d-regular graphs, n = 10^5, neighbourhood FOS, population 32: the first 20
+    generations (degree 3 and 6) or 5 (degree 12, about 270 colour classes and 4 s of oracle
+    time per generation) under class launch and the resident schedule."""
+    g = workloads.configuration_model(100_000, d, seed=3, weights="signed50")
+    scheds = [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_RESIDENT, 0)]
+    _trajectory(f"cm100k d{d} nbhd p32", g, 1, 32, 1, gens, scheds, 10)
+
+
+def test_torus1000_univariate_5_generations():
+    """The 10^6-vertex torus, univariate FOS, population 64: five generations under the
+    bit-sliced sweep and class launch, hashes every generation, full states at the end."""
+    g = workloads.torus(1000, 1, 100, seed=7)
+    scheds = [(gom.GOM_SCHED_BITSLICED, 0), (gom.GOM_SCHED_CLASS_LAUNCH, 0)]
+    _trajectory("torus1000 uni p64", g, 0, 64, 1, 5, scheds, 5)
+
+
+def test_torus1000_neighbourhood_2_generations():
+    """The 10^6-vertex torus, neighbourhood FOS, population 64, class launch: two
+    generations."""
+    g = workloads.torus(1000, 1, 100, seed=7)
+    _trajectory("torus1000 nbhd p64", g, 1, 64, 1, 2, [(gom.GOM_SCHED_CLASS_LAUNCH, 0)], 2)
