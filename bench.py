@@ -230,6 +230,13 @@ def run_batch_mode(args, torch, gom):
     batch = gom.gom_batch_init(insts, pops, step_seeds(items, 0), targets)
     gom.gom_batch_set_graph(batch, args.batch_graph == "on")
     log(f"batch states: {time.perf_counter() - t0:.1f} s")
+    if args.batch_narrow is None:
+        t0 = time.perf_counter()
+        narrow = gom.gom_batch_autotune(batch, 2)
+        log(f"batch autotune: threshold {narrow} in {time.perf_counter() - t0:.1f} s")
+    else:
+        gom.gom_batch_set_narrow(batch, args.batch_narrow)
+    narrow, sweep_launches = gom.gom_batch_get_narrow(batch)
 
     def one_step(k):
         gom.gom_batch_reseed(batch, step_seeds(items, k))
@@ -329,6 +336,8 @@ def run_batch_mode(args, torch, gom):
                    "pop_range": [16, 64], "max_generations": max_gens,
                    "fos": "univariate and neighbourhood alternating in pairs",
                    "mode": "batched", "schedule": "batched_resident",
+                   "narrow_blocks_max_n": narrow, "sweep_launches_per_step": sweep_launches,
+                   "block_sizes": "autotuned" if args.batch_narrow is None else "fixed",
                    "generation_steps": ("hip_graph_chunks_of_4" if args.batch_graph == "on"
                                         else "direct_launches"),
                    "step": "fresh populations (new seeds) and a batched run of the whole mix "
@@ -542,6 +551,10 @@ def main():
                          "(ROUNDS rounds of FLIPS drawn flips per solution)")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain mode: skip the comparison with the same seeds run as one batch")
+    ap.add_argument("--batch-narrow", type=int, default=None,
+                    help="batched mode: instances with at most this many vertices sweep with "
+                         "256-thread blocks, larger ones 1024 (-1: all 1024; default: "
+                         "autotuned)")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
                     help="batched steps as captured HIP graph chunks (default) or direct launches")
     ap.add_argument("--ims", action="store_true",

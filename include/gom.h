@@ -365,9 +365,10 @@ void gom_state_free(gom_state *s);
 /*
  * Batches: many independent instances (each its own graph, FOS, population and seed) run in
  * lockstep, one generation step for all of them per group of launches:
- *   - a sweep launch with one workgroup per (instance, solution) running every colour class
- *     of that instance (the resident schedule; each workgroup draws its instance's class order
- *     from the instance's seed and generation);
+ *   - sweep launches (one per group of instances with the same block size and blocks per
+ *     compute unit, see gom_batch_set_narrow) with one workgroup per (instance, solution)
+ *     running every colour class of that instance (the resident schedule; each workgroup
+ *     draws its instance's class order from the instance's seed and generation);
  *   - a finalize launch with one wave per instance;
  *   - a vertex-pass launch over all instances' vertices.
  * Every instance follows exactly the trajectory it has when run alone with the same seed:
@@ -432,6 +433,30 @@ int gom_batch_reseed(gom_batch *b, const uint64_t *seeds, void *stream);
  */
 int gom_batch_timing_enable(gom_batch *b, int enabled);
 int gom_batch_timing_read(gom_batch *b, double *sweep_ms_total, int64_t *sweep_launches);
+
+/*
+ * Block sizes of the batched sweep.  An instance with at most narrow_max_n vertices sweeps
+ * with 256-thread blocks, a larger one with 1024-thread blocks; it keeps a copy of the
+ * population words in LDS when that does not lower the number of its blocks a compute unit
+ * holds.  Instances with the same block size and blocks per compute unit share one sweep
+ * launch per step (longest blocks first).  Results do not depend on the choice.  Default
+ * 16384.  Synchronous (uploads the block map).
+ * gom_batch_get_narrow returns the threshold and the number of sweep launches per step.
+ * Errors: GOM_E_ARG, GOM_E_RANGE (an instance's LDS does not fit), GOM_E_DEVICE.
+ */
+int gom_batch_set_narrow(gom_batch *b, int64_t narrow_max_n, void *stream);
+int gom_batch_get_narrow(const gom_batch *b, int64_t *narrow_max_n, int32_t *launches);
+
+/*
+ * Autotuner of the block-size threshold: runs trial_steps generation steps under each
+ * candidate threshold (all 1024-thread blocks, 2048, 8192, 16384, 32768 vertices, all
+ * 256-thread blocks; candidates that give the same assignment once), timed with HIP events on
+ * `stream`, in two interleaved rounds, and keeps the fastest.  The trial steps are ordinary
+ * generation steps of the run (they count against gom_batch_run's step budget).
+ * Synchronous.  chosen (or NULL): the threshold kept.
+ * Errors: GOM_E_ARG, GOM_E_STATE (an open generation), GOM_E_RANGE, GOM_E_DEVICE.
+ */
+int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *stream, int64_t *chosen);
 
 /* Borrowed handle of instance `index` (for gom_state_read); valid until gom_batch_free. */
 int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <map>
 #include <new>
 #include <queue>
@@ -358,6 +359,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
 }  // namespace
 
 struct gom_state {
+    bool h_st_pinned = true;            // h_st from hipHostMalloc (else new[])
     int32_t n = 0, N = 0, n_sets = 0, k = 0, max_class = 0;
     int64_t m = 0;
     uint64_t seed = 0;
@@ -1072,10 +1074,11 @@ static int auto_schedule(const gom_state *s) {
     return GOM_SCHED_CLASS_LAUNCH;
 }
 
-extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
-                              int neutral_rule, int class_order_kind, void *dev_arena,
-                              size_t arena_bytes, void *stream, gom_state **out) {
-    GUARD_BEGIN
+// pinned_host: the run-scalar read-back buffer is pinned host memory (hipHostMalloc); else
+// ordinary host memory, so that the state's creation allocates nothing through HIP.
+static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
+                      int neutral_rule, int class_order_kind, void *dev_arena, size_t arena_bytes,
+                      void *stream, bool pinned_host, gom_state **out) {
     int rc = check_state_args(g, f, pop);
     if (rc) return rc;
     if (!dev_arena || !out) return fail(GOM_E_ARG, "gom_state_init: null arena or output");
@@ -1150,7 +1153,13 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     auto h2d = [&](void *dst, const void *src, size_t bytes) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
     };
-    hipError_t e = hipHostMalloc((void **)&s->h_st, 2 * sizeof(DevState), hipHostMallocDefault);
+    hipError_t e = hipSuccess;
+    if (pinned_host) {
+        e = hipHostMalloc((void **)&s->h_st, 2 * sizeof(DevState), hipHostMallocDefault);
+    } else {
+        s->h_st = new DevState[2];
+        s->h_st_pinned = false;
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->chunk_ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->chunk_ev[1], hipEventDisableTiming);
     if (e == hipSuccess) e = h2d(s->d_eu, g->eu.data(), sizeof(int32_t) * (size_t)g->m);
@@ -1191,6 +1200,14 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
         return cleanup(fail(GOM_E_DEVICE, "gom_state_init: %s", hipGetErrorString(e)));
     *out = s;
     return GOM_OK;
+}
+
+extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
+                              int neutral_rule, int class_order_kind, void *dev_arena,
+                              size_t arena_bytes, void *stream, gom_state **out) {
+    GUARD_BEGIN
+    return state_init(g, f, pop, seed, neutral_rule, class_order_kind, dev_arena, arena_bytes,
+                      stream, true, out);
     GUARD_END
 }
 
@@ -1727,7 +1744,10 @@ extern "C" void gom_state_free(gom_state *s) {
     for (hipEvent_t e : s->tev) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->chunk_ev)
         if (e) (void)hipEventDestroy(e);
-    if (s->h_st) (void)hipHostFree(s->h_st);
+    if (s->h_st) {
+        if (s->h_st_pinned) (void)hipHostFree(s->h_st);
+        else delete[] s->h_st;
+    }
     delete s;
 }
 
@@ -1742,8 +1762,10 @@ struct gom_batch {
     int2 *d_blk = nullptr;
     int32_t *d_vblk = nullptr;
     DevState *d_snap = nullptr;         // packed copy of the instances' run scalars
-    int sweep_blocks = 0, vblocks = 0;
-    size_t lds = 0;                     // dynamic LDS bytes of a sweep block
+    int vblocks = 0;
+    std::vector<BatchLaunch> groups;    // sweep launch groups of the current block sizes
+    int64_t narrow_max_n = -1;          // instances with n <= this run 256-thread blocks
+    size_t lds_max = 0;                 // LDS per CU of the device
     DevState *h_st = nullptr;           // pinned, 2 x count
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     double wall_khz = 0.0;
@@ -1824,6 +1846,82 @@ extern "C" void gom_batch_free(gom_batch *b) {
     delete b;
 }
 
+// Default block-size threshold of the batched sweep: instances with at most this many vertices
+// run 256-thread blocks, larger ones 1024.
+constexpr int64_t kBatchNarrowDefault = 16384;
+
+// Sweep blocks of one CU that the LDS of a block allows (at most 8).
+static int blocks_per_cu(size_t lds, size_t lds_max) {
+    return (int)std::min<size_t>(8, lds ? lds_max / lds : 8);
+}
+
+// Block sizes, P copies and launch groups for the threshold `narrow_max_n`: an instance with
+// n <= narrow_max_n sweeps with 256-thread blocks, else 1024.  It keeps a copy of P in LDS
+// when that does not lower the blocks a CU can hold.  Instances with equal (threads, blocks
+// per CU) form one launch; within it, instances with more classes and vertices per thread
+// (longer blocks) come first.  Uploads the instance table and the block map (synchronous)
+// and drops a captured graph.
+static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
+    struct Item {
+        int threads, occ;
+        double cost;
+        int32_t inst;
+        size_t lds;
+    };
+    std::vector<Item> items;
+    items.reserve((size_t)b->count);
+    for (int32_t i = 0; i < b->count; ++i) {
+        const gom_state *s = b->subs[(size_t)i];
+        const int T = (int64_t)s->n <= narrow_max_n ? 256 : 1024;
+        const size_t l0 = kBatchOrderBytes + resident_lds_bytes(s->n, false, T);
+        const size_t l1 = kBatchOrderBytes + resident_lds_bytes(s->n, true, T);
+        if (l0 > b->lds_max)
+            return fail(GOM_E_RANGE, "batch: instance %d needs %zu bytes of LDS", i, l0);
+        const bool plds = l1 <= b->lds_max &&
+                          blocks_per_cu(l1, b->lds_max) == blocks_per_cu(l0, b->lds_max);
+        b->h_insts[(size_t)i].plds = plds ? 1 : 0;
+        const size_t l = plds ? l1 : l0;
+        const double cost = (double)s->k + (double)s->n_sets / T;
+        items.push_back(Item{T, blocks_per_cu(l, b->lds_max), cost, i, l});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
+        if (x.threads != y.threads) return x.threads > y.threads;
+        if (x.occ != y.occ) return x.occ < y.occ;
+        return x.cost > y.cost;
+    });
+    std::vector<int2> blk;
+    std::vector<BatchLaunch> groups;
+    for (size_t q = 0; q < items.size(); ++q) {
+        const Item &it = items[q];
+        if (groups.empty() || q == 0 || it.threads != items[q - 1].threads ||
+            it.occ != items[q - 1].occ)
+            groups.push_back(BatchLaunch{(int)blk.size(), 0, it.threads, 0});
+        BatchLaunch &G = groups.back();
+        const gom_state *s = b->subs[(size_t)it.inst];
+        for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2(it.inst, i));
+        G.count += s->N;
+        G.lds = std::max(G.lds, it.lds);
+    }
+    HIP_TRY(hipStreamSynchronize(st));  // nothing in flight reads the tables
+    HIP_TRY(hipMemcpyAsync(b->d_insts, b->h_insts.data(), sizeof(BatchInst) * b->h_insts.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->d_blk, blk.data(), sizeof(int2) * blk.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(prepare_batch_step(groups.data(), (int)groups.size()));
+    if (b->graph_exec) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->groups = std::move(groups);
+    b->narrow_max_n = narrow_max_n;
+    return GOM_OK;
+}
+
 extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
                               const gom_fos *const *fos, const int32_t *pops,
                               const uint64_t *seeds, const int64_t *targets, int neutral_rule,
@@ -1862,32 +1960,26 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
         if (!s->resident_ok || need > s->lds_max)
             return cleanup(fail(GOM_E_RANGE, "gom_batch_init: instance %d does not fit the "
                                 "resident schedule (n = %d, %d classes)", b, s->n, s->k));
-        const bool plds = kBatchOrderBytes + resident_lds_bytes(s->n, true) <= s->lds_max;
+        bt->lds_max = s->lds_max;
         BatchInst &I = insts[(size_t)b];
-        I.plds = plds ? 1 : 0;
+        I.plds = 0;  // set with the block sizes (batch_regroup)
         I.res = resident_ctx(s, targets[b]);
         I.epi = epilogue_args(s, targets[b], true);
         I.kind = s->univariate ? 0 : 1;
         I.order_fixed = s->order == GOM_ORDER_FIXED;
         I.vblock0 = (int32_t)vblk.size();
-        for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2(b, i));
         for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back(b);
-        bt->lds = std::max(bt->lds, kBatchOrderBytes + resident_lds_bytes(s->n, plds));
     }
     bt->d_insts = (BatchInst *)(arena + B.insts);
     bt->d_blk = (int2 *)(arena + B.blk);
     bt->d_vblk = (int32_t *)(arena + B.vblk);
     bt->d_snap = (DevState *)(arena + B.snap);
-    bt->sweep_blocks = B.sweep_blocks;
     bt->vblocks = B.vblocks;
     int khz = 0, dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
     if (e == hipSuccess)
         e = hipMemcpyAsync(bt->d_insts, insts.data(), sizeof(BatchInst) * insts.size(),
-                           hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(bt->d_blk, blk.data(), sizeof(int2) * blk.size(),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(bt->d_vblk, vblk.data(), sizeof(int32_t) * vblk.size(),
@@ -1902,6 +1994,8 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
         return cleanup(fail(GOM_E_DEVICE, "gom_batch_init: %s", hipGetErrorString(e)));
     bt->wall_khz = (double)khz;
     bt->h_insts = std::move(insts);
+    rc = batch_regroup(bt, kBatchNarrowDefault, st);
+    if (rc) return cleanup(rc);
     *out = bt;
     return GOM_OK;
     GUARD_END
@@ -1920,15 +2014,15 @@ static hipError_t batch_snapshot(gom_batch *b, int slot, hipStream_t st) {
 // One chunk of generation steps and the gather of the run scalars, captured once as a graph.
 static hipError_t batch_chunk_graph(gom_batch *b, int32_t steps) {
     if (b->graph_exec) return hipSuccess;
-    hipError_t e = prepare_batch_step(b->lds);
+    hipError_t e = prepare_batch_step(b->groups.data(), (int)b->groups.size());
     if (e == hipSuccess && !b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int32_t t = 0; t < steps && le == hipSuccess; ++t)
-        le = launch_batch_step(b->d_insts, b->count, b->d_blk, b->sweep_blocks, b->d_vblk,
-                               b->vblocks, b->lds, b->cap);
+        le = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
+                               (int)b->groups.size(), b->d_vblk, b->vblocks, b->cap);
     if (le == hipSuccess) le = launch_batch_gather(b->d_insts, b->count, b->d_snap, b->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);  // always ends the capture
@@ -2066,8 +2160,8 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
                         const int rc = batch_timing_events(b, &ev);
                         if (rc) return rc;
                         HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk,
-                                                  b->sweep_blocks, b->d_vblk, b->vblocks, b->lds,
-                                                  st, ev));
+                                                  b->groups.data(), (int)b->groups.size(),
+                                                  b->d_vblk, b->vblocks, st, ev));
                     }
                     HIP_TRY(batch_snapshot(b, cur, st));
                 }
@@ -2113,6 +2207,88 @@ extern "C" int gom_batch_set_graph(gom_batch *b, int enabled) {
     if (!b) return fail(GOM_E_ARG, "gom_batch_set_graph: null batch");
     b->use_graph = enabled != 0;
     return GOM_OK;
+}
+
+extern "C" int gom_batch_set_narrow(gom_batch *b, int64_t narrow_max_n, void *stream) {
+    GUARD_BEGIN
+    if (!b) return fail(GOM_E_ARG, "gom_batch_set_narrow: null batch");
+    return batch_regroup(b, narrow_max_n, (hipStream_t)stream);
+    GUARD_END
+}
+
+extern "C" int gom_batch_get_narrow(const gom_batch *b, int64_t *narrow_max_n,
+                                    int32_t *launches) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_get_narrow: null batch");
+    if (narrow_max_n) *narrow_max_n = b->narrow_max_n;
+    if (launches) *launches = (int32_t)b->groups.size();
+    return GOM_OK;
+}
+
+extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *stream,
+                                  int64_t *chosen) {
+    GUARD_BEGIN
+    if (!b || trial_steps < 1) return fail(GOM_E_ARG, "gom_batch_autotune: bad arguments");
+    for (int32_t i = 0; i < b->count; ++i)
+        if (b->subs[(size_t)i]->open_next >= 0)
+            return fail(GOM_E_STATE, "gom_batch_autotune: instance %d has an open generation",
+                        i);
+    hipStream_t st = (hipStream_t)stream;
+    // thresholds that give distinct block-size assignments
+    std::vector<int64_t> sizes;
+    for (const gom_state *s : b->subs) sizes.push_back(s->n);
+    std::sort(sizes.begin(), sizes.end());
+    std::vector<int64_t> cands;
+    for (int64_t c : {(int64_t)-1, (int64_t)2048, (int64_t)8192, (int64_t)16384,
+                      (int64_t)32768, (int64_t)1 << 40}) {
+        const size_t narrow = (size_t)(std::upper_bound(sizes.begin(), sizes.end(), c) -
+                                       sizes.begin());
+        bool dup = false;
+        for (int64_t d : cands)
+            dup |= (size_t)(std::upper_bound(sizes.begin(), sizes.end(), d) - sizes.begin()) ==
+                   narrow;
+        if (!dup) cands.push_back(c);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GOM_E_DEVICE, "gom_batch_autotune: %s", hipGetErrorString(he));
+    }
+    std::vector<double> total(cands.size(), 0.0);
+    int rc = GOM_OK;
+    hipError_t e = hipSuccess;
+    for (int round = 0; round < 2 && rc == GOM_OK && e == hipSuccess; ++round) {
+        for (size_t q = 0; q < cands.size() && rc == GOM_OK && e == hipSuccess; ++q) {
+            rc = batch_regroup(b, cands[q], st);
+            if (rc) break;
+            e = hipEventRecord(e0, st);
+            for (int32_t t = 0; t < trial_steps && e == hipSuccess; ++t)
+                e = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
+                                      (int)b->groups.size(), b->d_vblk, b->vblocks, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            total[q] += ms;
+            b->g_done += trial_steps;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (e != hipSuccess)
+        return fail(GOM_E_DEVICE, "gom_batch_autotune: %s", hipGetErrorString(e));
+    const size_t best = (size_t)(std::min_element(total.begin(), total.end()) - total.begin());
+    rc = batch_regroup(b, cands[best], st);
+    if (rc) return rc;
+    // the trial steps advanced the instances: keep the host's generation counts in step
+    HIP_TRY(batch_snapshot(b, 0, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t i = 0; i < b->count; ++i) b->subs[(size_t)i]->g_host = b->h_st[i].generation;
+    if (chosen) *chosen = cands[best];
+    return GOM_OK;
+    GUARD_END
 }
 
 extern "C" int gom_batch_state(gom_batch *b, int32_t index, gom_state **state) {

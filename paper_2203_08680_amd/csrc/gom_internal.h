@@ -296,16 +296,21 @@ constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
 // plds: keep a copy of P in LDS (needs resident_lds_bytes(n, true) of LDS).
 hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hipStream_t s,
                                  KernelEvents ev = {});
-// Batched generation step over `count` instances: sweep grid = sum of populations (blk[b] =
-// {instance, solution}), vertex-pass grid = vblocks (vblk[b] = instance); lds = dynamic LDS
-// bytes of a sweep block (kBatchOrderBytes + the largest instance's resident bytes).
-// Allows k_batch_sweep blocks `lds` bytes of dynamic LDS (once per size; not a stream
+// Batched generation step over `count` instances.  The sweep runs as one launch per group of
+// blocks (blk[first .. first + count) = {instance, solution}) with `threads` threads (256 or
+// 1024) and `lds` dynamic LDS bytes per block; then the finalize (one wave per instance) and
+// the vertex pass (vblocks blocks, vblk[b] = instance).  ev: optional events, the start
+// recorded by the first sweep launch and the stop by the last.
+struct BatchLaunch {
+    int first, count, threads;
+    size_t lds;
+};
+// Allows each group's k_batch_sweep blocks their dynamic LDS (once per size; not a stream
 // operation, so it is done before a step is captured into a graph).
-hipError_t prepare_batch_step(size_t lds);
-// ev: optional events around the sweep launch.
-hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s,
-                             KernelEvents ev = {});
+hipError_t prepare_batch_step(const BatchLaunch *groups, int n_groups);
+hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
+                             const BatchLaunch *groups, int n_groups, const int32_t *vblk,
+                             int vblocks, hipStream_t s, KernelEvents ev = {});
 hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s);
 // Pack every instance's DevState into out[count].
 hipError_t launch_batch_gather(const BatchInst *insts, int count, DevState *out, hipStream_t s);
@@ -316,6 +321,6 @@ hipError_t launch_state_hash(const uint64_t *X, const uint64_t *E, int n, int N,
 // Generation end: finalize (one block) then the vertex pass.
 hipError_t launch_epilogue(const EpilogueArgs &a, hipStream_t s);
 // Dynamic LDS bytes of the resident sweep for n vertices, with or without the P copy.
-size_t resident_lds_bytes(int n, bool plds);
+size_t resident_lds_bytes(int n, bool plds, int threads = kResidentThreads);
 
 }  // namespace gom

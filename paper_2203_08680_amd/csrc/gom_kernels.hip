@@ -1355,7 +1355,9 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
 // barrier separates classes.  At the end the block packs O_i into a bit row (one ballot per
 // 64 vertices) and adds its fitness change and counts to its stripe.
 // ------------------------------------------------------------------------------------------
-constexpr int kResRngBytes = kResidentChunkSlots * 16;
+// LDS of a resident block of T threads: T Philox results (16 bytes each), the reduction
+// area, the optional P copy, then the offspring bytes.
+__host__ __device__ constexpr int res_rng_bytes(int T) { return T * 16; }
 constexpr int kResRedBytes = 272;  // 16 wave sums (int64), 32 counts, 2 flags, padding
 
 // LDS bytes of the P copy (16-byte multiple).
@@ -1372,9 +1374,10 @@ struct LdsCommit {
 
 // PLDS: the block also copies the population words P into LDS (8 bytes per vertex), so the
 // donors' genes are read from LDS instead of global memory.
-template <int KIND, bool PLDS>
+template <int KIND, bool PLDS, int T>
 __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16_t *order,
                                               int gen, int i, uint8_t *lds) {
+    constexpr int kResRngBytes = res_rng_bytes(T);
     const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
     if (a.st->elite_fitness >= a.target) return;
     uint32_t(*rng)[4] = reinterpret_cast<uint32_t(*)[4]>(lds);
@@ -1389,7 +1392,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
     const uint64_t cand = popm & ~(1ull << i);
     const bool neutral_ok = a.always || bit_of(wave_or64(mism), (uint32_t)i);
 
-    for (int v = tid; v < a.n; v += kResidentThreads) {
+    for (int v = tid; v < a.n; v += T) {
         const uint64_t w = a.P[v];
         if constexpr (PLDS) pl[v] = w;
         ob[v] = (uint8_t)bit_of(w, (uint32_t)i);
@@ -1408,8 +1411,8 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
         auto record = [&](int p) {
             return AosRec{cr.y ? a.recs + cr.x + p * cr.y : a.recs + a.roff[cbase + p]};
         };
-        for (int base = 0; base < csize; base += 8 * kResidentChunkSlots) {
-            const int span = min(csize - base, 8 * kResidentChunkSlots);
+        for (int base = 0; base < csize; base += 8 * T) {
+            const int span = min(csize - base, 8 * T);
             // issue this thread's first record of the round before the draws and the barrier
             AosRec R = record(base + (tid < span ? tid : 0));
             Head hd = load_head<KIND>(R);
@@ -1424,7 +1427,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
                 }
                 __syncthreads();
             }
-            for (int q = tid; q < span; q += kResidentThreads) {
+            for (int q = tid; q < span; q += T) {
                 uint32_t h = 0;
                 if constexpr (KIND != 0) {
                     const int f = q & 7;
@@ -1459,7 +1462,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
             const int cbase = a.class_ptr[c];
             const int csize = a.class_ptr[c + 1] - cbase;
             const int2 cr = a.class_rec[c];
-            for (int q = tid; q < csize; q += kResidentThreads) {
+            for (int q = tid; q < csize; q += T) {
                 const AosRec R{cr.y ? a.recs + cr.x + q * cr.y : a.recs + a.roff[cbase + q]};
                 const Head hd = load_head<KIND>(R);
                 const PairOut r = gom_pair<KIND>(R, hd, ew, bits, commit, ~0ull, 0u, neutral_ok);
@@ -1473,7 +1476,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
         }
     }
 
-    for (int v0 = wave * 64; v0 < a.n; v0 += kResidentThreads) {
+    for (int v0 = wave * 64; v0 < a.n; v0 += T) {
         const int v = v0 + lane;
         const uint64_t word = ballot64(v < a.n && ob[v] != 0);
         if (lane == 0) a.rows[(size_t)i * a.row_words + (v0 >> 6)] = word;
@@ -1489,7 +1492,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
     if (tid == 0) {
         int64_t sf = 0;
         uint32_t se = 0, sa = 0;
-        for (int w = 0; w < kResidentThreads / 64; ++w) {
+        for (int w = 0; w < T / 64; ++w) {
             sf += redf[w];
             se += redc[w];
             sa += redc[16 + w];
@@ -1506,7 +1509,7 @@ __device__ __forceinline__ void resident_body(const ResidentCtx &a, const uint16
 template <int KIND, bool PLDS>
 __global__ __launch_bounds__(kResidentThreads) void k_resident_sweep(ResidentArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    resident_body<KIND, PLDS>(a.c, a.order, a.c.gen, blockIdx.x, lds);
+    resident_body<KIND, PLDS, kResidentThreads>(a.c, a.order, a.c.gen, blockIdx.x, lds);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1671,8 +1674,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_vertex_pass(EpilogueArgs a) {
 // the draws in parallel, the swaps by one thread), then runs the resident sweep.  The
 // finalize and vertex-pass blocks find their instance through the block maps.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kResidentThreads) void k_batch_sweep(const BatchInst *insts,
-                                                                 const int2 *blk) {
+template <int T>
+__global__ __launch_bounds__(T) void k_batch_sweep(const BatchInst *insts, const int2 *blk) {
     extern __shared__ __align__(16) uint8_t lds_all[];
     uint16_t *order = reinterpret_cast<uint16_t *>(lds_all);
     uint16_t *draw = order + kResidentMaxClasses;
@@ -1682,7 +1685,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_batch_sweep(const BatchIns
     if (a.st->elite_fitness >= a.target) return;
     const int gen = a.st->generation;
     const bool fixed = I->order_fixed != 0;
-    for (int t = threadIdx.x; t < a.k; t += kResidentThreads) {
+    for (int t = threadIdx.x; t < a.k; t += T) {
         order[t] = (uint16_t)t;
         if (!fixed && t >= 1) {
             const U32x4 r = philox(a.seed, (uint32_t)gen, kOrderStream, (uint32_t)t, 0u);
@@ -1700,14 +1703,14 @@ __global__ __launch_bounds__(kResidentThreads) void k_batch_sweep(const BatchIns
     uint8_t *lds = lds_all + kBatchOrderBytes;
     if (I->kind == 0) {
         if (I->plds)
-            resident_body<0, true>(a, order, gen, bi.y, lds);
+            resident_body<0, true, T>(a, order, gen, bi.y, lds);
         else
-            resident_body<0, false>(a, order, gen, bi.y, lds);
+            resident_body<0, false, T>(a, order, gen, bi.y, lds);
     } else {
         if (I->plds)
-            resident_body<1, true>(a, order, gen, bi.y, lds);
+            resident_body<1, true, T>(a, order, gen, bi.y, lds);
         else
-            resident_body<1, false>(a, order, gen, bi.y, lds);
+            resident_body<1, false, T>(a, order, gen, bi.y, lds);
     }
 }
 
@@ -1803,7 +1806,7 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
 template <class K, class... Args>
 static void launch_timed(K kernel, dim3 gd, dim3 bd, size_t lds, hipStream_t s, KernelEvents ev,
                          Args... args) {
-    if (ev.start)
+    if (ev.start || ev.stop)
         hipExtLaunchKernelGGL(kernel, gd, bd, (uint32_t)lds, s, ev.start, ev.stop, 0u, args...);
     else
         hipLaunchKernelGGL(kernel, gd, bd, lds, s, args...);
@@ -1916,14 +1919,14 @@ hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow
     return hipGetLastError();
 }
 
-size_t resident_lds_bytes(int n, bool plds) {
-    return (size_t)kResRngBytes + kResRedBytes + (plds ? resident_words_bytes(n) : 0) +
-           (((size_t)n + 15) & ~(size_t)15);
+size_t resident_lds_bytes(int n, bool plds, int threads) {
+    return (size_t)res_rng_bytes(threads) + kResRedBytes +
+           (plds ? resident_words_bytes(n) : 0) + (((size_t)n + 15) & ~(size_t)15);
 }
 
 template <int KIND, bool PLDS>
 static hipError_t launch_resident_t(const ResidentArgs &a, hipStream_t s, KernelEvents ev) {
-    const size_t lds = resident_lds_bytes(a.c.n, PLDS);
+    const size_t lds = resident_lds_bytes(a.c.n, PLDS, kResidentThreads);
     hipError_t e = raise_lds_limit<k_resident_sweep<KIND, PLDS>>(lds);
     if (e != hipSuccess) return e;
     launch_timed(k_resident_sweep<KIND, PLDS>, dim3(a.c.N), dim3(kResidentThreads), lds, s, ev,
@@ -1938,17 +1941,37 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
     return plds ? launch_resident_t<1, true>(a, s, ev) : launch_resident_t<1, false>(a, s, ev);
 }
 
-hipError_t prepare_batch_step(size_t lds) { return raise_lds_limit<k_batch_sweep>(lds); }
+hipError_t prepare_batch_step(const BatchLaunch *groups, int n_groups) {
+    for (int q = 0; q < n_groups; ++q) {
+        const hipError_t e = groups[q].threads == 256
+                                 ? raise_lds_limit<k_batch_sweep<256>>(groups[q].lds)
+                                 : raise_lds_limit<k_batch_sweep<1024>>(groups[q].lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
-hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk, int sweep_blocks,
-                             const int32_t *vblk, int vblocks, size_t lds, hipStream_t s,
-                             KernelEvents ev) {
-    hipError_t pe = prepare_batch_step(lds);
-    if (pe != hipSuccess) return pe;
-    launch_timed(k_batch_sweep, dim3(sweep_blocks), dim3(kResidentThreads), lds, s, ev, insts,
-                 blk);
-    hipError_t e = hipGetLastError();
+hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
+                             const BatchLaunch *groups, int n_groups, const int32_t *vblk,
+                             int vblocks, hipStream_t s, KernelEvents ev) {
+    hipError_t e = prepare_batch_step(groups, n_groups);
     if (e != hipSuccess) return e;
+    for (int q = 0; q < n_groups; ++q) {
+        const BatchLaunch &G = groups[q];
+        if (G.threads != 256 && G.threads != 1024) return hipErrorInvalidValue;
+        // the step's timing spans the first sweep launch's start to the last one's end
+        KernelEvents gev;
+        gev.start = q == 0 ? ev.start : nullptr;
+        gev.stop = q == n_groups - 1 ? ev.stop : nullptr;
+        if (G.threads == 256)
+            launch_timed(k_batch_sweep<256>, dim3(G.count), dim3(256), G.lds, s, gev, insts,
+                         blk + G.first);
+        else
+            launch_timed(k_batch_sweep<1024>, dim3(G.count), dim3(1024), G.lds, s, gev, insts,
+                         blk + G.first);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(64), 0, s, insts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -35,7 +35,8 @@ EXPORTED = (
     "gom_ims_run",
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
     "gom_batch_set_graph", "gom_batch_reseed", "gom_batch_timing_enable",
-    "gom_batch_timing_read", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
+    "gom_batch_timing_read", "gom_batch_set_narrow", "gom_batch_get_narrow",
+    "gom_batch_autotune", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
 )
 
@@ -133,6 +134,9 @@ def lib() -> C.CDLL:
         "gom_batch_reseed": (C.c_int, [_vp, _vp, _vp]),
         "gom_batch_timing_enable": (C.c_int, [_vp, C.c_int]),
         "gom_batch_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
+        "gom_batch_set_narrow": (C.c_int, [_vp, _i64, _vp]),
+        "gom_batch_get_narrow": (C.c_int, [_vp, _P(_i64), _P(_i32)]),
+        "gom_batch_autotune": (C.c_int, [_vp, _i32, _vp, _P(_i64)]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
@@ -596,6 +600,28 @@ def gom_batch_timing_read(b: GomBatch):
     ms, n = C.c_double(), _i64()
     _check(lib().gom_batch_timing_read(b.handle, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def gom_batch_set_narrow(b: GomBatch, narrow_max_n: int, stream=None) -> None:
+    """Instances with at most narrow_max_n vertices sweep with 256-thread blocks, larger ones
+    with 1024 (-1: all 1024)."""
+    _check(lib().gom_batch_set_narrow(b.handle, int(narrow_max_n), _stream_handle(stream)))
+
+
+def gom_batch_get_narrow(b: GomBatch):
+    """(block-size threshold, sweep launches per step)."""
+    t, n = _i64(), _i32()
+    _check(lib().gom_batch_get_narrow(b.handle, C.byref(t), C.byref(n)))
+    return t.value, n.value
+
+
+def gom_batch_autotune(b: GomBatch, trial_steps: int = 2, stream=None) -> int:
+    """Time trial generation steps under each block-size threshold and keep the fastest;
+    returns it.  The trial steps are ordinary steps of the run."""
+    c = _i64()
+    _check(lib().gom_batch_autotune(b.handle, int(trial_steps), _stream_handle(stream),
+                                    C.byref(c)))
+    return c.value
 
 
 def gom_batch_set_graph(b: GomBatch, enabled: bool = True) -> None:

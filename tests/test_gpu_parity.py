@@ -856,6 +856,43 @@ def test_batch_reseed_and_timing(cuda):
             assert_same(a, ref.state(), f"reseeded instance {b} vs oracle")
 
 
+def test_batch_block_sizes_and_autotune(cuda):
+    """Every block-size threshold of the batched sweep (all 1024-thread blocks, mixed, all
+    256) and the autotuner's choice give each instance its solo trajectory; the trial steps of
+    the autotuner are ordinary generations."""
+    print("case batch block sizes", flush=True)
+    items = workloads.batch_mix(count=8, seed=16, n_lo=60, n_hi=6000)
+    insts, targets = _batch_setup(items)
+    pops, seeds = [it.pop for it in items], [it.seed for it in items]
+    solo = {}
+    for b in range(len(items)):
+        st = insts[b].state(pop=pops[b], seed=seeds[b])
+        r = gom.gom_run_to_target(st, targets[b], 10)
+        solo[b] = (r, gom.gom_state_hash(st))
+    for thr in (-1, 600, 1 << 40):
+        bt = gom.gom_batch_init(insts, pops, seeds, targets)
+        gom.gom_batch_set_narrow(bt, thr)
+        got_thr, launches = gom.gom_batch_get_narrow(bt)
+        assert got_thr == thr and launches >= 1
+        res, _ = gom.gom_batch_run(bt, 10)
+        for b in range(len(items)):
+            assert res[b] == solo[b][0], (thr, b)
+            assert gom.gom_state_hash(bt.state(b)) == solo[b][1], (thr, b)
+    bt = gom.gom_batch_init(insts, pops, seeds, targets)
+    chosen = gom.gom_batch_autotune(bt, 1)
+    print(f"  autotuner chose {chosen}", flush=True)
+    res, _ = gom.gom_batch_run(bt, 20)
+    for b, it in enumerate(items):
+        st = insts[b].state(pop=pops[b], seed=seeds[b])
+        r = gom.gom_run_to_target(st, targets[b], 20)
+        assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), b
+        if it.graph.n <= 400:
+            ptr, vars_ = oracle.fos(it.graph, it.fos)
+            ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=it.seed)
+            ref.run(targets[b], 20)
+            assert gom.gom_state_hash(bt.state(b)) == ref.hash(), f"instance {b} vs oracle"
+
+
 def test_batch_graph_replays_equal_direct_launches(cuda):
     """gom_batch_run with its chunks replayed from a captured HIP graph against the same batch
     with direct launches: after every call (one replay each, with other device work and host
