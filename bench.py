@@ -165,6 +165,42 @@ def cpu_baseline_mix(items, seeds, count, gens):
             "build": "gcc -O2 -fopenmp" + (" -march=native" if native else "")}
 
 
+def write_metrics_log(path, gom, torch, st, target, max_gens):
+    """Per-generation metrics of one more run (seed 1), one JSON line per generation: the
+    generation, the elitist's and the population's best and mean fitness, the cumulative
+    attempted / evaluated / accepted counts and the wall time of the generation (enqueue to
+    completion, ns).  Outside the timed region: each generation waits for its read-back."""
+    gom.gom_state_reseed(st, 1)
+    with open(path, "w") as fh:
+        for g in range(max_gens):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter_ns()
+            gom.gom_generation(st)
+            s = gom.gom_state_read(st, genes=False)
+            ns = time.perf_counter_ns() - t0
+            f = np.asarray(s["fitness"])
+            fh.write(json.dumps({"g": s["generation"], "elite": s["elite_fitness"],
+                                 "best": int(f.max()), "mean": float(f.mean()),
+                                 "attempted": s["attempted"], "evaluated": s["evaluated"],
+                                 "accepted": s["accepted"], "ns": ns}) + "\n")
+            if s["elite_fitness"] >= target:
+                break
+    log(f"metrics log: {path}")
+
+
+def copy_calibration(torch, mb):
+    """A device copy of a known byte count (3 times), for scaling profiler traffic counters."""
+    if not mb:
+        return
+    nbytes = mb << 20
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {nbytes} bytes")
+
+
 def step_seeds(items, k):
     """Seeds of timed step k (k >= 0); warm-up steps use k < 0.  Distinct per instance and
     step."""
@@ -267,6 +303,7 @@ def run_batch_mode(args, torch, gom):
     res_t, _ = one_step(0)
     sweep_ms, launches = gom.gom_batch_timing_read(batch)
     gom.gom_batch_timing_enable(batch, False)
+    copy_calibration(torch, args.copy_calib_mb)
     batch_hash = [gom.gom_state_hash(batch.state(b)) for b in range(len(items))]
     same_timed = all((a.generations, a.best, a.evaluated, a.accepted) ==
                      (b.generations, b.best, b.evaluated, b.accepted)
@@ -574,6 +611,12 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
+    ap.add_argument("--metrics-jsonl", default=None,
+                    help="plain mode: write per-generation metrics of one more run to this "
+                         "file (JSON lines)")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="bit-sliced schedule: one launch per class instead of the fused "
+                         "generation sweep")
     ap.add_argument("--block", type=int, default=0,
                     help="class-launch block size (with --schedule class; 0 = default)")
     ap.add_argument("--fi", action="store_true",
@@ -636,9 +679,14 @@ def main():
                                         "bitsliced": gom.GOM_SCHED_BITSLICED}[args.schedule])
     if args.block:
         gom.gom_state_set_block(st, args.block)
+    if args.no_fused and gom.gom_state_get_fused(st)[1]:
+        gom.gom_state_set_fused(st, False)
     sched = gom.gom_state_get_schedule(st)
     sched_name = {gom.GOM_SCHED_RESIDENT: "resident", gom.GOM_SCHED_BITSLICED: "bitsliced"}.get(
         sched, "class_launch")
+    fused = sched_name == "bitsliced" and gom.gom_state_get_fused(st)[0]
+    if fused:
+        sched_name = "bitsliced_fused"
     info = st.info()
     _, class_ptr, class_elems = inst.classes()
     set_ptr, set_vars = inst.fos.sets()
@@ -692,19 +740,14 @@ def main():
         one_run(args.steps + 1)
         sweep_ms, launches = gom.gom_timing_read(st)
         gom.gom_timing_enable(st, 0)
-    if args.copy_calib_mb:
-        nbytes = args.copy_calib_mb << 20
-        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {nbytes} bytes")
+    copy_calibration(torch, args.copy_calib_mb)
     for k, (r, dt) in enumerate(runs):
         log(f"step {k} seed {k + 1}: generations {r.generations} reached {r.reached} "
             f"best {r.best}/{target} attempted {r.attempted} evaluated {r.evaluated} "
             f"accepted {r.accepted} time {dt * 1e3:.2f} ms")
 
+    if args.metrics_jsonl:
+        write_metrics_log(args.metrics_jsonl, gom, torch, st, target, max_gens)
     attempted = sum(r.attempted for r, _ in runs)
     gens = sum(r.generations for r, _ in runs)
     tto = [dt * 1e3 for r, dt in runs if r.reached]
@@ -716,11 +759,13 @@ def main():
         # class launch: every class is swept once per generation, so the mean over launches
         # of the algorithmic bytes is the mean over classes; resident: one launch sweeps
         # every class of a generation
-        avg_bytes = float(cbytes.sum() if sched_name == "resident" else cbytes.mean())
+        # (the fused bit-sliced sweep, like the resident one, covers every class per launch)
+        whole = sched_name in ("resident", "bitsliced_fused")
+        avg_bytes = float(cbytes.sum() if whole else cbytes.mean())
         avg_s = sweep_ms / 1e3 / launches
         achieved = avg_bytes / avg_s / 1e9
-        kname = {"resident": "k_resident_sweep", "bitsliced": "k_uni_swar_sweep"}.get(
-            sched_name, "k_class_sweep")
+        kname = {"resident": "k_resident_sweep", "bitsliced": "k_uni_swar_sweep",
+                 "bitsliced_fused": "k_uni_swar_fused"}.get(sched_name, "k_class_sweep")
         meas = MEASURED_TRAFFIC.get((kname, args.workload))
         traffic = meas["bytes"] if meas and meas["source"] == kernel_source_hash() else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
@@ -769,6 +814,7 @@ def main():
         "time_to_optimum_ms_median": float(np.median(tto)) if tto else None,
         "reached": len(tto), "generations_total": gens,
         "us_per_generation": total * 1e6 / max(gens, 1),
+        "us_per_class": total * 1e6 / max(gens, 1) / max(info["n_classes"], 1),
         "roofline": roofline, "cpu_baseline": cpu,
         "batched": batched,
         "local_search_passes": ls_passes[0] if args.local_search else None,

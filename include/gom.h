@@ -341,6 +341,21 @@ int gom_state_get_fi(const gom_state *s, int *enabled);
 
 /* Block size of the class-launch sweeps: 64..512 threads, a multiple of 64 (default 256).
  * GOM_E_RANGE otherwise.  Results do not depend on it. */
+/*
+ * The fused form of the bit-sliced schedule: a whole generation's classes in one cooperative
+ * launch, each block waiting only for the chunks of earlier classes whose sets conflict with
+ * its own (same variable or an edge between them; Sec. 5.2's independence of the sets of a
+ * colour class).  Available when the bit-sliced schedule is, there are at most 8 classes and
+ * every dependency range spans at most 32 chunks (tori, not random graphs); used by default
+ * then.  Results are identical either way.  Its blocks wait for each other, so they must all
+ * be on the device at once: the launch is cooperative, and states that generate on several
+ * streams at the same time should turn it off (the serving loop does for its jobs).  A
+ * dependency wait that never ends gives up after a bounded number of polls; the next read of
+ * the state then fails with GOM_E_DEVICE.
+ * gom_state_set_fused errors: GOM_E_ARG, GOM_E_RANGE (not available).
+ */
+int gom_state_set_fused(gom_state *s, int enabled);
+int gom_state_get_fused(const gom_state *s, int *enabled, int *available);
 int gom_state_set_block(gom_state *s, int threads);
 int gom_state_get_block(const gom_state *s, int *threads);
 

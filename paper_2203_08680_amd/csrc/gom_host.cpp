@@ -13,6 +13,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <thread>
 #include <map>
 #include <new>
 #include <queue>
@@ -80,7 +81,7 @@ namespace {
 
 struct Layout {
     size_t st, fit, stripes, E, P, O, rows, cptr, crec, eu, ev, ew, roff, recs, coop, sw, smap,
-        split, total;
+        split, fdep, fflags, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -112,6 +113,10 @@ Layout make_layout(int32_t n, int64_t m, int32_t n_sets, int32_t k, int32_t pop,
     L.sw = take(sizeof(int32_t) * (size_t)sw_words);
     L.smap = take(sizeof(int4) * (size_t)n_smap);
     L.split = take(n_smap ? kSplitScratchBytes : 0);
+    // fused bit-sliced sweep: dependency ranges and chunk flags for up to kFusedMaxGrid chunks
+    const bool fused = sw_words > 0 && k <= kFusedMaxClasses;
+    L.fdep = take(fused ? sizeof(int4) * (size_t)k * k * kFusedMaxGrid : 0);
+    L.fflags = take(fused ? sizeof(uint32_t) * (size_t)k * kFusedMaxGrid : 0);
     L.total = o;
     return L;
 }
@@ -243,6 +248,72 @@ std::vector<int32_t> build_swar(const mc_graph &g, const gom_fos &f) {
     return T;
 }
 
+// Chunks of the fused bit-sliced sweep: class c's positions cut into `grid` chunks of
+// clen[c] = ceil(|class| / grid) positions.  dep[(c * grid + x) * k + c2] holds the chunks of
+// class c2 with a set whose variable is a variable of chunk x of class c or a neighbour of one
+// (the chunks that write what chunk x reads, or read what it writes) as two ranges {lo0, hi0,
+// lo1, hi1}: the sorted chunk ids split at their widest gap, so that the wrap-around edges of
+// a torus cost two short ranges instead of one that spans the class; an unused range is
+// {0, -1}.  Returns false when the two ranges of some entry span more than kFusedMaxDepChunks
+// chunks together.
+bool fused_deps(const mc_graph &g, const gom_fos &f, int grid, std::vector<int32_t> &clen,
+                std::vector<int4> &dep) {
+    const int k = f.k;
+    const size_t n = (size_t)g.n;
+    clen.assign((size_t)k, 1);
+    for (int c = 0; c < k; ++c) {
+        const int32_t cs = f.class_ptr[(size_t)c + 1] - f.class_ptr[c];
+        clen[(size_t)c] = std::max<int32_t>(1, (cs + grid - 1) / grid);
+    }
+    std::vector<int32_t> at((size_t)k * n, -1);  // chunk of class c holding variable v
+    for (int c = 0; c < k; ++c)
+        for (int32_t t = f.class_ptr[c]; t < f.class_ptr[(size_t)c + 1]; ++t) {
+            const int32_t u = f.vars[f.ptr[f.class_elems[t]]];
+            at[(size_t)c * n + u] = (t - f.class_ptr[c]) / clen[(size_t)c];
+        }
+    dep.assign((size_t)k * grid * k, make_int4(0, -1, 0, -1));
+    std::vector<int32_t> ids;
+    for (int c = 0; c < k; ++c) {
+        const int32_t c0 = f.class_ptr[c], cs = f.class_ptr[(size_t)c + 1] - c0;
+        for (int32_t x = 0; x < grid; ++x) {
+            const int32_t p0 = x * clen[(size_t)c], p1 = std::min(p0 + clen[(size_t)c], cs);
+            for (int c2 = 0; c2 < k; ++c2) {
+                if (c2 == c) continue;
+                ids.clear();
+                for (int32_t p = p0; p < p1; ++p) {
+                    const int32_t u = f.vars[f.ptr[f.class_elems[c0 + p]]];
+                    auto add = [&](int32_t w) {
+                        const int32_t y = at[(size_t)c2 * n + w];
+                        if (y >= 0) ids.push_back(y);
+                    };
+                    add(u);
+                    for (int32_t q = g.row_ptr[u]; q < g.row_ptr[(size_t)u + 1]; ++q)
+                        add(g.col[q]);
+                }
+                if (ids.empty()) continue;
+                std::sort(ids.begin(), ids.end());
+                ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+                size_t cut = ids.size() - 1;  // split after ids[cut] at the widest gap
+                int32_t gap = 0;
+                for (size_t q = 0; q + 1 < ids.size(); ++q)
+                    if (ids[q + 1] - ids[q] > gap) {
+                        gap = ids[q + 1] - ids[q];
+                        cut = q;
+                    }
+                int4 &r = dep[((size_t)c * grid + x) * k + c2];
+                r = make_int4(ids.front(), ids[cut], 0, -1);
+                if (cut + 1 < ids.size()) {
+                    r.z = ids[cut + 1];
+                    r.w = ids.back();
+                }
+                const int32_t span = (r.y - r.x + 1) + (r.w >= r.z ? r.w - r.z + 1 : 0);
+                if (span > kFusedMaxDepChunks) return false;
+            }
+        }
+    }
+    return true;
+}
+
 int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records &R) {
     const int32_t S = f.n_sets;
     std::vector<int32_t> pos((size_t)g.n, -1), owner((size_t)g.n, -1);
@@ -360,6 +431,14 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
 
 struct gom_state {
     bool h_st_pinned = true;            // h_st from hipHostMalloc (else new[])
+    bool fused_ok = false;              // the fused bit-sliced sweep can run this state
+    bool fused_use = true;              // ... and is used for whole generations
+    bool fused_narrow = false;          // its per-block fitness sums fit in int32
+    int fused_grid = 0;
+    std::vector<int32_t> fused_clen;    // chunk length per class
+    uint32_t fused_epoch = 0;           // stamp of the last fused launch
+    int4 *d_fdep = nullptr;
+    uint32_t *d_fflags = nullptr;
     int32_t n = 0, N = 0, n_sets = 0, k = 0, max_class = 0;
     int64_t m = 0;
     uint64_t seed = 0;
@@ -767,15 +846,33 @@ extern "C" int gom_colour(const mc_graph *g, gom_fos *f, int32_t *n_colours) {
             }
         }
     };
-    std::vector<int32_t> stamp((size_t)S, -1);
+    // LMIG degrees: each set's distinct conflicting sets, counted with a stamp array.  The
+    // sets are split into contiguous ranges over host threads, each with its own stamps; the
+    // degrees do not depend on the split.
     std::vector<int64_t> deg((size_t)S, 0);
-    for (int32_t j = 0; j < S; ++j) {
-        int64_t d = 0;
-        stamp[j] = j;
-        for_conflicts(j, [&](int32_t k) {
-            if (stamp[k] != j) { stamp[k] = j; ++d; }
-        });
-        deg[j] = d;
+    auto degrees = [&](int32_t j0, int32_t j1) {
+        std::vector<int32_t> stamp((size_t)S, -1);
+        for (int32_t j = j0; j < j1; ++j) {
+            int64_t d = 0;
+            stamp[j] = j;
+            for_conflicts(j, [&](int32_t k) {
+                if (stamp[k] != j) { stamp[k] = j; ++d; }
+            });
+            deg[j] = d;
+        }
+    };
+    const int64_t visits = (int64_t)f->vars.size() * (1 + g->max_degree);
+    const int nth = (int)std::min<int64_t>(
+        std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
+        std::max<int64_t>(1, visits / (1 << 20)));
+    if (nth <= 1) {
+        degrees(0, S);
+    } else {
+        std::vector<std::thread> pool;
+        for (int q = 0; q < nth; ++q)
+            pool.emplace_back(degrees, (int32_t)((int64_t)S * q / nth),
+                              (int32_t)((int64_t)S * (q + 1) / nth));
+        for (std::thread &t : pool) t.join();
     }
     std::vector<int32_t> order((size_t)S);
     for (int32_t j = 0; j < S; ++j) order[j] = j;
@@ -949,9 +1046,8 @@ static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool r
 
 // Class sweeps for order positions [t0, t1) of generation `gen` under the per-class schedules
 // (bit-sliced when chosen, else class launch).
-static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, int32_t gen,
-                               int32_t t0, int32_t t1, int64_t target, hipStream_t st,
-                               bool forced = false) {
+// The generation-wide fields of a class sweep's arguments.
+static SweepArgs sweep_args(const gom_state *s, int32_t gen, int64_t target, bool forced) {
     SweepArgs a{};
     a.mode = forced ? kSweepFi : (s->fi ? kSweepGomTrack : kSweepGom);
     a.E = s->d_E;
@@ -969,6 +1065,45 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
     a.N = s->N;
     a.gen = gen;
     a.always = s->rule == GOM_NEUTRAL_ALWAYS;
+    return a;
+}
+
+// Every class of a whole generation in one cooperative launch of the fused bit-sliced sweep.
+static int enqueue_fused_generation(gom_state *s, const std::vector<int32_t> &perm, int32_t gen,
+                                    int64_t target, hipStream_t st) {
+    FusedArgs f{};
+    f.a = sweep_args(s, gen, target, false);
+    f.dep = s->d_fdep;
+    f.flags = s->d_fflags;
+    f.epoch = ++s->fused_epoch;
+    if (f.epoch == 0) {
+        // after 2^32 launches the stamps wrap: start the flags again from zero
+        HIP_TRY(hipMemsetAsync(s->d_fflags, 0, sizeof(uint32_t) * (size_t)s->k * s->fused_grid,
+                               st));
+        f.epoch = s->fused_epoch = 1;
+    }
+    f.k = s->k;
+    f.grid = s->fused_grid;
+    for (int32_t t = 0; t < s->k; ++t) {
+        const int32_t c = perm[(size_t)t];
+        f.order[t] = c;
+        f.cbase[c] = s->class_ptr[c];
+        f.csize[c] = s->class_ptr[(size_t)c + 1] - s->class_ptr[c];
+        f.clen[c] = s->fused_clen[(size_t)c];
+    }
+    KernelEvents ev;
+    int rc = timing_events(s, &ev);
+    if (rc) return rc;
+    if (ev.start) HIP_TRY(hipEventRecord(ev.start, st));
+    HIP_TRY(launch_uni_swar_fused(f, s->partition, s->fused_narrow, st));
+    if (ev.stop) HIP_TRY(hipEventRecord(ev.stop, st));
+    return GOM_OK;
+}
+
+static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, int32_t gen,
+                               int32_t t0, int32_t t1, int64_t target, hipStream_t st,
+                               bool forced = false) {
+    SweepArgs a = sweep_args(s, gen, target, forced);
     for (int32_t t = t0; t < t1; ++t) {
         const int32_t c = perm[t];
         a.cls = c;
@@ -1032,6 +1167,11 @@ static int enqueue_generation(gom_state *s, int32_t gen, int64_t target, hipStre
         if (rc) return rc;
         HIP_TRY(launch_resident_sweep(r, s->univariate ? 0 : 1, s->resident_plds, st, ev));
         return enqueue_epilogue(s, target, st, true);
+    }
+    if (s->sched == GOM_SCHED_BITSLICED && s->fused_ok && s->fused_use && !s->fi) {
+        const int rc = enqueue_fused_generation(s, perm, gen, target, st);
+        if (rc) return rc;
+        return enqueue_epilogue(s, target, st, false);
     }
     int rc = enqueue_class_range(s, perm, gen, 0, s->k, target, st);
     // forced improvement: the classes again, with the elitist as donor
@@ -1146,6 +1286,8 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
     s->d_split_delta = (int64_t *)(s->arena + L.split + (size_t)kSplitBelow * 64 * 8);
     s->d_split_sel = (int32_t *)(s->arena + L.split + (size_t)kSplitBelow * 64 * 16);
     s->sw_stride = swar_stride(f->n_sets);
+    s->d_fdep = (int4 *)(s->arena + L.fdep);
+    s->d_fflags = (uint32_t *)(s->arena + L.fflags);
     auto cleanup = [&](int code) {
         gom_state_free(s);
         return code;
@@ -1192,6 +1334,26 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
     if (e == hipSuccess) e = h2d(s->d_coop, CS.pos.data(), sizeof(int32_t) * CS.pos.size());
     if (e == hipSuccess) e = h2d(s->d_sw, SW.data(), sizeof(int32_t) * SW.size());
     if (e == hipSuccess) e = h2d(s->d_smap, CS.smap.data(), sizeof(int4) * CS.smap.size());
+    std::vector<int4> fdep;
+    if (e == hipSuccess && swar && f->k <= kFusedMaxClasses) {
+        // the fused form of the bit-sliced sweep: one cooperative launch per generation
+        int grid = 0;
+        e = fused_swar_grid(&grid);
+        // no more blocks than a thread per set of the largest class needs: chunks of at least
+        // a block's width keep the dependency ranges short
+        grid = std::min<int64_t>(grid, ((int64_t)s->max_class + kSwarThreads - 1) / kSwarThreads);
+        if (e == hipSuccess && grid >= 1 && fused_deps(*g, *f, grid, s->fused_clen, fdep)) {
+            int64_t per_thread = 0;  // sets a thread sweeps per generation
+            for (int32_t c = 0; c < f->k; ++c)
+                per_thread += (s->fused_clen[(size_t)c] + kSwarThreads - 1) / kSwarThreads;
+            s->fused_narrow = swar_abs * kSwarThreads * per_thread < ((int64_t)1 << 31);
+            s->fused_grid = grid;
+            s->fused_ok = true;
+            e = h2d(s->d_fdep, fdep.data(), sizeof(int4) * fdep.size());
+            if (e == hipSuccess)
+                e = hipMemsetAsync(s->d_fflags, 0, sizeof(uint32_t) * (size_t)f->k * grid, st);
+        }
+    }
     if (e == hipSuccess && !CS.smap.empty())  // the split sweep's scratch starts cleared
         e = hipMemsetAsync(s->arena + L.split, 0, kSplitScratchBytes, st);
     if (e == hipSuccess) e = enqueue_initial_population(s, st);
@@ -1362,10 +1524,17 @@ extern "C" int gom_iterated_local_search(gom_state *s, int32_t round0, int32_t r
     GUARD_END
 }
 
+static int check_stall(const DevState &h) {
+    if (h.stall)
+        return fail(GOM_E_DEVICE, "a dependency wait of the fused bit-sliced sweep gave up; the "
+                    "state is not valid");
+    return GOM_OK;
+}
+
 static int read_scalars(gom_state *s, hipStream_t st, DevState *h) {
     HIP_TRY(hipMemcpyAsync(h, s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    return GOM_OK;
+    return check_stall(*h);
 }
 
 // Fitness and counters of the state.  While a generation is open the running values are the
@@ -1433,6 +1602,8 @@ extern "C" int gom_run_to_target(gom_state *s, int64_t target, int32_t max_gener
             }
             if (prev >= 0) {
                 HIP_TRY(hipEventSynchronize(s->chunk_ev[prev]));
+                rc = check_stall(s->h_st[prev]);
+                if (rc) return rc;
                 if (s->h_st[prev].elite_fitness >= target) break;
             }
             if (cur < 0) break;
@@ -1633,17 +1804,42 @@ extern "C" int gom_state_set_schedule(gom_state *s, int schedule) {
     }
 }
 
+extern "C" int gom_state_set_fused(gom_state *s, int enabled) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_fused: null state");
+    if (enabled && !s->fused_ok)
+        return fail(GOM_E_RANGE, "gom_state_set_fused: the fused bit-sliced sweep does not fit "
+                    "this state (needs the bit-sliced schedule's eligibility, at most %d classes "
+                    "and dependency ranges of at most %d chunks)", kFusedMaxClasses,
+                    kFusedMaxDepChunks);
+    s->fused_use = enabled != 0;
+    return GOM_OK;
+}
+
+extern "C" int gom_state_get_fused(const gom_state *s, int *enabled, int *available) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_get_fused: null state");
+    if (enabled) *enabled = s->fused_ok && s->fused_use;
+    if (available) *available = s->fused_ok;
+    return GOM_OK;
+}
+
 extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void *stream,
                                   int *chosen) {
     GUARD_BEGIN
     if (!s || trial_generations < 1) return fail(GOM_E_ARG, "gom_state_autotune: bad arguments");
     if (s->open_next >= 0) return fail(GOM_E_STATE, "gom_state_autotune: a generation is open");
     hipStream_t st = (hipStream_t)stream;
-    // (schedule, class-launch block size)
-    std::vector<std::pair<int, int>> cands;
-    for (int t : {64, 128, 256, 512}) cands.push_back({GOM_SCHED_CLASS_LAUNCH, t});
-    if (s->resident_ok) cands.push_back({GOM_SCHED_RESIDENT, s->sweep_threads});
-    if (s->bitsliced_ok && !s->fi) cands.push_back({GOM_SCHED_BITSLICED, s->sweep_threads});
+    // (schedule, class-launch block size, fused bit-sliced sweep)
+    struct Cand {
+        int sched, threads;
+        bool fused;
+    };
+    std::vector<Cand> cands;
+    for (int t : {64, 128, 256, 512}) cands.push_back({GOM_SCHED_CLASS_LAUNCH, t, s->fused_use});
+    if (s->resident_ok) cands.push_back({GOM_SCHED_RESIDENT, s->sweep_threads, s->fused_use});
+    if (s->bitsliced_ok && !s->fi) {
+        cands.push_back({GOM_SCHED_BITSLICED, s->sweep_threads, false});
+        if (s->fused_ok) cands.push_back({GOM_SCHED_BITSLICED, s->sweep_threads, true});
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -1659,8 +1855,9 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
     int rc = GOM_OK;
     for (int round = 0; round < kRounds && rc == GOM_OK; ++round) {
         for (size_t ci = 0; ci < cands.size() && rc == GOM_OK; ++ci) {
-            s->sched = cands[ci].first;
-            s->sweep_threads = cands[ci].second;
+            s->sched = cands[ci].sched;
+            s->sweep_threads = cands[ci].threads;
+            s->fused_use = cands[ci].fused;
             // one untimed generation loads the schedule's kernels, then the timed ones
             for (int32_t t = 0; t <= trial_generations && rc == GOM_OK; ++t) {
                 if (t == 1 && hipEventRecord(e0, st) != hipSuccess) rc = GOM_E_DEVICE;
@@ -1675,7 +1872,7 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
             if (rc == GOM_OK && (round == 0 || ms < cand_ms[ci])) cand_ms[ci] = ms;
         }
     }
-    std::pair<int, int> best = cands.front();
+    Cand best = cands.front();
     float best_ms = cand_ms.front();
     for (size_t ci = 1; ci < cands.size(); ++ci)
         if (cand_ms[ci] < best_ms) {
@@ -1686,9 +1883,10 @@ extern "C" int gom_state_autotune(gom_state *s, int32_t trial_generations, void 
     (void)hipEventDestroy(e1);
     s->timing = timing;
     if (rc != GOM_OK) return fail(rc, "gom_state_autotune: a trial generation failed");
-    s->sched = best.first;
-    s->sweep_threads = best.second;
-    if (chosen) *chosen = best.first;
+    s->sched = best.sched;
+    s->sweep_threads = best.threads;
+    s->fused_use = best.fused;
+    if (chosen) *chosen = best.sched;
     return GOM_OK;
     GUARD_END
 }
@@ -1855,6 +2053,21 @@ static int blocks_per_cu(size_t lds, size_t lds_max) {
     return (int)std::min<size_t>(8, lds ? lds_max / lds : 8);
 }
 
+// Blocks per CU by registers and threads of each (threads, kind) variant of the batched sweep,
+// looked up once per process (the library's device code is the same on every device).
+static int batch_reg_blocks(int threads, int kind) {
+    static std::mutex mu;
+    static int cache[2][2] = {{0, 0}, {0, 0}};
+    std::lock_guard<std::mutex> lk(mu);
+    int &c = cache[threads == 256 ? 0 : 1][kind ? 1 : 0];
+    if (c == 0) {
+        int b = 0;
+        if (batch_sweep_occupancy(threads, kind, &b) != hipSuccess || b < 1) b = 1;
+        c = b;
+    }
+    return c;
+}
+
 // Block sizes, P copies and launch groups for the threshold `narrow_max_n`: an instance with
 // n <= narrow_max_n sweeps with 256-thread blocks, else 1024.  It keeps a copy of P in LDS
 // when that does not lower the blocks a CU can hold.  Instances with equal (threads, blocks
@@ -1863,7 +2076,7 @@ static int blocks_per_cu(size_t lds, size_t lds_max) {
 // and drops a captured graph.
 static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
     struct Item {
-        int threads, occ;
+        int threads, kind, occ;
         double cost;
         int32_t inst;
         size_t lds;
@@ -1877,15 +2090,19 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
         const size_t l1 = kBatchOrderBytes + resident_lds_bytes(s->n, true, T);
         if (l0 > b->lds_max)
             return fail(GOM_E_RANGE, "batch: instance %d needs %zu bytes of LDS", i, l0);
-        const bool plds = l1 <= b->lds_max &&
-                          blocks_per_cu(l1, b->lds_max) == blocks_per_cu(l0, b->lds_max);
+        const int kind = s->univariate ? 0 : 1;
+        const int reg = batch_reg_blocks(T, kind);
+        const bool plds = l1 <= b->lds_max && std::min(blocks_per_cu(l1, b->lds_max), reg) ==
+                                                  std::min(blocks_per_cu(l0, b->lds_max), reg);
         b->h_insts[(size_t)i].plds = plds ? 1 : 0;
         const size_t l = plds ? l1 : l0;
         const double cost = (double)s->k + (double)s->n_sets / T;
-        items.push_back(Item{T, blocks_per_cu(l, b->lds_max), cost, i, l});
+        const int occ = std::min(blocks_per_cu(l, b->lds_max), reg);
+        items.push_back(Item{T, kind, occ, cost, i, l});
     }
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
         if (x.threads != y.threads) return x.threads > y.threads;
+        if (x.kind != y.kind) return x.kind > y.kind;
         if (x.occ != y.occ) return x.occ < y.occ;
         return x.cost > y.cost;
     });
@@ -1894,8 +2111,8 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
     for (size_t q = 0; q < items.size(); ++q) {
         const Item &it = items[q];
         if (groups.empty() || q == 0 || it.threads != items[q - 1].threads ||
-            it.occ != items[q - 1].occ)
-            groups.push_back(BatchLaunch{(int)blk.size(), 0, it.threads, 0});
+            it.kind != items[q - 1].kind || it.occ != items[q - 1].occ)
+            groups.push_back(BatchLaunch{(int)blk.size(), 0, it.threads, it.kind, 0});
         BatchLaunch &G = groups.back();
         const gom_state *s = b->subs[(size_t)it.inst];
         for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2(it.inst, i));
@@ -2463,6 +2680,9 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
             sv->queue.pop_front();
             continue;
         }
+        // jobs share the device: a fused sweep's chunks wait for each other, which needs all
+        // of its blocks on the device at once, so served jobs sweep class by class
+        s->fused_use = false;
         J.s = s;
         J.off = off;
         J.lane = lane;

@@ -68,7 +68,7 @@ struct alignas(64) DevState {
     uint64_t fi_fail;        // solutions the last generation's forced improvement replaced
                              // by the elitist
     uint32_t ls_any;         // local search: a flip happened in the current pass
-    uint32_t pad0;
+    uint32_t stall;          // a dependency wait of the fused bit-sliced sweep gave up
     uint32_t fi_at[64];      // forced improvement of this generation: 0 while solution i has
                              // not improved, else kFiBase - t for the first class position t
                              // (in the generation's order) at which a step raised its fitness
@@ -141,6 +141,29 @@ struct SweepArgs {
     uint64_t *split_D;
     int64_t *split_delta;
     int32_t *split_sel;
+};
+
+// Fused bit-sliced sweep: every colour class of a generation in one launch.  Block b owns
+// chunk x = xcd_tile(b, grid) of every class (class c's positions are cut into `grid` chunks
+// of clen[c] positions); it sweeps its chunk of each class in the generation's order and
+// first waits until the chunks of earlier classes that hold a conflicting set (the same
+// variable or a neighbour) are done in this launch.  A chunk is done when its flag holds the
+// launch's epoch stamp (a host counter, so flags never need clearing).
+constexpr int kFusedMaxGrid = 4096;
+constexpr int kFusedMaxClasses = 8;
+constexpr int kFusedMaxDepChunks = 32;  // widest dependency range (chunks) the fused sweep takes
+constexpr uint32_t kFusedSpinLimit = 1u << 22;  // polls before a wait gives up (sets stall)
+struct FusedArgs {
+    SweepArgs a;
+    const int4 *dep;   // [(c * grid + x) * k + c2]: two chunk ranges {lo0, hi0, lo1, hi1} of
+                       // class c2 that chunk x of class c depends on ({0, -1}: unused)
+    uint32_t *flags;   // [c * grid + x]: stamp of the last launch that finished the chunk
+    uint32_t epoch;    // this launch's stamp
+    int32_t k, grid;
+    int32_t order[kFusedMaxClasses];   // class at each position of the generation's order
+    int32_t cbase[kFusedMaxClasses];   // first class position (table entry) of class c
+    int32_t csize[kFusedMaxClasses];
+    int32_t clen[kFusedMaxClasses];    // chunk length of class c (positions)
 };
 
 // Groups of fewer than kSplitBelow large sets take the split sweep (three launches whose
@@ -293,6 +316,11 @@ hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threa
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow, int max_grid,
                                  hipStream_t s, KernelEvents ev = {});
 constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
+// Fused form (one cooperative launch per generation; see FusedArgs).
+hipError_t launch_uni_swar_fused(const FusedArgs &f, bool partition, bool narrow,
+                                 hipStream_t s);
+// Blocks of the fused sweep that the current device holds at once (its grid), or an error.
+hipError_t fused_swar_grid(int *grid);
 // plds: keep a copy of P in LDS (needs resident_lds_bytes(n, true) of LDS).
 hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hipStream_t s,
                                  KernelEvents ev = {});
@@ -302,9 +330,12 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
 // the vertex pass (vblocks blocks, vblk[b] = instance).  ev: optional events, the start
 // recorded by the first sweep launch and the stop by the last.
 struct BatchLaunch {
-    int first, count, threads;
+    int first, count, threads, kind;  // kind: FOS kind of the group's instances
     size_t lds;
 };
+// Blocks of the batched sweep (threads = 256 or 1024, FOS kind) that a CU holds at once by
+// registers and threads alone (without dynamic LDS).
+hipError_t batch_sweep_occupancy(int threads, int kind, int *blocks);
 // Allows each group's k_batch_sweep blocks their dynamic LDS (once per size; not a stream
 // operation, so it is done before a step is captured into a graph).
 hipError_t prepare_batch_step(const BatchLaunch *groups, int n_groups);

@@ -24,6 +24,7 @@
 // order in which waves run.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <type_traits>
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(256) void k_init_population(uint64_t *P, uint64_t *
             st->active = 0;
             st->start_tick = 0;
             st->done_tick = -1;
+            st->stall = 0;
         }
     }
     const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1243,38 +1245,28 @@ __device__ __forceinline__ uint64_t table16(uint32_t t, uint64_t q0, uint64_t q1
     return sel64(q3, m21, m20);
 }
 
-// NARROW: the block's per-solution fitness sums fit in int32 (the host checks the weights'
-// bound), so they are kept as 32-bit LDS counters; else 64-bit.
-template <bool PARTITION, bool NARROW>
-__global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
-    using Acc = std::conditional_t<NARROW, int, unsigned long long>;
-    const int stride = gridDim.x * kSwarThreads;
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+// One entry of the bit-sliced table: the set's variable, its neighbours, its truth tables.
+struct SwarEntry {
+    int u, v0, v1, v2, v3;
+    uint32_t tab;
+};
+
+// Entry q of the table (q: the set's position in the class order of all classes).
+__device__ __forceinline__ SwarEntry swar_entry(const SweepArgs &a, int q) {
     const size_t ss = (size_t)a.sw_stride;
-    // the first set's table entry is loaded before anything waits (the run-state loads and
-    // the block barrier below overlap with it); positions past the class read a valid entry
-    // of the table and are not used
-    int p = tile * kSwarThreads + threadIdx.x;
-    struct Entry {
-        int u, v0, v1, v2, v3;
-        uint32_t tab;
-    };
-    auto entry = [&](int q) {
-        const int32_t *T = a.sw + a.cbase + (q < a.csize ? q : 0);
-        return Entry{T[kSwU * ss], T[kSwV * ss], T[(kSwV + 1) * ss], T[(kSwV + 2) * ss],
+    const int32_t *T = a.sw + q;
+    return SwarEntry{T[kSwU * ss], T[kSwV * ss], T[(kSwV + 1) * ss], T[(kSwV + 2) * ss],
                      T[(kSwV + 3) * ss], (uint32_t)T[kSwTables * ss]};
-    };
-    Entry en = entry(p);
-    const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
-    const bool live = a.st->elite_fitness < a.target;
-    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
-    const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
-    __shared__ Acc fa[64];
-    __shared__ uint32_t redc[2][kSwarThreads / 64];
-    if (threadIdx.x < 64) fa[threadIdx.x] = 0;
-    __syncthreads();
-    if (!live) return;  // uniform over the grid
-    uint32_t n_eval = 0, n_acc = 0;
+}
+
+// The GOM step of every solution at once on the set of table entry q (univariate FOS): the
+// accepted mask is flipped into O[u] and each accepted solution's fitness change is added to
+// its LDS counter fa[j]; n_eval / n_acc count the lane's pairs with a donor / accepted.
+template <bool PARTITION, class Acc>
+__device__ __forceinline__ void swar_step(const SweepArgs &a, const SwarEntry &en, int q,
+                                          uint64_t popm, uint64_t nz, Acc *fa,
+                                          uint32_t &n_eval, uint32_t &n_acc) {
+    const size_t ss = (size_t)a.sw_stride;
     // change of solution base + j for every set bit j of m (one 32-bit half of the accepted
     // mask): 2 * (sum of w_k over the edges that become cut) - (sum of all four w_k)
     auto add_flips = [&](uint32_t m, int base, uint32_t h0, uint32_t h1, uint32_t h2,
@@ -1288,40 +1280,45 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
             atomicAdd(&fa[base + (int)j], (Acc)(2 * cut - wsum));
         }
     };
-    for (; p < a.csize; p += stride) {
-        if (p != tile * kSwarThreads + (int)threadIdx.x) en = entry(p);
-        const int32_t *T = a.sw + a.cbase + p;
-        const int u = en.u, v0 = en.v0, v1 = en.v1, v2 = en.v2, v3 = en.v3;
-        const uint32_t tab = en.tab;
-        const uint64_t o = a.O[u];
-        const uint64_t x = PARTITION ? o : a.P[u];
-        const uint64_t q0 = ~(o ^ a.O[v0]), q1 = ~(o ^ a.O[v1]);
-        const uint64_t q2 = ~(o ^ a.O[v2]), q3 = ~(o ^ a.O[v3]);
-        // donors: solutions with o_i = 1 need a zero of x other than i, o_i = 0 a one
-        const uint64_t ones = x & popm, zeros = ~x & popm;
-        const int co = __popcll(ones), cz = __popcll(zeros);
-        const uint64_t hz = cz >= 2 ? ~0ull : (cz == 1 ? ~zeros : 0ull);
-        const uint64_t ho = co >= 2 ? ~0ull : (co == 1 ? ~ones : 0ull);
-        const uint64_t has = ((o & hz) | (~o & ho)) & popm;
-        // truth tables over the 16 patterns, precomputed on the host
-        const uint32_t tp = tab & 0xFFFFu, tz = tab >> 16;
-        const uint64_t acc =
-            (table16(tp, q0, q1, q2, q3) | (table16(tz, q0, q1, q2, q3) & nz)) & has;
-        n_eval += (uint32_t)__popcll(has);
-        n_acc += (uint32_t)__popcll(acc);
-        if (acc) {
-            a.O[u] = o ^ acc;
-            // the weights are needed only here: loading them with the entry for every set
-            // costs more than this extra round trip for the sets that accept
-            const int w0 = T[kSwW * ss], w1 = T[(kSwW + 1) * ss];
-            const int w2 = T[(kSwW + 2) * ss], w3 = T[(kSwW + 3) * ss];
-            const int wsum = w0 + w1 + w2 + w3;
-            add_flips((uint32_t)acc, 0, (uint32_t)q0, (uint32_t)q1, (uint32_t)q2,
-                      (uint32_t)q3, w0, w1, w2, w3, wsum);
-            add_flips((uint32_t)(acc >> 32), 32, (uint32_t)(q0 >> 32), (uint32_t)(q1 >> 32),
-                      (uint32_t)(q2 >> 32), (uint32_t)(q3 >> 32), w0, w1, w2, w3, wsum);
-        }
+    const int32_t *T = a.sw + q;
+    const int u = en.u, v0 = en.v0, v1 = en.v1, v2 = en.v2, v3 = en.v3;
+    const uint32_t tab = en.tab;
+    const uint64_t o = a.O[u];
+    const uint64_t x = PARTITION ? o : a.P[u];
+    const uint64_t q0 = ~(o ^ a.O[v0]), q1 = ~(o ^ a.O[v1]);
+    const uint64_t q2 = ~(o ^ a.O[v2]), q3 = ~(o ^ a.O[v3]);
+    // donors: solutions with o_i = 1 need a zero of x other than i, o_i = 0 a one
+    const uint64_t ones = x & popm, zeros = ~x & popm;
+    const int co = __popcll(ones), cz = __popcll(zeros);
+    const uint64_t hz = cz >= 2 ? ~0ull : (cz == 1 ? ~zeros : 0ull);
+    const uint64_t ho = co >= 2 ? ~0ull : (co == 1 ? ~ones : 0ull);
+    const uint64_t has = ((o & hz) | (~o & ho)) & popm;
+    // truth tables over the 16 patterns, precomputed on the host
+    const uint32_t tp = tab & 0xFFFFu, tz = tab >> 16;
+    const uint64_t acc =
+        (table16(tp, q0, q1, q2, q3) | (table16(tz, q0, q1, q2, q3) & nz)) & has;
+    n_eval += (uint32_t)__popcll(has);
+    n_acc += (uint32_t)__popcll(acc);
+    if (acc) {
+        a.O[u] = o ^ acc;
+        // the weights are needed only here: loading them with the entry for every set
+        // costs more than this extra round trip for the sets that accept
+        const int w0 = T[kSwW * ss], w1 = T[(kSwW + 1) * ss];
+        const int w2 = T[(kSwW + 2) * ss], w3 = T[(kSwW + 3) * ss];
+        const int wsum = w0 + w1 + w2 + w3;
+        add_flips((uint32_t)acc, 0, (uint32_t)q0, (uint32_t)q1, (uint32_t)q2,
+                  (uint32_t)q3, w0, w1, w2, w3, wsum);
+        add_flips((uint32_t)(acc >> 32), 32, (uint32_t)(q0 >> 32), (uint32_t)(q1 >> 32),
+                  (uint32_t)(q2 >> 32), (uint32_t)(q3 >> 32), w0, w1, w2, w3, wsum);
     }
+}
+
+// Block totals of a bit-sliced sweep into the block's stripe: the LDS fitness counters of
+// the population's solutions and the wave sums of the pair counts.
+template <class Acc>
+__device__ __forceinline__ void swar_block_totals(const SweepArgs &a, const Acc *fa,
+                                                  uint32_t (*redc)[kSwarThreads / 64],
+                                                  uint32_t n_eval, uint32_t n_acc) {
     const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
@@ -1342,6 +1339,109 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
         if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
         if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
     }
+}
+
+// NARROW: the block's per-solution fitness sums fit in int32 (the host checks the weights'
+// bound), so they are kept as 32-bit LDS counters; else 64-bit.
+template <bool PARTITION, bool NARROW>
+__global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
+    using Acc = std::conditional_t<NARROW, int, unsigned long long>;
+    const int stride = gridDim.x * kSwarThreads;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    // the first set's table entry is loaded before anything waits (the run-state loads and
+    // the block barrier below overlap with it); positions past the class read a valid entry
+    // of the table and are not used
+    int p = tile * kSwarThreads + threadIdx.x;
+    SwarEntry en = swar_entry(a, a.cbase + (p < a.csize ? p : 0));
+    const uint64_t mism = a.stripes[threadIdx.x & 63].mism;
+    const bool live = a.st->elite_fitness < a.target;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
+    __shared__ Acc fa[64];
+    __shared__ uint32_t redc[2][kSwarThreads / 64];
+    if (threadIdx.x < 64) fa[threadIdx.x] = 0;
+    __syncthreads();
+    if (!live) return;  // uniform over the grid
+    uint32_t n_eval = 0, n_acc = 0;
+    for (; p < a.csize; p += stride) {
+        if (p != tile * kSwarThreads + (int)threadIdx.x) en = swar_entry(a, a.cbase + p);
+        swar_step<PARTITION>(a, en, a.cbase + p, popm, nz, fa, n_eval, n_acc);
+    }
+    swar_block_totals(a, fa, redc, n_eval, n_acc);
+}
+
+// Fused form: every class of the generation in one cooperative launch (all blocks resident at
+// once, so a block may wait for others).  Block b sweeps chunk x = xcd_tile(b, grid) of each
+// class in the generation's order.  Before a class it waits, one wave polling, until every
+// chunk of an earlier class that holds a conflicting set carries this launch's stamp; after
+// the class its threads' stores are made visible device-wide and the chunk is stamped.  A
+// wait that polls kFusedSpinLimit times gives up and sets st->stall (the host reports it), so
+// the kernel always ends.
+template <bool PARTITION, bool NARROW>
+__global__ __launch_bounds__(kSwarThreads) void k_uni_swar_fused(FusedArgs f) {
+    using Acc = std::conditional_t<NARROW, int, unsigned long long>;
+    const SweepArgs &a = f.a;
+    const int x = xcd_tile((int)blockIdx.x, f.grid);
+    const int lane = threadIdx.x & 63;
+    const uint64_t mism = a.stripes[lane].mism;
+    const bool live = a.st->elite_fitness < a.target;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
+    __shared__ Acc fa[64];
+    __shared__ uint32_t redc[2][kSwarThreads / 64];
+    if (threadIdx.x < 64) fa[threadIdx.x] = 0;
+    __syncthreads();
+    if (!live) return;  // uniform over the grid
+    uint32_t n_eval = 0, n_acc = 0;
+    for (int t = 0; t < f.k; ++t) {
+        const int c = f.order[t];
+        const int lo = x * f.clen[c];
+        const int hi = min(lo + f.clen[c], f.csize[c]);
+        int p = lo + (int)threadIdx.x;
+        // the chunk's first entries do not depend on other blocks: request them first
+        SwarEntry en = swar_entry(a, f.cbase[c] + (p < hi ? p : 0));
+        if (t > 0 && threadIdx.x < 64) {
+            // wave 0 polls the flags of the earlier classes' chunks this chunk depends on,
+            // lane l taking every 64th of them
+            const int4 *dep = f.dep + ((size_t)c * f.grid + x) * f.k;
+            uint32_t polls = 0;
+            bool gave_up = false;
+            for (int t2 = 0; t2 < t && !gave_up; ++t2) {
+                const int c2 = f.order[t2];
+                const int4 r4 = dep[c2];
+                for (int h = 0; h < 2 && !gave_up; ++h) {
+                    const int lo = h ? r4.z : r4.x, hi = h ? r4.w : r4.y;
+                    // an unused range ({0, -1}) or one outside [0, grid) indexes no flag
+                    if (lo < 0 || hi >= f.grid || lo > hi) continue;
+                    for (int y = lo + lane; y <= hi && !gave_up; y += 64) {
+                        uint32_t *fl = f.flags + (size_t)c2 * f.grid + y;
+                        while (__hip_atomic_load(fl, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
+                            if (++polls >= kFusedSpinLimit) {
+                                gave_up = true;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(2);
+                        }
+                    }
+                }
+            }
+            if (gave_up) atomicOr(const_cast<uint32_t *>(&a.st->stall), 1u);
+            __threadfence();  // the chunks' stores are visible to this block's loads
+        }
+        __syncthreads();
+        for (; p < hi; p += kSwarThreads) {
+            if (p != lo + (int)threadIdx.x) en = swar_entry(a, f.cbase[c] + p);
+            swar_step<PARTITION>(a, en, f.cbase[c] + p, popm, nz, fa, n_eval, n_acc);
+        }
+        __syncthreads();  // every store of the chunk is issued
+        if (threadIdx.x == 0) {
+            __threadfence();
+            __hip_atomic_store(f.flags + (size_t)c * f.grid + x, f.epoch, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    swar_block_totals(a, fa, redc, n_eval, n_acc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1674,7 +1774,9 @@ __global__ __launch_bounds__(kEpiThreads) void k_vertex_pass(EpilogueArgs a) {
 // the draws in parallel, the swaps by one thread), then runs the resident sweep.  The
 // finalize and vertex-pass blocks find their instance through the block maps.
 // ------------------------------------------------------------------------------------------
-template <int T>
+// KIND: the FOS kind of every instance of the launch (univariate records take far fewer
+// registers, so their blocks fill a CU twice as densely).
+template <int T, int KIND>
 __global__ __launch_bounds__(T) void k_batch_sweep(const BatchInst *insts, const int2 *blk) {
     extern __shared__ __align__(16) uint8_t lds_all[];
     uint16_t *order = reinterpret_cast<uint16_t *>(lds_all);
@@ -1701,17 +1803,10 @@ __global__ __launch_bounds__(T) void k_batch_sweep(const BatchInst *insts, const
         }
     __syncthreads();
     uint8_t *lds = lds_all + kBatchOrderBytes;
-    if (I->kind == 0) {
-        if (I->plds)
-            resident_body<0, true, T>(a, order, gen, bi.y, lds);
-        else
-            resident_body<0, false, T>(a, order, gen, bi.y, lds);
-    } else {
-        if (I->plds)
-            resident_body<1, true, T>(a, order, gen, bi.y, lds);
-        else
-            resident_body<1, false, T>(a, order, gen, bi.y, lds);
-    }
+    if (I->plds)
+        resident_body<KIND, true, T>(a, order, gen, bi.y, lds);
+    else
+        resident_body<KIND, false, T>(a, order, gen, bi.y, lds);
 }
 
 __global__ __launch_bounds__(64) void k_batch_finalize(const BatchInst *insts) {
@@ -1919,6 +2014,37 @@ hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow
     return hipGetLastError();
 }
 
+hipError_t fused_swar_grid(int *grid) {
+    int dev = 0, cus = 0, nb = 1 << 30;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *ks[4] = {(const void *)k_uni_swar_fused<true, true>,
+                         (const void *)k_uni_swar_fused<true, false>,
+                         (const void *)k_uni_swar_fused<false, true>,
+                         (const void *)k_uni_swar_fused<false, false>};
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) {
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, ks[q], kSwarThreads, 0);
+        nb = std::min(nb, b);
+    }
+    if (e != hipSuccess) return e;
+    *grid = std::max(0, std::min(kFusedMaxGrid, nb * cus));
+    return hipSuccess;
+}
+
+hipError_t launch_uni_swar_fused(const FusedArgs &f, bool partition, bool narrow,
+                                 hipStream_t s) {
+    if (f.grid < 1 || f.grid > kFusedMaxGrid || f.k < 1 || f.k > kFusedMaxClasses)
+        return hipErrorInvalidValue;
+    FusedArgs arg = f;
+    void *args[] = {&arg};
+    const void *k = partition ? (narrow ? (const void *)k_uni_swar_fused<true, true>
+                                        : (const void *)k_uni_swar_fused<true, false>)
+                              : (narrow ? (const void *)k_uni_swar_fused<false, true>
+                                        : (const void *)k_uni_swar_fused<false, false>);
+    return hipLaunchCooperativeKernel(k, dim3(f.grid), dim3(kSwarThreads), args, 0, s);
+}
+
 size_t resident_lds_bytes(int n, bool plds, int threads) {
     return (size_t)res_rng_bytes(threads) + kResRedBytes +
            (plds ? resident_words_bytes(n) : 0) + (((size_t)n + 15) & ~(size_t)15);
@@ -1941,11 +2067,29 @@ hipError_t launch_resident_sweep(const ResidentArgs &a, int kind, bool plds, hip
     return plds ? launch_resident_t<1, true>(a, s, ev) : launch_resident_t<1, false>(a, s, ev);
 }
 
+// The batched sweep kernel of a launch group.
+static const void *batch_kernel(int threads, int kind) {
+    if (threads == 256)
+        return kind == 0 ? (const void *)k_batch_sweep<256, 0> : (const void *)k_batch_sweep<256, 1>;
+    return kind == 0 ? (const void *)k_batch_sweep<1024, 0> : (const void *)k_batch_sweep<1024, 1>;
+}
+
+hipError_t batch_sweep_occupancy(int threads, int kind, int *blocks) {
+    if (threads != 256 && threads != 1024) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel(threads, kind),
+                                                        threads, 0);
+}
+
 hipError_t prepare_batch_step(const BatchLaunch *groups, int n_groups) {
     for (int q = 0; q < n_groups; ++q) {
-        const hipError_t e = groups[q].threads == 256
-                                 ? raise_lds_limit<k_batch_sweep<256>>(groups[q].lds)
-                                 : raise_lds_limit<k_batch_sweep<1024>>(groups[q].lds);
+        const BatchLaunch &G = groups[q];
+        hipError_t e;
+        if (G.threads == 256)
+            e = G.kind == 0 ? raise_lds_limit<k_batch_sweep<256, 0>>(G.lds)
+                            : raise_lds_limit<k_batch_sweep<256, 1>>(G.lds);
+        else
+            e = G.kind == 0 ? raise_lds_limit<k_batch_sweep<1024, 0>>(G.lds)
+                            : raise_lds_limit<k_batch_sweep<1024, 1>>(G.lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1963,12 +2107,17 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
         KernelEvents gev;
         gev.start = q == 0 ? ev.start : nullptr;
         gev.stop = q == n_groups - 1 ? ev.stop : nullptr;
-        if (G.threads == 256)
-            launch_timed(k_batch_sweep<256>, dim3(G.count), dim3(256), G.lds, s, gev, insts,
-                         blk + G.first);
+        const int2 *gb = blk + G.first;
+        if (G.threads == 256 && G.kind == 0)
+            launch_timed(k_batch_sweep<256, 0>, dim3(G.count), dim3(256), G.lds, s, gev, insts, gb);
+        else if (G.threads == 256)
+            launch_timed(k_batch_sweep<256, 1>, dim3(G.count), dim3(256), G.lds, s, gev, insts, gb);
+        else if (G.kind == 0)
+            launch_timed(k_batch_sweep<1024, 0>, dim3(G.count), dim3(1024), G.lds, s, gev, insts,
+                         gb);
         else
-            launch_timed(k_batch_sweep<1024>, dim3(G.count), dim3(1024), G.lds, s, gev, insts,
-                         blk + G.first);
+            launch_timed(k_batch_sweep<1024, 1>, dim3(G.count), dim3(1024), G.lds, s, gev, insts,
+                         gb);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

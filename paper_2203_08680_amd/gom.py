@@ -29,7 +29,8 @@ EXPORTED = (
     "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
-    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_local_search",
+    "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_state_set_fused",
+    "gom_state_get_fused", "gom_local_search",
     "gom_iterated_local_search",
     "gom_ims_bytes",
     "gom_ims_run",
@@ -121,6 +122,8 @@ def lib() -> C.CDLL:
         "gom_ims_run": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _u64, C.c_int, C.c_int, _i64,
                                   _i32, _vp, _sz, _vp, _vp, _vp]),
         "gom_state_get_block": (C.c_int, [_vp, _P(C.c_int)]),
+        "gom_state_set_fused": (C.c_int, [_vp, C.c_int]),
+        "gom_state_get_fused": (C.c_int, [_vp, _P(C.c_int), _P(C.c_int)]),
         "gom_state_get_fi": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
         "gom_state_hash": (C.c_int, [_vp, _vp, _P(C.c_uint64)]),
@@ -449,6 +452,18 @@ def gom_state_hash(s: GomState, stream=None) -> int:
     v = C.c_uint64()
     _check(lib().gom_state_hash(s.handle, _stream_handle(stream), C.byref(v)))
     return int(v.value)
+
+
+def gom_state_set_fused(s: GomState, enabled: bool) -> None:
+    """Whole generations of the bit-sliced schedule as one fused launch (when available)."""
+    _check(lib().gom_state_set_fused(s.handle, 1 if enabled else 0))
+
+
+def gom_state_get_fused(s: GomState):
+    """(in use, available)."""
+    e, a = C.c_int(), C.c_int()
+    _check(lib().gom_state_get_fused(s.handle, C.byref(e), C.byref(a)))
+    return bool(e.value), bool(a.value)
 
 
 def gom_state_set_block(s: GomState, threads: int) -> None:

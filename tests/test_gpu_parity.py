@@ -359,15 +359,17 @@ def test_autotune_generations_are_ordinary(cuda, kind):
     print(f"case autotune kind={kind}", flush=True)
     g = workloads.torus(20, 1, 9, seed=3)
     _, st, ref = make_pair(g, kind, 24, 5)
+    fused_available = gom.gom_state_get_fused(st)[1]
     chosen = gom.gom_state_autotune(st, 2)
     allowed = {gom.GOM_SCHED_CLASS_LAUNCH, gom.GOM_SCHED_RESIDENT}
     if kind == 0:
         allowed.add(gom.GOM_SCHED_BITSLICED)
     assert chosen in allowed and gom.gom_state_get_schedule(st) == chosen
     done = gom.gom_state_read(st, genes=False)["generation"]
-    # class launch is tried with blocks of 64, 128, 256 and 512 threads; two rounds of one
-    # untimed and two timed generations per candidate
-    assert done == 2 * 3 * (len(allowed) + 3)
+    # class launch is tried with blocks of 64, 128, 256 and 512 threads, the bit-sliced
+    # schedule with and without its fused form; two rounds of one untimed and two timed
+    # generations per candidate
+    assert done == 2 * 3 * (len(allowed) + 3 + (1 if kind == 0 and fused_available else 0))
     assert gom.gom_state_get_block(st) in (64, 128, 256, 512)
     for _ in range(done):
         ref.generation()
@@ -729,13 +731,16 @@ BITSLICED_CASES = [
 ]
 
 
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "per_class"])
 @pytest.mark.parametrize("label,maker,pop,rule,dups", BITSLICED_CASES,
                          ids=[c[0] for c in BITSLICED_CASES])
-def test_bitsliced_univariate(cuda, label, maker, pop, rule, dups):
+def test_bitsliced_univariate(cuda, label, maker, pop, rule, dups, fused):
     """Bit-sliced schedule (lane = set, all solutions in one word) on univariate FOS of graphs
     with degree <= 4, negative weights included; with duplicated singletons the sets are no
-    longer a partition (the kernel then reads P as well as O)."""
-    print(f"case bitsliced {label}", flush=True)
+    longer a partition (the kernel then reads P as well as O).  Each case runs with the fused
+    generation sweep where it is available (on these small graphs it is, including chunks
+    that depend on no chunk of some other class) and with one launch per class."""
+    print(f"case bitsliced {label} fused={fused}", flush=True)
     g = maker()
     if dups:
         sets = [[v] for v in range(g.n)] + [[v] for v in range(0, g.n, 3)]
@@ -747,7 +752,64 @@ def test_bitsliced_univariate(cuda, label, maker, pop, rule, dups):
     else:
         _, st, ref = make_pair(g, 0, pop, seed=7, rule=rule, sched=gom.GOM_SCHED_BITSLICED)
     assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_BITSLICED
-    lockstep(st, ref, 12, f"bitsliced {label}")
+    if gom.gom_state_get_fused(st)[1]:
+        gom.gom_state_set_fused(st, fused)
+    elif fused:
+        pytest.skip("the fused sweep is not available for this graph")
+    assert gom.gom_state_get_fused(st)[0] == fused
+    lockstep(st, ref, 12, f"bitsliced {label} fused={fused}")
+
+
+FUSED_CASES = [
+    # (label, graph maker, population, neutral rule)
+    ("torus10_p16", lambda: workloads.torus(10, 1, 5, seed=1), 16, 0),
+    ("torus33_p64_always", lambda: workloads.torus(33, 1, 9, seed=4), 64, 1),   # 3 classes
+    ("torus120_p40", lambda: workloads.torus(120, 1, 100, seed=15), 40, 0),
+    ("torus300x_p64_w2e27", lambda: workloads.torus(300, 1, 1 << 27, seed=16), 64, 0),
+]
+
+
+@pytest.mark.parametrize("label,maker,pop,rule", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_bitsliced_fused(cuda, label, maker, pop, rule):
+    """Tori under the fused bit-sliced sweep (all classes of a generation in one launch, each
+    chunk waiting for the conflicting chunks of earlier classes) against the oracle every
+    generation, and against the per-class launches; a generation cut by the debug stop runs
+    its remaining classes class by class."""
+    print(f"case fused {label}", flush=True)
+    g = maker()
+    _, st, ref = make_pair(g, 0, pop, seed=9, rule=rule, sched=gom.GOM_SCHED_BITSLICED)
+    assert gom.gom_state_get_fused(st) == (True, True)
+    inst = gom.Instance(g.n, g.u, g.v, g.w, 0)
+    other = inst.state(pop=pop, seed=9, neutral_rule=rule)
+    gom.gom_state_set_schedule(other, gom.GOM_SCHED_BITSLICED)
+    gom.gom_state_set_fused(other, False)
+    assert gom.gom_state_get_fused(other) == (False, True)
+    lockstep(st, ref, 8, f"fused {label}")
+    for _ in range(8):
+        gom.gom_generation(other)
+    assert gom.gom_state_hash(other) == gom.gom_state_hash(st)
+    gom.gom_debug_stop_after_class(st, 0)
+    ref.stop_after_class(0)
+    assert gom.gom_state_hash(st) == ref.hash()
+    lockstep(st, ref, 3, f"fused {label} after a cut generation")
+    r = gom.gom_run_to_target(st, g.total_weight, 40)
+    ran = ref.run(g.total_weight, 40)
+    assert r.generations == ran
+    assert_same(gom.gom_state_read(st), ref.state(), f"fused {label} run to target")
+
+
+def test_bitsliced_fused_not_available_on_random_graphs(cuda):
+    """A large random graph's chunks depend on chunks all over the other classes: no fused
+    sweep."""
+    g = workloads.configuration_model(200_000, 4, seed=17, weights="uniform", w_lo=1,
+                                      w_hi=100)
+    inst = gom.Instance(g.n, g.u, g.v, g.w, 0)
+    st = inst.state(pop=16, seed=1)
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+    assert gom.gom_state_get_fused(st) == (False, False)
+    with pytest.raises(gom.GomError) as e:
+        gom.gom_state_set_fused(st, True)
+    assert e.value.code == gom.GOM_E_RANGE
 
 
 def test_bitsliced_full_size(cuda):

@@ -147,6 +147,17 @@ WORKLOADS = {
 # 1000x1000 torus (10^6 vertices), weights U{1..100}: the HBM-bound size.
 WORKLOADS["torus1000_uni_p64"] = Workload("torus1000_uni_p64", _t1000, 0, 64, 1000, True)
 WORKLOADS["torus1000_nbhd_p64"] = Workload("torus1000_nbhd_p64", _t1000, 1, 64, 1000, True)
+# Random 4- and 8-regular graphs with 10^6 vertices, weights U{1..100}, univariate FOS: the
+# HBM-bound size beyond the torus (degree 8 is outside the bit-sliced sweep's degree limit).
+for _d in (4, 8):
+    WORKLOADS[f"cm1m_d{_d}_uni_p64"] = Workload(
+        f"cm1m_d{_d}_uni_p64",
+        (lambda d: lambda: configuration_model(1_000_000, d, seed=5, weights="uniform",
+                                               w_lo=1, w_hi=100))(_d), 0, 64, 200, False)
+# 3162x3162 torus (10^7 vertices), weights U{1..100}, univariate FOS: a working set (about
+# 520 MB) larger than the 256 MB Infinity Cache, so the sweep's traffic reaches HBM.
+WORKLOADS["torus3162_uni_p64"] = Workload("torus3162_uni_p64",
+                                          lambda: torus(3162, 1, 100, seed=9), 0, 64, 100, True)
 # 100x100 torus, weights U{1..100}, univariate FOS (the graph's own colouring: the classes of
 # the colouring-parallel local search).
 WORKLOADS["torus100_uni_p64"] = Workload("torus100_uni_p64", _c2, 0, 64, 500, True)
