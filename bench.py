@@ -314,6 +314,8 @@ def run_batch_mode(args, torch, gom):
     plain, plain_t, plain_hash = [], [], []
     t0 = time.perf_counter()
     for x, p, sd, tg in zip(insts, pops, seeds0, targets):
+        if args.no_plain:
+            break
         st = x.state(pop=p, seed=sd)
         torch.cuda.synchronize()
         s0 = time.perf_counter()
@@ -324,17 +326,17 @@ def run_batch_mode(args, torch, gom):
         del st
     t_plain = sum(plain_t)
     ev_plain = sum(r.attempted for r in plain)
-    same = same_timed and all(
+    same = None if args.no_plain else same_timed and all(
         (a.generations, a.reached, a.best, a.attempted, a.evaluated, a.accepted, ha) ==
         (b.generations, b.reached, b.best, b.attempted, b.evaluated, b.accepted, hb)
         for a, b, ha, hb in zip(steps[0][0], plain, batch_hash, plain_hash))
     log(f"plain: {t_plain * 1e3:.1f} ms for the first step's seeds, identical results: {same}")
 
     value = attempted / total
-    plain_value = ev_plain / t_plain
+    plain_value = ev_plain / t_plain if plain else None
     res0, tt0, t_step0 = steps[0]
     tori = [b for b, it in enumerate(items) if it.to_total_weight and res0[b].reached]
-    loop_t = np.cumsum(plain_t) * 1e3
+    loop_t = np.cumsum(plain_t) * 1e3 if plain else np.zeros(len(items))
     q = lambda x, p: float(np.percentile(np.asarray(x), p)) if len(x) else None
 
     # roofline of the batched sweep: the algorithmic bytes of every instance-generation the
@@ -380,19 +382,19 @@ def run_batch_mode(args, torch, gom):
                    "step": "fresh populations (new seeds) and a batched run of the whole mix "
                            "to every target or the generation limit"},
         "evaluated_per_s": evaluated / total,
-        "plain": {"value": plain_value, "ms": t_plain * 1e3,
-                  "seeds": "the first timed step's",
-                  "schedule": "auto per instance, one instance at a time"},
-        "batched_over_plain": value / plain_value,
+        "plain": None if not plain else {
+            "value": plain_value, "ms": t_plain * 1e3, "seeds": "the first timed step's",
+            "schedule": "auto per instance, one instance at a time"},
+        "batched_over_plain": value / plain_value if plain else None,
         "identical_results": same,
         "time_to_optimum_ms": {
             "instances_reached": len(tori),
             "batched_p50": q([tt0[b] for b in tori], 50),
             "batched_p99": q([tt0[b] for b in tori], 99),
-            "plain_loop_p50": q([loop_t[b] for b in tori], 50),
-            "plain_loop_p99": q([loop_t[b] for b in tori], 99),
-            "plain_alone_p50": q([plain_t[b] * 1e3 for b in tori], 50),
-            "plain_alone_p99": q([plain_t[b] * 1e3 for b in tori], 99),
+            "plain_loop_p50": q([loop_t[b] for b in tori], 50) if plain else None,
+            "plain_loop_p99": q([loop_t[b] for b in tori], 99) if plain else None,
+            "plain_alone_p50": q([plain_t[b] * 1e3 for b in tori], 50) if plain else None,
+            "plain_alone_p99": q([plain_t[b] * 1e3 for b in tori], 99) if plain else None,
             "note": None if tori else
             f"no torus of this mix reaches its total weight within {max_gens} generations "
             "in either mode (the pinned method without forced improvement stalls below the "
@@ -564,6 +566,8 @@ def main():
                          "per instance for the batched mix, 40 for a single workload)")
     ap.add_argument("--cpu-instances", type=int, default=8,
                     help="instances of the batched mix in the oracle sample")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched mode: skip the plain loop (no identity check; for profiling)")
     ap.add_argument("--no-small-mix", action="store_true",
                     help="batched mode: skip the time-to-optimum comparison on the mix of "
                          "small instances")

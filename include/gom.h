@@ -355,6 +355,12 @@ int gom_state_get_fi(const gom_state *s, int *enabled);
  * gom_state_set_fused errors: GOM_E_ARG, GOM_E_RANGE (not available).
  */
 int gom_state_set_fused(gom_state *s, int enabled);
+/*
+ * Grid cap (blocks) of the per-class sweeps (default 2048): a class larger than the cap's
+ * threads is swept with each group striding over several positions.  For tuning and tests;
+ * results do not depend on it.  Errors: GOM_E_ARG, GOM_E_RANGE (outside 1..65536).
+ */
+int gom_state_set_grid_limit(gom_state *s, int32_t blocks);
 int gom_state_get_fused(const gom_state *s, int *enabled, int *available);
 int gom_state_set_block(gom_state *s, int threads);
 int gom_state_get_block(const gom_state *s, int *threads);
@@ -388,8 +394,10 @@ void gom_state_free(gom_state *s);
  *   - a vertex-pass launch over all instances' vertices.
  * Every instance follows exactly the trajectory it has when run alone with the same seed:
  * batching changes when work runs, not what is computed.  Instances whose elitist has reached
- * their target stop changing.  Every instance must fit the resident schedule (n bytes of LDS,
- * at most GOM_RESIDENT_MAX_CLASSES classes).
+ * their target stop changing.  An instance beyond the resident schedule (its offspring bytes
+ * do not fit in LDS, or more than GOM_RESIDENT_MAX_CLASSES classes) runs its own per-class
+ * sweeps and epilogue within each step, with the schedule its state chooses (bit-sliced or
+ * class launch); those launches are enqueued after the captured graph of a chunk.
  */
 typedef struct gom_batch gom_batch;
 
@@ -402,8 +410,8 @@ int gom_batch_bytes(int32_t count, const mc_graph *const *graphs, const gom_fos 
  * instance b gets population pops[b], seed seeds[b] and target targets[b] (the elitist
  * fitness at which it stops).  Neutral rule and class order as for gom_state_init.  Host
  * arrays are borrowed; graphs and FOS may be freed afterwards.  Synchronous.
- * Errors: GOM_E_ARG, GOM_E_RANGE (an instance does not fit the resident schedule, population
- * outside 2..64), GOM_E_STATE (FOS not coloured), GOM_E_NOMEM, GOM_E_DEVICE.
+ * Errors: GOM_E_ARG, GOM_E_RANGE (population outside 2..64), GOM_E_STATE (FOS not
+ * coloured), GOM_E_NOMEM, GOM_E_DEVICE.
  */
 int gom_batch_init(int32_t count, const mc_graph *const *graphs, const gom_fos *const *fos,
                    const int32_t *pops, const uint64_t *seeds, const int64_t *targets,

@@ -481,7 +481,8 @@ struct gom_state {
     int64_t attempted_base = 0;
     DevState *h_st = nullptr;           // two pinned host slots
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
-    int max_grid = 2048;
+    int max_grid = 2048;                // grid cap of the class sweeps
+    int64_t swar_abs = 0;               // largest per-vertex |weight| sum (bit-sliced sweep)
     int sweep_threads = 256;            // class-launch block size (64..512)
     int timing = 0;                     // sample period of the sweep-launch events (0 = off)
     int64_t sweep_launches = 0;         // sweep launches enqueued (for the sampling)
@@ -1214,6 +1215,16 @@ static int auto_schedule(const gom_state *s) {
     return GOM_SCHED_CLASS_LAUNCH;
 }
 
+// The bit-sliced sweep's 32-bit block counters suffice: a block sums the changes of at most
+// 256 threads x (sets per thread) flips per solution, each at most the largest per-vertex
+// |weight| sum.
+static bool swar_narrow_ok(const gom_state *s) {
+    const int64_t per_thread =
+        ((int64_t)s->max_class + (int64_t)s->max_grid * kSwarThreads - 1) /
+        ((int64_t)s->max_grid * kSwarThreads);
+    return s->swar_abs * kSwarThreads * per_thread < ((int64_t)1 << 31);
+}
+
 // pinned_host: the run-scalar read-back buffer is pinned host memory (hipHostMalloc); else
 // ordinary host memory, so that the state's creation allocates nothing through HIP.
 static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
@@ -1319,11 +1330,8 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
                          resident_lds_bytes(s->n, false) <= s->lds_max;
         s->resident_plds = s->resident_ok && resident_lds_bytes(s->n, true) <= s->lds_max;
         s->bitsliced_ok = swar;
-        // a block sums the changes of at most 256 threads x (sets per thread) flips per solution
-        const int64_t per_thread =
-            ((int64_t)s->max_class + (int64_t)s->max_grid * kSwarThreads - 1) /
-            ((int64_t)s->max_grid * kSwarThreads);
-        s->swar_narrow = swar && swar_abs * kSwarThreads * per_thread < ((int64_t)1 << 31);
+        s->swar_abs = swar_abs;
+        s->swar_narrow = swar && swar_narrow_ok(s);
         s->partition = s->univariate && f->n_sets == g->n;
         s->sched = auto_schedule(s);
     }
@@ -1900,6 +1908,15 @@ extern "C" int gom_state_set_block(gom_state *s, int threads) {
     return GOM_OK;
 }
 
+extern "C" int gom_state_set_grid_limit(gom_state *s, int32_t blocks) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_grid_limit: null state");
+    if (blocks < 1 || blocks > 65536)
+        return fail(GOM_E_RANGE, "gom_state_set_grid_limit: %d blocks (1..65536)", blocks);
+    s->max_grid = blocks;
+    s->swar_narrow = s->bitsliced_ok && swar_narrow_ok(s);
+    return GOM_OK;
+}
+
 extern "C" int gom_state_get_block(const gom_state *s, int *threads) {
     if (!s || !threads) return fail(GOM_E_ARG, "gom_state_get_block: null argument");
     *threads = s->sweep_threads;
@@ -1962,6 +1979,7 @@ struct gom_batch {
     DevState *d_snap = nullptr;         // packed copy of the instances' run scalars
     int vblocks = 0;
     std::vector<BatchLaunch> groups;    // sweep launch groups of the current block sizes
+    std::vector<int32_t> solo;          // instances that run their own sweeps in each step
     int64_t narrow_max_n = -1;          // instances with n <= this run 256-thread blocks
     size_t lds_max = 0;                 // LDS per CU of the device
     DevState *h_st = nullptr;           // pinned, 2 x count
@@ -2085,7 +2103,9 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
     items.reserve((size_t)b->count);
     for (int32_t i = 0; i < b->count; ++i) {
         const gom_state *s = b->subs[(size_t)i];
-        const int T = (int64_t)s->n <= narrow_max_n ? 256 : 1024;
+        if (b->h_insts[(size_t)i].solo) continue;
+        int T = (int64_t)s->n <= narrow_max_n ? 256 : 1024;
+        if (kBatchOrderBytes + resident_lds_bytes(s->n, false, T) > b->lds_max) T = 256;
         const size_t l0 = kBatchOrderBytes + resident_lds_bytes(s->n, false, T);
         const size_t l1 = kBatchOrderBytes + resident_lds_bytes(s->n, true, T);
         if (l0 > b->lds_max)
@@ -2106,18 +2126,62 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
         if (x.occ != y.occ) return x.occ < y.occ;
         return x.cost > y.cost;
     });
+    // Launch groups; inside a group, every instance's blocks go to one XCD (the dispatcher
+    // sends block j of a launch to XCD j mod 8): instances are spread over the 8 XCDs by
+    // decreasing work (population x block cost) onto the least loaded, and the block list
+    // interleaves the XCDs' lists, so an instance's records and population words are fetched
+    // into one L2 instead of eight.  A list that runs out early is topped up from the longest.
     std::vector<int2> blk;
     std::vector<BatchLaunch> groups;
-    for (size_t q = 0; q < items.size(); ++q) {
-        const Item &it = items[q];
-        if (groups.empty() || q == 0 || it.threads != items[q - 1].threads ||
-            it.kind != items[q - 1].kind || it.occ != items[q - 1].occ)
-            groups.push_back(BatchLaunch{(int)blk.size(), 0, it.threads, it.kind, 0});
-        BatchLaunch &G = groups.back();
-        const gom_state *s = b->subs[(size_t)it.inst];
-        for (int32_t i = 0; i < s->N; ++i) blk.push_back(make_int2(it.inst, i));
-        G.count += s->N;
-        G.lds = std::max(G.lds, it.lds);
+    constexpr int kXcds = 8;
+    size_t q0 = 0;
+    while (q0 < items.size()) {
+        size_t q1 = q0 + 1;
+        while (q1 < items.size() && items[q1].threads == items[q0].threads &&
+               items[q1].kind == items[q0].kind && items[q1].occ == items[q0].occ)
+            ++q1;
+        BatchLaunch G{(int)blk.size(), 0, items[q0].threads, items[q0].kind, 0};
+        std::vector<std::deque<int2>> bins(kXcds);
+        std::vector<double> load(kXcds, 0.0);
+        std::vector<size_t> order;
+        for (size_t q = q0; q < q1; ++q) order.push_back(q);
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            const double wx = items[x].cost * b->subs[(size_t)items[x].inst]->N;
+            const double wy = items[y].cost * b->subs[(size_t)items[y].inst]->N;
+            return wx > wy;
+        });
+        for (size_t q : order) {
+            const Item &it = items[q];
+            const int32_t N = b->subs[(size_t)it.inst]->N;
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[(size_t)x] += it.cost * N;
+            for (int32_t i = 0; i < N; ++i) bins[(size_t)x].push_back(make_int2(it.inst, i));
+            G.count += N;
+            G.lds = std::max(G.lds, it.lds);
+        }
+        // each XCD's list longest blocks first (the instances were placed in that order of
+        // work, and a block's cost decides its length)
+        for (auto &bin : bins)
+            std::stable_sort(bin.begin(), bin.end(), [&](const int2 &u, const int2 &v) {
+                auto cost = [&](const int2 &e) {
+                    const gom_state *s = b->subs[(size_t)e.x];
+                    return (double)s->k + (double)s->n_sets / G.threads;
+                };
+                return cost(u) > cost(v);
+            });
+        for (int j = 0; j < G.count; ++j) {
+            size_t x = (size_t)(j % kXcds);
+            if (bins[x].empty()) {
+                size_t best = 0;
+                for (size_t y = 1; y < bins.size(); ++y)
+                    if (bins[y].size() > bins[best].size()) best = y;
+                x = best;
+            }
+            blk.push_back(bins[x].front());
+            bins[x].pop_front();
+        }
+        groups.push_back(G);
+        q0 = q1;
     }
     HIP_TRY(hipStreamSynchronize(st));  // nothing in flight reads the tables
     HIP_TRY(hipMemcpyAsync(b->d_insts, b->h_insts.data(), sizeof(BatchInst) * b->h_insts.size(),
@@ -2173,25 +2237,30 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
                             arena + B.sub_off[(size_t)b], B.sub_bytes[(size_t)b], stream, &s);
         if (rc) return cleanup(rc);
         bt->subs.push_back(s);
-        const size_t need = kBatchOrderBytes + resident_lds_bytes(s->n, false);
-        if (!s->resident_ok || need > s->lds_max)
-            return cleanup(fail(GOM_E_RANGE, "gom_batch_init: instance %d does not fit the "
-                                "resident schedule (n = %d, %d classes)", b, s->n, s->k));
+        const size_t need = kBatchOrderBytes + resident_lds_bytes(s->n, false, 256);
         bt->lds_max = s->lds_max;
         BatchInst &I = insts[(size_t)b];
         I.plds = 0;  // set with the block sizes (batch_regroup)
         I.res = resident_ctx(s, targets[b]);
-        I.epi = epilogue_args(s, targets[b], true);
         I.kind = s->univariate ? 0 : 1;
         I.order_fixed = s->order == GOM_ORDER_FIXED;
+        // an instance beyond the resident schedule (LDS or classes) runs its own sweeps in
+        // each step, with the schedule its state chose (bit-sliced or class launch)
+        I.solo = !s->resident_ok || need > s->lds_max;
+        I.epi = epilogue_args(s, targets[b], !I.solo);
         I.vblock0 = (int32_t)vblk.size();
-        for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back(b);
+        if (I.solo) {
+            if (s->sched == GOM_SCHED_RESIDENT) s->sched = GOM_SCHED_CLASS_LAUNCH;
+            bt->solo.push_back(b);
+        } else {
+            for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back(b);
+        }
     }
     bt->d_insts = (BatchInst *)(arena + B.insts);
     bt->d_blk = (int2 *)(arena + B.blk);
     bt->d_vblk = (int32_t *)(arena + B.vblk);
     bt->d_snap = (DevState *)(arena + B.snap);
-    bt->vblocks = B.vblocks;
+    bt->vblocks = (int)vblk.size();
     int khz = 0, dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
@@ -2263,6 +2332,20 @@ static bool batch_all_done(const gom_batch *b, int slot) {
     for (int32_t i = 0; i < b->count; ++i)
         if (h[i].elite_fitness < b->targets[(size_t)i]) return false;
     return true;
+}
+
+// `steps` generations of every instance that runs its own sweeps (solo), enqueued after the
+// batched launches of the same steps; its generation index is kept on the host.
+static int batch_solo_steps(gom_batch *b, int32_t steps, hipStream_t st) {
+    for (int32_t i : b->solo) {
+        gom_state *s = b->subs[(size_t)i];
+        for (int32_t t = 0; t < steps; ++t) {
+            const int rc = enqueue_generation(s, s->g_host, b->targets[(size_t)i], st);
+            if (rc) return rc;
+            s->g_host++;
+        }
+    }
+    return GOM_OK;
 }
 
 // Events of the next timed sweep launch (timing on), from the batch's pool; when the pool is
@@ -2355,7 +2438,10 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
     HIP_TRY(batch_snapshot(b, 0, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::vector<int32_t> g0((size_t)b->count);
-    for (int32_t i = 0; i < b->count; ++i) g0[(size_t)i] = b->h_st[i].generation;
+    for (int32_t i = 0; i < b->count; ++i) {
+        g0[(size_t)i] = b->h_st[i].generation;
+        b->subs[(size_t)i]->g_host = b->h_st[i].generation;
+    }
     constexpr int32_t kChunk = 4;
     if (!batch_all_done(b, 0)) {
         int32_t issued = b->g_done;
@@ -2368,6 +2454,13 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
                 if (n == kChunk && b->use_graph && !b->timing) {
                     HIP_TRY(batch_chunk_graph(b, kChunk));
                     HIP_TRY(hipGraphLaunch(b->graph_exec, st));
+                    if (!b->solo.empty()) {
+                        // the solo instances' generations (their class orders are drawn on
+                        // the host, so they stay out of the graph), then the scalars again
+                        const int rc = batch_solo_steps(b, kChunk, st);
+                        if (rc) return rc;
+                        HIP_TRY(launch_batch_gather(b->d_insts, b->count, b->d_snap, st));
+                    }
                     HIP_TRY(hipMemcpyAsync(b->h_st + (size_t)cur * (size_t)b->count, b->d_snap,
                                            sizeof(DevState) * (size_t)b->count,
                                            hipMemcpyDeviceToHost, st));
@@ -2379,6 +2472,8 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
                         HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk,
                                                   b->groups.data(), (int)b->groups.size(),
                                                   b->d_vblk, b->vblocks, st, ev));
+                        const int src = batch_solo_steps(b, 1, st);
+                        if (src) return src;
                     }
                     HIP_TRY(batch_snapshot(b, cur, st));
                 }
@@ -2480,9 +2575,12 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
             rc = batch_regroup(b, cands[q], st);
             if (rc) break;
             e = hipEventRecord(e0, st);
-            for (int32_t t = 0; t < trial_steps && e == hipSuccess; ++t)
+            for (int32_t t = 0; t < trial_steps && e == hipSuccess && rc == GOM_OK; ++t) {
                 e = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
                                       (int)b->groups.size(), b->d_vblk, b->vblocks, st);
+                if (e == hipSuccess) rc = batch_solo_steps(b, 1, st);
+            }
+            if (rc) break;
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;

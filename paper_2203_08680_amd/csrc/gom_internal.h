@@ -278,6 +278,9 @@ struct BatchInst {
     int32_t order_fixed;    // class order ascending instead of shuffled
     int32_t vblock0;        // first vertex-pass block of the instance
     int32_t plds;           // the sweep keeps a copy of P in LDS
+    int32_t solo;           // too large for the resident schedule: the instance runs its own
+                            // per-class sweeps and epilogue in each step (the batched
+                            // finalize and vertex pass skip it)
 };
 
 // Dynamic LDS of the batched sweep before the resident part: class order and draws.

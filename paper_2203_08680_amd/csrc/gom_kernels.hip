@@ -645,8 +645,13 @@ struct PlaneCommit {
 
 // B: record entries fetched per batch (4 for classes whose records have at most 16 entries:
 // fewer scalar registers live, fewer spills; else 8).
-template <int G, int KIND, bool FI, int B>
+// PPW: class positions per group and wave tile, 1 or 8.  With 8, a group sweeps the eight
+// consecutive positions whose donor draws come from one Philox call, and draws it once
+// instead of once per position (used for classes large enough that every group strides over
+// at least eight positions anyway).
+template <int G, int KIND, bool FI, int B, int PPW = 1>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
+    static_assert(PPW == 1 || (PPW == 8 && KIND != 0 && !FI), "shared draws: general, GOM");
     constexpr int GPW = 64 / G;          // sets per wave
     const int lane = threadIdx.x & 63;
     const int grp = lane / G;
@@ -662,13 +667,13 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     auto record = [&](int p) {
         return Rec{a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p]};
     };
-    auto position = [&](int wt) {
-        const int q = wt * GPW + grp;
+    auto position = [&](int wt, int f) {
+        const int q = (wt * GPW + grp) * PPW + f;
         return U ? __builtin_amdgcn_readfirstlane(q) : q;
     };
     // the first record's loads are issued before anything waits: the run-state loads and the
     // stripe reductions below overlap with them
-    int p = position(gw);
+    int p = position(gw, 0);
     Rec R = record(p < a.csize ? p : 0);
     HeadT<B> hd = load_head<KIND, B>(R);
     // (no branch before the loop: it would split the block and delay the record loads)
@@ -695,9 +700,16 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     bool flag = false;  // GOM: an accepted step; forced improvement: a step that improved
     const PlaneBits bits{a.O, i};
     const PlaneCommit<G> commit{a.O, grp, i};
-    const int nwt = (a.csize + GPW - 1) / GPW;  // wave tiles
+    const int nwt = (a.csize + GPW * PPW - 1) / (GPW * PPW);  // wave tiles
+    U32x4 draw{0u, 0u, 0u, 0u};  // the Philox call of the group's current eight positions
+    int f = 0;                   // position within the group's tile (PPW > 1)
     for (int wt = gw; live && wt < nwt;) {
         bool take = p < a.csize;
+        if constexpr (PPW > 1) {
+            // the tile's call: solution i, counter word 3 = p / 8 (the same for its 8 positions)
+            if (f == 0 && take)
+                draw = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i, (uint32_t)(p >> 3));
+        }
         if constexpr (KIND != 0) {
             const int nm = hd.h0.x;
             if (a.coop && nm >= kCoopMinMembers && nm <= kCoopMaxMembers) take = false;
@@ -711,12 +723,13 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
                 uint32_t h = 0;
                 if constexpr (KIND != 0) {
                     // each lane draws its own call; the 8 positions of a chunk share it
-                    const U32x4 q = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i,
-                                           (uint32_t)(p >> 3));
-                    const int f = p & 7;
-                    const uint32_t w = (f >> 1) == 0 ? q.x : (f >> 1) == 1 ? q.y
-                                     : (f >> 1) == 2 ? q.z : q.w;
-                    h = (w >> (16 * (f & 1))) & 0xFFFFu;
+                    const U32x4 q = PPW > 1 ? draw
+                                            : philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i,
+                                                     (uint32_t)(p >> 3));
+                    const int fl = p & 7;
+                    const uint32_t w = (fl >> 1) == 0 ? q.x : (fl >> 1) == 1 ? q.y
+                                     : (fl >> 1) == 2 ? q.z : q.w;
+                    h = (w >> (16 * (fl & 1))) & 0xFFFFu;
                 }
                 r = gom_pair<KIND>(R, hd, a.P, bits, commit, cand, h, neutral_ok);
                 flag |= r.acc;
@@ -725,9 +738,12 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
         }
         n_eval += (uint32_t)__popcll(ballot64(r.cnt > 0));
         n_acc += (uint32_t)__popcll(ballot64(r.acc));
-        wt += nwaves;
+        if (++f == PPW) {
+            f = 0;
+            wt += nwaves;
+        }
         if (wt < nwt) {
-            p = position(wt);
+            p = position(wt, f);
             R = record(p < a.csize ? p : 0);
             hd = load_head<KIND, B>(R);
         }
@@ -1810,6 +1826,7 @@ __global__ __launch_bounds__(T) void k_batch_sweep(const BatchInst *insts, const
 }
 
 __global__ __launch_bounds__(64) void k_batch_finalize(const BatchInst *insts) {
+    if (insts[blockIdx.x].solo) return;  // its own epilogue runs with its sweeps
     finalize_body(insts[blockIdx.x].epi);
 }
 
@@ -1938,6 +1955,12 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, 
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
     const dim3 gd(grid), bd(threads);
+    // general records: share each Philox call over its eight positions when every group of
+    // the largest grid would stride over at least eight positions anyway
+    const int64_t slots = (int64_t)max_grid * per_tile;
+    const bool shared = kind != 0 && a.mode != kSweepFi && (int64_t)a.csize >= 8 * slots;
+    const int grid8 = (int)std::min<int64_t>(max_grid, (a.csize + 8 * per_tile - 1) /
+                                                           (8 * (int64_t)per_tile));
     auto go = [&](auto fi) {
         constexpr bool FI = decltype(fi)::value;
         // several sets per wave (G < 64) read records with vector loads: no scalar registers
@@ -1947,6 +1970,22 @@ hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, 
             else if (G == 32) launch_timed(k_class_sweep<32, 0, FI, 8>, gd, bd, 0, s, ev, a);
             else if (short_records) launch_timed(k_class_sweep<64, 0, FI, 4>, gd, bd, 0, s, ev, a);
             else launch_timed(k_class_sweep<64, 0, FI, 8>, gd, bd, 0, s, ev, a);
+        } else if constexpr (!FI) {
+            if (shared) {
+                const dim3 gs(grid8);
+                if (G == 16) launch_timed(k_class_sweep<16, 1, false, 8, 8>, gs, bd, 0, s, ev, a);
+                else if (G == 32)
+                    launch_timed(k_class_sweep<32, 1, false, 8, 8>, gs, bd, 0, s, ev, a);
+                else if (short_records)
+                    launch_timed(k_class_sweep<64, 1, false, 4, 8>, gs, bd, 0, s, ev, a);
+                else launch_timed(k_class_sweep<64, 1, false, 8, 8>, gs, bd, 0, s, ev, a);
+            } else {
+                if (G == 16) launch_timed(k_class_sweep<16, 1, false, 8>, gd, bd, 0, s, ev, a);
+                else if (G == 32) launch_timed(k_class_sweep<32, 1, false, 8>, gd, bd, 0, s, ev, a);
+                else if (short_records)
+                    launch_timed(k_class_sweep<64, 1, false, 4>, gd, bd, 0, s, ev, a);
+                else launch_timed(k_class_sweep<64, 1, false, 8>, gd, bd, 0, s, ev, a);
+            }
         } else {
             if (G == 16) launch_timed(k_class_sweep<16, 1, FI, 8>, gd, bd, 0, s, ev, a);
             else if (G == 32) launch_timed(k_class_sweep<32, 1, FI, 8>, gd, bd, 0, s, ev, a);
@@ -2123,7 +2162,7 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
     }
     hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(64), 0, s, insts);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || vblocks < 1) return e;  // (a batch of solo instances only)
     hipLaunchKernelGGL(k_batch_vertex, dim3(vblocks), dim3(kEpiThreads), 0, s, insts, vblk);
     return hipGetLastError();
 }

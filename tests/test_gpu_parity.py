@@ -171,6 +171,33 @@ def test_block_cooperative_large_sets(cuda, sched, pop, fi):
     lockstep(st, ref, 4, f"large sets pop {pop}")
 
 
+@pytest.mark.parametrize("pop", [64, 24, 12])
+def test_class_sweep_shared_draws(cuda, pop):
+    """With a small grid cap every group of the per-class sweep strides over many positions,
+    so the neighbourhood sweep takes its form that draws one Philox call per eight positions
+    (groups of 64, 32 and 16 lanes); the trajectory equals the oracle's."""
+    print(f"case shared draws pop={pop}", flush=True)
+    g = workloads.configuration_model(3000, 5, seed=18)
+    _, st, ref = make_pair(g, 1, pop, seed=3, sched=gom.GOM_SCHED_CLASS_LAUNCH)
+    gom.gom_state_set_grid_limit(st, 3)
+    lockstep(st, ref, 5, f"shared draws pop={pop}")
+
+
+def test_grid_limit_bitsliced(cuda):
+    """The per-class bit-sliced sweep with a grid cap of one block (each thread strides over
+    many sets, 64-bit block counters when the weights require them)."""
+    print("case bitsliced grid limit", flush=True)
+    g = workloads.configuration_model(4000, 4, seed=19, weights="uniform", w_lo=-(1 << 24),
+                                      w_hi=1 << 24)
+    _, st, ref = make_pair(g, 0, 40, seed=4, sched=gom.GOM_SCHED_BITSLICED)
+    if gom.gom_state_get_fused(st)[1]:
+        gom.gom_state_set_fused(st, False)
+    gom.gom_state_set_grid_limit(st, 1)
+    lockstep(st, ref, 5, "bitsliced grid limit")
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_grid_limit(st, 0)
+
+
 def _components_with_sets(specs, seed):
     """A graph of disjoint random regular components and, per component, one set of its
     first `size` vertices, beside every vertex's singleton: the sets share no variable and no
@@ -953,6 +980,46 @@ def test_batch_block_sizes_and_autotune(cuda):
             ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=it.seed)
             ref.run(targets[b], 20)
             assert gom.gom_state_hash(bt.state(b)) == ref.hash(), f"instance {b} vs oracle"
+
+
+def test_batch_admits_instances_beyond_resident(cuda):
+    """Instances too large for the resident schedule (160 000-vertex torus: its offspring
+    bytes exceed LDS) join a batch and run their own sweeps within each step; every instance
+    equals its solo run, with graph chunks, a budget that ends inside a chunk, the autotuner
+    and a reseed; the small ones equal the oracle."""
+    print("case batch with solo instances", flush=True)
+    items = workloads.batch_mix(count=4, seed=20, n_lo=60, n_hi=900)
+    insts, targets = _batch_setup(items)
+    pops, seeds = [it.pop for it in items], [it.seed for it in items]
+    for L, kind, pop in ((400, 0, 64), (400, 1, 24)):
+        big = workloads.torus(L, 1, 100, seed=22 + kind)
+        insts.insert(1 + kind, gom.Instance(big.n, big.u, big.v, big.w, kind))
+        targets.insert(1 + kind, big.total_weight)
+        pops.insert(1 + kind, pop)
+        seeds.insert(1 + kind, 70 + kind)
+    bt = gom.gom_batch_init(insts, pops, seeds, targets)
+    gom.gom_batch_autotune(bt, 1)  # (its trial steps are steps of the run: at most 12)
+    res, _ = gom.gom_batch_run(bt, 30)
+    for b in range(len(insts)):
+        st = insts[b].state(pop=pops[b], seed=seeds[b])
+        r = gom.gom_run_to_target(st, targets[b], 30)
+        a = gom.gom_state_read(bt.state(b), genes=False)
+        assert (a["generation"], res[b].best, res[b].evaluated) == \
+            (r.generations, r.best, r.evaluated), b
+        assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), b
+    new_seeds = [s + 1000 for s in seeds]
+    gom.gom_batch_reseed(bt, new_seeds)
+    res, _ = gom.gom_batch_run(bt, 6)
+    k = 0
+    for b in range(len(insts)):
+        if insts[b].n > 1000:
+            continue
+        it = items[k]
+        k += 1
+        ptr, vars_ = oracle.fos(it.graph, it.fos)
+        ref = oracle.Run(it.graph, ptr, vars_, pop=pops[b], seed=new_seeds[b])
+        ref.run(targets[b], 6)
+        assert gom.gom_state_hash(bt.state(b)) == ref.hash(), f"instance {b} vs oracle"
 
 
 def test_batch_graph_replays_equal_direct_launches(cuda):
