@@ -167,6 +167,23 @@ int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t se
                    void *stream, gom_state **out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gom_state_init without a caller arena.  The state's
+ * device memory is the library's static arena, a file-scope device array of
+ * GOM_STATIC_ARENA_BYTES that every device the library runs on holds until the process ends.
+ * Nothing is allocated through HIP (the run-scalar read-back buffer is ordinary host memory).
+ * One such state per device at a time: the arena is shared by every call on that device and
+ * keeps the last state's contents, so a second gom_state_init_static on a device whose static
+ * state has not been freed fails with GOM_E_STATE; gom_state_free releases it.  Calls that use
+ * the static state from several host threads at once race, as for any state.
+ * Errors: as gom_state_init; GOM_E_RANGE also when gom_state_bytes exceeds
+ * GOM_STATIC_ARENA_BYTES; GOM_E_STATE when the device's static arena is in use.
+ */
+#define GOM_STATIC_ARENA_BYTES ((size_t)64 << 20)
+int gom_state_init_static(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t seed,
+                          int neutral_rule, int class_order, void *stream, gom_state **out);
+
+/*
  * Start the run again from a new initial population drawn with `seed` (Algorithm 3,
  * InitializePopulation, then the fitness of every solution and the initial elitist), keeping
  * the instance data already in the arena.  Generation and counters restart at 0.

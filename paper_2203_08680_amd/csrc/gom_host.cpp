@@ -430,6 +430,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
 }  // namespace
 
 struct gom_state {
+    int static_dev = -1;                // device whose static arena holds the state, or -1
     bool h_st_pinned = true;            // h_st from hipHostMalloc (else new[])
     bool fused_ok = false;              // the fused bit-sliced sweep can run this state
     bool fused_use = true;              // ... and is used for whole generations
@@ -1381,6 +1382,47 @@ extern "C" int gom_state_init(const mc_graph *g, const gom_fos *f, int32_t pop, 
     GUARD_END
 }
 
+// Devices whose static arena holds a live state (one at a time per device).
+static std::mutex g_static_mu;
+static std::vector<bool> g_static_busy;
+
+extern "C" int gom_state_init_static(const mc_graph *g, const gom_fos *f, int32_t pop,
+                                     uint64_t seed, int neutral_rule, int class_order_kind,
+                                     void *stream, gom_state **out) {
+    GUARD_BEGIN
+    if (!out) return fail(GOM_E_ARG, "gom_state_init_static: null output");
+    size_t need = 0;
+    int rc = gom_state_bytes(g, f, pop, &need);
+    if (rc) return rc;
+    if (need > kStaticArenaBytes)
+        return fail(GOM_E_RANGE, "gom_state_init_static: the state needs %zu bytes, the static "
+                    "arena holds %zu", need, (size_t)kStaticArenaBytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    void *arena = nullptr;
+    HIP_TRY(static_arena_address(&arena));
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_busy.size() <= (size_t)dev) g_static_busy.resize((size_t)dev + 1, false);
+        if (g_static_busy[(size_t)dev])
+            return fail(GOM_E_STATE, "gom_state_init_static: device %d's static arena holds a "
+                        "live state (free it first)", dev);
+        g_static_busy[(size_t)dev] = true;
+    }
+    gom_state *s = nullptr;
+    rc = state_init(g, f, pop, seed, neutral_rule, class_order_kind, arena, kStaticArenaBytes,
+                    stream, false, &s);
+    if (rc) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[(size_t)dev] = false;
+        return rc;
+    }
+    s->static_dev = dev;
+    *out = s;
+    return GOM_OK;
+    GUARD_END
+}
+
 extern "C" int gom_state_reseed(gom_state *s, uint64_t seed, void *stream) {
     GUARD_BEGIN
     if (!s) return fail(GOM_E_ARG, "gom_state_reseed: null state");
@@ -1962,6 +2004,10 @@ extern "C" void gom_state_free(gom_state *s) {
     if (s->h_st) {
         if (s->h_st_pinned) (void)hipHostFree(s->h_st);
         else delete[] s->h_st;
+    }
+    if (s->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[(size_t)s->static_dev] = false;
     }
     delete s;
 }

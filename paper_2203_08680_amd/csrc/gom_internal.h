@@ -292,6 +292,11 @@ struct KernelEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// Bytes of the static arena (gom_state_init_static), one per device.
+constexpr size_t kStaticArenaBytes = size_t(64) << 20;
+// Device address of the current device's static arena (looked up once per device).
+hipError_t static_arena_address(void **ptr);
+
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
                                   Stripe *stripes, int n, int N, uint64_t seed, hipStream_t s);

@@ -1946,6 +1946,31 @@ static hipError_t raise_lds_limit(size_t bytes) {
     return e;
 }
 
+// Static arena of gom_state_init_static: a state's device memory for callers that cannot
+// allocate.  Each device holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name is not a device address in
+// host code).
+static __device__ __align__(256) uint8_t scratch[kStaticArenaBytes];
+
+hipError_t static_arena_address(void **ptr) {
+    static void *addr[kMaxDevices] = {};
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
 hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, int max_grid,
                               int threads, hipStream_t s, KernelEvents ev) {
     if (threads < 64 || threads > kSweepMaxThreads || threads % 64) return hipErrorInvalidValue;

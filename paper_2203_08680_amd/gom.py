@@ -26,7 +26,7 @@ EXPORTED = (
     "mc_graph_free", "gom_fos_build", "gom_fos_from_sets", "gom_fos_build_lt", "gom_fos_info",
     "gom_fos_get",
     "gom_fos_free", "gom_colour", "gom_colour_get", "gom_state_bytes", "gom_state_init",
-    "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
+    "gom_state_init_static", "gom_state_reseed", "gom_generation", "gom_run_to_target", "gom_state_read", "gom_state_write",
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
     "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_state_set_fused",
@@ -136,6 +136,8 @@ def lib() -> C.CDLL:
         "gom_batch_run": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
         "gom_batch_set_graph": (C.c_int, [_vp, C.c_int]),
         "gom_batch_reseed": (C.c_int, [_vp, _vp, _vp]),
+        "gom_state_init_static": (C.c_int, [_vp, _vp, _i32, _u64, C.c_int, C.c_int, _vp,
+                                            _P(_vp)]),
         "gom_batch_timing_enable": (C.c_int, [_vp, C.c_int]),
         "gom_batch_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
         "gom_batch_set_narrow": (C.c_int, [_vp, _i64, _vp]),
@@ -339,6 +341,21 @@ def gom_state_init(g: McGraph, f: GomFos, pop: int, seed: int,
                                     arena.data_ptr() + off, nbytes, _stream_handle(stream),
                                     C.byref(h)))
     return GomState(h.value, arena, g.info()["n"], pop)
+
+
+GOM_STATIC_ARENA_BYTES = 64 << 20
+
+
+def gom_state_init_static(g: McGraph, f: GomFos, pop: int, seed: int,
+                          neutral_rule: int = GOM_NEUTRAL_PAPER,
+                          class_order: int = GOM_ORDER_RANDOM, stream=None) -> GomState:
+    """gom_state_init in the library's static device arena: no device memory is allocated.
+    One such state per device at a time (free it before creating the next)."""
+    h = _vp()
+    _check(lib().gom_state_init_static(g.handle, f.handle, int(pop), int(seed) & (2**64 - 1),
+                                       int(neutral_rule), int(class_order),
+                                       _stream_handle(stream), C.byref(h)))
+    return GomState(h.value, None, g.info()["n"], pop)
 
 
 def gom_state_reseed(s: GomState, seed: int, stream=None):
