@@ -266,13 +266,18 @@ def run_batch_mode(args, torch, gom):
     batch = gom.gom_batch_init(insts, pops, step_seeds(items, 0), targets)
     gom.gom_batch_set_graph(batch, args.batch_graph == "on")
     log(f"batch states: {time.perf_counter() - t0:.1f} s")
-    if args.batch_narrow is None:
+    tuned = args.batch_narrow is None and args.batch_class_min is None
+    if tuned:
         t0 = time.perf_counter()
-        narrow = gom.gom_batch_autotune(batch, 2)
-        log(f"batch autotune: threshold {narrow} in {time.perf_counter() - t0:.1f} s")
+        chosen = gom.gom_batch_autotune(batch, 2)
+        log(f"batch autotune: thresholds {chosen} in {time.perf_counter() - t0:.1f} s")
     else:
-        gom.gom_batch_set_narrow(batch, args.batch_narrow)
+        if args.batch_narrow is not None:
+            gom.gom_batch_set_narrow(batch, args.batch_narrow)
+        if args.batch_class_min is not None:
+            gom.gom_batch_set_class_launch(batch, args.batch_class_min)
     narrow, sweep_launches = gom.gom_batch_get_narrow(batch)
+    class_min, class_insts, class_launches = gom.gom_batch_get_class_launch(batch)
 
     def one_step(k):
         gom.gom_batch_reseed(batch, step_seeds(items, k))
@@ -346,13 +351,13 @@ def run_batch_mode(args, torch, gom):
         ib = [instance_bytes(x, p) for x, p in zip(insts, pops)]
         total_bytes = float(sum(ib[b] * res_t[b].generations for b in range(len(items))))
         achieved = total_bytes / (sweep_ms / 1e3) / 1e9
-        meas = MEASURED_TRAFFIC.get(("k_batch_sweep", "batch256_mix"))
+        meas = MEASURED_TRAFFIC.get(("batched_sweeps", "batch256_mix"))
         traffic = meas["bytes"] if meas and meas["source"] == kernel_source_hash() else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                     "traffic": traffic,
                     "traffic_profile": meas["profile"] if traffic else None,
-                    "kernel": "k_batch_sweep",
+                    "kernel": "k_batch_sweep + k_bcl_sweep" if class_insts else "k_batch_sweep",
                     "bytes_per_launch": round(total_bytes / launches, 1),
                     "avg_launch_us": round(sweep_ms / launches * 1e3, 3), "launches": launches,
                     "timing": "every sweep launch of one more batched run (the first timed "
@@ -375,8 +380,10 @@ def run_batch_mode(args, torch, gom):
                    "pop_range": [16, 64], "max_generations": max_gens,
                    "fos": "univariate and neighbourhood alternating in pairs",
                    "mode": "batched", "schedule": "batched_resident",
-                   "narrow_blocks_max_n": narrow, "sweep_launches_per_step": sweep_launches,
-                   "block_sizes": "autotuned" if args.batch_narrow is None else "fixed",
+                   "narrow_blocks_max_n": narrow, "resident_launches_per_step": sweep_launches,
+                   "class_launch_min_n": class_min, "class_launch_instances": class_insts,
+                   "class_launches_per_step": class_launches,
+                   "launch_shapes": "autotuned" if tuned else "fixed",
                    "generation_steps": ("hip_graph_chunks_of_4" if args.batch_graph == "on"
                                         else "direct_launches"),
                    "step": "fresh populations (new seeds) and a batched run of the whole mix "
@@ -450,6 +457,7 @@ def run_serve_mode(args, torch, gom):
     # served: the same arrivals through the serving loop
     arena_bytes = int(args.serve_arena_gb * (1 << 30))
     srv = gom.GomServer(arena_bytes, max_jobs=256, streams=args.serve_streams)
+    srv.set_large(args.serve_large_min)
     start = time.perf_counter()
     nxt, ids, res = 0, {}, {}
     while len(res) < len(jobs):
@@ -497,6 +505,7 @@ def run_serve_mode(args, torch, gom):
                    "jobs": len(jobs), "max_generations": args.serve_max_gens,
                    "arrival_rate_jobs_per_s": rate, "load": args.serve_load,
                    "arena_bytes": arena_bytes, "streams": args.serve_streams,
+                   "large_min_vertices": args.serve_large_min,
                    "mode": "served"},
         "time_to_solution_ms": {"served_p50": pct(served_tts, 50),
                                 "served_p99": pct(served_tts, 99),
@@ -596,6 +605,10 @@ def main():
                     help="batched mode: instances with at most this many vertices sweep with "
                          "256-thread blocks, larger ones 1024 (-1: all 1024; default: "
                          "autotuned)")
+    ap.add_argument("--batch-class-min", type=int, default=None,
+                    help="batched mode: neighbourhood instances with at least this many "
+                         "vertices take the batched class launches (-1: none; default: "
+                         "autotuned)")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
                     help="batched steps as captured HIP graph chunks (default) or direct launches")
     ap.add_argument("--ims", action="store_true",
@@ -613,6 +626,10 @@ def main():
                     help="arrival rate as a fraction of the measured plain capacity")
     ap.add_argument("--serve-arena-gb", type=float, default=32.0)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-large-min", type=int, default=50_000,
+                    help="jobs with at least this many vertices run one at a time on the "
+                         "first stream, small jobs on the others (-1: every job on the least "
+                         "loaded stream)")
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
     ap.add_argument("--metrics-jsonl", default=None,

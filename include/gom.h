@@ -488,15 +488,32 @@ int gom_batch_set_narrow(gom_batch *b, int64_t narrow_max_n, void *stream);
 int gom_batch_get_narrow(const gom_batch *b, int64_t *narrow_max_n, int32_t *launches);
 
 /*
- * Autotuner of the block-size threshold: runs trial_steps generation steps under each
- * candidate threshold (all 1024-thread blocks, 2048, 8192, 16384, 32768 vertices, all
- * 256-thread blocks; candidates that give the same assignment once), timed with HIP events on
- * `stream`, in two interleaved rounds, and keeps the fastest.  The trial steps are ordinary
- * generation steps of the run (they count against gom_batch_run's step budget).
- * Synchronous.  chosen (or NULL): the threshold kept.
+ * Batched class launches: instances of a general FOS whose sets all have at most 14 members
+ * (neighbourhoods of graphs up to degree 13) and at least min_n vertices are swept per colour
+ * class instead of by resident blocks: each step draws every such instance's class order on
+ * the device, then launches once per class position t, every launch covering class pi_i[t]
+ * of all of them with one wave per set and one lane per solution (Algorithm 3's loop over
+ * groups, for many instances at once), so a set's record is read once for all solutions.
+ * min_n < 0: none.  Default 20000.  Results do not depend on the choice.  Synchronous.
+ * gom_batch_get_class_launch returns the threshold, the instances it selects and the class
+ * launches per step.  Errors: GOM_E_ARG, GOM_E_DEVICE.
+ */
+int gom_batch_set_class_launch(gom_batch *b, int64_t min_n, void *stream);
+int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, int32_t *instances,
+                               int32_t *launches);
+
+/*
+ * Autotuner of the batch's launch shapes: runs trial_steps generation steps under each
+ * candidate class-launch threshold (none, 50000, 20000, 5000 vertices, all eligible), then
+ * under each block-size threshold (all 1024-thread blocks, 2048, 8192, 16384, 32768 vertices,
+ * all 256-thread blocks), candidates that give the same assignment only once, timed with HIP
+ * events on `stream` in two interleaved rounds, and keeps the fastest of each.  The trial
+ * steps are ordinary generation steps of the run (they count against gom_batch_run's step
+ * budget).  Synchronous.  narrow, class_min (or NULL): the thresholds kept.
  * Errors: GOM_E_ARG, GOM_E_STATE (an open generation), GOM_E_RANGE, GOM_E_DEVICE.
  */
-int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *stream, int64_t *chosen);
+int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *stream, int64_t *narrow,
+                       int64_t *class_min);
 
 /* Borrowed handle of instance `index` (for gom_state_read); valid until gom_batch_free. */
 int gom_batch_state(gom_batch *b, int32_t index, gom_state **state);
@@ -575,6 +592,16 @@ typedef struct {
  */
 int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t max_jobs, int32_t streams,
                       gom_server **out);
+
+/*
+ * Size-aware placement: a job whose graph has at least large_min_n vertices is large.  Large
+ * jobs run one at a time, on the server's first stream, first come first served among
+ * themselves; a large job that has to wait does not hold back the small jobs queued behind it,
+ * which run on the other streams.  So a large job shares the device only with small ones,
+ * and small jobs never queue behind large ones.  large_min_n < 0 (the default) or a server
+ * with one stream: every job is placed on the least loaded stream.  Errors: GOM_E_ARG.
+ */
+int gom_server_set_large(gom_server *s, int64_t large_min_n);
 
 /* Queue a job.  g and f (coloured) are borrowed: keep them alive until the job's result has
  * been returned.  *job receives its id (0, 1, ...).  Errors: as gom_state_bytes, GOM_E_NOMEM

@@ -445,6 +445,7 @@ struct gom_state {
     uint64_t seed = 0;
     int rule = 0, order = 0;
     bool univariate = false;
+    int32_t max_set = 0;                // largest set of the FOS
     std::vector<int32_t> class_ptr;
     char *arena = nullptr;
     Layout L{};
@@ -1266,6 +1267,7 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
     s->rule = neutral_rule;
     s->order = class_order_kind;
     s->univariate = f->max_set == 1;
+    s->max_set = f->max_set;
     s->class_ptr = f->class_ptr;
     for (int32_t c = 0; c < f->k; ++c)
         s->max_class = std::max(s->max_class, f->class_ptr[(size_t)c + 1] - f->class_ptr[c]);
@@ -2026,6 +2028,12 @@ struct gom_batch {
     int vblocks = 0;
     std::vector<BatchLaunch> groups;    // sweep launch groups of the current block sizes
     std::vector<int32_t> solo;          // instances that run their own sweeps in each step
+    std::vector<int32_t> bcl;           // instances swept by the batched class launches
+    int64_t bcl_min_n = -1;             // ... those eligible with at least this many vertices
+    BclInst *d_bcl = nullptr;
+    uint16_t *d_bcl_order = nullptr;
+    int32_t *d_bcl_tiles = nullptr;
+    int bcl_kmax = 0, bcl_grid = 0;
     int64_t narrow_max_n = -1;          // instances with n <= this run 256-thread blocks
     size_t lds_max = 0;                 // LDS per CU of the device
     DevState *h_st = nullptr;           // pinned, 2 x count
@@ -2047,8 +2055,9 @@ struct gom_batch {
 namespace {
 struct BatchLayout {
     std::vector<size_t> sub_off, sub_bytes;
-    size_t insts = 0, blk = 0, vblk = 0, snap = 0, total = 0;
-    int sweep_blocks = 0, vblocks = 0;
+    size_t insts = 0, blk = 0, vblk = 0, snap = 0, bcl = 0, bcl_order = 0, bcl_tiles = 0,
+           total = 0;
+    int sweep_blocks = 0, vblocks = 0, kmax = 0;
 };
 
 int batch_layout(int32_t count, const mc_graph *const *graphs, const gom_fos *const *fos,
@@ -2075,9 +2084,19 @@ int batch_layout(int32_t count, const mc_graph *const *graphs, const gom_fos *co
     o = align_up(o + sizeof(int32_t) * (size_t)vb);
     B.snap = o;
     o = align_up(o + sizeof(DevState) * (size_t)count);
+    // batched class launches: room for every instance (which ones take them is decided later)
+    int kmax = 1;
+    for (int32_t b = 0; b < count; ++b) kmax = std::max(kmax, fos[b]->k);
+    B.bcl = o;
+    o = align_up(o + sizeof(BclInst) * (size_t)count);
+    B.bcl_order = o;
+    o = align_up(o + sizeof(uint16_t) * (size_t)count * kmax);
+    B.bcl_tiles = o;
+    o = align_up(o + sizeof(int32_t) * (size_t)kmax * (count + 1));
     B.total = o;
     B.sweep_blocks = sweep;
     B.vblocks = vb;
+    B.kmax = kmax;
     return GOM_OK;
 }
 }  // namespace
@@ -2111,6 +2130,8 @@ extern "C" void gom_batch_free(gom_batch *b) {
 // Default block-size threshold of the batched sweep: instances with at most this many vertices
 // run 256-thread blocks, larger ones 1024.
 constexpr int64_t kBatchNarrowDefault = 16384;
+// Default vertex count from which eligible instances take the batched class launches.
+constexpr int64_t kBatchClassMinDefault = 20000;
 
 // Sweep blocks of one CU that the LDS of a block allows (at most 8).
 static int blocks_per_cu(size_t lds, size_t lds_max) {
@@ -2138,7 +2159,45 @@ static int batch_reg_blocks(int threads, int kind) {
 // per CU) form one launch; within it, instances with more classes and vertices per thread
 // (longer blocks) come first.  Uploads the instance table and the block map (synchronous)
 // and drops a captured graph.
-static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
+// May instance s take the batched class launches (general records of sets of at most
+// kBclMaxMembers members)?
+static bool bcl_eligible(const gom_state *s) {
+    return !s->univariate && s->max_set <= kBclMaxMembers && s->k <= 2048;
+}
+
+static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
+                         hipStream_t st) {
+    // which instances the batched class launches sweep (the others: resident blocks)
+    std::vector<BclInst> bi;
+    b->bcl.clear();
+    b->bcl_kmax = 0;
+    for (int32_t i = 0; i < b->count; ++i) {
+        BatchInst &I = b->h_insts[(size_t)i];
+        const gom_state *s = b->subs[(size_t)i];
+        if (I.solo) continue;
+        I.bcl = bcl_min_n >= 0 && (int64_t)s->n >= bcl_min_n && bcl_eligible(s);
+        I.epi = epilogue_args(s, b->targets[(size_t)i], !I.bcl);
+        if (!I.bcl) continue;
+        BclInst c{};
+        c.P = s->d_P;
+        c.O = s->d_O;
+        c.stripes = s->d_stripes;
+        c.st = s->d_st;
+        c.roff = s->d_roff;
+        c.recs = s->d_recs;
+        c.class_ptr = s->d_cptr;
+        c.class_rec = s->d_crec;
+        c.seed = s->seed;
+        c.target = b->targets[(size_t)i];
+        c.N = s->N;
+        c.always = s->rule == GOM_NEUTRAL_ALWAYS;
+        c.k = s->k;
+        c.order_fixed = s->order == GOM_ORDER_FIXED;
+        bi.push_back(c);
+        b->bcl.push_back(i);
+        b->bcl_kmax = std::max(b->bcl_kmax, s->k);
+    }
+    if (!bi.empty() && b->bcl_grid == 0) HIP_TRY(bcl_sweep_grid(&b->bcl_grid));
     struct Item {
         int threads, kind, occ;
         double cost;
@@ -2149,7 +2208,7 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
     items.reserve((size_t)b->count);
     for (int32_t i = 0; i < b->count; ++i) {
         const gom_state *s = b->subs[(size_t)i];
-        if (b->h_insts[(size_t)i].solo) continue;
+        if (b->h_insts[(size_t)i].solo || b->h_insts[(size_t)i].bcl) continue;
         int T = (int64_t)s->n <= narrow_max_n ? 256 : 1024;
         if (kBatchOrderBytes + resident_lds_bytes(s->n, false, T) > b->lds_max) T = 256;
         const size_t l0 = kBatchOrderBytes + resident_lds_bytes(s->n, false, T);
@@ -2232,8 +2291,12 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));  // nothing in flight reads the tables
     HIP_TRY(hipMemcpyAsync(b->d_insts, b->h_insts.data(), sizeof(BatchInst) * b->h_insts.size(),
                            hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(b->d_blk, blk.data(), sizeof(int2) * blk.size(),
-                           hipMemcpyHostToDevice, st));
+    if (!blk.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_blk, blk.data(), sizeof(int2) * blk.size(),
+                               hipMemcpyHostToDevice, st));
+    if (!bi.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_bcl, bi.data(), sizeof(BclInst) * bi.size(),
+                               hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(prepare_batch_step(groups.data(), (int)groups.size()));
     if (b->graph_exec) {
@@ -2246,7 +2309,20 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, hipStream_t st) {
     }
     b->groups = std::move(groups);
     b->narrow_max_n = narrow_max_n;
+    b->bcl_min_n = bcl_min_n;
     return GOM_OK;
+}
+
+// The batched class launches' plan arguments of the batch's current assignment.
+static BclPlan bcl_plan(const gom_batch *b) {
+    BclPlan p{};
+    p.insts = b->d_bcl;
+    p.order = b->d_bcl_order;
+    p.tiles = b->d_bcl_tiles;
+    p.count = (int32_t)b->bcl.size();
+    p.kmax = b->bcl_kmax;
+    p.grid = b->bcl_grid;
+    return p;
 }
 
 extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
@@ -2302,6 +2378,9 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
             for (int32_t q = 0; q < (s->n + 255) / 256; ++q) vblk.push_back(b);
         }
     }
+    bt->d_bcl = (BclInst *)(arena + B.bcl);
+    bt->d_bcl_order = (uint16_t *)(arena + B.bcl_order);
+    bt->d_bcl_tiles = (int32_t *)(arena + B.bcl_tiles);
     bt->d_insts = (BatchInst *)(arena + B.insts);
     bt->d_blk = (int2 *)(arena + B.blk);
     bt->d_vblk = (int32_t *)(arena + B.vblk);
@@ -2326,7 +2405,7 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
         return cleanup(fail(GOM_E_DEVICE, "gom_batch_init: %s", hipGetErrorString(e)));
     bt->wall_khz = (double)khz;
     bt->h_insts = std::move(insts);
-    rc = batch_regroup(bt, kBatchNarrowDefault, st);
+    rc = batch_regroup(bt, kBatchNarrowDefault, kBatchClassMinDefault, st);
     if (rc) return cleanup(rc);
     *out = bt;
     return GOM_OK;
@@ -2354,7 +2433,8 @@ static hipError_t batch_chunk_graph(gom_batch *b, int32_t steps) {
     hipError_t le = hipSuccess;
     for (int32_t t = 0; t < steps && le == hipSuccess; ++t)
         le = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
-                               (int)b->groups.size(), b->d_vblk, b->vblocks, b->cap);
+                               (int)b->groups.size(), b->d_vblk, b->vblocks, bcl_plan(b),
+                               b->cap);
     if (le == hipSuccess) le = launch_batch_gather(b->d_insts, b->count, b->d_snap, b->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);  // always ends the capture
@@ -2464,9 +2544,9 @@ extern "C" int gom_batch_reseed(gom_batch *b, const uint64_t *seeds, void *strea
         HIP_TRY(enqueue_initial_population(s, st));
         b->h_insts[(size_t)i].res.seed = seeds[i];
     }
-    HIP_TRY(hipMemcpyAsync(b->d_insts, b->h_insts.data(), sizeof(BatchInst) * b->h_insts.size(),
-                           hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    // the instance tables carry the seeds (the class launches' table too): upload them again
+    const int rc = batch_regroup(b, b->narrow_max_n, b->bcl_min_n, st);
+    if (rc) return rc;
     b->g_done = 0;
     return GOM_OK;
     GUARD_END
@@ -2513,11 +2593,15 @@ extern "C" int gom_batch_run(gom_batch *b, int32_t max_generations, void *stream
                 } else {
                     for (int32_t t = 0; t < n; ++t) {
                         KernelEvents ev;
-                        const int rc = batch_timing_events(b, &ev);
+                        // (a step of solo instances only has no batched sweep to time)
+                        const int rc = b->groups.empty() && b->bcl.empty()
+                                           ? GOM_OK
+                                           : batch_timing_events(b, &ev);
                         if (rc) return rc;
                         HIP_TRY(launch_batch_step(b->d_insts, b->count, b->d_blk,
                                                   b->groups.data(), (int)b->groups.size(),
-                                                  b->d_vblk, b->vblocks, st, ev));
+                                                  b->d_vblk, b->vblocks, bcl_plan(b), st,
+                                                  ev));
                         const int src = batch_solo_steps(b, 1, st);
                         if (src) return src;
                     }
@@ -2570,7 +2654,7 @@ extern "C" int gom_batch_set_graph(gom_batch *b, int enabled) {
 extern "C" int gom_batch_set_narrow(gom_batch *b, int64_t narrow_max_n, void *stream) {
     GUARD_BEGIN
     if (!b) return fail(GOM_E_ARG, "gom_batch_set_narrow: null batch");
-    return batch_regroup(b, narrow_max_n, (hipStream_t)stream);
+    return batch_regroup(b, narrow_max_n, b->bcl_min_n, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -2582,8 +2666,31 @@ extern "C" int gom_batch_get_narrow(const gom_batch *b, int64_t *narrow_max_n,
     return GOM_OK;
 }
 
+// Thresholds from `list` that give distinct assignments of the instances' sizes (the number
+// of instances with n <= threshold, or with n >= threshold when `at_least`).
+static std::vector<int64_t> distinct_thresholds(const gom_batch *b, std::vector<int64_t> list,
+                                                bool at_least) {
+    std::vector<int64_t> sizes;
+    for (const gom_state *s : b->subs) sizes.push_back(s->n);
+    std::sort(sizes.begin(), sizes.end());
+    auto key = [&](int64_t c) {
+        if (at_least) {
+            if (c < 0) return (size_t)0;  // (a negative class-launch threshold: none)
+            return (size_t)(sizes.end() - std::lower_bound(sizes.begin(), sizes.end(), c));
+        }
+        return (size_t)(std::upper_bound(sizes.begin(), sizes.end(), c) - sizes.begin());
+    };
+    std::vector<int64_t> out;
+    for (int64_t c : list) {
+        bool dup = false;
+        for (int64_t d : out) dup |= key(d) == key(c);
+        if (!dup) out.push_back(c);
+    }
+    return out;
+}
+
 extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *stream,
-                                  int64_t *chosen) {
+                                  int64_t *narrow_out, int64_t *class_min_out) {
     GUARD_BEGIN
     if (!b || trial_steps < 1) return fail(GOM_E_ARG, "gom_batch_autotune: bad arguments");
     for (int32_t i = 0; i < b->count; ++i)
@@ -2591,21 +2698,6 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
             return fail(GOM_E_STATE, "gom_batch_autotune: instance %d has an open generation",
                         i);
     hipStream_t st = (hipStream_t)stream;
-    // thresholds that give distinct block-size assignments
-    std::vector<int64_t> sizes;
-    for (const gom_state *s : b->subs) sizes.push_back(s->n);
-    std::sort(sizes.begin(), sizes.end());
-    std::vector<int64_t> cands;
-    for (int64_t c : {(int64_t)-1, (int64_t)2048, (int64_t)8192, (int64_t)16384,
-                      (int64_t)32768, (int64_t)1 << 40}) {
-        const size_t narrow = (size_t)(std::upper_bound(sizes.begin(), sizes.end(), c) -
-                                       sizes.begin());
-        bool dup = false;
-        for (int64_t d : cands)
-            dup |= (size_t)(std::upper_bound(sizes.begin(), sizes.end(), d) - sizes.begin()) ==
-                   narrow;
-        if (!dup) cands.push_back(c);
-    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -2613,43 +2705,77 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
         (void)hipEventDestroy(e0);
         return fail(GOM_E_DEVICE, "gom_batch_autotune: %s", hipGetErrorString(he));
     }
-    std::vector<double> total(cands.size(), 0.0);
     int rc = GOM_OK;
     hipError_t e = hipSuccess;
-    for (int round = 0; round < 2 && rc == GOM_OK && e == hipSuccess; ++round) {
-        for (size_t q = 0; q < cands.size() && rc == GOM_OK && e == hipSuccess; ++q) {
-            rc = batch_regroup(b, cands[q], st);
-            if (rc) break;
-            e = hipEventRecord(e0, st);
-            for (int32_t t = 0; t < trial_steps && e == hipSuccess && rc == GOM_OK; ++t) {
-                e = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
-                                      (int)b->groups.size(), b->d_vblk, b->vblocks, st);
-                if (e == hipSuccess) rc = batch_solo_steps(b, 1, st);
+    // time `trial_steps` steps under each (narrow, class-launch) pair, two interleaved rounds
+    auto tune = [&](const std::vector<std::pair<int64_t, int64_t>> &cands) {
+        std::vector<double> total(cands.size(), 0.0);
+        for (int round = 0; round < 2 && rc == GOM_OK && e == hipSuccess; ++round) {
+            for (size_t q = 0; q < cands.size() && rc == GOM_OK && e == hipSuccess; ++q) {
+                rc = batch_regroup(b, cands[q].first, cands[q].second, st);
+                if (rc) break;
+                e = hipEventRecord(e0, st);
+                for (int32_t t = 0; t < trial_steps && e == hipSuccess && rc == GOM_OK; ++t) {
+                    e = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
+                                          (int)b->groups.size(), b->d_vblk, b->vblocks,
+                                          bcl_plan(b), st);
+                    if (e == hipSuccess) rc = batch_solo_steps(b, 1, st);
+                }
+                if (rc) break;
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                total[q] += ms;
+                b->g_done += trial_steps;
             }
-            if (rc) break;
-            if (e == hipSuccess) e = hipEventRecord(e1, st);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            total[q] += ms;
-            b->g_done += trial_steps;
         }
+        return cands[(size_t)(std::min_element(total.begin(), total.end()) - total.begin())];
+    };
+    // first which instances take the batched class launches (with the current block sizes),
+    // then the resident block sizes of the others
+    std::vector<std::pair<int64_t, int64_t>> c1;
+    for (int64_t m : distinct_thresholds(b, {-1, 50000, 20000, 5000, 0}, true))
+        c1.push_back({b->narrow_max_n, m});
+    std::pair<int64_t, int64_t> best = tune(c1);
+    if (rc == GOM_OK && e == hipSuccess) {
+        std::vector<std::pair<int64_t, int64_t>> c2;
+        for (int64_t nm : distinct_thresholds(b, {-1, 2048, 8192, 16384, 32768, (int64_t)1 << 40},
+                                              false))
+            c2.push_back({nm, best.second});
+        best = tune(c2);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (e != hipSuccess)
         return fail(GOM_E_DEVICE, "gom_batch_autotune: %s", hipGetErrorString(e));
-    const size_t best = (size_t)(std::min_element(total.begin(), total.end()) - total.begin());
-    rc = batch_regroup(b, cands[best], st);
+    rc = batch_regroup(b, best.first, best.second, st);
     if (rc) return rc;
     // the trial steps advanced the instances: keep the host's generation counts in step
     HIP_TRY(batch_snapshot(b, 0, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int32_t i = 0; i < b->count; ++i) b->subs[(size_t)i]->g_host = b->h_st[i].generation;
-    if (chosen) *chosen = cands[best];
+    if (narrow_out) *narrow_out = best.first;
+    if (class_min_out) *class_min_out = best.second;
     return GOM_OK;
     GUARD_END
+}
+
+extern "C" int gom_batch_set_class_launch(gom_batch *b, int64_t min_n, void *stream) {
+    GUARD_BEGIN
+    if (!b) return fail(GOM_E_ARG, "gom_batch_set_class_launch: null batch");
+    return batch_regroup(b, b->narrow_max_n, min_n, (hipStream_t)stream);
+    GUARD_END
+}
+
+extern "C" int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, int32_t *instances,
+                                          int32_t *launches) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_get_class_launch: null batch");
+    if (min_n) *min_n = b->bcl_min_n;
+    if (instances) *instances = (int32_t)b->bcl.size();
+    if (launches) *launches = b->bcl.empty() ? 0 : b->bcl_kmax;
+    return GOM_OK;
 }
 
 extern "C" int gom_batch_state(gom_batch *b, int32_t index, gom_state **state) {
@@ -2680,6 +2806,7 @@ struct ServerJob {
     size_t bytes = 0, off = 0;
     gom_state *s = nullptr;
     int lane = 0;
+    bool large = false;       // runs alone on lane 0 (size-aware placement)
     bool in_flight = false;   // a chunk and its snapshot are enqueued
     bool retired = false;     // finished: result recorded, state and memory released
     double submit_ms = 0.0, admit_ms = 0.0;
@@ -2693,6 +2820,9 @@ struct gom_server {
     int32_t max_jobs = 0, chunk = 4;
     std::vector<hipStream_t> lanes;       // owned streams (default priority)
     std::vector<int32_t> lane_jobs;
+    int64_t large_min_n = -1;             // jobs with at least this many vertices are large
+                                          // (-1: no distinction)
+    int32_t large_active = 0;
     ArenaBlocks blocks;                   // first-fit, coalescing
     std::deque<ServerJob> queue;
     std::vector<ServerJob> active;
@@ -2742,6 +2872,12 @@ extern "C" int gom_server_create(void *dev_arena, size_t arena_bytes, int32_t ma
     *out = sv;
     return GOM_OK;
     GUARD_END
+}
+
+extern "C" int gom_server_set_large(gom_server *sv, int64_t large_min_n) {
+    if (!sv) return fail(GOM_E_ARG, "gom_server_set_large: null server");
+    sv->large_min_n = large_min_n;
+    return GOM_OK;
 }
 
 extern "C" int gom_server_submit(gom_server *sv, const mc_graph *g, const gom_fos *f,
@@ -2800,14 +2936,29 @@ int server_issue(gom_server *sv, ServerJob &J) {
 extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_queued) {
     GUARD_BEGIN
     if (!sv) return fail(GOM_E_ARG, "gom_server_step: null server");
-    // admission, first come first served
-    while (!sv->queue.empty() && (int32_t)sv->active.size() < sv->max_jobs) {
-        ServerJob &J = sv->queue.front();
+    // admission, first come first served while the arena has room; with size-aware
+    // placement a large job waits (without holding back the small jobs behind it) while
+    // another large job runs, and runs alone on lane 0, the small jobs on the other lanes
+    const bool sized = sv->large_min_n >= 0 && sv->lanes.size() >= 2;
+    size_t qi = 0;
+    while (qi < sv->queue.size() && (int32_t)sv->active.size() < sv->max_jobs) {
+        ServerJob &J = sv->queue[qi];
+        J.large = sized && (int64_t)J.g->n >= sv->large_min_n;
+        if (J.large && sv->large_active > 0) {
+            ++qi;
+            continue;
+        }
         size_t off = 0;
         if (!sv->blocks.alloc(J.bytes, &off)) break;
         int lane = 0;
-        for (int q = 1; q < (int)sv->lanes.size(); ++q)
-            if (sv->lane_jobs[(size_t)q] < sv->lane_jobs[(size_t)lane]) lane = q;
+        if (sized) {
+            lane = J.large ? 0 : 1;
+            for (int q = 2; q < (int)sv->lanes.size() && !J.large; ++q)
+                if (sv->lane_jobs[(size_t)q] < sv->lane_jobs[(size_t)lane]) lane = q;
+        } else {
+            for (int q = 1; q < (int)sv->lanes.size(); ++q)
+                if (sv->lane_jobs[(size_t)q] < sv->lane_jobs[(size_t)lane]) lane = q;
+        }
         gom_state *s = nullptr;
         int rc = gom_state_init(J.g, J.f, J.pop, J.seed, J.rule, J.order, sv->arena + off,
                                 align_up(J.bytes), sv->lanes[(size_t)lane], &s);
@@ -2821,7 +2972,7 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
             r.submit_ms = J.submit_ms;
             r.admit_ms = r.done_ms = sv->now_ms();
             sv->done.push_back(r);
-            sv->queue.pop_front();
+            sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)qi);
             continue;
         }
         // jobs share the device: a fused sweep's chunks wait for each other, which needs all
@@ -2831,9 +2982,10 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
         J.off = off;
         J.lane = lane;
         sv->lane_jobs[(size_t)lane]++;
+        if (J.large) sv->large_active++;
         J.admit_ms = sv->now_ms();
         sv->active.push_back(J);
-        sv->queue.pop_front();
+        sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)qi);
         rc = server_issue(sv, sv->active.back());
         if (rc) return rc;
     }
@@ -2871,6 +3023,7 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
         J.retired = true;
         sv->blocks.release(J.off, J.bytes);
         sv->lane_jobs[(size_t)J.lane]--;
+        if (J.large) sv->large_active--;
     }
     if (n_active) *n_active = (int32_t)sv->active.size() - (int32_t)std::count_if(
         sv->active.begin(), sv->active.end(), [](const ServerJob &J) { return J.retired; });

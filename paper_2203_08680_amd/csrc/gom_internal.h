@@ -278,6 +278,7 @@ struct BatchInst {
     int32_t order_fixed;    // class order ascending instead of shuffled
     int32_t vblock0;        // first vertex-pass block of the instance
     int32_t plds;           // the sweep keeps a copy of P in LDS
+    int32_t bcl;            // swept by the batched class launches (offspring in the O planes)
     int32_t solo;           // too large for the resident schedule: the instance runs its own
                             // per-class sweeps and epilogue in each step (the batched
                             // finalize and vertex pass skip it)
@@ -296,6 +297,40 @@ struct KernelEvents {
 constexpr size_t kStaticArenaBytes = size_t(64) << 20;
 // Device address of the current device's static arena (looked up once per device).
 hipError_t static_arena_address(void **ptr);
+
+// Batched class launch (general FOS whose sets all have at most 14 members, in a batch): one
+// launch per position t of the generation's class order covers class pi_i[t] of every such
+// instance i.  Lane = solution (64 lanes per wave), so a set's record is read once for all
+// solutions; a wave sweeps kBclPositions consecutive positions (one Philox call), a block
+// kBclWaves waves' worth (a tile).  Per step a planning pair of kernels draws every instance's
+// class order and the prefix sums of its tiles per position.
+constexpr int kBclWaves = 4;
+constexpr int kBclPositions = 8;
+constexpr int kBclTile = kBclWaves * kBclPositions;
+constexpr int kBclThreads = 64 * kBclWaves;
+constexpr int kBclMaxMembers = 9;  // largest set a class-launched batch instance may have
+                                   // (neighbourhoods of degree 8)
+struct BclInst {
+    const uint64_t *P;
+    uint64_t *O;
+    Stripe *stripes;
+    const DevState *st;
+    const int32_t *roff;
+    const int32_t *recs;
+    const int32_t *class_ptr;
+    const int2 *class_rec;
+    uint64_t seed;
+    int64_t target;
+    int32_t N, always, k, order_fixed;
+};
+// Blocks of the batched class-launch sweep for the current device (co-resident count).
+hipError_t bcl_sweep_grid(int *grid);
+struct BclPlan {
+    const BclInst *insts;  // count instances
+    uint16_t *order;       // [i * kmax + t]: class at position t of instance i's order
+    int32_t *tiles;        // [t * (count + 1) + i]: tiles of instances before i at position t
+    int32_t count, kmax, grid;
+};
 
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
@@ -349,7 +384,8 @@ hipError_t batch_sweep_occupancy(int threads, int kind, int *blocks);
 hipError_t prepare_batch_step(const BatchLaunch *groups, int n_groups);
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
                              const BatchLaunch *groups, int n_groups, const int32_t *vblk,
-                             int vblocks, hipStream_t s, KernelEvents ev = {});
+                             int vblocks, const BclPlan &bcl, hipStream_t s,
+                             KernelEvents ev = {});
 hipError_t launch_batch_mark(const BatchInst *insts, int count, hipStream_t s);
 // Pack every instance's DevState into out[count].
 hipError_t launch_batch_gather(const BatchInst *insts, int count, DevState *out, hipStream_t s);

@@ -1836,6 +1836,151 @@ __global__ __launch_bounds__(kEpiThreads) void k_batch_vertex(const BatchInst *i
     vertex_body(I->epi, (int)blockIdx.x - I->vblock0);
 }
 
+// ------------------------------------------------------------------------------------------
+// Batched class launch.  Planning, part 1 (one block per instance): the instance's class order
+// of its current generation, the same Fisher-Yates draws as the host and the batched resident
+// sweep.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bcl_order(const BclInst *insts, uint16_t *order,
+                                                   int kmax) {
+    __shared__ uint16_t draw[2048];
+    const BclInst &I = insts[blockIdx.x];
+    uint16_t *ord = order + (size_t)blockIdx.x * kmax;
+    const int gen = I.st->generation;
+    const bool fixed = I.order_fixed != 0;
+    for (int t = threadIdx.x; t < I.k; t += 256) {
+        ord[t] = (uint16_t)t;
+        if (!fixed && t >= 1) {
+            const U32x4 r = philox(I.seed, (uint32_t)gen, kOrderStream, (uint32_t)t, 0u);
+            draw[t] = (uint16_t)(((uint64_t)r.x * (uint64_t)(t + 1)) >> 32);
+        }
+    }
+    __syncthreads();
+    if (!fixed && threadIdx.x == 0)
+        for (int t = I.k - 1; t >= 1; --t) {
+            const uint16_t x = ord[t];
+            ord[t] = ord[draw[t]];
+            ord[draw[t]] = x;
+        }
+}
+
+// Planning, part 2 (one block per position t): tiles of each instance's class at position t
+// (none past its class count or once its target is reached), and their exclusive prefix sums
+// over the instances; the total follows the last instance.
+__global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const uint16_t *order,
+                                                   int32_t *tiles, int count, int kmax) {
+    __shared__ int32_t part[256];
+    const int t = blockIdx.x;
+    int32_t *row = tiles + (size_t)t * (count + 1);
+    int32_t base = 0;
+    for (int i0 = 0; i0 < count; i0 += 256) {
+        const int i = i0 + (int)threadIdx.x;
+        int32_t n = 0;
+        if (i < count) {
+            const BclInst &I = insts[i];
+            if (t < I.k && I.st->elite_fitness < I.target) {
+                const int c = order[(size_t)i * kmax + t];
+                const int32_t cs = I.class_ptr[c + 1] - I.class_ptr[c];
+                n = (cs + kBclTile - 1) / kBclTile;
+            }
+        }
+        part[threadIdx.x] = n;
+        __syncthreads();
+        // inclusive scan of the 256 counts (Hillis-Steele)
+        for (int off = 1; off < 256; off <<= 1) {
+            const int32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (i < count) row[i] = base + part[threadIdx.x] - n;
+        base += part[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row[count] = base;
+}
+
+// The sweep of position t: blocks stride over the position's tiles; a tile is kBclTile
+// consecutive class positions of one instance, wave w of the block takes kBclPositions of
+// them, lane = solution (as the class-launch sweep with groups of 64: the record is wave-
+// uniform, one Philox call serves the wave's positions).  Fitness changes and counts go to
+// the instance's stripe of the tile, after each tile.
+constexpr int kBclRowLds = 1024;  // instances whose tile offsets a block keeps in LDS
+
+// (about 145 VGPRs: three waves per SIMD; capping it at 128 for four spilled to scratch)
+__global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
+    __shared__ int32_t srow[kBclRowLds + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t *row = pl.tiles + (size_t)t * (pl.count + 1);
+    // the position's tile offsets in LDS (for the instance search of every tile), when they fit
+    const bool in_lds = pl.count <= kBclRowLds;
+    if (in_lds)
+        for (int q = threadIdx.x; q <= pl.count; q += kBclThreads) srow[q] = row[q];
+    __syncthreads();
+    const int32_t *rs = in_lds ? srow : row;
+    const int32_t total = rs[pl.count];
+    const uint32_t i = (uint32_t)lane;
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        // the instance of this tile: the last one whose first tile is <= tile
+        int lo = 0, hi = pl.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rs[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = __builtin_amdgcn_readfirstlane(lo);
+        const BclInst &I = pl.insts[b];
+        const int c = pl.order[(size_t)b * pl.kmax + t];
+        const int cbase = I.class_ptr[c];
+        const int csize = I.class_ptr[c + 1] - cbase;
+        const int2 cr = I.class_rec[c];
+        const int p0 = __builtin_amdgcn_readfirstlane((tile - rs[b]) * kBclTile +
+                                                      wave * kBclPositions);
+        if (p0 >= csize) continue;
+        const uint64_t mism = I.stripes[lane].mism;
+        const bool act = (int)i < I.N;
+        const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
+        const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
+        const bool neutral_ok = (I.always != 0) | (bit_of(wave_or64(mism), i) != 0);
+        const int gen = I.st->generation;
+        const U32x4 q = philox(I.seed, (uint32_t)gen, (uint32_t)c, i, (uint32_t)(p0 >> 3));
+        const PlaneBits bits{I.O, i};
+        const PlaneCommit<64> commit{I.O, 0, i};
+        int64_t facc = 0;
+        uint32_t n_eval = 0, n_acc = 0;
+#pragma unroll 1
+        for (int f = 0; f < kBclPositions; ++f) {
+            const int p = p0 + f;
+            if (p >= csize) break;
+            const UniformAosRec R{cr.y ? I.recs + cr.x + p * cr.y : I.recs + I.roff[cbase + p]};
+            const HeadT<4> hd = load_head<1, 4>(R);  // entries 4 at a time: fewer registers
+            const int fl = p & 7;  // (wave-uniform) field of the call
+            const uint32_t w = (fl >> 1) == 0 ? q.x : (fl >> 1) == 1 ? q.y
+                             : (fl >> 1) == 2 ? q.z : q.w;
+            const uint32_t h = (w >> (16 * (fl & 1))) & 0xFFFFu;
+            // sets of at most kBclMaxMembers members (the host's eligibility rule): the small-
+            // set paths specialised to 4, 5, 8 and 9 member slots only
+            const int nm = hd.h0.x;
+            const PairOut r =
+                nm <= 4 ? small_pair_planes<4>(R, hd, I.P, bits, commit, cand, h, neutral_ok)
+                : nm <= 5 ? small_pair_planes<5>(R, hd, I.P, bits, commit, cand, h, neutral_ok)
+                : nm <= 8 ? small_pair_planes<8>(R, hd, I.P, bits, commit, cand, h, neutral_ok)
+                          : small_pair_planes<kBclMaxMembers>(R, hd, I.P, bits, commit, cand, h,
+                                                              neutral_ok);
+            facc += r.acc ? r.delta : 0;
+            n_eval += (uint32_t)__popcll(ballot64(r.cnt > 0));
+            n_acc += (uint32_t)__popcll(ballot64(r.acc));
+        }
+        Stripe *sp = I.stripes + ((p0 >> 3) % kStripes);
+        if (act && facc)
+            atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
+        if (lane == 0) {
+            if (n_eval) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)n_eval);
+            if (n_acc) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)n_acc);
+        }
+    }
+}
+
 // Start of a batch run: every instance's start tick, and its done tick if the target is
 // already reached.
 __global__ void k_batch_mark(const BatchInst *insts, int count) {
@@ -2078,6 +2223,18 @@ hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow
     return hipGetLastError();
 }
 
+hipError_t bcl_sweep_grid(int *grid) {
+    int dev = 0, cus = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_bcl_sweep,
+                                                         kBclThreads, 0);
+    if (e != hipSuccess) return e;
+    *grid = std::max(1, nb * cus);
+    return hipSuccess;
+}
+
 hipError_t fused_swar_grid(int *grid) {
     int dev = 0, cus = 0, nb = 1 << 30;
     hipError_t e = hipGetDevice(&dev);
@@ -2161,16 +2318,18 @@ hipError_t prepare_batch_step(const BatchLaunch *groups, int n_groups) {
 
 hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
                              const BatchLaunch *groups, int n_groups, const int32_t *vblk,
-                             int vblocks, hipStream_t s, KernelEvents ev) {
+                             int vblocks, const BclPlan &bcl, hipStream_t s, KernelEvents ev) {
     hipError_t e = prepare_batch_step(groups, n_groups);
     if (e != hipSuccess) return e;
+    // the step's timing spans the first sweep launch's start to the last one's end
+    const int n_bcl = bcl.count > 0 ? bcl.kmax : 0;  // sweep launches of the class launches
+    const int n_sweeps = n_groups + n_bcl;
     for (int q = 0; q < n_groups; ++q) {
         const BatchLaunch &G = groups[q];
         if (G.threads != 256 && G.threads != 1024) return hipErrorInvalidValue;
-        // the step's timing spans the first sweep launch's start to the last one's end
         KernelEvents gev;
         gev.start = q == 0 ? ev.start : nullptr;
-        gev.stop = q == n_groups - 1 ? ev.stop : nullptr;
+        gev.stop = q == n_sweeps - 1 ? ev.stop : nullptr;
         const int2 *gb = blk + G.first;
         if (G.threads == 256 && G.kind == 0)
             launch_timed(k_batch_sweep<256, 0>, dim3(G.count), dim3(256), G.lds, s, gev, insts, gb);
@@ -2184,6 +2343,25 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
                          gb);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    if (n_bcl > 0) {
+        if (bcl.kmax > 2048 || bcl.grid < 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_bcl_order, dim3(bcl.count), dim3(256), 0, s, bcl.insts, bcl.order,
+                           bcl.kmax);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bcl_tiles, dim3(bcl.kmax), dim3(256), 0, s, bcl.insts, bcl.order,
+                           bcl.tiles, bcl.count, bcl.kmax);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        for (int t = 0; t < bcl.kmax; ++t) {
+            KernelEvents gev;
+            gev.start = n_groups == 0 && t == 0 ? ev.start : nullptr;
+            gev.stop = t == bcl.kmax - 1 ? ev.stop : nullptr;
+            launch_timed(k_bcl_sweep, dim3(bcl.grid), dim3(kBclThreads), 0, s, gev, bcl, t);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(64), 0, s, insts);
     e = hipGetLastError();

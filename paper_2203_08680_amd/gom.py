@@ -37,8 +37,10 @@ EXPORTED = (
     "gom_state_info", "gom_state_free", "gom_batch_bytes", "gom_batch_init", "gom_batch_run",
     "gom_batch_set_graph", "gom_batch_reseed", "gom_batch_timing_enable",
     "gom_batch_timing_read", "gom_batch_set_narrow", "gom_batch_get_narrow",
-    "gom_batch_autotune", "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
+    "gom_batch_autotune", "gom_batch_set_class_launch", "gom_batch_get_class_launch",
+    "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
+    "gom_server_set_large",
 )
 
 
@@ -142,7 +144,9 @@ def lib() -> C.CDLL:
         "gom_batch_timing_read": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
         "gom_batch_set_narrow": (C.c_int, [_vp, _i64, _vp]),
         "gom_batch_get_narrow": (C.c_int, [_vp, _P(_i64), _P(_i32)]),
-        "gom_batch_autotune": (C.c_int, [_vp, _i32, _vp, _P(_i64)]),
+        "gom_batch_autotune": (C.c_int, [_vp, _i32, _vp, _P(_i64), _P(_i64)]),
+        "gom_batch_set_class_launch": (C.c_int, [_vp, _i64, _vp]),
+        "gom_batch_get_class_launch": (C.c_int, [_vp, _P(_i64), _P(_i32), _P(_i32)]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
@@ -151,6 +155,7 @@ def lib() -> C.CDLL:
         "gom_server_submit": (C.c_int, [_vp, _vp, _vp, _i32, _u64, _i64, _i32, C.c_int, C.c_int,
                                         _P(_i64)]),
         "gom_server_step": (C.c_int, [_vp, _P(_i32), _P(_i32)]),
+        "gom_server_set_large": (C.c_int, [_vp, _i64]),
         "gom_server_results": (C.c_int, [_vp, _vp, _i32, _P(_i32)]),
         "gom_server_info": (C.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_sz)]),
         "gom_server_free": (None, [_vp]),
@@ -653,13 +658,27 @@ def gom_batch_get_narrow(b: GomBatch):
     return t.value, n.value
 
 
-def gom_batch_autotune(b: GomBatch, trial_steps: int = 2, stream=None) -> int:
-    """Time trial generation steps under each block-size threshold and keep the fastest;
-    returns it.  The trial steps are ordinary steps of the run."""
-    c = _i64()
+def gom_batch_autotune(b: GomBatch, trial_steps: int = 2, stream=None):
+    """Time trial generation steps under each class-launch threshold, then each block-size
+    threshold, and keep the fastest; returns (block-size threshold, class-launch threshold).
+    The trial steps are ordinary steps of the run."""
+    c, m = _i64(), _i64()
     _check(lib().gom_batch_autotune(b.handle, int(trial_steps), _stream_handle(stream),
-                                    C.byref(c)))
-    return c.value
+                                    C.byref(c), C.byref(m)))
+    return c.value, m.value
+
+
+def gom_batch_set_class_launch(b: GomBatch, min_n: int, stream=None) -> None:
+    """Eligible instances with at least min_n vertices take the batched class launches
+    (-1: none)."""
+    _check(lib().gom_batch_set_class_launch(b.handle, int(min_n), _stream_handle(stream)))
+
+
+def gom_batch_get_class_launch(b: GomBatch):
+    """(threshold, instances selected, class launches per step)."""
+    m, n, k = _i64(), _i32(), _i32()
+    _check(lib().gom_batch_get_class_launch(b.handle, C.byref(m), C.byref(n), C.byref(k)))
+    return m.value, n.value, k.value
 
 
 def gom_batch_set_graph(b: GomBatch, enabled: bool = True) -> None:
@@ -706,6 +725,11 @@ class GomServer:
                                        int(class_order), C.byref(j)))
         self._jobs[j.value] = inst
         return j.value
+
+    def set_large(self, large_min_n: int) -> None:
+        """Jobs with at least large_min_n vertices run one at a time on the first stream
+        (-1: no size-aware placement)."""
+        _check(lib().gom_server_set_large(self.handle, int(large_min_n)))
 
     def step(self):
         """Admit what fits, retire or continue finished chunks; returns (active, queued)

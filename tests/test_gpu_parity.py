@@ -970,15 +970,16 @@ def test_batch_block_sizes_and_autotune(cuda):
     bt = gom.gom_batch_init(insts, pops, seeds, targets)
     chosen = gom.gom_batch_autotune(bt, 1)
     print(f"  autotuner chose {chosen}", flush=True)
-    res, _ = gom.gom_batch_run(bt, 20)
+    # (at most 2 x (5 + 6) trial steps ran)
+    res, _ = gom.gom_batch_run(bt, 40)
     for b, it in enumerate(items):
         st = insts[b].state(pop=pops[b], seed=seeds[b])
-        r = gom.gom_run_to_target(st, targets[b], 20)
+        r = gom.gom_run_to_target(st, targets[b], 40)
         assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), b
         if it.graph.n <= 400:
             ptr, vars_ = oracle.fos(it.graph, it.fos)
             ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=it.seed)
-            ref.run(targets[b], 20)
+            ref.run(targets[b], 40)
             assert gom.gom_state_hash(bt.state(b)) == ref.hash(), f"instance {b} vs oracle"
 
 
@@ -998,7 +999,7 @@ def test_batch_admits_instances_beyond_resident(cuda):
         pops.insert(1 + kind, pop)
         seeds.insert(1 + kind, 70 + kind)
     bt = gom.gom_batch_init(insts, pops, seeds, targets)
-    gom.gom_batch_autotune(bt, 1)  # (its trial steps are steps of the run: at most 12)
+    gom.gom_batch_autotune(bt, 1)  # (its trial steps are steps of the run: at most 22)
     res, _ = gom.gom_batch_run(bt, 30)
     for b in range(len(insts)):
         st = insts[b].state(pop=pops[b], seed=seeds[b])
@@ -1020,6 +1021,57 @@ def test_batch_admits_instances_beyond_resident(cuda):
         ref = oracle.Run(it.graph, ptr, vars_, pop=pops[b], seed=new_seeds[b])
         ref.run(targets[b], 6)
         assert gom.gom_state_hash(bt.state(b)) == ref.hash(), f"instance {b} vs oracle"
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "direct"])
+def test_batch_class_launches(cuda, graph):
+    """Neighbourhood instances swept by the batched class launches (one launch per class
+    position covering every such instance, lane = solution) beside univariate instances in
+    resident blocks: each instance equals its solo run, populations 2 to 64 (inactive lanes),
+    degree 3 to 8 neighbourhoods and tori; with graph chunks or direct launches, across calls
+    and a reseed; the small ones equal the oracle; switching the assignment mid-run keeps
+    every trajectory."""
+    print(f"case batch class launches graph={graph}", flush=True)
+    gs = [(workloads.configuration_model(900, 8, seed=30, weights="uniform", w_lo=1,
+                                         w_hi=100), 1, 64),
+          (workloads.torus(24, 1, 100, seed=31), 1, 17),
+          (workloads.configuration_model(2500, 3, seed=32), 1, 2),
+          (workloads.configuration_model(300, 6, seed=33), 1, 40),
+          (workloads.torus(30, 1, 100, seed=34), 0, 33),
+          (workloads.configuration_model(1200, 5, seed=35), 1, 33)]
+    insts = [gom.Instance(g.n, g.u, g.v, g.w, k) for g, k, _ in gs]
+    pops = [p for _, _, p in gs]
+    seeds = [40 + b for b in range(len(gs))]
+    targets = [g.total_weight if b in (1, 4) else (1 << 62) for b, (g, _, _) in enumerate(gs)]
+    bt = gom.gom_batch_init(insts, pops, seeds, targets)
+    gom.gom_batch_set_graph(bt, graph)
+    gom.gom_batch_set_class_launch(bt, 0)
+    m, n_inst, launches = gom.gom_batch_get_class_launch(bt)
+    assert m == 0 and n_inst == 5 and launches >= 1
+    gom.gom_batch_run(bt, 5)
+    gom.gom_batch_set_class_launch(bt, 1000)   # the two largest only
+    assert gom.gom_batch_get_class_launch(bt)[1] == 2
+    gom.gom_batch_run(bt, 9)
+    gom.gom_batch_set_class_launch(bt, 0)
+    res, _ = gom.gom_batch_run(bt, 15)
+    for b in range(len(gs)):
+        st = insts[b].state(pop=pops[b], seed=seeds[b])
+        r = gom.gom_run_to_target(st, targets[b], 15)
+        # (res counts the generations of the last call only)
+        g = gom.gom_state_read(bt.state(b), genes=False)["generation"]
+        assert (g, res[b].best, res[b].evaluated, res[b].accepted) == \
+            (r.generations, r.best, r.evaluated, r.accepted), b
+        assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), b
+    new_seeds = [s + 500 for s in seeds]
+    gom.gom_batch_reseed(bt, new_seeds)
+    gom.gom_batch_run(bt, 7)
+    for b, (g, kind, pop) in enumerate(gs):
+        if g.n > 1000:
+            continue
+        ptr, vars_ = oracle.fos(g, kind)
+        ref = oracle.Run(g, ptr, vars_, pop=pop, seed=new_seeds[b])
+        ref.run(targets[b], 7)
+        assert_same(gom.gom_state_read(bt.state(b)), ref.state(), f"class-launch batch {b}")
 
 
 def test_batch_graph_replays_equal_direct_launches(cuda):
@@ -1117,6 +1169,43 @@ def test_server_jobs_equal_solo_runs(cuda):
         assert (got["generations"], got["best"], got["evaluated"], got["accepted"]) == \
             (ran, s["elite_fitness"], s["evaluated"], s["accepted"]), f"job {jid} vs oracle"
         assert got["hash"] == ref.hash(), f"job {jid}: hash differs from the oracle's"
+
+
+def test_server_size_aware_placement(cuda):
+    """With size-aware placement the large jobs run one at a time (each admitted after the
+    previous large one finished) while small jobs submitted after them still start; every
+    result equals its solo run."""
+    print("case server size-aware", flush=True)
+    small = workloads.batch_mix(count=6, seed=23, n_lo=100, n_hi=600)
+    jobs = []
+    for it in small:
+        inst = gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
+        jobs.append((inst, it.pop, it.seed, 1 << 62, 8))
+    for k, L in enumerate((40, 44, 48)):
+        g = workloads.torus(L, 1, 100, seed=60 + k)
+        jobs.insert(2 * k, (gom.Instance(g.n, g.u, g.v, g.w, k % 2), 32, 80 + k, 1 << 62, 10))
+    srv = gom.GomServer(64 << 20, max_jobs=16, streams=3)
+    srv.set_large(1500)
+    ids = [srv.submit(*j) for j in jobs]
+    res = {}
+    t_end = time.time() + 60
+    while time.time() < t_end:
+        a, q = srv.step()
+        for r in srv.results():
+            res[r["job"]] = r
+        if a == 0 and q == 0:
+            break
+    assert sorted(res) == sorted(ids)
+    large = sorted((res[ids[2 * k]] for k in range(3)), key=lambda r: r["admit_ms"])
+    for prev, nxt in zip(large, large[1:]):
+        assert nxt["admit_ms"] >= prev["done_ms"], "two large jobs overlapped"
+    # a small job submitted after the first large one started before that one finished
+    assert min(res[ids[k]]["admit_ms"] for k in (1, 3)) < large[0]["done_ms"]
+    for jid, (inst, pop, seed, tg, mg) in zip(ids, jobs):
+        st = inst.state(pop=pop, seed=seed)
+        r = gom.gom_run_to_target(st, tg, mg)
+        assert res[jid]["hash"] == gom.gom_state_hash(st), jid
+        assert res[jid]["generations"] == r.generations
 
 
 def _two_vertices():
