@@ -626,10 +626,10 @@ def main():
                     help="arrival rate as a fraction of the measured plain capacity")
     ap.add_argument("--serve-arena-gb", type=float, default=32.0)
     ap.add_argument("--serve-streams", type=int, default=4)
-    ap.add_argument("--serve-large-min", type=int, default=50_000,
+    ap.add_argument("--serve-large-min", type=int, default=-1,
                     help="jobs with at least this many vertices run one at a time on the "
-                         "first stream, small jobs on the others (-1: every job on the least "
-                         "loaded stream)")
+                         "first stream, small jobs on the others (default -1: every job on "
+                         "the least loaded stream)")
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
     ap.add_argument("--metrics-jsonl", default=None,

@@ -422,8 +422,9 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
     }
     R.roff[S] = (int32_t)R.words.size();
     // zero tail: the kernels fetch the first entry batches of a record together with its
-    // header, which may read up to 48 words past the end of the last record
-    for (int q = 0; q < 64; ++q) R.words.push_back(0);
+    // header (up to 48 words past the end of the last record), the batched class launches a
+    // record's first kRecordTailWords words
+    for (int q = 0; q < kRecordTailWords; ++q) R.words.push_back(0);
     return GOM_OK;
 }
 
@@ -2160,9 +2161,12 @@ static int batch_reg_blocks(int threads, int kind) {
 // (longer blocks) come first.  Uploads the instance table and the block map (synchronous)
 // and drops a captured graph.
 // May instance s take the batched class launches (general records of sets of at most
-// kBclMaxMembers members)?
+// kBclMaxMembers members and kBclMaxEntries dependent edges)?
 static bool bcl_eligible(const gom_state *s) {
-    return !s->univariate && s->max_set <= kBclMaxMembers && s->k <= 2048;
+    if (s->univariate || s->max_set > kBclMaxMembers || s->k > 2048) return false;
+    for (int32_t e : s->class_entries)
+        if (e > kBclMaxEntries) return false;
+    return true;
 }
 
 static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,

@@ -310,6 +310,9 @@ constexpr int kBclTile = kBclWaves * kBclPositions;
 constexpr int kBclThreads = 64 * kBclWaves;
 constexpr int kBclMaxMembers = 9;  // largest set a class-launched batch instance may have
                                    // (neighbourhoods of degree 8)
+constexpr int kBclMaxEntries = 72; // ... and most dependent edges of one of its sets
+// Words past a record's start that a sweep may read (the record buffer's zero tail).
+constexpr int kRecordTailWords = 192;
 struct BclInst {
     const uint64_t *P;
     uint64_t *O;

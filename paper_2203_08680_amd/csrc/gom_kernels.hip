@@ -1905,6 +1905,96 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
 // them, lane = solution (as the class-launch sweep with groups of 64: the record is wave-
 // uniform, one Philox call serves the wave's positions).  Fitness changes and counts go to
 // the instance's stripe of the tile, after each tile.
+// Wave-uniform broadcast of lane l's 32- and 64-bit values (l wave-uniform).
+__device__ __forceinline__ int32_t lane_i32(int32_t v, int l) {
+    return __builtin_amdgcn_readlane(v, l);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+// Word idx (< 192) of a record staged as three registers of 64 words (lane l of rK holds word
+// 64 K + l), fetched by every lane for its own idx.
+__device__ __forceinline__ int32_t staged_word(int32_t r0, int32_t r1, int32_t r2, int idx) {
+    const int src = (idx & 63) << 2;  // ds_bpermute addresses bytes
+    const int32_t a = __builtin_amdgcn_ds_bpermute(src, r0);
+    const int32_t b = __builtin_amdgcn_ds_bpermute(src, r1);
+    const int32_t c = __builtin_amdgcn_ds_bpermute(src, r2);
+    return idx < 64 ? a : (idx < 128 ? b : c);
+}
+
+// GOM step of every solution of the wave (lane i = solution i) on one small set (at most
+// kBclMaxMembers members, kBclMaxEntries dependent edges), with the set's data staged by the
+// wave in two rounds of loads instead of one round per batch of entries:
+//   1. the record's first 192 words, three coalesced loads per lane (the record buffer keeps
+//      a zero tail of that length, so a load past the last record stays inside it);
+//   2. lane k < nm loads member k's P and O words, lane e < nd (and e + 64) the O word at
+//      the far end of dependent edge e when that end lies outside the set;
+// then every lane reads members, entries and words with lane reads (wave-uniform values)
+// and decides its own step exactly as the other sweeps do: donors D, the draw's r-th donor,
+// the changed members C, delta over the dependent edges, acceptance, and a masked store of
+// each changed member's word.
+__device__ __forceinline__ PairOut staged_pair(const int32_t *rec, const uint64_t *P, uint64_t *O,
+                                               uint32_t i, uint64_t cand, uint32_t h,
+                                               bool neutral_ok) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t r0 = rec[lane], r1 = rec[64 + lane], r2 = rec[128 + lane];
+    const int nm = __builtin_amdgcn_readfirstlane(r0);        // word 0
+    const int nd = __builtin_amdgcn_readlane(r0, 1);           // word 1
+    // round 2: member words (lanes < nm) and far-end words (lanes < nd, and lane + 64 < nd)
+    const int u = staged_word(r0, r1, r2, 2 + (lane < kBclMaxMembers ? lane : 0));
+    const int32_t xlo = staged_word(r0, r1, r2, 16 + 2 * lane);
+    const int32_t wlo = staged_word(r0, r1, r2, 17 + 2 * lane);
+    const int hl = lane < kBclMaxEntries - 64 ? lane : 0;      // entries 64.. (at most 8)
+    const int32_t xhi = staged_word(r0, r1, r2, 16 + 2 * (64 + hl));
+    const int32_t whi = staged_word(r0, r1, r2, 17 + 2 * (64 + hl));
+    const bool mem = lane < nm;
+    const uint64_t pw = mem ? P[u] : 0ull, ow = mem ? O[u] : 0ull;
+    const bool olo = lane < nd && xlo >= 0, ohi = 64 + lane < nd && xhi >= 0;
+    const uint64_t flo = olo ? O[(uint32_t)xlo & kSmallIdx] : 0ull;
+    const uint64_t fhi = ohi ? O[(uint32_t)xhi & kSmallIdx] : 0ull;
+    PairOut out{0u, false, 0};
+    uint32_t om = 0;
+    uint64_t D = 0;
+    for (int k = 0; k < nm; ++k) {
+        const uint32_t ok = bit_of(lane_u64(ow, k), i);
+        om |= ok << k;
+        D |= lane_u64(pw, k) ^ (0ull - (uint64_t)ok);
+    }
+    D &= cand;
+    out.cnt = (uint32_t)__popcll(D);
+    const uint32_t d = out.cnt ? select_bit(D, (h * out.cnt) >> 16) : 0u;
+    uint32_t cm = 0;
+    for (int k = 0; k < nm; ++k) cm |= (bit_of(lane_u64(pw, k), d) ^ ((om >> k) & 1u)) << k;
+    int64_t delta = 0;
+    for (int e = 0; e < nd; ++e) {
+        const bool hi = e >= 64;
+        const int l = e & 63;
+        const int32_t x = lane_i32(hi ? xhi : xlo, l);
+        const int32_t w = lane_i32(hi ? whi : wlo, l);
+        const uint32_t a = ((uint32_t)x >> kSmallPosShift) & 15u;
+        const uint32_t y = (uint32_t)x & kSmallIdx;
+        const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
+        uint32_t ov, flip;
+        if (x < 0) {  // inside edge to member y (wave-uniform branch)
+            ov = (om >> y) & 1u;
+            flip = ca ^ ((cm >> y) & 1u);
+        } else {
+            ov = bit_of(lane_u64(hi ? fhi : flo, l), i);
+            flip = ca;
+        }
+        delta += flip ? signed_w(oa == ov, w) : 0;
+    }
+    out.delta = delta;
+    out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+    // commit: each changed member's new word, stored by the lane that loaded it
+    for (int k = 0; k < nm; ++k) {
+        const uint64_t fm = ballot64(out.acc && ((cm >> k) & 1u));
+        if (fm && lane == k) O[u] = ow ^ fm;
+    }
+    return out;
+}
+
 constexpr int kBclRowLds = 1024;  // instances whose tile offsets a block keeps in LDS
 
 // (about 145 VGPRs: three waves per SIMD; capping it at 128 for four spilled to scratch)
@@ -1944,29 +2034,18 @@ __global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
         const bool neutral_ok = (I.always != 0) | (bit_of(wave_or64(mism), i) != 0);
         const int gen = I.st->generation;
         const U32x4 q = philox(I.seed, (uint32_t)gen, (uint32_t)c, i, (uint32_t)(p0 >> 3));
-        const PlaneBits bits{I.O, i};
-        const PlaneCommit<64> commit{I.O, 0, i};
         int64_t facc = 0;
         uint32_t n_eval = 0, n_acc = 0;
 #pragma unroll 1
         for (int f = 0; f < kBclPositions; ++f) {
             const int p = p0 + f;
             if (p >= csize) break;
-            const UniformAosRec R{cr.y ? I.recs + cr.x + p * cr.y : I.recs + I.roff[cbase + p]};
-            const HeadT<4> hd = load_head<1, 4>(R);  // entries 4 at a time: fewer registers
+            const int32_t *rec = cr.y ? I.recs + cr.x + p * cr.y : I.recs + I.roff[cbase + p];
             const int fl = p & 7;  // (wave-uniform) field of the call
             const uint32_t w = (fl >> 1) == 0 ? q.x : (fl >> 1) == 1 ? q.y
                              : (fl >> 1) == 2 ? q.z : q.w;
             const uint32_t h = (w >> (16 * (fl & 1))) & 0xFFFFu;
-            // sets of at most kBclMaxMembers members (the host's eligibility rule): the small-
-            // set paths specialised to 4, 5, 8 and 9 member slots only
-            const int nm = hd.h0.x;
-            const PairOut r =
-                nm <= 4 ? small_pair_planes<4>(R, hd, I.P, bits, commit, cand, h, neutral_ok)
-                : nm <= 5 ? small_pair_planes<5>(R, hd, I.P, bits, commit, cand, h, neutral_ok)
-                : nm <= 8 ? small_pair_planes<8>(R, hd, I.P, bits, commit, cand, h, neutral_ok)
-                          : small_pair_planes<kBclMaxMembers>(R, hd, I.P, bits, commit, cand, h,
-                                                              neutral_ok);
+            const PairOut r = staged_pair(rec, I.P, I.O, i, cand, h, neutral_ok);
             facc += r.acc ? r.delta : 0;
             n_eval += (uint32_t)__popcll(ballot64(r.cnt > 0));
             n_acc += (uint32_t)__popcll(ballot64(r.acc));
