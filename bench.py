@@ -266,7 +266,8 @@ def run_batch_mode(args, torch, gom):
     batch = gom.gom_batch_init(insts, pops, step_seeds(items, 0), targets)
     gom.gom_batch_set_graph(batch, args.batch_graph == "on")
     log(f"batch states: {time.perf_counter() - t0:.1f} s")
-    tuned = args.batch_narrow is None and args.batch_class_min is None
+    tuned = (args.batch_narrow is None and args.batch_class_min is None and
+             args.batch_class_ppw is None)
     if tuned:
         t0 = time.perf_counter()
         chosen = gom.gom_batch_autotune(batch, 2)
@@ -276,8 +277,10 @@ def run_batch_mode(args, torch, gom):
             gom.gom_batch_set_narrow(batch, args.batch_narrow)
         if args.batch_class_min is not None:
             gom.gom_batch_set_class_launch(batch, args.batch_class_min)
+        if args.batch_class_ppw is not None:
+            gom.gom_batch_set_class_positions(batch, args.batch_class_ppw)
     narrow, sweep_launches = gom.gom_batch_get_narrow(batch)
-    class_min, class_insts, class_launches = gom.gom_batch_get_class_launch(batch)
+    class_min, class_insts, class_launches, class_ppw = gom.gom_batch_get_class_launch(batch)
 
     def one_step(k):
         gom.gom_batch_reseed(batch, step_seeds(items, k))
@@ -383,6 +386,7 @@ def run_batch_mode(args, torch, gom):
                    "narrow_blocks_max_n": narrow, "resident_launches_per_step": sweep_launches,
                    "class_launch_min_n": class_min, "class_launch_instances": class_insts,
                    "class_launches_per_step": class_launches,
+                   "class_positions_per_wave": class_ppw,
                    "launch_shapes": "autotuned" if tuned else "fixed",
                    "generation_steps": ("hip_graph_chunks_of_4" if args.batch_graph == "on"
                                         else "direct_launches"),
@@ -609,6 +613,8 @@ def main():
                     help="batched mode: neighbourhood instances with at least this many "
                          "vertices take the batched class launches (-1: none; default: "
                          "autotuned)")
+    ap.add_argument("--batch-class-ppw", type=int, default=None,
+                    help="batched mode: class positions per wave of the class launches (1..8)")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",
                     help="batched steps as captured HIP graph chunks (default) or direct launches")
     ap.add_argument("--ims", action="store_true",
@@ -635,6 +641,9 @@ def main():
     ap.add_argument("--metrics-jsonl", default=None,
                     help="plain mode: write per-generation metrics of one more run to this "
                          "file (JSON lines)")
+    ap.add_argument("--staged", action="store_true",
+                    help="plain mode: class sweeps of small general sets take the staged "
+                         "evaluation (two rounds of loads per set)")
     ap.add_argument("--no-fused", action="store_true",
                     help="bit-sliced schedule: one launch per class instead of the fused "
                          "generation sweep")
@@ -702,6 +711,8 @@ def main():
         gom.gom_state_set_block(st, args.block)
     if args.no_fused and gom.gom_state_get_fused(st)[1]:
         gom.gom_state_set_fused(st, False)
+    if args.staged:
+        gom.gom_state_set_staged(st, True)
     sched = gom.gom_state_get_schedule(st)
     sched_name = {gom.GOM_SCHED_RESIDENT: "resident", gom.GOM_SCHED_BITSLICED: "bitsliced"}.get(
         sched, "class_launch")
@@ -828,6 +839,7 @@ def main():
                    "classes": info["n_classes"], "seeds": list(range(1, args.steps + 1)),
                    "mode": "plain", "schedule": sched_name,
                    "class_sweep_block": gom.gom_state_get_block(st),
+                   "staged_evaluation": bool(args.staged),
                    "forced_improvement": bool(args.fi),
                    "local_search_after_each_generation": bool(args.local_search),
                    "iterated_local_search": ({"rounds": args.ils[0], "flips": args.ils[1]}

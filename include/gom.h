@@ -378,6 +378,14 @@ int gom_state_set_fused(gom_state *s, int enabled);
  * results do not depend on it.  Errors: GOM_E_ARG, GOM_E_RANGE (outside 1..65536).
  */
 int gom_state_set_grid_limit(gom_state *s, int32_t blocks);
+/*
+ * Class sweeps of small general sets (at most 9 members and 72 dependent edges; population
+ * above 32) stage each set in two rounds of loads by its wave (record, then member and
+ * far-end words) instead of fetching the record's entries in batches (default off: on the
+ * 100x100 torus's neighbourhoods it was 7 % slower per generation, on the 10^6-vertex torus's
+ * within 1 %).  Results are identical either way.  Errors: GOM_E_ARG.
+ */
+int gom_state_set_staged(gom_state *s, int enabled);
 int gom_state_get_fused(const gom_state *s, int *enabled, int *available);
 int gom_state_set_block(gom_state *s, int threads);
 int gom_state_get_block(const gom_state *s, int *threads);
@@ -500,14 +508,18 @@ int gom_batch_get_narrow(const gom_batch *b, int64_t *narrow_max_n, int32_t *lau
  */
 int gom_batch_set_class_launch(gom_batch *b, int64_t min_n, void *stream);
 int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, int32_t *instances,
-                               int32_t *launches);
+                               int32_t *launches, int32_t *positions_per_wave);
+/* Consecutive class positions a wave of the class launches sweeps (1..8; default 2): more
+ * share a Philox call, fewer give small classes more waves.  Errors: GOM_E_ARG, GOM_E_RANGE. */
+int gom_batch_set_class_positions(gom_batch *b, int32_t positions_per_wave);
 
 /*
  * Autotuner of the batch's launch shapes: runs trial_steps generation steps under each
  * candidate class-launch threshold (none, 50000, 20000, 5000 vertices, all eligible), then
  * under each block-size threshold (all 1024-thread blocks, 2048, 8192, 16384, 32768 vertices,
- * all 256-thread blocks), candidates that give the same assignment only once, timed with HIP
- * events on `stream` in two interleaved rounds, and keeps the fastest of each.  The trial
+ * all 256-thread blocks), then (when some instance takes the class launches) under 1, 2, 4
+ * and 8 positions per wave, candidates that give the same assignment only once, timed with
+ * HIP events on `stream` in two interleaved rounds, and keeps the fastest of each.  The trial
  * steps are ordinary generation steps of the run (they count against gom_batch_run's step
  * budget).  Synchronous.  narrow, class_min (or NULL): the thresholds kept.
  * Errors: GOM_E_ARG, GOM_E_STATE (an open generation), GOM_E_RANGE, GOM_E_DEVICE.

@@ -130,6 +130,7 @@ struct Records {
     std::vector<int32_t> roff, words;
     std::vector<int2> class_rec;        // per class {first word, stride or 0}
     std::vector<int32_t> class_entries;  // per class: most dependent-edge entries of a record
+    std::vector<int32_t> class_members;  // per class: most members of a set
 };
 
 constexpr int kSmallSet = 14;         // members held in a small record's header
@@ -326,6 +327,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
     std::vector<int32_t> ends;
     R.class_rec.assign((size_t)f.k, make_int2(0, 0));
     R.class_entries.assign((size_t)f.k, 0);
+    R.class_members.assign((size_t)f.k, 1);
     int32_t s = 0;
     for (int32_t c = 0; c < f.k; ++c) {
         const size_t class_first = R.words.size();
@@ -377,6 +379,7 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
             }
             const int32_t nd = (int32_t)ent.size();
             R.class_entries[c] = std::max(R.class_entries[c], nd);
+            R.class_members[c] = std::max(R.class_members[c], nm);
             R.words.push_back(nm);
             R.words.push_back(nd);
             if (small) {
@@ -468,6 +471,8 @@ struct gom_state {
     int2 *d_crec = nullptr;
     std::vector<int2> class_rec;  // host copy of the per-class record placement
     std::vector<int32_t> class_entries;  // per class: most entries of one of its records
+    std::vector<int32_t> class_members;  // per class: most members of one of its sets
+    bool staged_use = false;            // per-class sweeps of small general sets staged
     std::vector<int32_t> coop_ptr, coop_max;  // large sets per class (block-cooperative)
     int32_t *d_coop = nullptr;                // their class positions
     int32_t *d_sw = nullptr;                  // bit-sliced sweep table (when eligible)
@@ -1050,6 +1055,11 @@ static int enqueue_epilogue(gom_state *s, int64_t target, hipStream_t st, bool r
 
 // Class sweeps for order positions [t0, t1) of generation `gen` under the per-class schedules
 // (bit-sliced when chosen, else class launch).
+// Class c has no set for the block-cooperative or split sweeps.
+static bool nl_coop_free(const gom_state *s, int32_t c) {
+    return s->coop_ptr[2 * (size_t)c + 2] == s->coop_ptr[2 * (size_t)c] && !s->split[(size_t)c];
+}
+
 // The generation-wide fields of a class sweep's arguments.
 static SweepArgs sweep_args(const gom_state *s, int32_t gen, int64_t target, bool forced) {
     SweepArgs a{};
@@ -1121,8 +1131,15 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         if (rc) return rc;
         const int32_t nl = s->coop_ptr[2 * (size_t)c + 2] - s->coop_ptr[2 * (size_t)c];
         a.coop = nl > 0 ? 1 : 0;
+        // small general sets swept with every solution of a wave (64 lanes) take the staged
+        // evaluation: the set's record and words in two rounds of loads
+        const bool staged = s->staged_use && !forced && !s->univariate && s->N > 32 &&
+                            s->class_members[c] <= kBclMaxMembers &&
+                            s->class_entries[c] <= kBclMaxEntries && nl_coop_free(s, c);
         if (s->sched == GOM_SCHED_BITSLICED && !forced)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->swar_narrow, s->max_grid, st, ev));
+        else if (staged)
+            HIP_TRY(launch_class_sweep_staged(a, s->max_grid, s->sweep_threads, st, ev));
         else
             HIP_TRY(launch_class_sweep(a, s->univariate ? 0 : 1,
                                        s->class_entries[c] <= kShortRecordEntries, s->max_grid,
@@ -1290,6 +1307,7 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
     s->d_crec = (int2 *)(s->arena + L.crec);
     s->class_rec = R.class_rec;
     s->class_entries = R.class_entries;
+    s->class_members = R.class_members;
     s->coop_ptr = CS.ptr;
     s->coop_max = CS.max_members;
     s->d_coop = (int32_t *)(s->arena + L.coop);
@@ -1953,6 +1971,12 @@ extern "C" int gom_state_set_block(gom_state *s, int threads) {
     return GOM_OK;
 }
 
+extern "C" int gom_state_set_staged(gom_state *s, int enabled) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_staged: null state");
+    s->staged_use = enabled != 0;
+    return GOM_OK;
+}
+
 extern "C" int gom_state_set_grid_limit(gom_state *s, int32_t blocks) {
     if (!s) return fail(GOM_E_ARG, "gom_state_set_grid_limit: null state");
     if (blocks < 1 || blocks > 65536)
@@ -2035,6 +2059,7 @@ struct gom_batch {
     uint16_t *d_bcl_order = nullptr;
     int32_t *d_bcl_tiles = nullptr;
     int bcl_kmax = 0, bcl_grid = 0;
+    int bcl_ppw = 2;                    // class positions per wave of the class launches
     int64_t narrow_max_n = -1;          // instances with n <= this run 256-thread blocks
     size_t lds_max = 0;                 // LDS per CU of the device
     DevState *h_st = nullptr;           // pinned, 2 x count
@@ -2326,6 +2351,7 @@ static BclPlan bcl_plan(const gom_batch *b) {
     p.count = (int32_t)b->bcl.size();
     p.kmax = b->bcl_kmax;
     p.grid = b->bcl_grid;
+    p.ppw = b->bcl_ppw;
     return p;
 }
 
@@ -2749,6 +2775,30 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
             c2.push_back({nm, best.second});
         best = tune(c2);
     }
+    // then the class launches' positions per wave (when some instance takes them)
+    rc = rc == GOM_OK && e == hipSuccess ? batch_regroup(b, best.first, best.second, st) : rc;
+    if (rc == GOM_OK && e == hipSuccess && !b->bcl.empty()) {
+        const int ppws[] = {1, 2, 4, 8};
+        std::vector<double> total(4, 0.0);
+        for (int round = 0; round < 2 && rc == GOM_OK && e == hipSuccess; ++round)
+            for (int q = 0; q < 4 && rc == GOM_OK && e == hipSuccess; ++q) {
+                b->bcl_ppw = ppws[q];
+                e = hipEventRecord(e0, st);
+                for (int32_t t = 0; t < trial_steps && e == hipSuccess && rc == GOM_OK; ++t) {
+                    e = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
+                                          (int)b->groups.size(), b->d_vblk, b->vblocks,
+                                          bcl_plan(b), st);
+                    if (e == hipSuccess) rc = batch_solo_steps(b, 1, st);
+                }
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                total[(size_t)q] += ms;
+                b->g_done += trial_steps;
+            }
+        b->bcl_ppw = ppws[std::min_element(total.begin(), total.end()) - total.begin()];
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
@@ -2774,11 +2824,29 @@ extern "C" int gom_batch_set_class_launch(gom_batch *b, int64_t min_n, void *str
 }
 
 extern "C" int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, int32_t *instances,
-                                          int32_t *launches) {
+                                          int32_t *launches, int32_t *positions_per_wave) {
     if (!b) return fail(GOM_E_ARG, "gom_batch_get_class_launch: null batch");
     if (min_n) *min_n = b->bcl_min_n;
     if (instances) *instances = (int32_t)b->bcl.size();
     if (launches) *launches = b->bcl.empty() ? 0 : b->bcl_kmax;
+    if (positions_per_wave) *positions_per_wave = b->bcl_ppw;
+    return GOM_OK;
+}
+
+extern "C" int gom_batch_set_class_positions(gom_batch *b, int32_t positions_per_wave) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_set_class_positions: null batch");
+    if (positions_per_wave < 1 || positions_per_wave > kBclPositions)
+        return fail(GOM_E_RANGE, "gom_batch_set_class_positions: %d (1..%d)", positions_per_wave,
+                    kBclPositions);
+    b->bcl_ppw = positions_per_wave;
+    if (b->graph_exec) {  // the captured chunk holds the old launch arguments
+        (void)hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
     return GOM_OK;
 }
 

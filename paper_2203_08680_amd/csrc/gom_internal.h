@@ -298,15 +298,15 @@ constexpr size_t kStaticArenaBytes = size_t(64) << 20;
 // Device address of the current device's static arena (looked up once per device).
 hipError_t static_arena_address(void **ptr);
 
-// Batched class launch (general FOS whose sets all have at most 14 members, in a batch): one
-// launch per position t of the generation's class order covers class pi_i[t] of every such
-// instance i.  Lane = solution (64 lanes per wave), so a set's record is read once for all
-// solutions; a wave sweeps kBclPositions consecutive positions (one Philox call), a block
-// kBclWaves waves' worth (a tile).  Per step a planning pair of kernels draws every instance's
-// class order and the prefix sums of its tiles per position.
+// Batched class launch (FOS whose sets all have at most kBclMaxMembers members, in a batch):
+// one launch per position t of the generation's class order covers class pi_i[t] of every
+// such instance i.  Lane = solution (64 lanes per wave), so a set's record is read once for
+// all solutions; a wave sweeps ppw consecutive positions (at most kBclPositions, the positions
+// one Philox call serves), a block kBclWaves waves' worth (a tile).  Per step a planning pair
+// of kernels draws every instance's class order and the prefix sums of its tiles per
+// position.
 constexpr int kBclWaves = 4;
 constexpr int kBclPositions = 8;
-constexpr int kBclTile = kBclWaves * kBclPositions;
 constexpr int kBclThreads = 64 * kBclWaves;
 constexpr int kBclMaxMembers = 9;  // largest set a class-launched batch instance may have
                                    // (neighbourhoods of degree 8)
@@ -333,6 +333,8 @@ struct BclPlan {
     uint16_t *order;       // [i * kmax + t]: class at position t of instance i's order
     int32_t *tiles;        // [t * (count + 1) + i]: tiles of instances before i at position t
     int32_t count, kmax, grid;
+    int32_t ppw;           // consecutive class positions per wave (1..kBclPositions); a tile
+                           // is kBclWaves * ppw positions
 };
 
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
@@ -349,6 +351,10 @@ hipError_t launch_full_fitness(const uint64_t *P, const int32_t *eu, const int32
 constexpr int kShortRecordEntries = 16;
 hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, int max_grid,
                               int threads, hipStream_t s, KernelEvents ev = {});
+// Class sweep of small general sets (at most kBclMaxMembers members, kBclMaxEntries dependent
+// edges, population above 32) with each set staged by its wave in two rounds of loads.
+hipError_t launch_class_sweep_staged(const SweepArgs &a, int max_grid, int threads,
+                                     hipStream_t s, KernelEvents ev = {});
 // Bit-parallel class sweep: univariate FOS, degree <= 4, per-set |weight| sums below 2^30.
 // Block-cooperative sweep of the large sets of one class (a.n_large blocks); max_members:
 // the largest of them (dynamic LDS of 8 bytes per member).

@@ -766,6 +766,149 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep(SweepArgs a) {
     }
 }
 
+// Wave-uniform broadcast of lane l's 32- and 64-bit values (l wave-uniform).
+__device__ __forceinline__ int32_t lane_i32(int32_t v, int l) {
+    return __builtin_amdgcn_readlane(v, l);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+// Word idx (< 192) of a record staged as three registers of 64 words (lane l of rK holds word
+// 64 K + l), fetched by every lane for its own idx.
+__device__ __forceinline__ int32_t staged_word(int32_t r0, int32_t r1, int32_t r2, int idx) {
+    const int src = (idx & 63) << 2;  // ds_bpermute addresses bytes
+    const int32_t a = __builtin_amdgcn_ds_bpermute(src, r0);
+    const int32_t b = __builtin_amdgcn_ds_bpermute(src, r1);
+    const int32_t c = __builtin_amdgcn_ds_bpermute(src, r2);
+    return idx < 64 ? a : (idx < 128 ? b : c);
+}
+
+// GOM step of every solution of the wave (lane i = solution i) on one small set (at most
+// kBclMaxMembers members, kBclMaxEntries dependent edges), with the set's data staged by the
+// wave in two rounds of loads instead of one round per batch of entries:
+//   1. the record's first 192 words, three coalesced loads per lane (the record buffer keeps
+//      a zero tail of that length, so a load past the last record stays inside it);
+//   2. lane k < nm loads member k's P and O words, lane e < nd (and e + 64) the O word at
+//      the far end of dependent edge e when that end lies outside the set;
+// then every lane reads members, entries and words with lane reads (wave-uniform values)
+// and decides its own step exactly as the other sweeps do: donors D, the draw's r-th donor,
+// the changed members C, delta over the dependent edges, acceptance, and a masked store of
+// each changed member's word.
+__device__ __forceinline__ PairOut staged_pair(const int32_t *rec, const uint64_t *P, uint64_t *O,
+                                               uint32_t i, uint64_t cand, uint32_t h,
+                                               bool neutral_ok) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t r0 = rec[lane], r1 = rec[64 + lane], r2 = rec[128 + lane];
+    const int nm = __builtin_amdgcn_readfirstlane(r0);        // word 0
+    const int nd = __builtin_amdgcn_readlane(r0, 1);           // word 1
+    // round 2: member words (lanes < nm) and far-end words (lanes < nd, and lane + 64 < nd)
+    const int u = staged_word(r0, r1, r2, 2 + (lane < kBclMaxMembers ? lane : 0));
+    const int32_t xlo = staged_word(r0, r1, r2, 16 + 2 * lane);
+    const int32_t wlo = staged_word(r0, r1, r2, 17 + 2 * lane);
+    const int hl = lane < kBclMaxEntries - 64 ? lane : 0;      // entries 64.. (at most 8)
+    const int32_t xhi = staged_word(r0, r1, r2, 16 + 2 * (64 + hl));
+    const int32_t whi = staged_word(r0, r1, r2, 17 + 2 * (64 + hl));
+    const bool mem = lane < nm;
+    const uint64_t pw = mem ? P[u] : 0ull, ow = mem ? O[u] : 0ull;
+    const bool olo = lane < nd && xlo >= 0, ohi = 64 + lane < nd && xhi >= 0;
+    const uint64_t flo = olo ? O[(uint32_t)xlo & kSmallIdx] : 0ull;
+    const uint64_t fhi = ohi ? O[(uint32_t)xhi & kSmallIdx] : 0ull;
+    PairOut out{0u, false, 0};
+    uint32_t om = 0;
+    uint64_t D = 0;
+    for (int k = 0; k < nm; ++k) {
+        const uint32_t ok = bit_of(lane_u64(ow, k), i);
+        om |= ok << k;
+        D |= lane_u64(pw, k) ^ (0ull - (uint64_t)ok);
+    }
+    D &= cand;
+    out.cnt = (uint32_t)__popcll(D);
+    const uint32_t d = out.cnt ? select_bit(D, (h * out.cnt) >> 16) : 0u;
+    uint32_t cm = 0;
+    for (int k = 0; k < nm; ++k) cm |= (bit_of(lane_u64(pw, k), d) ^ ((om >> k) & 1u)) << k;
+    int64_t delta = 0;
+    for (int e = 0; e < nd; ++e) {
+        const bool hi = e >= 64;
+        const int l = e & 63;
+        const int32_t x = lane_i32(hi ? xhi : xlo, l);
+        const int32_t w = lane_i32(hi ? whi : wlo, l);
+        const uint32_t a = ((uint32_t)x >> kSmallPosShift) & 15u;
+        const uint32_t y = (uint32_t)x & kSmallIdx;
+        const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
+        uint32_t ov, flip;
+        if (x < 0) {  // inside edge to member y (wave-uniform branch)
+            ov = (om >> y) & 1u;
+            flip = ca ^ ((cm >> y) & 1u);
+        } else {
+            ov = bit_of(lane_u64(hi ? fhi : flo, l), i);
+            flip = ca;
+        }
+        delta += flip ? signed_w(oa == ov, w) : 0;
+    }
+    out.delta = delta;
+    out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
+    // commit: each changed member's new word, stored by the lane that loaded it
+    for (int k = 0; k < nm; ++k) {
+        const uint64_t fm = ballot64(out.acc && ((cm >> k) & 1u));
+        if (fm && lane == k) O[u] = ow ^ fm;
+    }
+    return out;
+}
+
+// One colour class of small general sets with the staged evaluation (staged_pair): lane =
+// solution, one set per wave at a time; PPW consecutive positions per wave tile (8: one Philox
+// call for all of them, for classes large enough that every wave strides over eight
+// positions anyway).  Forced improvement keeps the other sweep.
+template <int PPW>
+__global__ __launch_bounds__(kSweepMaxThreads) void k_class_sweep_staged(SweepArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t i = (uint32_t)lane;
+    const int wpb = (int)(blockDim.x >> 6);
+    const int gw = xcd_tile((int)blockIdx.x, (int)gridDim.x) * wpb + (int)(threadIdx.x >> 6);
+    const int nwaves = gridDim.x * wpb;
+    const uint64_t mism = a.stripes[lane].mism;
+    const bool live = a.st->elite_fitness < a.target;
+    const bool act = (int)i < a.N;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
+    const bool neutral_ok = (a.always != 0) | (bit_of(wave_or64(mism), i) != 0);
+    int64_t facc = 0;
+    uint32_t n_eval = 0, n_acc = 0;
+    bool flag = false;
+    const int nwt = (a.csize + PPW - 1) / PPW;
+    for (int wt = gw; live && wt < nwt; wt += nwaves) {
+        const int p0 = __builtin_amdgcn_readfirstlane(wt * PPW);
+        U32x4 q = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i, (uint32_t)(p0 >> 3));
+#pragma unroll 1
+        for (int f = 0; f < PPW; ++f) {
+            const int p = p0 + f;
+            if (p >= a.csize) break;
+            if (PPW == 1 && f > 0)
+                q = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls, i, (uint32_t)(p >> 3));
+            const int32_t *rec = a.rstride ? a.recs + a.rbase + p * a.rstride
+                                           : a.recs + a.roff[a.cbase + p];
+            const int fl = p & 7;
+            const uint32_t w = (fl >> 1) == 0 ? q.x : (fl >> 1) == 1 ? q.y
+                             : (fl >> 1) == 2 ? q.z : q.w;
+            const uint32_t h = (w >> (16 * (fl & 1))) & 0xFFFFu;
+            const PairOut r = staged_pair(rec, a.P, a.O, i, cand, h, neutral_ok);
+            facc += r.acc ? r.delta : 0;
+            flag |= r.acc;
+            n_eval += (uint32_t)__popcll(ballot64(r.cnt > 0));
+            n_acc += (uint32_t)__popcll(ballot64(r.acc));
+        }
+    }
+    Stripe *sp = a.stripes + (gw % kStripes);
+    if (act && facc) atomicAdd((unsigned long long *)&sp->fit[i], (unsigned long long)facc);
+    const uint64_t fm = a.mode == kSweepGomTrack ? ballot64(flag && act) : 0ull;
+    if (lane == 0) {
+        if (n_eval) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)n_eval);
+        if (n_acc) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)n_acc);
+        if (fm) atomicOr((unsigned long long *)&sp->acc, (unsigned long long)fm);
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Block-cooperative sweep of one large set (general record layout) for every solution at
 // once: block = set, lane = solution, the block's waves split the set's members.
@@ -1868,7 +2011,8 @@ __global__ __launch_bounds__(256) void k_bcl_order(const BclInst *insts, uint16_
 // (none past its class count or once its target is reached), and their exclusive prefix sums
 // over the instances; the total follows the last instance.
 __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const uint16_t *order,
-                                                   int32_t *tiles, int count, int kmax) {
+                                                   int32_t *tiles, int count, int kmax,
+                                                   int tile) {
     __shared__ int32_t part[256];
     const int t = blockIdx.x;
     int32_t *row = tiles + (size_t)t * (count + 1);
@@ -1881,7 +2025,7 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
             if (t < I.k && I.st->elite_fitness < I.target) {
                 const int c = order[(size_t)i * kmax + t];
                 const int32_t cs = I.class_ptr[c + 1] - I.class_ptr[c];
-                n = (cs + kBclTile - 1) / kBclTile;
+                n = (cs + tile - 1) / tile;
             }
         }
         part[threadIdx.x] = n;
@@ -1900,104 +2044,14 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
     if (threadIdx.x == 0) row[count] = base;
 }
 
-// The sweep of position t: blocks stride over the position's tiles; a tile is kBclTile
-// consecutive class positions of one instance, wave w of the block takes kBclPositions of
-// them, lane = solution (as the class-launch sweep with groups of 64: the record is wave-
-// uniform, one Philox call serves the wave's positions).  Fitness changes and counts go to
-// the instance's stripe of the tile, after each tile.
-// Wave-uniform broadcast of lane l's 32- and 64-bit values (l wave-uniform).
-__device__ __forceinline__ int32_t lane_i32(int32_t v, int l) {
-    return __builtin_amdgcn_readlane(v, l);
-}
-__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-}
-// Word idx (< 192) of a record staged as three registers of 64 words (lane l of rK holds word
-// 64 K + l), fetched by every lane for its own idx.
-__device__ __forceinline__ int32_t staged_word(int32_t r0, int32_t r1, int32_t r2, int idx) {
-    const int src = (idx & 63) << 2;  // ds_bpermute addresses bytes
-    const int32_t a = __builtin_amdgcn_ds_bpermute(src, r0);
-    const int32_t b = __builtin_amdgcn_ds_bpermute(src, r1);
-    const int32_t c = __builtin_amdgcn_ds_bpermute(src, r2);
-    return idx < 64 ? a : (idx < 128 ? b : c);
-}
-
-// GOM step of every solution of the wave (lane i = solution i) on one small set (at most
-// kBclMaxMembers members, kBclMaxEntries dependent edges), with the set's data staged by the
-// wave in two rounds of loads instead of one round per batch of entries:
-//   1. the record's first 192 words, three coalesced loads per lane (the record buffer keeps
-//      a zero tail of that length, so a load past the last record stays inside it);
-//   2. lane k < nm loads member k's P and O words, lane e < nd (and e + 64) the O word at
-//      the far end of dependent edge e when that end lies outside the set;
-// then every lane reads members, entries and words with lane reads (wave-uniform values)
-// and decides its own step exactly as the other sweeps do: donors D, the draw's r-th donor,
-// the changed members C, delta over the dependent edges, acceptance, and a masked store of
-// each changed member's word.
-__device__ __forceinline__ PairOut staged_pair(const int32_t *rec, const uint64_t *P, uint64_t *O,
-                                               uint32_t i, uint64_t cand, uint32_t h,
-                                               bool neutral_ok) {
-    const int lane = (int)(threadIdx.x & 63);
-    const int32_t r0 = rec[lane], r1 = rec[64 + lane], r2 = rec[128 + lane];
-    const int nm = __builtin_amdgcn_readfirstlane(r0);        // word 0
-    const int nd = __builtin_amdgcn_readlane(r0, 1);           // word 1
-    // round 2: member words (lanes < nm) and far-end words (lanes < nd, and lane + 64 < nd)
-    const int u = staged_word(r0, r1, r2, 2 + (lane < kBclMaxMembers ? lane : 0));
-    const int32_t xlo = staged_word(r0, r1, r2, 16 + 2 * lane);
-    const int32_t wlo = staged_word(r0, r1, r2, 17 + 2 * lane);
-    const int hl = lane < kBclMaxEntries - 64 ? lane : 0;      // entries 64.. (at most 8)
-    const int32_t xhi = staged_word(r0, r1, r2, 16 + 2 * (64 + hl));
-    const int32_t whi = staged_word(r0, r1, r2, 17 + 2 * (64 + hl));
-    const bool mem = lane < nm;
-    const uint64_t pw = mem ? P[u] : 0ull, ow = mem ? O[u] : 0ull;
-    const bool olo = lane < nd && xlo >= 0, ohi = 64 + lane < nd && xhi >= 0;
-    const uint64_t flo = olo ? O[(uint32_t)xlo & kSmallIdx] : 0ull;
-    const uint64_t fhi = ohi ? O[(uint32_t)xhi & kSmallIdx] : 0ull;
-    PairOut out{0u, false, 0};
-    uint32_t om = 0;
-    uint64_t D = 0;
-    for (int k = 0; k < nm; ++k) {
-        const uint32_t ok = bit_of(lane_u64(ow, k), i);
-        om |= ok << k;
-        D |= lane_u64(pw, k) ^ (0ull - (uint64_t)ok);
-    }
-    D &= cand;
-    out.cnt = (uint32_t)__popcll(D);
-    const uint32_t d = out.cnt ? select_bit(D, (h * out.cnt) >> 16) : 0u;
-    uint32_t cm = 0;
-    for (int k = 0; k < nm; ++k) cm |= (bit_of(lane_u64(pw, k), d) ^ ((om >> k) & 1u)) << k;
-    int64_t delta = 0;
-    for (int e = 0; e < nd; ++e) {
-        const bool hi = e >= 64;
-        const int l = e & 63;
-        const int32_t x = lane_i32(hi ? xhi : xlo, l);
-        const int32_t w = lane_i32(hi ? whi : wlo, l);
-        const uint32_t a = ((uint32_t)x >> kSmallPosShift) & 15u;
-        const uint32_t y = (uint32_t)x & kSmallIdx;
-        const uint32_t oa = (om >> a) & 1u, ca = (cm >> a) & 1u;
-        uint32_t ov, flip;
-        if (x < 0) {  // inside edge to member y (wave-uniform branch)
-            ov = (om >> y) & 1u;
-            flip = ca ^ ((cm >> y) & 1u);
-        } else {
-            ov = bit_of(lane_u64(hi ? fhi : flo, l), i);
-            flip = ca;
-        }
-        delta += flip ? signed_w(oa == ov, w) : 0;
-    }
-    out.delta = delta;
-    out.acc = out.cnt > 0 && (delta > 0 || (delta == 0 && neutral_ok));
-    // commit: each changed member's new word, stored by the lane that loaded it
-    for (int k = 0; k < nm; ++k) {
-        const uint64_t fm = ballot64(out.acc && ((cm >> k) & 1u));
-        if (fm && lane == k) O[u] = ow ^ fm;
-    }
-    return out;
-}
-
+// The sweep of position t: blocks stride over the position's tiles; a tile is kBclWaves x ppw
+// consecutive class positions of one instance, wave w of the block takes ppw of them, lane =
+// solution (as the class-launch sweep with groups of 64: the record is wave-uniform, one
+// Philox call serves up to eight consecutive positions).  Fitness changes and counts go to the
+// instance's stripe of the tile, after each tile.
 constexpr int kBclRowLds = 1024;  // instances whose tile offsets a block keeps in LDS
 
-// (about 145 VGPRs: three waves per SIMD; capping it at 128 for four spilled to scratch)
+// (about 60 VGPRs with the staged pair evaluation: eight waves per SIMD)
 __global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
     __shared__ int32_t srow[kBclRowLds + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -2024,8 +2078,8 @@ __global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
         const int cbase = I.class_ptr[c];
         const int csize = I.class_ptr[c + 1] - cbase;
         const int2 cr = I.class_rec[c];
-        const int p0 = __builtin_amdgcn_readfirstlane((tile - rs[b]) * kBclTile +
-                                                      wave * kBclPositions);
+        const int p0 = __builtin_amdgcn_readfirstlane((tile - rs[b]) * kBclWaves * pl.ppw +
+                                                      wave * pl.ppw);
         if (p0 >= csize) continue;
         const uint64_t mism = I.stripes[lane].mism;
         const bool act = (int)i < I.N;
@@ -2033,13 +2087,16 @@ __global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
         const uint64_t cand = act ? (popm & ~(1ull << i)) : 0ull;
         const bool neutral_ok = (I.always != 0) | (bit_of(wave_or64(mism), i) != 0);
         const int gen = I.st->generation;
-        const U32x4 q = philox(I.seed, (uint32_t)gen, (uint32_t)c, i, (uint32_t)(p0 >> 3));
+        U32x4 q{0u, 0u, 0u, 0u};
         int64_t facc = 0;
         uint32_t n_eval = 0, n_acc = 0;
 #pragma unroll 1
-        for (int f = 0; f < kBclPositions; ++f) {
+        for (int f = 0; f < pl.ppw; ++f) {
             const int p = p0 + f;
             if (p >= csize) break;
+            // one call per eight positions (counter word 3 = p / 8)
+            if (f == 0 || (p & 7) == 0)
+                q = philox(I.seed, (uint32_t)gen, (uint32_t)c, i, (uint32_t)(p >> 3));
             const int32_t *rec = cr.y ? I.recs + cr.x + p * cr.y : I.recs + I.roff[cbase + p];
             const int fl = p & 7;  // (wave-uniform) field of the call
             const uint32_t w = (fl >> 1) == 0 ? q.x : (fl >> 1) == 1 ? q.y
@@ -2193,6 +2250,21 @@ hipError_t static_arena_address(void **ptr) {
     }
     *ptr = addr[dev];
     return hipSuccess;
+}
+
+hipError_t launch_class_sweep_staged(const SweepArgs &a, int max_grid, int threads,
+                                     hipStream_t s, KernelEvents ev) {
+    if (threads < 64 || threads > kSweepMaxThreads || threads % 64) return hipErrorInvalidValue;
+    const int wpb = threads / 64;
+    const int64_t slots = (int64_t)max_grid * wpb;
+    const bool shared = (int64_t)a.csize >= 8 * slots;
+    const int per = shared ? 8 : 1;
+    int grid = (int)std::min<int64_t>(max_grid, (a.csize + (int64_t)per * wpb - 1) /
+                                                    ((int64_t)per * wpb));
+    if (grid < 1) return hipSuccess;
+    if (shared) launch_timed(k_class_sweep_staged<8>, dim3(grid), dim3(threads), 0, s, ev, a);
+    else launch_timed(k_class_sweep_staged<1>, dim3(grid), dim3(threads), 0, s, ev, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_class_sweep(const SweepArgs &a, int kind, bool short_records, int max_grid,
@@ -2429,8 +2501,9 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
                            bcl.kmax);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (bcl.ppw < 1 || bcl.ppw > kBclPositions) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_bcl_tiles, dim3(bcl.kmax), dim3(256), 0, s, bcl.insts, bcl.order,
-                           bcl.tiles, bcl.count, bcl.kmax);
+                           bcl.tiles, bcl.count, bcl.kmax, kBclWaves * bcl.ppw);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         for (int t = 0; t < bcl.kmax; ++t) {

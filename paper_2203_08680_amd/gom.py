@@ -30,7 +30,7 @@ EXPORTED = (
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
     "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_state_set_fused",
-    "gom_state_get_fused", "gom_state_set_grid_limit", "gom_local_search",
+    "gom_state_get_fused", "gom_state_set_grid_limit", "gom_state_set_staged", "gom_local_search",
     "gom_iterated_local_search",
     "gom_ims_bytes",
     "gom_ims_run",
@@ -38,6 +38,7 @@ EXPORTED = (
     "gom_batch_set_graph", "gom_batch_reseed", "gom_batch_timing_enable",
     "gom_batch_timing_read", "gom_batch_set_narrow", "gom_batch_get_narrow",
     "gom_batch_autotune", "gom_batch_set_class_launch", "gom_batch_get_class_launch",
+    "gom_batch_set_class_positions",
     "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
     "gom_server_set_large",
@@ -126,6 +127,7 @@ def lib() -> C.CDLL:
         "gom_state_get_block": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_set_fused": (C.c_int, [_vp, C.c_int]),
         "gom_state_set_grid_limit": (C.c_int, [_vp, _i32]),
+        "gom_state_set_staged": (C.c_int, [_vp, C.c_int]),
         "gom_state_get_fused": (C.c_int, [_vp, _P(C.c_int), _P(C.c_int)]),
         "gom_state_get_fi": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_debug_stop_after_class": (C.c_int, [_vp, _i32, _vp]),
@@ -146,7 +148,8 @@ def lib() -> C.CDLL:
         "gom_batch_get_narrow": (C.c_int, [_vp, _P(_i64), _P(_i32)]),
         "gom_batch_autotune": (C.c_int, [_vp, _i32, _vp, _P(_i64), _P(_i64)]),
         "gom_batch_set_class_launch": (C.c_int, [_vp, _i64, _vp]),
-        "gom_batch_get_class_launch": (C.c_int, [_vp, _P(_i64), _P(_i32), _P(_i32)]),
+        "gom_batch_get_class_launch": (C.c_int, [_vp, _P(_i64), _P(_i32), _P(_i32), _P(_i32)]),
+        "gom_batch_set_class_positions": (C.c_int, [_vp, _i32]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
@@ -494,6 +497,11 @@ def gom_state_set_grid_limit(s: GomState, blocks: int) -> None:
     _check(lib().gom_state_set_grid_limit(s.handle, int(blocks)))
 
 
+def gom_state_set_staged(s: GomState, enabled: bool) -> None:
+    """Staged evaluation of small general sets in the class sweeps (results identical)."""
+    _check(lib().gom_state_set_staged(s.handle, 1 if enabled else 0))
+
+
 def gom_state_set_block(s: GomState, threads: int) -> None:
     """Block size of the class-launch sweeps (64..512, a multiple of 64)."""
     _check(lib().gom_state_set_block(s.handle, int(threads)))
@@ -675,10 +683,16 @@ def gom_batch_set_class_launch(b: GomBatch, min_n: int, stream=None) -> None:
 
 
 def gom_batch_get_class_launch(b: GomBatch):
-    """(threshold, instances selected, class launches per step)."""
-    m, n, k = _i64(), _i32(), _i32()
-    _check(lib().gom_batch_get_class_launch(b.handle, C.byref(m), C.byref(n), C.byref(k)))
-    return m.value, n.value, k.value
+    """(threshold, instances selected, class launches per step, positions per wave)."""
+    m, n, k, w = _i64(), _i32(), _i32(), _i32()
+    _check(lib().gom_batch_get_class_launch(b.handle, C.byref(m), C.byref(n), C.byref(k),
+                                            C.byref(w)))
+    return m.value, n.value, k.value, w.value
+
+
+def gom_batch_set_class_positions(b: GomBatch, positions_per_wave: int) -> None:
+    """Consecutive class positions per wave of the class launches (1..8)."""
+    _check(lib().gom_batch_set_class_positions(b.handle, int(positions_per_wave)))
 
 
 def gom_batch_set_graph(b: GomBatch, enabled: bool = True) -> None:

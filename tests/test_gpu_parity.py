@@ -171,14 +171,16 @@ def test_block_cooperative_large_sets(cuda, sched, pop, fi):
     lockstep(st, ref, 4, f"large sets pop {pop}")
 
 
-@pytest.mark.parametrize("pop", [64, 24, 12])
-def test_class_sweep_shared_draws(cuda, pop):
+@pytest.mark.parametrize("pop,staged", [(64, True), (64, False), (24, True), (12, True)])
+def test_class_sweep_shared_draws(cuda, pop, staged):
     """With a small grid cap every group of the per-class sweep strides over many positions,
     so the neighbourhood sweep takes its form that draws one Philox call per eight positions
-    (groups of 64, 32 and 16 lanes); the trajectory equals the oracle's."""
-    print(f"case shared draws pop={pop}", flush=True)
+    (groups of 64, 32 and 16 lanes; population 64 also staged); the trajectory equals the
+    oracle's."""
+    print(f"case shared draws pop={pop} staged={staged}", flush=True)
     g = workloads.configuration_model(3000, 5, seed=18)
     _, st, ref = make_pair(g, 1, pop, seed=3, sched=gom.GOM_SCHED_CLASS_LAUNCH)
+    gom.gom_state_set_staged(st, staged)
     gom.gom_state_set_grid_limit(st, 3)
     lockstep(st, ref, 5, f"shared draws pop={pop}")
 
@@ -1046,13 +1048,16 @@ def test_batch_class_launches(cuda, graph):
     bt = gom.gom_batch_init(insts, pops, seeds, targets)
     gom.gom_batch_set_graph(bt, graph)
     gom.gom_batch_set_class_launch(bt, 0)
-    m, n_inst, launches = gom.gom_batch_get_class_launch(bt)
+    m, n_inst, launches, _ = gom.gom_batch_get_class_launch(bt)
     assert m == 0 and n_inst == 5 and launches >= 1
+    gom.gom_batch_set_class_positions(bt, 8)
     gom.gom_batch_run(bt, 5)
     gom.gom_batch_set_class_launch(bt, 1000)   # the two largest only
+    gom.gom_batch_set_class_positions(bt, 1)
     assert gom.gom_batch_get_class_launch(bt)[1] == 2
     gom.gom_batch_run(bt, 9)
     gom.gom_batch_set_class_launch(bt, 0)
+    gom.gom_batch_set_class_positions(bt, 3)
     res, _ = gom.gom_batch_run(bt, 15)
     for b in range(len(gs)):
         st = insts[b].state(pop=pops[b], seed=seeds[b])

@@ -35,13 +35,16 @@ def assert_same(a, b, where):
 
 
 def _states(inst, pop, seed, scheds):
+    """One state per (schedule, block size[, staged evaluation])."""
     out = []
-    for sched, block in scheds:
+    for sched, block, *rest in scheds:
         st = inst.state(pop=pop, seed=seed)
         gom.gom_state_set_schedule(st, sched)
         if block:
             gom.gom_state_set_block(st, block)
-        out.append((f"sched {sched} block {block}", st))
+        if rest:
+            gom.gom_state_set_staged(st, rest[0])
+        out.append((f"sched {sched} block {block} {rest}", st))
     return out
 
 
@@ -79,11 +82,12 @@ def _trajectory(label, g, kind, pop, seed, gens, scheds, full_every, target=None
 
 def test_c2_full_trajectory():
     """100x100 torus, neighbourhood FOS, population 64, seed 1: the whole 500-generation run
-    of the benchmark workload, under the class-launch schedule with 64-thread blocks (the
-    benchmark's tuned choice), 256-thread blocks and the resident schedule."""
+    of the plain single-instance workload, under the class-launch schedule with 64-thread
+    blocks, 256-thread blocks, 64-thread blocks with the staged evaluation, and the resident
+    schedule."""
     g = workloads.torus(100, 1, 100, seed=2)
     scheds = [(gom.GOM_SCHED_CLASS_LAUNCH, 64), (gom.GOM_SCHED_CLASS_LAUNCH, 256),
-              (gom.GOM_SCHED_RESIDENT, 0)]
+              (gom.GOM_SCHED_CLASS_LAUNCH, 64, True), (gom.GOM_SCHED_RESIDENT, 0)]
     _trajectory("torus100 nbhd p64 seed 1", g, 1, 64, 1, 500, scheds, 50,
                 target=g.total_weight)
 
@@ -135,7 +139,8 @@ def test_torus1000_univariate_5_generations():
 
 
 def test_torus1000_neighbourhood_2_generations():
-    """The 10^6-vertex torus, neighbourhood FOS, population 64, class launch: two
-    generations."""
+    """The 10^6-vertex torus, neighbourhood FOS, population 64, class launch (staged
+    evaluation with shared draws, and the batched-entries form): two generations."""
     g = workloads.torus(1000, 1, 100, seed=7)
-    _trajectory("torus1000 nbhd p64", g, 1, 64, 1, 2, [(gom.GOM_SCHED_CLASS_LAUNCH, 0)], 2)
+    _trajectory("torus1000 nbhd p64", g, 1, 64, 1, 2,
+                [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_CLASS_LAUNCH, 0, True)], 2)
