@@ -644,9 +644,12 @@ def main():
     ap.add_argument("--staged", action="store_true",
                     help="plain mode: class sweeps of small general sets take the staged "
                          "evaluation (two rounds of loads per set)")
-    ap.add_argument("--no-fused", action="store_true",
-                    help="bit-sliced schedule: one launch per class instead of the fused "
-                         "generation sweep")
+    ap.add_argument("--fused", action="store_true",
+                    help="bit-sliced schedule: the fused generation sweep (one cooperative "
+                         "launch per generation) instead of one launch per class")
+    ap.add_argument("--bitsliced-min-sets", type=int, default=None,
+                    help="plain mode, general FOS: smallest class the bit-sliced schedule "
+                         "sweeps with the general bit-sliced sweep (library default 8192)")
     ap.add_argument("--block", type=int, default=0,
                     help="class-launch block size (with --schedule class; 0 = default)")
     ap.add_argument("--fi", action="store_true",
@@ -700,6 +703,8 @@ def main():
     st = inst.state(pop=wl.pop, seed=1000)
     if args.fi:
         gom.gom_state_set_fi(st, True)
+    if args.bitsliced_min_sets is not None:
+        gom.gom_state_set_bitsliced_min_sets(st, args.bitsliced_min_sets)
     if args.schedule == "tuned":
         gom.gom_state_autotune(st, 10)
     else:
@@ -709,8 +714,8 @@ def main():
                                         "bitsliced": gom.GOM_SCHED_BITSLICED}[args.schedule])
     if args.block:
         gom.gom_state_set_block(st, args.block)
-    if args.no_fused and gom.gom_state_get_fused(st)[1]:
-        gom.gom_state_set_fused(st, False)
+    if args.fused and gom.gom_state_get_fused(st)[1]:
+        gom.gom_state_set_fused(st, True)
     if args.staged:
         gom.gom_state_set_staged(st, True)
     sched = gom.gom_state_get_schedule(st)
@@ -796,7 +801,9 @@ def main():
         avg_bytes = float(cbytes.sum() if whole else cbytes.mean())
         avg_s = sweep_ms / 1e3 / launches
         achieved = avg_bytes / avg_s / 1e9
-        kname = {"resident": "k_resident_sweep", "bitsliced": "k_uni_swar_sweep",
+        kname = {"resident": "k_resident_sweep",
+                 "bitsliced": "k_uni_swar_sweep" if wl.fos == 0 else
+                              "k_gen_swar_sweep + k_class_sweep",
                  "bitsliced_fused": "k_uni_swar_fused"}.get(sched_name, "k_class_sweep")
         meas = MEASURED_TRAFFIC.get((kname, args.workload))
         traffic = meas["bytes"] if meas and meas["source"] == kernel_source_hash() else None

@@ -327,12 +327,18 @@ int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launche
  *                           offspring in LDS and running all classes with barriers between
  *                           them; needs n bytes of LDS per workgroup and at most
  *                           GOM_RESIDENT_MAX_CLASSES classes
- *   GOM_SCHED_BITSLICED     one launch per colour class, lane = set, every solution of the
- *                           set processed at once with 64-bit bitwise operations; needs a
- *                           univariate FOS, maximum degree <= 4 and per-vertex sums of |w|
- *                           below 2^30
- *   GOM_SCHED_AUTO          resident when it fits the device, else bit-sliced when the
- *                           instance qualifies, else class launch
+ *   GOM_SCHED_BITSLICED     one launch per colour class, lane = set, the solutions of the
+ *                           set as the bits of machine words.  Univariate FOS: every class,
+ *                           all solutions at once with 64-bit bitwise operations; needs
+ *                           maximum degree <= 4 and per-vertex sums of |w| below 2^30.
+ *                           General FOS (population <= 64): the classes whose sets have at
+ *                           most 9 members, per-set sums of |w| over their dependent edges of
+ *                           at most 16383 and at least gom_state_set_bitsliced_min_sets sets
+ *                           (default 8192): per solution the donor draw and the changed
+ *                           members, then the fitness changes of 32 solutions at once as a
+ *                           bit-sliced sum; the other classes as under class launch
+ *   GOM_SCHED_AUTO          resident when it fits the device, else bit-sliced when a
+ *                           univariate instance qualifies, else class launch
  * GOM_E_RANGE when the requested schedule does not fit this instance or device.
  */
 enum { GOM_SCHED_AUTO = 0, GOM_SCHED_CLASS_LAUNCH = 1, GOM_SCHED_RESIDENT = 2,
@@ -363,8 +369,10 @@ int gom_state_get_fi(const gom_state *s, int *enabled);
  * launch, each block waiting only for the chunks of earlier classes whose sets conflict with
  * its own (same variable or an edge between them; Sec. 5.2's independence of the sets of a
  * colour class).  Available when the bit-sliced schedule is, there are at most 8 classes and
- * every dependency range spans at most 32 chunks (tori, not random graphs); used by default
- * then.  Results are identical either way.  Its blocks wait for each other, so they must all
+ * every dependency range spans at most 32 chunks (tori, not random graphs); off by default:
+ * each block's device-scope release and acquire write back and invalidate its L2, which on
+ * the 10^6- and 10^7-vertex tori cost more than the per-class launches save (220 against 37
+ * and 520 against 232 us per generation).  Results are identical either way.  Its blocks wait for each other, so they must all
  * be on the device at once: the launch is cooperative, and states that generate on several
  * streams at the same time should turn it off (the serving loop does for its jobs).  A
  * dependency wait that never ends gives up after a bounded number of polls; the next read of
@@ -378,6 +386,14 @@ int gom_state_set_fused(gom_state *s, int enabled);
  * results do not depend on it.  Errors: GOM_E_ARG, GOM_E_RANGE (outside 1..65536).
  */
 int gom_state_set_grid_limit(gom_state *s, int32_t blocks);
+/*
+ * Smallest class (sets) that the bit-sliced schedule sweeps with the general bit-sliced
+ * sweep (general FOS; default 8192: one set per lane leaves a smaller class too few waves).
+ * Results do not depend on it.  A state under the bit-sliced schedule that no class
+ * qualifies for any more falls back to GOM_SCHED_AUTO's choice.
+ * Errors: GOM_E_ARG, GOM_E_RANGE (negative).
+ */
+int gom_state_set_bitsliced_min_sets(gom_state *s, int32_t sets);
 /*
  * Class sweeps of small general sets (at most 9 members and 72 dependent edges; population
  * above 32) stage each set in two rounds of loads by its wave (record, then member and

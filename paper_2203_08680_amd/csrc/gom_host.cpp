@@ -131,6 +131,8 @@ struct Records {
     std::vector<int2> class_rec;        // per class {first word, stride or 0}
     std::vector<int32_t> class_entries;  // per class: most dependent-edge entries of a record
     std::vector<int32_t> class_members;  // per class: most members of a set
+    std::vector<int64_t> class_wsum;     // per class: largest sum of |w| over a set's entries
+    std::vector<int64_t> class_wmax;     // per class: largest |w| of an entry
 };
 
 constexpr int kSmallSet = 14;         // members held in a small record's header
@@ -328,6 +330,8 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
     R.class_rec.assign((size_t)f.k, make_int2(0, 0));
     R.class_entries.assign((size_t)f.k, 0);
     R.class_members.assign((size_t)f.k, 1);
+    R.class_wsum.assign((size_t)f.k, 0);
+    R.class_wmax.assign((size_t)f.k, 0);
     int32_t s = 0;
     for (int32_t c = 0; c < f.k; ++c) {
         const size_t class_first = R.words.size();
@@ -380,6 +384,13 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
             const int32_t nd = (int32_t)ent.size();
             R.class_entries[c] = std::max(R.class_entries[c], nd);
             R.class_members[c] = std::max(R.class_members[c], nm);
+            int64_t wsum = 0;
+            for (const auto &xw : ent) {
+                const int64_t aw = std::llabs((long long)xw.second);
+                wsum += aw;
+                R.class_wmax[c] = std::max(R.class_wmax[c], aw);
+            }
+            R.class_wsum[c] = std::max(R.class_wsum[c], wsum);
             R.words.push_back(nm);
             R.words.push_back(nd);
             if (small) {
@@ -437,7 +448,7 @@ struct gom_state {
     int static_dev = -1;                // device whose static arena holds the state, or -1
     bool h_st_pinned = true;            // h_st from hipHostMalloc (else new[])
     bool fused_ok = false;              // the fused bit-sliced sweep can run this state
-    bool fused_use = true;              // ... and is used for whole generations
+    bool fused_use = false;             // ... and is used for whole generations
     bool fused_narrow = false;          // its per-block fitness sums fit in int32
     int fused_grid = 0;
     std::vector<int32_t> fused_clen;    // chunk length per class
@@ -472,6 +483,11 @@ struct gom_state {
     std::vector<int2> class_rec;  // host copy of the per-class record placement
     std::vector<int32_t> class_entries;  // per class: most entries of one of its records
     std::vector<int32_t> class_members;  // per class: most members of one of its sets
+    std::vector<int8_t> gs_wbits;        // per class: bits of its largest |w| when the general
+                                         // bit-sliced sweep takes it, else 0
+    std::vector<int64_t> class_wsum, class_wmax;  // per class (see Records)
+    int32_t gs_min_sets = kGsMinSets;    // smallest class the general bit-sliced sweep takes
+    bool swar_uni = false;               // the univariate bit-sliced sweep fits the instance
     bool staged_use = false;            // per-class sweeps of small general sets staged
     std::vector<int32_t> coop_ptr, coop_max;  // large sets per class (block-cooperative)
     int32_t *d_coop = nullptr;                // their class positions
@@ -1060,6 +1076,27 @@ static bool nl_coop_free(const gom_state *s, int32_t c) {
     return s->coop_ptr[2 * (size_t)c + 2] == s->coop_ptr[2 * (size_t)c] && !s->split[(size_t)c];
 }
 
+// Classes the general bit-sliced sweep takes (general FOS, population <= 64): sets of at most
+// kGsMaxMembers members, per-set sums of |w| within kGsMaxWeightSum, |w| within
+// kGsMaxWeightBits bits, no set left to a block-cooperative sweep, at least gs_min_sets sets.
+// Records the largest |w|'s bit count per class (0: not taken); true when some class is taken.
+static bool gs_select(gom_state *s) {
+    s->gs_wbits.assign((size_t)s->k, 0);
+    if (s->univariate || s->N > 64) return false;
+    bool any = false;
+    for (int32_t c = 0; c < s->k; ++c) {
+        int bits = 1;
+        while (bits < 62 && (s->class_wmax[c] >> bits) != 0) ++bits;
+        const bool ok = s->class_members[c] <= kGsMaxMembers &&
+                        s->class_wsum[c] <= kGsMaxWeightSum && bits <= kGsMaxWeightBits &&
+                        nl_coop_free(s, c) &&
+                        s->class_ptr[(size_t)c + 1] - s->class_ptr[c] >= s->gs_min_sets;
+        s->gs_wbits[c] = ok ? (int8_t)bits : 0;
+        any |= ok;
+    }
+    return any;
+}
+
 // The generation-wide fields of a class sweep's arguments.
 static SweepArgs sweep_args(const gom_state *s, int32_t gen, int64_t target, bool forced) {
     SweepArgs a{};
@@ -1136,8 +1173,11 @@ static int enqueue_class_range(gom_state *s, const std::vector<int32_t> &perm, i
         const bool staged = s->staged_use && !forced && !s->univariate && s->N > 32 &&
                             s->class_members[c] <= kBclMaxMembers &&
                             s->class_entries[c] <= kBclMaxEntries && nl_coop_free(s, c);
-        if (s->sched == GOM_SCHED_BITSLICED && !forced)
+        if (s->sched == GOM_SCHED_BITSLICED && !forced && s->univariate)
             HIP_TRY(launch_uni_swar_sweep(a, s->partition, s->swar_narrow, s->max_grid, st, ev));
+        else if (s->sched == GOM_SCHED_BITSLICED && !forced && s->gs_wbits[c])
+            HIP_TRY(launch_gen_swar_sweep(a, s->class_members[c], s->gs_wbits[c], s->max_grid,
+                                          st, ev));
         else if (staged)
             HIP_TRY(launch_class_sweep_staged(a, s->max_grid, s->sweep_threads, st, ev));
         else
@@ -1231,7 +1271,7 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
 
 static int auto_schedule(const gom_state *s) {
     if (s->resident_ok) return GOM_SCHED_RESIDENT;
-    if (s->bitsliced_ok && !s->fi) return GOM_SCHED_BITSLICED;
+    if (s->swar_uni && !s->fi) return GOM_SCHED_BITSLICED;
     return GOM_SCHED_CLASS_LAUNCH;
 }
 
@@ -1308,6 +1348,8 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
     s->class_rec = R.class_rec;
     s->class_entries = R.class_entries;
     s->class_members = R.class_members;
+    s->class_wsum = R.class_wsum;
+    s->class_wmax = R.class_wmax;
     s->coop_ptr = CS.ptr;
     s->coop_max = CS.max_members;
     s->d_coop = (int32_t *)(s->arena + L.coop);
@@ -1351,7 +1393,8 @@ static int state_init(const mc_graph *g, const gom_fos *f, int32_t pop, uint64_t
         s->resident_ok = e == hipSuccess && s->k <= kResidentMaxClasses &&
                          resident_lds_bytes(s->n, false) <= s->lds_max;
         s->resident_plds = s->resident_ok && resident_lds_bytes(s->n, true) <= s->lds_max;
-        s->bitsliced_ok = swar;
+        s->swar_uni = swar;
+        s->bitsliced_ok = swar || gs_select(s);
         s->swar_abs = swar_abs;
         s->swar_narrow = swar && swar_narrow_ok(s);
         s->partition = s->univariate && f->n_sets == g->n;
@@ -1982,7 +2025,16 @@ extern "C" int gom_state_set_grid_limit(gom_state *s, int32_t blocks) {
     if (blocks < 1 || blocks > 65536)
         return fail(GOM_E_RANGE, "gom_state_set_grid_limit: %d blocks (1..65536)", blocks);
     s->max_grid = blocks;
-    s->swar_narrow = s->bitsliced_ok && swar_narrow_ok(s);
+    s->swar_narrow = s->swar_uni && swar_narrow_ok(s);
+    return GOM_OK;
+}
+
+extern "C" int gom_state_set_bitsliced_min_sets(gom_state *s, int32_t sets) {
+    if (!s) return fail(GOM_E_ARG, "gom_state_set_bitsliced_min_sets: null state");
+    if (sets < 0) return fail(GOM_E_RANGE, "gom_state_set_bitsliced_min_sets: %d sets", sets);
+    s->gs_min_sets = sets;
+    s->bitsliced_ok = s->swar_uni || gs_select(s);
+    if (s->sched == GOM_SCHED_BITSLICED && !s->bitsliced_ok) s->sched = auto_schedule(s);
     return GOM_OK;
 }
 

@@ -368,6 +368,18 @@ hipError_t launch_large_set_sweep(const SweepArgs &a, int max_members, int threa
 hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow, int max_grid,
                                  hipStream_t s, KernelEvents ev = {});
 constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
+// Bit-sliced sweep of small general sets (lane = set): classes whose sets have at most
+// kGsMaxMembers members, whose per-set sum of |w| over the dependent edges is at most
+// kGsMaxWeightSum (the bit-sliced sum 2 W stays below 2^15) and whose largest |w| has at most
+// kGsMaxWeightBits bits; classes of fewer than kGsMinSets sets keep the class sweep (one set
+// per lane leaves a small class too few waves).
+constexpr int kGsThreads = 256;
+constexpr int kGsMaxMembers = 9;
+constexpr int64_t kGsMaxWeightSum = 16383;
+constexpr int kGsMaxWeightBits = 13;
+constexpr int32_t kGsMinSets = 8192;
+hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bits, int max_grid,
+                                 hipStream_t s, KernelEvents ev);
 // Fused form (one cooperative launch per generation; see FusedArgs).
 hipError_t launch_uni_swar_fused(const FusedArgs &f, bool partition, bool narrow,
                                  hipStream_t s);

@@ -1529,6 +1529,233 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
     swar_block_totals(a, fa, redc, n_eval, n_acc);
 }
 
+// ------------------------------------------------------------------------------------------
+// Bit-sliced sweep of one colour class of small general sets (lane = set, the solutions of a
+// set as the bits of 32-bit words, in two halves of 32).  Each pair gets the step of the
+// class sweep (k_class_sweep): the donor set D, the draw's donor, the changed members C, the
+// partial evaluation and the acceptance rule, with the same Philox draws.  Per half:
+//   1. draws: the eight lanes of class positions 8j..8j+7 share one Philox call per solution
+//      (counter (g, c, i, j)); lane l computes the calls of solutions l, l+8, l+16, l+24 of
+//      the half and leaves their words in LDS, where each lane reads its own 16-bit field;
+//   2. per solution i (a loop): D_i = OR over the members of (P[u] xor O_i[u] spread), the
+//      donor d = the r-th set bit of D_i, and bit i of each member's change mask F_k (the
+//      donor's gene differs from O_i's);
+//   3. the fitness change of all 32 solutions at once: for dependent edge e with weight w_e,
+//      X_e (the edge's cut changes: one end changes) and A_e (it changes towards +|w_e|:
+//      becomes cut for w_e > 0, uncut for w_e < 0) give Y_e = 2 A_e + (1 - X_e) in {0, 1, 2},
+//      and T = sum_e |w_e| Y_e = delta + W with W = sum_e |w_e|.  T is summed bit-sliced in
+//      carry-save form over kGsPlanes bit planes (the host bounds W so that 2 W < 2^kGsPlanes);
+//   4. accept = donor exists & (T > W | (T == W & (always | P_i != elitist))); member words
+//      are stored with F_k & accept flipped, and each accepted solution's T - W is added to
+//      its LDS counter.
+// M: member slots (a class's largest set); WB: bits of the class's largest |w|.  Sets of a
+// class are independent, so each lane alone reads and writes its members' words, and the
+// outside ends of its edges belong to no set of the class.
+// ------------------------------------------------------------------------------------------
+constexpr int kGsPlanes = 15;
+
+__device__ __forceinline__ uint32_t maj3(uint32_t x, uint32_t y, uint32_t z) {
+    return __builtin_amdgcn_bitop3_b32(x, y, z, 0xE8);  // at least two of the three bits
+}
+__device__ __forceinline__ uint32_t xor3(uint32_t x, uint32_t y, uint32_t z) {
+    return __builtin_amdgcn_bitop3_b32(x, y, z, 0x96);
+}
+
+template <int M, int WB>
+__global__ __launch_bounds__(kGsThreads) void k_gen_swar_sweep(SweepArgs a) {
+    static_assert(M >= 1 && M <= kSmallSet && WB >= 1 && WB + 1 < kGsPlanes, "shape");
+    __shared__ uint4 rnd[kGsThreads / 8][32];        // Philox words: lane group, solution
+    __shared__ uint32_t fo[2][M][kGsThreads];        // F_k and O half-words by member slot
+    __shared__ unsigned long long fa[64];
+    __shared__ uint32_t redc[2][kGsThreads / 64];
+    const int tid = (int)threadIdx.x;
+    const int grp = tid >> 3, fl = tid & 7;
+    const uint64_t mism = a.stripes[tid & 63].mism;
+    const bool live = a.st->elite_fitness < a.target;
+    const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
+    const uint64_t nz = a.always ? popm : (wave_or64(mism) & popm);
+    if (tid < 64) fa[tid] = 0;
+    __syncthreads();
+    uint32_t n_eval = 0, n_acc = 0;
+    uint64_t accm = 0;  // solutions with an accepted step (tracking mode)
+    const uint32_t *O32 = reinterpret_cast<const uint32_t *>(a.O);
+    uint32_t *W32 = reinterpret_cast<uint32_t *>(a.O);
+    const int halves = a.N > 32 ? 2 : 1;
+    for (int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+         live && tile * kGsThreads < a.csize; tile += gridDim.x) {
+        const int p = tile * kGsThreads + tid;  // class position
+        const bool act = p < a.csize;
+        int nm = 0, nd = 0;
+        int u[M];
+        uint64_t pw[M], ow[M];
+        const int32_t *R = nullptr;
+        if (act) {
+            R = a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p];
+            const int4 h0 = reinterpret_cast<const int4 *>(R)[0];
+            const int4 h1 = reinterpret_cast<const int4 *>(R)[1];
+            const int4 h2 = reinterpret_cast<const int4 *>(R)[2];
+            const int4 h3 = reinterpret_cast<const int4 *>(R)[3];
+            nm = h0.x;
+            nd = h0.y;
+            const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
+                                        h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
+#pragma unroll
+            for (int k = 0; k < M; ++k) u[k] = k < nm ? mem[k] : -1;
+        } else {
+#pragma unroll
+            for (int k = 0; k < M; ++k) u[k] = -1;
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            pw[k] = u[k] >= 0 ? a.P[u[k]] : 0ull;
+            ow[k] = u[k] >= 0 ? a.O[u[k]] : 0ull;
+        }
+        for (int h = 0; h < halves; ++h) {
+            // 1. draws of this half's solutions for the lane's group of eight positions
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int ii = fl + 8 * t;
+                const U32x4 q = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls,
+                                       (uint32_t)(32 * h + ii), (uint32_t)(p >> 3));
+                rnd[grp][ii] = make_uint4(q.x, q.y, q.z, q.w);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const uint16_t *rb = reinterpret_cast<const uint16_t *>(&rnd[grp][0]) + fl;
+            // 2. donors and change masks, one solution at a time
+            uint32_t oh[M], F[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                oh[k] = h ? (uint32_t)(ow[k] >> 32) : (uint32_t)ow[k];
+                F[k] = 0u;
+            }
+            uint32_t has = 0u;
+            const int n_i = min(32, a.N - 32 * h);
+            for (int ii = 0; ii < n_i; ++ii) {
+                const int i = 32 * h + ii;
+                uint32_t dlo = 0u, dhi = 0u;
+                uint32_t s[M];
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    s[k] = (uint32_t)__builtin_amdgcn_sbfe((int)oh[k], ii, 1u);
+                    dlo |= (uint32_t)pw[k] ^ s[k];
+                    dhi |= (uint32_t)(pw[k] >> 32) ^ s[k];
+                }
+                const uint64_t cand = popm & ~(1ull << i);
+                dlo &= (uint32_t)cand;
+                dhi &= (uint32_t)(cand >> 32);
+                const uint32_t cnt = (uint32_t)__popc(dlo) + (uint32_t)__popc(dhi);
+                const uint32_t h16 = rb[8 * ii];
+                const uint32_t d = cnt ? select_bit(((uint64_t)dhi << 32) | dlo,
+                                                    (h16 * cnt) >> 16) : 0u;
+                has |= (cnt ? 1u : 0u) << ii;
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const uint32_t fk = (bit_of(pw[k], d) ^ s[k]) & (cnt ? 1u : 0u);
+                    F[k] |= fk << ii;
+                }
+            }
+            // 3. fitness changes, bit-sliced over the half's solutions
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                fo[0][k][tid] = F[k];
+                fo[1][k][tid] = oh[k];
+            }
+            uint32_t S[kGsPlanes], C[kGsPlanes];
+#pragma unroll
+            for (int j = 0; j < kGsPlanes; ++j) S[j] = C[j] = 0u;
+            int32_t W = 0;
+            for (int e = 0; e < nd; ++e) {
+                const int2 en = reinterpret_cast<const int2 *>(R + 16)[e];
+                const uint32_t x = (uint32_t)en.x;
+                const int ka = (int)((x >> kSmallPosShift) & 15u);
+                const uint32_t y = x & kSmallIdx;
+                const bool inside = (int32_t)x < 0;
+                const int kb = inside ? (int)y : ka;
+                const uint32_t fa_ = fo[0][ka][tid], oa = fo[1][ka][tid];
+                const uint32_t fb = fo[0][kb][tid], ob = fo[1][kb][tid];
+                const uint32_t ov = inside ? ob : O32[2 * (size_t)y + h];
+                const uint32_t X = inside ? fa_ ^ fb : fa_;
+                const uint32_t cut = oa ^ ov;
+                const uint32_t aw = (uint32_t)(en.y < 0 ? -en.y : en.y);
+                const uint32_t A = X & (en.y > 0 ? ~cut : cut);
+                const uint32_t nX = ~X;
+                W += (int32_t)aw;
+                // add |w| * (2 A + nX): plane j gets (A & bit j-1 of |w|) | (nX & bit j); a
+                // full adder per plane, from the top so that C[j + 1] is read before it is
+                // replaced by plane j's carry
+                uint32_t wb[WB + 1];
+#pragma unroll
+                for (int j = 0; j < WB; ++j)
+                    wb[j] = (uint32_t)__builtin_amdgcn_sbfe((int)aw, j, 1u);
+                wb[WB] = 0u;
+#pragma unroll
+                for (int j = kGsPlanes - 1; j >= 0; --j) {
+                    uint32_t z = 0u;
+                    if (j <= WB) z = (j ? A & wb[j - 1] : 0u) | (nX & wb[j]);
+                    const uint32_t sj = S[j], cj = C[j];
+                    S[j] = xor3(sj, cj, z);
+                    if (j + 1 < kGsPlanes) C[j + 1] = maj3(sj, cj, z);
+                }
+                C[0] = 0u;
+            }
+            // 4. T = S + C against W: greater / equal, all solutions at once
+            uint32_t T[kGsPlanes];
+            uint32_t carry = 0u;
+#pragma unroll
+            for (int j = 0; j < kGsPlanes; ++j) {
+                T[j] = xor3(S[j], C[j], carry);
+                carry = maj3(S[j], C[j], carry);
+            }
+            uint32_t gt = 0u, eq = ~0u;
+#pragma unroll
+            for (int j = kGsPlanes - 1; j >= 0; --j) {
+                const uint32_t wj = (uint32_t)__builtin_amdgcn_sbfe(W, j, 1u);
+                gt |= eq & T[j] & ~wj;
+                eq &= ~(T[j] ^ wj);
+            }
+            const uint32_t nzh = (uint32_t)(nz >> (32 * h));
+            const uint32_t acc = has & (gt | (eq & nzh));
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const uint32_t m = F[k] & acc;
+                if (u[k] >= 0 && m) W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
+            }
+            for (uint32_t m = acc; m; m &= m - 1) {
+                const int ii = __builtin_ctz(m);
+                int32_t t = 0;
+#pragma unroll
+                for (int j = 0; j < kGsPlanes; ++j) t |= (int32_t)((T[j] >> ii) & 1u) << j;
+                atomicAdd(&fa[32 * h + ii], (unsigned long long)(long long)(t - W));
+            }
+            n_eval += (uint32_t)__popc(has);
+            n_acc += (uint32_t)__popc(acc);
+            accm |= (uint64_t)acc << (32 * h);
+        }
+    }
+    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
+    const uint64_t am = a.mode == kSweepGomTrack ? wave_or64(accm) : 0ull;
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0) {
+        redc[0][wave] = ce;
+        redc[1][wave] = ca;
+    }
+    __syncthreads();
+    Stripe *sp = a.stripes + (blockIdx.x % kStripes);
+    if (tid < a.N && fa[tid])
+        atomicAdd((unsigned long long *)&sp->fit[tid], fa[tid]);
+    if (tid == 0) {
+        uint32_t se = 0, sa = 0;
+        for (int w = 0; w < kGsThreads / 64; ++w) {
+            se += redc[0][w];
+            sa += redc[1][w];
+        }
+        if (se) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)se);
+        if (sa) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)sa);
+    }
+    if (lane == 0 && am) atomicOr((unsigned long long *)&sp->acc, (unsigned long long)am);
+}
+
 // Fused form: every class of the generation in one cooperative launch (all blocks resident at
 // once, so a block may wait for others).  Block b sweeps chunk x = xcd_tile(b, grid) of each
 // class in the generation's order.  Before a class it waits, one wave polling, until every
@@ -2371,6 +2598,22 @@ hipError_t launch_uni_swar_sweep(const SweepArgs &a, bool partition, bool narrow
     else if (partition) launch_timed(k_uni_swar_sweep<true, false>, gd, bd, 0, s, ev, a);
     else if (narrow) launch_timed(k_uni_swar_sweep<false, true>, gd, bd, 0, s, ev, a);
     else launch_timed(k_uni_swar_sweep<false, false>, gd, bd, 0, s, ev, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bits, int max_grid,
+                                 hipStream_t s, KernelEvents ev) {
+    if (members < 1 || members > kGsMaxMembers || weight_bits < 1 ||
+        weight_bits > kGsMaxWeightBits || a.N > 64)
+        return hipErrorInvalidValue;
+    int grid = (a.csize + kGsThreads - 1) / kGsThreads;
+    if (grid > max_grid) grid = max_grid;
+    if (grid < 1) return hipSuccess;
+    const dim3 gd(grid), bd(kGsThreads);
+    if (members <= 5 && weight_bits <= 7) launch_timed(k_gen_swar_sweep<5, 7>, gd, bd, 0, s, ev, a);
+    else if (members <= 5) launch_timed(k_gen_swar_sweep<5, 13>, gd, bd, 0, s, ev, a);
+    else if (weight_bits <= 7) launch_timed(k_gen_swar_sweep<9, 7>, gd, bd, 0, s, ev, a);
+    else launch_timed(k_gen_swar_sweep<9, 13>, gd, bd, 0, s, ev, a);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ EXPORTED = (
     "gom_timing_enable", "gom_timing_read", "gom_state_set_schedule", "gom_state_get_schedule",
     "gom_state_autotune", "gom_debug_stop_after_class", "gom_state_hash", "gom_state_set_fi",
     "gom_state_get_fi", "gom_state_set_block", "gom_state_get_block", "gom_state_set_fused",
-    "gom_state_get_fused", "gom_state_set_grid_limit", "gom_state_set_staged", "gom_local_search",
+    "gom_state_get_fused", "gom_state_set_grid_limit", "gom_state_set_bitsliced_min_sets", "gom_state_set_staged", "gom_local_search",
     "gom_iterated_local_search",
     "gom_ims_bytes",
     "gom_ims_run",
@@ -127,6 +127,7 @@ def lib() -> C.CDLL:
         "gom_state_get_block": (C.c_int, [_vp, _P(C.c_int)]),
         "gom_state_set_fused": (C.c_int, [_vp, C.c_int]),
         "gom_state_set_grid_limit": (C.c_int, [_vp, _i32]),
+        "gom_state_set_bitsliced_min_sets": (C.c_int, [_vp, _i32]),
         "gom_state_set_staged": (C.c_int, [_vp, C.c_int]),
         "gom_state_get_fused": (C.c_int, [_vp, _P(C.c_int), _P(C.c_int)]),
         "gom_state_get_fi": (C.c_int, [_vp, _P(C.c_int)]),
@@ -495,6 +496,11 @@ def gom_state_get_fused(s: GomState):
 def gom_state_set_grid_limit(s: GomState, blocks: int) -> None:
     """Grid cap of the per-class sweeps (results do not depend on it)."""
     _check(lib().gom_state_set_grid_limit(s.handle, int(blocks)))
+
+
+def gom_state_set_bitsliced_min_sets(s: GomState, sets: int) -> None:
+    """Smallest class the bit-sliced schedule sweeps with the general bit-sliced sweep."""
+    _check(lib().gom_state_set_bitsliced_min_sets(s.handle, int(sets)))
 
 
 def gom_state_set_staged(s: GomState, enabled: bool) -> None:

@@ -789,6 +789,82 @@ def test_bitsliced_univariate(cuda, label, maker, pop, rule, dups, fused):
     lockstep(st, ref, 12, f"bitsliced {label} fused={fused}")
 
 
+def _nbhd_plus_large_sets(g, every, size, seed):
+    """Neighbourhood sets of every vertex plus, for every `every`-th vertex, a set of `size`
+    vertices around it (breadth-first): classes that hold a large set keep the class sweep
+    under the bit-sliced schedule while the others take the bit-sliced general sweep."""
+    rng = np.random.default_rng(seed)
+    adj = [[] for _ in range(g.n)]
+    for a, b in zip(g.u.tolist(), g.v.tolist()):
+        adj[a].append(b)
+        adj[b].append(a)
+    sets = [sorted({v, *adj[v]}) for v in range(g.n)]
+    for v in range(0, g.n, every):
+        seen, frontier = [v], [v]
+        while frontier and len(seen) < size:
+            nxt = []
+            for x in frontier:
+                for y in adj[x]:
+                    if y not in seen and len(seen) < size:
+                        seen.append(y)
+                        nxt.append(y)
+            frontier = nxt
+        sets.append(sorted(seen))
+    rng.shuffle(sets)
+    ptr = np.zeros(len(sets) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(x) for x in sets])
+    return ptr, np.asarray(sum(sets, []), np.int32)
+
+
+GENERAL_BITSLICED_CASES = [
+    # (label, graph maker, population, neutral rule, explicit sets maker or None)
+    ("torus40_nbhd_p64", lambda: workloads.torus(40, 1, 100, seed=21), 64, 0, None),
+    ("torus40_nbhd_p40_w1000_always", lambda: workloads.torus(40, 1, 1000, seed=22), 40, 1,
+     None),
+    ("cm_d8_nbhd_p32_signed", lambda: workloads.configuration_model(3000, 8, seed=23), 32, 0,
+     None),
+    ("cm_d6_nbhd_p64_w200", lambda: workloads.configuration_model(
+        2000, 6, seed=24, weights="uniform", w_lo=-200, w_hi=200), 64, 0, None),
+    ("cm_d3_nbhd_p12", lambda: workloads.configuration_model(2000, 3, seed=25), 12, 0, None),
+    ("cm_d4_nbhd_p64_mixed", lambda: workloads.configuration_model(1500, 4, seed=26), 64, 0,
+     lambda g: _nbhd_plus_large_sets(g, 37, 12, seed=27)),
+]
+
+
+@pytest.mark.parametrize("label,maker,pop,rule,sets", GENERAL_BITSLICED_CASES,
+                         ids=[c[0] for c in GENERAL_BITSLICED_CASES])
+def test_bitsliced_general(cuda, label, maker, pop, rule, sets):
+    """Bit-sliced schedule on general FOS (lane = set, the fitness changes of 32 solutions as
+    one bit-sliced sum): neighbourhoods of tori and random graphs, weights of up to 7 and up to
+    13 bits, negative weights, populations of 12 to 64 (one or two halves, a partial second
+    half), both neutral rules, and a FOS whose larger sets keep some classes on the class
+    sweep.  Every class qualifies regardless of its size here (minimum 0 sets)."""
+    print(f"case bitsliced general {label}", flush=True)
+    g = maker()
+    explicit = sets(g) if sets else None
+    _, st, ref = make_pair(g, 1, pop, seed=9, rule=rule, sets=explicit)
+    gom.gom_state_set_bitsliced_min_sets(st, 0)
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_BITSLICED
+    lockstep(st, ref, 10, f"bitsliced general {label}")
+
+
+def test_bitsliced_general_min_sets(cuda):
+    """The size threshold: with the default (8192 sets) a 40x40 torus's neighbourhood classes
+    do not qualify, so the bit-sliced schedule is unavailable; lowering it makes it
+    available, and raising it again under that schedule falls back to the automatic choice."""
+    g = workloads.torus(40, 1, 100, seed=21)
+    _, st, _ = make_pair(g, 1, 16, seed=1)
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+    gom.gom_state_set_bitsliced_min_sets(st, 1)
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_BITSLICED)
+    gom.gom_state_set_bitsliced_min_sets(st, 1 << 20)
+    assert gom.gom_state_get_schedule(st) != gom.GOM_SCHED_BITSLICED
+    with pytest.raises(gom.GomError):
+        gom.gom_state_set_bitsliced_min_sets(st, -1)
+
+
 FUSED_CASES = [
     # (label, graph maker, population, neutral rule)
     ("torus10_p16", lambda: workloads.torus(10, 1, 5, seed=1), 16, 0),
@@ -807,11 +883,12 @@ def test_bitsliced_fused(cuda, label, maker, pop, rule):
     print(f"case fused {label}", flush=True)
     g = maker()
     _, st, ref = make_pair(g, 0, pop, seed=9, rule=rule, sched=gom.GOM_SCHED_BITSLICED)
+    assert gom.gom_state_get_fused(st) == (False, True)  # available, off by default
+    gom.gom_state_set_fused(st, True)
     assert gom.gom_state_get_fused(st) == (True, True)
     inst = gom.Instance(g.n, g.u, g.v, g.w, 0)
     other = inst.state(pop=pop, seed=9, neutral_rule=rule)
     gom.gom_state_set_schedule(other, gom.GOM_SCHED_BITSLICED)
-    gom.gom_state_set_fused(other, False)
     assert gom.gom_state_get_fused(other) == (False, True)
     lockstep(st, ref, 8, f"fused {label}")
     for _ in range(8):

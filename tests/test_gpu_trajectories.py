@@ -35,10 +35,13 @@ def assert_same(a, b, where):
 
 
 def _states(inst, pop, seed, scheds):
-    """One state per (schedule, block size[, staged evaluation])."""
+    """One state per (schedule, block size[, staged evaluation]); under the bit-sliced
+    schedule every class that qualifies takes the bit-sliced sweep, whatever its size."""
     out = []
     for sched, block, *rest in scheds:
         st = inst.state(pop=pop, seed=seed)
+        if sched == gom.GOM_SCHED_BITSLICED:
+            gom.gom_state_set_bitsliced_min_sets(st, 0)
         gom.gom_state_set_schedule(st, sched)
         if block:
             gom.gom_state_set_block(st, block)
@@ -83,11 +86,12 @@ def _trajectory(label, g, kind, pop, seed, gens, scheds, full_every, target=None
 def test_c2_full_trajectory():
     """100x100 torus, neighbourhood FOS, population 64, seed 1: the whole 500-generation run
     of the plain single-instance workload, under the class-launch schedule with 64-thread
-    blocks, 256-thread blocks, 64-thread blocks with the staged evaluation, and the resident
-    schedule."""
+    blocks, 256-thread blocks, 64-thread blocks with the staged evaluation, the resident
+    schedule and the bit-sliced schedule."""
     g = workloads.torus(100, 1, 100, seed=2)
     scheds = [(gom.GOM_SCHED_CLASS_LAUNCH, 64), (gom.GOM_SCHED_CLASS_LAUNCH, 256),
-              (gom.GOM_SCHED_CLASS_LAUNCH, 64, True), (gom.GOM_SCHED_RESIDENT, 0)]
+              (gom.GOM_SCHED_CLASS_LAUNCH, 64, True), (gom.GOM_SCHED_RESIDENT, 0),
+              (gom.GOM_SCHED_BITSLICED, 0)]
     _trajectory("torus100 nbhd p64 seed 1", g, 1, 64, 1, 500, scheds, 50,
                 target=g.total_weight)
 
@@ -127,6 +131,8 @@ def test_c3_neighbourhood_prefix(d, gens):
     time per generation) under class launch and the resident schedule."""
     g = workloads.configuration_model(100_000, d, seed=3, weights="signed50")
     scheds = [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_RESIDENT, 0)]
+    if d <= 8:  # (degree 12: 13 members, beyond the bit-sliced general sweep)
+        scheds.append((gom.GOM_SCHED_BITSLICED, 0))
     _trajectory(f"cm100k d{d} nbhd p32", g, 1, 32, 1, gens, scheds, 10)
 
 
@@ -139,8 +145,10 @@ def test_torus1000_univariate_5_generations():
 
 
 def test_torus1000_neighbourhood_2_generations():
-    """The 10^6-vertex torus, neighbourhood FOS, population 64, class launch (staged
-    evaluation with shared draws, and the batched-entries form): two generations."""
+    """The 10^6-vertex torus, neighbourhood FOS, population 64, class launch (the batched-
+    entries form with shared draws, and the staged evaluation) and the bit-sliced schedule:
+    two generations."""
     g = workloads.torus(1000, 1, 100, seed=7)
     _trajectory("torus1000 nbhd p64", g, 1, 64, 1, 2,
-                [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_CLASS_LAUNCH, 0, True)], 2)
+                [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_CLASS_LAUNCH, 0, True),
+                 (gom.GOM_SCHED_BITSLICED, 0)], 2)
