@@ -267,7 +267,7 @@ def run_batch_mode(args, torch, gom):
     gom.gom_batch_set_graph(batch, args.batch_graph == "on")
     log(f"batch states: {time.perf_counter() - t0:.1f} s")
     tuned = (args.batch_narrow is None and args.batch_class_min is None and
-             args.batch_class_ppw is None)
+             args.batch_class_ppw is None and args.batch_class_form is None)
     if tuned:
         t0 = time.perf_counter()
         chosen = gom.gom_batch_autotune(batch, 2)
@@ -279,8 +279,11 @@ def run_batch_mode(args, torch, gom):
             gom.gom_batch_set_class_launch(batch, args.batch_class_min)
         if args.batch_class_ppw is not None:
             gom.gom_batch_set_class_positions(batch, args.batch_class_ppw)
+        if args.batch_class_form is not None:
+            gom.gom_batch_set_class_bitsliced(batch, args.batch_class_form == "bitsliced")
     narrow, sweep_launches = gom.gom_batch_get_narrow(batch)
     class_min, class_insts, class_launches, class_ppw = gom.gom_batch_get_class_launch(batch)
+    class_bits = gom.gom_batch_get_class_bitsliced(batch)[0] if class_insts else False
 
     def one_step(k):
         gom.gom_batch_reseed(batch, step_seeds(items, k))
@@ -360,7 +363,9 @@ def run_batch_mode(args, torch, gom):
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                     "traffic": traffic,
                     "traffic_profile": meas["profile"] if traffic else None,
-                    "kernel": "k_batch_sweep + k_bcl_sweep" if class_insts else "k_batch_sweep",
+                    "kernel": ("k_batch_sweep + " +
+                               ("k_bcl_gs_sweep" if class_bits else "k_bcl_sweep"))
+                              if class_insts else "k_batch_sweep",
                     "bytes_per_launch": round(total_bytes / launches, 1),
                     "avg_launch_us": round(sweep_ms / launches * 1e3, 3), "launches": launches,
                     "timing": "every sweep launch of one more batched run (the first timed "
@@ -386,7 +391,9 @@ def run_batch_mode(args, torch, gom):
                    "narrow_blocks_max_n": narrow, "resident_launches_per_step": sweep_launches,
                    "class_launch_min_n": class_min, "class_launch_instances": class_insts,
                    "class_launches_per_step": class_launches,
-                   "class_positions_per_wave": class_ppw,
+                   "class_positions_per_wave": None if class_bits else class_ppw,
+                   "class_launch_form": ("bitsliced" if class_bits else "lane_per_solution")
+                                        if class_insts else None,
                    "launch_shapes": "autotuned" if tuned else "fixed",
                    "generation_steps": ("hip_graph_chunks_of_4" if args.batch_graph == "on"
                                         else "direct_launches"),
@@ -613,6 +620,9 @@ def main():
                     help="batched mode: neighbourhood instances with at least this many "
                          "vertices take the batched class launches (-1: none; default: "
                          "autotuned)")
+    ap.add_argument("--batch-class-form", choices=("bitsliced", "lanes"), default=None,
+                    help="batched mode: form of the class launches (bit-sliced where "
+                         "available, or lane = solution)")
     ap.add_argument("--batch-class-ppw", type=int, default=None,
                     help="batched mode: class positions per wave of the class launches (1..8)")
     ap.add_argument("--batch-graph", choices=("on", "off"), default="on",

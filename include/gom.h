@@ -528,14 +528,26 @@ int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, int32_t *inst
 /* Consecutive class positions a wave of the class launches sweeps (1..8; default 2): more
  * share a Philox call, fewer give small classes more waves.  Errors: GOM_E_ARG, GOM_E_RANGE. */
 int gom_batch_set_class_positions(gom_batch *b, int32_t positions_per_wave);
+/*
+ * Bit-sliced form of the class launches (default on where available): lane = one half of a
+ * set's solutions, over the sets of every class-launched instance's class at a position,
+ * with the donor draws per solution and the fitness changes of 32 solutions as one bit-sliced
+ * sum (as the bit-sliced schedule's general sweep).  Available when every class-launched
+ * instance's per-set sums of |w| over the dependent edges are at most 16383 and its |w| have
+ * at most 13 bits.  Results are identical either way.  gom_batch_get_class_bitsliced: in use,
+ * available (either may be NULL).  Errors: GOM_E_ARG.
+ */
+int gom_batch_set_class_bitsliced(gom_batch *b, int enabled);
+int gom_batch_get_class_bitsliced(const gom_batch *b, int *enabled, int *available);
 
 /*
  * Autotuner of the batch's launch shapes: runs trial_steps generation steps under each
  * candidate class-launch threshold (none, 50000, 20000, 5000 vertices, all eligible), then
  * under each block-size threshold (all 1024-thread blocks, 2048, 8192, 16384, 32768 vertices,
- * all 256-thread blocks), then (when some instance takes the class launches) under 1, 2, 4
- * and 8 positions per wave, candidates that give the same assignment only once, timed with
- * HIP events on `stream` in two interleaved rounds, and keeps the fastest of each.  The trial
+ * all 256-thread blocks), then (when some instance takes the class launches) the bit-sliced
+ * form where available against 1, 2, 4 and 8 positions per wave of the lane-per-solution
+ * form, candidates that give the same assignment only once, timed with HIP events on `stream`
+ * in two interleaved rounds, and keeps the fastest of each.  The trial
  * steps are ordinary generation steps of the run (they count against gom_batch_run's step
  * budget).  Synchronous.  narrow, class_min (or NULL): the thresholds kept.
  * Errors: GOM_E_ARG, GOM_E_STATE (an open generation), GOM_E_RANGE, GOM_E_DEVICE.

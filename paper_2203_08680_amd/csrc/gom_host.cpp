@@ -2112,6 +2112,10 @@ struct gom_batch {
     int32_t *d_bcl_tiles = nullptr;
     int bcl_kmax = 0, bcl_grid = 0;
     int bcl_ppw = 2;                    // class positions per wave of the class launches
+    uint64_t *d_bcl_nzm = nullptr;      // per class-launched instance: neutral-step mask
+    bool bcl_gs_use = true;             // class launches in the bit-sliced form when ...
+    bool bcl_gs_ok = false;             // ... every class-launched instance admits it
+    int bcl_gs_wb = 0, bcl_gs_grid = 0; // its weight bits (7 or 13) and blocks per launch
     int64_t narrow_max_n = -1;          // instances with n <= this run 256-thread blocks
     size_t lds_max = 0;                 // LDS per CU of the device
     DevState *h_st = nullptr;           // pinned, 2 x count
@@ -2134,7 +2138,7 @@ namespace {
 struct BatchLayout {
     std::vector<size_t> sub_off, sub_bytes;
     size_t insts = 0, blk = 0, vblk = 0, snap = 0, bcl = 0, bcl_order = 0, bcl_tiles = 0,
-           total = 0;
+           bcl_nzm = 0, total = 0;
     int sweep_blocks = 0, vblocks = 0, kmax = 0;
 };
 
@@ -2171,6 +2175,8 @@ int batch_layout(int32_t count, const mc_graph *const *graphs, const gom_fos *co
     o = align_up(o + sizeof(uint16_t) * (size_t)count * kmax);
     B.bcl_tiles = o;
     o = align_up(o + sizeof(int32_t) * (size_t)kmax * (count + 1));
+    B.bcl_nzm = o;
+    o = align_up(o + sizeof(uint64_t) * (size_t)count);
     B.total = o;
     B.sweep_blocks = sweep;
     B.vblocks = vb;
@@ -2246,6 +2252,18 @@ static bool bcl_eligible(const gom_state *s) {
     return true;
 }
 
+// Drop the captured chunk graph (it holds the launch arguments of the current plan).
+static void drop_graph(gom_batch *b) {
+    if (b->graph_exec) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+}
+
 static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
                          hipStream_t st) {
     // which instances the batched class launches sweep (the others: resident blocks)
@@ -2279,6 +2297,25 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
         b->bcl_kmax = std::max(b->bcl_kmax, s->k);
     }
     if (!bi.empty() && b->bcl_grid == 0) HIP_TRY(bcl_sweep_grid(&b->bcl_grid));
+    // the bit-sliced form: every class-launched instance within its weight bounds; blocks for
+    // the most slots a position can have (every instance at its largest class)
+    b->bcl_gs_ok = !b->bcl.empty();
+    int wbits = 1;
+    int64_t slots = 0;
+    for (int32_t i : b->bcl) {
+        const gom_state *s = b->subs[(size_t)i];
+        for (int32_t c = 0; c < s->k; ++c) {
+            int bits = 1;
+            while (bits < 62 && (s->class_wmax[c] >> bits) != 0) ++bits;
+            wbits = std::max(wbits, bits);
+            if (s->class_wsum[c] > kGsMaxWeightSum) b->bcl_gs_ok = false;
+        }
+        if (s->N > 64) b->bcl_gs_ok = false;
+        slots += gs_slots(s->max_class, s->N > 32 ? 2 : 1);
+    }
+    if (wbits > kGsMaxWeightBits) b->bcl_gs_ok = false;
+    b->bcl_gs_wb = wbits <= 7 ? 7 : 13;
+    b->bcl_gs_grid = (int)std::min<int64_t>((slots + kGsThreads - 1) / kGsThreads, 1 << 30);
     struct Item {
         int threads, kind, occ;
         double cost;
@@ -2380,14 +2417,7 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
                                hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(prepare_batch_step(groups.data(), (int)groups.size()));
-    if (b->graph_exec) {
-        (void)hipGraphExecDestroy(b->graph_exec);
-        b->graph_exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    drop_graph(b);
     b->groups = std::move(groups);
     b->narrow_max_n = narrow_max_n;
     b->bcl_min_n = bcl_min_n;
@@ -2404,6 +2434,10 @@ static BclPlan bcl_plan(const gom_batch *b) {
     p.kmax = b->bcl_kmax;
     p.grid = b->bcl_grid;
     p.ppw = b->bcl_ppw;
+    p.gs = b->bcl_gs_ok && b->bcl_gs_use ? 1 : 0;
+    p.gs_wb = b->bcl_gs_wb;
+    p.gs_grid = b->bcl_gs_grid;
+    p.nzm = b->d_bcl_nzm;
     return p;
 }
 
@@ -2463,6 +2497,7 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
     bt->d_bcl = (BclInst *)(arena + B.bcl);
     bt->d_bcl_order = (uint16_t *)(arena + B.bcl_order);
     bt->d_bcl_tiles = (int32_t *)(arena + B.bcl_tiles);
+    bt->d_bcl_nzm = (uint64_t *)(arena + B.bcl_nzm);
     bt->d_insts = (BatchInst *)(arena + B.insts);
     bt->d_blk = (int2 *)(arena + B.blk);
     bt->d_vblk = (int32_t *)(arena + B.vblk);
@@ -2830,10 +2865,14 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
     // then the class launches' positions per wave (when some instance takes them)
     rc = rc == GOM_OK && e == hipSuccess ? batch_regroup(b, best.first, best.second, st) : rc;
     if (rc == GOM_OK && e == hipSuccess && !b->bcl.empty()) {
-        const int ppws[] = {1, 2, 4, 8};
-        std::vector<double> total(4, 0.0);
+        // (the bit-sliced form when admitted, else lane = solution with 1, 2, 4, 8 positions)
+        const int gsv[] = {1, 0, 0, 0, 0}, ppws[] = {b->bcl_ppw, 1, 2, 4, 8};
+        const int q0 = b->bcl_gs_ok ? 0 : 1;
+        std::vector<double> total(5, 0.0);
+        total[0] = b->bcl_gs_ok ? 0.0 : 1e300;
         for (int round = 0; round < 2 && rc == GOM_OK && e == hipSuccess; ++round)
-            for (int q = 0; q < 4 && rc == GOM_OK && e == hipSuccess; ++q) {
+            for (int q = q0; q < 5 && rc == GOM_OK && e == hipSuccess; ++q) {
+                b->bcl_gs_use = gsv[q] != 0;
                 b->bcl_ppw = ppws[q];
                 e = hipEventRecord(e0, st);
                 for (int32_t t = 0; t < trial_steps && e == hipSuccess && rc == GOM_OK; ++t) {
@@ -2849,7 +2888,9 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
                 total[(size_t)q] += ms;
                 b->g_done += trial_steps;
             }
-        b->bcl_ppw = ppws[std::min_element(total.begin(), total.end()) - total.begin()];
+        const size_t qb = (size_t)(std::min_element(total.begin(), total.end()) - total.begin());
+        b->bcl_gs_use = gsv[qb] != 0;
+        b->bcl_ppw = ppws[qb];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2885,20 +2926,27 @@ extern "C" int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, in
     return GOM_OK;
 }
 
+extern "C" int gom_batch_set_class_bitsliced(gom_batch *b, int enabled) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_set_class_bitsliced: null batch");
+    b->bcl_gs_use = enabled != 0;
+    drop_graph(b);
+    return GOM_OK;
+}
+
+extern "C" int gom_batch_get_class_bitsliced(const gom_batch *b, int *enabled, int *available) {
+    if (!b) return fail(GOM_E_ARG, "gom_batch_get_class_bitsliced: null batch");
+    if (enabled) *enabled = b->bcl_gs_ok && b->bcl_gs_use;
+    if (available) *available = b->bcl_gs_ok;
+    return GOM_OK;
+}
+
 extern "C" int gom_batch_set_class_positions(gom_batch *b, int32_t positions_per_wave) {
     if (!b) return fail(GOM_E_ARG, "gom_batch_set_class_positions: null batch");
     if (positions_per_wave < 1 || positions_per_wave > kBclPositions)
         return fail(GOM_E_RANGE, "gom_batch_set_class_positions: %d (1..%d)", positions_per_wave,
                     kBclPositions);
     b->bcl_ppw = positions_per_wave;
-    if (b->graph_exec) {  // the captured chunk holds the old launch arguments
-        (void)hipGraphExecDestroy(b->graph_exec);
-        b->graph_exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    drop_graph(b);
     return GOM_OK;
 }
 

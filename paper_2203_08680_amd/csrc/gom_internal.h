@@ -335,7 +335,15 @@ struct BclPlan {
     int32_t count, kmax, grid;
     int32_t ppw;           // consecutive class positions per wave (1..kBclPositions); a tile
                            // is kBclWaves * ppw positions
+    // bit-sliced form (k_bcl_gs_sweep): lanes = slots (one or two a set, see gs_slots) over
+    // all instances' classes at a position; `tiles` then holds slot prefix sums
+    int32_t gs;            // 1: bit-sliced form
+    int32_t gs_wb;         // its weight bits (7 or 13)
+    int32_t gs_grid;       // blocks per launch (enough for every position's slots)
+    uint64_t *nzm;         // [i]: solutions whose neutral steps are accepted (always, or those
+                           // that differ from the elitist), written by k_bcl_order
 };
+
 
 // Kernel launchers (gom_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_init_population(uint64_t *P, uint64_t *O, int64_t *fit, DevState *st,
@@ -374,10 +382,20 @@ constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
 // kGsMaxWeightBits bits; classes of fewer than kGsMinSets sets keep the class sweep (one set
 // per lane leaves a small class too few waves).
 constexpr int kGsThreads = 256;
+constexpr int kGsEntryBatch = 8;   // dependent-edge entries whose loads are issued together
 constexpr int kGsMaxMembers = 9;
 constexpr int64_t kGsMaxWeightSum = 16383;
 constexpr int kGsMaxWeightBits = 13;
 constexpr int32_t kGsMinSets = 8192;
+// Instances of a batch that one block of the bit-sliced class launch can span (its slots, at
+// least 16 per instance present, aligned to 16).
+constexpr int kGsBlockInsts = kGsThreads / 16 + 1;
+// Lane slots of a class of `csize` sets under the bit-sliced general sweep (a multiple of
+// 16): 16 slots hold 8 positions x 2 halves (population above 32) or 16 positions.
+__host__ __device__ __forceinline__ int gs_slots(int csize, int halves) {
+    const int per = 16 / halves;  // positions per 16 slots
+    return (csize + per - 1) / per * 16;
+}
 hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bits, int max_grid,
                                  hipStream_t s, KernelEvents ev);
 // Fused form (one cooperative launch per generation; see FusedArgs).

@@ -1530,13 +1530,14 @@ __global__ __launch_bounds__(kSwarThreads) void k_uni_swar_sweep(SweepArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Bit-sliced sweep of one colour class of small general sets (lane = set, the solutions of a
-// set as the bits of 32-bit words, in two halves of 32).  Each pair gets the step of the
-// class sweep (k_class_sweep): the donor set D, the draw's donor, the changed members C, the
-// partial evaluation and the acceptance rule, with the same Philox draws.  Per half:
-//   1. draws: the eight lanes of class positions 8j..8j+7 share one Philox call per solution
-//      (counter (g, c, i, j)); lane l computes the calls of solutions l, l+8, l+16, l+24 of
-//      the half and leaves their words in LDS, where each lane reads its own 16-bit field;
+// Bit-sliced sweep of one colour class of small general sets (lane = one half of a set's
+// solutions as the bits of a 32-bit word: two lanes a set when the population is above 32,
+// else one).  Each pair gets the step of the class sweep (k_class_sweep): the donor set D,
+// the draw's donor, the changed members C, the partial evaluation and the acceptance rule,
+// with the same Philox draws.  Per lane:
+//   1. draws: the eight lanes of class positions 8j..8j+7 (one half) share one Philox call per
+//      solution (counter (g, c, i, j)); lane l computes the calls of solutions l, l+8, l+16,
+//      l+24 of the half and leaves their words in LDS, where each lane reads its own field;
 //   2. per solution i (a loop): D_i = OR over the members of (P[u] xor O_i[u] spread), the
 //      donor d = the r-th set bit of D_i, and bit i of each member's change mask F_k (the
 //      donor's gene differs from O_i's);
@@ -1562,14 +1563,200 @@ __device__ __forceinline__ uint32_t xor3(uint32_t x, uint32_t y, uint32_t z) {
 }
 
 template <int M, int WB>
+struct GsLds {
+    uint4 rnd[kGsThreads / 8][32];     // Philox words: lane group of eight, solution of the half
+    uint32_t fo[2][M][kGsThreads];     // F_k and O half-words by member slot, one column a lane
+};
+
+// Work item of lane slot q (a multiple-of-16 offset into a class's slots): 16 consecutive
+// slots hold 8 positions x 2 halves (population above 32: slots 0-7 half 0, 8-15 half 1) or
+// 16 positions (one half).  Every aligned group of 8 slots then shares (position / 8, half),
+// i.e. one Philox call per solution, and slot & 7 is the position's field of that call.
+struct GsItem {
+    int p, h;
+};
+__device__ __forceinline__ GsItem gs_item(int q, int halves) {
+    const int g16 = q >> 4, r = q & 15;
+    return halves == 2 ? GsItem{g16 * 8 + (r & 7), r >> 3} : GsItem{g16 * 16 + r, 0};
+}
+
+// Draws of the lane's group: lane j of the group (j = slot & 7) computes the calls of
+// solutions 32h + j + 8t, t < 4, with counter (g, c, i, p / 8), the group's common values.
+__device__ __forceinline__ void gs_draws(uint4 (*rnd)[32], int tid, uint64_t seed, int gen,
+                                         int cls, int p, int h) {
+    const int j = tid & 7;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int ii = j + 8 * t;
+        const U32x4 q = philox(seed, (uint32_t)gen, (uint32_t)cls, (uint32_t)(32 * h + ii),
+                               (uint32_t)(p >> 3));
+        rnd[tid >> 3][ii] = make_uint4(q.x, q.y, q.z, q.w);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The step of one lane: half h of the set whose record is R (act: the lane has a set; n_i:
+// solutions of the half, 32h .. 32h + n_i - 1).  Member words are stored with the accepted
+// changes; fit_add(ii, delta) receives each accepted solution's fitness change.
+template <int M, int WB, class FitAdd>
+__device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t *P, uint64_t *O,
+                                        const int32_t *R, bool act, int h, int n_i,
+                                        uint64_t popm, uint32_t nzh, FitAdd fit_add,
+                                        uint32_t &n_eval, uint32_t &n_acc, uint64_t &accm) {
+    int nm = 0, nd = 0;
+    int u[M];
+    uint64_t pw[M];
+    uint32_t oh[M];
+    if (act) {
+        const int4 h0 = reinterpret_cast<const int4 *>(R)[0];
+        const int4 h1 = reinterpret_cast<const int4 *>(R)[1];
+        const int4 h2 = reinterpret_cast<const int4 *>(R)[2];
+        const int4 h3 = reinterpret_cast<const int4 *>(R)[3];
+        nm = h0.x;
+        nd = h0.y;
+        const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
+                                    h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
+#pragma unroll
+        for (int k = 0; k < M; ++k) u[k] = k < nm ? mem[k] : -1;
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k) u[k] = -1;
+    }
+    const uint32_t *O32 = reinterpret_cast<const uint32_t *>(O);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        pw[k] = u[k] >= 0 ? P[u[k]] : 0ull;
+        oh[k] = u[k] >= 0 ? O32[2 * (size_t)u[k] + h] : 0u;
+    }
+    const uint16_t *rb = reinterpret_cast<const uint16_t *>(&L.rnd[tid >> 3][0]) + (tid & 7);
+    // donors and change masks, one solution at a time
+    uint32_t F[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) F[k] = 0u;
+    uint32_t has = 0u;
+#pragma unroll 2
+    for (int ii = 0; ii < n_i; ++ii) {
+        const int i = 32 * h + ii;
+        uint32_t dlo = 0u, dhi = 0u;
+        uint32_t s[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            s[k] = (uint32_t)__builtin_amdgcn_sbfe((int)oh[k], ii, 1u);
+            dlo |= (uint32_t)pw[k] ^ s[k];
+            dhi |= (uint32_t)(pw[k] >> 32) ^ s[k];
+        }
+        const uint64_t cand = popm & ~(1ull << i);
+        dlo &= (uint32_t)cand;
+        dhi &= (uint32_t)(cand >> 32);
+        const uint32_t cnt = (uint32_t)__popc(dlo) + (uint32_t)__popc(dhi);
+        const uint32_t h16 = rb[8 * ii];
+        const uint32_t d = cnt ? select_bit(((uint64_t)dhi << 32) | dlo, (h16 * cnt) >> 16) : 0u;
+        const uint32_t any = cnt ? 1u : 0u;
+        has |= any << ii;
+#pragma unroll
+        for (int k = 0; k < M; ++k) F[k] |= ((bit_of(pw[k], d) ^ s[k]) & any) << ii;
+    }
+    // fitness changes of the half's solutions, bit-sliced
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        L.fo[0][k][tid] = F[k];
+        L.fo[1][k][tid] = oh[k];
+    }
+    uint32_t S[kGsPlanes], C[kGsPlanes];
+#pragma unroll
+    for (int j = 0; j < kGsPlanes; ++j) S[j] = C[j] = 0u;
+    int32_t W = 0;
+    // entries in batches of kGsEntryBatch: the batch's record words, then its far-end words,
+    // are requested before any is used (few waves share a SIMD, so each dependent round trip
+    // would otherwise be paid in full)
+    for (int e0 = 0; e0 < nd; e0 += kGsEntryBatch) {
+        int2 enb[kGsEntryBatch];
+        uint32_t ovb[kGsEntryBatch];
+#pragma unroll
+        for (int q = 0; q < kGsEntryBatch; ++q)  // past nd: inside, 0-0, weight 0
+            enb[q] = e0 + q < nd ? reinterpret_cast<const int2 *>(R + 16)[e0 + q]
+                                 : make_int2((int)0x80000000, 0);
+#pragma unroll
+        for (int q = 0; q < kGsEntryBatch; ++q)
+            ovb[q] = enb[q].x >= 0 ? O32[2 * (size_t)((uint32_t)enb[q].x & kSmallIdx) + h] : 0u;
+#pragma unroll
+        for (int q = 0; q < kGsEntryBatch; ++q) {
+            const int2 en = enb[q];
+            const uint32_t x = (uint32_t)en.x;
+            const int ka = (int)((x >> kSmallPosShift) & 15u);
+            const uint32_t y = x & kSmallIdx;
+            const bool inside = (int32_t)x < 0;
+            const int kb = inside ? (int)y : ka;
+            const uint32_t fa = L.fo[0][ka][tid], oa = L.fo[1][ka][tid];
+            const uint32_t fb = L.fo[0][kb][tid], ob = L.fo[1][kb][tid];
+            const uint32_t ov = inside ? ob : ovb[q];
+            const uint32_t X = inside ? fa ^ fb : fa;
+            const uint32_t cut = oa ^ ov;
+            const uint32_t aw = (uint32_t)(en.y < 0 ? -en.y : en.y);
+            const uint32_t A = X & (en.y > 0 ? ~cut : cut);
+            const uint32_t nX = ~X;
+            W += (int32_t)aw;
+            // add |w| * (2 A + nX): plane j gets (A & bit j-1 of |w|) | (nX & bit j); a full
+            // adder per plane, from the top so that C[j + 1] is read before plane j's carry
+            // replaces it
+            uint32_t wb[WB + 1];
+#pragma unroll
+            for (int j = 0; j < WB; ++j) wb[j] = (uint32_t)__builtin_amdgcn_sbfe((int)aw, j, 1u);
+            wb[WB] = 0u;
+#pragma unroll
+            for (int j = kGsPlanes - 1; j >= 0; --j) {
+                uint32_t z = 0u;
+                if (j <= WB) z = (j ? A & wb[j - 1] : 0u) | (nX & wb[j]);
+                const uint32_t sj = S[j], cj = C[j];
+                S[j] = xor3(sj, cj, z);
+                if (j + 1 < kGsPlanes) C[j + 1] = maj3(sj, cj, z);
+            }
+            C[0] = 0u;
+        }
+    }
+    // T = S + C against W: greater / equal, all solutions at once
+    uint32_t T[kGsPlanes];
+    uint32_t carry = 0u;
+#pragma unroll
+    for (int j = 0; j < kGsPlanes; ++j) {
+        T[j] = xor3(S[j], C[j], carry);
+        carry = maj3(S[j], C[j], carry);
+    }
+    uint32_t gt = 0u, eq = ~0u;
+#pragma unroll
+    for (int j = kGsPlanes - 1; j >= 0; --j) {
+        const uint32_t wj = (uint32_t)__builtin_amdgcn_sbfe(W, j, 1u);
+        gt |= eq & T[j] & ~wj;
+        eq &= ~(T[j] ^ wj);
+    }
+    const uint32_t acc = has & (gt | (eq & nzh));
+    uint32_t *W32 = reinterpret_cast<uint32_t *>(O);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const uint32_t m = F[k] & acc;
+        if (u[k] >= 0 && m) W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
+    }
+    for (uint32_t m = acc; m; m &= m - 1) {
+        const int ii = __builtin_ctz(m);
+        int32_t t = 0;
+#pragma unroll
+        for (int j = 0; j < kGsPlanes; ++j) t |= (int32_t)((T[j] >> ii) & 1u) << j;
+        fit_add(ii, (int64_t)(t - W));
+    }
+    n_eval += (uint32_t)__popc(has);
+    n_acc += (uint32_t)__popc(acc);
+    accm |= (uint64_t)acc << (32 * h);
+}
+
+// One colour class (per-class launch).  Blocks stride over tiles of kGsThreads slots.
+template <int M, int WB>
 __global__ __launch_bounds__(kGsThreads) void k_gen_swar_sweep(SweepArgs a) {
     static_assert(M >= 1 && M <= kSmallSet && WB >= 1 && WB + 1 < kGsPlanes, "shape");
-    __shared__ uint4 rnd[kGsThreads / 8][32];        // Philox words: lane group, solution
-    __shared__ uint32_t fo[2][M][kGsThreads];        // F_k and O half-words by member slot
+    __shared__ GsLds<M, WB> L;
     __shared__ unsigned long long fa[64];
     __shared__ uint32_t redc[2][kGsThreads / 64];
     const int tid = (int)threadIdx.x;
-    const int grp = tid >> 3, fl = tid & 7;
     const uint64_t mism = a.stripes[tid & 63].mism;
     const bool live = a.st->elite_fitness < a.target;
     const uint64_t popm = a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull);
@@ -1578,160 +1765,22 @@ __global__ __launch_bounds__(kGsThreads) void k_gen_swar_sweep(SweepArgs a) {
     __syncthreads();
     uint32_t n_eval = 0, n_acc = 0;
     uint64_t accm = 0;  // solutions with an accepted step (tracking mode)
-    const uint32_t *O32 = reinterpret_cast<const uint32_t *>(a.O);
-    uint32_t *W32 = reinterpret_cast<uint32_t *>(a.O);
     const int halves = a.N > 32 ? 2 : 1;
+    const int slots = gs_slots(a.csize, halves);
     for (int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-         live && tile * kGsThreads < a.csize; tile += gridDim.x) {
-        const int p = tile * kGsThreads + tid;  // class position
-        const bool act = p < a.csize;
-        int nm = 0, nd = 0;
-        int u[M];
-        uint64_t pw[M], ow[M];
-        const int32_t *R = nullptr;
-        if (act) {
-            R = a.rstride ? a.recs + a.rbase + p * a.rstride : a.recs + a.roff[a.cbase + p];
-            const int4 h0 = reinterpret_cast<const int4 *>(R)[0];
-            const int4 h1 = reinterpret_cast<const int4 *>(R)[1];
-            const int4 h2 = reinterpret_cast<const int4 *>(R)[2];
-            const int4 h3 = reinterpret_cast<const int4 *>(R)[3];
-            nm = h0.x;
-            nd = h0.y;
-            const int mem[kSmallSet] = {h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x,
-                                        h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
-#pragma unroll
-            for (int k = 0; k < M; ++k) u[k] = k < nm ? mem[k] : -1;
-        } else {
-#pragma unroll
-            for (int k = 0; k < M; ++k) u[k] = -1;
-        }
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            pw[k] = u[k] >= 0 ? a.P[u[k]] : 0ull;
-            ow[k] = u[k] >= 0 ? a.O[u[k]] : 0ull;
-        }
-        for (int h = 0; h < halves; ++h) {
-            // 1. draws of this half's solutions for the lane's group of eight positions
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int ii = fl + 8 * t;
-                const U32x4 q = philox(a.seed, (uint32_t)a.gen, (uint32_t)a.cls,
-                                       (uint32_t)(32 * h + ii), (uint32_t)(p >> 3));
-                rnd[grp][ii] = make_uint4(q.x, q.y, q.z, q.w);
-            }
-            __builtin_amdgcn_wave_barrier();
-            const uint16_t *rb = reinterpret_cast<const uint16_t *>(&rnd[grp][0]) + fl;
-            // 2. donors and change masks, one solution at a time
-            uint32_t oh[M], F[M];
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                oh[k] = h ? (uint32_t)(ow[k] >> 32) : (uint32_t)ow[k];
-                F[k] = 0u;
-            }
-            uint32_t has = 0u;
-            const int n_i = min(32, a.N - 32 * h);
-            for (int ii = 0; ii < n_i; ++ii) {
-                const int i = 32 * h + ii;
-                uint32_t dlo = 0u, dhi = 0u;
-                uint32_t s[M];
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    s[k] = (uint32_t)__builtin_amdgcn_sbfe((int)oh[k], ii, 1u);
-                    dlo |= (uint32_t)pw[k] ^ s[k];
-                    dhi |= (uint32_t)(pw[k] >> 32) ^ s[k];
-                }
-                const uint64_t cand = popm & ~(1ull << i);
-                dlo &= (uint32_t)cand;
-                dhi &= (uint32_t)(cand >> 32);
-                const uint32_t cnt = (uint32_t)__popc(dlo) + (uint32_t)__popc(dhi);
-                const uint32_t h16 = rb[8 * ii];
-                const uint32_t d = cnt ? select_bit(((uint64_t)dhi << 32) | dlo,
-                                                    (h16 * cnt) >> 16) : 0u;
-                has |= (cnt ? 1u : 0u) << ii;
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const uint32_t fk = (bit_of(pw[k], d) ^ s[k]) & (cnt ? 1u : 0u);
-                    F[k] |= fk << ii;
-                }
-            }
-            // 3. fitness changes, bit-sliced over the half's solutions
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                fo[0][k][tid] = F[k];
-                fo[1][k][tid] = oh[k];
-            }
-            uint32_t S[kGsPlanes], C[kGsPlanes];
-#pragma unroll
-            for (int j = 0; j < kGsPlanes; ++j) S[j] = C[j] = 0u;
-            int32_t W = 0;
-            for (int e = 0; e < nd; ++e) {
-                const int2 en = reinterpret_cast<const int2 *>(R + 16)[e];
-                const uint32_t x = (uint32_t)en.x;
-                const int ka = (int)((x >> kSmallPosShift) & 15u);
-                const uint32_t y = x & kSmallIdx;
-                const bool inside = (int32_t)x < 0;
-                const int kb = inside ? (int)y : ka;
-                const uint32_t fa_ = fo[0][ka][tid], oa = fo[1][ka][tid];
-                const uint32_t fb = fo[0][kb][tid], ob = fo[1][kb][tid];
-                const uint32_t ov = inside ? ob : O32[2 * (size_t)y + h];
-                const uint32_t X = inside ? fa_ ^ fb : fa_;
-                const uint32_t cut = oa ^ ov;
-                const uint32_t aw = (uint32_t)(en.y < 0 ? -en.y : en.y);
-                const uint32_t A = X & (en.y > 0 ? ~cut : cut);
-                const uint32_t nX = ~X;
-                W += (int32_t)aw;
-                // add |w| * (2 A + nX): plane j gets (A & bit j-1 of |w|) | (nX & bit j); a
-                // full adder per plane, from the top so that C[j + 1] is read before it is
-                // replaced by plane j's carry
-                uint32_t wb[WB + 1];
-#pragma unroll
-                for (int j = 0; j < WB; ++j)
-                    wb[j] = (uint32_t)__builtin_amdgcn_sbfe((int)aw, j, 1u);
-                wb[WB] = 0u;
-#pragma unroll
-                for (int j = kGsPlanes - 1; j >= 0; --j) {
-                    uint32_t z = 0u;
-                    if (j <= WB) z = (j ? A & wb[j - 1] : 0u) | (nX & wb[j]);
-                    const uint32_t sj = S[j], cj = C[j];
-                    S[j] = xor3(sj, cj, z);
-                    if (j + 1 < kGsPlanes) C[j + 1] = maj3(sj, cj, z);
-                }
-                C[0] = 0u;
-            }
-            // 4. T = S + C against W: greater / equal, all solutions at once
-            uint32_t T[kGsPlanes];
-            uint32_t carry = 0u;
-#pragma unroll
-            for (int j = 0; j < kGsPlanes; ++j) {
-                T[j] = xor3(S[j], C[j], carry);
-                carry = maj3(S[j], C[j], carry);
-            }
-            uint32_t gt = 0u, eq = ~0u;
-#pragma unroll
-            for (int j = kGsPlanes - 1; j >= 0; --j) {
-                const uint32_t wj = (uint32_t)__builtin_amdgcn_sbfe(W, j, 1u);
-                gt |= eq & T[j] & ~wj;
-                eq &= ~(T[j] ^ wj);
-            }
-            const uint32_t nzh = (uint32_t)(nz >> (32 * h));
-            const uint32_t acc = has & (gt | (eq & nzh));
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const uint32_t m = F[k] & acc;
-                if (u[k] >= 0 && m) W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
-            }
-            for (uint32_t m = acc; m; m &= m - 1) {
-                const int ii = __builtin_ctz(m);
-                int32_t t = 0;
-#pragma unroll
-                for (int j = 0; j < kGsPlanes; ++j) t |= (int32_t)((T[j] >> ii) & 1u) << j;
-                atomicAdd(&fa[32 * h + ii], (unsigned long long)(long long)(t - W));
-            }
-            n_eval += (uint32_t)__popc(has);
-            n_acc += (uint32_t)__popc(acc);
-            accm |= (uint64_t)acc << (32 * h);
-        }
+         live && tile * kGsThreads < slots; tile += gridDim.x) {
+        const GsItem it = gs_item(tile * kGsThreads + tid, halves);
+        const bool act = it.p < a.csize;
+        const int32_t *R = !act ? nullptr
+                           : a.rstride ? a.recs + a.rbase + it.p * a.rstride
+                                       : a.recs + a.roff[a.cbase + it.p];
+        gs_draws(L.rnd, tid, a.seed, a.gen, a.cls, it.p, it.h);
+        const int n_i = min(32, a.N - 32 * it.h);
+        gs_step<M, WB>(L, tid, a.P, a.O, R, act, it.h, n_i, popm, (uint32_t)(nz >> (32 * it.h)),
+                       [&](int ii, int64_t dl) {
+                           atomicAdd(&fa[32 * it.h + ii], (unsigned long long)dl);
+                       },
+                       n_eval, n_acc, accm);
     }
     const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
     const uint64_t am = a.mode == kSweepGomTrack ? wave_or64(accm) : 0ull;
@@ -2212,12 +2261,17 @@ __global__ __launch_bounds__(kEpiThreads) void k_batch_vertex(const BatchInst *i
 // sweep.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bcl_order(const BclInst *insts, uint16_t *order,
-                                                   int kmax) {
+                                                   int kmax, uint64_t *nzm) {
     __shared__ uint16_t draw[2048];
     const BclInst &I = insts[blockIdx.x];
     uint16_t *ord = order + (size_t)blockIdx.x * kmax;
     const int gen = I.st->generation;
     const bool fixed = I.order_fixed != 0;
+    if (nzm && threadIdx.x < 64) {  // (wave 0, every lane) the neutral-step mask
+        const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
+        const uint64_t m = wave_or64(I.stripes[threadIdx.x].mism);
+        if (threadIdx.x == 0) nzm[blockIdx.x] = I.always ? popm : (m & popm);
+    }
     for (int t = threadIdx.x; t < I.k; t += 256) {
         ord[t] = (uint16_t)t;
         if (!fixed && t >= 1) {
@@ -2239,7 +2293,7 @@ __global__ __launch_bounds__(256) void k_bcl_order(const BclInst *insts, uint16_
 // over the instances; the total follows the last instance.
 __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const uint16_t *order,
                                                    int32_t *tiles, int count, int kmax,
-                                                   int tile) {
+                                                   int tile, int gs) {
     __shared__ int32_t part[256];
     const int t = blockIdx.x;
     int32_t *row = tiles + (size_t)t * (count + 1);
@@ -2252,7 +2306,7 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
             if (t < I.k && I.st->elite_fitness < I.target) {
                 const int c = order[(size_t)i * kmax + t];
                 const int32_t cs = I.class_ptr[c + 1] - I.class_ptr[c];
-                n = (cs + tile - 1) / tile;
+                n = gs ? gs_slots(cs, I.N > 32 ? 2 : 1) : (cs + tile - 1) / tile;
             }
         }
         part[threadIdx.x] = n;
@@ -2341,6 +2395,84 @@ __global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
             if (n_eval) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)n_eval);
             if (n_acc) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)n_acc);
         }
+    }
+}
+
+// Bit-sliced form of the batched class launch at position t: lane = slot over the slots of
+// every instance's class pi_i[t] (gs_slots per instance, prefix sums in `tiles`), one or two
+// a set as in k_gen_swar_sweep; a block's slots may span several instances (each lane finds
+// its own), whose fitness changes and counts it gathers in LDS and adds to their stripes at
+// the end.  Eight aligned slots always belong to one instance, position group and half.
+template <int WB>
+__global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) {
+    constexpr int M = kBclMaxMembers;
+    __shared__ int32_t srow[kBclRowLds + 1];
+    __shared__ GsLds<M, WB> L;
+    __shared__ unsigned long long fa[kGsBlockInsts][64];
+    __shared__ uint32_t cnt[kGsBlockInsts][2];
+    const int tid = (int)threadIdx.x;
+    const int32_t *row = pl.tiles + (size_t)t * (pl.count + 1);
+    const bool in_lds = pl.count <= kBclRowLds;
+    if (in_lds)
+        for (int q = tid; q <= pl.count; q += kGsThreads) srow[q] = row[q];
+    for (int q = tid; q < kGsBlockInsts * 64; q += kGsThreads) (&fa[0][0])[q] = 0ull;
+    if (tid < kGsBlockInsts * 2) (&cnt[0][0])[tid] = 0u;
+    __syncthreads();
+    const int32_t *rs = in_lds ? srow : row;
+    const int32_t total = rs[pl.count];
+    const int base = (int)blockIdx.x * kGsThreads;
+    if (base >= total) return;  // (uniform over the block)
+    // the instance of a slot: the last one whose first slot is <= q
+    auto find = [&](int q) {
+        int lo = 0, hi = pl.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rs[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    const int b0 = find(base);
+    const int q = base + tid;
+    const bool slot_ok = q < total;
+    const int b = slot_ok ? find(q) : b0;
+    const BclInst &I = pl.insts[b];
+    const int halves = I.N > 32 ? 2 : 1;
+    const GsItem it = gs_item(q - rs[b], halves);
+    const int c = pl.order[(size_t)b * pl.kmax + t];
+    const int cbase = I.class_ptr[c];
+    const int csize = I.class_ptr[c + 1] - cbase;
+    const bool act = slot_ok && it.p < csize;
+    const int2 cr = I.class_rec[c];
+    const int32_t *R = !act ? nullptr
+                       : cr.y ? I.recs + cr.x + it.p * cr.y : I.recs + I.roff[cbase + it.p];
+    gs_draws(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h);
+    const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
+    const int rel = b - b0;
+    uint32_t n_eval = 0, n_acc = 0;
+    uint64_t accm = 0;
+    gs_step<M, WB>(L, tid, I.P, I.O, R, act, it.h, act ? min(32, I.N - 32 * it.h) : 0, popm,
+                   (uint32_t)(pl.nzm[b] >> (32 * it.h)),
+                   [&](int ii, int64_t dl) {
+                       atomicAdd(&fa[rel][32 * it.h + ii], (unsigned long long)dl);
+                   },
+                   n_eval, n_acc, accm);
+    if (n_eval) atomicAdd(&cnt[rel][0], n_eval);
+    if (n_acc) atomicAdd(&cnt[rel][1], n_acc);
+    __syncthreads();
+    const int span = find(min(base + kGsThreads, total) - 1) - b0 + 1;  // instances present
+    const int stripe = (int)blockIdx.x % kStripes;
+    for (int e = tid; e < span * 64; e += kGsThreads) {
+        const unsigned long long v = fa[e >> 6][e & 63];
+        if (v) atomicAdd((unsigned long long *)&pl.insts[b0 + (e >> 6)].stripes[stripe].fit[e & 63],
+                         v);
+    }
+    if (tid < span) {
+        Stripe *sp = pl.insts[b0 + tid].stripes + stripe;
+        if (cnt[tid][0]) atomicAdd((unsigned long long *)&sp->evaluated,
+                                   (unsigned long long)cnt[tid][0]);
+        if (cnt[tid][1]) atomicAdd((unsigned long long *)&sp->accepted,
+                                   (unsigned long long)cnt[tid][1]);
     }
 }
 
@@ -2606,7 +2738,7 @@ hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bit
     if (members < 1 || members > kGsMaxMembers || weight_bits < 1 ||
         weight_bits > kGsMaxWeightBits || a.N > 64)
         return hipErrorInvalidValue;
-    int grid = (a.csize + kGsThreads - 1) / kGsThreads;
+    int grid = (gs_slots(a.csize, a.N > 32 ? 2 : 1) + kGsThreads - 1) / kGsThreads;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) return hipSuccess;
     const dim3 gd(grid), bd(kGsThreads);
@@ -2740,20 +2872,29 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
     }
     if (n_bcl > 0) {
         if (bcl.kmax > 2048 || bcl.grid < 1) return hipErrorInvalidValue;
+        if (bcl.gs && (!bcl.nzm || bcl.gs_grid < 1 || (bcl.gs_wb != 7 && bcl.gs_wb != 13)))
+            return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_bcl_order, dim3(bcl.count), dim3(256), 0, s, bcl.insts, bcl.order,
-                           bcl.kmax);
+                           bcl.kmax, bcl.gs ? bcl.nzm : nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (bcl.ppw < 1 || bcl.ppw > kBclPositions) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_bcl_tiles, dim3(bcl.kmax), dim3(256), 0, s, bcl.insts, bcl.order,
-                           bcl.tiles, bcl.count, bcl.kmax, kBclWaves * bcl.ppw);
+                           bcl.tiles, bcl.count, bcl.kmax, kBclWaves * bcl.ppw, bcl.gs);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         for (int t = 0; t < bcl.kmax; ++t) {
             KernelEvents gev;
             gev.start = n_groups == 0 && t == 0 ? ev.start : nullptr;
             gev.stop = t == bcl.kmax - 1 ? ev.stop : nullptr;
-            launch_timed(k_bcl_sweep, dim3(bcl.grid), dim3(kBclThreads), 0, s, gev, bcl, t);
+            if (!bcl.gs)
+                launch_timed(k_bcl_sweep, dim3(bcl.grid), dim3(kBclThreads), 0, s, gev, bcl, t);
+            else if (bcl.gs_wb == 7)
+                launch_timed(k_bcl_gs_sweep<7>, dim3(bcl.gs_grid), dim3(kGsThreads), 0, s, gev,
+                             bcl, t);
+            else
+                launch_timed(k_bcl_gs_sweep<13>, dim3(bcl.gs_grid), dim3(kGsThreads), 0, s, gev,
+                             bcl, t);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -38,7 +38,8 @@ EXPORTED = (
     "gom_batch_set_graph", "gom_batch_reseed", "gom_batch_timing_enable",
     "gom_batch_timing_read", "gom_batch_set_narrow", "gom_batch_get_narrow",
     "gom_batch_autotune", "gom_batch_set_class_launch", "gom_batch_get_class_launch",
-    "gom_batch_set_class_positions",
+    "gom_batch_set_class_positions", "gom_batch_set_class_bitsliced",
+    "gom_batch_get_class_bitsliced",
     "gom_batch_state", "gom_batch_free", "gom_server_create", "gom_server_submit",
     "gom_server_step", "gom_server_results", "gom_server_info", "gom_server_free",
     "gom_server_set_large",
@@ -151,6 +152,8 @@ def lib() -> C.CDLL:
         "gom_batch_set_class_launch": (C.c_int, [_vp, _i64, _vp]),
         "gom_batch_get_class_launch": (C.c_int, [_vp, _P(_i64), _P(_i32), _P(_i32), _P(_i32)]),
         "gom_batch_set_class_positions": (C.c_int, [_vp, _i32]),
+        "gom_batch_set_class_bitsliced": (C.c_int, [_vp, C.c_int]),
+        "gom_batch_get_class_bitsliced": (C.c_int, [_vp, _P(C.c_int), _P(C.c_int)]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
         "gom_batch_state": (C.c_int, [_vp, _i32, _P(_vp)]),
@@ -694,6 +697,18 @@ def gom_batch_get_class_launch(b: GomBatch):
     _check(lib().gom_batch_get_class_launch(b.handle, C.byref(m), C.byref(n), C.byref(k),
                                             C.byref(w)))
     return m.value, n.value, k.value, w.value
+
+
+def gom_batch_set_class_bitsliced(b: GomBatch, enabled: bool) -> None:
+    """Bit-sliced form of the batched class launches (on by default where available)."""
+    _check(lib().gom_batch_set_class_bitsliced(b.handle, 1 if enabled else 0))
+
+
+def gom_batch_get_class_bitsliced(b: GomBatch):
+    """(in use, available) of the bit-sliced form of the batched class launches."""
+    en, av = C.c_int(), C.c_int()
+    _check(lib().gom_batch_get_class_bitsliced(b.handle, C.byref(en), C.byref(av)))
+    return bool(en.value), bool(av.value)
 
 
 def gom_batch_set_class_positions(b: GomBatch, positions_per_wave: int) -> None:

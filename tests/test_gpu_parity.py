@@ -1102,15 +1102,34 @@ def test_batch_admits_instances_beyond_resident(cuda):
         assert gom.gom_state_hash(bt.state(b)) == ref.hash(), f"instance {b} vs oracle"
 
 
+def test_batch_class_bitsliced_availability(cuda):
+    """The bit-sliced form of the batched class launches needs every class-launched
+    instance's |w| within 13 bits: one instance with weights up to 10^5 makes it unavailable
+    (the lane-per-solution form then runs, and matches the solo runs)."""
+    gs = [workloads.configuration_model(600, 4, seed=50, weights="uniform", w_lo=1, w_hi=100),
+          workloads.configuration_model(700, 4, seed=51, weights="uniform", w_lo=1,
+                                        w_hi=100_000)]
+    insts = [gom.Instance(g.n, g.u, g.v, g.w, 1) for g in gs]
+    bt = gom.gom_batch_init(insts, [20, 36], [1, 2], [1 << 62] * 2)
+    gom.gom_batch_set_class_launch(bt, 0)
+    assert gom.gom_batch_get_class_bitsliced(bt) == (False, False)
+    gom.gom_batch_run(bt, 4)
+    for b, inst in enumerate(insts):
+        st = inst.state(pop=[20, 36][b], seed=[1, 2][b])
+        gom.gom_run_to_target(st, 1 << 62, 4)
+        assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), b
+
+
+@pytest.mark.parametrize("form", ["bitsliced", "lanes"])
 @pytest.mark.parametrize("graph", [True, False], ids=["graph", "direct"])
-def test_batch_class_launches(cuda, graph):
+def test_batch_class_launches(cuda, graph, form):
     """Neighbourhood instances swept by the batched class launches (one launch per class
-    position covering every such instance, lane = solution) beside univariate instances in
-    resident blocks: each instance equals its solo run, populations 2 to 64 (inactive lanes),
-    degree 3 to 8 neighbourhoods and tori; with graph chunks or direct launches, across calls
-    and a reseed; the small ones equal the oracle; switching the assignment mid-run keeps
-    every trajectory."""
-    print(f"case batch class launches graph={graph}", flush=True)
+    position covering every such instance; bit-sliced, or lane = solution) beside univariate
+    instances in resident blocks: each instance equals its solo run, populations 2 to 64
+    (inactive lanes, one or two halves), degree 3 to 8 neighbourhoods and tori; with graph
+    chunks or direct launches, across calls and a reseed; the small ones equal the oracle;
+    switching the assignment and the form mid-run keeps every trajectory."""
+    print(f"case batch class launches graph={graph} form={form}", flush=True)
     gs = [(workloads.configuration_model(900, 8, seed=30, weights="uniform", w_lo=1,
                                          w_hi=100), 1, 64),
           (workloads.torus(24, 1, 100, seed=31), 1, 17),
@@ -1127,14 +1146,19 @@ def test_batch_class_launches(cuda, graph):
     gom.gom_batch_set_class_launch(bt, 0)
     m, n_inst, launches, _ = gom.gom_batch_get_class_launch(bt)
     assert m == 0 and n_inst == 5 and launches >= 1
+    bits = form == "bitsliced"
+    gom.gom_batch_set_class_bitsliced(bt, bits)
+    assert gom.gom_batch_get_class_bitsliced(bt) == (bits, True)
     gom.gom_batch_set_class_positions(bt, 8)
     gom.gom_batch_run(bt, 5)
     gom.gom_batch_set_class_launch(bt, 1000)   # the two largest only
     gom.gom_batch_set_class_positions(bt, 1)
+    gom.gom_batch_set_class_bitsliced(bt, not bits)
     assert gom.gom_batch_get_class_launch(bt)[1] == 2
     gom.gom_batch_run(bt, 9)
     gom.gom_batch_set_class_launch(bt, 0)
     gom.gom_batch_set_class_positions(bt, 3)
+    gom.gom_batch_set_class_bitsliced(bt, bits)
     res, _ = gom.gom_batch_run(bt, 15)
     for b in range(len(gs)):
         st = insts[b].state(pop=pops[b], seed=seeds[b])
