@@ -2311,7 +2311,7 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
             if (s->class_wsum[c] > kGsMaxWeightSum) b->bcl_gs_ok = false;
         }
         if (s->N > 64) b->bcl_gs_ok = false;
-        slots += gs_slots(s->max_class, s->N > 32 ? 2 : 1);
+        slots += gs_slots_bcl(s->max_class, s->N > 32 ? 2 : 1);
     }
     if (wbits > kGsMaxWeightBits) b->bcl_gs_ok = false;
     b->bcl_gs_wb = wbits <= 7 ? 7 : 13;

@@ -383,6 +383,7 @@ constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
 // per lane leaves a small class too few waves).
 constexpr int kGsThreads = 256;
 constexpr int kGsEntryBatch = 8;   // dependent-edge entries whose loads are issued together
+constexpr int kGsEntryBatchBcl = 8;   // ... in the batched class launches
 constexpr int kGsMaxMembers = 9;
 constexpr int64_t kGsMaxWeightSum = 16383;
 constexpr int kGsMaxWeightBits = 13;
@@ -395,6 +396,13 @@ constexpr int kGsBlockInsts = kGsThreads / 16 + 1;
 __host__ __device__ __forceinline__ int gs_slots(int csize, int halves) {
     const int per = 16 / halves;  // positions per 16 slots
     return (csize + per - 1) / per * 16;
+}
+// ... in the batched class launches, where each half is split between two lanes: 8 positions
+// take 16 x halves slots; the count is rounded up to 32 so that every instance's slots start
+// at a multiple of 32 and a lane's partner (8 lanes away) is always in its wave.
+__host__ __device__ __forceinline__ int gs_slots_bcl(int csize, int halves) {
+    const int n = (csize + 7) / 8 * 16 * halves;
+    return (n + 31) / 32 * 32;
 }
 hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bits, int max_grid,
                                  hipStream_t s, KernelEvents ev);

@@ -1581,14 +1581,16 @@ __device__ __forceinline__ GsItem gs_item(int q, int halves) {
 }
 
 // Draws of the lane's group: lane j of the group (j = slot & 7) computes the calls of
-// solutions 32h + j + 8t, t < 4, with counter (g, c, i, p / 8), the group's common values.
+// solutions 32h + i0 + j + 8t, t < 4 / PARTS (i0 = 16 x the lane's part when a half is split
+// between two lanes), with counter (g, c, i, p / 8), the group's common values.
+template <int PARTS = 1>
 __device__ __forceinline__ void gs_draws(uint4 (*rnd)[32], int tid, uint64_t seed, int gen,
-                                         int cls, int p, int h) {
+                                         int cls, int p, int h, int i0 = 0) {
     const int j = tid & 7;
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int ii = j + 8 * t;
+    for (int t = 0; t < 4 / PARTS; ++t) {
+        const int ii = i0 + j + 8 * t;
         const U32x4 q = philox(seed, (uint32_t)gen, (uint32_t)cls, (uint32_t)(32 * h + ii),
                                (uint32_t)(p >> 3));
         rnd[tid >> 3][ii] = make_uint4(q.x, q.y, q.z, q.w);
@@ -1596,14 +1598,33 @@ __device__ __forceinline__ void gs_draws(uint4 (*rnd)[32], int tid, uint64_t see
     __builtin_amdgcn_wave_barrier();
 }
 
+// Work item of a batched class-launch slot, where each half of a set is split between two
+// lanes (parts): 8 positions take 8 x 2 x halves consecutive slots, in groups of 8 lanes of one
+// (half, part); the partner of a lane (the other part) is the lane 8 away.
+struct GsItem2 {
+    int p, h, pt;
+};
+__device__ __forceinline__ GsItem2 gs_item2(int q, int halves) {
+    const int lp = 2 * halves;              // lanes per position
+    const int g = q / (8 * lp), r = q % (8 * lp);
+    const int sub = r >> 3;
+    return GsItem2{g * 8 + (r & 7), halves == 2 ? sub >> 1 : 0, sub & 1};
+}
+
 // The step of one lane: half h of the set whose record is R (act: the lane has a set; n_i:
 // solutions of the half, 32h .. 32h + n_i - 1).  Member words are stored with the accepted
 // changes; fit_add(ii, delta) receives each accepted solution's fitness change.
-template <int M, int WB, class FitAdd>
+// PARTS = 2: the half is split between this lane and its partner 8 lanes away (part pt):
+// each draws the donors of 16 of the 32 solutions and sums half of the edges; they exchange
+// their change masks and their partial sums, then each commits alternate members and accounts
+// for its 16 solutions.
+template <int M, int WB, int EB, int PARTS = 1, class FitAdd>
 __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t *P, uint64_t *O,
                                         const int32_t *R, bool act, int h, int n_i,
                                         uint64_t popm, uint32_t nzh, FitAdd fit_add,
-                                        uint32_t &n_eval, uint32_t &n_acc, uint64_t &accm) {
+                                        uint32_t &n_eval, uint32_t &n_acc, uint64_t &accm,
+                                        int pt = 0) {
+    static_assert(PARTS == 1 || PARTS == 2, "parts");
     int nm = 0, nd = 0;
     int u[M];
     uint64_t pw[M];
@@ -1635,8 +1656,10 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
     for (int k = 0; k < M; ++k) F[k] = 0u;
     uint32_t has = 0u;
+    const int ii_lo = PARTS == 2 ? 16 * pt : 0;
+    const int ii_hi = PARTS == 2 ? min(n_i, 16 * pt + 16) : n_i;
 #pragma unroll 2
-    for (int ii = 0; ii < n_i; ++ii) {
+    for (int ii = ii_lo; ii < ii_hi; ++ii) {
         const int i = 32 * h + ii;
         uint32_t dlo = 0u, dhi = 0u;
         uint32_t s[M];
@@ -1657,6 +1680,11 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
         for (int k = 0; k < M; ++k) F[k] |= ((bit_of(pw[k], d) ^ s[k]) & any) << ii;
     }
+    if constexpr (PARTS == 2) {  // the partner's solutions' bits
+#pragma unroll
+        for (int k = 0; k < M; ++k) F[k] |= (uint32_t)__shfl_xor((int)F[k], 8, 64);
+        has |= (uint32_t)__shfl_xor((int)has, 8, 64);
+    }
     // fitness changes of the half's solutions, bit-sliced
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -1667,21 +1695,24 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
     for (int j = 0; j < kGsPlanes; ++j) S[j] = C[j] = 0u;
     int32_t W = 0;
-    // entries in batches of kGsEntryBatch: the batch's record words, then its far-end words,
-    // are requested before any is used (few waves share a SIMD, so each dependent round trip
+    // entries in batches of EB: the batch's record words, then its far-end words, are
+    // requested before any is used (few waves share a SIMD, so each dependent round trip
     // would otherwise be paid in full)
-    for (int e0 = 0; e0 < nd; e0 += kGsEntryBatch) {
-        int2 enb[kGsEntryBatch];
-        uint32_t ovb[kGsEntryBatch];
+    // (two parts: this lane's share of the entries)
+    const int e_lo = PARTS == 2 && pt ? (nd + 1) / 2 : 0;
+    const int e_hi = PARTS == 2 && !pt ? (nd + 1) / 2 : nd;
+    for (int e0 = e_lo; e0 < e_hi; e0 += EB) {
+        int2 enb[EB];
+        uint32_t ovb[EB];
 #pragma unroll
-        for (int q = 0; q < kGsEntryBatch; ++q)  // past nd: inside, 0-0, weight 0
-            enb[q] = e0 + q < nd ? reinterpret_cast<const int2 *>(R + 16)[e0 + q]
-                                 : make_int2((int)0x80000000, 0);
+        for (int q = 0; q < EB; ++q)  // past the share: inside, 0-0, weight 0
+            enb[q] = e0 + q < e_hi ? reinterpret_cast<const int2 *>(R + 16)[e0 + q]
+                                   : make_int2((int)0x80000000, 0);
 #pragma unroll
-        for (int q = 0; q < kGsEntryBatch; ++q)
+        for (int q = 0; q < EB; ++q)
             ovb[q] = enb[q].x >= 0 ? O32[2 * (size_t)((uint32_t)enb[q].x & kSmallIdx) + h] : 0u;
 #pragma unroll
-        for (int q = 0; q < kGsEntryBatch; ++q) {
+        for (int q = 0; q < EB; ++q) {
             const int2 en = enb[q];
             const uint32_t x = (uint32_t)en.x;
             const int ka = (int)((x >> kSmallPosShift) & 15u);
@@ -1715,6 +1746,25 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
             C[0] = 0u;
         }
     }
+    if constexpr (PARTS == 2) {  // add the partner's partial sum (two carry-save additions)
+        W += __shfl_xor(W, 8, 64);
+        uint32_t XS[kGsPlanes], XC[kGsPlanes];  // (both read before either lane changes its own)
+#pragma unroll
+        for (int j = 0; j < kGsPlanes; ++j) {
+            XS[j] = (uint32_t)__shfl_xor((int)S[j], 8, 64);
+            XC[j] = (uint32_t)__shfl_xor((int)C[j], 8, 64);
+        }
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int j = kGsPlanes - 1; j >= 0; --j) {
+                const uint32_t sj = S[j], cj = C[j], xj = pass ? XC[j] : XS[j];
+                S[j] = xor3(sj, cj, xj);
+                if (j + 1 < kGsPlanes) C[j + 1] = maj3(sj, cj, xj);
+            }
+            C[0] = 0u;
+        }
+    }
     // T = S + C against W: greater / equal, all solutions at once
     uint32_t T[kGsPlanes];
     uint32_t carry = 0u;
@@ -1735,18 +1785,22 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const uint32_t m = F[k] & acc;
-        if (u[k] >= 0 && m) W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
+        if ((PARTS == 1 || (k & 1) == pt) && u[k] >= 0 && m)
+            W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
     }
-    for (uint32_t m = acc; m; m &= m - 1) {
+    const uint32_t mine = PARTS == 1 ? acc : acc & (pt ? 0xFFFF0000u : 0x0000FFFFu);
+    for (uint32_t m = mine; m; m &= m - 1) {
         const int ii = __builtin_ctz(m);
         int32_t t = 0;
 #pragma unroll
         for (int j = 0; j < kGsPlanes; ++j) t |= (int32_t)((T[j] >> ii) & 1u) << j;
         fit_add(ii, (int64_t)(t - W));
     }
-    n_eval += (uint32_t)__popc(has);
-    n_acc += (uint32_t)__popc(acc);
-    accm |= (uint64_t)acc << (32 * h);
+    if (PARTS == 1 || pt == 0) {
+        n_eval += (uint32_t)__popc(has);
+        n_acc += (uint32_t)__popc(acc);
+        accm |= (uint64_t)acc << (32 * h);
+    }
 }
 
 // One colour class (per-class launch).  Blocks stride over tiles of kGsThreads slots.
@@ -1776,7 +1830,8 @@ __global__ __launch_bounds__(kGsThreads) void k_gen_swar_sweep(SweepArgs a) {
                                        : a.recs + a.roff[a.cbase + it.p];
         gs_draws(L.rnd, tid, a.seed, a.gen, a.cls, it.p, it.h);
         const int n_i = min(32, a.N - 32 * it.h);
-        gs_step<M, WB>(L, tid, a.P, a.O, R, act, it.h, n_i, popm, (uint32_t)(nz >> (32 * it.h)),
+        gs_step<M, WB, kGsEntryBatch>(L, tid, a.P, a.O, R, act, it.h, n_i, popm,
+                                      (uint32_t)(nz >> (32 * it.h)),
                        [&](int ii, int64_t dl) {
                            atomicAdd(&fa[32 * it.h + ii], (unsigned long long)dl);
                        },
@@ -2306,7 +2361,7 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
             if (t < I.k && I.st->elite_fitness < I.target) {
                 const int c = order[(size_t)i * kmax + t];
                 const int32_t cs = I.class_ptr[c + 1] - I.class_ptr[c];
-                n = gs ? gs_slots(cs, I.N > 32 ? 2 : 1) : (cs + tile - 1) / tile;
+                n = gs ? gs_slots_bcl(cs, I.N > 32 ? 2 : 1) : (cs + tile - 1) / tile;
             }
         }
         part[threadIdx.x] = n;
@@ -2412,6 +2467,11 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     __shared__ uint32_t cnt[kGsBlockInsts][2];
     const int tid = (int)threadIdx.x;
     const int32_t *row = pl.tiles + (size_t)t * (pl.count + 1);
+    // the grid covers the most slots any position can have: blocks past this position's
+    // slots end before touching LDS (uniform over the block)
+    const int32_t total = row[pl.count];
+    const int base = (int)blockIdx.x * kGsThreads;
+    if (base >= total) return;
     const bool in_lds = pl.count <= kBclRowLds;
     if (in_lds)
         for (int q = tid; q <= pl.count; q += kGsThreads) srow[q] = row[q];
@@ -2419,9 +2479,6 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     if (tid < kGsBlockInsts * 2) (&cnt[0][0])[tid] = 0u;
     __syncthreads();
     const int32_t *rs = in_lds ? srow : row;
-    const int32_t total = rs[pl.count];
-    const int base = (int)blockIdx.x * kGsThreads;
-    if (base >= total) return;  // (uniform over the block)
     // the instance of a slot: the last one whose first slot is <= q
     auto find = [&](int q) {
         int lo = 0, hi = pl.count - 1;
@@ -2438,7 +2495,7 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     const int b = slot_ok ? find(q) : b0;
     const BclInst &I = pl.insts[b];
     const int halves = I.N > 32 ? 2 : 1;
-    const GsItem it = gs_item(q - rs[b], halves);
+    const GsItem2 it = gs_item2(q - rs[b], halves);
     const int c = pl.order[(size_t)b * pl.kmax + t];
     const int cbase = I.class_ptr[c];
     const int csize = I.class_ptr[c + 1] - cbase;
@@ -2446,17 +2503,19 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     const int2 cr = I.class_rec[c];
     const int32_t *R = !act ? nullptr
                        : cr.y ? I.recs + cr.x + it.p * cr.y : I.recs + I.roff[cbase + it.p];
-    gs_draws(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h);
+    gs_draws<2>(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h, 16 * it.pt);
     const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
     const int rel = b - b0;
     uint32_t n_eval = 0, n_acc = 0;
     uint64_t accm = 0;
-    gs_step<M, WB>(L, tid, I.P, I.O, R, act, it.h, act ? min(32, I.N - 32 * it.h) : 0, popm,
-                   (uint32_t)(pl.nzm[b] >> (32 * it.h)),
-                   [&](int ii, int64_t dl) {
-                       atomicAdd(&fa[rel][32 * it.h + ii], (unsigned long long)dl);
-                   },
-                   n_eval, n_acc, accm);
+    gs_step<M, WB, kGsEntryBatchBcl, 2>(L, tid, I.P, I.O, R, act, it.h,
+                                        act ? min(32, I.N - 32 * it.h) : 0, popm,
+                                        (uint32_t)(pl.nzm[b] >> (32 * it.h)),
+                                        [&](int ii, int64_t dl) {
+                                            atomicAdd(&fa[rel][32 * it.h + ii],
+                                                      (unsigned long long)dl);
+                                        },
+                                        n_eval, n_acc, accm, it.pt);
     if (n_eval) atomicAdd(&cnt[rel][0], n_eval);
     if (n_acc) atomicAdd(&cnt[rel][1], n_acc);
     __syncthreads();
