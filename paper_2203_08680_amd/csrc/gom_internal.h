@@ -388,21 +388,20 @@ constexpr int kGsMaxMembers = 9;
 constexpr int64_t kGsMaxWeightSum = 16383;
 constexpr int kGsMaxWeightBits = 13;
 constexpr int32_t kGsMinSets = 8192;
-// Instances of a batch that one block of the bit-sliced class launch can span (its slots, at
-// least 16 per instance present, aligned to 16).
-constexpr int kGsBlockInsts = kGsThreads / 16 + 1;
 // Lane slots of a class of `csize` sets under the bit-sliced general sweep (a multiple of
 // 16): 16 slots hold 8 positions x 2 halves (population above 32) or 16 positions.
 __host__ __device__ __forceinline__ int gs_slots(int csize, int halves) {
     const int per = 16 / halves;  // positions per 16 slots
     return (csize + per - 1) / per * 16;
 }
-// ... in the batched class launches, where each half is split between two lanes: 8 positions
-// take 16 x halves slots; the count is rounded up to 32 so that every instance's slots start
-// at a multiple of 32 and a lane's partner (8 lanes away) is always in its wave.
+// ... in the batched class launches, where each half is split between kGsPartsBcl lanes: 8
+// positions take 8 x parts x halves slots; the count is rounded up to a wave (64) so that every
+// instance's slots start at a multiple of 64 and a lane's partners (8, 16, ... lanes away) are
+// always in its wave.
+constexpr int kGsPartsBcl = 4;
 __host__ __device__ __forceinline__ int gs_slots_bcl(int csize, int halves) {
-    const int n = (csize + 7) / 8 * 16 * halves;
-    return (n + 31) / 32 * 32;
+    const int n = (csize + 7) / 8 * 8 * kGsPartsBcl * halves;
+    return (n + 63) / 64 * 64;
 }
 hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bits, int max_grid,
                                  hipStream_t s, KernelEvents ev);

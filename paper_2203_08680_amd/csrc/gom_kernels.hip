@@ -1598,33 +1598,34 @@ __device__ __forceinline__ void gs_draws(uint4 (*rnd)[32], int tid, uint64_t see
     __builtin_amdgcn_wave_barrier();
 }
 
-// Work item of a batched class-launch slot, where each half of a set is split between two
-// lanes (parts): 8 positions take 8 x 2 x halves consecutive slots, in groups of 8 lanes of one
-// (half, part); the partner of a lane (the other part) is the lane 8 away.
+// Work item of a batched class-launch slot, where each half of a set is split between
+// kGsPartsBcl lanes (parts): 8 positions take 8 x parts x halves consecutive slots, in groups
+// of 8 lanes of one (half, part); the partners of a lane are the lanes 8, 16, ... away.
 struct GsItem2 {
     int p, h, pt;
 };
 __device__ __forceinline__ GsItem2 gs_item2(int q, int halves) {
-    const int lp = 2 * halves;              // lanes per position
+    const int lp = kGsPartsBcl * halves;    // lanes per position
     const int g = q / (8 * lp), r = q % (8 * lp);
     const int sub = r >> 3;
-    return GsItem2{g * 8 + (r & 7), halves == 2 ? sub >> 1 : 0, sub & 1};
+    return GsItem2{g * 8 + (r & 7), sub / kGsPartsBcl, sub % kGsPartsBcl};
 }
 
 // The step of one lane: half h of the set whose record is R (act: the lane has a set; n_i:
 // solutions of the half, 32h .. 32h + n_i - 1).  Member words are stored with the accepted
 // changes; fit_add(ii, delta) receives each accepted solution's fitness change.
-// PARTS = 2: the half is split between this lane and its partner 8 lanes away (part pt):
-// each draws the donors of 16 of the 32 solutions and sums half of the edges; they exchange
-// their change masks and their partial sums, then each commits alternate members and accounts
-// for its 16 solutions.
+// PARTS > 1: the half is split between PARTS lanes 8 apart (this lane is part pt): each draws
+// the donors of 32 / PARTS of the 32 solutions and sums a share of the edges; they exchange
+// their change masks and their partial sums, then each commits every PARTS-th member and
+// accounts for its own solutions.
 template <int M, int WB, int EB, int PARTS = 1, class FitAdd>
 __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t *P, uint64_t *O,
                                         const int32_t *R, bool act, int h, int n_i,
                                         uint64_t popm, uint32_t nzh, FitAdd fit_add,
                                         uint32_t &n_eval, uint32_t &n_acc, uint64_t &accm,
                                         int pt = 0) {
-    static_assert(PARTS == 1 || PARTS == 2, "parts");
+    static_assert(PARTS == 1 || PARTS == 2 || PARTS == 4, "parts");
+    constexpr int SP = 32 / PARTS;  // solutions of the half per part
     int nm = 0, nd = 0;
     int u[M];
     uint64_t pw[M];
@@ -1656,8 +1657,8 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
     for (int k = 0; k < M; ++k) F[k] = 0u;
     uint32_t has = 0u;
-    const int ii_lo = PARTS == 2 ? 16 * pt : 0;
-    const int ii_hi = PARTS == 2 ? min(n_i, 16 * pt + 16) : n_i;
+    const int ii_lo = SP * pt;
+    const int ii_hi = min(n_i, SP * pt + SP);
 #pragma unroll 2
     for (int ii = ii_lo; ii < ii_hi; ++ii) {
         const int i = 32 * h + ii;
@@ -1680,10 +1681,11 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
         for (int k = 0; k < M; ++k) F[k] |= ((bit_of(pw[k], d) ^ s[k]) & any) << ii;
     }
-    if constexpr (PARTS == 2) {  // the partner's solutions' bits
 #pragma unroll
-        for (int k = 0; k < M; ++k) F[k] |= (uint32_t)__shfl_xor((int)F[k], 8, 64);
-        has |= (uint32_t)__shfl_xor((int)has, 8, 64);
+    for (int d = 8; d < 8 * PARTS; d <<= 1) {  // the partners' solutions' bits
+#pragma unroll
+        for (int k = 0; k < M; ++k) F[k] |= (uint32_t)__shfl_xor((int)F[k], d, 64);
+        has |= (uint32_t)__shfl_xor((int)has, d, 64);
     }
     // fitness changes of the half's solutions, bit-sliced
 #pragma unroll
@@ -1698,9 +1700,10 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
     // entries in batches of EB: the batch's record words, then its far-end words, are
     // requested before any is used (few waves share a SIMD, so each dependent round trip
     // would otherwise be paid in full)
-    // (two parts: this lane's share of the entries)
-    const int e_lo = PARTS == 2 && pt ? (nd + 1) / 2 : 0;
-    const int e_hi = PARTS == 2 && !pt ? (nd + 1) / 2 : nd;
+    // (this lane's share of the entries)
+    const int e_share = (nd + PARTS - 1) / PARTS;
+    const int e_lo = min(nd, e_share * pt);
+    const int e_hi = min(nd, e_lo + e_share);
     for (int e0 = e_lo; e0 < e_hi; e0 += EB) {
         int2 enb[EB];
         uint32_t ovb[EB];
@@ -1746,13 +1749,14 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
             C[0] = 0u;
         }
     }
-    if constexpr (PARTS == 2) {  // add the partner's partial sum (two carry-save additions)
-        W += __shfl_xor(W, 8, 64);
+#pragma unroll
+    for (int d = 8; d < 8 * PARTS; d <<= 1) {  // add a partner's partial sum (two carry-save
+        W += __shfl_xor(W, d, 64);             // additions per round)
         uint32_t XS[kGsPlanes], XC[kGsPlanes];  // (both read before either lane changes its own)
 #pragma unroll
         for (int j = 0; j < kGsPlanes; ++j) {
-            XS[j] = (uint32_t)__shfl_xor((int)S[j], 8, 64);
-            XC[j] = (uint32_t)__shfl_xor((int)C[j], 8, 64);
+            XS[j] = (uint32_t)__shfl_xor((int)S[j], d, 64);
+            XC[j] = (uint32_t)__shfl_xor((int)C[j], d, 64);
         }
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
@@ -1785,10 +1789,9 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const uint32_t m = F[k] & acc;
-        if ((PARTS == 1 || (k & 1) == pt) && u[k] >= 0 && m)
-            W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
+        if (k % PARTS == pt && u[k] >= 0 && m) W32[2 * (size_t)u[k] + h] = oh[k] ^ m;
     }
-    const uint32_t mine = PARTS == 1 ? acc : acc & (pt ? 0xFFFF0000u : 0x0000FFFFu);
+    const uint32_t mine = PARTS == 1 ? acc : acc & (((1u << SP) - 1u) << (SP * pt));
     for (uint32_t m = mine; m; m &= m - 1) {
         const int ii = __builtin_ctz(m);
         int32_t t = 0;
@@ -1796,7 +1799,7 @@ __device__ __forceinline__ void gs_step(GsLds<M, WB> &L, int tid, const uint64_t
         for (int j = 0; j < kGsPlanes; ++j) t |= (int32_t)((T[j] >> ii) & 1u) << j;
         fit_add(ii, (int64_t)(t - W));
     }
-    if (PARTS == 1 || pt == 0) {
+    if (pt == 0) {
         n_eval += (uint32_t)__popc(has);
         n_acc += (uint32_t)__popc(acc);
         accm |= (uint64_t)acc << (32 * h);
@@ -2461,11 +2464,11 @@ __global__ __launch_bounds__(kBclThreads) void k_bcl_sweep(BclPlan pl, int t) {
 template <int WB>
 __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) {
     constexpr int M = kBclMaxMembers;
+    constexpr int kWaves = kGsThreads / 64;
     __shared__ int32_t srow[kBclRowLds + 1];
     __shared__ GsLds<M, WB> L;
-    __shared__ unsigned long long fa[kGsBlockInsts][64];
-    __shared__ uint32_t cnt[kGsBlockInsts][2];
-    const int tid = (int)threadIdx.x;
+    __shared__ unsigned long long fa[kWaves][64];  // per wave: its instance's fitness changes
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int32_t *row = pl.tiles + (size_t)t * (pl.count + 1);
     // the grid covers the most slots any position can have: blocks past this position's
     // slots end before touching LDS (uniform over the block)
@@ -2475,63 +2478,53 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     const bool in_lds = pl.count <= kBclRowLds;
     if (in_lds)
         for (int q = tid; q <= pl.count; q += kGsThreads) srow[q] = row[q];
-    for (int q = tid; q < kGsBlockInsts * 64; q += kGsThreads) (&fa[0][0])[q] = 0ull;
-    if (tid < kGsBlockInsts * 2) (&cnt[0][0])[tid] = 0u;
+    fa[wave][lane] = 0ull;
     __syncthreads();
     const int32_t *rs = in_lds ? srow : row;
-    // the instance of a slot: the last one whose first slot is <= q
-    auto find = [&](int q) {
-        int lo = 0, hi = pl.count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rs[mid] <= q) lo = mid;
-            else hi = mid - 1;
-        }
-        return lo;
-    };
-    const int b0 = find(base);
-    const int q = base + tid;
-    const bool slot_ok = q < total;
-    const int b = slot_ok ? find(q) : b0;
+    // Every instance's slot count is a multiple of 64, so a wave's slots belong to one
+    // instance (or all lie past the position's total): the last instance whose first slot is
+    // <= the wave's first slot, found by a wave-uniform binary search
+    const int q0 = base + 64 * wave, q = q0 + lane;
+    const bool wave_ok = q0 < total;
+    int lo = 0, hi = pl.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rs[mid] <= q0) lo = mid;
+        else hi = mid - 1;
+    }
+    const int b = __builtin_amdgcn_readfirstlane(lo);
     const BclInst &I = pl.insts[b];
     const int halves = I.N > 32 ? 2 : 1;
     const GsItem2 it = gs_item2(q - rs[b], halves);
     const int c = pl.order[(size_t)b * pl.kmax + t];
     const int cbase = I.class_ptr[c];
     const int csize = I.class_ptr[c + 1] - cbase;
-    const bool act = slot_ok && it.p < csize;
+    const bool act = wave_ok && it.p < csize;
     const int2 cr = I.class_rec[c];
     const int32_t *R = !act ? nullptr
                        : cr.y ? I.recs + cr.x + it.p * cr.y : I.recs + I.roff[cbase + it.p];
-    gs_draws<2>(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h, 16 * it.pt);
+    gs_draws<kGsPartsBcl>(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h,
+                          32 / kGsPartsBcl * it.pt);
     const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
-    const int rel = b - b0;
     uint32_t n_eval = 0, n_acc = 0;
     uint64_t accm = 0;
-    gs_step<M, WB, kGsEntryBatchBcl, 2>(L, tid, I.P, I.O, R, act, it.h,
-                                        act ? min(32, I.N - 32 * it.h) : 0, popm,
-                                        (uint32_t)(pl.nzm[b] >> (32 * it.h)),
-                                        [&](int ii, int64_t dl) {
-                                            atomicAdd(&fa[rel][32 * it.h + ii],
-                                                      (unsigned long long)dl);
-                                        },
-                                        n_eval, n_acc, accm, it.pt);
-    if (n_eval) atomicAdd(&cnt[rel][0], n_eval);
-    if (n_acc) atomicAdd(&cnt[rel][1], n_acc);
-    __syncthreads();
-    const int span = find(min(base + kGsThreads, total) - 1) - b0 + 1;  // instances present
-    const int stripe = (int)blockIdx.x % kStripes;
-    for (int e = tid; e < span * 64; e += kGsThreads) {
-        const unsigned long long v = fa[e >> 6][e & 63];
-        if (v) atomicAdd((unsigned long long *)&pl.insts[b0 + (e >> 6)].stripes[stripe].fit[e & 63],
-                         v);
-    }
-    if (tid < span) {
-        Stripe *sp = pl.insts[b0 + tid].stripes + stripe;
-        if (cnt[tid][0]) atomicAdd((unsigned long long *)&sp->evaluated,
-                                   (unsigned long long)cnt[tid][0]);
-        if (cnt[tid][1]) atomicAdd((unsigned long long *)&sp->accepted,
-                                   (unsigned long long)cnt[tid][1]);
+    gs_step<M, WB, kGsEntryBatchBcl, kGsPartsBcl>(L, tid, I.P, I.O, R, act, it.h,
+                                                  act ? min(32, I.N - 32 * it.h) : 0, popm,
+                                                  (uint32_t)(pl.nzm[b] >> (32 * it.h)),
+                                                  [&](int ii, int64_t dl) {
+                                                      atomicAdd(&fa[wave][32 * it.h + ii],
+                                                                (unsigned long long)dl);
+                                                  },
+                                                  n_eval, n_acc, accm, it.pt);
+    const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
+    __builtin_amdgcn_wave_barrier();
+    if (!wave_ok) return;  // (uniform over the wave; no block barrier follows)
+    Stripe *sp = I.stripes + ((int)blockIdx.x * kWaves + wave) % kStripes;
+    const unsigned long long v = fa[wave][lane];
+    if (v) atomicAdd((unsigned long long *)&sp->fit[lane], v);
+    if (lane == 0) {
+        if (ce) atomicAdd((unsigned long long *)&sp->evaluated, (unsigned long long)ce);
+        if (ca) atomicAdd((unsigned long long *)&sp->accepted, (unsigned long long)ca);
     }
 }
 

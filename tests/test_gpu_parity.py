@@ -1120,6 +1120,46 @@ def test_batch_class_bitsliced_availability(cuda):
         assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), b
 
 
+def test_batch_class_launches_many_instances(cuda):
+    """48 instances in the batched class launches, both forms: small tori that reach their
+    optimum early (no slots afterwards) between random graphs of degree 3 to 8 with different
+    class counts (instances whose classes are used up), populations 2 to 64.  Late positions
+    then have most instances without a class, so the blocks of a launch hold few of them
+    among many empty ones.  Every instance equals its solo run after 30 generations."""
+    print("case batch class launches many instances", flush=True)
+    rng = np.random.default_rng(60)
+    gs, pops, targets = [], [], []
+    for k in range(48):
+        if k % 3 == 0:
+            g = workloads.torus(int(rng.choice([4, 6, 8])), 1, 20, seed=600 + k)
+            targets.append(g.total_weight)
+        else:
+            d = int(rng.integers(3, 9))
+            n = int(rng.integers(60, 1500))
+            g = workloads.configuration_model(n + (n * d) % 2, d, seed=600 + k,
+                                              weights="uniform", w_lo=1, w_hi=100)
+            targets.append(1 << 62)
+        gs.append(g)
+        pops.append(int(rng.choice([2, 9, 16, 33, 40, 64])))
+    insts = [gom.Instance(g.n, g.u, g.v, g.w, 1) for g in gs]
+    seeds = [900 + k for k in range(len(gs))]
+    for bits in (True, False):
+        bt = gom.gom_batch_init(insts, pops, seeds, targets)
+        gom.gom_batch_set_class_launch(bt, 0)
+        assert gom.gom_batch_get_class_launch(bt)[1] == len(gs)
+        gom.gom_batch_set_class_bitsliced(bt, bits)
+        assert gom.gom_batch_get_class_bitsliced(bt) == (bits, True)
+        res, _ = gom.gom_batch_run(bt, 30)
+        assert sum(r.reached for r in res) > 0  # some tori finish early
+        for b in range(len(gs)):
+            st = insts[b].state(pop=pops[b], seed=seeds[b])
+            r = gom.gom_run_to_target(st, targets[b], 30)
+            assert (res[b].generations, res[b].best, res[b].attempted, res[b].evaluated,
+                    res[b].accepted) == (r.generations, r.best, r.attempted, r.evaluated,
+                                         r.accepted), (bits, b)
+            assert gom.gom_state_hash(bt.state(b)) == gom.gom_state_hash(st), (bits, b)
+
+
 @pytest.mark.parametrize("form", ["bitsliced", "lanes"])
 @pytest.mark.parametrize("graph", [True, False], ids=["graph", "direct"])
 def test_batch_class_launches(cuda, graph, form):
