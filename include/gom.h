@@ -529,15 +529,18 @@ int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, int32_t *inst
  * share a Philox call, fewer give small classes more waves.  Errors: GOM_E_ARG, GOM_E_RANGE. */
 int gom_batch_set_class_positions(gom_batch *b, int32_t positions_per_wave);
 /*
- * Bit-sliced form of the class launches (default on where available): lane = one half of a
- * set's solutions, over the sets of every class-launched instance's class at a position,
- * with the donor draws per solution and the fitness changes of 32 solutions as one bit-sliced
- * sum (as the bit-sliced schedule's general sweep).  Available when every class-launched
- * instance's per-set sums of |w| over the dependent edges are at most 16383 and its |w| have
- * at most 13 bits.  Results are identical either way.  gom_batch_get_class_bitsliced: in use,
- * available (either may be NULL).  Errors: GOM_E_ARG.
+ * Bit-sliced form of the class launches (default on where available): four lanes share each
+ * half (32 solutions) of a set, over the sets of every class-launched instance's class at a
+ * position, with the donor draws per solution and the fitness changes of 32 solutions as one
+ * bit-sliced sum (as the bit-sliced schedule's general sweep).  Available when every general
+ * instance that takes the class launches has per-set sums of |w| over the dependent edges of
+ * at most 16383 and |w| of at most 13 bits.  In this form, univariate instances that the
+ * univariate bit-sliced sweep fits (degree <= 4) take the class launches too, at the same
+ * size threshold, one lane a set with all solutions in one word.  Results are identical
+ * either way.  Regroups the batch (synchronous on `stream`).  gom_batch_get_class_bitsliced:
+ * in use, available (either may be NULL).  Errors: GOM_E_ARG, GOM_E_DEVICE.
  */
-int gom_batch_set_class_bitsliced(gom_batch *b, int enabled);
+int gom_batch_set_class_bitsliced(gom_batch *b, int enabled, void *stream);
 int gom_batch_get_class_bitsliced(const gom_batch *b, int *enabled, int *available);
 
 /*

@@ -2264,17 +2264,45 @@ static void drop_graph(gom_batch *b) {
     }
 }
 
+// May general instance s take the bit-sliced form of the class launches (population <= 64,
+// per-set |w| sums and |w| within the bounds of the bit-sliced sum)?
+static bool gs_admissible(const gom_state *s) {
+    if (s->N > 64) return false;
+    for (int32_t c = 0; c < s->k; ++c) {
+        int bits = 1;
+        while (bits < 62 && (s->class_wmax[c] >> bits) != 0) ++bits;
+        if (s->class_wsum[c] > kGsMaxWeightSum || bits > kGsMaxWeightBits) return false;
+    }
+    return true;
+}
+
 static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
                          hipStream_t st) {
     // which instances the batched class launches sweep (the others: resident blocks)
     std::vector<BclInst> bi;
     b->bcl.clear();
     b->bcl_kmax = 0;
+    // the bit-sliced form is admitted when every general instance that takes the class
+    // launches admits it; univariate instances that the univariate bit-sliced sweep fits then
+    // take the class launches as well, one lane a set (the lane-per-solution form reads only
+    // general records)
+    bool gs_ok = true, any = false;
+    for (int32_t i = 0; i < b->count; ++i) {
+        const gom_state *s = b->subs[(size_t)i];
+        if (b->h_insts[(size_t)i].solo || bcl_min_n < 0 || (int64_t)s->n < bcl_min_n ||
+            !bcl_eligible(s))
+            continue;
+        any = true;
+        if (!gs_admissible(s)) gs_ok = false;
+    }
+    const bool gs = gs_ok && b->bcl_gs_use;
     for (int32_t i = 0; i < b->count; ++i) {
         BatchInst &I = b->h_insts[(size_t)i];
         const gom_state *s = b->subs[(size_t)i];
         if (I.solo) continue;
-        I.bcl = bcl_min_n >= 0 && (int64_t)s->n >= bcl_min_n && bcl_eligible(s);
+        const bool uni = gs && s->univariate && s->swar_uni && s->N <= 64;
+        I.bcl = bcl_min_n >= 0 && (int64_t)s->n >= bcl_min_n && (bcl_eligible(s) || uni);
+        any |= I.bcl;
         I.epi = epilogue_args(s, b->targets[(size_t)i], !I.bcl);
         if (!I.bcl) continue;
         BclInst c{};
@@ -2292,28 +2320,33 @@ static int batch_regroup(gom_batch *b, int64_t narrow_max_n, int64_t bcl_min_n,
         c.always = s->rule == GOM_NEUTRAL_ALWAYS;
         c.k = s->k;
         c.order_fixed = s->order == GOM_ORDER_FIXED;
+        c.uni = s->univariate ? 1 : 0;
+        c.sw = s->d_sw;
+        c.sw_stride = s->sw_stride;
+        c.partition = s->partition ? 1 : 0;
         bi.push_back(c);
         b->bcl.push_back(i);
         b->bcl_kmax = std::max(b->bcl_kmax, s->k);
     }
     if (!bi.empty() && b->bcl_grid == 0) HIP_TRY(bcl_sweep_grid(&b->bcl_grid));
-    // the bit-sliced form: every class-launched instance within its weight bounds; blocks for
-    // the most slots a position can have (every instance at its largest class)
-    b->bcl_gs_ok = !b->bcl.empty();
+    // the bit-sliced form's launch grid: the most slots a position can have (every instance
+    // at its largest class), and its weight bits (the general instances')
+    b->bcl_gs_ok = any && gs_ok;
     int wbits = 1;
     int64_t slots = 0;
     for (int32_t i : b->bcl) {
         const gom_state *s = b->subs[(size_t)i];
+        if (s->univariate) {
+            slots += gs_slots_uni(s->max_class);
+            continue;
+        }
         for (int32_t c = 0; c < s->k; ++c) {
             int bits = 1;
             while (bits < 62 && (s->class_wmax[c] >> bits) != 0) ++bits;
             wbits = std::max(wbits, bits);
-            if (s->class_wsum[c] > kGsMaxWeightSum) b->bcl_gs_ok = false;
         }
-        if (s->N > 64) b->bcl_gs_ok = false;
         slots += gs_slots_bcl(s->max_class, s->N > 32 ? 2 : 1);
     }
-    if (wbits > kGsMaxWeightBits) b->bcl_gs_ok = false;
     b->bcl_gs_wb = wbits <= 7 ? 7 : 13;
     b->bcl_gs_grid = (int)std::min<int64_t>((slots + kGsThreads - 1) / kGsThreads, 1 << 30);
     struct Item {
@@ -2874,6 +2907,9 @@ extern "C" int gom_batch_autotune(gom_batch *b, int32_t trial_steps, void *strea
             for (int q = q0; q < 5 && rc == GOM_OK && e == hipSuccess; ++q) {
                 b->bcl_gs_use = gsv[q] != 0;
                 b->bcl_ppw = ppws[q];
+                // (the form decides whether univariate instances take the class launches)
+                rc = batch_regroup(b, best.first, best.second, st);
+                if (rc) break;
                 e = hipEventRecord(e0, st);
                 for (int32_t t = 0; t < trial_steps && e == hipSuccess && rc == GOM_OK; ++t) {
                     e = launch_batch_step(b->d_insts, b->count, b->d_blk, b->groups.data(),
@@ -2926,11 +2962,13 @@ extern "C" int gom_batch_get_class_launch(const gom_batch *b, int64_t *min_n, in
     return GOM_OK;
 }
 
-extern "C" int gom_batch_set_class_bitsliced(gom_batch *b, int enabled) {
+extern "C" int gom_batch_set_class_bitsliced(gom_batch *b, int enabled, void *stream) {
+    GUARD_BEGIN
     if (!b) return fail(GOM_E_ARG, "gom_batch_set_class_bitsliced: null batch");
     b->bcl_gs_use = enabled != 0;
-    drop_graph(b);
-    return GOM_OK;
+    // (which instances take the class launches depends on the form)
+    return batch_regroup(b, b->narrow_max_n, b->bcl_min_n, (hipStream_t)stream);
+    GUARD_END
 }
 
 extern "C" int gom_batch_get_class_bitsliced(const gom_batch *b, int *enabled, int *available) {

@@ -325,6 +325,10 @@ struct BclInst {
     uint64_t seed;
     int64_t target;
     int32_t N, always, k, order_fixed;
+    // univariate instance in the bit-sliced form: its bit-sliced table (one lane per set, all
+    // solutions in one word, as k_uni_swar_sweep); uni = 0 for general records
+    const int32_t *sw;
+    int32_t sw_stride, uni, partition, pad;
 };
 // Blocks of the batched class-launch sweep for the current device (co-resident count).
 hipError_t bcl_sweep_grid(int *grid);
@@ -403,6 +407,8 @@ __host__ __device__ __forceinline__ int gs_slots_bcl(int csize, int halves) {
     const int n = (csize + 7) / 8 * 8 * kGsPartsBcl * halves;
     return (n + 63) / 64 * 64;
 }
+// ... and of a univariate instance's class (one lane a set), also rounded to a wave.
+__host__ __device__ __forceinline__ int gs_slots_uni(int csize) { return (csize + 63) / 64 * 64; }
 hipError_t launch_gen_swar_sweep(const SweepArgs &a, int members, int weight_bits, int max_grid,
                                  hipStream_t s, KernelEvents ev);
 // Fused form (one cooperative launch per generation; see FusedArgs).

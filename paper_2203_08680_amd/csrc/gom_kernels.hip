@@ -2364,7 +2364,8 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
             if (t < I.k && I.st->elite_fitness < I.target) {
                 const int c = order[(size_t)i * kmax + t];
                 const int32_t cs = I.class_ptr[c + 1] - I.class_ptr[c];
-                n = gs ? gs_slots_bcl(cs, I.N > 32 ? 2 : 1) : (cs + tile - 1) / tile;
+                n = !gs ? (cs + tile - 1) / tile
+                    : I.uni ? gs_slots_uni(cs) : gs_slots_bcl(cs, I.N > 32 ? 2 : 1);
             }
         }
         part[threadIdx.x] = n;
@@ -2494,28 +2495,44 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     }
     const int b = __builtin_amdgcn_readfirstlane(lo);
     const BclInst &I = pl.insts[b];
-    const int halves = I.N > 32 ? 2 : 1;
-    const GsItem2 it = gs_item2(q - rs[b], halves);
     const int c = pl.order[(size_t)b * pl.kmax + t];
     const int cbase = I.class_ptr[c];
     const int csize = I.class_ptr[c + 1] - cbase;
-    const bool act = wave_ok && it.p < csize;
-    const int2 cr = I.class_rec[c];
-    const int32_t *R = !act ? nullptr
-                       : cr.y ? I.recs + cr.x + it.p * cr.y : I.recs + I.roff[cbase + it.p];
-    gs_draws<kGsPartsBcl>(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h,
-                          32 / kGsPartsBcl * it.pt);
     const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
     uint32_t n_eval = 0, n_acc = 0;
-    uint64_t accm = 0;
-    gs_step<M, WB, kGsEntryBatchBcl, kGsPartsBcl>(L, tid, I.P, I.O, R, act, it.h,
-                                                  act ? min(32, I.N - 32 * it.h) : 0, popm,
-                                                  (uint32_t)(pl.nzm[b] >> (32 * it.h)),
-                                                  [&](int ii, int64_t dl) {
-                                                      atomicAdd(&fa[wave][32 * it.h + ii],
-                                                                (unsigned long long)dl);
-                                                  },
-                                                  n_eval, n_acc, accm, it.pt);
+    if (I.uni) {  // (wave-uniform) univariate: lane = set, all solutions in one word
+        const int p = q - rs[b];
+        if (wave_ok && p < csize) {
+            SweepArgs a{};
+            a.P = I.P;
+            a.O = I.O;
+            a.sw = I.sw;
+            a.sw_stride = I.sw_stride;
+            const SwarEntry en = swar_entry(a, cbase + p);
+            if (I.partition)
+                swar_step<true>(a, en, cbase + p, popm, pl.nzm[b], &fa[wave][0], n_eval, n_acc);
+            else
+                swar_step<false>(a, en, cbase + p, popm, pl.nzm[b], &fa[wave][0], n_eval, n_acc);
+        }
+    } else {
+        const int halves = I.N > 32 ? 2 : 1;
+        const GsItem2 it = gs_item2(q - rs[b], halves);
+        const bool act = wave_ok && it.p < csize;
+        const int2 cr = I.class_rec[c];
+        const int32_t *R = !act ? nullptr
+                           : cr.y ? I.recs + cr.x + it.p * cr.y : I.recs + I.roff[cbase + it.p];
+        gs_draws<kGsPartsBcl>(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h,
+                              32 / kGsPartsBcl * it.pt);
+        uint64_t accm = 0;
+        gs_step<M, WB, kGsEntryBatchBcl, kGsPartsBcl>(L, tid, I.P, I.O, R, act, it.h,
+                                                      act ? min(32, I.N - 32 * it.h) : 0, popm,
+                                                      (uint32_t)(pl.nzm[b] >> (32 * it.h)),
+                                                      [&](int ii, int64_t dl) {
+                                                          atomicAdd(&fa[wave][32 * it.h + ii],
+                                                                    (unsigned long long)dl);
+                                                      },
+                                                      n_eval, n_acc, accm, it.pt);
+    }
     const uint32_t ce = wave_sum32(n_eval), ca = wave_sum32(n_acc);
     __builtin_amdgcn_wave_barrier();
     if (!wave_ok) return;  // (uniform over the wave; no block barrier follows)

@@ -152,7 +152,7 @@ def lib() -> C.CDLL:
         "gom_batch_set_class_launch": (C.c_int, [_vp, _i64, _vp]),
         "gom_batch_get_class_launch": (C.c_int, [_vp, _P(_i64), _P(_i32), _P(_i32), _P(_i32)]),
         "gom_batch_set_class_positions": (C.c_int, [_vp, _i32]),
-        "gom_batch_set_class_bitsliced": (C.c_int, [_vp, C.c_int]),
+        "gom_batch_set_class_bitsliced": (C.c_int, [_vp, C.c_int, _vp]),
         "gom_batch_get_class_bitsliced": (C.c_int, [_vp, _P(C.c_int), _P(C.c_int)]),
         "gom_local_search": (C.c_int, [_vp, _i32, _vp, _P(_i32)]),
         "gom_iterated_local_search": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _P(_i32)]),
@@ -699,9 +699,10 @@ def gom_batch_get_class_launch(b: GomBatch):
     return m.value, n.value, k.value, w.value
 
 
-def gom_batch_set_class_bitsliced(b: GomBatch, enabled: bool) -> None:
+def gom_batch_set_class_bitsliced(b: GomBatch, enabled: bool, stream=None) -> None:
     """Bit-sliced form of the batched class launches (on by default where available)."""
-    _check(lib().gom_batch_set_class_bitsliced(b.handle, 1 if enabled else 0))
+    _check(lib().gom_batch_set_class_bitsliced(b.handle, 1 if enabled else 0,
+                                               _stream_handle(stream)))
 
 
 def gom_batch_get_class_bitsliced(b: GomBatch):

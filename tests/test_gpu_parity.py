@@ -1123,9 +1123,11 @@ def test_batch_class_bitsliced_availability(cuda):
 def test_batch_class_launches_many_instances(cuda):
     """48 instances in the batched class launches, both forms: small tori that reach their
     optimum early (no slots afterwards) between random graphs of degree 3 to 8 with different
-    class counts (instances whose classes are used up), populations 2 to 64.  Late positions
-    then have most instances without a class, so the blocks of a launch hold few of them
-    among many empty ones.  Every instance equals its solo run after 30 generations."""
+    class counts (instances whose classes are used up), populations 2 to 64, neighbourhood
+    FOS and (every fourth instance) univariate FOS, whose instances of degree at most 4 take
+    the class launches in the bit-sliced form (one lane a set).  Late positions then have most
+    instances without a class, so the blocks of a launch hold few of them among many empty
+    ones.  Every instance equals its solo run after 30 generations."""
     print("case batch class launches many instances", flush=True)
     rng = np.random.default_rng(60)
     gs, pops, targets = [], [], []
@@ -1141,14 +1143,21 @@ def test_batch_class_launches_many_instances(cuda):
             targets.append(1 << 62)
         gs.append(g)
         pops.append(int(rng.choice([2, 9, 16, 33, 40, 64])))
-    insts = [gom.Instance(g.n, g.u, g.v, g.w, 1) for g in gs]
+    kinds = [0 if k % 4 == 3 else 1 for k in range(len(gs))]
+    insts = [gom.Instance(g.n, g.u, g.v, g.w, kd) for g, kd in zip(gs, kinds)]
     seeds = [900 + k for k in range(len(gs))]
+
+    def max_degree(g):
+        return int(np.bincount(np.concatenate([g.u, g.v]), minlength=g.n).max())
+
+    uni_in = sum(1 for g, kd in zip(gs, kinds) if kd == 0 and max_degree(g) <= 4)
+    assert uni_in > 0
     for bits in (True, False):
         bt = gom.gom_batch_init(insts, pops, seeds, targets)
         gom.gom_batch_set_class_launch(bt, 0)
-        assert gom.gom_batch_get_class_launch(bt)[1] == len(gs)
         gom.gom_batch_set_class_bitsliced(bt, bits)
         assert gom.gom_batch_get_class_bitsliced(bt) == (bits, True)
+        assert gom.gom_batch_get_class_launch(bt)[1] == kinds.count(1) + (uni_in if bits else 0)
         res, _ = gom.gom_batch_run(bt, 30)
         assert sum(r.reached for r in res) > 0  # some tori finish early
         for b in range(len(gs)):
@@ -1184,11 +1193,12 @@ def test_batch_class_launches(cuda, graph, form):
     bt = gom.gom_batch_init(insts, pops, seeds, targets)
     gom.gom_batch_set_graph(bt, graph)
     gom.gom_batch_set_class_launch(bt, 0)
-    m, n_inst, launches, _ = gom.gom_batch_get_class_launch(bt)
-    assert m == 0 and n_inst == 5 and launches >= 1
     bits = form == "bitsliced"
     gom.gom_batch_set_class_bitsliced(bt, bits)
     assert gom.gom_batch_get_class_bitsliced(bt) == (bits, True)
+    m, n_inst, launches, _ = gom.gom_batch_get_class_launch(bt)
+    # (in the bit-sliced form the univariate torus takes the class launches too)
+    assert m == 0 and n_inst == (6 if bits else 5) and launches >= 1
     gom.gom_batch_set_class_positions(bt, 8)
     gom.gom_batch_run(bt, 5)
     gom.gom_batch_set_class_launch(bt, 1000)   # the two largest only
