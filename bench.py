@@ -98,20 +98,41 @@ def class_sweep_bytes(csr, set_ptr, set_vars, class_ptr, class_elems, pop):
     return np.array(out)
 
 
-def cpu_baseline(g, fos_kind, pop, gens, target, fi=False):
-    """The oracle, unchanged, on seed 1's first `gens` generations of the same workload; the
-    oracle builds its own FOS (and colouring) from the graph."""
+def native_oracle():
+    """Point the oracle at a -march=native build of its unchanged source for this host (the
+    portable in-tree build when the compiler refuses).  Returns whether the native one is used."""
+    import tempfile
     import oracle
+    try:
+        oracle.use_native_build(os.path.join(tempfile.gettempdir(),
+                                             f"liboracle_native_{os.getpid()}.so"))
+        return True
+    except Exception as e:
+        log(f"cpu baseline: native build failed ({e}); portable build used")
+        return False
+
+
+def cpu_baseline(g, fos_kind, pop, gens, target, fi=False):
+    """The oracle, unchanged, on seed 1's first `gens` generations of the same workload, each
+    colour class's solutions spread over every host core (up to 16); the oracle builds its own
+    FOS (and colouring) from the graph."""
+    import oracle
+    native = native_oracle()
+    workers = max(1, min(16, os.cpu_count() or 1))
     set_ptr, set_vars = oracle.fos(g, fos_kind)
     run = oracle.Run(g, set_ptr, set_vars, pop=pop, seed=1, flags=oracle.FLAG_FI if fi else 0)
+    used = run.set_workers(workers)
     t0 = time.perf_counter()
     ran = run.run(target, gens)
     dt = time.perf_counter() - t0
     s = run.state(genes=False)
-    return {"value": s["attempted"] / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+    run.close()
+    return {"value": s["attempted"] / dt, "unit": "evals/s", "cores": used, "kind": "oracle",
             "sample": f"seed 1, first {ran} generations of the benchmark run "
-                      f"({s['attempted']} attempted partial evaluations in {dt:.2f} s, "
-                      "single-threaded C oracle)"}
+                      f"({s['attempted']} attempted partial evaluations in {dt:.2f} s; each "
+                      f"colour class's solutions spread over {used} threads)",
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count(),
+            "build": "gcc -O2 -fopenmp -march=native" if native else "in-tree portable build"}
 
 
 def instance_bytes(inst, pop):
@@ -137,16 +158,9 @@ def cpu_baseline_mix(items, seeds, count, gens):
     """The oracle, unchanged, built with -march=native on this host, on the first `count`
     instances of the mix for `gens` generations each (the seeds of the first timed step), its
     colour classes' solutions spread over every host core (up to 16)."""
-    import tempfile
     import oracle
     workers = max(1, min(16, os.cpu_count() or 1))
-    native = True
-    try:
-        oracle.use_native_build(os.path.join(tempfile.gettempdir(),
-                                             f"liboracle_native_{os.getpid()}.so"))
-    except Exception as e:  # a compiler without -march=native: the portable in-tree build
-        native = False
-        log(f"cpu baseline: native build failed ({e}); portable build used")
+    native = native_oracle()
     attempted, dt, used = 0, 0.0, 1
     for it, sd in zip(items[:count], seeds[:count]):
         set_ptr, set_vars = oracle.fos(it.graph, it.fos)

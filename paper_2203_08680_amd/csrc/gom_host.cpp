@@ -2113,6 +2113,7 @@ struct gom_batch {
     int bcl_kmax = 0, bcl_grid = 0;
     int bcl_ppw = 2;                    // class positions per wave of the class launches
     uint64_t *d_bcl_nzm = nullptr;      // per class-launched instance: neutral-step mask
+    int4 *d_bcl_pos = nullptr;          // per position and instance: its class (bit-sliced form)
     bool bcl_gs_use = true;             // class launches in the bit-sliced form when ...
     bool bcl_gs_ok = false;             // ... every class-launched instance admits it
     int bcl_gs_wb = 0, bcl_gs_grid = 0; // its weight bits (7 or 13) and blocks per launch
@@ -2138,7 +2139,7 @@ namespace {
 struct BatchLayout {
     std::vector<size_t> sub_off, sub_bytes;
     size_t insts = 0, blk = 0, vblk = 0, snap = 0, bcl = 0, bcl_order = 0, bcl_tiles = 0,
-           bcl_nzm = 0, total = 0;
+           bcl_nzm = 0, bcl_pos = 0, total = 0;
     int sweep_blocks = 0, vblocks = 0, kmax = 0;
 };
 
@@ -2177,6 +2178,8 @@ int batch_layout(int32_t count, const mc_graph *const *graphs, const gom_fos *co
     o = align_up(o + sizeof(int32_t) * (size_t)kmax * (count + 1));
     B.bcl_nzm = o;
     o = align_up(o + sizeof(uint64_t) * (size_t)count);
+    B.bcl_pos = o;
+    o = align_up(o + 2 * sizeof(int4) * (size_t)kmax * count);
     B.total = o;
     B.sweep_blocks = sweep;
     B.vblocks = vb;
@@ -2471,6 +2474,7 @@ static BclPlan bcl_plan(const gom_batch *b) {
     p.gs_wb = b->bcl_gs_wb;
     p.gs_grid = b->bcl_gs_grid;
     p.nzm = b->d_bcl_nzm;
+    p.pos = b->d_bcl_pos;
     return p;
 }
 
@@ -2531,6 +2535,7 @@ extern "C" int gom_batch_init(int32_t count, const mc_graph *const *graphs,
     bt->d_bcl_order = (uint16_t *)(arena + B.bcl_order);
     bt->d_bcl_tiles = (int32_t *)(arena + B.bcl_tiles);
     bt->d_bcl_nzm = (uint64_t *)(arena + B.bcl_nzm);
+    bt->d_bcl_pos = (int4 *)(arena + B.bcl_pos);
     bt->d_insts = (BatchInst *)(arena + B.insts);
     bt->d_blk = (int2 *)(arena + B.blk);
     bt->d_vblk = (int32_t *)(arena + B.vblk);

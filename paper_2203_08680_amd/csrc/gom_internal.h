@@ -346,6 +346,9 @@ struct BclPlan {
     int32_t gs_grid;       // blocks per launch (enough for every position's slots)
     uint64_t *nzm;         // [i]: solutions whose neutral steps are accepted (always, or those
                            // that differ from the elitist), written by k_bcl_order
+    int4 *pos;             // [2 (t count + i) + 0/1]: instance i's class at position t as
+                           // {class, first set, sets, generation}, {record start, stride, 0, 0},
+                           // written by k_bcl_tiles in the bit-sliced form
 };
 
 

@@ -2351,7 +2351,7 @@ __global__ __launch_bounds__(256) void k_bcl_order(const BclInst *insts, uint16_
 // over the instances; the total follows the last instance.
 __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const uint16_t *order,
                                                    int32_t *tiles, int count, int kmax,
-                                                   int tile, int gs) {
+                                                   int tile, int gs, int4 *pos) {
     __shared__ int32_t part[256];
     const int t = blockIdx.x;
     int32_t *row = tiles + (size_t)t * (count + 1);
@@ -2363,9 +2363,15 @@ __global__ __launch_bounds__(256) void k_bcl_tiles(const BclInst *insts, const u
             const BclInst &I = insts[i];
             if (t < I.k && I.st->elite_fitness < I.target) {
                 const int c = order[(size_t)i * kmax + t];
-                const int32_t cs = I.class_ptr[c + 1] - I.class_ptr[c];
+                const int32_t c0 = I.class_ptr[c], cs = I.class_ptr[c + 1] - c0;
                 n = !gs ? (cs + tile - 1) / tile
                     : I.uni ? gs_slots_uni(cs) : gs_slots_bcl(cs, I.N > 32 ? 2 : 1);
+                if (gs) {  // the sweep's view of the class, one load away
+                    const int2 cr = I.class_rec[c];
+                    int4 *ps = pos + 2 * ((size_t)t * count + i);
+                    ps[0] = make_int4(c, c0, cs, I.st->generation);
+                    ps[1] = make_int4(cr.x, cr.y, 0, 0);
+                }
             }
         }
         part[threadIdx.x] = n;
@@ -2495,9 +2501,9 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
     }
     const int b = __builtin_amdgcn_readfirstlane(lo);
     const BclInst &I = pl.insts[b];
-    const int c = pl.order[(size_t)b * pl.kmax + t];
-    const int cbase = I.class_ptr[c];
-    const int csize = I.class_ptr[c + 1] - cbase;
+    const int4 pa = pl.pos[2 * ((size_t)t * pl.count + b)];
+    const int4 pb = pl.pos[2 * ((size_t)t * pl.count + b) + 1];
+    const int c = pa.x, cbase = pa.y, csize = pa.z, gen = pa.w;
     const uint64_t popm = I.N >= 64 ? ~0ull : ((1ull << I.N) - 1ull);
     uint32_t n_eval = 0, n_acc = 0;
     if (I.uni) {  // (wave-uniform) univariate: lane = set, all solutions in one word
@@ -2518,11 +2524,9 @@ __global__ __launch_bounds__(kGsThreads) void k_bcl_gs_sweep(BclPlan pl, int t) 
         const int halves = I.N > 32 ? 2 : 1;
         const GsItem2 it = gs_item2(q - rs[b], halves);
         const bool act = wave_ok && it.p < csize;
-        const int2 cr = I.class_rec[c];
         const int32_t *R = !act ? nullptr
-                           : cr.y ? I.recs + cr.x + it.p * cr.y : I.recs + I.roff[cbase + it.p];
-        gs_draws<kGsPartsBcl>(L.rnd, tid, I.seed, I.st->generation, c, it.p, it.h,
-                              32 / kGsPartsBcl * it.pt);
+                           : pb.y ? I.recs + pb.x + it.p * pb.y : I.recs + I.roff[cbase + it.p];
+        gs_draws<kGsPartsBcl>(L.rnd, tid, I.seed, gen, c, it.p, it.h, 32 / kGsPartsBcl * it.pt);
         uint64_t accm = 0;
         gs_step<M, WB, kGsEntryBatchBcl, kGsPartsBcl>(L, tid, I.P, I.O, R, act, it.h,
                                                       act ? min(32, I.N - 32 * it.h) : 0, popm,
@@ -2941,7 +2945,8 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
     }
     if (n_bcl > 0) {
         if (bcl.kmax > 2048 || bcl.grid < 1) return hipErrorInvalidValue;
-        if (bcl.gs && (!bcl.nzm || bcl.gs_grid < 1 || (bcl.gs_wb != 7 && bcl.gs_wb != 13)))
+        if (bcl.gs && (!bcl.nzm || !bcl.pos || bcl.gs_grid < 1 ||
+                       (bcl.gs_wb != 7 && bcl.gs_wb != 13)))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_bcl_order, dim3(bcl.count), dim3(256), 0, s, bcl.insts, bcl.order,
                            bcl.kmax, bcl.gs ? bcl.nzm : nullptr);
@@ -2949,7 +2954,7 @@ hipError_t launch_batch_step(const BatchInst *insts, int count, const int2 *blk,
         if (e != hipSuccess) return e;
         if (bcl.ppw < 1 || bcl.ppw > kBclPositions) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_bcl_tiles, dim3(bcl.kmax), dim3(256), 0, s, bcl.insts, bcl.order,
-                           bcl.tiles, bcl.count, bcl.kmax, kBclWaves * bcl.ppw, bcl.gs);
+                           bcl.tiles, bcl.count, bcl.kmax, kBclWaves * bcl.ppw, bcl.gs, bcl.pos);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         for (int t = 0; t < bcl.kmax; ++t) {
