@@ -51,15 +51,22 @@ WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_50
 # roofline.traffic only while the sources still hash the same; the summaries and commands are
 # in profiles/.
 MEASURED_TRAFFIC = {
-    ("k_class_sweep", "torus100_nbhd_p64"): {
-        "bytes": 1030201, "source": "1fea3fa46b78b064",
-        "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
-    ("k_resident_sweep", "torus100_nbhd_p64"): {
-        "bytes": 16374068, "source": "1fea3fa46b78b064",
-        "profile": "profiles/k_resident_sweep_torus100_nbhd_p64.md"},
+    # per generation step: 108 k_bcl_gs_sweep dispatches x 118110792 bytes
+    ("batched_sweeps", "batch256_mix"): {
+        "bytes": 12755965536, "source": "fce5914e347abd03",
+        "profile": "profiles/k_bcl_gs_sweep_batch256_mix.md"},
+    ("k_gen_swar_sweep + k_class_sweep", "torus1000_nbhd_p64"): {
+        "bytes": 49310592, "source": "fce5914e347abd03",
+        "profile": "profiles/k_gen_swar_sweep_torus1000_nbhd_p64.md"},
+    ("k_uni_swar_sweep", "torus3162_uni_p64"): {
+        "bytes": 269255872, "source": "fce5914e347abd03",
+        "profile": "profiles/k_uni_swar_sweep_torus3162_uni_p64.md"},
     ("k_uni_swar_sweep", "torus1000_uni_p64"): {
-        "bytes": 24140655, "source": "1fea3fa46b78b064",
+        "bytes": 23209750, "source": "fce5914e347abd03",
         "profile": "profiles/k_uni_swar_sweep_torus1000_uni_p64.md"},
+    ("k_class_sweep", "torus100_nbhd_p64"): {
+        "bytes": 934260, "source": "fce5914e347abd03",
+        "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
 }
 
 
