@@ -30,6 +30,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -267,6 +268,16 @@ def small_mix_time_to_optimum(torch, gom, count, max_gens):
             "plain_alone_p99": q([plain_t[b] * 1e3 for b in tori], 99)}
 
 
+def batch_groups(insts, k):
+    """Instance indices of k batches: dealt round-robin in order of class count (largest
+    first), each group in instance order."""
+    if k <= 1:
+        return [list(range(len(insts)))]
+    kc = [len(x.classes()[1]) - 1 for x in insts]
+    order = sorted(range(len(insts)), key=lambda i: (-kc[i], i))
+    return [sorted(order[g::k]) for g in range(k)]
+
+
 def run_batch_mode(args, torch, gom):
     """Batched vs plain on the 256-instance mix (the default line).  A step is one batched run
     of the whole mix: fresh initial populations (new seeds), then lockstep generations until
@@ -285,32 +296,74 @@ def run_batch_mode(args, torch, gom):
     t_setup = time.perf_counter() - t0
     log(f"batch set-up: {len(items)} instances, {sum(x.n for x in insts)} vertices, graphs, "
         f"FOS and colourings in {t_setup:.1f} s")
+    # the mix as `batch_streams` batches, each on its own stream (instances dealt round-robin
+    # in order of their class counts, so every batch holds a like share of long and short
+    # class sequences); each batch runs from its own host thread
+    groups = batch_groups(insts, args.batch_streams)
     t0 = time.perf_counter()
-    batch = gom.gom_batch_init(insts, pops, step_seeds(items, 0), targets)
-    gom.gom_batch_set_graph(batch, args.batch_graph == "on")
-    log(f"batch states: {time.perf_counter() - t0:.1f} s")
+    seeds_init = step_seeds(items, 0)
+    batches = [gom.gom_batch_init([insts[i] for i in g], [pops[i] for i in g],
+                                  [seeds_init[i] for i in g], [targets[i] for i in g])
+               for g in groups]
+    streams = [torch.cuda.Stream() for _ in groups] if len(groups) > 1 else [None]
+    for batch in batches:
+        gom.gom_batch_set_graph(batch, args.batch_graph == "on")
+    log(f"batch states: {time.perf_counter() - t0:.1f} s ({len(batches)} batches)")
     tuned = (args.batch_narrow is None and args.batch_class_min is None and
              args.batch_class_ppw is None and args.batch_class_form is None)
-    if tuned:
-        t0 = time.perf_counter()
-        chosen = gom.gom_batch_autotune(batch, 2)
-        log(f"batch autotune: thresholds {chosen} in {time.perf_counter() - t0:.1f} s")
-    else:
-        if args.batch_narrow is not None:
-            gom.gom_batch_set_narrow(batch, args.batch_narrow)
-        if args.batch_class_min is not None:
-            gom.gom_batch_set_class_launch(batch, args.batch_class_min)
-        if args.batch_class_ppw is not None:
-            gom.gom_batch_set_class_positions(batch, args.batch_class_ppw)
-        if args.batch_class_form is not None:
-            gom.gom_batch_set_class_bitsliced(batch, args.batch_class_form == "bitsliced")
-    narrow, sweep_launches = gom.gom_batch_get_narrow(batch)
-    class_min, class_insts, class_launches, class_ppw = gom.gom_batch_get_class_launch(batch)
-    class_bits = gom.gom_batch_get_class_bitsliced(batch)[0] if class_insts else False
+    for batch in batches:
+        if tuned:
+            t0 = time.perf_counter()
+            chosen = gom.gom_batch_autotune(batch, 2)
+            log(f"batch autotune: thresholds {chosen} in {time.perf_counter() - t0:.1f} s")
+        else:
+            if args.batch_narrow is not None:
+                gom.gom_batch_set_narrow(batch, args.batch_narrow)
+            if args.batch_class_min is not None:
+                gom.gom_batch_set_class_launch(batch, args.batch_class_min)
+            if args.batch_class_ppw is not None:
+                gom.gom_batch_set_class_positions(batch, args.batch_class_ppw)
+            if args.batch_class_form is not None:
+                gom.gom_batch_set_class_bitsliced(batch, args.batch_class_form == "bitsliced")
+    shapes = [(gom.gom_batch_get_narrow(b), gom.gom_batch_get_class_launch(b)) for b in batches]
+    narrow = [x[0][0] for x in shapes]
+    sweep_launches = [x[0][1] for x in shapes]
+    class_min = [x[1][0] for x in shapes]
+    class_insts = sum(x[1][1] for x in shapes)
+    class_launches = [x[1][2] for x in shapes]
+    class_ppw = [x[1][3] for x in shapes]
+    class_bits = all(gom.gom_batch_get_class_bitsliced(b)[0] for b, x in zip(batches, shapes)
+                     if x[1][1]) if class_insts else False
+
+    def run_all(k, timing=False):
+        """Fresh populations (the seeds of step k) and a run of every batch, the batches at
+        once on their streams (one host thread each) or, for the timing pass, one by one."""
+        seeds = step_seeds(items, k)
+        for batch, g, s in zip(batches, groups, streams):
+            gom.gom_batch_reseed(batch, [seeds[i] for i in g], stream=s)
+        out = [None] * len(batches)
+
+        def go(j):
+            out[j] = gom.gom_batch_run(batches[j], max_gens, stream=streams[j])
+
+        if len(batches) == 1 or timing:
+            for j in range(len(batches)):
+                go(j)
+        else:
+            th = [threading.Thread(target=go, args=(j,)) for j in range(len(batches))]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+        res, tt = [None] * len(items), np.zeros(len(items))
+        for j, g in enumerate(groups):
+            for pos, i in enumerate(g):
+                res[i] = out[j][0][pos]
+                tt[i] = out[j][1][pos]
+        return res, tt
 
     def one_step(k):
-        gom.gom_batch_reseed(batch, step_seeds(items, k))
-        return gom.gom_batch_run(batch, max_gens)
+        return run_all(k)
 
     for w in range(args.warmup):
         res, _ = one_step(-1 - w)
@@ -332,13 +385,20 @@ def run_batch_mode(args, torch, gom):
 
     # kernel-timing pass after the timed region: the first timed step's seeds again, every
     # sweep launch timed with HIP events recorded by its own dispatch (direct launches)
-    gom.gom_batch_timing_enable(batch, True)
-    gom.gom_batch_timing_read(batch)
-    res_t, _ = one_step(0)
-    sweep_ms, launches = gom.gom_batch_timing_read(batch)
-    gom.gom_batch_timing_enable(batch, False)
+    for batch in batches:
+        gom.gom_batch_timing_enable(batch, True)
+        gom.gom_batch_timing_read(batch)
+    res_t, _ = run_all(0, timing=True)
+    sweep_ms, launches = 0.0, 0
+    for batch in batches:  # (summed over the batches, per generation step)
+        ms, n = gom.gom_batch_timing_read(batch)
+        sweep_ms += ms
+        launches = max(launches, n)
+        gom.gom_batch_timing_enable(batch, False)
     copy_calibration(torch, args.copy_calib_mb)
-    batch_hash = [gom.gom_state_hash(batch.state(b)) for b in range(len(items))]
+    where = {i: (j, pos) for j, g in enumerate(groups) for pos, i in enumerate(g)}
+    batch_hash = [gom.gom_state_hash(batches[where[i][0]].state(where[i][1]))
+                  for i in range(len(items))]
     same_timed = all((a.generations, a.best, a.evaluated, a.accepted) ==
                      (b.generations, b.best, b.evaluated, b.accepted)
                      for a, b in zip(res_t, steps[0][0]))
@@ -392,8 +452,9 @@ def run_batch_mode(args, torch, gom):
                     "bytes_per_launch": round(total_bytes / launches, 1),
                     "avg_launch_us": round(sweep_ms / launches * 1e3, 3), "launches": launches,
                     "timing": "every sweep launch of one more batched run (the first timed "
-                              "step's seeds) after the timed region, HIP events recorded by "
-                              "the dispatch"}
+                              "step's seeds, the batches one after another) after the timed "
+                              "region, HIP events recorded by the dispatch; summed over the "
+                              "batches per generation step"}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_mix(items, seeds0, args.cpu_instances, args.cpu_gens)
@@ -410,7 +471,8 @@ def run_batch_mode(args, torch, gom):
                    "instances": len(items), "vertices": int(sum(x.n for x in insts)),
                    "pop_range": [16, 64], "max_generations": max_gens,
                    "fos": "univariate and neighbourhood alternating in pairs",
-                   "mode": "batched", "schedule": "batched_resident",
+                   "mode": "batched", "batches": len(batches),
+                   "batch_streams": "one batch a stream, each run from its own host thread",
                    "narrow_blocks_max_n": narrow, "resident_launches_per_step": sweep_launches,
                    "class_launch_min_n": class_min, "class_launch_instances": class_insts,
                    "class_launches_per_step": class_launches,
@@ -643,6 +705,9 @@ def main():
                     help="batched mode: neighbourhood instances with at least this many "
                          "vertices take the batched class launches (-1: none; default: "
                          "autotuned)")
+    ap.add_argument("--batch-streams", type=int, default=2,
+                    help="batched mode: split the mix into this many batches, one a stream, "
+                         "run at the same time from their own host threads")
     ap.add_argument("--batch-class-form", choices=("bitsliced", "lanes"), default=None,
                     help="batched mode: form of the class launches (bit-sliced where "
                          "available, or lane = solution)")

@@ -69,3 +69,58 @@ def test_states_on_three_host_threads(cuda):
         a, b = gom.gom_state_read(st), ref.state()
         for key in KEYS:
             assert np.array_equal(np.asarray(a[key]), np.asarray(b[key])), f"{label}: {key}"
+
+
+def test_batches_on_two_host_threads(cuda):
+    """Two batches (the benchmark's way of running its mix on two streams), each with graph
+    chunks and the bit-sliced class launches, run at the same time from two host threads on
+    two streams: every instance equals its solo run, and a second round after a reseed does
+    too."""
+    import torch
+    rng = np.random.default_rng(70)
+    gs, kinds, pops = [], [], []
+    for k in range(16):
+        if k % 2 == 0:
+            gs.append(workloads.torus(int(rng.choice([10, 20, 30])), 1, 100, seed=700 + k))
+        else:
+            d = int(rng.choice([4, 8]))
+            n = int(rng.integers(500, 3000))
+            gs.append(workloads.configuration_model(n + (n * d) % 2, d, seed=700 + k,
+                                                    weights="uniform", w_lo=1, w_hi=100))
+        kinds.append(0 if k % 4 < 2 else 1)
+        pops.append(int(rng.choice([16, 33, 64])))
+    insts = [gom.Instance(g.n, g.u, g.v, g.w, kd) for g, kd in zip(gs, kinds)]
+    targets = [g.total_weight if k % 2 == 0 else (1 << 62) for k, g in enumerate(gs)]
+    groups = [list(range(0, 16, 2)), list(range(1, 16, 2))]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    batches = []
+    for g in groups:
+        b = gom.gom_batch_init([insts[i] for i in g], [pops[i] for i in g],
+                               [50 + i for i in g], [targets[i] for i in g])
+        gom.gom_batch_set_class_launch(b, 0)
+        batches.append(b)
+    for rnd, gens in ((0, 24), (1, 16)):
+        if rnd:
+            for b, g, s in zip(batches, groups, streams):
+                gom.gom_batch_reseed(b, [90 + i for i in g], stream=s)
+        out = [None, None]
+
+        def go(j):
+            out[j] = gom.gom_batch_run(batches[j], gens, stream=streams[j])
+
+        th = [threading.Thread(target=go, args=(j,)) for j in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        torch.cuda.synchronize()
+        for j, g in enumerate(groups):
+            for pos, i in enumerate(g):
+                st = insts[i].state(pop=pops[i], seed=(90 if rnd else 50) + i)
+                r = gom.gom_run_to_target(st, targets[i], gens)
+                got = out[j][0][pos]
+                assert (got.generations, got.best, got.attempted, got.evaluated,
+                        got.accepted) == (r.generations, r.best, r.attempted, r.evaluated,
+                                          r.accepted), (rnd, i)
+                assert gom.gom_state_hash(batches[j].state(pos)) == gom.gom_state_hash(st), \
+                    (rnd, i)
