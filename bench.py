@@ -4,11 +4,11 @@ batched against plain.
 Default line (the batched configuration): 256 independent Max-Cut instances with n
 log-uniform in [10^3, 10^5] (even positions L x L tori, odd positions random 4- and 8-regular
 graphs), weights uniform in [1, 100], populations uniform in [16, 64], univariate and
-neighbourhood FOS alternating in pairs, run in one lockstep batch until every torus reaches
-its total weight or 200 generations: per generation step, resident-block sweeps for the
-instances the autotuner leaves there, one class launch per class position covering every
-other instance (bit-sliced where admitted), one finalize and one vertex pass, replayed from
-captured HIP graphs.
+neighbourhood FOS alternating in pairs, run as lockstep batches (two by default, one a
+stream, at the same time) until every torus reaches its total weight or 200 generations: per
+generation step, resident-block sweeps for the instances the autotuner leaves there, one class
+launch per class position covering every other instance (bit-sliced where admitted), one
+finalize and one vertex pass, replayed from captured HIP graphs.
 
 A step is one batched run of the whole mix from fresh initial populations (new seeds per
 step).  `value` = attempted partial evaluations (population x FOS sets x generations, summed
