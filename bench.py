@@ -552,7 +552,7 @@ def run_serve_mode(args, torch, gom):
     log(f"plain: capacity {capacity:.2f} jobs/s, arrival rate {rate:.2f} jobs/s")
     # served: the same arrivals through the serving loop
     arena_bytes = int(args.serve_arena_gb * (1 << 30))
-    srv = gom.GomServer(arena_bytes, max_jobs=256, streams=args.serve_streams)
+    srv = gom.GomServer(arena_bytes, max_jobs=args.serve_max_active, streams=args.serve_streams)
     srv.set_large(args.serve_large_min)
     start = time.perf_counter()
     nxt, ids, res = 0, {}, {}
@@ -601,6 +601,7 @@ def run_serve_mode(args, torch, gom):
                    "jobs": len(jobs), "max_generations": args.serve_max_gens,
                    "arrival_rate_jobs_per_s": rate, "load": args.serve_load,
                    "arena_bytes": arena_bytes, "streams": args.serve_streams,
+                   "max_active_jobs": args.serve_max_active,
                    "large_min_vertices": args.serve_large_min,
                    "mode": "served"},
         "time_to_solution_ms": {"served_p50": pct(served_tts, 50),
@@ -730,6 +731,8 @@ def main():
                     help="arrival rate as a fraction of the measured plain capacity")
     ap.add_argument("--serve-arena-gb", type=float, default=32.0)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-max-active", type=int, default=256,
+                    help="serving: most jobs admitted (running) at once; the others queue")
     ap.add_argument("--serve-large-min", type=int, default=-1,
                     help="jobs with at least this many vertices run one at a time on the "
                          "first stream, small jobs on the others (default -1: every job on "

@@ -606,9 +606,10 @@ int gom_ims_run(const mc_graph *g, const gom_fos *f, int32_t n_base, int32_t c_i
  * gom_server_step admits queued jobs first come first served while their states fit in the
  * server's arena (the HBM budget), and moves every admitted job forward without waiting for
  * the others: each job runs on one of the server's streams (the least loaded at admission),
- * a chunk of 4 generations at a time under the schedule gom_state_init chose for it, and as
- * soon as a chunk has finished the job is retired (target or generation limit reached; its
- * memory is freed) or given its next chunk.  Jobs on different streams overlap on the device.
+ * in chunks of 4 generations under the schedule gom_state_init chose for it, two chunks in
+ * flight (the next one queued while one runs); as soon as a chunk has finished the job is
+ * retired once its last chunk is done (target or generation limit reached; its memory is
+ * freed) or given another chunk.  Jobs on different streams overlap on the device.
  * A job's random numbers depend on its seed alone, so its result equals that of
  * gom_run_to_target on a fresh state with the same arguments, whatever else runs beside it.
  * ------------------------------------------------------------------------------------------ */

@@ -3022,7 +3022,11 @@ struct ServerJob {
     gom_state *s = nullptr;
     int lane = 0;
     bool large = false;       // runs alone on lane 0 (size-aware placement)
-    bool in_flight = false;   // a chunk and its snapshot are enqueued
+    int slot = 0;             // chunk slot (event, snapshot) the next chunk uses
+    int oldest = 0;           // slot of the oldest chunk in flight
+    int pending = 0;          // chunks in flight (at most two: one runs while one waits)
+    bool finishing = false;   // finished (target or limit); waits for its last chunk
+    DevState last{};          // the run scalars when it finished
     bool retired = false;     // finished: result recorded, state and memory released
     double submit_ms = 0.0, admit_ms = 0.0;
 };
@@ -3131,18 +3135,26 @@ extern "C" int gom_server_submit(gom_server *sv, const mc_graph *g, const gom_fo
 namespace {
 
 // Enqueue the job's next chunk of generations and the copy of its run scalars.
+// The job's next chunk of generations and the snapshot of its run scalars, in the next slot;
+// nothing once its generation limit has been enqueued (but a snapshot when no chunk is in
+// flight, so that a job with no generation left still reports).  A generation enqueued after the target
+// was reached does nothing on the device, so a job keeps two chunks in flight: the next one
+// is queued while the last one runs, and no host round trip separates them.
 int server_issue(gom_server *sv, ServerJob &J) {
     gom_state *s = J.s;
     hipStream_t q = sv->lanes[(size_t)J.lane];
     const int32_t n = std::min(sv->chunk, J.max_gens - s->g_host);
+    if (n <= 0 && J.pending > 0) return GOM_OK;  // (with none in flight: a snapshot alone)
     for (int32_t t = 0; t < n; ++t) {
         int rc = enqueue_generation(s, s->g_host, J.target, q);
         if (rc) return rc;
         s->g_host++;
     }
-    HIP_TRY(hipMemcpyAsync(&s->h_st[0], s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, q));
-    HIP_TRY(hipEventRecord(s->chunk_ev[0], q));
-    J.in_flight = true;
+    HIP_TRY(hipMemcpyAsync(&s->h_st[J.slot], s->d_st, sizeof(DevState), hipMemcpyDeviceToHost,
+                           q));
+    HIP_TRY(hipEventRecord(s->chunk_ev[J.slot], q));
+    J.slot ^= 1;
+    J.pending++;
     return GOM_OK;
 }
 
@@ -3202,6 +3214,7 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
         sv->active.push_back(J);
         sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)qi);
         rc = server_issue(sv, sv->active.back());
+        if (rc == GOM_OK) rc = server_issue(sv, sv->active.back());
         if (rc) return rc;
     }
     // progress: every job whose chunk has finished is retired or given its next chunk; a
@@ -3209,15 +3222,25 @@ extern "C" int gom_server_step(gom_server *sv, int32_t *n_active, int32_t *n_que
     RetiredSweep<ServerJob> sweep{sv->active};
     for (ServerJob &J : sv->active) {
         gom_state *s = J.s;
-        const hipError_t qe = hipEventQuery(s->chunk_ev[0]);
-        if (qe == hipErrorNotReady) continue;
-        HIP_TRY(qe);
-        const DevState h = s->h_st[0];
-        if (h.elite_fitness < J.target && h.generation < J.max_gens) {
-            int rc = server_issue(sv, J);
-            if (rc) return rc;
-            continue;
+        // every finished chunk, oldest first: a job not yet finished gets its next chunk
+        while (J.pending > 0) {
+            const hipError_t qe = hipEventQuery(s->chunk_ev[J.oldest]);
+            if (qe == hipErrorNotReady) break;
+            HIP_TRY(qe);
+            const DevState h = s->h_st[J.oldest];
+            J.oldest ^= 1;
+            J.pending--;
+            if (J.finishing) continue;
+            if (h.elite_fitness >= J.target || h.generation >= J.max_gens) {
+                J.finishing = true;
+                J.last = h;
+            } else {
+                int rc = server_issue(sv, J);
+                if (rc) return rc;
+            }
         }
+        if (!J.finishing || J.pending > 0) continue;  // (its last chunk still runs)
+        const DevState h = J.last;
         gom_job_result r{};
         r.job = J.id;
         r.status = GOM_OK;
