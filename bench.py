@@ -212,6 +212,36 @@ def write_metrics_log(path, gom, torch, st, target, max_gens):
     log(f"metrics log: {path}")
 
 
+def write_batch_metrics_log(path, gom, torch, batches, groups, seeds, targets, max_gens):
+    """Per-generation metrics of one more batched run (the given seeds), one JSON line per
+    generation step: the generation, instances at their target, the sum and the mean of the
+    instances' elitist fitnesses, the cumulative attempted / evaluated / accepted counts over
+    all instances and the wall time of the step (enqueue to completion, ns).  Outside the
+    timed region: each step waits for its read-back, the batches one after another."""
+    for batch, g in zip(batches, groups):
+        gom.gom_batch_reseed(batch, [seeds[i] for i in g])
+    with open(path, "w") as fh:
+        for gen in range(1, max_gens + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter_ns()
+            res = []
+            for batch in batches:
+                res.extend(gom.gom_batch_run(batch, gen)[0])
+            ns = time.perf_counter_ns() - t0
+            states = [gom.gom_state_read(batch.state(p), genes=False)
+                      for batch, g in zip(batches, groups) for p in range(len(g))]
+            order = [i for g in groups for i in g]
+            reached = sum(1 for s_, i in zip(states, order) if s_["elite_fitness"] >= targets[i])
+            elites = [s_["elite_fitness"] for s_ in states]
+            fh.write(json.dumps({
+                "g": gen, "reached": reached, "elite_sum": int(sum(elites)),
+                "elite_mean": float(np.mean(elites)),
+                "attempted": int(sum(s_["attempted"] for s_ in states)),
+                "evaluated": int(sum(s_["evaluated"] for s_ in states)),
+                "accepted": int(sum(s_["accepted"] for s_ in states)), "ns": ns}) + "\n")
+    log(f"metrics log: {path}")
+
+
 def copy_calibration(torch, mb):
     """A device copy of a known byte count (3 times), for scaling profiler traffic counters."""
     if not mb:
@@ -425,6 +455,9 @@ def run_batch_mode(args, torch, gom):
         (b.generations, b.reached, b.best, b.attempted, b.evaluated, b.accepted, hb)
         for a, b, ha, hb in zip(steps[0][0], plain, batch_hash, plain_hash))
     log(f"plain: {t_plain * 1e3:.1f} ms for the first step's seeds, identical results: {same}")
+    if args.metrics_jsonl:  # one more run (the first timed step's seeds), after the checks
+        write_batch_metrics_log(args.metrics_jsonl, gom, torch, batches, groups, seeds0,
+                                targets, max_gens)
 
     value = attempted / total
     plain_value = ev_plain / t_plain if plain else None
@@ -740,8 +773,8 @@ def main():
     ap.add_argument("--max-gens", type=int, default=None,
                     help="override the workload's generation limit")
     ap.add_argument("--metrics-jsonl", default=None,
-                    help="plain mode: write per-generation metrics of one more run to this "
-                         "file (JSON lines)")
+                    help="write per-generation metrics of one more run to this file (JSON "
+                         "lines; batched mode: totals over the instances)")
     ap.add_argument("--staged", action="store_true",
                     help="plain mode: class sweeps of small general sets take the staged "
                          "evaluation (two rounds of loads per set)")
