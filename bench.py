@@ -50,23 +50,25 @@ WORKLOAD_NAMES = {"torus100_nbhd_p64": "torus100x100_nbhd_pop64_to_optimum_or_50
 # HBM traffic per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a device
 # copy of known size), with the hash of the kernel sources they were taken on.  Reported as
 # roofline.traffic only while the sources still hash the same; the summaries and commands are
-# in profiles/.
+# in profiles/.  A source change whose gfx950 assembly is identical (hipcc
+# --offload-device-only -S, apart from the compilation-unit id) carries the figures over to
+# the new hash.
 MEASURED_TRAFFIC = {
     # per generation step: 108 k_bcl_gs_sweep dispatches x 118110792 bytes
     ("batched_sweeps", "batch256_mix"): {
-        "bytes": 12755965536, "source": "fce5914e347abd03",
+        "bytes": 12755965536, "source": "706ff9da0b9d659e",
         "profile": "profiles/k_bcl_gs_sweep_batch256_mix.md"},
     ("k_gen_swar_sweep + k_class_sweep", "torus1000_nbhd_p64"): {
-        "bytes": 49310592, "source": "fce5914e347abd03",
+        "bytes": 49310592, "source": "706ff9da0b9d659e",
         "profile": "profiles/k_gen_swar_sweep_torus1000_nbhd_p64.md"},
     ("k_uni_swar_sweep", "torus3162_uni_p64"): {
-        "bytes": 269255872, "source": "fce5914e347abd03",
+        "bytes": 269255872, "source": "706ff9da0b9d659e",
         "profile": "profiles/k_uni_swar_sweep_torus3162_uni_p64.md"},
     ("k_uni_swar_sweep", "torus1000_uni_p64"): {
-        "bytes": 23209750, "source": "fce5914e347abd03",
+        "bytes": 23209750, "source": "706ff9da0b9d659e",
         "profile": "profiles/k_uni_swar_sweep_torus1000_uni_p64.md"},
     ("k_class_sweep", "torus100_nbhd_p64"): {
-        "bytes": 934260, "source": "fce5914e347abd03",
+        "bytes": 934260, "source": "706ff9da0b9d659e",
         "profile": "profiles/k_class_sweep_torus100_nbhd_p64.md"},
 }
 

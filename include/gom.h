@@ -334,11 +334,12 @@ int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launche
  *                           General FOS (population <= 64): the classes whose sets have at
  *                           most 9 members, per-set sums of |w| over their dependent edges of
  *                           at most 16383 and at least gom_state_set_bitsliced_min_sets sets
- *                           (default 8192): per solution the donor draw and the changed
+ *                           (default 32768): per solution the donor draw and the changed
  *                           members, then the fitness changes of 32 solutions at once as a
  *                           bit-sliced sum; the other classes as under class launch
- *   GOM_SCHED_AUTO          resident when it fits the device, else bit-sliced when a
- *                           univariate instance qualifies, else class launch
+ *   GOM_SCHED_AUTO          resident when it fits the device, else bit-sliced when the
+ *                           instance qualifies (univariate, or general with a class of at
+ *                           least the bit-sliced threshold), else class launch
  * GOM_E_RANGE when the requested schedule does not fit this instance or device.
  */
 enum { GOM_SCHED_AUTO = 0, GOM_SCHED_CLASS_LAUNCH = 1, GOM_SCHED_RESIDENT = 2,
@@ -388,7 +389,7 @@ int gom_state_set_fused(gom_state *s, int enabled);
 int gom_state_set_grid_limit(gom_state *s, int32_t blocks);
 /*
  * Smallest class (sets) that the bit-sliced schedule sweeps with the general bit-sliced
- * sweep (general FOS; default 8192: one set per lane leaves a smaller class too few waves).
+ * sweep (general FOS; default 32768: one set per lane leaves a smaller class too few waves).
  * Results do not depend on it.  A state under the bit-sliced schedule that no class
  * qualifies for any more falls back to GOM_SCHED_AUTO's choice.
  * Errors: GOM_E_ARG, GOM_E_RANGE (negative).

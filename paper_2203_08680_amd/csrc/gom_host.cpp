@@ -444,6 +444,12 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
 
 }  // namespace
 
+// Default least class size (sets) for the general bit-sliced sweep: with one set per lane a
+// smaller class leaves too few waves. A 3-regular graph's classes of about 10^4
+// neighbourhoods are swept faster by the class sweep, the 10^6-vertex torus's of 1.25*10^5
+// neighbourhoods 2.6 times slower.
+constexpr int32_t kGsMinSets = 32768;
+
 struct gom_state {
     int static_dev = -1;                // device whose static arena holds the state, or -1
     bool h_st_pinned = true;            // h_st from hipHostMalloc (else new[])
@@ -1271,7 +1277,9 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
 
 static int auto_schedule(const gom_state *s) {
     if (s->resident_ok) return GOM_SCHED_RESIDENT;
-    if (s->swar_uni && !s->fi) return GOM_SCHED_BITSLICED;
+    // (general FOS: only classes of at least gs_min_sets sets take the bit-sliced sweep, the
+    // others the class sweep, so an instance with such a class gains and none loses)
+    if (s->bitsliced_ok && !s->fi) return GOM_SCHED_BITSLICED;
     return GOM_SCHED_CLASS_LAUNCH;
 }
 

@@ -386,15 +386,13 @@ constexpr int kSwarThreads = 256;  // threads per block of the bit-sliced sweep
 // Bit-sliced sweep of small general sets (lane = set): classes whose sets have at most
 // kGsMaxMembers members, whose per-set sum of |w| over the dependent edges is at most
 // kGsMaxWeightSum (the bit-sliced sum 2 W stays below 2^15) and whose largest |w| has at most
-// kGsMaxWeightBits bits; classes of fewer than kGsMinSets sets keep the class sweep (one set
-// per lane leaves a small class too few waves).
+// kGsMaxWeightBits bits (the host also requires a least class size).
 constexpr int kGsThreads = 256;
 constexpr int kGsEntryBatch = 8;   // dependent-edge entries whose loads are issued together
 constexpr int kGsEntryBatchBcl = 8;   // ... in the batched class launches
 constexpr int kGsMaxMembers = 9;
 constexpr int64_t kGsMaxWeightSum = 16383;
 constexpr int kGsMaxWeightBits = 13;
-constexpr int32_t kGsMinSets = 8192;
 // Lane slots of a class of `csize` sets under the bit-sliced general sweep (a multiple of
 // 16): 16 slots hold 8 positions x 2 halves (population above 32) or 16 positions.
 __host__ __device__ __forceinline__ int gs_slots(int csize, int halves) {

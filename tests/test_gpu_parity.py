@@ -378,6 +378,18 @@ def test_schedule_selection(cuda):
     assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_BITSLICED
     with pytest.raises(gom.GomError):
         gom.gom_state_set_schedule(st, gom.GOM_SCHED_RESIDENT)
+    # general FOS: bit-sliced when some class is large enough (the 10^6-vertex torus's
+    # neighbourhood classes of 1.25*10^5 sets), class launch when none is (a 2*10^5-vertex
+    # 3-regular graph's classes of at most 2*10^4 sets; too large for the resident schedule)
+    nb = gom.Instance(g.n, g.u, g.v, g.w, 1)
+    assert gom.gom_state_get_schedule(nb.state(pop=64, seed=1)) == gom.GOM_SCHED_BITSLICED
+    g = workloads.configuration_model(200_000, 3, seed=3)
+    small = gom.Instance(g.n, g.u, g.v, g.w, 1)
+    st = small.state(pop=32, seed=1)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_CLASS_LAUNCH
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_CLASS_LAUNCH)
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_AUTO)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_CLASS_LAUNCH
 
 
 @pytest.mark.parametrize("kind", [0, 1])
@@ -850,7 +862,7 @@ def test_bitsliced_general(cuda, label, maker, pop, rule, sets):
 
 
 def test_bitsliced_general_min_sets(cuda):
-    """The size threshold: with the default (8192 sets) a 40x40 torus's neighbourhood classes
+    """The size threshold: with the default (32768 sets) a 40x40 torus's neighbourhood classes
     do not qualify, so the bit-sliced schedule is unavailable; lowering it makes it
     available, and raising it again under that schedule falls back to the automatic choice."""
     g = workloads.torus(40, 1, 100, seed=21)

@@ -152,3 +152,66 @@ def test_torus1000_neighbourhood_2_generations():
     _trajectory("torus1000 nbhd p64", g, 1, 64, 1, 2,
                 [(gom.GOM_SCHED_CLASS_LAUNCH, 0), (gom.GOM_SCHED_CLASS_LAUNCH, 0, True),
                  (gom.GOM_SCHED_BITSLICED, 0)], 2)
+
+
+def test_headline_mix_sampled():
+    """The 256-instance mix (tori and 4/8-regular graphs of 10^3-10^5 vertices, univariate and
+    neighbourhood FOS, populations 16-64) in the benchmark's launch configuration: two
+    batches (instances dealt round-robin by class count), each autotuned, reseeded and run
+    on its own stream from its own host thread.  After two generations the state hash of
+    each sampled instance (the largest of each FOS kind, every 11th of the rest) equals the
+    oracle's, and every instance ran both generations."""
+    import threading
+    import torch
+    print("case headline mix: set-up", flush=True)
+    items = workloads.batch_mix()
+    insts = [gom.Instance(it.graph.n, it.graph.u, it.graph.v, it.graph.w, it.fos)
+             for it in items]
+    targets = [it.graph.total_weight if it.to_total_weight else (1 << 62) for it in items]
+    kc = [len(x.classes()[1]) - 1 for x in insts]
+    order = sorted(range(len(items)), key=lambda i: (-kc[i], i))
+    groups = [sorted(order[j::2]) for j in range(2)]
+    batches = [gom.gom_batch_init([insts[i] for i in g], [items[i].pop for i in g],
+                                  [items[i].seed for i in g], [targets[i] for i in g])
+               for g in groups]
+    streams = [torch.cuda.Stream() for _ in groups]
+    for batch, g, s in zip(batches, groups, streams):
+        gom.gom_batch_autotune(batch, 2, stream=s)
+        gom.gom_batch_reseed(batch, [items[i].seed for i in g], stream=s)
+    print(f"case headline mix: class forms {[gom.gom_batch_get_class_bitsliced(b) for b in batches]}",
+          flush=True)
+    gens = 2
+    out = [None, None]
+
+    def go(j):
+        out[j] = gom.gom_batch_run(batches[j], gens, stream=streams[j])
+
+    threads = [threading.Thread(target=go, args=(j,)) for j in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    where = {}
+    for j, g in enumerate(groups):
+        for b, i in enumerate(g):
+            where[i] = (j, b)
+            assert out[j][0][b].generations == gens, f"instance {i}"
+    sizes = [it.graph.n for it in items]
+    sample = set(range(0, len(items), 11))
+    for kind in (0, 1):
+        sample.add(max((i for i in range(len(items)) if items[i].fos == kind),
+                       key=lambda i: sizes[i]))
+    for i in sorted(sample):
+        it = items[i]
+        j, b = where[i]
+        print(f"case headline mix: instance {i} (n {it.graph.n}, fos {it.fos}, pop {it.pop})",
+              flush=True)
+        ptr, vars_ = oracle.fos(it.graph, it.fos)
+        ref = oracle.Run(it.graph, ptr, vars_, pop=it.pop, seed=it.seed, workers=WORKERS)
+        ref.run(targets[i], gens)
+        st = batches[j].state(b)
+        if gom.gom_state_hash(st) != ref.hash():
+            assert_same(gom.gom_state_read(st), ref.state(), f"mix instance {i}")
+            raise AssertionError(f"mix instance {i}: hash differs")
+        ref.close()
