@@ -337,9 +337,11 @@ int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launche
  *                           (default 32768): per solution the donor draw and the changed
  *                           members, then the fitness changes of 32 solutions at once as a
  *                           bit-sliced sum; the other classes as under class launch
- *   GOM_SCHED_AUTO          resident when it fits the device, else bit-sliced when the
- *                           instance qualifies (univariate, or general with a class of at
- *                           least the bit-sliced threshold), else class launch
+ *   GOM_SCHED_AUTO          resident when it fits the device and the instance has at most
+ *                           4096 vertices (larger ones run faster spread over the device
+ *                           by class), else bit-sliced when the instance qualifies
+ *                           (univariate, or general with a class of at least the bit-sliced
+ *                           threshold), else class launch
  * GOM_E_RANGE when the requested schedule does not fit this instance or device.
  */
 enum { GOM_SCHED_AUTO = 0, GOM_SCHED_CLASS_LAUNCH = 1, GOM_SCHED_RESIDENT = 2,

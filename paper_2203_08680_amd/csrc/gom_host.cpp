@@ -450,6 +450,13 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
 // neighbourhoods 2.6 times slower.
 constexpr int32_t kGsMinSets = 32768;
 
+// Largest instance (vertices) GOM_SCHED_AUTO gives the resident schedule. Its N blocks (one a
+// solution) occupy N compute units, so past a few thousand vertices the class launches, which
+// spread each class over the whole device, are faster: per generation, 45.9 against 47.4 us at
+// 1024 vertices (32x32 torus, neighbourhoods, N = 64), 80.0 against 56.7 us at 10^4 (100x100
+// torus), 740 against 192 us at 10^5 (3-regular, neighbourhoods, N = 32).
+constexpr int32_t kResidentAutoMaxVertices = 4096;
+
 struct gom_state {
     int static_dev = -1;                // device whose static arena holds the state, or -1
     bool h_st_pinned = true;            // h_st from hipHostMalloc (else new[])
@@ -1276,7 +1283,7 @@ static hipError_t enqueue_initial_population(gom_state *s, hipStream_t st) {
 }
 
 static int auto_schedule(const gom_state *s) {
-    if (s->resident_ok) return GOM_SCHED_RESIDENT;
+    if (s->resident_ok && s->n <= kResidentAutoMaxVertices) return GOM_SCHED_RESIDENT;
     // (general FOS: only classes of at least gs_min_sets sets take the bit-sliced sweep, the
     // others the class sweep, so an instance with such a class gains and none loses)
     if (s->bitsliced_ok && !s->fi) return GOM_SCHED_BITSLICED;

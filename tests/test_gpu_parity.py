@@ -387,6 +387,13 @@ def test_schedule_selection(cuda):
     small = gom.Instance(g.n, g.u, g.v, g.w, 1)
     st = small.state(pop=32, seed=1)
     assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_CLASS_LAUNCH
+    # the 100x100 torus fits the resident schedule, but at 10^4 vertices AUTO spreads it over
+    # the device by class; it can still be asked for
+    g = workloads.torus(100, 1, 100, seed=2)
+    st = gom.Instance(g.n, g.u, g.v, g.w, 1).state(pop=64, seed=1)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_CLASS_LAUNCH
+    gom.gom_state_set_schedule(st, gom.GOM_SCHED_RESIDENT)
+    assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_RESIDENT
     gom.gom_state_set_schedule(st, gom.GOM_SCHED_CLASS_LAUNCH)
     gom.gom_state_set_schedule(st, gom.GOM_SCHED_AUTO)
     assert gom.gom_state_get_schedule(st) == gom.GOM_SCHED_CLASS_LAUNCH
