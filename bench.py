@@ -566,12 +566,13 @@ def run_serve_mode(args, torch, gom):
     while ws.step() != (0, 0):
         pass
     ws.close()
-    # plain: each job alone, one after another
+    # plain: each job alone, one after another; a job's service time includes the creation of
+    # its state (records, uploads, initial population), which the server does at admission
     solo, service = [], []
     for x, j in zip(insts, jobs):
-        st = x.state(pop=j.pop, seed=j.seed)
         torch.cuda.synchronize()
         s0 = time.perf_counter()
+        st = x.state(pop=j.pop, seed=j.seed)
         r = gom.gom_run_to_target(st, j.target, j.max_gens)
         service.append(time.perf_counter() - s0)
         solo.append((r, gom.gom_state_hash(st)))
