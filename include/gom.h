@@ -338,7 +338,7 @@ int gom_timing_read(gom_state *s, double *class_ms_total, int64_t *class_launche
  *                           members, then the fitness changes of 32 solutions at once as a
  *                           bit-sliced sum; the other classes as under class launch
  *   GOM_SCHED_AUTO          resident when it fits the device and the instance has at most
- *                           4096 vertices (larger ones run faster spread over the device
+ *                           1536 vertices (larger ones run faster spread over the device
  *                           by class), else bit-sliced when the instance qualifies
  *                           (univariate, or general with a class of at least the bit-sliced
  *                           threshold), else class launch

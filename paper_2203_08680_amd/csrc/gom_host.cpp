@@ -451,11 +451,12 @@ int build_records(const mc_graph &g, const gom_fos &f, bool univariate, Records 
 constexpr int32_t kGsMinSets = 32768;
 
 // Largest instance (vertices) GOM_SCHED_AUTO gives the resident schedule. Its N blocks (one a
-// solution) occupy N compute units, so past a few thousand vertices the class launches, which
-// spread each class over the whole device, are faster: per generation, 45.9 against 47.4 us at
-// 1024 vertices (32x32 torus, neighbourhoods, N = 64), 80.0 against 56.7 us at 10^4 (100x100
-// torus), 740 against 192 us at 10^5 (3-regular, neighbourhoods, N = 32).
-constexpr int32_t kResidentAutoMaxVertices = 4096;
+// solution) occupy N compute units, so past about a thousand vertices the class launches,
+// which spread each class over the whole device, are faster. Per generation, resident against
+// class launch (tori with neighbourhoods, N = 64): 45.9 / 47.4 us at 32x32, 53.0 / 47.9 at
+// 48x48, 55.3 / 47.4 at 64x64, 80.0 / 56.7 at 100x100; 740 / 192 us on a 10^5-vertex
+// 3-regular graph with neighbourhoods, N = 32.
+constexpr int32_t kResidentAutoMaxVertices = 1536;
 
 struct gom_state {
     int static_dev = -1;                // device whose static arena holds the state, or -1

@@ -164,6 +164,11 @@ WORKLOADS["torus100_uni_p64"] = Workload("torus100_uni_p64", _c2, 0, 64, 500, Tr
 # 32x32 torus, weights U{1..100}, neighbourhood FOS: small enough to reach its optimum.
 WORKLOADS["torus32_nbhd_p64"] = Workload("torus32_nbhd_p64", lambda: torus(32, 1, 100, seed=8),
                                          1, 64, 500, True)
+# 48x48, 64x64 and 80x80 tori, weights U{1..100}, neighbourhood FOS: the sizes around the
+# largest instance the automatic schedule choice keeps resident.
+for _L in (48, 64, 80):
+    WORKLOADS[f"torus{_L}_nbhd_p64"] = Workload(
+        f"torus{_L}_nbhd_p64", (lambda L: lambda: torus(L, 1, 100, seed=8))(_L), 1, 64, 500, True)
 # 100x100 torus with fixed linkage trees: the full tree and trees bounded to 10 and 100.
 for _b in (0, 10, 100):
     _name = f"torus100_bflt{_b}_p64" if _b else "torus100_flt_p64"
